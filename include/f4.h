@@ -1,0 +1,229 @@
+/*
+ * f4.h - C-ABI of the MI355X (gfx950) F4 reduction-step library.
+ *
+ * One F4 step over F_p, as the paper states the problem:
+ *   symbolic preprocessing SP : B -> (T, R, Pi)   (Definition "Symbolic
+ *     preprocessing operator"; Algorithm "FBSP", two-pass count -> scan -> fill
+ *     -> sort/unique -> join), producing the Macaulay matrix of Definition
+ *     "Sparse Macaulay matrix for a batch" in CSR form with columns in
+ *     descending grevlex order;
+ *   elimination mod p of that matrix (section "PSGE: panel-structured Gaussian
+ *     elimination"; two panels: pivot / non-pivot columns), with the modular
+ *     multiply-add of equation "mod-fma" and Barrett reduction (section
+ *     "Barrett reduction as reciprocal multiplication");
+ *   and the F4 loop around it (section "F4 as batched module reduction").
+ *
+ * Conventions (fixed where the paper is silent):
+ *   - Term order: grevlex with x_1 > x_2 > ... > x_n.
+ *   - Monomials are packed exponent words ("P words"), see f4_pack(): the
+ *     total degree in bits 56..63 and exponent a_i in a lane of w(n) bits at
+ *     bit offset w(n)*(i-1), w(n) = min(8, floor(56/n)).  Monomial product is
+ *     the integer sum of P words while no lane overflows.
+ *   - Column 0 of a matrix is the largest monomial; dictionary keys are P words.
+ *   - Reducer choice: among active basis elements whose leading monomial
+ *     divides m, the one with the largest index.
+ *   - Row order: leading monomial descending, then basis index ascending;
+ *     duplicate (t, k) rows collapse to one.
+ *   - Pivot row of a pivot column: fewest nonzeros, then lowest row index.
+ *   - Echelon form: the reduced row echelon form (monic) of the trailing block.
+ *
+ * All functions return an int status (F4_OK on success).  No C++ exception
+ * crosses this boundary.  Device work is asynchronous on the given stream
+ * (a hipStream_t passed as void*; NULL = the context's own stream); outputs are
+ * valid after that stream is synchronized.  The library never frees caller
+ * memory.  A context is used by one host thread at a time; its cached device
+ * memory is reused in stream order, so when a caller switches streams between
+ * calls the context first synchronizes the stream it used before.
+ */
+#ifndef F4_H
+#define F4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    F4_OK = 0,
+    F4_E_ARG = 1,     /* bad argument: n = 0 or n > 14, p not an odd prime < 2^31,
+                         unsorted / repeated terms, coefficient >= p, NULL pointer */
+    F4_E_RANGE = 2,   /* an exponent lane or the degree field would overflow, or a
+                         size exceeds 32-bit offsets */
+    F4_E_NOMEM = 3,   /* device or host allocation failed; the context stays usable */
+    F4_E_BUSY = 4,    /* request not admissible now (serving); retry later */
+    F4_E_DEVICE = 5,  /* HIP runtime error; destroy the context */
+    F4_E_STATE = 6    /* call not valid in the current state (e.g. unknown handle) */
+};
+
+typedef struct f4_ctx f4_ctx;
+typedef struct f4_matrix f4_matrix;
+typedef struct f4_reduced f4_reduced;
+typedef struct f4_basis f4_basis;
+
+/* Options for f4_create.  flags: bitwise OR of the F4_OPT_* values. */
+enum {
+    F4_OPT_TIMING = 1u << 0,     /* record per-stage HIP-event timings in f4_step_stats */
+    F4_OPT_DICT_RANK = 1u << 1,  /* force the dense-rank dictionary (bitmap sort/unique) */
+    F4_OPT_DICT_RADIX = 1u << 2  /* force the radix-sort dictionary (sort + unique + join) */
+};
+typedef struct f4_opts {
+    uint32_t flags;
+    uint32_t reserved;
+} f4_opts;
+
+/* Create a context on HIP device `device` (opts may be NULL).  The context owns
+ * a device memory cache, a stream, events and host staging buffers. */
+int f4_create(f4_ctx** out, int device, const f4_opts* opts);
+int f4_destroy(f4_ctx* ctx);
+/* Text of the last error on this context (static storage owned by the context). */
+const char* f4_last_error(const f4_ctx* ctx);
+/* Copy `bytes` from device memory (e.g. a view pointer) to host memory `dst`
+ * on the context's current stream and wait for it. */
+int f4_download(f4_ctx* ctx, void* dst, const void* src, size_t bytes);
+
+/* ------------------------------------------------------------- monomials */
+/* Lane width w(n) in bits for n variables (0 if n is 0 or > 14). */
+uint32_t f4_lane_bits(uint32_t n);
+/* Pack n exponents into a P word (section "Monomial keys: order-refining
+ * encodings"; key (deg, tie) in one machine word).  F4_E_RANGE if an exponent
+ * exceeds 2^w(n)-1 or the degree exceeds 255; F4_E_ARG for a bad n. */
+int f4_pack(uint32_t n, const uint32_t* exps, uint64_t* out);
+/* Unpack a P word into n exponents. */
+int f4_unpack(uint32_t n, uint64_t word, uint32_t* exps);
+/* Dense grevlex rank of a monomial of degree <= D among the N(n, D) =
+ * C(n+D, n) monomials of degree <= D (equation "monomial-count"): rank 0 is the
+ * largest monomial x_1^D, and ranks increase as monomials decrease, so sorting
+ * by rank is sorting by descending grevlex.  Host-side, for checking. */
+int f4_grevlex_rank(uint32_t n, uint32_t D, uint64_t word, uint32_t* rank);
+/* Inverse of f4_grevlex_rank. */
+int f4_grevlex_unrank(uint32_t n, uint32_t D, uint32_t rank, uint64_t* word);
+
+/* ------------------------------------------------------------ polynomials */
+/* A list of polynomials in structure-of-arrays form (section "Coalesced sparse
+ * polynomial storage: SoA support vectors"): the terms of polynomial k are
+ * mon[offset[k] .. offset[k+1]) and coeff[...].  Terms are sorted by monomial,
+ * largest first, with no repeated monomial and coefficients in [1, p).
+ * on_device = 1: mon/coeff/offset are device pointers; 0: host pointers. */
+typedef struct f4_polys {
+    uint32_t n;
+    uint32_t npolys;
+    const uint64_t* mon;
+    const uint32_t* coeff;
+    const uint64_t* offset; /* npolys + 1 entries */
+    int on_device;
+} f4_polys;
+
+/* A critical pair of basis indices (i < j). */
+typedef struct f4_pair {
+    uint32_t i, j;
+} f4_pair;
+
+/* A shifted reducer t * g_k: t a P word, k a basis index. */
+typedef struct f4_rowspec {
+    uint64_t t;
+    uint32_t k;
+    uint32_t pad;
+} f4_rowspec;
+
+/* ------------------------------------------------------- matrix (SP output) */
+typedef struct f4_matrix_view {
+    uint32_t n;        /* variables */
+    uint32_t r;        /* rows */
+    uint32_t N;        /* columns = dictionary size |T| */
+    uint32_t deg;      /* largest degree in the dictionary */
+    uint64_t nnz;      /* = M, the total row length */
+    const uint32_t* row_ptr;   /* device, r + 1: exclusive scan of row lengths */
+    const uint32_t* col_ind;   /* device, nnz: column of each entry, ascending per row */
+    const uint32_t* val;       /* device, nnz: coefficient in [1, p) */
+    const uint64_t* dict_keys; /* device, N: P word of each column, descending grevlex */
+    const uint64_t* row_t;     /* device, r: shift monomial t_i (P word) */
+    const uint32_t* row_k;     /* device, r: basis index k_i */
+} f4_matrix_view;
+
+/* Symbolic preprocessing of one F4 step (Definition "Symbolic preprocessing
+ * operator"; Algorithm "FBSP"): the rows are the two halves
+ * (lcm/LM(g_i), i), (lcm/LM(g_j), j) of every selected pair, closed under
+ * one-step reduction (Remark "Truncation and why symbolic preprocessing
+ * matters", Definition "Support-closure for correctness") by the reducer rule
+ * above; the dictionary is the sorted, deduplicated union of the row supports
+ * and the CSR is written by a two-pass count -> prefix-sum -> fill plan.
+ *   p       : odd prime < 2^31.
+ *   G       : basis (host or device SoA); all elements monic.
+ *   active  : host array of G->npolys bytes, nonzero = usable as a reducer.
+ *   sel     : host array of nsel pairs, all with the same lcm degree.
+ *   A       : out, a context-owned matrix handle (free with f4_matrix_free).
+ * Errors: F4_E_ARG (bad p, n, indices, empty selection), F4_E_RANGE (lane
+ * overflow), F4_E_NOMEM, F4_E_DEVICE. */
+int f4_build_matrix(f4_ctx* ctx, uint32_t p, const f4_polys* G, const uint8_t* active,
+                    const f4_pair* sel, uint32_t nsel, f4_matrix** A, void* stream);
+
+/* The same map for an explicit row list R (host, r entries) with no closure:
+ * the matrix of Definition "Sparse Macaulay matrix for a batch" for
+ * (T = union of supports, R).  Theorem "Matrix materialization correctness"
+ * is stated for exactly this object. */
+int f4_build_matrix_rows(f4_ctx* ctx, uint32_t p, const f4_polys* G, const f4_rowspec* R, uint32_t r,
+                         f4_matrix** A, void* stream);
+
+/* A matrix from caller CSR arrays (host): r rows, N columns, entries sorted by
+ * column within each row, values in [1, p).  Used to run f4_reduce on given
+ * matrices.  dict_keys/row_t/row_k of the view are NULL for such a matrix. */
+int f4_matrix_from_csr(f4_ctx* ctx, uint32_t r, uint32_t N, const uint32_t* row_ptr, const uint32_t* col_ind,
+                       const uint32_t* val, f4_matrix** A, void* stream);
+
+int f4_matrix_get(const f4_matrix* A, f4_matrix_view* out);
+int f4_matrix_free(f4_matrix* A);
+
+/* ------------------------------------------------- reduce (elimination) */
+typedef struct f4_reduced_view {
+    uint32_t N;          /* columns of A */
+    uint32_t npivot;     /* |Pc|: distinct leading columns of the rows of A */
+    uint32_t rho;        /* rank of the reduced trailing block */
+    uint32_t rank;       /* rank(A) = npivot + rho */
+    uint64_t nnz;        /* entries of the echelon rows */
+    const uint32_t* pivot_cols; /* device, npivot, ascending */
+    const uint32_t* row_ptr;    /* device, rho + 1 */
+    const uint32_t* col_ind;    /* device: columns of A, ascending per row */
+    const uint32_t* val;        /* device: first entry of each row is 1 */
+} f4_reduced_view;
+
+/* Elimination of A mod p (section "PSGE"): pivot columns = leading columns of
+ * the rows; one pivot row per pivot column; the other rows are reduced by the
+ * pivot rows on the pivot columns (sparse triangular solve), and the reduced
+ * row echelon form of the remaining trailing block is returned as CSR over the
+ * columns of A, rows ordered by leading column.  A is not modified. */
+int f4_reduce(f4_ctx* ctx, uint32_t p, const f4_matrix* A, f4_reduced** out, void* stream);
+int f4_reduced_get(const f4_reduced* R, f4_reduced_view* out);
+int f4_reduced_free(f4_reduced* R);
+
+/* ----------------------------------------------------------- full F4 */
+typedef struct f4_step_stats {
+    uint32_t deg, nsel, r, N;
+    uint64_t nnz;
+    uint32_t npivot, lower, rho, rank;
+    uint32_t closure_rounds, dict_path; /* dict_path: 0 dense rank, 1 radix sort */
+    float t_dict_ms;      /* DictBuild: row emission, closure, sort + unique (HIP events) */
+    float t_assemble_ms;  /* RowAssemble: count, scan, fill + join */
+    float t_numeric_ms;   /* NumericCore: split, triangular solve, echelon, emit */
+    float t_trsm_ms;      /* of which the sparse triangular solve */
+    float t_echelon_ms;   /* of which the trailing-block echelon */
+    float t_step_ms;      /* host wall time of the whole step */
+} f4_step_stats;
+
+/* Reduced Groebner basis of <F> under grevlex (unique: monic, minimal,
+ * inter-reduced), computed by F4 with the Gebauer-Moeller pair update and the
+ * normal selection strategy.  F: host SoA polynomials (any coefficients < p,
+ * terms sorted as above; zero polynomials allowed).  gb: out handle. */
+int f4_groebner(f4_ctx* ctx, uint32_t p, const f4_polys* F, f4_basis** gb, void* stream);
+/* Host view of a basis: polynomials sorted by leading monomial, largest first. */
+int f4_basis_view(const f4_basis* B, f4_polys* out);
+int f4_basis_stats(const f4_basis* B, const f4_step_stats** steps, uint32_t* nsteps);
+int f4_basis_free(f4_basis* B);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* F4_H */

@@ -1,0 +1,223 @@
+// Internal host-side interfaces shared by the library's translation units.
+#pragma once
+
+#include <map>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+
+// --------------------------------------------------------------- device cache
+// A caching device allocator.  Blocks are reused in stream order: every launch
+// of a context goes to one stream, so a block released after enqueueing the
+// kernels that read it can be handed to kernels enqueued later on that stream.
+struct Pool {
+    std::multimap<size_t, void*> free_;
+    std::unordered_map<void*, size_t> size_;
+    size_t live_bytes = 0, cached_bytes = 0, peak_bytes = 0;
+
+    static size_t round_size(size_t b) {
+        if (b < 256) b = 256;
+        size_t c = 256;
+        while (c < b) c <<= 1;
+        if (c > (64u << 20)) c = (b + (4u << 20) - 1) & ~size_t((4u << 20) - 1);  // 4 MiB steps above 64 MiB
+        return c;
+    }
+    void* alloc(size_t bytes) {
+        size_t want = round_size(bytes);
+        auto it = free_.lower_bound(want);
+        if (it != free_.end() && it->first <= 2 * want) {
+            void* p = it->second;
+            cached_bytes -= it->first;
+            live_bytes += it->first;
+            free_.erase(it);
+            return p;
+        }
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim();
+            e = hipMalloc(&p, want);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw F4Error{3, "device allocation of " + std::to_string(want) + " bytes failed"};
+            }
+        }
+        size_[p] = want;
+        live_bytes += want;
+        if (live_bytes > peak_bytes) peak_bytes = live_bytes;
+        return p;
+    }
+    void release(void* p) {
+        if (!p) return;
+        auto it = size_.find(p);
+        if (it == size_.end()) return;
+        live_bytes -= it->second;
+        cached_bytes += it->second;
+        free_.insert({it->second, p});
+    }
+    void trim() {
+        for (auto& kv : free_) {
+            (void)hipFree(kv.second);
+            size_.erase(kv.second);
+        }
+        free_.clear();
+        cached_bytes = 0;
+    }
+    ~Pool() {
+        for (auto& kv : size_) (void)hipFree(kv.first);
+    }
+};
+
+// A typed device buffer owned by a pool (released on destruction).
+template <class T>
+struct DBuf {
+    Pool* pool = nullptr;
+    T* ptr = nullptr;
+    size_t n = 0;
+    DBuf() {}
+    DBuf(Pool* p, size_t count) { reset(p, count); }
+    void reset(Pool* p, size_t count) {
+        free();
+        pool = p;
+        n = count;
+        ptr = (T*)pool->alloc((count ? count : 1) * sizeof(T));
+    }
+    void free() {
+        if (pool && ptr) pool->release(ptr);
+        ptr = nullptr;
+        n = 0;
+    }
+    T* release_owner() {  // hand ownership to someone else
+        T* p = ptr;
+        ptr = nullptr;
+        n = 0;
+        return p;
+    }
+    ~DBuf() { free(); }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept : pool(o.pool), ptr(o.ptr), n(o.n) {
+        o.ptr = nullptr;
+        o.n = 0;
+    }
+    DBuf& operator=(DBuf&& o) noexcept {
+        free();
+        pool = o.pool;
+        ptr = o.ptr;
+        n = o.n;
+        o.ptr = nullptr;
+        o.n = 0;
+        return *this;
+    }
+};
+
+// -------------------------------------------------------------- primitives
+// (prim.hip)
+void fill_u32(u32* p, u64 n, u32 v, hipStream_t s);
+void fill_u64(u64* p, u64 n, u64 v, hipStream_t s);
+// Exclusive scan of n u32 values into out (may alias in); out[n] = total.
+// out must have room for n + 1 values.
+void exclusive_scan_u32(const u32* in, u32* out, u64 n, Pool& pool, hipStream_t s);
+// Stable LSD radix sort of (key, val) pairs on key bits [lo_bit, hi_bit).
+// keys/vals hold the input and receive the output; tmp buffers come from pool.
+void radix_sort_pairs(u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s);
+// Sort keys only (vals unused)
+void radix_sort_keys(u64* keys, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s);
+// Unique of sorted keys: writes distinct keys to out, count to *d_count (device).
+void unique_sorted_u64(const u64* keys, u64 n, u64* out, u32* d_count, Pool& pool, hipStream_t s);
+
+// ----------------------------------------------------------------- context
+struct StepTimer;
+
+struct DevInfo {
+    int device = 0;
+    size_t max_lds = 65536;  // dynamic LDS bytes per workgroup usable by a kernel
+    int cus = 256;
+};
+
+// Per-context state.  All device work of a call goes to `stream`.
+struct Ctx {
+    DevInfo dev;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;  // stream of the current call
+    Pool pool;
+    u32 flags = 0;
+    std::string last_error;
+    // pinned host staging for small uploads / readbacks
+    u8* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipEvent_t staging_done = nullptr;  // last async copy out of / into `pinned`
+    bool staging_pending = false;
+    // caches keyed by (n, D): binomial table and dense-rank -> monomial table
+    std::map<std::pair<u32, u32>, DBuf<u32>> binom;
+    std::map<std::pair<u32, u32>, DBuf<u64>> montab;
+    // timing events (F4_OPT_TIMING)
+    std::vector<hipEvent_t> events;
+    u32 ev_used = 0;
+};
+
+// Wait until the pinned staging buffer can be rewritten, return it (>= bytes).
+u8* staging(Ctx& c, size_t bytes);
+// Enqueue an H2D copy of host data through the staging buffer (small arrays).
+void upload(Ctx& c, void* dst, const void* src, size_t bytes);
+// Synchronous readback of a small device array through the staging buffer.
+void readback(Ctx& c, void* dst, const void* src, size_t bytes);
+// Event for stage timing (nullptr when timing is off).
+hipEvent_t stage_event(Ctx& c);
+float event_ms(hipEvent_t a, hipEvent_t b);
+
+// Binomial table C(x, y), x <= n+D+1, y <= min(n, 15), on the device.
+const u32* rank_table(Ctx& c, u32 n, u32 D);
+// P word of every dense rank q < N(n, D).
+const u64* unrank_table(Ctx& c, u32 n, u32 D);
+u64 binom_host(u32 x, u32 y);
+
+// ------------------------------------------------------------- basis view
+struct DevBasis {
+    u32 n = 0, w = 0, npolys = 0;
+    const u64* mon = nullptr;
+    const u32* coeff = nullptr;
+    const u64* off = nullptr;
+    const u64* lm = nullptr;   // leading monomial per polynomial
+    const u32* len = nullptr;  // term count per polynomial
+};
+
+// --------------------------------------------------------------- matrix
+struct Matrix {
+    u32 n = 0, r = 0, N = 0, deg = 0;
+    u64 nnz = 0;
+    DBuf<u32> row_ptr, col_ind, val, row_k;
+    DBuf<u64> dict_keys, row_t;
+    u32 closure_rounds = 0, dict_path = 0;
+    float t_dict = 0, t_assemble = 0;
+};
+
+struct BuildArgs {
+    DevBasis G;
+    const u64* rows_t = nullptr;  // device, r0 initial rows (distinct (t, k))
+    const u32* rows_k = nullptr;
+    u32 r0 = 0;
+    const u32* active = nullptr;  // device, active basis indices in descending order
+    u32 nactive = 0;
+    u32 D = 0;                    // largest degree of any row
+    bool closure = true;
+    int dict_path = -1;           // -1 auto, 0 dense rank, 1 radix sort
+};
+void build_matrix(Ctx& c, const BuildArgs& a, Matrix& out);
+
+// ----------------------------------------------------------- elimination
+struct Reduced {
+    u32 N = 0, npivot = 0, rho = 0, rank = 0;
+    u64 nnz = 0;
+    DBuf<u32> pivot_cols, row_ptr, col_ind, val;
+    float t_split = 0, t_trsm = 0, t_echelon = 0, t_emit = 0;
+    u32 lower = 0;
+};
+// Full elimination of a matrix (pivot split, triangular solve, echelon, emit).
+void reduce_matrix(Ctx& c, u32 p, const Matrix& A, Reduced& out);
+// Inter-reduction: every row of A is a pivot row (distinct leading columns);
+// returns, for each row, its tail reduced by the other rows, as CSR over the
+// columns of A (the leading entry itself is not included).
+void tail_reduce_matrix(Ctx& c, u32 p, const Matrix& A, DBuf<u32>& tptr, DBuf<u32>& tcol, DBuf<u32>& tval);

@@ -1,0 +1,337 @@
+"""Thin ctypes binding of libf4.so (include/f4.h): argument marshalling only.
+
+Every step of the F4 path runs in the HIP library; this module packs
+exponent tuples into P words, lays polynomials out as host arrays or takes
+device tensors (torch, for device memory and streams), and copies results
+back.  There is no fallback: if the library is missing, importing fails.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libf4.so")
+
+F4_OK, F4_E_ARG, F4_E_RANGE, F4_E_NOMEM, F4_E_BUSY, F4_E_DEVICE, F4_E_STATE = range(7)
+F4_OPT_TIMING, F4_OPT_DICT_RANK, F4_OPT_DICT_RADIX = 1, 2, 4
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libf4.so is not built: run `python -m paper_2601_06765_amd.build` "
+                      "(or __graft_entry__.build()) first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+c_u32, c_u64, c_int, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
+P = ctypes.POINTER
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("flags", c_u32), ("reserved", c_u32)]
+
+
+class Polys(ctypes.Structure):
+    _fields_ = [("n", c_u32), ("npolys", c_u32), ("mon", c_vp), ("coeff", c_vp), ("offset", c_vp),
+                ("on_device", c_int)]
+
+
+class Pair(ctypes.Structure):
+    _fields_ = [("i", c_u32), ("j", c_u32)]
+
+
+class RowSpec(ctypes.Structure):
+    _fields_ = [("t", c_u64), ("k", c_u32), ("pad", c_u32)]
+
+
+class MatrixView(ctypes.Structure):
+    _fields_ = [("n", c_u32), ("r", c_u32), ("N", c_u32), ("deg", c_u32), ("nnz", c_u64),
+                ("row_ptr", c_vp), ("col_ind", c_vp), ("val", c_vp), ("dict_keys", c_vp),
+                ("row_t", c_vp), ("row_k", c_vp)]
+
+
+class ReducedView(ctypes.Structure):
+    _fields_ = [("N", c_u32), ("npivot", c_u32), ("rho", c_u32), ("rank", c_u32), ("nnz", c_u64),
+                ("pivot_cols", c_vp), ("row_ptr", c_vp), ("col_ind", c_vp), ("val", c_vp)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("deg", c_u32), ("nsel", c_u32), ("r", c_u32), ("N", c_u32), ("nnz", c_u64),
+                ("npivot", c_u32), ("lower", c_u32), ("rho", c_u32), ("rank", c_u32),
+                ("closure_rounds", c_u32), ("dict_path", c_u32),
+                ("t_dict_ms", ctypes.c_float), ("t_assemble_ms", ctypes.c_float),
+                ("t_numeric_ms", ctypes.c_float), ("t_trsm_ms", ctypes.c_float),
+                ("t_echelon_ms", ctypes.c_float), ("t_step_ms", ctypes.c_float)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("f4_create", c_int, [P(c_vp), c_int, P(Opts)])
+_sig("f4_destroy", c_int, [c_vp])
+_sig("f4_last_error", ctypes.c_char_p, [c_vp])
+_sig("f4_download", c_int, [c_vp, c_vp, c_vp, ctypes.c_size_t])
+_sig("f4_lane_bits", c_u32, [c_u32])
+_sig("f4_pack", c_int, [c_u32, P(c_u32), P(c_u64)])
+_sig("f4_unpack", c_int, [c_u32, c_u64, P(c_u32)])
+_sig("f4_grevlex_rank", c_int, [c_u32, c_u32, c_u64, P(c_u32)])
+_sig("f4_grevlex_unrank", c_int, [c_u32, c_u32, c_u32, P(c_u64)])
+_sig("f4_build_matrix", c_int, [c_vp, c_u32, P(Polys), P(ctypes.c_uint8), P(Pair), c_u32, P(c_vp), c_vp])
+_sig("f4_build_matrix_rows", c_int, [c_vp, c_u32, P(Polys), P(RowSpec), c_u32, P(c_vp), c_vp])
+_sig("f4_matrix_from_csr", c_int, [c_vp, c_u32, c_u32, P(c_u32), P(c_u32), P(c_u32), P(c_vp), c_vp])
+_sig("f4_matrix_get", c_int, [c_vp, P(MatrixView)])
+_sig("f4_matrix_free", c_int, [c_vp])
+_sig("f4_reduce", c_int, [c_vp, c_u32, c_vp, P(c_vp), c_vp])
+_sig("f4_reduced_get", c_int, [c_vp, P(ReducedView)])
+_sig("f4_reduced_free", c_int, [c_vp])
+_sig("f4_groebner", c_int, [c_vp, c_u32, P(Polys), P(c_vp), c_vp])
+_sig("f4_basis_view", c_int, [c_vp, P(Polys)])
+_sig("f4_basis_stats", c_int, [c_vp, P(P(StepStats)), P(c_u32)])
+_sig("f4_basis_free", c_int, [c_vp])
+
+
+class F4Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("f4 error %d: %s" % (code, msg))
+        self.code = code
+
+
+# ------------------------------------------------------------- monomials
+def lane_bits(n):
+    return _lib.f4_lane_bits(n)
+
+
+def pack(n, exps):
+    arr = (c_u32 * n)(*exps)
+    out = c_u64()
+    rc = _lib.f4_pack(n, arr, ctypes.byref(out))
+    if rc:
+        raise F4Error(rc, "cannot pack %r" % (tuple(exps),))
+    return out.value
+
+
+def unpack(n, word):
+    arr = (c_u32 * n)()
+    rc = _lib.f4_unpack(n, word, arr)
+    if rc:
+        raise F4Error(rc, "cannot unpack")
+    return tuple(arr)
+
+
+def grevlex_rank(n, D, word):
+    out = c_u32()
+    rc = _lib.f4_grevlex_rank(n, D, word, ctypes.byref(out))
+    if rc:
+        raise F4Error(rc, "rank")
+    return out.value
+
+
+def grevlex_unrank(n, D, rank):
+    out = c_u64()
+    rc = _lib.f4_grevlex_unrank(n, D, rank, ctypes.byref(out))
+    if rc:
+        raise F4Error(rc, "unrank")
+    return out.value
+
+
+def polys_to_arrays(n, polys, sort=False):
+    """List of polys [(exps, coeff), ...] -> (mon u64, coeff u32, offset u64) host arrays.
+    With sort=True the terms of each polynomial are ordered by the library's
+    order key (largest monomial first), as f4_build_matrix requires."""
+    w = lane_bits(n)
+    lanes = (1 << (n * w)) - 1
+    mons, coeffs, offs = [], [], [0]
+    for f in polys:
+        words = [(pack(n, e), c) for e, c in f]
+        if sort:
+            words.sort(key=lambda t: t[0] ^ lanes, reverse=True)
+        for wd, c in words:
+            mons.append(wd)
+            coeffs.append(c)
+        offs.append(len(mons))
+    return (np.array(mons, dtype=np.uint64), np.array(coeffs, dtype=np.uint32),
+            np.array(offs, dtype=np.uint64))
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):  # torch tensor (device or host)
+        return c_vp(a.data_ptr())
+    return a.ctypes.data_as(c_vp)
+
+
+class _PolysArg:
+    """Keeps the arrays alive while the struct is in use."""
+
+    def __init__(self, n, mon, coeff, off, on_device=False):
+        self.keep = (mon, coeff, off)
+        self.s = Polys(n, len(off) - 1, _ptr(mon), _ptr(coeff), _ptr(off), 1 if on_device else 0)
+
+
+# --------------------------------------------------------------- context
+class Context:
+    def __init__(self, device=0, timing=False, dict_path=None):
+        flags = F4_OPT_TIMING if timing else 0
+        if dict_path == "rank":
+            flags |= F4_OPT_DICT_RANK
+        elif dict_path == "radix":
+            flags |= F4_OPT_DICT_RADIX
+        self._h = c_vp()
+        rc = _lib.f4_create(ctypes.byref(self._h), device, ctypes.byref(Opts(flags, 0)))
+        if rc:
+            raise F4Error(rc, "f4_create failed")
+
+    def close(self):
+        if self._h:
+            _lib.f4_destroy(self._h)
+            self._h = c_vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc:
+            raise F4Error(rc, (_lib.f4_last_error(self._h) or b"").decode())
+
+    def download(self, ptr, count, dtype):
+        out = np.empty(count, dtype=dtype)
+        if count:
+            self._check(_lib.f4_download(self._h, out.ctypes.data_as(c_vp), c_vp(ptr), out.nbytes))
+        return out
+
+    # -- full F4
+    def groebner(self, p, n, polys, stream=None):
+        """Reduced Groebner basis of a system given as lists of (exps, coeff).
+        Returns (basis, steps): basis as lists of (exps, coeff), leading term
+        first, sorted by leading monomial (largest first); steps as dicts."""
+        mon, coeff, off = polys_to_arrays(n, [[(e, c % p) for e, c in f] for f in polys])
+        arg = _PolysArg(n, mon, coeff, off)
+        h = c_vp()
+        self._check(_lib.f4_groebner(self._h, p, ctypes.byref(arg.s), ctypes.byref(h), c_vp(stream)))
+        try:
+            v = Polys()
+            _lib.f4_basis_view(h, ctypes.byref(v))
+            k = v.npolys
+            offs = np.ctypeslib.as_array(ctypes.cast(v.offset, P(c_u64)), (k + 1,)).copy() if k else [0]
+            nt = int(offs[-1])
+            mons = np.ctypeslib.as_array(ctypes.cast(v.mon, P(c_u64)), (nt,)).copy() if nt else []
+            cfs = np.ctypeslib.as_array(ctypes.cast(v.coeff, P(c_u32)), (nt,)).copy() if nt else []
+            basis = []
+            for a in range(k):
+                basis.append([(unpack(n, int(mons[q])), int(cfs[q])) for q in range(int(offs[a]), int(offs[a + 1]))])
+            sp = P(StepStats)()
+            ns = c_u32()
+            _lib.f4_basis_stats(h, ctypes.byref(sp), ctypes.byref(ns))
+            steps = []
+            for i in range(ns.value):
+                s = sp[i]
+                steps.append({name: getattr(s, name) for name, _ in StepStats._fields_})
+        finally:
+            _lib.f4_basis_free(h)
+        return basis, steps
+
+    # -- one step
+    def build_matrix(self, p, n, G, active, sel, stream=None, device_arrays=None):
+        """Symbolic preprocessing for the selected pairs.  G: list of polys
+        (monic, any term order) or, with device_arrays=(mon, coeff, off) torch
+        tensors, a device-resident basis."""
+        if device_arrays is not None:
+            arg = _PolysArg(n, *device_arrays, on_device=True)
+        else:
+            arg = _PolysArg(n, *polys_to_arrays(n, G, sort=True))
+        act = np.array([1 if a else 0 for a in active], dtype=np.uint8)
+        pairs = (Pair * len(sel))(*[Pair(i, j) for i, j in sel])
+        h = c_vp()
+        self._check(_lib.f4_build_matrix(self._h, p, ctypes.byref(arg.s),
+                                         act.ctypes.data_as(P(ctypes.c_uint8)), pairs, len(sel),
+                                         ctypes.byref(h), c_vp(stream)))
+        return Matrix(self, h, n)
+
+    def build_matrix_rows(self, p, n, G, rows, stream=None):
+        arg = _PolysArg(n, *polys_to_arrays(n, G, sort=True))
+        rs = (RowSpec * len(rows))(*[RowSpec(pack(n, t), k, 0) for t, k in rows])
+        h = c_vp()
+        self._check(_lib.f4_build_matrix_rows(self._h, p, ctypes.byref(arg.s), rs, len(rows), ctypes.byref(h),
+                                              c_vp(stream)))
+        return Matrix(self, h, n)
+
+    def matrix_from_csr(self, r, N, row_ptr, col_ind, val, stream=None):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.uint32)
+        ci = np.ascontiguousarray(col_ind, dtype=np.uint32)
+        vv = np.ascontiguousarray(val, dtype=np.uint32)
+        h = c_vp()
+        self._check(_lib.f4_matrix_from_csr(self._h, r, N, rp.ctypes.data_as(P(c_u32)),
+                                            ci.ctypes.data_as(P(c_u32)) if len(ci) else None,
+                                            vv.ctypes.data_as(P(c_u32)) if len(vv) else None,
+                                            ctypes.byref(h), c_vp(stream)))
+        return Matrix(self, h, 0)
+
+    def reduce(self, p, A, stream=None):
+        h = c_vp()
+        self._check(_lib.f4_reduce(self._h, p, A._h, ctypes.byref(h), c_vp(stream)))
+        return Reduced(self, h)
+
+
+class Matrix:
+    def __init__(self, ctx, h, n):
+        self.ctx, self._h, self.n = ctx, h, n
+        self.view = MatrixView()
+        _lib.f4_matrix_get(h, ctypes.byref(self.view))
+
+    def free(self):
+        if self._h:
+            _lib.f4_matrix_free(self._h)
+            self._h = c_vp()
+
+    def __del__(self):
+        try:
+            if self.ctx._h:
+                self.free()
+        except Exception:
+            pass
+
+    def to_host(self):
+        v, d = self.view, self.ctx.download
+        out = {"r": v.r, "N": v.N, "nnz": v.nnz, "deg": v.deg,
+               "row_ptr": d(v.row_ptr, v.r + 1, np.uint32),
+               "col_ind": d(v.col_ind, v.nnz, np.uint32),
+               "val": d(v.val, v.nnz, np.uint32)}
+        if v.dict_keys:
+            out["dict_keys"] = d(v.dict_keys, v.N, np.uint64)
+            out["row_t"] = d(v.row_t, v.r, np.uint64)
+            out["row_k"] = d(v.row_k, v.r, np.uint32)
+        return out
+
+
+class Reduced:
+    def __init__(self, ctx, h):
+        self.ctx, self._h = ctx, h
+        self.view = ReducedView()
+        _lib.f4_reduced_get(h, ctypes.byref(self.view))
+
+    def free(self):
+        if self._h:
+            _lib.f4_reduced_free(self._h)
+            self._h = c_vp()
+
+    def __del__(self):
+        try:
+            if self.ctx._h:
+                self.free()
+        except Exception:
+            pass
+
+    def to_host(self):
+        v, d = self.view, self.ctx.download
+        return {"N": v.N, "npivot": v.npivot, "rho": v.rho, "rank": v.rank, "nnz": v.nnz,
+                "pivot_cols": d(v.pivot_cols, v.npivot, np.uint32),
+                "row_ptr": d(v.row_ptr, v.rho + 1, np.uint32),
+                "col_ind": d(v.col_ind, v.nnz, np.uint32),
+                "val": d(v.val, v.nnz, np.uint32)}
