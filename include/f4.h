@@ -217,10 +217,51 @@ typedef struct f4_step_stats {
  * normal selection strategy.  F: host SoA polynomials (any coefficients < p,
  * terms sorted as above; zero polynomials allowed).  gb: out handle. */
 int f4_groebner(f4_ctx* ctx, uint32_t p, const f4_polys* F, f4_basis** gb, void* stream);
+/* The same for nsys independent systems (prime p[i], input F[i]) processed
+ * together: every F4 iteration advances all unfinished systems by one step
+ * with one batched launch sequence (symbolic preprocessing and elimination of
+ * all their matrices at once), and the finished ones are inter-reduced
+ * together.  gb: array of nsys out handles.  Each result equals what
+ * f4_groebner returns for that system alone. */
+int f4_groebner_batch(f4_ctx* ctx, uint32_t nsys, const uint32_t* p, const f4_polys* F, f4_basis** gb,
+                      void* stream);
 /* Host view of a basis: polynomials sorted by leading monomial, largest first. */
 int f4_basis_view(const f4_basis* B, f4_polys* out);
 int f4_basis_stats(const f4_basis* B, const f4_step_stats** steps, uint32_t* nsteps);
 int f4_basis_free(f4_basis* B);
+
+/* ------------------------------------------------------------- serving */
+typedef struct f4_server f4_server;
+
+/* Estimated device footprint of one system with n variables and m quadratic
+ * generators: 8 * N(n, D) * N(n, D - 1) bytes + 64 MiB, where D is the
+ * degree of regularity of a semi-regular sequence of m quadratics (first
+ * non-positive coefficient of (1 - t^2)^m / (1 - t)^n) and N(n, d) = C(n+d, d)
+ * (equation "monomial-count"): the size of a dense trailing block of the
+ * widest step.  Host-side only. */
+int f4_server_footprint(uint32_t n, uint32_t m, uint64_t* bytes);
+
+/* A serving engine on a context.  Systems are admitted while their estimated
+ * footprint fits in hbm_budget bytes and fewer than max_slots are resident;
+ * their bases and pair sets stay on the device.  Each f4_server_step advances
+ * every resident unfinished system by one F4 iteration with one batched
+ * launch sequence (continuous batching: systems admitted between steps join
+ * the next one), and systems whose pairs are exhausted get their reduced
+ * basis in the same step.  One host thread at a time. */
+int f4_server_create(f4_ctx* ctx, uint64_t hbm_budget, uint32_t max_slots, f4_server** out);
+/* Admit a system (host SoA input, as for f4_groebner).  F4_E_BUSY when its
+ * footprint or a slot is not available now (nothing is kept; retry after a
+ * step).  ticket: out id, also when the system finishes at once. */
+int f4_server_submit(f4_server* srv, uint32_t p, const f4_polys* F, uint64_t* ticket);
+/* One engine iteration; *completed (may be NULL) = systems it finished. */
+int f4_server_step(f4_server* srv, uint32_t* completed);
+/* *done = 1 and *gb = the reduced basis (caller frees it with f4_basis_free)
+ * when the ticket's system is finished; its slot and footprint are released.
+ * *done = 0 otherwise.  F4_E_STATE for an unknown ticket. */
+int f4_server_poll(f4_server* srv, uint64_t ticket, f4_basis** gb, int* done);
+/* Resident systems, unfinished systems, footprint in use. */
+int f4_server_load(const f4_server* srv, uint32_t* resident, uint32_t* running, uint64_t* used);
+int f4_server_destroy(f4_server* srv);
 
 #ifdef __cplusplus
 }

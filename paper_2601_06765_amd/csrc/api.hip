@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <set>
 
@@ -21,11 +22,13 @@
 struct f4_matrix;
 struct f4_reduced;
 struct f4_basis;
+struct f4_server;
 struct f4_ctx {
     Ctx c;
     std::set<f4_matrix*> matrices;
     std::set<f4_reduced*> reduceds;
     std::set<f4_basis*> bases;
+    std::set<f4_server*> servers;
 };
 struct f4_matrix {
     f4_ctx* owner;
@@ -100,21 +103,26 @@ float event_ms(hipEvent_t a, hipEvent_t b) {
 }
 
 // ----------------------------------------------------- packed monomials (host)
-// SWAR forms valid while every exponent is below 2^(w-1) (guard bit free).
+// SWAR forms are valid while every exponent is below 2^(w-1) (the lane's top
+// bit free as a guard), which holds when the degree is below 2^(w-1); above
+// that the lanes are compared one by one.
 struct MonoOps {
-    u32 n, w;
+    u32 n, w, guard;
     u64 lanes, H;  // lane bits, lane top bits
     void init(u32 n_) {
         n = n_;
         w = lane_bits(n);
+        guard = 1u << (w - 1);
         lanes = (n * w >= 64) ? ~0ull : ((1ull << (n * w)) - 1);
         H = 0;
         for (u32 i = 0; i < n; ++i) H |= 1ull << (w * i + w - 1);
     }
     bool divides(u64 a, u64 b) const {  // a | b
+        if ((u32)(a >> 56) >= guard || (u32)(b >> 56) >= guard) return mono_divides(a, b, n, w);
         return ((((b & lanes) | H) - (a & lanes)) & H) == H;
     }
     u64 lcm(u64 a, u64 b) const {
+        if ((u32)(a >> 56) >= guard || (u32)(b >> 56) >= guard) return mono_lcm(a, b, n, w);
         u64 ge = (((a & lanes) | H) - (b & lanes)) & H;  // lanes where a >= b
         u64 m = (ge >> (w - 1)) * ((1ull << w) - 1);
         u64 l = (a & m) | (b & ~m & lanes);
@@ -326,34 +334,397 @@ static void load_polys(Ctx& c, const f4_polys* G, DevG& D) {
 
 static u32 deg_of(u64 P) { return (u32)(P >> 56); }
 
-// One F4 step's matrix for given halves; rows deduplicated on the host.
-static void build_step(Ctx& c, const DevG& D, std::vector<std::pair<u64, u32>>& rows, const std::vector<u32>& act,
-                       u32 deg, bool closure, Matrix& A) {
+// Per-system state of the F4 loop.  The basis lives on the device; the host
+// keeps leading monomials, activity flags and the pair set.
+struct SysState {
+    u32 n = 0, p = 0;
+    MonoOps mo;
+    DevG D;
+    std::vector<u64> lm;
+    std::vector<u8> active;
+    std::vector<HPair> P;
+    bool unit = false, done = false;
+    std::vector<f4_step_stats> steps;
+    // reduced basis (host), filled at the end
+    std::vector<u64> gmon, goff{0};
+    std::vector<u32> gcoeff;
+    // scratch of the current step
+    std::vector<u64> rt;
+    std::vector<u32> rk, act;
+    u32 d = 0, nsel = 0;
+    std::chrono::steady_clock::time_point t0;
+};
+
+// halves (t, k) deduplicated and sorted, active list (descending index)
+static void prepare_rows(SysState& S, std::vector<std::pair<u64, u32>>& rows) {
     std::sort(rows.begin(), rows.end());
     rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
-    const u32 r0 = (u32)rows.size();
-    std::vector<u64> t(r0);
-    std::vector<u32> k(r0);
-    for (u32 i = 0; i < r0; ++i) {
-        t[i] = rows[i].first;
-        k[i] = rows[i].second;
+    S.rt.resize(rows.size());
+    S.rk.resize(rows.size());
+    for (size_t i = 0; i < rows.size(); ++i) {
+        S.rt[i] = rows[i].first;
+        S.rk[i] = rows[i].second;
     }
-    DBuf<u64> dt(&c.pool, r0);
-    DBuf<u32> dk(&c.pool, r0), da(&c.pool, std::max<size_t>(act.size(), 1));
-    upload(c, dt.ptr, t.data(), (u64)r0 * 8);
-    upload(c, dk.ptr, k.data(), (u64)r0 * 4);
-    upload(c, da.ptr, act.data(), act.size() * 4);
-    BuildArgs a;
-    a.G = devg_view(D);
-    a.rows_t = dt.ptr;
-    a.rows_k = dk.ptr;
-    a.r0 = r0;
-    a.active = da.ptr;
-    a.nactive = (u32)act.size();
-    a.D = deg;
-    a.closure = closure;
-    build_matrix(c, a, A);
+    S.act.clear();
+    for (u32 g = S.D.npolys; g-- > 0;)
+        if (S.active.size() > g && S.active[g]) S.act.push_back(g);
 }
+
+static BuildArgs args_of(const SysState& S, bool closure) {
+    BuildArgs a;
+    a.G = devg_view(S.D);
+    a.rows_t_host = S.rt.data();
+    a.rows_k_host = S.rk.data();
+    a.r0 = (u32)S.rt.size();
+    a.active_host = S.act.data();
+    a.nactive = (u32)S.act.size();
+    a.D = S.d;
+    a.closure = closure;
+    return a;
+}
+
+// new basis elements of one system, appended on the device
+struct AppendSeg {
+    u32 row_base, rho;
+    u64 nnz_base;
+    u32 dict_base, poly_base;
+    u64 term_base;
+    u64* mon;
+    u32* coeff;
+    u64* off;
+    u64* lm;
+    u32* len;
+    u32 lm_out;  // first slot in the leading-monomial readback array
+    u32 pad;
+};
+
+// append the echelon rows (CSR over the matrix columns) as new basis elements,
+// with their leading monomial and length; one workgroup row per system
+__global__ void k_append(const AppendSeg* segs, const u32* rptr, const u32* rcol, const u32* rval,
+                         const u64* dict_keys, u64* lm_out) {
+    const AppendSeg A = segs[blockIdx.y];
+    const u32 e0 = rptr[A.row_base], e1 = rptr[A.row_base + A.rho];
+    for (u32 e = e0 + blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += gridDim.x * blockDim.x) {
+        A.mon[A.term_base + (e - e0)] = dict_keys[A.dict_base + rcol[e]];
+        A.coeff[A.term_base + (e - e0)] = rval[e];
+    }
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t <= A.rho; t += gridDim.x * blockDim.x) {
+        A.off[A.poly_base + t] = A.term_base + (rptr[A.row_base + t] - e0);
+        if (t < A.rho) {
+            const u64 l = dict_keys[A.dict_base + rcol[rptr[A.row_base + t]]];
+            A.lm[A.poly_base + t] = l;
+            A.len[A.poly_base + t] = rptr[A.row_base + t + 1] - rptr[A.row_base + t];
+            lm_out[A.lm_out + t] = l;
+        }
+    }
+}
+
+// P words of the tail entries of the final rows (dictionary of each row's system)
+__global__ void k_tail_words(const u32* tptr, const u32* tcol, const u32* row_sys, const u32* dict_base, u32 R,
+                             const u64* dict_keys, u64* out) {
+    for (u32 i = blockIdx.x; i < R; i += gridDim.x) {
+        const u32 db = dict_base[row_sys[i]];
+        for (u32 e = tptr[i] + threadIdx.x; e < tptr[i + 1]; e += blockDim.x) out[e] = dict_keys[db + tcol[e]];
+    }
+}
+
+// Normalise one input system and insert its polynomials (Gebauer-Moeller).
+static void init_system(Ctx& c, SysState& S, u32 p, const f4_polys* F) {
+    if (!F || F->on_device || F->n == 0 || F->n > 14 || !is_odd_prime(p) || p >= (1u << 31))
+        throw F4Error{F4_E_ARG, "bad argument"};
+    const u32 n = F->n;
+    S.n = n;
+    S.p = p;
+    S.mo.init(n);
+    const u32 w = S.mo.w;
+    std::vector<std::vector<std::pair<u64, u32>>> inputs;
+    for (u32 k = 0; k < F->npolys; ++k) {
+        std::vector<std::pair<u64, u32>> f;  // (order key, coeff)
+        for (u64 e = F->offset[k]; e < F->offset[k + 1]; ++e) {
+            const u64 P = F->mon[e];
+            if ((P & ~(S.mo.lanes | (0xffull << 56))) != 0) throw F4Error{F4_E_ARG, "bad monomial word"};
+            u32 d = 0;
+            for (u32 i = 0; i < n; ++i) d += mono_exp(P, i, w);
+            if (d != deg_of(P)) throw F4Error{F4_E_ARG, "monomial degree field mismatch"};
+            f.push_back({S.mo.order_key(P), (u32)(F->coeff[e] % p)});
+        }
+        std::sort(f.begin(), f.end(), [](auto& a, auto& b) { return a.first > b.first; });
+        std::vector<std::pair<u64, u32>> g;
+        for (auto& t : f) {
+            if (!g.empty() && g.back().first == t.first)
+                g.back().second = (u32)(((u64)g.back().second + t.second) % p);
+            else
+                g.push_back(t);
+        }
+        std::vector<std::pair<u64, u32>> h;
+        for (auto& t : g)
+            if (t.second) h.push_back({t.first ^ S.mo.lanes, t.second});  // back to P words
+        if (h.empty()) continue;
+        const u64 inv = powmod_host(h[0].second, p - 2, p);
+        for (auto& t : h) t.second = (u32)((u64)t.second * inv % p);
+        if (deg_of(h[0].first) == 0) S.unit = true;
+        inputs.push_back(std::move(h));
+    }
+    if (S.unit || inputs.empty()) {
+        S.done = true;
+        return;
+    }
+    DevG& D = S.D;
+    D.n = n;
+    std::vector<u64> mon, off{0};
+    std::vector<u32> coeff;
+    for (auto& f : inputs) {
+        for (auto& t : f) {
+            mon.push_back(t.first);
+            coeff.push_back(t.second);
+        }
+        off.push_back(mon.size());
+    }
+    devg_reserve(c, D, mon.size(), (u32)inputs.size());
+    upload(c, D.mon.ptr, mon.data(), mon.size() * 8);
+    upload(c, D.coeff.ptr, coeff.data(), coeff.size() * 4);
+    upload(c, D.off.ptr, off.data(), off.size() * 8);
+    D.npolys = (u32)inputs.size();
+    D.nterms = mon.size();
+    hipLaunchKernelGGL(k_basis_meta, dim3(gridn(D.npolys, 256, 1024)), dim3(256), 0, c.stream, D.mon.ptr, D.off.ptr,
+                       0u, D.npolys, D.lm.ptr, D.len.ptr);
+    F4_LAUNCH_CHECK();
+    for (u32 k = 0; k < D.npolys; ++k) {
+        S.lm.push_back(inputs[k][0].first);
+        S.active.push_back(0);
+        gm_update(S.mo, S.lm, S.active, S.P, k);
+    }
+}
+
+// One F4 iteration for a batch of systems: every system that still has pairs
+// advances by one step (symbolic preprocessing and elimination of all of them
+// in one batched launch sequence).  Returns the number of systems advanced.
+static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
+    {
+        std::vector<SysState*> work;
+        for (SysState* S : sys)
+            if (!S->done && !S->unit && !S->P.empty()) work.push_back(S);
+        if (work.empty()) return 0;
+        std::vector<BuildArgs> args;
+        std::vector<u32> primes;
+        for (SysState* S : work) {
+            S->t0 = std::chrono::steady_clock::now();
+            u32 d = 255;
+            for (auto& q : S->P) d = std::min(d, deg_of(q.lcm));
+            if (d >= (1u << S->mo.w)) throw F4Error{F4_E_RANGE, "step degree overflows an exponent lane"};
+            std::vector<HPair> sel, rest;
+            for (auto& q : S->P) (deg_of(q.lcm) == d ? sel : rest).push_back(q);
+            S->P.swap(rest);
+            std::vector<std::pair<u64, u32>> rows;
+            for (auto& q : sel) {
+                rows.push_back({q.lcm - S->lm[q.i], q.i});
+                rows.push_back({q.lcm - S->lm[q.j], q.j});
+            }
+            prepare_rows(*S, rows);
+            S->d = d;
+            S->nsel = (u32)sel.size();
+            args.push_back(args_of(*S, true));
+            primes.push_back(S->p);
+        }
+        Matrix A;
+        build_batch(c, args, A);
+        Reduced R;
+        reduce_batch(c, primes, A, R);
+        // ---- new elements: append the echelon rows to each basis on the device
+        std::vector<AppendSeg> ap;
+        std::vector<u32> lmbase(work.size(), 0);
+        u32 nl = 0, maxr = 1;
+        for (size_t i = 0; i < work.size(); ++i) {
+            SysState& S = *work[i];
+            const RedPart& P = R.sys[i];
+            lmbase[i] = nl;
+            if (!P.rho) continue;
+            devg_reserve(c, S.D, S.D.nterms + P.nnz, S.D.npolys + P.rho);
+            AppendSeg g;
+            std::memset(&g, 0, sizeof(g));
+            g.row_base = P.row_base;
+            g.rho = P.rho;
+            g.nnz_base = P.nnz_base;
+            g.dict_base = A.sys[i].dict_base;
+            g.poly_base = S.D.npolys;
+            g.term_base = S.D.nterms;
+            g.mon = S.D.mon.ptr;
+            g.coeff = S.D.coeff.ptr;
+            g.off = S.D.off.ptr;
+            g.lm = S.D.lm.ptr;
+            g.len = S.D.len.ptr;
+            g.lm_out = nl;
+            ap.push_back(g);
+            nl += P.rho;
+            maxr = std::max<u32>(maxr, std::max<u32>(P.rho, (u32)std::min<u64>(P.nnz, 1u << 30)));
+        }
+        std::vector<u64> newlm(nl);
+        if (!ap.empty()) {
+            DBuf<AppendSeg> dap(&c.pool, ap.size());
+            DBuf<u64> dlm(&c.pool, nl);
+            upload(c, dap.ptr, ap.data(), ap.size() * sizeof(AppendSeg));
+            hipLaunchKernelGGL(k_append, dim3(gridn(maxr, 256, 64), (u32)ap.size()), dim3(256), 0, c.stream, dap.ptr,
+                               R.row_ptr.ptr, R.col_ind.ptr, R.val.ptr, A.dict_keys.ptr, dlm.ptr);
+            F4_LAUNCH_CHECK();
+            readback(c, newlm.data(), dlm.ptr, (u64)nl * 8);
+        }
+        for (size_t i = 0; i < work.size(); ++i) {
+            SysState& S = *work[i];
+            const RedPart& P = R.sys[i];
+            const SysPart& M = A.sys[i];
+            S.D.npolys += P.rho;
+            S.D.nterms += P.nnz;
+            f4_step_stats st;
+            std::memset(&st, 0, sizeof(st));
+            st.deg = S.d;
+            st.nsel = S.nsel;
+            st.r = M.r;
+            st.N = M.N;
+            st.nnz = M.nnz;
+            st.npivot = P.npivot;
+            st.lower = P.lower;
+            st.rho = P.rho;
+            st.rank = P.rank;
+            st.closure_rounds = A.closure_rounds;
+            st.dict_path = A.dict_path;
+            st.t_dict_ms = A.t_dict;
+            st.t_assemble_ms = A.t_assemble;
+            st.t_numeric_ms = R.t_split + R.t_trsm + R.t_echelon + R.t_emit;
+            st.t_trsm_ms = R.t_trsm;
+            st.t_echelon_ms = R.t_echelon;
+            for (u32 t = 0; t < P.rho && !S.unit; ++t) {
+                const u32 h = (u32)S.lm.size();
+                S.lm.push_back(newlm[lmbase[i] + t]);
+                S.active.push_back(0);
+                if (deg_of(newlm[lmbase[i] + t]) == 0) {
+                    S.unit = true;
+                    break;
+                }
+                gm_update(S.mo, S.lm, S.active, S.P, h);
+            }
+            st.t_step_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - S.t0).count();
+            S.steps.push_back(st);
+        }
+        c.ev_used = 0;
+        return work.size();
+    }
+}
+
+// Reduced bases of the systems that have no pairs left: minimal leading
+// monomials, tails reduced by the others (all such systems in one batch).
+static void f4_finish(Ctx& c, const std::vector<SysState*>& sys) {
+    std::vector<SysState*> fin;
+    std::vector<BuildArgs> args;
+    std::vector<u32> primes;
+    std::vector<std::set<u32>> minimal;
+    for (SysState* S : sys) {
+        if (S->done || (!S->unit && !S->P.empty())) continue;
+        S->done = true;
+        if (S->unit) continue;
+        std::vector<u32> mins;
+        for (u32 g = 0; g < S->lm.size(); ++g) {
+            if (!S->active[g]) continue;
+            bool mn = true;
+            for (u32 h = 0; h < S->lm.size() && mn; ++h)
+                if (h != g && S->active[h] && S->mo.divides(S->lm[h], S->lm[g])) mn = false;
+            if (mn) mins.push_back(g);
+        }
+        std::vector<std::pair<u64, u32>> rows;
+        u32 dmax = 0;
+        for (u32 g : mins) {
+            rows.push_back({0ull, g});
+            dmax = std::max(dmax, deg_of(S->lm[g]));
+        }
+        prepare_rows(*S, rows);
+        S->d = dmax;
+        fin.push_back(S);
+        args.push_back(args_of(*S, true));
+        primes.push_back(S->p);
+        minimal.emplace_back(mins.begin(), mins.end());
+    }
+    if (fin.empty()) return;
+    Matrix A;
+    build_batch(c, args, A);
+    DBuf<u32> tptr, tcol, tval;
+    tail_reduce_batch(c, primes, A, tptr, tcol, tval);
+    const u32 R = A.R;
+    std::vector<u64> rt(R);
+    std::vector<u32> rk(R), hp((u64)R + 1);
+    readback(c, rt.data(), A.row_t.ptr, (u64)R * 8);
+    readback(c, rk.data(), A.row_k.ptr, (u64)R * 4);
+    readback(c, hp.data(), tptr.ptr, ((u64)R + 1) * 4);
+    const u32 nt = hp[R];
+    std::vector<u64> hw(nt);
+    std::vector<u32> hv(nt);
+    if (nt) {
+        std::vector<u32> db(fin.size());
+        for (size_t i = 0; i < fin.size(); ++i) db[i] = A.sys[i].dict_base;
+        DBuf<u32> ddb(&c.pool, db.size());
+        DBuf<u64> dw(&c.pool, nt);
+        upload(c, ddb.ptr, db.data(), db.size() * 4);
+        hipLaunchKernelGGL(k_tail_words, dim3(gridn(R, 1, 4096)), dim3(64), 0, c.stream, tptr.ptr, tcol.ptr,
+                           A.row_sys.ptr, ddb.ptr, R, A.dict_keys.ptr, dw.ptr);
+        F4_LAUNCH_CHECK();
+        readback(c, hw.data(), dw.ptr, (u64)nt * 8);
+        readback(c, hv.data(), tval.ptr, (u64)nt * 4);
+    }
+    for (size_t i = 0; i < fin.size(); ++i) {
+        SysState& S = *fin[i];
+        const SysPart& M = A.sys[i];
+        std::set<u32>& mset = minimal[i];
+        // rows of a system are sorted by leading monomial, largest first
+        for (u32 r = M.row_base; r < M.row_base + M.r; ++r) {
+            if (rt[r] != 0 || !mset.count(rk[r])) continue;
+            S.gmon.push_back(S.lm[rk[r]]);
+            S.gcoeff.push_back(1);
+            for (u32 e = hp[r]; e < hp[r + 1]; ++e) {
+                S.gmon.push_back(hw[e]);
+                S.gcoeff.push_back(hv[e]);
+            }
+            S.goff.push_back(S.gmon.size());
+            mset.erase(rk[r]);
+        }
+        if (!mset.empty()) throw F4Error{F4_E_STATE, "inter-reduction lost a basis element"};
+    }
+}
+
+// The F4 loop for a batch of systems, then their reduced bases.
+static void run_f4(Ctx& c, std::vector<SysState*>& sys) {
+    while (f4_iterate(c, sys)) {
+    }
+    f4_finish(c, sys);
+}
+
+static f4_basis* basis_of(f4_ctx* X, SysState& S) {
+    f4_basis* B = new f4_basis();
+    B->owner = X;
+    B->n = S.n;
+    if (S.unit) {
+        B->mon = {0};
+        B->coeff = {1};
+        B->off = {0, 1};
+    } else {
+        B->mon = std::move(S.gmon);
+        B->coeff = std::move(S.gcoeff);
+        B->off = std::move(S.goff);
+    }
+    B->steps = std::move(S.steps);
+    return B;
+}
+
+// ---------------------------------------------------------------- serving state
+struct ServerReq {
+    u64 footprint = 0;
+    std::unique_ptr<SysState> st;
+};
+
+struct f4_server {
+    f4_ctx* owner = nullptr;
+    u64 budget = 0, used = 0;
+    u32 max_slots = 0;
+    u64 next_ticket = 1;
+    std::map<u64, ServerReq> reqs;
+};
 
 // ====================================================================== API
 extern "C" {
@@ -389,6 +760,8 @@ int f4_destroy(f4_ctx* X) {
     (void)hipSetDevice(X->c.dev.device);
     if (X->c.stream) (void)hipStreamSynchronize(X->c.stream);
     // live handles own pool memory: free them before the pool goes
+    for (f4_server* v : X->servers) delete v;
+    X->servers.clear();
     for (f4_matrix* m : X->matrices) delete m;
     for (f4_reduced* r : X->reduceds) delete r;
     for (f4_basis* b : X->bases) delete b;
@@ -499,10 +872,15 @@ int f4_build_matrix(f4_ctx* X, uint32_t p, const f4_polys* G, const uint8_t* act
     std::vector<u32> act;
     for (u32 g = D.npolys; g-- > 0;)
         if (active[g]) act.push_back(g);
+    SysState st;
+    st.D = std::move(D);
+    st.d = deg;
+    prepare_rows(st, rows);
+    st.act = act;
     f4_matrix* M = new f4_matrix();
     M->owner = X;
     try {
-        build_step(c, D, rows, act, deg, true, M->m);
+        build_batch(c, std::vector<BuildArgs>{args_of(st, true)}, M->m);
     } catch (...) {
         delete M;
         throw;
@@ -536,11 +914,15 @@ int f4_build_matrix_rows(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_rows
         rows.push_back({R[i].t, R[i].k});
     }
     if (deg >= (1u << w)) throw F4Error{F4_E_RANGE, "degree overflows an exponent lane"};
-    std::vector<u32> act;
+    SysState st;
+    st.D = std::move(D);
+    st.d = deg;
+    prepare_rows(st, rows);
+    st.act.clear();
     f4_matrix* M = new f4_matrix();
     M->owner = X;
     try {
-        build_step(c, D, rows, act, deg, false, M->m);
+        build_batch(c, std::vector<BuildArgs>{args_of(st, false)}, M->m);
     } catch (...) {
         delete M;
         throw;
@@ -569,9 +951,15 @@ int f4_matrix_from_csr(f4_ctx* X, uint32_t r, uint32_t N, const uint32_t* row_pt
     f4_matrix* M = new f4_matrix();
     M->owner = X;
     Matrix& m = M->m;
-    m.r = r;
-    m.N = N;
+    m.S = 1;
+    m.R = r;
     m.nnz = nnz;
+    m.sys.assign(1, SysPart());
+    m.sys[0].r = r;
+    m.sys[0].N = N;
+    m.sys[0].nnz = nnz;
+    m.row_sys.reset(&c.pool, std::max<u32>(r, 1));
+    fill_u32(m.row_sys.ptr, r, 0, c.stream);
     m.row_ptr.reset(&c.pool, (u64)r + 1);
     m.col_ind.reset(&c.pool, std::max<u32>(nnz, 1));
     m.val.reset(&c.pool, std::max<u32>(nnz, 1));
@@ -586,11 +974,12 @@ int f4_matrix_from_csr(f4_ctx* X, uint32_t r, uint32_t N, const uint32_t* row_pt
 int f4_matrix_get(const f4_matrix* A, f4_matrix_view* out) {
     if (!A || !out) return F4_E_ARG;
     const Matrix& m = A->m;
-    out->n = m.n;
-    out->r = m.r;
-    out->N = m.N;
-    out->deg = m.deg;
-    out->nnz = m.nnz;
+    const SysPart& P = m.sys[0];
+    out->n = P.n;
+    out->r = P.r;
+    out->N = P.N;
+    out->deg = P.deg;
+    out->nnz = P.nnz;
     out->row_ptr = m.row_ptr.ptr;
     out->col_ind = m.col_ind.ptr;
     out->val = m.val.ptr;
@@ -615,7 +1004,7 @@ int f4_reduce(f4_ctx* X, uint32_t p, const f4_matrix* A, f4_reduced** out, void*
     f4_reduced* R = new f4_reduced();
     R->owner = X;
     try {
-        reduce_matrix(X->c, p, A->m, R->r);
+        reduce_batch(X->c, std::vector<u32>{p}, A->m, R->r);
     } catch (...) {
         delete R;
         throw;
@@ -628,11 +1017,12 @@ int f4_reduce(f4_ctx* X, uint32_t p, const f4_matrix* A, f4_reduced** out, void*
 int f4_reduced_get(const f4_reduced* R, f4_reduced_view* out) {
     if (!R || !out) return F4_E_ARG;
     const Reduced& r = R->r;
-    out->N = r.N;
-    out->npivot = r.npivot;
-    out->rho = r.rho;
-    out->rank = r.rank;
-    out->nnz = r.nnz;
+    const RedPart& P = r.sys[0];
+    out->N = P.N;
+    out->npivot = P.npivot;
+    out->rho = P.rho;
+    out->rank = P.rank;
+    out->nnz = P.nnz;
     out->pivot_cols = r.pivot_cols.ptr;
     out->row_ptr = r.row_ptr.ptr;
     out->col_ind = r.col_ind.ptr;
@@ -649,210 +1039,37 @@ int f4_reduced_free(f4_reduced* R) {
 
 int f4_groebner(f4_ctx* X, uint32_t p, const f4_polys* F, f4_basis** gb, void* stream) {
     F4_API_BEGIN(X)
-    if (!gb || !F || F->on_device || F->n == 0 || F->n > 14 || !is_odd_prime(p) || p >= (1u << 31))
-        throw F4Error{F4_E_ARG, "bad argument"};
+    if (!gb) throw F4Error{F4_E_ARG, "bad argument"};
     *gb = nullptr;
     set_stream(X, stream);
-    Ctx& c = X->c;
-    const u32 n = F->n;
-    MonoOps mo;
-    mo.init(n);
-    const u32 w = mo.w;
-    // ---- normalise inputs: reduce mod p, merge, sort by monomial, drop zeros, monic
-    std::vector<std::vector<std::pair<u64, u32>>> inputs;
-    bool unit = false;
-    for (u32 k = 0; k < F->npolys; ++k) {
-        std::vector<std::pair<u64, u32>> f;  // (order key, coeff)
-        for (u64 e = F->offset[k]; e < F->offset[k + 1]; ++e) {
-            const u64 P = F->mon[e];
-            if ((P & ~(mo.lanes | (0xffull << 56))) != 0) throw F4Error{F4_E_ARG, "bad monomial word"};
-            u32 d = 0;
-            for (u32 i = 0; i < n; ++i) d += mono_exp(P, i, w);
-            if (d != deg_of(P)) throw F4Error{F4_E_ARG, "monomial degree field mismatch"};
-            f.push_back({mo.order_key(P), (u32)(F->coeff[e] % p)});
-        }
-        std::sort(f.begin(), f.end(), [](auto& a, auto& b) { return a.first > b.first; });
-        std::vector<std::pair<u64, u32>> g;
-        for (auto& t : f) {
-            if (!g.empty() && g.back().first == t.first)
-                g.back().second = (u32)(((u64)g.back().second + t.second) % p);
-            else
-                g.push_back(t);
-        }
-        std::vector<std::pair<u64, u32>> h;
-        for (auto& t : g)
-            if (t.second) h.push_back({t.first ^ mo.lanes, t.second});  // back to P words
-        if (h.empty()) continue;
-        const u64 inv = powmod_host(h[0].second, p - 2, p);
-        for (auto& t : h) t.second = (u32)((u64)t.second * inv % p);
-        if (deg_of(h[0].first) == 0) unit = true;
-        inputs.push_back(std::move(h));
-    }
-    f4_basis* B = new f4_basis();
-    B->owner = X;
-    B->n = n;
-    std::unique_ptr<f4_basis> Bguard(B);
-    B->off.push_back(0);
-    auto finish_unit = [&]() {
-        B->mon = {0};
-        B->coeff = {1};
-        B->off = {0, 1};
-    };
-    if (unit) {
-        finish_unit();
-    } else if (!inputs.empty()) {
-        DevG D;
-        D.n = n;
-        std::vector<u64> lm;
-        std::vector<u8> active;
-        std::vector<HPair> P;
-        // ---- upload inputs, GM-insert each in order
-        {
-            std::vector<u64> mon, off{0};
-            std::vector<u32> coeff;
-            for (auto& f : inputs) {
-                for (auto& t : f) {
-                    mon.push_back(t.first);
-                    coeff.push_back(t.second);
-                }
-                off.push_back(mon.size());
-            }
-            devg_reserve(c, D, mon.size(), (u32)inputs.size());
-            upload(c, D.mon.ptr, mon.data(), mon.size() * 8);
-            upload(c, D.coeff.ptr, coeff.data(), coeff.size() * 4);
-            upload(c, D.off.ptr, off.data(), off.size() * 8);
-            D.npolys = (u32)inputs.size();
-            D.nterms = mon.size();
-            hipLaunchKernelGGL(k_basis_meta, dim3(gridn(D.npolys, 256, 1024)), dim3(256), 0, c.stream, D.mon.ptr,
-                               D.off.ptr, 0u, D.npolys, D.lm.ptr, D.len.ptr);
-            F4_LAUNCH_CHECK();
-            for (u32 k = 0; k < D.npolys; ++k) {
-                lm.push_back(inputs[k][0].first);
-                active.push_back(0);
-                gm_update(mo, lm, active, P, k);
-            }
-        }
-        const u32 guard = 1u << (w - 1);
-        while (!unit && !P.empty()) {
-            auto t0 = std::chrono::steady_clock::now();
-            u32 d = 255;
-            for (auto& q : P) d = std::min(d, deg_of(q.lcm));
-            if (d >= guard) throw F4Error{F4_E_RANGE, "step degree reaches an exponent lane's guard bit"};
-            std::vector<HPair> sel, rest;
-            for (auto& q : P) (deg_of(q.lcm) == d ? sel : rest).push_back(q);
-            P.swap(rest);
-            std::vector<std::pair<u64, u32>> rows;
-            for (auto& q : sel) {
-                rows.push_back({q.lcm - lm[q.i], q.i});
-                rows.push_back({q.lcm - lm[q.j], q.j});
-            }
-            std::vector<u32> act;
-            for (u32 g = D.npolys; g-- > 0;)
-                if (active[g]) act.push_back(g);
-            Matrix A;
-            build_step(c, D, rows, act, d, true, A);
-            Reduced R;
-            reduce_matrix(c, p, A, R);
-            // ---- new elements: append the echelon rows to G on the device
-            const u32 rho = R.rho;
-            std::vector<u64> newlm(rho);
-            if (rho) {
-                devg_reserve(c, D, D.nterms + R.nnz, D.npolys + rho);
-                hipLaunchKernelGGL(k_append, dim3(gridn(std::max<u64>(R.nnz, rho + 1), 256, 4096)), dim3(256), 0,
-                                   c.stream, R.row_ptr.ptr, R.col_ind.ptr, R.val.ptr, rho, A.dict_keys.ptr, D.nterms,
-                                   D.npolys, D.mon.ptr, D.coeff.ptr, D.off.ptr);
-                F4_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_basis_meta, dim3(gridn(rho, 256, 1024)), dim3(256), 0, c.stream, D.mon.ptr,
-                                   D.off.ptr, D.npolys, D.npolys + rho, D.lm.ptr, D.len.ptr);
-                F4_LAUNCH_CHECK();
-                readback(c, newlm.data(), D.lm.ptr + D.npolys, (u64)rho * 8);
-                D.npolys += rho;
-                D.nterms += R.nnz;
-            }
-            f4_step_stats st;
-            memset(&st, 0, sizeof(st));
-            st.deg = d;
-            st.nsel = (u32)sel.size();
-            st.r = A.r;
-            st.N = A.N;
-            st.nnz = A.nnz;
-            st.npivot = R.npivot;
-            st.lower = R.lower;
-            st.rho = rho;
-            st.rank = R.rank;
-            st.closure_rounds = A.closure_rounds;
-            st.dict_path = A.dict_path;
-            st.t_dict_ms = A.t_dict;
-            st.t_assemble_ms = A.t_assemble;
-            st.t_numeric_ms = R.t_split + R.t_trsm + R.t_echelon + R.t_emit;
-            st.t_trsm_ms = R.t_trsm;
-            st.t_echelon_ms = R.t_echelon;
-            for (u32 t = 0; t < rho && !unit; ++t) {
-                const u32 h = (u32)lm.size();
-                lm.push_back(newlm[t]);
-                active.push_back(0);
-                if (deg_of(newlm[t]) == 0) {
-                    unit = true;
-                    break;
-                }
-                gm_update(mo, lm, active, P, h);
-            }
-            st.t_step_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            B->steps.push_back(st);
-            c.ev_used = 0;
-        }
-        if (unit) {
-            finish_unit();
-        } else {
-            // ---- reduced basis: minimal leading monomials, tails reduced by the others
-            std::vector<u32> minimal;
-            for (u32 g = 0; g < lm.size(); ++g) {
-                if (!active[g]) continue;
-                bool mn = true;
-                for (u32 h = 0; h < lm.size() && mn; ++h)
-                    if (h != g && active[h] && mo.divides(lm[h], lm[g])) mn = false;
-                if (mn) minimal.push_back(g);
-            }
-            std::vector<std::pair<u64, u32>> rows;
-            u32 dmax = 0;
-            for (u32 g : minimal) {
-                rows.push_back({0ull, g});
-                dmax = std::max(dmax, deg_of(lm[g]));
-            }
-            std::vector<u32> act;
-            for (u32 g = D.npolys; g-- > 0;)
-                if (active[g]) act.push_back(g);
-            Matrix A;
-            build_step(c, D, rows, act, dmax, true, A);
-            DBuf<u32> tptr, tcol, tval;
-            tail_reduce_matrix(c, p, A, tptr, tcol, tval);
-            std::vector<u64> rt(A.r), dict(A.N);
-            std::vector<u32> rk(A.r), hp((u64)A.r + 1);
-            readback(c, rt.data(), A.row_t.ptr, (u64)A.r * 8);
-            readback(c, rk.data(), A.row_k.ptr, (u64)A.r * 4);
-            readback(c, dict.data(), A.dict_keys.ptr, (u64)A.N * 8);
-            readback(c, hp.data(), tptr.ptr, ((u64)A.r + 1) * 4);
-            std::vector<u32> hc(hp[A.r]), hv(hp[A.r]);
-            readback(c, hc.data(), tcol.ptr, (u64)hp[A.r] * 4);
-            readback(c, hv.data(), tval.ptr, (u64)hp[A.r] * 4);
-            std::set<u32> mset(minimal.begin(), minimal.end());
-            // rows of A are sorted by leading monomial, largest first
-            for (u32 i = 0; i < A.r; ++i) {
-                if (rt[i] != 0 || !mset.count(rk[i])) continue;
-                B->mon.push_back(lm[rk[i]]);
-                B->coeff.push_back(1);
-                for (u32 e = hp[i]; e < hp[i + 1]; ++e) {
-                    B->mon.push_back(dict[hc[e]]);
-                    B->coeff.push_back(hv[e]);
-                }
-                B->off.push_back(B->mon.size());
-                mset.erase(rk[i]);
-            }
-            if (!mset.empty()) throw F4Error{F4_E_STATE, "inter-reduction lost a basis element"};
-        }
-    }
+    SysState S;
+    init_system(X->c, S, p, F);
+    std::vector<SysState*> v{&S};
+    run_f4(X->c, v);
+    f4_basis* B = basis_of(X, S);
     X->bases.insert(B);
-    *gb = Bguard.release();
+    *gb = B;
+    F4_API_END(X)
+}
+
+int f4_groebner_batch(f4_ctx* X, uint32_t nsys, const uint32_t* p, const f4_polys* F, f4_basis** gb,
+                      void* stream) {
+    F4_API_BEGIN(X)
+    if (!gb || !p || !F || nsys == 0) throw F4Error{F4_E_ARG, "bad argument"};
+    for (u32 i = 0; i < nsys; ++i) gb[i] = nullptr;
+    set_stream(X, stream);
+    std::vector<std::unique_ptr<SysState>> own(nsys);
+    std::vector<SysState*> v;
+    for (u32 i = 0; i < nsys; ++i) {
+        own[i].reset(new SysState());
+        init_system(X->c, *own[i], p[i], &F[i]);
+        v.push_back(own[i].get());
+    }
+    run_f4(X->c, v);
+    for (u32 i = 0; i < nsys; ++i) {
+        gb[i] = basis_of(X, *own[i]);
+        X->bases.insert(gb[i]);
+    }
     F4_API_END(X)
 }
 
@@ -878,6 +1095,122 @@ int f4_basis_free(f4_basis* B) {
     if (!B) return F4_E_ARG;
     B->owner->bases.erase(B);
     delete B;
+    return F4_OK;
+}
+
+
+// ---------------------------------------------------------------- serving
+}  // extern "C"
+
+static u64 footprint_of(u32 n, u32 m) {
+    // degree of regularity of m generic quadratics in n variables
+    std::vector<long double> hs(64, 0.0L);
+    hs[0] = 1;
+    for (u32 k = 0; k < m; ++k)  // multiply by (1 - t^2)
+        for (int d = 63; d >= 2; --d) hs[d] -= hs[d - 2];
+    for (u32 k = 0; k < n; ++k)  // divide by (1 - t)
+        for (int d = 1; d < 64; ++d) hs[d] += hs[d - 1];
+    u32 D = 63;
+    for (u32 d = 0; d < 64; ++d)
+        if (hs[d] <= 0) {
+            D = d;
+            break;
+        }
+    if (D < 2) D = 2;
+    const long double a = (long double)binom_host(n + D, n), b = (long double)binom_host(n + D - 1, n);
+    const long double bytes = 8.0L * a * b + (long double)(64u << 20);
+    return bytes > 1.8e19L ? ~0ull : (u64)bytes;
+}
+
+extern "C" {
+
+int f4_server_footprint(uint32_t n, uint32_t m, uint64_t* bytes) {
+    if (!bytes || n == 0 || n > 14) return F4_E_ARG;
+    *bytes = footprint_of(n, m);
+    return F4_OK;
+}
+
+int f4_server_create(f4_ctx* X, uint64_t hbm_budget, uint32_t max_slots, f4_server** out) {
+    F4_API_BEGIN(X)
+    if (!out || max_slots == 0) throw F4Error{F4_E_ARG, "bad argument"};
+    f4_server* S = new f4_server();
+    S->owner = X;
+    S->budget = hbm_budget;
+    S->max_slots = max_slots;
+    X->servers.insert(S);
+    *out = S;
+    F4_API_END(X)
+}
+
+int f4_server_submit(f4_server* srv, uint32_t p, const f4_polys* F, uint64_t* ticket) {
+    if (!srv) return F4_E_ARG;
+    f4_ctx* X = srv->owner;
+    F4_API_BEGIN(X)
+    if (!F || !ticket) throw F4Error{F4_E_ARG, "bad argument"};
+    const u64 fp = footprint_of(F->n ? F->n : 1, F->npolys);
+    if (srv->reqs.size() >= srv->max_slots || srv->used + fp > srv->budget) return F4_E_BUSY;
+    set_stream(X, nullptr);
+    ServerReq r;
+    r.footprint = fp;
+    r.st.reset(new SysState());
+    init_system(X->c, *r.st, p, F);
+    srv->used += fp;
+    const u64 t = srv->next_ticket++;
+    srv->reqs.emplace(t, std::move(r));
+    *ticket = t;
+    F4_API_END(X)
+}
+
+int f4_server_step(f4_server* srv, uint32_t* completed) {
+    if (!srv) return F4_E_ARG;
+    f4_ctx* X = srv->owner;
+    F4_API_BEGIN(X)
+    set_stream(X, nullptr);
+    std::vector<SysState*> live;
+    for (auto& kv : srv->reqs)
+        if (!kv.second.st->done) live.push_back(kv.second.st.get());
+    f4_iterate(X->c, live);
+    f4_finish(X->c, live);
+    u32 k = 0;
+    for (SysState* S : live) k += S->done ? 1 : 0;
+    if (completed) *completed = k;
+    F4_API_END(X)
+}
+
+int f4_server_poll(f4_server* srv, uint64_t ticket, f4_basis** gb, int* done) {
+    if (!srv) return F4_E_ARG;
+    f4_ctx* X = srv->owner;
+    F4_API_BEGIN(X)
+    if (!gb || !done) throw F4Error{F4_E_ARG, "bad argument"};
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) throw F4Error{F4_E_STATE, "unknown ticket"};
+    *done = 0;
+    *gb = nullptr;
+    if (it->second.st->done) {
+        f4_basis* B = basis_of(X, *it->second.st);
+        X->bases.insert(B);
+        *gb = B;
+        *done = 1;
+        srv->used -= it->second.footprint;
+        srv->reqs.erase(it);
+    }
+    F4_API_END(X)
+}
+
+int f4_server_load(const f4_server* srv, uint32_t* resident, uint32_t* running, uint64_t* used) {
+    if (!srv) return F4_E_ARG;
+    u32 run = 0;
+    for (auto& kv : srv->reqs) run += kv.second.st->done ? 0 : 1;
+    if (resident) *resident = (u32)srv->reqs.size();
+    if (running) *running = run;
+    if (used) *used = srv->used;
+    return F4_OK;
+}
+
+int f4_server_destroy(f4_server* srv) {
+    if (!srv) return F4_E_ARG;
+    srv->owner->servers.erase(srv);
+    delete srv;
     return F4_OK;
 }
 

@@ -1,6 +1,9 @@
-// Symbolic preprocessing SP : B -> (T, R, Pi) on gfx950 (Definition "Symbolic
-// preprocessing operator"; Algorithm "FBSP"; section "FBSP: frontier-based
-// symbolic preprocessing as bulk set algebra").
+// Symbolic preprocessing SP : B -> (T, R, Pi) on gfx950 for a batch of
+// independent systems (Definition "Symbolic preprocessing operator";
+// Algorithm "FBSP"; section "FBSP: frontier-based symbolic preprocessing as
+// bulk set algebra").  One launch of each kernel covers every system of the
+// batch: per-system work uses a 2-D grid (blockIdx.y = system), flat work
+// carries a system index per element.  A single system is the batch of one.
 //
 // Monomials of a step all have degree <= D, so the dictionary T lives inside
 // Mon_{<=D}, which the dense grevlex rank maps order-isomorphically onto
@@ -45,8 +48,7 @@ const u32* rank_table(Ctx& c, u32 n, u32 D) {
             tab[(size_t)x * F4_BSTRIDE + y] = v > 0xffffffffull ? 0xffffffffu : (u32)v;
         }
     DBuf<u32> buf(&c.pool, tab.size());
-    F4_HIP_TRY(hipMemcpyAsync(buf.ptr, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, c.stream));
-    F4_HIP_TRY(hipStreamSynchronize(c.stream));
+    upload(c, buf.ptr, tab.data(), tab.size() * 4);
     const u32* p = buf.ptr;
     c.binom.emplace(key, std::move(buf));
     return p;
@@ -72,110 +74,147 @@ const u64* unrank_table(Ctx& c, u32 n, u32 D) {
     return p;
 }
 
+// ----------------------------------------------------- per-system descriptor
+struct SegSP {
+    const u64* mon;
+    const u32* coeff;
+    const u64* off;
+    const u64* lm;
+    const u32* len;
+    const u32* binom;
+    const u64* montab;
+    u32 n, w, D, nmax;
+    u32 wbase, nwords;   // bitmap words [wbase, wbase + nwords)
+    u32 rbase, rcap;     // raw rows [rbase, rbase + rcap)
+    u32 abase, nactive;  // active basis indices (descending)
+    u32 tabn, npolys;
+    u32 cmbase;          // colmap / dictionary capacity base
+    u32 obase, r;        // ordered rows [obase, obase + r) (after the closure)
+    u32 ibase, r0;       // initial rows in the packed upload
+};
+
+// counters per system: [0] row range begin, [1] row range end (= rows so
+// far), [2] unused, [3] error (1 bad monomial, 2 row capacity)
+#define CTR 4
+
 // ----------------------------------------------------------- row emission
-// Rows [range[0], range[1]): record the rank of each row's leading monomial,
-// mark it processed, and mark the rank of every term t * m of the row as seen.
-// One wave per row, lanes over the terms; the seen-bits are gathered in an LDS
-// bitmap per workgroup and flushed with one atomic OR per nonzero word.
-__global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const u64* rows_t, const u32* rows_k, u32* row_lmrank,
-                                                           const u32* range, DevBasis G, const u32* binom_g,
-                                                           u32 tabn, u32 D, u32* present, u32* done, u32 nwords,
-                                                           int local_bitmap, u32* errflag) {
+// Rows of the current range of system blockIdx.y: record the rank of each
+// row's leading monomial, mark it processed, and mark the rank of every term
+// t * m of the row as seen.  One wave per row, lanes over terms; seen-bits are
+// gathered in an LDS bitmap per workgroup, flushed with one atomic OR per
+// nonzero word.
+__global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, const u64* rows_t, const u32* rows_k,
+                                                           u32* row_lmrank, u32* ctr, u32* present, u32* done,
+                                                           int local_bitmap) {
     extern __shared__ u32 sm[];
+    const SegSP S = segs[blockIdx.y];
     u32* tab = sm;
-    u32* lbits = sm + tabn;
-    for (u32 i = threadIdx.x; i < tabn; i += MB_THREADS) tab[i] = binom_g[i];
+    u32* lbits = sm + S.tabn;
+    for (u32 i = threadIdx.x; i < S.tabn; i += MB_THREADS) tab[i] = S.binom[i];
     if (local_bitmap)
-        for (u32 i = threadIdx.x; i < nwords; i += MB_THREADS) lbits[i] = 0;
+        for (u32 i = threadIdx.x; i < S.nwords; i += MB_THREADS) lbits[i] = 0;
     __syncthreads();
-    const u32 n = G.n, w = G.w, lane = lane_id();
-    const u32 rb = range[0], re = range[1];
+    u32* C = ctr + CTR * blockIdx.y;
+    u32* P = present + S.wbase;
+    u32* Dn = done + S.wbase;
+    const u32 n = S.n, w = S.w, D = S.D, lane = lane_id();
+    const u32 rb = C[0], re = C[1];
     const u32 nw_total = gridDim.x * MB_WAVES;
     for (u32 row = rb + blockIdx.x * MB_WAVES + threadIdx.x / F4_WAVE; row < re; row += nw_total) {
-        const u64 t = rows_t[row];
-        const u32 k = rows_k[row];
+        const u64 t = rows_t[S.rbase + row];
+        const u32 k = rows_k[S.rbase + row];
         if (lane == 0) {
-            u32 q = mono_rank(t + G.lm[k], n, w, D, tab);
+            u32 q = mono_rank(t + S.lm[k], n, w, D, tab);
             if (q == F4_BAD_RANK) {
-                errflag[0] = 1u;
+                C[3] = 1u;
                 q = 0;
             }
-            row_lmrank[row] = q;
-            atomicOr(&done[q >> 5], 1u << (q & 31));
+            row_lmrank[S.rbase + row] = q;
+            atomicOr(&Dn[q >> 5], 1u << (q & 31));
         }
-        const u64 off = G.off[k];
-        const u32 len = G.len[k];
+        const u64 off = S.off[k];
+        const u32 len = S.len[k];
         for (u32 j = lane; j < len; j += F4_WAVE) {
-            u32 q = mono_rank(t + G.mon[off + j], n, w, D, tab);
+            const u32 q = mono_rank(t + S.mon[off + j], n, w, D, tab);
             if (q == F4_BAD_RANK) {
-                errflag[0] = 1u;
+                C[3] = 1u;
                 continue;
             }
             if (local_bitmap)
                 atomicOr(&lbits[q >> 5], 1u << (q & 31));
             else
-                atomicOr(&present[q >> 5], 1u << (q & 31));
+                atomicOr(&P[q >> 5], 1u << (q & 31));
         }
     }
     if (local_bitmap) {
         __syncthreads();
-        for (u32 i = threadIdx.x; i < nwords; i += MB_THREADS) {
-            u32 v = lbits[i];
-            if (v) atomicOr(&present[i], v);
+        for (u32 i = threadIdx.x; i < S.nwords; i += MB_THREADS) {
+            const u32 v = lbits[i];
+            if (v) atomicOr(&P[i], v);
         }
     }
 }
 
-// frontier = seen and not processed
+// scatter the packed initial rows of every system into its row segment
+__global__ void k_init_rows(const SegSP* segs, const u64* t0, const u32* k0, u64* rows_t, u32* rows_k) {
+    const SegSP S = segs[blockIdx.y];
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < S.r0; i += gridDim.x * blockDim.x) {
+        rows_t[S.rbase + i] = t0[S.ibase + i];
+        rows_k[S.rbase + i] = k0[S.ibase + i];
+    }
+}
+
+// frontier = seen and not processed (flat over all bitmap words)
 __global__ void k_frontier_count(const u32* present, const u32* done, u32 nwords, u32* cnt) {
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x)
         cnt[i] = __popc(present[i] & ~done[i]);
 }
 
-// write frontier ranks in ascending order, mark them processed, and open a
-// new row range [range[1], ...) for the reducer rows appended next
-__global__ void k_frontier_write(const u32* present, u32* done, u32 nwords, const u32* off, u32* list, u32* range) {
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) {
-        u32 f = present[i] & ~done[i];
+// write the frontier ranks of system blockIdx.y (ascending), mark them
+// processed, and open the system's next row range at its current row count
+__global__ void k_frontier_write(const SegSP* segs, const u32* present, u32* done, const u32* off, u32* list_q,
+                                 u32* list_s, u32* ctr) {
+    const u32 s = blockIdx.y;
+    const SegSP S = segs[s];
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < S.nwords; i += gridDim.x * blockDim.x) {
+        const u32 wi = S.wbase + i;
+        u32 f = present[wi] & ~done[wi];
         if (!f) continue;
-        done[i] |= f;
-        u32 pos = off[i];
+        done[wi] |= f;
+        u32 pos = off[wi];
         while (f) {
-            u32 b = __ffs(f) - 1;
-            list[pos++] = i * 32 + b;
+            const u32 b = __ffs(f) - 1;
+            list_q[pos] = i * 32 + b;
+            list_s[pos] = s;
+            ++pos;
             f &= f - 1;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) range[0] = range[1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[CTR * s] = ctr[CTR * s + 1];
 }
 
 // One reducer per frontier monomial m: the active element with the largest
 // index whose leading monomial divides m; the new row is (m / LM(g), g).
-__global__ __launch_bounds__(MB_THREADS) void k_reducers(const u32* list, const u32* count_ptr, const u64* montab,
-                                                          DevBasis G, const u32* active, u32 nactive, int lds_active,
-                                                          u64* rows_t, u32* rows_k, u32* row_lmrank, u32* range,
-                                                          u32 rcap) {
-    extern __shared__ u64 slm[];
-    if (lds_active) {
-        for (u32 i = threadIdx.x; i < nactive; i += MB_THREADS) slm[i] = G.lm[active[i]];
-        __syncthreads();
-    }
-    const u32 n = G.n, w = G.w;
+__global__ __launch_bounds__(MB_THREADS) void k_reducers(const SegSP* segs, const u32* list_q, const u32* list_s,
+                                                          const u32* count_ptr, const u32* active, u64* rows_t,
+                                                          u32* rows_k, u32* row_lmrank, u32* ctr) {
     const u32 cnt = *count_ptr;
     for (u32 i = blockIdx.x * MB_THREADS + threadIdx.x; i < cnt; i += gridDim.x * MB_THREADS) {
-        const u32 q = list[i];
-        const u64 m = montab[q];
-        for (u32 a = 0; a < nactive; ++a) {
-            const u64 l = lds_active ? slm[a] : G.lm[active[a]];
-            if (mono_divides(l, m, n, w)) {
-                u32 slot = atomicAdd(&range[1], 1u);
-                if (slot >= rcap) {
-                    range[3] = 2u;
+        const u32 q = list_q[i], s = list_s[i];
+        const SegSP& S = segs[s];
+        const u64 m = S.montab[q];
+        const u32* act = active + S.abase;
+        for (u32 a = 0; a < S.nactive; ++a) {
+            const u64 l = S.lm[act[a]];
+            if (mono_divides(l, m, S.n, S.w)) {
+                const u32 slot = atomicAdd(&ctr[CTR * s + 1], 1u);
+                if (slot >= S.rcap) {
+                    ctr[CTR * s + 3] = 2u;
                     break;
                 }
-                rows_t[slot] = m - l;
-                rows_k[slot] = active[a];
-                row_lmrank[slot] = q;
+                rows_t[S.rbase + slot] = m - l;
+                rows_k[S.rbase + slot] = act[a];
+                row_lmrank[S.rbase + slot] = q;
                 break;
             }
         }
@@ -187,72 +226,100 @@ __global__ void k_word_popc(const u32* present, u32 nwords, u32* cnt) {
         cnt[i] = __popc(present[i]);
 }
 
-// Dictionary: column of rank q = number of seen ranks below q; the columns are
-// therefore the seen monomials in descending grevlex order.
-__global__ void k_dict(const u32* present, u32 nwords, const u32* off, const u64* montab, u32* colmap,
-                       u64* dict_keys) {
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) {
-        u32 f = present[i];
-        u32 pos = off[i];
+// Dictionary: column of rank q = number of seen ranks below q in the system;
+// the columns are the seen monomials in descending grevlex order.
+__global__ void k_dict(const SegSP* segs, const u32* present, const u32* off, u32* colmap, u64* dict_keys) {
+    const SegSP S = segs[blockIdx.y];
+    const u32 base0 = off[S.wbase];
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < S.nwords; i += gridDim.x * blockDim.x) {
+        u32 f = present[S.wbase + i];
+        u32 pos = off[S.wbase + i] - base0;
         while (f) {
-            u32 b = __ffs(f) - 1;
-            u32 q = i * 32 + b;
-            colmap[q] = pos;
-            dict_keys[pos] = montab[q];
+            const u32 b = __ffs(f) - 1;
+            const u32 q = i * 32 + b;
+            colmap[S.cmbase + q] = pos;
+            dict_keys[S.cmbase + pos] = S.montab[q];
             ++pos;
             f &= f - 1;
         }
     }
 }
 
-// M = sum of the row lengths (first pass of the two-pass plan, reduced)
-__global__ void k_sum_len(const u32* rows_k, const u32* range, const u32* len, unsigned long long* M) {
-    const u32 r = range[1];
-    u32 s = 0;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x) s += len[rows_k[i]];
-    for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, F4_WAVE);
-    if (lane_id() == 0 && s) atomicAdd(M, (unsigned long long)s);
+// per-system M = sum of row lengths (first pass of the two-pass plan)
+__global__ void k_sum_len(const SegSP* segs, const u32* rows_k, const u32* ctr, unsigned long long* M) {
+    const u32 s = blockIdx.y;
+    const SegSP S = segs[s];
+    const u32 r = ctr[CTR * s + 1];
+    u32 acc = 0;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x)
+        acc += S.len[rows_k[S.rbase + i]];
+    for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, F4_WAVE);
+    if (lane_id() == 0 && acc) atomicAdd(&M[s], (unsigned long long)acc);
 }
 
-// Row order: leading monomial descending (= rank ascending), then basis index.
-__global__ void k_row_keys(const u32* row_lmrank, const u32* rows_k, u32 r, u32 kbits, u64* keys, u32* vals) {
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x) {
-        keys[i] = ((u64)row_lmrank[i] << kbits) | rows_k[i];
-        vals[i] = i;
+// summary per system: rows, remaining frontier, error, N, M lo, M hi
+__global__ void k_sp_summary(const SegSP* segs, u32 S, const u32* ctr, const u32* fscan, const u32* pscan,
+                             const unsigned long long* M, u32* out) {
+    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+        const SegSP& G = segs[s];
+        out[8 * s + 0] = ctr[CTR * s + 1];
+        out[8 * s + 1] = fscan[G.wbase + G.nwords] - fscan[G.wbase];
+        out[8 * s + 2] = ctr[CTR * s + 3];
+        out[8 * s + 3] = pscan[G.wbase + G.nwords] - pscan[G.wbase];
+        out[8 * s + 4] = (u32)M[s];
+        out[8 * s + 5] = (u32)(M[s] >> 32);
     }
 }
 
-__global__ void k_gather_rows(const u32* perm, const u64* rows_t, const u32* rows_k, const u32* glen, u32 r,
-                              u64* out_t, u32* out_k, u32* out_len) {
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x) {
-        u32 s = perm[i];
-        u32 k = rows_k[s];
-        out_t[i] = rows_t[s];
+// Row order: system, then leading monomial descending (= rank ascending), then
+// basis index.
+__global__ void k_row_keys(const SegSP* segs, const u32* row_lmrank, const u32* rows_k, u32 sshift, u32 kbits,
+                           u64* keys, u32* vals) {
+    const u32 s = blockIdx.y;
+    const SegSP S = segs[s];
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < S.r; i += gridDim.x * blockDim.x) {
+        const u32 src = S.rbase + i;
+        keys[S.obase + i] = ((u64)s << sshift) | ((u64)row_lmrank[src] << kbits) | rows_k[src];
+        vals[S.obase + i] = src;
+    }
+}
+
+__global__ void k_gather_rows(const SegSP* segs, const u32* perm, const u64* keys, u32 sshift, const u64* rows_t,
+                              const u32* rows_k, u32 R, u64* out_t, u32* out_k, u32* out_len, u32* row_sys) {
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < R; i += gridDim.x * blockDim.x) {
+        const u32 src = perm[i];
+        const u32 s = sshift >= 64 ? 0u : (u32)(keys[i] >> sshift);
+        const u32 k = rows_k[src];
+        out_t[i] = rows_t[src];
         out_k[i] = k;
-        out_len[i] = glen[k];
+        out_len[i] = segs[s].len[k];
+        row_sys[i] = s;
     }
 }
 
 // Pass 2 of the two-pass plan fused with the dictionary join (dense rank):
 // row i writes col_ind/val into its own segment [row_ptr[i], row_ptr[i+1]).
-__global__ __launch_bounds__(MB_THREADS) void k_fill_rank(const u64* row_t, const u32* row_k, const u32* row_ptr,
-                                                           u32 r, DevBasis G, const u32* binom_g, u32 tabn, u32 D,
-                                                           u32 nmax, const u32* colmap, u32* col_ind, u32* val) {
+__global__ __launch_bounds__(MB_THREADS) void k_fill_rank(const SegSP* segs, const u64* row_t, const u32* row_k,
+                                                           const u32* row_ptr, const u32* colmap, u32* col_ind,
+                                                           u32* val) {
     extern __shared__ u32 sm[];
-    for (u32 i = threadIdx.x; i < tabn; i += MB_THREADS) sm[i] = binom_g[i];
+    const SegSP S = segs[blockIdx.y];
+    for (u32 i = threadIdx.x; i < S.tabn; i += MB_THREADS) sm[i] = S.binom[i];
     __syncthreads();
-    const u32 n = G.n, w = G.w, lane = lane_id();
+    const u32 n = S.n, w = S.w, D = S.D, lane = lane_id();
     const u32 nw_total = gridDim.x * MB_WAVES;
-    for (u32 row = blockIdx.x * MB_WAVES + threadIdx.x / F4_WAVE; row < r; row += nw_total) {
+    const u32* cm = colmap + S.cmbase;
+    for (u32 ri = blockIdx.x * MB_WAVES + threadIdx.x / F4_WAVE; ri < S.r; ri += nw_total) {
+        const u32 row = S.obase + ri;
         const u64 t = row_t[row];
         const u32 k = row_k[row];
-        const u64 off = G.off[k];
-        const u32 len = G.len[k];
-        const u32 s = row_ptr[row];
+        const u64 off = S.off[k];
+        const u32 len = S.len[k];
+        const u32 s0 = row_ptr[row];
         for (u32 j = lane; j < len; j += F4_WAVE) {
-            u32 q = mono_rank(t + G.mon[off + j], n, w, D, sm);
-            col_ind[s + j] = q < nmax ? colmap[q] : 0u;
-            val[s + j] = G.coeff[off + j];
+            const u32 q = mono_rank(t + S.mon[off + j], n, w, D, sm);
+            col_ind[s0 + j] = q < S.nmax ? cm[q] : 0u;
+            val[s0 + j] = S.coeff[off + j];
         }
     }
 }
@@ -260,17 +327,19 @@ __global__ __launch_bounds__(MB_THREADS) void k_fill_rank(const u64* row_t, cons
 // ------------------------------------------------------- radix-sort path
 // Compact order key of a monomial of degree <= D: (D - deg) on top, then the
 // exponents a_n .. a_1 in fields of b = bitlength(D) bits.  Ascending keys are
-// descending grevlex, and the key is injective on Mon_{<=D}.
+// descending grevlex, and the key is injective on Mon_{<=D}.  The system index
+// sits above the key so one sort serves the whole batch.
+__device__ __forceinline__ u32 bitlen_d(u32 x) { return 32 - __clz(x); }
 __device__ __forceinline__ u64 compact_key(u64 P, u32 n, u32 w, u32 b, u32 D) {
     u64 k = (u64)(D - mono_deg(P)) << (n * b);
     for (u32 i = 0; i < n; ++i) k |= (u64)mono_exp(P, i, w) << (b * i);
     return k;
 }
-__device__ __forceinline__ u64 compact_to_P(u64 k, u32 n, u32 w, u32 b, u32 D) {
+__device__ __forceinline__ u64 compact_to_P(u64 k, u32 n, u32 w, u32 b) {
     u64 P = 0;
     u32 deg = 0;
     for (u32 i = 0; i < n; ++i) {
-        u32 a = (u32)((k >> (b * i)) & ((1u << b) - 1));
+        const u32 a = (u32)((k >> (b * i)) & ((1u << b) - 1));
         P |= (u64)a << (w * i);
         deg += a;
     }
@@ -278,41 +347,64 @@ __device__ __forceinline__ u64 compact_to_P(u64 k, u32 n, u32 w, u32 b, u32 D) {
 }
 
 // Pass 2 of the two-pass plan as written: materialise row_key / row_val
-__global__ __launch_bounds__(MB_THREADS) void k_fill_keys(const u64* row_t, const u32* row_k, const u32* row_ptr,
-                                                           u32 r, DevBasis G, u32 b, u32 D, u64* row_key,
+__global__ __launch_bounds__(MB_THREADS) void k_fill_keys(const SegSP* segs, const u64* row_t, const u32* row_k,
+                                                           const u32* row_ptr, u32 kshift, u64* row_key,
                                                            u32* row_val) {
-    const u32 n = G.n, w = G.w, lane = lane_id();
+    const u32 s = blockIdx.y;
+    const SegSP S = segs[s];
+    const u32 n = S.n, w = S.w, D = S.D, b = bitlen_d(S.D ? S.D : 1), lane = lane_id();
+    const u64 sk = kshift >= 64 ? 0ull : ((u64)s << kshift);
     const u32 nw_total = gridDim.x * MB_WAVES;
-    for (u32 row = blockIdx.x * MB_WAVES + threadIdx.x / F4_WAVE; row < r; row += nw_total) {
+    for (u32 ri = blockIdx.x * MB_WAVES + threadIdx.x / F4_WAVE; ri < S.r; ri += nw_total) {
+        const u32 row = S.obase + ri;
         const u64 t = row_t[row];
         const u32 k = row_k[row];
-        const u64 off = G.off[k];
-        const u32 len = G.len[k];
-        const u32 s = row_ptr[row];
+        const u64 off = S.off[k];
+        const u32 len = S.len[k];
+        const u32 s0 = row_ptr[row];
         for (u32 j = lane; j < len; j += F4_WAVE) {
-            row_key[s + j] = compact_key(t + G.mon[off + j], n, w, b, D);
-            row_val[s + j] = G.coeff[off + j];
+            row_key[s0 + j] = sk | compact_key(t + S.mon[off + j], n, w, b, D);
+            row_val[s0 + j] = S.coeff[off + j];
         }
     }
 }
 
-// Join: position of every row key in the sorted dictionary (binary search; the
-// dictionary sits in LDS when it fits).
-__global__ __launch_bounds__(MB_THREADS) void k_join(const u64* row_key, u64 M, const u64* dict, const u32* N_ptr,
-                                                      u32 Ncap, int lds_dict, u32* col_ind) {
-    extern __shared__ u64 sd[];
-    const u32 N = min(*N_ptr, Ncap);
-    if (lds_dict) {
-        for (u32 i = threadIdx.x; i < N; i += MB_THREADS) sd[i] = dict[i];
-        __syncthreads();
-    }
-    const u64* D_ = lds_dict ? sd : dict;
-    for (u64 e = (u64)blockIdx.x * MB_THREADS + threadIdx.x; e < M; e += (u64)gridDim.x * MB_THREADS) {
-        const u64 key = row_key[e];
+// first position of each system's keys in the sorted unique key list
+__global__ void k_seg_bounds(const u64* dict, const u32* N_ptr, u32 S, u32 kshift, u32* dstart) {
+    const u32 N = *N_ptr;
+    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s <= S; s += gridDim.x * blockDim.x) {
         u32 lo = 0, hi = N;
         while (lo < hi) {
-            u32 mid = (lo + hi) >> 1;
-            if (D_[mid] < key)
+            const u32 mid = (lo + hi) >> 1;
+            const u32 ks = kshift >= 64 ? 0u : (u32)(dict[mid] >> kshift);
+            if (ks < s)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        dstart[s] = lo;
+    }
+}
+
+// Join: position of every row key in its system's part of the sorted
+// dictionary (binary search; in LDS when the batch has one system and fits).
+__global__ __launch_bounds__(MB_THREADS) void k_join(const u64* row_key, u64 M, const u64* dict, const u32* dstart,
+                                                      u32 kshift, int lds_dict, u32 Ncap, u32* col_ind) {
+    extern __shared__ u64 sd[];
+    if (lds_dict) {
+        const u32 N = min(dstart[1] - dstart[0], Ncap);
+        for (u32 i = threadIdx.x; i < N; i += MB_THREADS) sd[i] = dict[dstart[0] + i];
+        __syncthreads();
+    }
+    for (u64 e = (u64)blockIdx.x * MB_THREADS + threadIdx.x; e < M; e += (u64)gridDim.x * MB_THREADS) {
+        const u64 key = row_key[e];
+        const u32 s = kshift >= 64 ? 0u : (u32)(key >> kshift);
+        const u32 a = dstart[s], bnd = dstart[s + 1];
+        const u64* Dd = lds_dict ? sd : dict + a;
+        u32 lo = 0, hi = lds_dict ? min(bnd - a, Ncap) : bnd - a;
+        while (lo < hi) {
+            const u32 mid = (lo + hi) >> 1;
+            if (Dd[mid] < key)
                 lo = mid + 1;
             else
                 hi = mid;
@@ -321,11 +413,17 @@ __global__ __launch_bounds__(MB_THREADS) void k_join(const u64* row_key, u64 M, 
     }
 }
 
-__global__ void k_dict_from_compact(const u64* dictc, const u32* N_ptr, u32 Ncap, u32 n, u32 w, u32 b, u32 D,
-                                    u64* dict_keys) {
-    const u32 N = min(*N_ptr, Ncap);
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
-        dict_keys[i] = compact_to_P(dictc[i], n, w, b, D);
+__global__ void k_dict_from_compact(const SegSP* segs, const u64* dictc, const u32* N_ptr, const u32* dstart,
+                                    u32 kshift, u32 S, u64* dict_keys) {
+    const u32 N = *N_ptr;
+    const u64 kmask = kshift >= 64 ? ~0ull : ((1ull << kshift) - 1);
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const u32 s = kshift >= 64 ? 0u : (u32)(dictc[i] >> kshift);
+        if (s >= S) continue;
+        const SegSP& G = segs[s];
+        const u32 col = i - dstart[s];
+        if (col < G.nmax) dict_keys[G.cmbase + col] = compact_to_P(dictc[i] & kmask, G.n, G.w, bitlen_d(G.D ? G.D : 1));
+    }
 }
 
 static u32 bitlen(u64 x) {
@@ -345,173 +443,256 @@ static u32 grid_for(u64 items, u32 per_block, u32 cap) {
 }
 
 // --------------------------------------------------------------- driver
-void build_matrix(Ctx& c, const BuildArgs& a, Matrix& out) {
+void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     hipStream_t s = c.stream;
-    const u32 n = a.G.n, w = a.G.w, D = a.D;
-    if (a.r0 == 0) throw F4Error{1, "empty row list"};
-    const u64 nmax64 = binom_host(n + D, n);
-    if (nmax64 > (1ull << 27)) throw F4Error{2, "N(n, D) too large for the dense-rank closure"};
-    const u32 nmax = (u32)nmax64;
-    const u32 nwords = ceil_div(nmax, 32);
-    const u32* binom_g = rank_table(c, n, D);
-    const u32 tabn = (n + D + 2) * F4_BSTRIDE;
-    const u64* montab = unrank_table(c, n, D);
-
+    const u32 S = (u32)args.size();
+    if (S == 0) throw F4Error{1, "empty batch"};
+    if (S > 65535) throw F4Error{2, "batch has more than 65535 systems"};
     hipEvent_t ev0 = stage_event(c);
 
-    // bitmaps of seen / processed monomials, rows with capacity r0 + N(n, D)
-    DBuf<u32> present(&c.pool, nwords), done(&c.pool, nwords);
-    fill_u32(present.ptr, nwords, 0, s);
-    fill_u32(done.ptr, nwords, 0, s);
-    const u64 rcap = (u64)a.r0 + (a.closure ? nmax : 0);
-    DBuf<u64> rows_t(&c.pool, rcap);
-    DBuf<u32> rows_k(&c.pool, rcap), row_lmrank(&c.pool, rcap);
-    F4_HIP_TRY(hipMemcpyAsync(rows_t.ptr, a.rows_t, (u64)a.r0 * 8, hipMemcpyDeviceToDevice, s));
-    F4_HIP_TRY(hipMemcpyAsync(rows_k.ptr, a.rows_k, (u64)a.r0 * 4, hipMemcpyDeviceToDevice, s));
-    // range[0..1] = current row range, range[2] = frontier count slot (unused), M at hdr
-    DBuf<u32> range(&c.pool, 4);
-    {
-        u32 h[4] = {0, a.r0, 0, 0};
-        upload(c, range.ptr, h, sizeof(h));
+    // ---- per-system layout (host)
+    std::vector<SegSP> segs(S);
+    std::vector<u32> actv;
+    u64 W = 0, RC = 0, CM = 0, IB = 0;
+    u32 max_tabn = 0, max_words = 0, max_nmax = 0, max_np = 1;
+    for (u32 i = 0; i < S; ++i) {
+        const BuildArgs& a = args[i];
+        if (a.r0 == 0) throw F4Error{1, "empty row list"};
+        const u32 n = a.G.n, D = a.D;
+        const u64 nmax64 = binom_host(n + D, n);
+        if (nmax64 > (1ull << 27)) throw F4Error{2, "N(n, D) too large for the dense-rank closure"};
+        SegSP& g = segs[i];
+        std::memset(&g, 0, sizeof(g));
+        g.mon = a.G.mon;
+        g.coeff = a.G.coeff;
+        g.off = a.G.off;
+        g.lm = a.G.lm;
+        g.len = a.G.len;
+        g.binom = rank_table(c, n, D);
+        g.montab = unrank_table(c, n, D);
+        g.n = n;
+        g.w = a.G.w;
+        g.D = D;
+        g.nmax = (u32)nmax64;
+        g.nwords = ceil_div(g.nmax, 32);
+        g.wbase = (u32)W;
+        g.rcap = a.r0 + (a.closure ? g.nmax : 0);
+        g.rbase = (u32)RC;
+        g.abase = (u32)actv.size();
+        g.nactive = a.nactive;
+        for (u32 k = 0; k < a.nactive; ++k) actv.push_back(a.active_host[k]);
+        g.tabn = (n + D + 2) * F4_BSTRIDE;
+        g.npolys = a.G.npolys;
+        g.cmbase = (u32)CM;
+        g.ibase = (u32)IB;
+        g.r0 = a.r0;
+        IB += a.r0;
+        W += g.nwords;
+        RC += g.rcap;
+        CM += g.nmax;
+        max_tabn = std::max(max_tabn, g.tabn);
+        max_words = std::max(max_words, g.nwords);
+        max_nmax = std::max(max_nmax, g.nmax);
+        max_np = std::max(max_np, g.npolys);
     }
-    DBuf<unsigned long long> Mdev(&c.pool, 1);
-    fill_u64((u64*)Mdev.ptr, 1, 0, s);
+    if (W >= (1ull << 31) || RC >= (1ull << 31) || CM >= (1ull << 31)) throw F4Error{2, "batch too large"};
+    const bool closure = args[0].closure;
 
-    const int local_bitmap = (tabn + nwords) * 4 <= 48 * 1024;
-    const size_t mark_lds = (tabn + (local_bitmap ? nwords : 0)) * 4;
-    const u32 mark_grid = (u32)std::max(1, c.dev.cus);
+    DBuf<SegSP> dsegs(&c.pool, S);
+    upload(c, dsegs.ptr, segs.data(), S * sizeof(SegSP));
+    DBuf<u32> present(&c.pool, W), done(&c.pool, W);
+    fill_u32(present.ptr, W, 0, s);
+    fill_u32(done.ptr, W, 0, s);
+    DBuf<u64> rows_t(&c.pool, RC);
+    DBuf<u32> rows_k(&c.pool, RC), row_lmrank(&c.pool, RC), active(&c.pool, std::max<size_t>(actv.size(), 1));
+    DBuf<u32> ctr(&c.pool, CTR * S);
+    upload(c, active.ptr, actv.data(), actv.size() * 4);
+    {
+        // initial rows of every system, packed once on the host
+        u64 I = 0;
+        for (u32 i = 0; i < S; ++i) I += args[i].r0;
+        std::vector<u64> t(I);
+        std::vector<u32> k(I);
+        std::vector<u32> hc(CTR * S, 0);
+        for (u32 i = 0; i < S; ++i) {
+            const BuildArgs& a = args[i];
+            std::memcpy(t.data() + segs[i].ibase, a.rows_t_host, (size_t)a.r0 * 8);
+            std::memcpy(k.data() + segs[i].ibase, a.rows_k_host, (size_t)a.r0 * 4);
+            hc[CTR * i + 1] = a.r0;
+        }
+        DBuf<u64> t0(&c.pool, I);
+        DBuf<u32> k0(&c.pool, I);
+        upload(c, t0.ptr, t.data(), I * 8);
+        upload(c, k0.ptr, k.data(), I * 4);
+        upload(c, ctr.ptr, hc.data(), hc.size() * 4);
+        u32 mr = 1;
+        for (u32 i = 0; i < S; ++i) mr = std::max(mr, args[i].r0);
+        hipLaunchKernelGGL(k_init_rows, dim3(std::min<u32>(64, ceil_div(mr, 256)), S), dim3(256), 0, s, dsegs.ptr,
+                           t0.ptr, k0.ptr, rows_t.ptr, rows_k.ptr);
+        F4_LAUNCH_CHECK();
+    }
+    DBuf<unsigned long long> Mdev(&c.pool, S);
+
+    const int local_bitmap = (max_tabn + max_words) * 4 <= 48 * 1024;
+    const size_t mark_lds = (max_tabn + (local_bitmap ? max_words : 0)) * 4;
+    const u32 bx = std::max<u32>(1, std::min<u32>((u32)std::max(1, c.dev.cus), ceil_div(2048, S)));
     auto mark = [&]() {
-        hipLaunchKernelGGL(k_mark_rows, dim3(mark_grid), dim3(MB_THREADS), mark_lds, s, rows_t.ptr, rows_k.ptr,
-                           row_lmrank.ptr, range.ptr, a.G, binom_g, tabn, D, present.ptr, done.ptr, nwords,
-                           local_bitmap, range.ptr + 3);
+        hipLaunchKernelGGL(k_mark_rows, dim3(bx, S), dim3(MB_THREADS), mark_lds, s, dsegs.ptr, rows_t.ptr,
+                           rows_k.ptr, row_lmrank.ptr, ctr.ptr, present.ptr, done.ptr, local_bitmap);
         F4_LAUNCH_CHECK();
     };
     mark();
 
-    DBuf<u32> cnt(&c.pool, nwords + 1), list(&c.pool, a.closure ? nmax : 1);
-    const int lds_active = a.nactive * 8 <= 32 * 1024;
-    const u32 wgrid = grid_for(nwords, 256, 1024);
+    DBuf<u32> fcnt(&c.pool, W + 1), pcnt(&c.pool, W + 1);
+    DBuf<u32> list_q(&c.pool, closure ? CM : 1), list_s(&c.pool, closure ? CM : 1);
+    DBuf<u32> summary(&c.pool, 8 * S);
+    const u32 wgrid = grid_for(W, 256, 2048);
+    const u32 wbx = std::max<u32>(1, std::min<u32>(64, ceil_div(max_words, 256)));
     u32 rounds = 0;
-    u32 hdr[4];
+    std::vector<u32> hs(8 * S);
     for (;;) {
-        if (a.closure) {
+        if (closure) {
             // two speculative rounds per host check: dense systems converge in two
             for (int k = 0; k < 2; ++k) {
-                hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present.ptr, done.ptr, nwords,
-                                   cnt.ptr);
+                hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present.ptr, done.ptr, (u32)W,
+                                   fcnt.ptr);
                 F4_LAUNCH_CHECK();
-                exclusive_scan_u32(cnt.ptr, cnt.ptr, nwords, c.pool, s);
-                hipLaunchKernelGGL(k_frontier_write, dim3(wgrid), dim3(256), 0, s, present.ptr, done.ptr, nwords,
-                                   cnt.ptr, list.ptr, range.ptr);
+                exclusive_scan_u32(fcnt.ptr, fcnt.ptr, W, c.pool, s);
+                hipLaunchKernelGGL(k_frontier_write, dim3(wbx, S), dim3(256), 0, s, dsegs.ptr, present.ptr, done.ptr,
+                                   fcnt.ptr, list_q.ptr, list_s.ptr, ctr.ptr);
                 F4_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_reducers, dim3(grid_for(nmax, MB_THREADS, 1024)), dim3(MB_THREADS),
-                                   lds_active ? a.nactive * 8 : 0, s, list.ptr, cnt.ptr + nwords, montab, a.G,
-                                   a.active, a.nactive, lds_active, rows_t.ptr, rows_k.ptr, row_lmrank.ptr,
-                                   range.ptr, (u32)rcap);
+                hipLaunchKernelGGL(k_reducers, dim3(grid_for(CM, MB_THREADS, 2048)), dim3(MB_THREADS), 0, s,
+                                   dsegs.ptr, list_q.ptr, list_s.ptr, fcnt.ptr + W, active.ptr, rows_t.ptr,
+                                   rows_k.ptr, row_lmrank.ptr, ctr.ptr);
                 F4_LAUNCH_CHECK();
                 mark();
                 ++rounds;
             }
-            // remaining frontier after the rounds
-            hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present.ptr, done.ptr, nwords,
-                               cnt.ptr);
+            hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present.ptr, done.ptr, (u32)W,
+                               fcnt.ptr);
             F4_LAUNCH_CHECK();
-            exclusive_scan_u32(cnt.ptr, cnt.ptr, nwords, c.pool, s);
-            F4_HIP_TRY(hipMemcpyAsync(range.ptr + 2, cnt.ptr + nwords, 4, hipMemcpyDeviceToDevice, s));
+            exclusive_scan_u32(fcnt.ptr, fcnt.ptr, W, c.pool, s);
+        } else {
+            fill_u32(fcnt.ptr, W + 1, 0, s);
         }
-        readback(c, hdr, range.ptr, sizeof(hdr));
-        if (hdr[3]) throw F4Error{1, hdr[3] == 1 ? "a row term is not a monomial of degree <= D (unsorted or "
-                                                   "inconsistent input terms)"
-                                                 : "row capacity exceeded"};
-        if (!a.closure || hdr[2] == 0) break;
-        if (rounds > 4 * (D + 8)) throw F4Error{5, "closure did not converge"};
+        // dictionary sizes and M alongside the convergence check: one readback
+        hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, present.ptr, (u32)W, pcnt.ptr);
+        F4_LAUNCH_CHECK();
+        exclusive_scan_u32(pcnt.ptr, pcnt.ptr, W, c.pool, s);
+        fill_u64((u64*)Mdev.ptr, S, 0, s);
+        hipLaunchKernelGGL(k_sum_len, dim3(bx, S), dim3(256), 0, s, dsegs.ptr, rows_k.ptr, ctr.ptr, Mdev.ptr);
+        F4_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sp_summary, dim3(grid_for(S, 256, 64)), dim3(256), 0, s, dsegs.ptr, S, ctr.ptr, fcnt.ptr,
+                           pcnt.ptr, Mdev.ptr, summary.ptr);
+        F4_LAUNCH_CHECK();
+        readback(c, hs.data(), summary.ptr, hs.size() * 4);
+        bool more = false;
+        for (u32 i = 0; i < S; ++i) {
+            if (hs[8 * i + 2])
+                throw F4Error{1, hs[8 * i + 2] == 1 ? "a row term is not a monomial of degree <= D (unsorted or "
+                                                      "inconsistent input terms)"
+                                                    : "row capacity exceeded"};
+            if (hs[8 * i + 1]) more = true;
+        }
+        if (!closure || !more) break;
+        if (rounds > 4 * (max_nmax + 8)) throw F4Error{5, "closure did not converge"};
     }
-    const u32 r = hdr[1];
 
-    // dictionary (dense rank): popcount prefix of the seen bitmap
-    DBuf<u32> colmap(&c.pool, nmax);
-    hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, present.ptr, nwords, cnt.ptr);
-    F4_LAUNCH_CHECK();
-    exclusive_scan_u32(cnt.ptr, cnt.ptr, nwords, c.pool, s);
-    out.dict_keys.reset(&c.pool, nmax);  // trimmed view: first N entries are valid
-    hipLaunchKernelGGL(k_dict, dim3(wgrid), dim3(256), 0, s, present.ptr, nwords, cnt.ptr, montab, colmap.ptr,
-                       out.dict_keys.ptr);
-    F4_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sum_len, dim3(grid_for(r, 256, 1024)), dim3(256), 0, s, rows_k.ptr, range.ptr, a.G.len,
-                       Mdev.ptr);
-    F4_LAUNCH_CHECK();
-    u32 Nhost = 0;
-    unsigned long long Mhost = 0;
-    {
-        u8* st = staging(c, 16);
-        F4_HIP_TRY(hipMemcpyAsync(st, cnt.ptr + nwords, 4, hipMemcpyDeviceToHost, s));
-        F4_HIP_TRY(hipMemcpyAsync(st + 8, Mdev.ptr, 8, hipMemcpyDeviceToHost, s));
-        F4_HIP_TRY(hipStreamSynchronize(s));
-        std::memcpy(&Nhost, st, 4);
-        std::memcpy(&Mhost, st + 8, 8);
+    // ---- sizes and output layout
+    out.S = S;
+    out.sys.assign(S, SysPart());
+    u64 R = 0, Mtot = 0;
+    for (u32 i = 0; i < S; ++i) {
+        SysPart& P = out.sys[i];
+        P.n = segs[i].n;
+        P.deg = segs[i].D;
+        P.r = hs[8 * i + 0];
+        P.N = hs[8 * i + 3];
+        P.nnz = (u64)hs[8 * i + 4] | ((u64)hs[8 * i + 5] << 32);
+        P.row_base = (u32)R;
+        P.nnz_base = Mtot;
+        P.dict_base = segs[i].cmbase;
+        segs[i].obase = (u32)R;
+        segs[i].r = P.r;
+        if (P.N >= (1u << 26)) throw F4Error{2, "dictionary has 2^26 or more columns"};
+        R += P.r;
+        Mtot += P.nnz;
     }
-    if (Mhost >= (1ull << 32)) throw F4Error{2, "matrix has 2^32 or more entries"};
-    if (Nhost >= (1u << 26)) throw F4Error{2, "dictionary has 2^26 or more columns"};
-    const u32 N = Nhost;
-    const u32 M = (u32)Mhost;
+    if (Mtot >= (1ull << 32) || R >= (1ull << 31)) throw F4Error{2, "batch matrix has 2^32 or more entries"};
+    upload(c, dsegs.ptr, segs.data(), S * sizeof(SegSP));
     hipEvent_t ev1 = stage_event(c);
 
-    // row order: sort by (rank of LM, basis index)
-    const u32 kbits = std::max<u32>(1, bitlen(a.G.npolys ? a.G.npolys - 1 : 0));
-    const u32 rbits = std::max<u32>(1, bitlen(nmax - 1));
-    DBuf<u64> keys(&c.pool, r);
-    DBuf<u32> perm(&c.pool, r);
-    const u32 rgrid = grid_for(r, 256, 4096);
-    hipLaunchKernelGGL(k_row_keys, dim3(rgrid), dim3(256), 0, s, row_lmrank.ptr, rows_k.ptr, r, kbits, keys.ptr,
-                       perm.ptr);
+    // dictionary (dense rank): popcount prefix of the seen bitmap
+    DBuf<u32> colmap(&c.pool, CM);
+    out.dict_keys.reset(&c.pool, CM);
+    hipLaunchKernelGGL(k_dict, dim3(wbx, S), dim3(256), 0, s, dsegs.ptr, present.ptr, pcnt.ptr, colmap.ptr,
+                       out.dict_keys.ptr);
     F4_LAUNCH_CHECK();
-    radix_sort_pairs(keys.ptr, perm.ptr, r, 0, rbits + kbits, c.pool, s);
-    out.row_t.reset(&c.pool, r);
-    out.row_k.reset(&c.pool, r);
-    out.row_ptr.reset(&c.pool, (u64)r + 1);
-    hipLaunchKernelGGL(k_gather_rows, dim3(rgrid), dim3(256), 0, s, perm.ptr, rows_t.ptr, rows_k.ptr, a.G.len, r,
-                       out.row_t.ptr, out.row_k.ptr, out.row_ptr.ptr);
-    F4_LAUNCH_CHECK();
-    exclusive_scan_u32(out.row_ptr.ptr, out.row_ptr.ptr, r, c.pool, s);
 
-    out.col_ind.reset(&c.pool, M);
-    out.val.reset(&c.pool, M);
-    int path = a.dict_path;
+    // row order: sort by (system, rank of LM, basis index)
+    const u32 kbits = std::max<u32>(1, bitlen(max_np - 1));
+    const u32 rbits = std::max<u32>(1, bitlen(max_nmax - 1));
+    const u32 sshift = rbits + kbits;
+    const u32 sbits = S > 1 ? bitlen(S - 1) : 0;
+    if (sshift + sbits > 64) throw F4Error{2, "row key does not fit 64 bits"};
+    DBuf<u64> keys(&c.pool, R);
+    DBuf<u32> perm(&c.pool, R);
+    const u32 rbx = std::max<u32>(1, std::min<u32>(64, ceil_div(ceil_div(R, S), 256)));
+    hipLaunchKernelGGL(k_row_keys, dim3(rbx, S), dim3(256), 0, s, dsegs.ptr, row_lmrank.ptr, rows_k.ptr, sshift, kbits,
+                       keys.ptr, perm.ptr);
+    F4_LAUNCH_CHECK();
+    radix_sort_pairs(keys.ptr, perm.ptr, R, 0, sshift + sbits, c.pool, s);
+    out.row_t.reset(&c.pool, R);
+    out.row_k.reset(&c.pool, R);
+    out.row_sys.reset(&c.pool, R);
+    out.row_ptr.reset(&c.pool, R + 1);
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(R, 256, 4096)), dim3(256), 0, s, dsegs.ptr, perm.ptr, keys.ptr,
+                       S > 1 ? sshift : 64u, rows_t.ptr, rows_k.ptr, (u32)R, out.row_t.ptr, out.row_k.ptr,
+                       out.row_ptr.ptr, out.row_sys.ptr);
+    F4_LAUNCH_CHECK();
+    exclusive_scan_u32(out.row_ptr.ptr, out.row_ptr.ptr, R, c.pool, s);
+
+    out.col_ind.reset(&c.pool, std::max<u64>(Mtot, 1));
+    out.val.reset(&c.pool, std::max<u64>(Mtot, 1));
+    int path = args[0].dict_path;
     if (path < 0) path = (c.flags & 4u) ? 1 : 0;  // F4_OPT_DICT_RADIX
-    const u32 fgrid = grid_for(r, MB_WAVES, 8 * (u32)std::max(1, c.dev.cus));
+    const u32 fbx =
+        std::max<u32>(1, std::min<u32>(8 * (u32)std::max(1, c.dev.cus), ceil_div(ceil_div(R, S), MB_WAVES)));
     if (path == 0) {
-        hipLaunchKernelGGL(k_fill_rank, dim3(fgrid), dim3(MB_THREADS), tabn * 4, s, out.row_t.ptr, out.row_k.ptr,
-                           out.row_ptr.ptr, r, a.G, binom_g, tabn, D, nmax, colmap.ptr, out.col_ind.ptr,
-                           out.val.ptr);
+        hipLaunchKernelGGL(k_fill_rank, dim3(fbx, S), dim3(MB_THREADS), max_tabn * 4, s, dsegs.ptr, out.row_t.ptr,
+                           out.row_k.ptr, out.row_ptr.ptr, colmap.ptr, out.col_ind.ptr, out.val.ptr);
         F4_LAUNCH_CHECK();
     } else {
-        const u32 b = std::max<u32>(1, bitlen(D));
-        const u32 kb = (n + 1) * b;
-        if (kb > 64) throw F4Error{2, "compact key does not fit 64 bits"};
-        DBuf<u64> row_key(&c.pool, M), cand(&c.pool, M), dictc(&c.pool, M);
-        hipLaunchKernelGGL(k_fill_keys, dim3(fgrid), dim3(MB_THREADS), 0, s, out.row_t.ptr, out.row_k.ptr,
-                           out.row_ptr.ptr, r, a.G, b, D, row_key.ptr, out.val.ptr);
+        u32 kb = 0;
+        for (u32 i = 0; i < S; ++i) kb = std::max(kb, (segs[i].n + 1) * std::max<u32>(1, bitlen(segs[i].D)));
+        if (kb + sbits > 64) throw F4Error{2, "compact key does not fit 64 bits"};
+        const u32 kshift = S > 1 ? kb : 64u;
+        DBuf<u64> row_key(&c.pool, std::max<u64>(Mtot, 1)), cand(&c.pool, std::max<u64>(Mtot, 1)),
+            dictc(&c.pool, std::max<u64>(Mtot, 1));
+        hipLaunchKernelGGL(k_fill_keys, dim3(fbx, S), dim3(MB_THREADS), 0, s, dsegs.ptr, out.row_t.ptr, out.row_k.ptr,
+                           out.row_ptr.ptr, kshift, row_key.ptr, out.val.ptr);
         F4_LAUNCH_CHECK();
-        F4_HIP_TRY(hipMemcpyAsync(cand.ptr, row_key.ptr, (u64)M * 8, hipMemcpyDeviceToDevice, s));
-        radix_sort_keys(cand.ptr, M, 0, kb, c.pool, s);
-        DBuf<u32> ncount(&c.pool, 1);
-        unique_sorted_u64(cand.ptr, M, dictc.ptr, ncount.ptr, c.pool, s);
-        const int lds_dict = (u64)N * 8 <= c.dev.max_lds;
-        hipLaunchKernelGGL(k_join, dim3(grid_for(M, MB_THREADS, 16 * (u32)std::max(1, c.dev.cus))), dim3(MB_THREADS),
-                           lds_dict ? (size_t)N * 8 : 0, s, row_key.ptr, (u64)M, dictc.ptr, ncount.ptr, N, lds_dict,
-                           out.col_ind.ptr);
+        F4_HIP_TRY(hipMemcpyAsync(cand.ptr, row_key.ptr, Mtot * 8, hipMemcpyDeviceToDevice, s));
+        radix_sort_keys(cand.ptr, Mtot, 0, kb + sbits, c.pool, s);
+        DBuf<u32> ncount(&c.pool, 1), dstart(&c.pool, S + 1);
+        unique_sorted_u64(cand.ptr, Mtot, dictc.ptr, ncount.ptr, c.pool, s);
+        hipLaunchKernelGGL(k_seg_bounds, dim3(grid_for(S + 1, 256, 64)), dim3(256), 0, s, dictc.ptr, ncount.ptr, S,
+                           kshift, dstart.ptr);
         F4_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_dict_from_compact, dim3(grid_for(N, 256, 1024)), dim3(256), 0, s, dictc.ptr,
-                           ncount.ptr, N, n, w, b, D, out.dict_keys.ptr);
+        const u32 N0 = out.sys[0].N;
+        const int lds_dict = S == 1 && (u64)N0 * 8 <= c.dev.max_lds;
+        hipLaunchKernelGGL(k_join, dim3(grid_for(Mtot, MB_THREADS, 16 * (u32)std::max(1, c.dev.cus))),
+                           dim3(MB_THREADS), lds_dict ? (size_t)N0 * 8 : 0, s, row_key.ptr, Mtot, dictc.ptr,
+                           dstart.ptr, kshift, lds_dict, N0, out.col_ind.ptr);
+        F4_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_dict_from_compact, dim3(grid_for(Mtot, 256, 2048)), dim3(256), 0, s, dsegs.ptr,
+                           dictc.ptr, ncount.ptr, dstart.ptr, kshift, S, out.dict_keys.ptr);
         F4_LAUNCH_CHECK();
     }
     hipEvent_t ev2 = stage_event(c);
 
-    out.n = n;
-    out.r = r;
-    out.N = N;
-    out.nnz = M;
-    out.deg = D;
+    out.R = (u32)R;
+    out.nnz = Mtot;
     out.closure_rounds = rounds;
     out.dict_path = (u32)path;
     if (ev0) {

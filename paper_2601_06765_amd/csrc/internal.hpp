@@ -185,10 +185,23 @@ struct DevBasis {
 };
 
 // --------------------------------------------------------------- matrix
-struct Matrix {
-    u32 n = 0, r = 0, N = 0, deg = 0;
+// A batch of independent Macaulay matrices in one set of buffers.  System i
+// owns rows [row_base, row_base + r), entries [nnz_base, nnz_base + nnz) and
+// dictionary entries [dict_base, dict_base + N); column indices are local to
+// the system.  A single matrix is the batch of one.
+struct SysPart {
+    u32 n = 0, deg = 0, r = 0, N = 0;
     u64 nnz = 0;
-    DBuf<u32> row_ptr, col_ind, val, row_k;
+    u32 row_base = 0;
+    u64 nnz_base = 0;
+    u32 dict_base = 0;
+};
+
+struct Matrix {
+    u32 S = 0, R = 0;
+    u64 nnz = 0;
+    std::vector<SysPart> sys;
+    DBuf<u32> row_ptr, col_ind, val, row_k, row_sys;  // row_ptr holds batch-global offsets
     DBuf<u64> dict_keys, row_t;
     u32 closure_rounds = 0, dict_path = 0;
     float t_dict = 0, t_assemble = 0;
@@ -196,28 +209,37 @@ struct Matrix {
 
 struct BuildArgs {
     DevBasis G;
-    const u64* rows_t = nullptr;  // device, r0 initial rows (distinct (t, k))
-    const u32* rows_k = nullptr;
+    const u64* rows_t_host = nullptr;  // r0 initial rows (distinct (t, k)), host
+    const u32* rows_k_host = nullptr;
     u32 r0 = 0;
-    const u32* active = nullptr;  // device, active basis indices in descending order
+    const u32* active_host = nullptr;  // active basis indices in descending order, host
     u32 nactive = 0;
-    u32 D = 0;                    // largest degree of any row
+    u32 D = 0;                         // largest degree of any row
     bool closure = true;
-    int dict_path = -1;           // -1 auto, 0 dense rank, 1 radix sort
+    int dict_path = -1;                // -1 auto, 0 dense rank, 1 radix sort
 };
-void build_matrix(Ctx& c, const BuildArgs& a, Matrix& out);
+// SP for every system of the batch (one launch per kernel for the batch).
+void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out);
 
 // ----------------------------------------------------------- elimination
-struct Reduced {
-    u32 N = 0, npivot = 0, rho = 0, rank = 0;
+struct RedPart {
+    u32 N = 0, npivot = 0, lower = 0, rho = 0, rank = 0;
     u64 nnz = 0;
-    DBuf<u32> pivot_cols, row_ptr, col_ind, val;
-    float t_split = 0, t_trsm = 0, t_echelon = 0, t_emit = 0;
-    u32 lower = 0;
+    u32 row_base = 0;   // first echelon row of the system
+    u64 nnz_base = 0;   // first echelon entry
+    u32 piv_base = 0;   // first pivot column entry
 };
-// Full elimination of a matrix (pivot split, triangular solve, echelon, emit).
-void reduce_matrix(Ctx& c, u32 p, const Matrix& A, Reduced& out);
-// Inter-reduction: every row of A is a pivot row (distinct leading columns);
-// returns, for each row, its tail reduced by the other rows, as CSR over the
-// columns of A (the leading entry itself is not included).
-void tail_reduce_matrix(Ctx& c, u32 p, const Matrix& A, DBuf<u32>& tptr, DBuf<u32>& tcol, DBuf<u32>& tval);
+
+struct Reduced {
+    u32 S = 0;
+    std::vector<RedPart> sys;
+    DBuf<u32> pivot_cols, row_ptr, col_ind, val;  // row_ptr holds batch-global offsets
+    float t_split = 0, t_trsm = 0, t_echelon = 0, t_emit = 0;
+};
+// Elimination of every system of a batched matrix (p[i] for system i).
+void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& out);
+// Inter-reduction: in every system all rows are pivot rows (distinct leading
+// columns); returns each row's tail reduced by the other rows, as CSR over the
+// system's columns (leading entry excluded), row order of A.
+void tail_reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, DBuf<u32>& tptr, DBuf<u32>& tcol,
+                       DBuf<u32>& tval);

@@ -1,5 +1,7 @@
-// Elimination mod p of the Macaulay matrix (section "PSGE: panel-structured
-// Gaussian elimination", two panels: pivot columns / non-pivot columns).
+// Elimination mod p of the Macaulay matrices of a batch of systems (section
+// "PSGE: panel-structured Gaussian elimination", two panels: pivot columns /
+// non-pivot columns).  One launch per kernel covers the whole batch; each
+// system has its own prime.
 //
 //  1. Split.  Pivot columns are the leading columns of the rows; each pivot
 //     column keeps one pivot row (fewest entries, then lowest index); every
@@ -11,11 +13,12 @@
 //     one wave; the panel's pivot rows beyond the panel are then applied by the
 //     whole workgroup with LDS atomic adds (no ordering needed inside a panel).
 //     The result is the trailing block D' = D - C A^-1 B, one dense row each.
-//  3. Echelon of D'.  Blocked Gauss-Jordan by lead selection: each round
-//     takes up to 32 remaining rows with distinct smallest leading columns
-//     (independent by their echelon shape), inverts their 32x32 upper
-//     triangular block at those columns, forms the new pivot rows and removes
-//     those columns from every other row (remaining rows and earlier pivots).
+//  3. Echelon of D'.  Blocked Gauss-Jordan: each round one workgroup per
+//     system computes, in place, the reduced row echelon form of the 32
+//     remaining rows with the smallest leading columns; their leading columns
+//     are pivot columns of the whole block, their nonzero rows become new
+//     pivot rows, and those columns are removed from every other row
+//     (remaining rows and earlier pivot rows) by a multi-workgroup update.
 //  4. Emit the pivot rows of D' as CSR over the original columns, sorted by
 //     leading column: the reduced row echelon form of the trailing block.
 // All arithmetic is exact mod p with Barrett reduction (equation "mod-fma").
@@ -26,44 +29,64 @@
 
 #define PANEL 64
 #define TR_THREADS 256
-#define ECH_Q 32
+#define ECH_B 32
+
+// per-system elimination descriptor
+struct SegR {
+    Fp f;
+    u32 small;     // p < 2^16 and npiv < 2^16: u32 lazy accumulators
+    u32 N, cb;     // columns, base in the concatenated column space
+    u32 rb, r;     // rows in the batch matrix
+    u32 npiv, pb;  // pivot columns, base in the concatenated pivot space
+    u32 L, lb;     // rows to reduce, base in the row list
+    u32 c, nb;     // trailing columns N - npiv, base in the concatenated non-pivot space
+    u32 tb;        // first 64x64 diagonal panel
+    u32 cap, capb; // pivot-row store capacity min(L, c), base (rows)
+    u32 ub;        // first block of the system in the echelon update grid
+    u64 dpb;       // D' base (u32 entries, row stride c)
+    u64 prb;       // pivot-row store base (u32 entries, row stride c)
+};
 
 // ------------------------------------------------------------------ split
-__global__ void k_lead_best(const u32* row_ptr, const u32* col_ind, u32 r, unsigned long long* best) {
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x) {
-        u32 len = row_ptr[i + 1] - row_ptr[i];
-        if (len) atomicMin(&best[col_ind[row_ptr[i]]], ((unsigned long long)len << 32) | i);
+__global__ void k_lead_best(const SegR* segs, const u32* row_ptr, const u32* col_ind, const u32* row_sys, u32 R,
+                            unsigned long long* best) {
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < R; i += gridDim.x * blockDim.x) {
+        const u32 len = row_ptr[i + 1] - row_ptr[i];
+        if (len) atomicMin(&best[segs[row_sys[i]].cb + col_ind[row_ptr[i]]], ((unsigned long long)len << 32) | i);
     }
 }
 
-__global__ void k_pivflag(const unsigned long long* best, u32 N, u32* flag) {
-    for (u32 c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x)
+__global__ void k_pivflag(const unsigned long long* best, u32 C, u32* flag) {
+    for (u32 c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x)
         flag[c] = best[c] != ~0ull ? 1u : 0u;
 }
 
-// perm: original column -> renumbered column (pivots first, then the rest,
-// each in original order); prow: pivot index -> its pivot row
-__global__ void k_perm(const unsigned long long* best, const u32* ppos, u32 N, u32* perm, u32* prow, u32* pivot_cols,
-                       u32* nonpiv) {
-    const u32 npiv = ppos[N];
-    for (u32 c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
-        u32 q = ppos[c];
-        if (best[c] != ~0ull) {
-            perm[c] = q;
-            prow[q] = (u32)(best[c] & 0xffffffffu);
-            pivot_cols[q] = c;
+// perm: column -> renumbered column (pivots first, then the rest, each in
+// column order); prow: pivot -> its pivot row (batch row index)
+__global__ void k_perm(const SegR* segs, const unsigned long long* best, const u32* ppos, u32* perm, u32* prow,
+                       u32* pivot_cols, u32* nonpiv) {
+    const SegR S = segs[blockIdx.y];
+    const u32 p0 = ppos[S.cb];
+    const u32 npiv = ppos[S.cb + S.N] - p0;
+    for (u32 c = blockIdx.x * blockDim.x + threadIdx.x; c < S.N; c += gridDim.x * blockDim.x) {
+        const u32 g = S.cb + c;
+        const u32 q = ppos[g] - p0;
+        if (best[g] != ~0ull) {
+            perm[g] = q;
+            prow[p0 + q] = (u32)(best[g] & 0xffffffffu);
+            pivot_cols[p0 + q] = c;
         } else {
-            perm[c] = npiv + (c - q);
-            nonpiv[c - q] = c;
+            perm[g] = npiv + (c - q);
+            nonpiv[(S.cb - p0) + (c - q)] = c;
         }
     }
 }
 
-__global__ void k_lower_flags(const u32* row_ptr, const u32* col_ind, u32 r, const unsigned long long* best,
-                              u32* flag) {
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x) {
-        u32 len = row_ptr[i + 1] - row_ptr[i];
-        flag[i] = (len == 0 || (u32)(best[col_ind[row_ptr[i]]] & 0xffffffffu) != i) ? 1u : 0u;
+__global__ void k_lower_flags(const SegR* segs, const u32* row_ptr, const u32* col_ind, const u32* row_sys, u32 R,
+                              const unsigned long long* best, u32* flag) {
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < R; i += gridDim.x * blockDim.x) {
+        const u32 len = row_ptr[i + 1] - row_ptr[i];
+        flag[i] = (len == 0 || (u32)(best[segs[row_sys[i]].cb + col_ind[row_ptr[i]]] & 0xffffffffu) != i) ? 1u : 0u;
     }
 }
 
@@ -72,43 +95,53 @@ __global__ void k_compact_idx(const u32* flag, const u32* pos, u32 n, u32* out) 
         if (flag[i]) out[pos[i]] = i;
 }
 
+__global__ void k_split_summary(const SegR* segs, u32 S, const u32* ppos, const u32* lpos, u32* out) {
+    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+        const SegR& G = segs[s];
+        out[2 * s] = ppos[G.cb + G.N] - ppos[G.cb];
+        out[2 * s + 1] = lpos[G.rb + G.r] - lpos[G.rb];
+    }
+}
+
 // Trailing-entry count of each pivot row (entries beyond its own panel).
-__global__ void k_upper_count(const u32* row_ptr, const u32* col_ind, const u32* prow, const u32* perm, u32 npiv,
-                              u32* tcnt) {
+__global__ void k_upper_count(const SegR* segs, const u32* row_ptr, const u32* col_ind, const u32* prow,
+                              const u32* perm, u32* tcnt) {
+    const SegR S = segs[blockIdx.y];
     const u32 lane = lane_id();
     const u32 nw = gridDim.x * (blockDim.x / F4_WAVE);
-    for (u32 q = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; q < npiv; q += nw) {
-        const u32 i = prow[q];
-        const u32 pend = min((q / PANEL + 1) * PANEL, npiv);  // end of the row's panel among pivots
+    for (u32 q = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; q < S.npiv; q += nw) {
+        const u32 i = prow[S.pb + q];
+        const u32 pend = min((q / PANEL + 1) * PANEL, S.npiv);
         u32 cnt = 0;
-        for (u32 e = row_ptr[i] + lane; e < row_ptr[i + 1]; e += F4_WAVE) cnt += perm[col_ind[e]] >= pend;
+        for (u32 e = row_ptr[i] + lane; e < row_ptr[i + 1]; e += F4_WAVE) cnt += perm[S.cb + col_ind[e]] >= pend;
         for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) cnt += __shfl_xor(cnt, d, F4_WAVE);
-        if (lane == 0) tcnt[q] = cnt;
+        if (lane == 0) tcnt[S.pb + q] = cnt;
     }
 }
 
 // Monic pivot rows: the part inside the row's panel goes to the dense 64x64
 // block T[panel] (unit diagonal), the rest to the packed trailing list
 // entry = val << 32 | (row within panel) << 26 | renumbered column.
-__global__ void k_upper_fill(const u32* row_ptr, const u32* col_ind, const u32* val, const u32* prow, const u32* perm,
-                             u32 npiv, Fp f, const u32* tptr, u64* tent, u32* T) {
+__global__ void k_upper_fill(const SegR* segs, const u32* row_ptr, const u32* col_ind, const u32* val,
+                             const u32* prow, const u32* perm, const u32* tptr, u64* tent, u32* T) {
+    const SegR S = segs[blockIdx.y];
     const u32 lane = lane_id();
     const u32 nw = gridDim.x * (blockDim.x / F4_WAVE);
     const u64 lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (u32 q = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; q < npiv; q += nw) {
-        const u32 i = prow[q];
+    for (u32 q = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; q < S.npiv; q += nw) {
+        const u32 i = prow[S.pb + q];
         const u32 kp = q / PANEL, b = q % PANEL;
-        const u32 pend = min((kp + 1) * PANEL, npiv);
-        const u32 inv = fp_inv(f, val[row_ptr[i]]);
-        u32* Tk = T + (u64)kp * PANEL * PANEL + (u64)b * PANEL;
-        u32 base = tptr[q];
+        const u32 pend = min((kp + 1) * PANEL, S.npiv);
+        const u32 inv = fp_inv(S.f, val[row_ptr[i]]);
+        u32* Tk = T + (u64)(S.tb + kp) * PANEL * PANEL + (u64)b * PANEL;
+        u32 base = tptr[S.pb + q];
         for (u32 e0 = row_ptr[i]; e0 < row_ptr[i + 1]; e0 += F4_WAVE) {
             const u32 e = e0 + lane;
             const bool ok = e < row_ptr[i + 1];
             u32 pc = 0, v = 0;
             if (ok) {
-                pc = perm[col_ind[e]];
-                v = fp_mul(f, val[e], inv);
+                pc = perm[S.cb + col_ind[e]];
+                v = fp_mul(S.f, val[e], inv);
             }
             const bool trail = ok && pc >= pend;
             const u64 m = wave_ballot(trail);
@@ -122,8 +155,9 @@ __global__ void k_upper_fill(const u32* row_ptr, const u32* col_ind, const u32* 
 }
 
 // ------------------------------------------------------ triangular solve
-// One workgroup per row to reduce.  SMALL: p < 2^16 (u32 lazy accumulator:
-// every column receives at most npiv additions of values < p).
+// One workgroup per row to reduce (entry g of the row list).  SMALL: p < 2^16
+// (u32 lazy accumulator: a column receives at most npiv additions of values
+// below p); otherwise u64.  Blocks of the other class return at once.
 template <bool SMALL>
 struct AccOf {
     typedef u64 T;
@@ -134,26 +168,32 @@ struct AccOf<true> {
 };
 
 template <bool SMALL, bool LDS>
-__global__ __launch_bounds__(TR_THREADS) void k_trsm(const u32* row_ptr, const u32* col_ind, const u32* val,
-                                                     const u32* src_rows, u32 row_base, u32 nrows, int skip_lead,
-                                                     const u32* perm, u32 N, u32 npiv, Fp f, const u32* T,
-                                                     const u32* tptr, const u64* tent,
-                                                     typename AccOf<SMALL>::T* gacc, u32* Dp, u64 ldd, u32* lead_out) {
+__global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, const u32* row_ptr, const u32* col_ind,
+                                                     const u32* val, const u32* row_sys, const u32* list,
+                                                     u32 list_base, u32 nlist, int skip_lead, const u32* perm,
+                                                     const u32* T, const u32* tptr, const u64* tent,
+                                                     typename AccOf<SMALL>::T* gacc, u32 gstride, u32* Dp,
+                                                     u32* lead_out) {
     typedef typename AccOf<SMALL>::T AccT;
     extern __shared__ unsigned char smraw[];
     __shared__ u32 s_x[PANEL];
     __shared__ u64 s_hit;
     __shared__ u32 s_lead;
     const u32 tid = threadIdx.x;
-    const u32 ridx = row_base + blockIdx.x;
-    if (ridx >= nrows) return;
-    AccT* acc = LDS ? (AccT*)smraw : gacc + (u64)blockIdx.x * N;
+    const u32 g = list_base + blockIdx.x;
+    if (g >= nlist) return;
+    const u32 i = list[g];
+    const SegR S = segs[row_sys[i]];
+    if ((S.small != 0) != SMALL || S.c == 0) return;
+    const Fp f = S.f;
+    const u32 N = S.N, npiv = S.npiv;
+    AccT* acc = LDS ? (AccT*)smraw : gacc + (u64)blockIdx.x * gstride;
     for (u32 j = tid; j < N; j += TR_THREADS) acc[j] = 0;
     if (tid == 0) s_lead = 0xffffffffu;
     __syncthreads();
-    const u32 i = src_rows[ridx];
+    const u32* pm = perm + S.cb;
     for (u32 e = row_ptr[i] + (skip_lead ? 1 : 0) + tid; e < row_ptr[i + 1]; e += TR_THREADS)
-        acc[perm[col_ind[e]]] = val[e];
+        acc[pm[col_ind[e]]] = val[e];
     __syncthreads();
     const u32 npanels = (npiv + PANEL - 1) / PANEL;
     const u32 lane = lane_id();
@@ -164,7 +204,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const u32* row_ptr, const u
             if (c0 < npiv) v = SMALL ? fp_reduce32(f, (u32)acc[c0]) : fp_reduce_any(f, (u64)acc[c0]);
             const u64 any = wave_ballot(v != 0);
             if (any) {
-                const u32* Tk = T + (u64)kp * PANEL * PANEL;
+                const u32* Tk = T + (u64)(S.tb + kp) * PANEL * PANEL;
                 u32 tc[PANEL];
 #pragma unroll
                 for (int b = 0; b < PANEL; ++b) tc[b] = Tk[b * PANEL + lane];
@@ -182,7 +222,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const u32* row_ptr, const u
         __syncthreads();
         if (s_hit) {
             const u32 qa = kp * PANEL, qb = min(npiv, qa + PANEL);
-            const u32 ea = tptr[qa], eb = tptr[qb];
+            const u32 ea = tptr[S.pb + qa], eb = tptr[S.pb + qb];
             for (u32 e = ea + tid; e < eb; e += TR_THREADS) {
                 const u64 t = tent[e];
                 const u32 xb = s_x[(t >> 26) & (PANEL - 1)];
@@ -196,9 +236,10 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const u32* row_ptr, const u
         __syncthreads();
     }
     // trailing block row: non-pivot part of the accumulator
-    const u32 c = N - npiv;
+    const u32 c = S.c;
+    const u32 local = g - S.lb;
+    u32* out = Dp + S.dpb + (u64)local * c;
     u32 first = 0xffffffffu;
-    u32* out = Dp + (u64)ridx * ldd;
     for (u32 j = tid; j < c; j += TR_THREADS) {
         const AccT a = acc[npiv + j];
         const u32 v = SMALL ? fp_reduce32(f, (u32)a) : fp_reduce_any(f, (u64)a);
@@ -207,128 +248,264 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const u32* row_ptr, const u
     }
     if (first != 0xffffffffu) atomicMin(&s_lead, first);
     __syncthreads();
-    if (tid == 0 && lead_out) lead_out[ridx] = s_lead;
+    if (tid == 0 && lead_out) lead_out[g] = s_lead;
 }
 
 // ---------------------------------------------------------------- echelon
-// Round header (device): [0] done flag, [1] q of this round, [2] npr (pivot
-// rows stored so far), [3] npr before this round, [4] smallest chosen column
+// Round header per system: done flag, q (new pivots this round), npr (pivot
+// rows stored so far), npr0 (npr before this round), smallest new pivot
+// column, and the new pivot columns in the order of the new pivot rows.
 struct EchRound {
-    u32 done, q, npr, npr0, cmin;
-    u32 cols[ECH_Q];
-    u32 rows[ECH_Q];
-    u32 Z[ECH_Q * ECH_Q];  // inverse of the chosen rows' block at the chosen columns
+    u32 done, q, npr, npr0, cmin, b;
+    u32 cols[ECH_B];
+    u32 rows[ECH_B];
+    u32 Z[ECH_B * ECH_B];  // row t: coefficients of new pivot row t on the block rows
 };
 
-__global__ __launch_bounds__(1024) void k_ech_select(u32 L, u32 c, const u32* lead, u32* status, const u32* Dp,
-                                                     u64 ldd, u32* cand_g, Fp f, EchRound* R, u32* prlead,
-                                                     int cand_lds) {
-    extern __shared__ u32 scand[];
+// One round of the blocked echelon, one workgroup per system.  The block is
+// the ECH_B remaining rows with the smallest (leading column, index).  The
+// workgroup finds the block's pivot columns by Gauss-Jordan elimination
+// recorded in a b x b transform Z (LDS): the block's columns are visited in
+// chunks of 64, each chunk is loaded and multiplied by Z, and the first column
+// where a non-pivot row is nonzero becomes the next pivot.  Every such column
+// is the leading column of a vector of the row space, hence a pivot column of
+// the RREF of the whole trailing block.  Scanning stops once every block row
+// is a pivot or the columns are exhausted (the other rows are then zero), so
+// all block rows are consumed; the new pivot rows are Z * (block rows), formed
+// by k_ech_np.
+#define ECH_CH 64
+__global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead, u32* status, const u32* Dp,
+                                                    u32* cnt_g, int cnt_lds, EchRound* rounds, u32* prlead,
+                                                    u32* ndone) {
+    extern __shared__ u32 scnt[];
     __shared__ u32 s_wave[33];
-    __shared__ u32 s_cols[ECH_Q], s_rows[ECH_Q];
-    __shared__ u32 s_K[ECH_Q * ECH_Q];
-    __shared__ u32 s_Z[ECH_Q * ECH_Q];
-    __shared__ u32 s_inv[ECH_Q];
+    __shared__ u32 s_rows[ECH_B], s_ispiv[ECH_B], s_f[ECH_B];
+    __shared__ u32 s_Z[ECH_B * ECH_B];
+    __shared__ u32 s_R[ECH_B * ECH_CH];
+    __shared__ u32 s_B[ECH_B * ECH_CH];
+    __shared__ u32 s_pcol[ECH_B], s_prow[ECH_B];
+    __shared__ u32 s_thr, s_need, s_q, s_cmin, s_next;
+    EchRound* R = rounds + blockIdx.y;
     if (R->done) return;
-    u32* cand = cand_lds ? scand : cand_g;
+    const SegR S = segs[blockIdx.y];
+    const Fp f = S.f;
+    const u32 L = S.L, c = S.c;
     const u32 tid = threadIdx.x;
-    for (u32 j = tid; j < c; j += 1024) cand[j] = 0xffffffffu;
+    u32* ld = lead + S.lb;
+    u32* st = status + S.lb;
+    const u32* D = Dp + S.dpb;
+    u32* cnt = cnt_lds ? scnt : cnt_g + S.nb;
+    for (u32 j = tid; j < c; j += 1024) cnt[j] = 0;
+    if (tid == 0) {
+        s_thr = c;
+        s_need = 0;
+        s_cmin = c;
+    }
     __syncthreads();
     for (u32 i = tid; i < L; i += 1024)
-        if (status[i] == 0 && lead[i] < c) atomicMin(&cand[lead[i]], i);
+        if (st[i] == 0 && ld[i] < c) atomicAdd(&cnt[ld[i]], 1u);
     __syncthreads();
-    // first ECH_Q columns that lead some remaining row
+    // threshold column: the first column where the cumulative count reaches ECH_B
     u32 carry = 0;
-    for (u32 base = 0; base < c && carry < ECH_Q; base += 1024) {
+    for (u32 base = 0; base < c; base += 1024) {
         const u32 j = base + tid;
-        const u32 fl = (j < c && cand[j] != 0xffffffffu) ? 1u : 0u;
+        const u32 v = j < c ? cnt[j] : 0;
         u32 tot;
-        const u32 pre = block_exclusive_scan(fl, s_wave, &tot);
-        if (fl && carry + pre < ECH_Q) {
-            s_cols[carry + pre] = j;
-            s_rows[carry + pre] = cand[j];
+        const u32 pre = block_exclusive_scan(v, s_wave, &tot);
+        if (j < c && carry + pre < ECH_B && carry + pre + v >= ECH_B) {
+            s_thr = j;
+            s_need = ECH_B - (carry + pre);
         }
         carry += tot;
         __syncthreads();
+        if (s_thr != c) break;
     }
-    const u32 q = carry < ECH_Q ? carry : ECH_Q;
-    if (q == 0) {
-        if (tid == 0) R->done = 1;
+    const u32 thr = s_thr, need = s_need;
+    // block rows in index order: lead < thr, then the first `need` rows with lead == thr
+    u32 nb = 0, neq = 0;
+    for (u32 base = 0; base < L; base += 1024) {
+        const u32 i = base + tid;
+        const bool live = i < L && st[i] == 0;
+        const u32 li = live ? ld[i] : c;
+        const bool eq = live && li == thr && thr < c;
+        u32 teq;
+        const u32 peq = block_exclusive_scan(eq ? 1u : 0u, s_wave, &teq);
+        const bool sel = (live && li < thr) || (eq && neq + peq < need);
+        u32 tsel;
+        const u32 psel = block_exclusive_scan(sel ? 1u : 0u, s_wave, &tsel);
+        if (sel && nb + psel < ECH_B) {
+            s_rows[nb + psel] = i;
+            s_ispiv[nb + psel] = 0;
+            atomicMin(&s_cmin, li);
+        }
+        nb += tsel;
+        neq += teq;
+    }
+    const u32 b = nb < ECH_B ? nb : ECH_B;
+    if (b == 0) {
+        if (tid == 0) {
+            R->done = 1;
+            atomicAdd(ndone, 1u);
+        }
         return;
     }
-    // block K[u][t] = D'[row_u][col_t] (upper triangular, nonzero diagonal)
-    for (u32 x = tid; x < q * q; x += 1024) {
-        const u32 u = x / q, t = x % q;
-        s_K[u * ECH_Q + t] = Dp[(u64)s_rows[u] * ldd + s_cols[t]];
-    }
+    for (u32 x = tid; x < ECH_B * ECH_B; x += 1024) s_Z[x] = (x / ECH_B == x % ECH_B) ? 1u : 0u;
+    if (tid == 0) s_q = 0;
     __syncthreads();
-    // Z = K^-1 (upper triangular): lane j solves K z = e_j by back substitution
-    if (tid < q) s_inv[tid] = fp_inv(f, s_K[tid * ECH_Q + tid]);
-    __syncthreads();
-    if (tid < q) {
-        const u32 j = tid;
-        for (int u = (int)q - 1; u >= 0; --u) {
-            u64 acc = (u32)u == j ? 1u : 0u;
-            for (u32 t = u + 1; t < q; ++t) acc += (u64)(f.p - fp_mul(f, s_K[u * ECH_Q + t], s_Z[t * ECH_Q + j]));
-            s_Z[u * ECH_Q + j] = fp_mul(f, fp_reduce_any(f, acc), s_inv[u]);
+    // chunks of 64 columns from the smallest leading column of the block
+    for (u32 j0 = s_cmin; j0 < c && s_q < b; j0 += ECH_CH) {
+        const u32 w = min((u32)ECH_CH, c - j0);
+        for (u32 x = tid; x < b * ECH_CH; x += 1024) {
+            const u32 k = x / ECH_CH, j = x % ECH_CH;
+            s_B[x] = j < w ? D[(u64)s_rows[k] * c + j0 + j] : 0u;
         }
+        __syncthreads();
+        // R = Z * B_chunk
+        for (u32 x = tid; x < b * ECH_CH; x += 1024) {
+            const u32 k = x / ECH_CH, j = x % ECH_CH;
+            u64 acc = 0;
+            for (u32 u = 0; u < b; ++u) {
+                const u32 z = s_Z[k * ECH_B + u];
+                if (z) acc += fp_mul(f, z, s_B[u * ECH_CH + j]);
+            }
+            s_R[x] = fp_reduce_any(f, acc);
+        }
+        __syncthreads();
+        u32 jstart = 0;
+        for (;;) {
+            // first column (from jstart) with a nonzero in a non-pivot row
+            if (tid == 0) s_next = ECH_CH;
+            __syncthreads();
+            if (tid < ECH_CH && tid >= jstart && tid < w) {
+                for (u32 k = 0; k < b; ++k)
+                    if (!s_ispiv[k] && s_R[k * ECH_CH + tid]) {
+                        atomicMin(&s_next, tid);
+                        break;
+                    }
+            }
+            __syncthreads();
+            const u32 jp = s_next;
+            if (jp == ECH_CH) break;
+            // pivot row: first non-pivot row nonzero at jp
+            u32 kp = ECH_B;
+            for (u32 k = 0; k < b; ++k)
+                if (!s_ispiv[k] && s_R[k * ECH_CH + jp]) {
+                    kp = k;
+                    break;
+                }
+            const u32 inv = fp_inv(f, s_R[kp * ECH_CH + jp]);
+            __syncthreads();
+            // scale the pivot row of R and Z
+            if (tid < ECH_CH) s_R[kp * ECH_CH + tid] = fp_mul(f, s_R[kp * ECH_CH + tid], inv);
+            if (tid >= ECH_CH && tid < ECH_CH + ECH_B)
+                s_Z[kp * ECH_B + (tid - ECH_CH)] = fp_mul(f, s_Z[kp * ECH_B + (tid - ECH_CH)], inv);
+            __syncthreads();
+            // eliminate column jp from the other rows of R and Z
+            if (tid < b) s_f[tid] = tid == kp ? 0u : s_R[tid * ECH_CH + jp];
+            __syncthreads();
+            for (u32 x = tid; x < b * (ECH_CH + ECH_B); x += 1024) {
+                const u32 k = x / (ECH_CH + ECH_B), col = x % (ECH_CH + ECH_B);
+                const u32 fk = s_f[k];
+                if (!fk) continue;
+                if (col < ECH_CH) {
+                    const u32 sub = fp_mul(f, fk, s_R[kp * ECH_CH + col]);
+                    const u32 old = s_R[k * ECH_CH + col];
+                    s_R[k * ECH_CH + col] = old >= sub ? old - sub : old + f.p - sub;
+                } else {
+                    const u32 cz = col - ECH_CH;
+                    const u32 sub = fp_mul(f, fk, s_Z[kp * ECH_B + cz]);
+                    const u32 old = s_Z[k * ECH_B + cz];
+                    s_Z[k * ECH_B + cz] = old >= sub ? old - sub : old + f.p - sub;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                s_ispiv[kp] = 1;
+                s_pcol[s_q] = j0 + jp;
+                s_prow[s_q] = kp;
+                s_q = s_q + 1;
+            }
+            __syncthreads();
+            jstart = jp + 1;
+            if (s_q >= b) break;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (u32 x = tid; x < q * q; x += 1024) R->Z[(x / q) * ECH_Q + (x % q)] = s_Z[(x / q) * ECH_Q + (x % q)];
+    const u32 q = s_q, npr = R->npr;
+    // round record: pivot columns, block rows and Z rows of the pivots
     if (tid < q) {
-        R->cols[tid] = s_cols[tid];
+        R->cols[tid] = s_pcol[tid];
+        prlead[S.capb + npr + tid] = s_pcol[tid];
+    }
+    for (u32 x = tid; x < q * ECH_B; x += 1024) {
+        const u32 t = x / ECH_B, u = x % ECH_B;
+        R->Z[t * ECH_B + u] = u < b ? s_Z[s_prow[t] * ECH_B + u] : 0u;
+    }
+    if (tid < b) {
         R->rows[tid] = s_rows[tid];
-        status[s_rows[tid]] = 1;
-        prlead[R->npr + tid] = s_cols[tid];
+        st[s_rows[tid]] = 1;
     }
     __syncthreads();
     if (tid == 0) {
         R->q = q;
-        R->npr0 = R->npr;
-        R->npr = R->npr + q;
-        R->cmin = s_cols[0];
+        R->b = b;
+        R->npr0 = npr;
+        R->npr = npr + q;
+        R->cmin = q ? s_pcol[0] : c;
     }
 }
 
-// New pivot rows NP = Z * (chosen rows), written to the pivot-row store.
-__global__ void k_ech_np(u32 c, const u32* Dp, u64 ldd, const EchRound* R, u32* PR, Fp f) {
+// New pivot rows NP_t = sum_u Z[t][u] * (block row u), written to the store.
+__global__ void k_ech_np(const SegR* segs, const EchRound* rounds, const u32* Dp, u32* PR) {
+    const EchRound* R = rounds + blockIdx.y;
     if (R->done) return;
-    const u32 q = R->q, npr0 = R->npr0;
+    const SegR S = segs[blockIdx.y];
+    const Fp f = S.f;
+    const u32 q = R->q, b = R->b, c = S.c;
     const u64 total = (u64)q * c;
     for (u64 x = (u64)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (u64)gridDim.x * blockDim.x) {
         const u32 t = (u32)(x / c), j = (u32)(x % c);
-        u32 v = 0;
-        if (j >= R->cmin) {
-            u64 s = 0;
-            for (u32 u = t; u < q; ++u) {
-                const u32 z = R->Z[t * ECH_Q + u];
-                if (z) s += fp_mul(f, z, Dp[(u64)R->rows[u] * ldd + j]);
-            }
-            v = fp_reduce_any(f, s);
+        u64 acc = 0;
+        for (u32 u = 0; u < b; ++u) {
+            const u32 z = R->Z[t * ECH_B + u];
+            if (z) acc += fp_mul(f, z, Dp[S.dpb + (u64)R->rows[u] * c + j]);
         }
-        PR[(u64)(npr0 + t) * ldd + j] = v;
+        PR[S.prb + (u64)(R->npr0 + t) * c + j] = fp_reduce_any(f, acc);
     }
 }
 
-// Remove the chosen columns from every other row: remaining rows of D' (grid
-// part 1) and the pivot rows stored in earlier rounds (grid part 2).
-template <bool SMALL>
-__global__ __launch_bounds__(256) void k_ech_update(u32 L, u32 c, u32* Dp, u64 ldd, u32* status, u32* lead,
-                                                    const EchRound* R, u32* PR, Fp f) {
-    __shared__ u32 s_coef[ECH_Q];
+// Remove this round's pivot columns from every other row of the system:
+// remaining rows of D' (first L blocks of the system) and the pivot rows
+// stored in earlier rounds (next cap blocks).
+__global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, const u32* ubase, u32* Dp, u32* status,
+                                                    u32* lead, const EchRound* rounds, u32* PR) {
+    __shared__ u32 s_coef[ECH_B];
     __shared__ u32 s_any, s_lead;
+    const u32 u = blockIdx.x;
+    u32 lo = 0, hi = S;  // system: last s with ubase[s] <= u
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (ubase[mid] <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const u32 s = lo;
+    const EchRound* R = rounds + s;
     if (R->done) return;
-    const u32 q = R->q, npr0 = R->npr0;
-    const u32 b = blockIdx.x;
+    const SegR G = segs[s];
+    const Fp f = G.f;
+    const u32 c = G.c, q = R->q, npr0 = R->npr0;
+    const u32 local = u - G.ub;
     u32* row;
     bool is_rem;
-    if (b < L) {
-        if (status[b] != 0 || lead[b] >= c) return;
-        row = Dp + (u64)b * ldd;
+    if (local < G.L) {
+        if (status[G.lb + local] != 0 || lead[G.lb + local] >= c) return;
+        row = Dp + G.dpb + (u64)local * c;
         is_rem = true;
     } else {
-        if (b - L >= npr0) return;
-        row = PR + (u64)(b - L) * ldd;
+        if (local - G.L >= npr0) return;
+        row = PR + G.prb + (u64)(local - G.L) * c;
         is_rem = false;
     }
     const u32 tid = threadIdx.x;
@@ -345,21 +522,21 @@ __global__ __launch_bounds__(256) void k_ech_update(u32 L, u32 c, u32* Dp, u64 l
     __syncthreads();
     if (!s_any) return;
     const u32 cmin = R->cmin;
-    const u32* NP = PR + (u64)npr0 * ldd;
+    const u32* NP = PR + G.prb + (u64)npr0 * c;
     u32 first = 0xffffffffu;
     for (u32 j = cmin + tid; j < c; j += 256) {
-        u64 s = 0;
+        u64 acc = 0;
         for (u32 t = 0; t < q; ++t) {
             const u32 cf = s_coef[t];
             if (cf) {
-                const u32 np = NP[(u64)t * ldd + j];
-                if (SMALL)
-                    s += (u64)cf * np;
+                const u32 np = NP[(u64)t * c + j];
+                if (G.small)
+                    acc += (u64)cf * np;
                 else
-                    s += fp_mul(f, cf, np);
+                    acc += fp_mul(f, cf, np);
             }
         }
-        const u32 sub = fp_reduce_any(f, s);
+        const u32 sub = fp_reduce_any(f, acc);
         const u32 old = row[j];
         const u32 nv = old >= sub ? old - sub : old + f.p - sub;
         row[j] = nv;
@@ -369,47 +546,62 @@ __global__ __launch_bounds__(256) void k_ech_update(u32 L, u32 c, u32* Dp, u64 l
         // columns below cmin are zero for remaining rows (their lead is >= cmin)
         if (first != 0xffffffffu) atomicMin(&s_lead, first);
         __syncthreads();
-        if (tid == 0) lead[b] = s_lead;
+        if (tid == 0) lead[G.lb + local] = s_lead;
     }
 }
 
+__global__ void k_ech_npr(const EchRound* rounds, u32 S, u32* out) {
+    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) out[s] = rounds[s].npr;
+}
+
 // ------------------------------------------------------------------- emit
-__global__ void k_count_nz(const u32* rows, u32 nrows, u32 c, u64 ldd, u32* cnt) {
+// keys of the pivot rows: (system, leading column); value: store row index
+__global__ void k_emit_keys(const SegR* segs, const u32* npr, const u32* ebase, const u32* prlead, u32 cbits,
+                            u64* keys, u32* vals) {
+    const u32 s = blockIdx.y;
+    const SegR G = segs[s];
+    const u32 n = npr[s];
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        keys[ebase[s] + t] = ((u64)s << cbits) | prlead[G.capb + t];
+        vals[ebase[s] + t] = G.capb + t;
+    }
+}
+
+// nonzero count of each listed row (wave per row); row `id` of system s lives
+// at base + (id - idbase) * c
+__global__ void k_count_nz(const SegR* segs, const u64* keys, u32 cbits, const u32* ids, u32 n, int from_pr,
+                           const u32* Dp, const u32* PR, u32* cnt) {
     const u32 lane = lane_id();
     const u32 nw = gridDim.x * (blockDim.x / F4_WAVE);
-    for (u32 t = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; t < nrows; t += nw) {
-        const u32* row = rows + (u64)t * ldd;
+    for (u32 t = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; t < n; t += nw) {
+        const u32 s = cbits >= 64 ? 0u : (u32)(keys[t] >> cbits);
+        const SegR G = segs[s];
+        const u32* row = from_pr ? PR + G.prb + (u64)(ids[t] - G.capb) * G.c : Dp + G.dpb + (u64)(ids[t] - G.lb) * G.c;
         u32 k = 0;
-        for (u32 j = lane; j < c; j += F4_WAVE) k += row[j] != 0;
+        for (u32 j = lane; j < G.c; j += F4_WAVE) k += row[j] != 0;
         for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) k += __shfl_xor(k, d, F4_WAVE);
         if (lane == 0) cnt[t] = k;
     }
 }
 
-// Row t of `rows` (source order `order[t]`) -> CSR row t over original columns.
-__global__ void k_emit(const u32* rows, const u32* order, u32 nrows, u32 c, u64 ldd, const u32* nonpiv,
-                       const u32* optr, u32* ocol, u32* oval, const u32* lead_col_orig, int with_lead) {
+// row t of the listed rows -> CSR row t over the system's original columns
+__global__ void k_emit(const SegR* segs, const u64* keys, u32 cbits, const u32* ids, u32 n, int from_pr,
+                       const u32* Dp, const u32* PR, const u32* nonpiv, const u32* optr, u32* ocol, u32* oval) {
     const u32 lane = lane_id();
     const u64 lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const u32 nw = gridDim.x * (blockDim.x / F4_WAVE);
-    for (u32 t = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; t < nrows; t += nw) {
-        const u32 src = order ? order[t] : t;
-        const u32* row = rows + (u64)src * ldd;
+    for (u32 t = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; t < n; t += nw) {
+        const u32 s = cbits >= 64 ? 0u : (u32)(keys[t] >> cbits);
+        const SegR G = segs[s];
+        const u32* row = from_pr ? PR + G.prb + (u64)(ids[t] - G.capb) * G.c : Dp + G.dpb + (u64)(ids[t] - G.lb) * G.c;
         u32 base = optr[t];
-        if (with_lead) {
-            if (lane == 0) {
-                ocol[base] = lead_col_orig[src];
-                oval[base] = 1;
-            }
-            base += 1;
-        }
-        for (u32 j0 = 0; j0 < c; j0 += F4_WAVE) {
+        for (u32 j0 = 0; j0 < G.c; j0 += F4_WAVE) {
             const u32 j = j0 + lane;
-            const u32 v = j < c ? row[j] : 0;
+            const u32 v = j < G.c ? row[j] : 0;
             const u64 m = wave_ballot(v != 0);
             if (v) {
                 const u32 pos = base + __popcll(m & lt);
-                ocol[pos] = nonpiv[j];
+                ocol[pos] = nonpiv[G.nb + j];
                 oval[pos] = v;
             }
             base += __popcll(m);
@@ -421,19 +613,19 @@ __global__ void k_gather_u32(const u32* in, const u32* idx, u32 n, u32* out) {
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = in[idx[i]];
 }
 
+__global__ void k_row_sys_keys(const u32* row_sys, u32 n, u64* keys) {
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        keys[i] = (u64)row_sys[i] << 32;
+}
+
 __global__ void k_iota(u32* out, u32 n) {
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = i;
 }
 
-__global__ void k_lead_keys(const u32* prlead, u32 n, u64* keys, u32* vals) {
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        keys[i] = prlead[i];
-        vals[i] = i;
-    }
-}
-
-__global__ void k_add_one(u32* cnt, u32 n) {
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) cnt[i] += 1;
+// per-system sums of a count array laid out by system: out[s] = pos[end_s] - pos[begin_s]
+__global__ void k_seg_total(const u32* pos, const u32* ebase, u32 S, u32* out) {
+    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x)
+        out[s] = pos[ebase[s + 1]] - pos[ebase[s]];
 }
 
 static u32 grid_of(u64 items, u32 per, u32 cap) {
@@ -443,209 +635,322 @@ static u32 grid_of(u64 items, u32 per, u32 cap) {
     return (u32)g;
 }
 
+static u32 bitlen(u64 x) {
+    u32 b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
 // ------------------------------------------------------------ host side
 struct SplitState {
-    u32 npiv = 0, L = 0;
+    u32 S = 0;
+    std::vector<SegR> segs;
+    DBuf<SegR> dsegs;
     DBuf<u32> perm, prow, pivot_cols, nonpiv, lower, tptr;
     DBuf<u64> tent;
     DBuf<u32> T;
+    u32 P = 0, Ltot = 0, C = 0;
 };
 
-static void do_split(Ctx& c, const Matrix& A, SplitState& S) {
+static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitState& X) {
     hipStream_t s = c.stream;
-    const u32 r = A.r, N = A.N;
-    DBuf<unsigned long long> best(&c.pool, N);
-    fill_u64((u64*)best.ptr, N, ~0ull, s);
-    hipLaunchKernelGGL(k_lead_best, dim3(grid_of(r, 256, 4096)), dim3(256), 0, s, A.row_ptr.ptr, A.col_ind.ptr, r,
-                       best.ptr);
-    F4_LAUNCH_CHECK();
-    DBuf<u32> ppos(&c.pool, (u64)N + 1);
-    hipLaunchKernelGGL(k_pivflag, dim3(grid_of(N, 256, 4096)), dim3(256), 0, s, best.ptr, N, ppos.ptr);
-    F4_LAUNCH_CHECK();
-    exclusive_scan_u32(ppos.ptr, ppos.ptr, N, c.pool, s);
-    S.perm.reset(&c.pool, N);
-    S.prow.reset(&c.pool, N);
-    S.pivot_cols.reset(&c.pool, N);
-    S.nonpiv.reset(&c.pool, N);
-    hipLaunchKernelGGL(k_perm, dim3(grid_of(N, 256, 4096)), dim3(256), 0, s, best.ptr, ppos.ptr, N, S.perm.ptr,
-                       S.prow.ptr, S.pivot_cols.ptr, S.nonpiv.ptr);
-    F4_LAUNCH_CHECK();
-    DBuf<u32> lf(&c.pool, (u64)r + 1), lpos(&c.pool, (u64)r + 1);
-    hipLaunchKernelGGL(k_lower_flags, dim3(grid_of(r, 256, 4096)), dim3(256), 0, s, A.row_ptr.ptr, A.col_ind.ptr, r,
-                       best.ptr, lf.ptr);
-    F4_LAUNCH_CHECK();
-    exclusive_scan_u32(lf.ptr, lpos.ptr, r, c.pool, s);
-    S.lower.reset(&c.pool, r);
-    hipLaunchKernelGGL(k_compact_idx, dim3(grid_of(r, 256, 4096)), dim3(256), 0, s, lf.ptr, lpos.ptr, r,
-                       S.lower.ptr);
-    F4_LAUNCH_CHECK();
-    u32 h[2];
-    {
-        u8* st = staging(c, 8);
-        F4_HIP_TRY(hipMemcpyAsync(st, ppos.ptr + N, 4, hipMemcpyDeviceToHost, s));
-        F4_HIP_TRY(hipMemcpyAsync(st + 4, lpos.ptr + r, 4, hipMemcpyDeviceToHost, s));
-        F4_HIP_TRY(hipStreamSynchronize(s));
-        std::memcpy(h, st, 8);
+    const u32 S = A.S, R = A.R;
+    X.S = S;
+    X.segs.assign(S, SegR());
+    u64 C = 0;
+    for (u32 i = 0; i < S; ++i) {
+        SegR& g = X.segs[i];
+        std::memset(&g, 0, sizeof(g));
+        g.f = make_fp(p[i]);
+        g.N = A.sys[i].N;
+        g.cb = (u32)C;
+        g.rb = A.sys[i].row_base;
+        g.r = A.sys[i].r;
+        C += g.N;
     }
-    S.npiv = h[0];
-    S.L = h[1];
-    // pivot rows: dense diagonal panels + trailing entries
-    const u32 npiv = S.npiv;
-    const u32 npanels = (npiv + PANEL - 1) / PANEL;
-    S.tptr.reset(&c.pool, (u64)npiv + 1);
-    S.T.reset(&c.pool, (u64)std::max<u32>(npanels, 1) * PANEL * PANEL);
-    fill_u32(S.T.ptr, (u64)npanels * PANEL * PANEL, 0, s);
-    if (npiv) {
-        hipLaunchKernelGGL(k_upper_count, dim3(grid_of(npiv, 4, 8192)), dim3(256), 0, s, A.row_ptr.ptr,
-                           A.col_ind.ptr, S.prow.ptr, S.perm.ptr, npiv, S.tptr.ptr);
+    if (C >= (1ull << 31)) throw F4Error{2, "batch has too many columns"};
+    X.C = (u32)C;
+    X.dsegs.reset(&c.pool, S);
+    upload(c, X.dsegs.ptr, X.segs.data(), S * sizeof(SegR));
+    DBuf<unsigned long long> best(&c.pool, std::max<u64>(C, 1));
+    fill_u64((u64*)best.ptr, C, ~0ull, s);
+    if (R) {
+        hipLaunchKernelGGL(k_lead_best, dim3(grid_of(R, 256, 4096)), dim3(256), 0, s, X.dsegs.ptr, A.row_ptr.ptr,
+                           A.col_ind.ptr, A.row_sys.ptr, R, best.ptr);
         F4_LAUNCH_CHECK();
     }
-    exclusive_scan_u32(S.tptr.ptr, S.tptr.ptr, npiv, c.pool, s);
-    S.tent.reset(&c.pool, std::max<u64>(A.nnz, 1));
-}
-
-static void fill_upper(Ctx& c, u32 p, const Matrix& A, SplitState& S) {
-    if (!S.npiv) return;
-    Fp f = make_fp(p);
-    hipLaunchKernelGGL(k_upper_fill, dim3(grid_of(S.npiv, 4, 8192)), dim3(256), 0, c.stream, A.row_ptr.ptr,
-                       A.col_ind.ptr, A.val.ptr, S.prow.ptr, S.perm.ptr, S.npiv, f, S.tptr.ptr, S.tent.ptr, S.T.ptr);
+    DBuf<u32> ppos(&c.pool, C + 1);
+    if (C) {
+        hipLaunchKernelGGL(k_pivflag, dim3(grid_of(C, 256, 4096)), dim3(256), 0, s, best.ptr, (u32)C, ppos.ptr);
+        F4_LAUNCH_CHECK();
+    }
+    exclusive_scan_u32(ppos.ptr, ppos.ptr, C, c.pool, s);
+    X.perm.reset(&c.pool, std::max<u64>(C, 1));
+    X.prow.reset(&c.pool, std::max<u64>(C, 1));
+    X.pivot_cols.reset(&c.pool, std::max<u64>(C, 1));
+    X.nonpiv.reset(&c.pool, std::max<u64>(C, 1));
+    u32 maxN = 1;
+    for (auto& g : X.segs) maxN = std::max(maxN, g.N);
+    hipLaunchKernelGGL(k_perm, dim3(std::min<u32>(64, ceil_div(maxN, 256)), S), dim3(256), 0, s, X.dsegs.ptr, best.ptr,
+                       ppos.ptr, X.perm.ptr, X.prow.ptr, X.pivot_cols.ptr, X.nonpiv.ptr);
     F4_LAUNCH_CHECK();
-}
-
-// Reduce rows src_rows[0..nrows) by the pivot rows: dense trailing rows into Dp.
-static void run_trsm(Ctx& c, u32 p, const Matrix& A, const SplitState& S, const u32* src_rows, u32 nrows,
-                     int skip_lead, u32* Dp, u64 ldd, u32* lead_out) {
-    if (!nrows) return;
-    hipStream_t s = c.stream;
-    Fp f = make_fp(p);
-    const u32 N = A.N;
-    const bool small = p < 65536 && S.npiv < 65536;
-    const size_t acc_bytes = (size_t)N * (small ? 4 : 8);
-    const bool lds = acc_bytes + 1024 <= c.dev.max_lds;
-    if (lds) {
-        if (small)
-            hipLaunchKernelGGL((k_trsm<true, true>), dim3(nrows), dim3(TR_THREADS), acc_bytes, s, A.row_ptr.ptr,
-                               A.col_ind.ptr, A.val.ptr, src_rows, 0u, nrows, skip_lead, S.perm.ptr, N, S.npiv, f,
-                               S.T.ptr, S.tptr.ptr, S.tent.ptr, (u32*)nullptr, Dp, ldd, lead_out);
-        else
-            hipLaunchKernelGGL((k_trsm<false, true>), dim3(nrows), dim3(TR_THREADS), acc_bytes, s, A.row_ptr.ptr,
-                               A.col_ind.ptr, A.val.ptr, src_rows, 0u, nrows, skip_lead, S.perm.ptr, N, S.npiv, f,
-                               S.T.ptr, S.tptr.ptr, S.tent.ptr, (u64*)nullptr, Dp, ldd, lead_out);
-        F4_LAUNCH_CHECK();
-        return;
-    }
-    // accumulators in global memory, rows in batches
-    const u32 batch = (u32)std::max<u64>(1, std::min<u64>(nrows, (u64)(1u << 30) / acc_bytes));
-    DBuf<u8> gacc(&c.pool, (u64)batch * acc_bytes);
-    for (u32 b0 = 0; b0 < nrows; b0 += batch) {
-        const u32 nb = std::min(batch, nrows - b0);
-        if (small)
-            hipLaunchKernelGGL((k_trsm<true, false>), dim3(nb), dim3(TR_THREADS), 0, s, A.row_ptr.ptr, A.col_ind.ptr,
-                               A.val.ptr, src_rows, b0, nrows, skip_lead, S.perm.ptr, N, S.npiv, f, S.T.ptr,
-                               S.tptr.ptr, S.tent.ptr, (u32*)gacc.ptr, Dp, ldd, lead_out);
-        else
-            hipLaunchKernelGGL((k_trsm<false, false>), dim3(nb), dim3(TR_THREADS), 0, s, A.row_ptr.ptr,
-                               A.col_ind.ptr, A.val.ptr, src_rows, b0, nrows, skip_lead, S.perm.ptr, N, S.npiv, f,
-                               S.T.ptr, S.tptr.ptr, S.tent.ptr, (u64*)gacc.ptr, Dp, ldd, lead_out);
+    DBuf<u32> lf(&c.pool, (u64)R + 1), lpos(&c.pool, (u64)R + 1);
+    if (R) {
+        hipLaunchKernelGGL(k_lower_flags, dim3(grid_of(R, 256, 4096)), dim3(256), 0, s, X.dsegs.ptr, A.row_ptr.ptr,
+                           A.col_ind.ptr, A.row_sys.ptr, R, best.ptr, lf.ptr);
         F4_LAUNCH_CHECK();
     }
+    exclusive_scan_u32(lf.ptr, lpos.ptr, R, c.pool, s);
+    X.lower.reset(&c.pool, std::max<u32>(R, 1));
+    if (R) {
+        hipLaunchKernelGGL(k_compact_idx, dim3(grid_of(R, 256, 4096)), dim3(256), 0, s, lf.ptr, lpos.ptr, R,
+                           X.lower.ptr);
+        F4_LAUNCH_CHECK();
+    }
+    DBuf<u32> summ(&c.pool, 2 * S);
+    hipLaunchKernelGGL(k_split_summary, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, X.dsegs.ptr, S, ppos.ptr,
+                       lpos.ptr, summ.ptr);
+    F4_LAUNCH_CHECK();
+    std::vector<u32> hs(2 * S);
+    readback(c, hs.data(), summ.ptr, hs.size() * 4);
+    // per-system layout of the elimination
+    u32 P = 0, Lb = 0, nbase = 0, tb = 0, capb = 0, ub = 0;
+    u64 dpb = 0, prb = 0;
+    for (u32 i = 0; i < S; ++i) {
+        SegR& g = X.segs[i];
+        g.npiv = hs[2 * i];
+        g.L = hs[2 * i + 1];
+        g.small = (p[i] < 65536 && g.npiv < 65536) ? 1u : 0u;
+        g.pb = P;
+        g.lb = Lb;
+        g.c = g.N - g.npiv;
+        g.nb = nbase;
+        g.tb = tb;
+        g.cap = std::min(g.L, g.c);
+        g.capb = capb;
+        g.ub = ub;
+        g.dpb = dpb;
+        g.prb = prb;
+        P += g.npiv;
+        Lb += g.L;
+        nbase += g.c;
+        tb += (g.npiv + PANEL - 1) / PANEL;
+        capb += g.cap;
+        ub += g.L + g.cap;
+        dpb += (u64)g.L * g.c;
+        prb += (u64)g.cap * g.c;
+    }
+    X.P = P;
+    X.Ltot = Lb;
+    upload(c, X.dsegs.ptr, X.segs.data(), S * sizeof(SegR));
+    X.tptr.reset(&c.pool, (u64)P + 1);
+    X.T.reset(&c.pool, (u64)std::max<u32>(tb, 1) * PANEL * PANEL);
+    fill_u32(X.T.ptr, (u64)tb * PANEL * PANEL, 0, s);
+    u32 maxP = 1;
+    for (auto& g : X.segs) maxP = std::max(maxP, g.npiv);
+    if (P) {
+        hipLaunchKernelGGL(k_upper_count, dim3(std::min<u32>(256, ceil_div(maxP, 4)), S), dim3(256), 0, s,
+                           X.dsegs.ptr, A.row_ptr.ptr, A.col_ind.ptr, X.prow.ptr, X.perm.ptr, X.tptr.ptr);
+        F4_LAUNCH_CHECK();
+    }
+    exclusive_scan_u32(X.tptr.ptr, X.tptr.ptr, P, c.pool, s);
+    X.tent.reset(&c.pool, std::max<u64>(A.nnz, 1));
+    if (P) {
+        hipLaunchKernelGGL(k_upper_fill, dim3(std::min<u32>(256, ceil_div(maxP, 4)), S), dim3(256), 0, s,
+                           X.dsegs.ptr, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, X.prow.ptr, X.perm.ptr, X.tptr.ptr,
+                           X.tent.ptr, X.T.ptr);
+        F4_LAUNCH_CHECK();
+    }
 }
 
-void reduce_matrix(Ctx& c, u32 p, const Matrix& A, Reduced& out) {
+// Reduce rows list[0..n) (batch row indices) by the pivot rows of their
+// systems; dense trailing rows go to Dp at segs[s].dpb + (g - segs[s].lb) * c.
+static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* list, u32 n, int skip_lead, u32* Dp,
+                     u32* lead_out) {
+    if (!n) return;
     hipStream_t s = c.stream;
-    if (A.N >= (1u << 26)) throw F4Error{2, "matrix has 2^26 or more columns"};
-    Fp f = make_fp(p);
+    bool any_small = false, any_large = false;
+    size_t max_small = 0, max_large = 0;
+    for (const SegR& g : X.segs) {
+        if (!g.c) continue;
+        if (g.small) {
+            any_small = true;
+            max_small = std::max<size_t>(max_small, (size_t)g.N * 4);
+        } else {
+            any_large = true;
+            max_large = std::max<size_t>(max_large, (size_t)g.N * 8);
+        }
+    }
+    for (int cls = 0; cls < 2; ++cls) {
+        const bool small = cls == 0;
+        if (small ? !any_small : !any_large) continue;
+        const size_t acc_bytes = small ? max_small : max_large;
+        const bool lds = acc_bytes + 1024 <= c.dev.max_lds;
+        if (lds) {
+            if (small)
+                hipLaunchKernelGGL((k_trsm<true, true>), dim3(n), dim3(TR_THREADS), acc_bytes, s, X.dsegs.ptr,
+                                   A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, A.row_sys.ptr, list, 0u, n, skip_lead,
+                                   X.perm.ptr, X.T.ptr, X.tptr.ptr, X.tent.ptr, (u32*)nullptr, 0u, Dp, lead_out);
+            else
+                hipLaunchKernelGGL((k_trsm<false, true>), dim3(n), dim3(TR_THREADS), acc_bytes, s, X.dsegs.ptr,
+                                   A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, A.row_sys.ptr, list, 0u, n, skip_lead,
+                                   X.perm.ptr, X.T.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, 0u, Dp, lead_out);
+            F4_LAUNCH_CHECK();
+            continue;
+        }
+        // accumulators in global memory, rows in batches
+        const u32 stride = (u32)(acc_bytes / (small ? 4 : 8));
+        const u32 batch = (u32)std::max<u64>(1, std::min<u64>(n, (u64)(1u << 30) / acc_bytes));
+        DBuf<u8> gacc(&c.pool, (u64)batch * acc_bytes);
+        for (u32 b0 = 0; b0 < n; b0 += batch) {
+            const u32 nb = std::min(batch, n - b0);
+            if (small)
+                hipLaunchKernelGGL((k_trsm<true, false>), dim3(nb), dim3(TR_THREADS), 0, s, X.dsegs.ptr,
+                                   A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, A.row_sys.ptr, list, b0, n, skip_lead,
+                                   X.perm.ptr, X.T.ptr, X.tptr.ptr, X.tent.ptr, (u32*)gacc.ptr, stride, Dp,
+                                   lead_out);
+            else
+                hipLaunchKernelGGL((k_trsm<false, false>), dim3(nb), dim3(TR_THREADS), 0, s, X.dsegs.ptr,
+                                   A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, A.row_sys.ptr, list, b0, n, skip_lead,
+                                   X.perm.ptr, X.T.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, stride, Dp,
+                                   lead_out);
+            F4_LAUNCH_CHECK();
+        }
+    }
+}
+
+void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& out) {
+    hipStream_t s = c.stream;
+    for (const SysPart& P : A.sys)
+        if (P.N >= (1u << 26)) throw F4Error{2, "matrix has 2^26 or more columns"};
     hipEvent_t e0 = stage_event(c);
-    SplitState S;
-    do_split(c, A, S);
-    fill_upper(c, p, A, S);
-    const u32 N = A.N, npiv = S.npiv, L = S.L, cc = N - npiv;
+    SplitState X;
+    do_split(c, p, A, X);
+    const u32 S = X.S;
     hipEvent_t e1 = stage_event(c);
-    out.N = N;
-    out.npivot = npiv;
-    out.lower = L;
-    out.pivot_cols = std::move(S.pivot_cols);
-    const u64 ldd = cc;
-    DBuf<u32> Dp(&c.pool, std::max<u64>((u64)L * ldd, 1)), lead(&c.pool, std::max<u32>(L, 1));
-    if (cc) run_trsm(c, p, A, S, S.lower.ptr, L, 0, Dp.ptr, ldd, lead.ptr);
+    u64 Dtot = 0, PRtot = 0;
+    u32 CAP = 0, UB = 0, maxc = 0;
+    for (const SegR& g : X.segs) {
+        Dtot += (u64)g.L * g.c;
+        PRtot += (u64)g.cap * g.c;
+        CAP += g.cap;
+        UB += g.L + g.cap;
+        maxc = std::max(maxc, g.c);
+    }
+    DBuf<u32> Dp(&c.pool, std::max<u64>(Dtot, 1)), lead(&c.pool, std::max<u32>(X.Ltot, 1));
+    run_trsm(c, A, X, X.lower.ptr, X.Ltot, 0, Dp.ptr, lead.ptr);
     hipEvent_t e2 = stage_event(c);
 
-    // echelon of D' (L x cc)
-    u32 rho = 0;
-    const u32 cap = std::min(L, cc);
-    DBuf<u32> PR(&c.pool, std::max<u64>((u64)cap * ldd, 1)), prlead(&c.pool, std::max<u32>(cap, 1));
-    if (L && cc) {
-        DBuf<u32> status(&c.pool, L);
-        fill_u32(status.ptr, L, 0, s);
-        DBuf<EchRound> R(&c.pool, 1);
-        fill_u32((u32*)R.ptr, sizeof(EchRound) / 4, 0, s);
-        const int cand_lds = (size_t)cc * 4 + 12288 <= c.dev.max_lds;
-        DBuf<u32> cand(&c.pool, cand_lds ? 1 : cc);
-        const bool small = p < 65536;
-        const u32 npgrid = grid_of((u64)ECH_Q * cc, 256, 4096);
-        u32 done = 0;
-        u32 rounds = 0;
-        while (!done) {
+    // echelon of every system's D' (L x c)
+    DBuf<u32> PR(&c.pool, std::max<u64>(PRtot, 1)), prlead(&c.pool, std::max<u32>(CAP, 1));
+    DBuf<EchRound> rounds(&c.pool, S);
+    fill_u32((u32*)rounds.ptr, (u64)S * sizeof(EchRound) / 4, 0, s);
+    std::vector<u32> npr(S, 0);
+    u32 active = 0;
+    for (const SegR& g : X.segs) active += (g.L && g.c) ? 1 : 0;
+    if (active) {
+        // systems with nothing to eliminate are done from the start
+        std::vector<EchRound> init(S);
+        std::memset(init.data(), 0, S * sizeof(EchRound));
+        for (u32 i = 0; i < S; ++i) init[i].done = (X.segs[i].L && X.segs[i].c) ? 0u : 1u;
+        upload(c, rounds.ptr, init.data(), S * sizeof(EchRound));
+        DBuf<u32> status(&c.pool, std::max<u32>(X.Ltot, 1)), ndone(&c.pool, 1), ub(&c.pool, S + 1);
+        fill_u32(status.ptr, X.Ltot, 0, s);
+        fill_u32(ndone.ptr, 1, 0, s);
+        std::vector<u32> hub(S + 1);
+        for (u32 i = 0; i < S; ++i) hub[i] = X.segs[i].ub;
+        hub[S] = UB;
+        upload(c, ub.ptr, hub.data(), (S + 1) * 4);
+        const int cnt_lds = (size_t)maxc * 4 + 32768 <= c.dev.max_lds;
+        DBuf<u32> cnt(&c.pool, cnt_lds ? 1 : std::max<u64>(X.C, 1));
+        u32 done = 0, r = 0;
+        while (done < active) {
             for (int k = 0; k < 4; ++k) {
-                hipLaunchKernelGGL(k_ech_select, dim3(1), dim3(1024), cand_lds ? (size_t)cc * 4 : 0, s, L, cc,
-                                   lead.ptr, status.ptr, Dp.ptr, ldd, cand.ptr, f, R.ptr, prlead.ptr, cand_lds);
+                hipLaunchKernelGGL(k_ech_block, dim3(1, S), dim3(1024), cnt_lds ? (size_t)maxc * 4 : 0, s,
+                                   X.dsegs.ptr, lead.ptr, status.ptr, Dp.ptr, cnt.ptr, cnt_lds, rounds.ptr,
+                                   prlead.ptr, ndone.ptr);
                 F4_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_ech_np, dim3(npgrid), dim3(256), 0, s, cc, Dp.ptr, ldd, R.ptr, PR.ptr, f);
+                hipLaunchKernelGGL(k_ech_np, dim3(grid_of((u64)ECH_B * maxc, 256, 256), S), dim3(256), 0, s,
+                                   X.dsegs.ptr, rounds.ptr, Dp.ptr, PR.ptr);
                 F4_LAUNCH_CHECK();
-                if (small)
-                    hipLaunchKernelGGL(k_ech_update<true>, dim3(L + cap), dim3(256), 0, s, L, cc, Dp.ptr, ldd,
-                                       status.ptr, lead.ptr, R.ptr, PR.ptr, f);
-                else
-                    hipLaunchKernelGGL(k_ech_update<false>, dim3(L + cap), dim3(256), 0, s, L, cc, Dp.ptr, ldd,
-                                       status.ptr, lead.ptr, R.ptr, PR.ptr, f);
+                hipLaunchKernelGGL(k_ech_update, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s, X.dsegs.ptr, S, ub.ptr,
+                                   Dp.ptr, status.ptr, lead.ptr, rounds.ptr, PR.ptr);
                 F4_LAUNCH_CHECK();
-                ++rounds;
+                ++r;
             }
-            u32 h[3];
-            readback(c, h, R.ptr, 12);
-            done = h[0];
-            rho = h[2];
-            if (rounds > cap + 8) throw F4Error{5, "echelon did not converge"};
+            readback(c, &done, ndone.ptr, 4);
+            if (r > CAP + 8 + 4 * (X.Ltot / ECH_B + 1)) throw F4Error{5, "echelon did not converge"};
         }
+        DBuf<u32> dnpr(&c.pool, S);
+        hipLaunchKernelGGL(k_ech_npr, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, rounds.ptr, S, dnpr.ptr);
+        F4_LAUNCH_CHECK();
+        readback(c, npr.data(), dnpr.ptr, S * 4);
     }
     hipEvent_t e3 = stage_event(c);
 
-    // emit RREF(D') over the original columns, rows by leading column
-    out.rho = rho;
-    out.rank = npiv + rho;
-    out.row_ptr.reset(&c.pool, (u64)rho + 1);
-    if (rho) {
-        DBuf<u64> keys(&c.pool, rho);
-        DBuf<u32> order(&c.pool, rho);
-        hipLaunchKernelGGL(k_lead_keys, dim3(grid_of(rho, 256, 1024)), dim3(256), 0, s, prlead.ptr, rho, keys.ptr,
-                           order.ptr);
+    // emit RREF(D') over the original columns, rows by (system, leading column)
+    out.S = S;
+    out.sys.assign(S, RedPart());
+    std::vector<u32> eb(S + 1, 0);
+    for (u32 i = 0; i < S; ++i) eb[i + 1] = eb[i] + npr[i];
+    const u32 E = eb[S];
+    out.row_ptr.reset(&c.pool, (u64)E + 1);
+    std::vector<u32> rnnz(S, 0);
+    if (E) {
+        const u32 cbits = std::max<u32>(1, bitlen(std::max<u32>(maxc, 1)));
+        const u32 sbits = S > 1 ? bitlen(S - 1) : 0;
+        DBuf<u32> debase(&c.pool, S + 1);
+        upload(c, debase.ptr, eb.data(), (S + 1) * 4);
+        DBuf<u64> keys(&c.pool, E);
+        DBuf<u32> ids(&c.pool, E), cnt(&c.pool, (u64)E + 1);
+        u32 maxr = 1;
+        for (u32 v : npr) maxr = std::max(maxr, v);
+        DBuf<u32> dnpr(&c.pool, S);
+        upload(c, dnpr.ptr, npr.data(), S * 4);
+        hipLaunchKernelGGL(k_emit_keys, dim3(std::min<u32>(16, ceil_div(maxr, 256)), S), dim3(256), 0, s, X.dsegs.ptr,
+                           dnpr.ptr, debase.ptr, prlead.ptr, cbits, keys.ptr, ids.ptr);
         F4_LAUNCH_CHECK();
-        u32 bits = 1;
-        while ((1ull << bits) < cc) ++bits;
-        radix_sort_pairs(keys.ptr, order.ptr, rho, 0, bits, c.pool, s);
-        DBuf<u32> cnt(&c.pool, (u64)rho + 1);
-        DBuf<u32> sorted_cnt(&c.pool, (u64)rho + 1);
-        hipLaunchKernelGGL(k_count_nz, dim3(grid_of(rho, 4, 4096)), dim3(256), 0, s, PR.ptr, rho, cc, ldd, cnt.ptr);
+        radix_sort_pairs(keys.ptr, ids.ptr, E, 0, cbits + sbits, c.pool, s);
+        const u32 kc = S > 1 ? cbits : 64u;
+        hipLaunchKernelGGL(k_count_nz, dim3(grid_of(E, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, kc,
+                           ids.ptr, E, 1, Dp.ptr, PR.ptr, cnt.ptr);
         F4_LAUNCH_CHECK();
-        // counts in output order
-        hipLaunchKernelGGL(k_gather_u32, dim3(grid_of(rho, 256, 1024)), dim3(256), 0, s, cnt.ptr, order.ptr, rho,
-                           sorted_cnt.ptr);
+        exclusive_scan_u32(cnt.ptr, out.row_ptr.ptr, E, c.pool, s);
+        DBuf<u32> tot(&c.pool, S);
+        hipLaunchKernelGGL(k_seg_total, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, out.row_ptr.ptr, debase.ptr, S,
+                           tot.ptr);
         F4_LAUNCH_CHECK();
-        exclusive_scan_u32(sorted_cnt.ptr, out.row_ptr.ptr, rho, c.pool, s);
-        u32 nnz = 0;
-        readback(c, &nnz, out.row_ptr.ptr + rho, 4);
-        out.nnz = nnz;
-        out.col_ind.reset(&c.pool, std::max<u32>(nnz, 1));
-        out.val.reset(&c.pool, std::max<u32>(nnz, 1));
-        hipLaunchKernelGGL(k_emit, dim3(grid_of(rho, 4, 4096)), dim3(256), 0, s, PR.ptr, order.ptr, rho, cc, ldd,
-                           S.nonpiv.ptr, out.row_ptr.ptr, out.col_ind.ptr, out.val.ptr, (const u32*)nullptr, 0);
+        readback(c, rnnz.data(), tot.ptr, S * 4);
+        u64 nnz = 0;
+        for (u32 v : rnnz) nnz += v;
+        out.col_ind.reset(&c.pool, std::max<u64>(nnz, 1));
+        out.val.reset(&c.pool, std::max<u64>(nnz, 1));
+        hipLaunchKernelGGL(k_emit, dim3(grid_of(E, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, kc, ids.ptr, E,
+                           1, Dp.ptr, PR.ptr, X.nonpiv.ptr, out.row_ptr.ptr, out.col_ind.ptr, out.val.ptr);
         F4_LAUNCH_CHECK();
     } else {
         fill_u32(out.row_ptr.ptr, 1, 0, s);
-        out.nnz = 0;
         out.col_ind.reset(&c.pool, 1);
         out.val.reset(&c.pool, 1);
     }
+    u64 nb = 0;
+    for (u32 i = 0; i < S; ++i) {
+        RedPart& P = out.sys[i];
+        P.N = X.segs[i].N;
+        P.npivot = X.segs[i].npiv;
+        P.lower = X.segs[i].L;
+        P.rho = npr[i];
+        P.rank = P.npivot + P.rho;
+        P.nnz = rnnz[i];
+        P.row_base = eb[i];
+        P.nnz_base = nb;
+        P.piv_base = X.segs[i].pb;
+        nb += rnnz[i];
+    }
+    out.pivot_cols = std::move(X.pivot_cols);
     hipEvent_t e4 = stage_event(c);
     if (e0) {
         F4_HIP_TRY(hipEventSynchronize(e4));
@@ -656,27 +961,40 @@ void reduce_matrix(Ctx& c, u32 p, const Matrix& A, Reduced& out) {
     }
 }
 
-void tail_reduce_matrix(Ctx& c, u32 p, const Matrix& A, DBuf<u32>& tptr, DBuf<u32>& tcol, DBuf<u32>& tval) {
+void tail_reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, DBuf<u32>& tptr, DBuf<u32>& tcol,
+                       DBuf<u32>& tval) {
     hipStream_t s = c.stream;
-    SplitState S;
-    do_split(c, A, S);
-    if (S.L != 0) throw F4Error{6, "inter-reduction matrix has repeated leading monomials"};
-    fill_upper(c, p, A, S);
-    const u32 r = A.r, cc = A.N - S.npiv;
-    const u64 ldd = std::max<u32>(cc, 1);
-    DBuf<u32> rows(&c.pool, r), Dp(&c.pool, (u64)r * ldd), cnt(&c.pool, (u64)r + 1);
-    hipLaunchKernelGGL(k_iota, dim3(grid_of(r, 256, 1024)), dim3(256), 0, s, rows.ptr, r);
+    SplitState X;
+    do_split(c, p, A, X);
+    if (X.Ltot != 0) throw F4Error{6, "inter-reduction matrix has repeated leading monomials"};
+    const u32 S = X.S, R = A.R;
+    // every row is reduced: the row list is all rows, D' rows follow the row order
+    u64 dpb = 0;
+    for (u32 i = 0; i < S; ++i) {
+        SegR& g = X.segs[i];
+        g.lb = g.rb;
+        g.dpb = dpb;
+        dpb += (u64)g.r * g.c;
+    }
+    upload(c, X.dsegs.ptr, X.segs.data(), S * sizeof(SegR));
+    DBuf<u32> rows(&c.pool, std::max<u32>(R, 1)), Dp(&c.pool, std::max<u64>(dpb, 1)), cnt(&c.pool, (u64)R + 1);
+    DBuf<u64> keys(&c.pool, std::max<u32>(R, 1));
+    hipLaunchKernelGGL(k_iota, dim3(grid_of(R, 256, 1024)), dim3(256), 0, s, rows.ptr, R);
     F4_LAUNCH_CHECK();
-    if (cc) run_trsm(c, p, A, S, rows.ptr, r, 1, Dp.ptr, ldd, nullptr);
-    hipLaunchKernelGGL(k_count_nz, dim3(grid_of(r, 4, 4096)), dim3(256), 0, s, Dp.ptr, r, cc, ldd, cnt.ptr);
+    // system of each row as a key (for the wave kernels below)
+    hipLaunchKernelGGL(k_row_sys_keys, dim3(grid_of(R, 256, 1024)), dim3(256), 0, s, A.row_sys.ptr, R, keys.ptr);
     F4_LAUNCH_CHECK();
-    tptr.reset(&c.pool, (u64)r + 1);
-    exclusive_scan_u32(cnt.ptr, tptr.ptr, r, c.pool, s);
+    run_trsm(c, A, X, rows.ptr, R, 1, Dp.ptr, nullptr);
+    hipLaunchKernelGGL(k_count_nz, dim3(grid_of(R, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, 32u, rows.ptr, R,
+                       0, Dp.ptr, Dp.ptr, cnt.ptr);
+    F4_LAUNCH_CHECK();
+    tptr.reset(&c.pool, (u64)R + 1);
+    exclusive_scan_u32(cnt.ptr, tptr.ptr, R, c.pool, s);
     u32 nnz = 0;
-    readback(c, &nnz, tptr.ptr + r, 4);
+    readback(c, &nnz, tptr.ptr + R, 4);
     tcol.reset(&c.pool, std::max<u32>(nnz, 1));
     tval.reset(&c.pool, std::max<u32>(nnz, 1));
-    hipLaunchKernelGGL(k_emit, dim3(grid_of(r, 4, 4096)), dim3(256), 0, s, Dp.ptr, (const u32*)nullptr, r, cc, ldd,
-                       S.nonpiv.ptr, tptr.ptr, tcol.ptr, tval.ptr, (const u32*)nullptr, 0);
+    hipLaunchKernelGGL(k_emit, dim3(grid_of(R, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, 32u, rows.ptr, R, 0,
+                       Dp.ptr, Dp.ptr, X.nonpiv.ptr, tptr.ptr, tcol.ptr, tval.ptr);
     F4_LAUNCH_CHECK();
 }

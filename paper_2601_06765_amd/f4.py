@@ -88,9 +88,17 @@ _sig("f4_reduce", c_int, [c_vp, c_u32, c_vp, P(c_vp), c_vp])
 _sig("f4_reduced_get", c_int, [c_vp, P(ReducedView)])
 _sig("f4_reduced_free", c_int, [c_vp])
 _sig("f4_groebner", c_int, [c_vp, c_u32, P(Polys), P(c_vp), c_vp])
+_sig("f4_groebner_batch", c_int, [c_vp, c_u32, P(c_u32), P(Polys), P(c_vp), c_vp])
 _sig("f4_basis_view", c_int, [c_vp, P(Polys)])
 _sig("f4_basis_stats", c_int, [c_vp, P(P(StepStats)), P(c_u32)])
 _sig("f4_basis_free", c_int, [c_vp])
+_sig("f4_server_footprint", c_int, [c_u32, c_u32, P(c_u64)])
+_sig("f4_server_create", c_int, [c_vp, c_u64, c_u32, P(c_vp)])
+_sig("f4_server_submit", c_int, [c_vp, c_u32, P(Polys), P(c_u64)])
+_sig("f4_server_step", c_int, [c_vp, P(c_u32)])
+_sig("f4_server_poll", c_int, [c_vp, c_u64, P(c_vp), P(c_int)])
+_sig("f4_server_load", c_int, [c_vp, P(c_u32), P(c_u32), P(c_u64)])
+_sig("f4_server_destroy", c_int, [c_vp])
 
 
 class F4Error(RuntimeError):
@@ -207,6 +215,26 @@ class Context:
         return out
 
     # -- full F4
+    def _basis(self, h, n):
+        v = Polys()
+        _lib.f4_basis_view(h, ctypes.byref(v))
+        k = v.npolys
+        offs = np.ctypeslib.as_array(ctypes.cast(v.offset, P(c_u64)), (k + 1,)).copy() if k else [0]
+        nt = int(offs[-1])
+        mons = np.ctypeslib.as_array(ctypes.cast(v.mon, P(c_u64)), (nt,)).copy() if nt else []
+        cfs = np.ctypeslib.as_array(ctypes.cast(v.coeff, P(c_u32)), (nt,)).copy() if nt else []
+        basis = []
+        for a in range(k):
+            basis.append([(unpack(n, int(mons[q])), int(cfs[q])) for q in range(int(offs[a]), int(offs[a + 1]))])
+        sp = P(StepStats)()
+        ns = c_u32()
+        _lib.f4_basis_stats(h, ctypes.byref(sp), ctypes.byref(ns))
+        steps = []
+        for i in range(ns.value):
+            s = sp[i]
+            steps.append({name: getattr(s, name) for name, _ in StepStats._fields_})
+        return basis, steps
+
     def groebner(self, p, n, polys, stream=None):
         """Reduced Groebner basis of a system given as lists of (exps, coeff).
         Returns (basis, steps): basis as lists of (exps, coeff), leading term
@@ -216,26 +244,37 @@ class Context:
         h = c_vp()
         self._check(_lib.f4_groebner(self._h, p, ctypes.byref(arg.s), ctypes.byref(h), c_vp(stream)))
         try:
-            v = Polys()
-            _lib.f4_basis_view(h, ctypes.byref(v))
-            k = v.npolys
-            offs = np.ctypeslib.as_array(ctypes.cast(v.offset, P(c_u64)), (k + 1,)).copy() if k else [0]
-            nt = int(offs[-1])
-            mons = np.ctypeslib.as_array(ctypes.cast(v.mon, P(c_u64)), (nt,)).copy() if nt else []
-            cfs = np.ctypeslib.as_array(ctypes.cast(v.coeff, P(c_u32)), (nt,)).copy() if nt else []
-            basis = []
-            for a in range(k):
-                basis.append([(unpack(n, int(mons[q])), int(cfs[q])) for q in range(int(offs[a]), int(offs[a + 1]))])
-            sp = P(StepStats)()
-            ns = c_u32()
-            _lib.f4_basis_stats(h, ctypes.byref(sp), ctypes.byref(ns))
-            steps = []
-            for i in range(ns.value):
-                s = sp[i]
-                steps.append({name: getattr(s, name) for name, _ in StepStats._fields_})
+            return self._basis(h, n)
         finally:
             _lib.f4_basis_free(h)
-        return basis, steps
+
+    def prepare_batch(self, systems):
+        """Marshal [(p, n, polys), ...] once; the result feeds groebner_batch_prepared."""
+        args = [_PolysArg(n, *polys_to_arrays(n, [[(e, c % p) for e, c in f] for f in polys]))
+                for p, n, polys in systems]
+        arr = (Polys * len(args))(*[a.s for a in args])
+        ps = (c_u32 * len(args))(*[p for p, _, _ in systems])
+        ns = [n for _, n, _ in systems]
+        return (args, arr, ps, ns)
+
+    def groebner_batch_prepared(self, prep, stream=None):
+        args, arr, ps, ns = prep
+        hs = (c_vp * len(args))()
+        self._check(_lib.f4_groebner_batch(self._h, len(args), ps, arr, hs, c_vp(stream)))
+        out = []
+        try:
+            for i, n in enumerate(ns):
+                out.append(self._basis(hs[i], n))
+        finally:
+            for i in range(len(args)):
+                if hs[i]:
+                    _lib.f4_basis_free(hs[i])
+        return out
+
+    def groebner_batch(self, systems, stream=None):
+        """Reduced Groebner bases of independent systems [(p, n, polys), ...],
+        computed together (one batched launch sequence per F4 iteration)."""
+        return self.groebner_batch_prepared(self.prepare_batch(systems), stream)
 
     # -- one step
     def build_matrix(self, p, n, G, active, sel, stream=None, device_arrays=None):
@@ -335,3 +374,66 @@ class Reduced:
                 "row_ptr": d(v.row_ptr, v.rho + 1, np.uint32),
                 "col_ind": d(v.col_ind, v.nnz, np.uint32),
                 "val": d(v.val, v.nnz, np.uint32)}
+
+
+def server_footprint(n, m):
+    out = c_u64()
+    rc = _lib.f4_server_footprint(n, m, ctypes.byref(out))
+    if rc:
+        raise F4Error(rc, "footprint")
+    return out.value
+
+
+class Server:
+    """Continuous-batching F4 server on a context (f4_server_* of include/f4.h)."""
+
+    def __init__(self, ctx, hbm_budget, max_slots):
+        self.ctx = ctx
+        self._h = c_vp()
+        ctx._check(_lib.f4_server_create(ctx._h, hbm_budget, max_slots, ctypes.byref(self._h)))
+        self._n = {}
+
+    @staticmethod
+    def prepare(p, n, polys):
+        return (p, n, _PolysArg(n, *polys_to_arrays(n, [[(e, c % p) for e, c in f] for f in polys])))
+
+    def submit_prepared(self, prep):
+        """Ticket, or None when the server is busy (retry after a step)."""
+        p, n, arg = prep
+        t = c_u64()
+        rc = _lib.f4_server_submit(self._h, p, ctypes.byref(arg.s), ctypes.byref(t))
+        if rc == F4_E_BUSY:
+            return None
+        self.ctx._check(rc)
+        self._n[t.value] = n
+        return t.value
+
+    def submit(self, p, n, polys):
+        return self.submit_prepared(self.prepare(p, n, polys))
+
+    def step(self):
+        k = c_u32()
+        self.ctx._check(_lib.f4_server_step(self._h, ctypes.byref(k)))
+        return k.value
+
+    def poll(self, ticket):
+        """(basis, steps) when finished (the slot is released), else None."""
+        h = c_vp()
+        d = c_int()
+        self.ctx._check(_lib.f4_server_poll(self._h, ticket, ctypes.byref(h), ctypes.byref(d)))
+        if not d.value:
+            return None
+        try:
+            return self.ctx._basis(h, self._n.pop(ticket))
+        finally:
+            _lib.f4_basis_free(h)
+
+    def load(self):
+        a, b, u = c_u32(), c_u32(), c_u64()
+        _lib.f4_server_load(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(u))
+        return a.value, b.value, u.value
+
+    def close(self):
+        if self._h and self.ctx._h:
+            _lib.f4_server_destroy(self._h)
+        self._h = c_vp()
