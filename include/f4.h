@@ -210,6 +210,7 @@ typedef struct f4_step_stats {
     float t_trsm_ms;      /* of which the sparse triangular solve */
     float t_echelon_ms;   /* of which the trailing-block echelon */
     float t_step_ms;      /* host wall time of the whole step */
+    float t_pairs_ms;     /* host time of pair selection and Gebauer-Moeller updates */
 } f4_step_stats;
 
 /* Reduced Groebner basis of <F> under grevlex (unique: monic, minimal,

@@ -352,6 +352,7 @@ struct SysState {
     std::vector<u64> rt;
     std::vector<u32> rk, act;
     u32 d = 0, nsel = 0;
+    float tpairs = 0;
     std::chrono::steady_clock::time_point t0;
 };
 
@@ -509,6 +510,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
         std::vector<u32> primes;
         for (SysState* S : work) {
             S->t0 = std::chrono::steady_clock::now();
+            const auto tp0 = S->t0;
             u32 d = 255;
             for (auto& q : S->P) d = std::min(d, deg_of(q.lcm));
             if (d >= (1u << S->mo.w)) throw F4Error{F4_E_RANGE, "step degree overflows an exponent lane"};
@@ -523,6 +525,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             prepare_rows(*S, rows);
             S->d = d;
             S->nsel = (u32)sel.size();
+            S->tpairs = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - tp0).count();
             args.push_back(args_of(*S, true));
             primes.push_back(S->p);
         }
@@ -592,6 +595,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             st.t_numeric_ms = R.t_split + R.t_trsm + R.t_echelon + R.t_emit;
             st.t_trsm_ms = R.t_trsm;
             st.t_echelon_ms = R.t_echelon;
+            const auto tg0 = std::chrono::steady_clock::now();
             for (u32 t = 0; t < P.rho && !S.unit; ++t) {
                 const u32 h = (u32)S.lm.size();
                 S.lm.push_back(newlm[lmbase[i] + t]);
@@ -602,7 +606,9 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
                 }
                 gm_update(S.mo, S.lm, S.active, S.P, h);
             }
-            st.t_step_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - S.t0).count();
+            const auto tg1 = std::chrono::steady_clock::now();
+            st.t_pairs_ms = S.tpairs + std::chrono::duration<float, std::milli>(tg1 - tg0).count();
+            st.t_step_ms = std::chrono::duration<float, std::milli>(tg1 - S.t0).count();
             S.steps.push_back(st);
         }
         c.ev_used = 0;

@@ -195,17 +195,25 @@ __global__ void k_frontier_write(const SegSP* segs, const u32* present, u32* don
 
 // One reducer per frontier monomial m: the active element with the largest
 // index whose leading monomial divides m; the new row is (m / LM(g), g).
-__global__ __launch_bounds__(MB_THREADS) void k_reducers(const SegSP* segs, const u32* list_q, const u32* list_s,
-                                                          const u32* count_ptr, const u32* active, u64* rows_t,
+// Grid (blocks, systems): a system's frontier entries are contiguous in the
+// list, and its active leading monomials are staged in LDS when they fit.
+__global__ __launch_bounds__(MB_THREADS) void k_reducers(const SegSP* segs, const u32* list_q, const u32* fscan,
+                                                          const u32* active, int lds_active, u64* rows_t,
                                                           u32* rows_k, u32* row_lmrank, u32* ctr) {
-    const u32 cnt = *count_ptr;
-    for (u32 i = blockIdx.x * MB_THREADS + threadIdx.x; i < cnt; i += gridDim.x * MB_THREADS) {
-        const u32 q = list_q[i], s = list_s[i];
-        const SegSP& S = segs[s];
+    extern __shared__ u64 slm[];
+    const u32 s = blockIdx.y;
+    const SegSP S = segs[s];
+    const u32* act = active + S.abase;
+    if (lds_active) {
+        for (u32 a = threadIdx.x; a < S.nactive; a += MB_THREADS) slm[a] = S.lm[act[a]];
+        __syncthreads();
+    }
+    const u32 f0 = fscan[S.wbase], f1 = fscan[S.wbase + S.nwords];
+    for (u32 i = f0 + blockIdx.x * MB_THREADS + threadIdx.x; i < f1; i += gridDim.x * MB_THREADS) {
+        const u32 q = list_q[i];
         const u64 m = S.montab[q];
-        const u32* act = active + S.abase;
         for (u32 a = 0; a < S.nactive; ++a) {
-            const u64 l = S.lm[act[a]];
+            const u64 l = lds_active ? slm[a] : S.lm[act[a]];
             if (mono_divides(l, m, S.n, S.w)) {
                 const u32 slot = atomicAdd(&ctr[CTR * s + 1], 1u);
                 if (slot >= S.rcap) {
@@ -548,6 +556,10 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     DBuf<u32> summary(&c.pool, 8 * S);
     const u32 wgrid = grid_for(W, 256, 2048);
     const u32 wbx = std::max<u32>(1, std::min<u32>(64, ceil_div(max_words, 256)));
+    u32 max_act = 0;
+    for (u32 i = 0; i < S; ++i) max_act = std::max(max_act, segs[i].nactive);
+    const int lds_active = (size_t)max_act * 8 <= 64 * 1024;
+    const u32 rbx_red = std::max<u32>(1, std::min<u32>(256, ceil_div(ceil_div(max_nmax, MB_THREADS), 1)));
     u32 rounds = 0;
     std::vector<u32> hs(8 * S);
     for (;;) {
@@ -561,9 +573,9 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
                 hipLaunchKernelGGL(k_frontier_write, dim3(wbx, S), dim3(256), 0, s, dsegs.ptr, present.ptr, done.ptr,
                                    fcnt.ptr, list_q.ptr, list_s.ptr, ctr.ptr);
                 F4_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_reducers, dim3(grid_for(CM, MB_THREADS, 2048)), dim3(MB_THREADS), 0, s,
-                                   dsegs.ptr, list_q.ptr, list_s.ptr, fcnt.ptr + W, active.ptr, rows_t.ptr,
-                                   rows_k.ptr, row_lmrank.ptr, ctr.ptr);
+                hipLaunchKernelGGL(k_reducers, dim3(rbx_red, S), dim3(MB_THREADS), lds_active ? max_act * 8 : 0, s,
+                                   dsegs.ptr, list_q.ptr, fcnt.ptr, active.ptr, lds_active, rows_t.ptr, rows_k.ptr,
+                                   row_lmrank.ptr, ctr.ptr);
                 F4_LAUNCH_CHECK();
                 mark();
                 ++rounds;

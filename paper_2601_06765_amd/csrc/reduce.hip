@@ -220,15 +220,24 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, const u32
             if (lane == 0) s_hit = hit;
         }
         __syncthreads();
-        if (s_hit) {
-            const u32 qa = kp * PANEL, qb = min(npiv, qa + PANEL);
-            const u32 ea = tptr[S.pb + qa], eb = tptr[S.pb + qb];
-            for (u32 e = ea + tid; e < eb; e += TR_THREADS) {
-                const u64 t = tent[e];
-                const u32 xb = s_x[(t >> 26) & (PANEL - 1)];
-                if (xb) {
-                    const u32 add = SMALL ? fp_reduce32(f, (f.p - xb) * (u32)(t >> 32))
-                                          : fp_reduce(f, (u64)(f.p - xb) * (u32)(t >> 32));
+        const u64 hit = s_hit;
+        if (hit) {
+            // each wave takes every fourth hit pivot row; lanes stride over the
+            // row's trailing entries (contiguous), LDS atomics merge columns
+            const u32 wave = tid / F4_WAVE;
+            const u32* tp = tptr + S.pb + kp * PANEL;
+            u64 hm = hit;
+            u32 rk = 0;
+            while (hm) {
+                const u32 b = __ffsll((long long)hm) - 1;
+                hm &= hm - 1;
+                if ((rk++ & (TR_THREADS / F4_WAVE - 1)) != wave) continue;
+                const u32 negx = f.p - s_x[b];
+                const u32 ea = tp[b], eb = tp[b + 1];
+                for (u32 e = ea + lane; e < eb; e += F4_WAVE) {
+                    const u64 t = tent[e];
+                    const u32 add = SMALL ? fp_reduce32(f, negx * (u32)(t >> 32))
+                                          : fp_reduce(f, (u64)negx * (u32)(t >> 32));
                     atomicAdd(&acc[(u32)t & 0x3ffffffu], (AccT)add);
                 }
             }
@@ -265,26 +274,112 @@ struct EchRound {
 // One round of the blocked echelon, one workgroup per system.  The block is
 // the ECH_B remaining rows with the smallest (leading column, index).  The
 // workgroup finds the block's pivot columns by Gauss-Jordan elimination
-// recorded in a b x b transform Z (LDS): the block's columns are visited in
-// chunks of 64, each chunk is loaded and multiplied by Z, and the first column
-// where a non-pivot row is nonzero becomes the next pivot.  Every such column
-// is the leading column of a vector of the row space, hence a pivot column of
-// the RREF of the whole trailing block.  Scanning stops once every block row
-// is a pivot or the columns are exhausted (the other rows are then zero), so
-// all block rows are consumed; the new pivot rows are Z * (block rows), formed
-// by k_ech_np.
-#define ECH_CH 64
+// recorded in a b x b transform Z: the block's columns are visited in chunks
+// of ECH_CH, each chunk is loaded and multiplied by Z (all threads), then one
+// wave eliminates on the chunk with the rows in registers (lane j < ECH_CH
+// holds column j of the chunk, lane ECH_CH + u holds column u of Z), so a
+// pivot costs one modular product per row and no block barrier.  The first
+// column where a non-pivot row is nonzero becomes the next pivot; every such
+// column is the leading column of a vector of the row space, hence a pivot
+// column of the RREF of the whole trailing block.  Scanning stops once every
+// block row is a pivot or the columns are exhausted (the other rows are then
+// zero), so all block rows are consumed; the new pivot rows Z * (block rows),
+// formed by k_ech_np, are reduced on all pivot columns of the round.
+#define ECH_CH 32
+
+template <bool SMALL>
+__device__ __forceinline__ u32 fp_mul_t(const Fp& f, u32 a, u32 b) {
+    return SMALL ? fp_reduce32(f, a * b) : fp_reduce(f, (u64)a * b);  // SMALL: a*b < p^2 < 2^32
+}
+
+template <bool SMALL>
+__device__ __forceinline__ u32 fp_inv_t(const Fp& f, u32 a) {
+    u32 e = f.p - 2, r = 1;
+    while (e) {
+        if (e & 1) r = fp_mul_t<SMALL>(f, r, a);
+        a = fp_mul_t<SMALL>(f, a, a);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Gauss-Jordan on one chunk by the calling wave.  s_R: b x ECH_CH chunk of
+// Z * B; s_Z: the transform (row stride ECH_B); *s_q / *s_pmask: pivots so far
+// and the bit mask of block rows that are pivots.  Appends the new pivots'
+// columns and rows to s_pcol / s_prow and writes Z back.
+template <bool SMALL>
+__device__ void ech_chunk_gj(const Fp& f, u32 b, u32 w, u32 j0, const u32* s_R, u32* s_Z, u32* s_q, u32* s_pmask,
+                             u32* s_pcol, u32* s_prow) {
+    const u32 lane = lane_id();
+    u32 r[ECH_B];
+#pragma unroll
+    for (int k = 0; k < ECH_B; ++k)
+        r[k] = (u32)k < b ? (lane < ECH_CH ? s_R[k * ECH_CH + lane] : s_Z[k * ECH_B + lane - ECH_CH]) : 0u;
+    const u32 live = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
+    u32 q = *s_q, pmask = *s_pmask, jstart = 0;
+    while (q < b) {
+        const u32 np = live & ~pmask;
+        u32 nz = 0;
+#pragma unroll
+        for (int k = 0; k < ECH_B; ++k)
+            if ((np >> k) & 1u) nz |= r[k];
+        const u64 m = wave_ballot(nz != 0 && lane >= jstart && lane < w);
+        if (!m) break;
+        const u32 jp = __ffsll((long long)m) - 1;
+        u32 kp = ECH_B, piv = 0;
+#pragma unroll
+        for (int k = 0; k < ECH_B; ++k) {
+            const u32 v = __builtin_amdgcn_readlane(r[k], jp);
+            if (kp == ECH_B && ((np >> k) & 1u) && v) {
+                kp = k;
+                piv = v;
+            }
+        }
+        const u32 inv = fp_inv_t<SMALL>(f, piv);
+        u32 prow = 0;
+#pragma unroll
+        for (int k = 0; k < ECH_B; ++k)
+            if ((u32)k == kp) {
+                r[k] = fp_mul_t<SMALL>(f, r[k], inv);
+                prow = r[k];
+            }
+#pragma unroll
+        for (int k = 0; k < ECH_B; ++k) {
+            if ((u32)k == kp) continue;
+            const u32 fk = __builtin_amdgcn_readlane(r[k], jp);
+            if (fk) {
+                const u32 x = r[k] + fp_mul_t<SMALL>(f, f.p - fk, prow);
+                r[k] = x >= f.p ? x - f.p : x;
+            }
+        }
+        if (lane == 0) {
+            s_pcol[q] = j0 + jp;
+            s_prow[q] = kp;
+        }
+        pmask |= 1u << kp;
+        ++q;
+        jstart = jp + 1;
+    }
+#pragma unroll
+    for (int k = 0; k < ECH_B; ++k)
+        if ((u32)k < b && lane >= ECH_CH) s_Z[k * ECH_B + lane - ECH_CH] = r[k];
+    if (lane == 0) {
+        *s_q = q;
+        *s_pmask = pmask;
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead, u32* status, const u32* Dp,
                                                     u32* cnt_g, int cnt_lds, EchRound* rounds, u32* prlead,
                                                     u32* ndone) {
     extern __shared__ u32 scnt[];
     __shared__ u32 s_wave[33];
-    __shared__ u32 s_rows[ECH_B], s_ispiv[ECH_B], s_f[ECH_B];
+    __shared__ u32 s_rows[ECH_B];
     __shared__ u32 s_Z[ECH_B * ECH_B];
     __shared__ u32 s_R[ECH_B * ECH_CH];
     __shared__ u32 s_B[ECH_B * ECH_CH];
     __shared__ u32 s_pcol[ECH_B], s_prow[ECH_B];
-    __shared__ u32 s_thr, s_need, s_q, s_cmin, s_next;
+    __shared__ u32 s_thr, s_need, s_q, s_pmask, s_cmin;
     EchRound* R = rounds + blockIdx.y;
     if (R->done) return;
     const SegR S = segs[blockIdx.y];
@@ -335,7 +430,6 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         const u32 psel = block_exclusive_scan(sel ? 1u : 0u, s_wave, &tsel);
         if (sel && nb + psel < ECH_B) {
             s_rows[nb + psel] = i;
-            s_ispiv[nb + psel] = 0;
             atomicMin(&s_cmin, li);
         }
         nb += tsel;
@@ -350,9 +444,13 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         return;
     }
     for (u32 x = tid; x < ECH_B * ECH_B; x += 1024) s_Z[x] = (x / ECH_B == x % ECH_B) ? 1u : 0u;
-    if (tid == 0) s_q = 0;
+    if (tid == 0) {
+        s_q = 0;
+        s_pmask = 0;
+    }
     __syncthreads();
-    // chunks of 64 columns from the smallest leading column of the block
+    const bool small = S.small != 0;
+    // chunks of ECH_CH columns from the smallest leading column of the block
     for (u32 j0 = s_cmin; j0 < c && s_q < b; j0 += ECH_CH) {
         const u32 w = min((u32)ECH_CH, c - j0);
         for (u32 x = tid; x < b * ECH_CH; x += 1024) {
@@ -360,74 +458,27 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
             s_B[x] = j < w ? D[(u64)s_rows[k] * c + j0 + j] : 0u;
         }
         __syncthreads();
-        // R = Z * B_chunk
+        // R = Z * B_chunk: the block rows as transformed so far, on this chunk
+        const bool ident = s_q == 0;
         for (u32 x = tid; x < b * ECH_CH; x += 1024) {
             const u32 k = x / ECH_CH, j = x % ECH_CH;
+            if (ident) {
+                s_R[x] = s_B[x];
+                continue;
+            }
             u64 acc = 0;
             for (u32 u = 0; u < b; ++u) {
                 const u32 z = s_Z[k * ECH_B + u];
-                if (z) acc += fp_mul(f, z, s_B[u * ECH_CH + j]);
+                if (z) acc += small ? (u64)z * s_B[u * ECH_CH + j] : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
             }
             s_R[x] = fp_reduce_any(f, acc);
         }
         __syncthreads();
-        u32 jstart = 0;
-        for (;;) {
-            // first column (from jstart) with a nonzero in a non-pivot row
-            if (tid == 0) s_next = ECH_CH;
-            __syncthreads();
-            if (tid < ECH_CH && tid >= jstart && tid < w) {
-                for (u32 k = 0; k < b; ++k)
-                    if (!s_ispiv[k] && s_R[k * ECH_CH + tid]) {
-                        atomicMin(&s_next, tid);
-                        break;
-                    }
-            }
-            __syncthreads();
-            const u32 jp = s_next;
-            if (jp == ECH_CH) break;
-            // pivot row: first non-pivot row nonzero at jp
-            u32 kp = ECH_B;
-            for (u32 k = 0; k < b; ++k)
-                if (!s_ispiv[k] && s_R[k * ECH_CH + jp]) {
-                    kp = k;
-                    break;
-                }
-            const u32 inv = fp_inv(f, s_R[kp * ECH_CH + jp]);
-            __syncthreads();
-            // scale the pivot row of R and Z
-            if (tid < ECH_CH) s_R[kp * ECH_CH + tid] = fp_mul(f, s_R[kp * ECH_CH + tid], inv);
-            if (tid >= ECH_CH && tid < ECH_CH + ECH_B)
-                s_Z[kp * ECH_B + (tid - ECH_CH)] = fp_mul(f, s_Z[kp * ECH_B + (tid - ECH_CH)], inv);
-            __syncthreads();
-            // eliminate column jp from the other rows of R and Z
-            if (tid < b) s_f[tid] = tid == kp ? 0u : s_R[tid * ECH_CH + jp];
-            __syncthreads();
-            for (u32 x = tid; x < b * (ECH_CH + ECH_B); x += 1024) {
-                const u32 k = x / (ECH_CH + ECH_B), col = x % (ECH_CH + ECH_B);
-                const u32 fk = s_f[k];
-                if (!fk) continue;
-                if (col < ECH_CH) {
-                    const u32 sub = fp_mul(f, fk, s_R[kp * ECH_CH + col]);
-                    const u32 old = s_R[k * ECH_CH + col];
-                    s_R[k * ECH_CH + col] = old >= sub ? old - sub : old + f.p - sub;
-                } else {
-                    const u32 cz = col - ECH_CH;
-                    const u32 sub = fp_mul(f, fk, s_Z[kp * ECH_B + cz]);
-                    const u32 old = s_Z[k * ECH_B + cz];
-                    s_Z[k * ECH_B + cz] = old >= sub ? old - sub : old + f.p - sub;
-                }
-            }
-            __syncthreads();
-            if (tid == 0) {
-                s_ispiv[kp] = 1;
-                s_pcol[s_q] = j0 + jp;
-                s_prow[s_q] = kp;
-                s_q = s_q + 1;
-            }
-            __syncthreads();
-            jstart = jp + 1;
-            if (s_q >= b) break;
+        if (tid < F4_WAVE) {
+            if (small)
+                ech_chunk_gj<true>(f, b, w, j0, s_R, s_Z, &s_q, &s_pmask, s_pcol, s_prow);
+            else
+                ech_chunk_gj<false>(f, b, w, j0, s_R, s_Z, &s_q, &s_pmask, s_pcol, s_prow);
         }
         __syncthreads();
     }

@@ -60,7 +60,8 @@ class StepStats(ctypes.Structure):
                 ("closure_rounds", c_u32), ("dict_path", c_u32),
                 ("t_dict_ms", ctypes.c_float), ("t_assemble_ms", ctypes.c_float),
                 ("t_numeric_ms", ctypes.c_float), ("t_trsm_ms", ctypes.c_float),
-                ("t_echelon_ms", ctypes.c_float), ("t_step_ms", ctypes.c_float)]
+                ("t_echelon_ms", ctypes.c_float), ("t_step_ms", ctypes.c_float),
+                ("t_pairs_ms", ctypes.c_float)]
 
 
 def _sig(name, res, args):
