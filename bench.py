@@ -33,7 +33,23 @@ def parse():
     ap.add_argument("--dict", choices=["rank", "radix"], default=None)
     ap.add_argument("--batch-systems", type=int, default=256, help="systems in the batched leg (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg (0: skip)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 5 times (reference kernel for HBM byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """A plain device-to-device copy of known size: under rocprofv3 --pmc its
+    FETCH_SIZE / WRITE_SIZE per dispatch give the counters' scale."""
+    import torch
+    n = mib << 20
+    src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "launches": 5}))
 
 
 def cpu_baseline(n, p, polys, seconds):
@@ -139,6 +155,9 @@ def main():
         print("bench.py measures one GPU only (this build has no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     import torch
     import synth
     import paper_2601_06765_amd.f4 as f4

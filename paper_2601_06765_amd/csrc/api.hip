@@ -48,18 +48,26 @@ struct f4_basis {
 
 // ------------------------------------------------------------ staging
 u8* staging(Ctx& c, size_t bytes) {
-    if (c.staging_pending) {
-        F4_HIP_TRY(hipEventSynchronize(c.staging_done));
-        c.staging_pending = false;
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (c.pinned_used + need > c.pinned_bytes) {
+        // wrap around: every copy out of the arena must have finished
+        if (c.staging_pending) {
+            F4_HIP_TRY(hipEventSynchronize(c.staging_done));
+            c.staging_pending = false;
+        }
+        c.pinned_used = 0;
+        if (need > c.pinned_bytes) {
+            const size_t nb = std::max(need, (size_t)2 * c.pinned_bytes);
+            if (c.pinned) F4_HIP_TRY(hipHostFree(c.pinned));
+            c.pinned = nullptr;
+            c.pinned_bytes = 0;
+            F4_HIP_TRY(hipHostMalloc((void**)&c.pinned, nb, hipHostMallocDefault));
+            c.pinned_bytes = nb;
+        }
     }
-    if (bytes > c.pinned_bytes) {
-        if (c.pinned) F4_HIP_TRY(hipHostFree(c.pinned));
-        c.pinned = nullptr;
-        size_t nb = std::max(bytes, (size_t)2 * c.pinned_bytes);
-        F4_HIP_TRY(hipHostMalloc((void**)&c.pinned, nb, hipHostMallocDefault));
-        c.pinned_bytes = nb;
-    }
-    return c.pinned;
+    u8* p = c.pinned + c.pinned_used;
+    c.pinned_used += need;
+    return p;
 }
 
 void upload(Ctx& c, void* dst, const void* src, size_t bytes) {
@@ -82,6 +90,9 @@ void readback(Ctx& c, void* dst, const void* src, size_t bytes) {
     F4_HIP_TRY(hipMemcpyAsync(st, src, bytes, hipMemcpyDeviceToHost, c.stream));
     F4_HIP_TRY(hipStreamSynchronize(c.stream));
     std::memcpy(dst, st, bytes);
+    // the stream is idle: no copy uses the arena any more
+    c.staging_pending = false;
+    c.pinned_used = 0;
 }
 
 hipEvent_t stage_event(Ctx& c) {
@@ -102,47 +113,7 @@ float event_ms(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-// ----------------------------------------------------- packed monomials (host)
-// SWAR forms are valid while every exponent is below 2^(w-1) (the lane's top
-// bit free as a guard), which holds when the degree is below 2^(w-1); above
-// that the lanes are compared one by one.
-struct MonoOps {
-    u32 n, w, guard;
-    u64 lanes, H;  // lane bits, lane top bits
-    void init(u32 n_) {
-        n = n_;
-        w = lane_bits(n);
-        guard = 1u << (w - 1);
-        lanes = (n * w >= 64) ? ~0ull : ((1ull << (n * w)) - 1);
-        H = 0;
-        for (u32 i = 0; i < n; ++i) H |= 1ull << (w * i + w - 1);
-    }
-    bool divides(u64 a, u64 b) const {  // a | b
-        if ((u32)(a >> 56) >= guard || (u32)(b >> 56) >= guard) return mono_divides(a, b, n, w);
-        return ((((b & lanes) | H) - (a & lanes)) & H) == H;
-    }
-    u64 lcm(u64 a, u64 b) const {
-        if ((u32)(a >> 56) >= guard || (u32)(b >> 56) >= guard) return mono_lcm(a, b, n, w);
-        u64 ge = (((a & lanes) | H) - (b & lanes)) & H;  // lanes where a >= b
-        u64 m = (ge >> (w - 1)) * ((1ull << w) - 1);
-        u64 l = (a & m) | (b & ~m & lanes);
-        u32 d = 0;
-        for (u32 i = 0; i < n; ++i) d += (u32)((l >> (w * i)) & ((1u << w) - 1));
-        return l | ((u64)d << 56);
-    }
-    bool coprime(u64 a, u64 b) const {
-        for (u32 i = 0; i < n; ++i)
-            if (mono_exp(a, i, w) && mono_exp(b, i, w)) return false;
-        return true;
-    }
-    u64 order_key(u64 P) const { return P ^ lanes; }
-};
-
-// ------------------------------------------------------------ driver state
-struct HPair {
-    u32 i, j;
-    u64 lcm;
-};
+#include "pairs.hpp"
 
 struct DevG {
     u32 n = 0, npolys = 0;
@@ -216,47 +187,6 @@ static DevBasis devg_view(const DevG& G) {
     b.lm = G.lm.ptr;
     b.len = G.len.ptr;
     return b;
-}
-
-// Gebauer-Moeller update inserting basis element h (Becker-Weispfenning):
-// new pairs (h, g) are pruned by the chain and product criteria, old pairs
-// whose lcm is a proper multiple witnessed by LM(h) are removed, and basis
-// elements whose leading monomial LM(h) divides become inactive.
-static void gm_update(const MonoOps& mo, std::vector<u64>& lm, std::vector<u8>& active, std::vector<HPair>& P,
-                      u32 h) {
-    const u64 lh = lm[h];
-    std::vector<u32> C;
-    for (u32 g = 0; g < h; ++g)
-        if (active[g]) C.push_back(g);
-    const size_t nc = C.size();
-    std::vector<u64> L(nc);
-    for (size_t a = 0; a < nc; ++a) L[a] = mo.lcm(lh, lm[C[a]]);
-    std::vector<u8> kept(nc, 0);
-    for (size_t a = 0; a < nc; ++a) {
-        bool keep = mo.coprime(lh, lm[C[a]]);
-        if (!keep) {
-            bool covered = false;
-            // still-pending pairs (b > a) and already kept ones (b < a)
-            for (size_t b = 0; b < nc && !covered; ++b) {
-                if (b == a) continue;
-                if ((b > a || kept[b]) && mo.divides(L[b], L[a])) covered = true;
-            }
-            keep = !covered;
-        }
-        kept[a] = keep;
-    }
-    std::vector<HPair> Pn;
-    Pn.reserve(P.size() + nc);
-    for (const HPair& q : P) {
-        bool drop = mo.divides(lh, q.lcm) && mo.lcm(lm[q.i], lh) != q.lcm && mo.lcm(lh, lm[q.j]) != q.lcm;
-        if (!drop) Pn.push_back(q);
-    }
-    for (size_t a = 0; a < nc; ++a)
-        if (kept[a] && !mo.coprime(lh, lm[C[a]])) Pn.push_back({C[a], h, L[a]});
-    P.swap(Pn);
-    for (u32 g = 0; g < h; ++g)
-        if (active[g] && mo.divides(lh, lm[g])) active[g] = 0;
-    active[h] = 1;
 }
 
 static u32 powmod_host(u64 a, u64 e, u64 p) {
@@ -343,6 +273,7 @@ struct SysState {
     std::vector<u64> lm;
     std::vector<u8> active;
     std::vector<HPair> P;
+    GmScratch gm;
     bool unit = false, done = false;
     std::vector<f4_step_stats> steps;
     // reduced basis (host), filled at the end
@@ -493,7 +424,7 @@ static void init_system(Ctx& c, SysState& S, u32 p, const f4_polys* F) {
     for (u32 k = 0; k < D.npolys; ++k) {
         S.lm.push_back(inputs[k][0].first);
         S.active.push_back(0);
-        gm_update(S.mo, S.lm, S.active, S.P, k);
+        gm_insert(S.mo, S.gm, S.lm, S.active, S.P, k);
     }
 }
 
@@ -571,6 +502,8 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             F4_LAUNCH_CHECK();
             readback(c, newlm.data(), dlm.ptr, (u64)nl * 8);
         }
+        A.read_times();
+        R.read_times();
         for (size_t i = 0; i < work.size(); ++i) {
             SysState& S = *work[i];
             const RedPart& P = R.sys[i];
@@ -604,7 +537,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
                     S.unit = true;
                     break;
                 }
-                gm_update(S.mo, S.lm, S.active, S.P, h);
+                gm_insert(S.mo, S.gm, S.lm, S.active, S.P, h);
             }
             const auto tg1 = std::chrono::steady_clock::now();
             st.t_pairs_ms = S.tpairs + std::chrono::duration<float, std::milli>(tg1 - tg0).count();
@@ -751,7 +684,8 @@ int f4_create(f4_ctx** out, int device, const f4_opts* opts) {
         F4_HIP_TRY(hipStreamCreateWithFlags(&X->c.own_stream, hipStreamNonBlocking));
         X->c.stream = X->c.own_stream;
         F4_HIP_TRY(hipEventCreateWithFlags(&X->c.staging_done, hipEventDisableTiming));
-        staging(X->c, 1 << 20);
+        staging(X->c, 8u << 20);
+        X->c.pinned_used = 0;
     } catch (const F4Error& e) {
         int code = e.code;
         delete X;

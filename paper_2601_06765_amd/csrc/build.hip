@@ -707,9 +707,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     out.nnz = Mtot;
     out.closure_rounds = rounds;
     out.dict_path = (u32)path;
-    if (ev0) {
-        F4_HIP_TRY(hipEventSynchronize(ev2));
-        out.t_dict = event_ms(ev0, ev1);
-        out.t_assemble = event_ms(ev1, ev2);
-    }
+    out.ev[0] = ev0;
+    out.ev[1] = ev1;
+    out.ev[2] = ev2;
 }

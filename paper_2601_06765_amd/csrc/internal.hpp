@@ -145,10 +145,12 @@ struct Ctx {
     Pool pool;
     u32 flags = 0;
     std::string last_error;
-    // pinned host staging for small uploads / readbacks
+    // pinned host arena for small uploads / readbacks: uploads take successive
+    // regions (no wait while the arena has room); a readback drains the
+    // stream, after which the whole arena is free again
     u8* pinned = nullptr;
-    size_t pinned_bytes = 0;
-    hipEvent_t staging_done = nullptr;  // last async copy out of / into `pinned`
+    size_t pinned_bytes = 0, pinned_used = 0;
+    hipEvent_t staging_done = nullptr;  // last async copy out of the arena
     bool staging_pending = false;
     // caches keyed by (n, D): binomial table and dense-rank -> monomial table
     std::map<std::pair<u32, u32>, DBuf<u32>> binom;
@@ -158,7 +160,8 @@ struct Ctx {
     u32 ev_used = 0;
 };
 
-// Wait until the pinned staging buffer can be rewritten, return it (>= bytes).
+// Next free region (>= bytes) of the pinned arena; waits for the copies in
+// flight only when the arena has to wrap around.
 u8* staging(Ctx& c, size_t bytes);
 // Enqueue an H2D copy of host data through the staging buffer (small arrays).
 void upload(Ctx& c, void* dst, const void* src, size_t bytes);
@@ -204,7 +207,14 @@ struct Matrix {
     DBuf<u32> row_ptr, col_ind, val, row_k, row_sys;  // row_ptr holds batch-global offsets
     DBuf<u64> dict_keys, row_t;
     u32 closure_rounds = 0, dict_path = 0;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // stage boundaries (timing on)
     float t_dict = 0, t_assemble = 0;
+    void read_times() {  // once the stream has passed ev[2]
+        if (!ev[0]) return;
+        (void)hipEventSynchronize(ev[2]);
+        t_dict = event_ms(ev[0], ev[1]);
+        t_assemble = event_ms(ev[1], ev[2]);
+    }
 };
 
 struct BuildArgs {
@@ -234,7 +244,16 @@ struct Reduced {
     u32 S = 0;
     std::vector<RedPart> sys;
     DBuf<u32> pivot_cols, row_ptr, col_ind, val;  // row_ptr holds batch-global offsets
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_split = 0, t_trsm = 0, t_echelon = 0, t_emit = 0;
+    void read_times() {
+        if (!ev[0]) return;
+        (void)hipEventSynchronize(ev[4]);
+        t_split = event_ms(ev[0], ev[1]);
+        t_trsm = event_ms(ev[1], ev[2]);
+        t_echelon = event_ms(ev[2], ev[3]);
+        t_emit = event_ms(ev[3], ev[4]);
+    }
 };
 // Elimination of every system of a batched matrix (p[i] for system i).
 void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& out);

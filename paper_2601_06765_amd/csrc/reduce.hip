@@ -284,7 +284,7 @@ struct EchRound {
 // column of the RREF of the whole trailing block.  Scanning stops once every
 // block row is a pivot or the columns are exhausted (the other rows are then
 // zero), so all block rows are consumed; the new pivot rows Z * (block rows),
-// formed by k_ech_np, are reduced on all pivot columns of the round.
+// formed by k_ech_update, are reduced on all pivot columns of the round.
 #define ECH_CH 32
 
 template <bool SMALL>
@@ -506,31 +506,16 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     }
 }
 
-// New pivot rows NP_t = sum_u Z[t][u] * (block row u), written to the store.
-__global__ void k_ech_np(const SegR* segs, const EchRound* rounds, const u32* Dp, u32* PR) {
-    const EchRound* R = rounds + blockIdx.y;
-    if (R->done) return;
-    const SegR S = segs[blockIdx.y];
-    const Fp f = S.f;
-    const u32 q = R->q, b = R->b, c = S.c;
-    const u64 total = (u64)q * c;
-    for (u64 x = (u64)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (u64)gridDim.x * blockDim.x) {
-        const u32 t = (u32)(x / c), j = (u32)(x % c);
-        u64 acc = 0;
-        for (u32 u = 0; u < b; ++u) {
-            const u32 z = R->Z[t * ECH_B + u];
-            if (z) acc += fp_mul(f, z, Dp[S.dpb + (u64)R->rows[u] * c + j]);
-        }
-        PR[S.prb + (u64)(R->npr0 + t) * c + j] = fp_reduce_any(f, acc);
-    }
-}
-
-// Remove this round's pivot columns from every other row of the system:
-// remaining rows of D' (first L blocks of the system) and the pivot rows
-// stored in earlier rounds (next cap blocks).
+// One kernel per round after the block step, one workgroup per row slot of a
+// system (remaining rows of D': the first L slots; the pivot-row store: the
+// next cap slots).  Store slots npr0 .. npr0+q-1 form this round's new pivot
+// rows NP_t = sum_u Z[t][u] * (block row u).  Every other live row r loses its
+// entries on the round's pivot columns: with coef_t = r[col_t],
+// r - sum_t coef_t NP_t = r - sum_u w_u (block row u), w = coef * Z, so the
+// update reads the block rows directly and does not wait for NP.
 __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, const u32* ubase, u32* Dp, u32* status,
                                                     u32* lead, const EchRound* rounds, u32* PR) {
-    __shared__ u32 s_coef[ECH_B];
+    __shared__ u32 s_coef[ECH_B], s_w[ECH_B], s_rows[ECH_B];
     __shared__ u32 s_any, s_lead;
     const u32 u = blockIdx.x;
     u32 lo = 0, hi = S;  // system: last s with ubase[s] <= u
@@ -546,8 +531,11 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
     if (R->done) return;
     const SegR G = segs[s];
     const Fp f = G.f;
-    const u32 c = G.c, q = R->q, npr0 = R->npr0;
+    const bool small = G.small != 0;
+    const u32 c = G.c, q = R->q, b = R->b, npr0 = R->npr0;
     const u32 local = u - G.ub;
+    const u32 tid = threadIdx.x;
+    const u32* D = Dp + G.dpb;
     u32* row;
     bool is_rem;
     if (local < G.L) {
@@ -555,15 +543,36 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
         row = Dp + G.dpb + (u64)local * c;
         is_rem = true;
     } else {
-        if (local - G.L >= npr0) return;
-        row = PR + G.prb + (u64)(local - G.L) * c;
+        const u32 k = local - G.L;
+        if (k >= npr0 + q) return;
+        row = PR + G.prb + (u64)k * c;
         is_rem = false;
+        if (k >= npr0) {
+            const u32 t = k - npr0;
+            if (tid < b) {
+                s_w[tid] = R->Z[t * ECH_B + tid];
+                s_rows[tid] = R->rows[tid];
+            }
+            __syncthreads();
+            for (u32 j = tid; j < c; j += 256) {
+                u64 acc = 0;
+                for (u32 v = 0; v < b; ++v) {
+                    const u32 z = s_w[v];
+                    if (z) {
+                        const u32 x = D[(u64)s_rows[v] * c + j];
+                        acc += small ? (u64)z * x : (u64)fp_mul(f, z, x);
+                    }
+                }
+                row[j] = fp_reduce_any(f, acc);
+            }
+            return;
+        }
     }
-    const u32 tid = threadIdx.x;
     if (tid == 0) {
         s_any = 0;
         s_lead = 0xffffffffu;
     }
+    if (tid < b) s_rows[tid] = R->rows[tid];
     __syncthreads();
     if (tid < q) {
         const u32 v = row[R->cols[tid]];
@@ -572,19 +581,27 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
     }
     __syncthreads();
     if (!s_any) return;
-    const u32 cmin = R->cmin;
-    const u32* NP = PR + G.prb + (u64)npr0 * c;
-    u32 first = 0xffffffffu;
-    for (u32 j = cmin + tid; j < c; j += 256) {
+    if (tid < b) {
         u64 acc = 0;
         for (u32 t = 0; t < q; ++t) {
             const u32 cf = s_coef[t];
             if (cf) {
-                const u32 np = NP[(u64)t * c + j];
-                if (G.small)
-                    acc += (u64)cf * np;
-                else
-                    acc += fp_mul(f, cf, np);
+                const u32 z = R->Z[t * ECH_B + tid];
+                acc += small ? (u64)cf * z : (u64)fp_mul(f, cf, z);
+            }
+        }
+        s_w[tid] = fp_reduce_any(f, acc);
+    }
+    __syncthreads();
+    const u32 cmin = R->cmin;
+    u32 first = 0xffffffffu;
+    for (u32 j = cmin + tid; j < c; j += 256) {
+        u64 acc = 0;
+        for (u32 v = 0; v < b; ++v) {
+            const u32 w = s_w[v];
+            if (w) {
+                const u32 x = D[(u64)s_rows[v] * c + j];
+                acc += small ? (u64)w * x : (u64)fp_mul(f, w, x);
             }
         }
         const u32 sub = fp_reduce_any(f, acc);
@@ -924,9 +941,6 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
                                    X.dsegs.ptr, lead.ptr, status.ptr, Dp.ptr, cnt.ptr, cnt_lds, rounds.ptr,
                                    prlead.ptr, ndone.ptr);
                 F4_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_ech_np, dim3(grid_of((u64)ECH_B * maxc, 256, 256), S), dim3(256), 0, s,
-                                   X.dsegs.ptr, rounds.ptr, Dp.ptr, PR.ptr);
-                F4_LAUNCH_CHECK();
                 hipLaunchKernelGGL(k_ech_update, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s, X.dsegs.ptr, S, ub.ptr,
                                    Dp.ptr, status.ptr, lead.ptr, rounds.ptr, PR.ptr);
                 F4_LAUNCH_CHECK();
@@ -1003,13 +1017,11 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
     }
     out.pivot_cols = std::move(X.pivot_cols);
     hipEvent_t e4 = stage_event(c);
-    if (e0) {
-        F4_HIP_TRY(hipEventSynchronize(e4));
-        out.t_split = event_ms(e0, e1);
-        out.t_trsm = event_ms(e1, e2);
-        out.t_echelon = event_ms(e2, e3);
-        out.t_emit = event_ms(e3, e4);
-    }
+    out.ev[0] = e0;
+    out.ev[1] = e1;
+    out.ev[2] = e2;
+    out.ev[3] = e3;
+    out.ev[4] = e4;
 }
 
 void tail_reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, DBuf<u32>& tptr, DBuf<u32>& tcol,
