@@ -28,7 +28,8 @@
 #include "internal.hpp"
 
 #define PANEL 64
-#define TR_THREADS 256
+#define TR_THREADS 1024
+#define TR_UNROLL 8
 #define ECH_B 32
 
 // per-system elimination descriptor
@@ -154,10 +155,50 @@ __global__ void k_upper_fill(const SegR* segs, const u32* row_ptr, const u32* co
     }
 }
 
+// Inverse of every panel's diagonal block (unit upper triangular, the pivot
+// rows are monic): row b of T^-1 is the x with x T = e_b, found by forward
+// substitution, one wave per row (lanes are columns).  A row's panel solve is
+// then x = l T^-1: independent products instead of a 64-step chain.
+__global__ __launch_bounds__(256) void k_tinv(const SegR* segs, const u32* T, u32* Tinv) {
+    const SegR S = segs[blockIdx.y];
+    const Fp f = S.f;
+    const u32 np = (S.npiv + PANEL - 1) / PANEL;
+    const u32 lane = lane_id();
+    const u32 nw = gridDim.x * (blockDim.x / F4_WAVE);
+    for (u32 w = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; w < np * PANEL; w += nw) {
+        const u32 kp = w / PANEL, b = w % PANEL;
+        const u32* Tk = T + (u64)(S.tb + kp) * PANEL * PANEL;
+        u32 tc[PANEL];
+#pragma unroll
+        for (int k = 0; k < PANEL; ++k) tc[k] = Tk[k * PANEL + lane];
+        u32 v = lane == b ? 1u : 0u;
+        if (S.small) {
+#pragma unroll
+            for (int k = 0; k < PANEL; ++k) {
+                const u32 xk = __builtin_amdgcn_readlane(v, k);
+                if (xk != 0 && (u32)k < lane) v = fp_fma_t<true>(f, v, f.p - xk, tc[k]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < PANEL; ++k) {
+                const u32 xk = __builtin_amdgcn_readlane(v, k);
+                if (xk != 0 && (u32)k < lane) v = fp_fma_t<false>(f, v, f.p - xk, tc[k]);
+            }
+        }
+        Tinv[(u64)(S.tb + kp) * PANEL * PANEL + (u64)b * PANEL + lane] = v;
+    }
+}
+
 // ------------------------------------------------------ triangular solve
-// One workgroup per row to reduce (entry g of the row list).  SMALL: p < 2^16
-// (u32 lazy accumulator: a column receives at most npiv additions of values
-// below p); otherwise u64.  Blocks of the other class return at once.
+// One workgroup per tile of up to TR_MAXR consecutive rows of one system
+// (grid: tiles x systems), one dense accumulator per row.  Each pivot panel
+// is solved for every row of the tile at once (wave r solves row r), then the
+// panel's trailing entries are read once and applied to all rows of the tile,
+// so the upper block is streamed once per tile rather than once per row.
+// SMALL: p < 2^16 and npiv < 2^16 (u32 lazy accumulator: a column receives at
+// most npiv additions of values below p); otherwise u64.  Systems of the other
+// class return at once.
+#define TR_MAXR 4
 template <bool SMALL>
 struct AccOf {
     typedef u64 T;
@@ -168,96 +209,118 @@ struct AccOf<true> {
 };
 
 template <bool SMALL, bool LDS>
-__global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, const u32* row_ptr, const u32* col_ind,
-                                                     const u32* val, const u32* row_sys, const u32* list,
-                                                     u32 list_base, u32 nlist, int skip_lead, const u32* perm,
-                                                     const u32* T, const u32* tptr, const u64* tent,
-                                                     typename AccOf<SMALL>::T* gacc, u32 gstride, u32* Dp,
+__global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_base, const u32* row_ptr,
+                                                     const u32* col_ind, const u32* val, const u32* list,
+                                                     int tail, u32 rr, u32 tile_base, int skip_lead,
+                                                     const u32* perm, const u32* Tinv, const u32* tptr,
+                                                     const u64* tent, typename AccOf<SMALL>::T* gacc, u32* Dp,
                                                      u32* lead_out) {
     typedef typename AccOf<SMALL>::T AccT;
     extern __shared__ unsigned char smraw[];
-    __shared__ u32 s_x[PANEL];
-    __shared__ u64 s_hit;
-    __shared__ u32 s_lead;
-    const u32 tid = threadIdx.x;
-    const u32 g = list_base + blockIdx.x;
-    if (g >= nlist) return;
-    const u32 i = list[g];
-    const SegR S = segs[row_sys[i]];
+    __shared__ u32 s_x[TR_MAXR][PANEL];
+    __shared__ u64 s_hit[TR_MAXR];
+    __shared__ u32 s_lead[TR_MAXR];
+    const SegR S = segs[sys_base + blockIdx.y];
     if ((S.small != 0) != SMALL || S.c == 0) return;
+    const u32 cnt = tail ? S.r : S.L;  // rows of this system in the list
+    const u32 t0 = (tile_base + blockIdx.x) * rr;
+    if (t0 >= cnt) return;
+    const u32 nr = min(rr, cnt - t0);
+    const u32 tid = threadIdx.x, lane = lane_id(), wave = tid / F4_WAVE;
     const Fp f = S.f;
     const u32 N = S.N, npiv = S.npiv;
-    AccT* acc = LDS ? (AccT*)smraw : gacc + (u64)blockIdx.x * gstride;
-    for (u32 j = tid; j < N; j += TR_THREADS) acc[j] = 0;
-    if (tid == 0) s_lead = 0xffffffffu;
+    AccT* acc = LDS ? (AccT*)smraw : gacc + ((u64)blockIdx.y * gridDim.x + blockIdx.x) * TR_MAXR * (u64)N;
+    for (u32 j = tid; j < nr * N; j += TR_THREADS) acc[j] = 0;
+    if (tid < TR_MAXR) s_lead[tid] = 0xffffffffu;
     __syncthreads();
     const u32* pm = perm + S.cb;
-    for (u32 e = row_ptr[i] + (skip_lead ? 1 : 0) + tid; e < row_ptr[i + 1]; e += TR_THREADS)
-        acc[pm[col_ind[e]]] = val[e];
+    for (u32 r = 0; r < nr; ++r) {
+        const u32 i = list[S.lb + t0 + r];
+        for (u32 e = row_ptr[i] + (skip_lead ? 1 : 0) + tid; e < row_ptr[i + 1]; e += TR_THREADS)
+            acc[r * N + pm[col_ind[e]]] = val[e];
+    }
     __syncthreads();
     const u32 npanels = (npiv + PANEL - 1) / PANEL;
-    const u32 lane = lane_id();
     for (u32 kp = 0; kp < npanels; ++kp) {
-        if (tid < F4_WAVE) {
-            const u32 c0 = kp * PANEL + lane;
+        // the panel's first TR_THREADS * TR_UNROLL trailing entries are loaded
+        // before the panel solve, so their latency overlaps it
+        const u32 qa = kp * PANEL, qb = min(npiv, qa + PANEL);
+        const u32 ea = tptr[S.pb + qa], eb = tptr[S.pb + qb];
+        u64 t[TR_UNROLL];
+#pragma unroll
+        for (int k = 0; k < TR_UNROLL; ++k) {
+            const u32 e = ea + tid + k * TR_THREADS;
+            t[k] = e < eb ? tent[e] : 0ull;
+        }
+        if (wave < nr) {
+            AccT* a = acc + wave * N;
+            const u32 c0 = qa + lane;
             u32 v = 0;
-            if (c0 < npiv) v = SMALL ? fp_reduce32(f, (u32)acc[c0]) : fp_reduce_any(f, (u64)acc[c0]);
-            const u64 any = wave_ballot(v != 0);
-            if (any) {
-                const u32* Tk = T + (u64)(S.tb + kp) * PANEL * PANEL;
+            if (c0 < npiv) v = SMALL ? fp_reduce32(f, (u32)a[c0]) : fp_reduce_any(f, (u64)a[c0]);
+            if (wave_ballot(v != 0)) {
+                // x = l T^-1 (T^-1 upper triangular: lane j sums rows b <= j)
+                const u32* Tk = Tinv + (u64)(S.tb + kp) * PANEL * PANEL;
                 u32 tc[PANEL];
 #pragma unroll
                 for (int b = 0; b < PANEL; ++b) tc[b] = Tk[b * PANEL + lane];
+                u64 x = 0;
 #pragma unroll
                 for (int b = 0; b < PANEL; ++b) {
-                    const u32 xb = __builtin_amdgcn_readlane(v, b);
-                    if (xb != 0 && (u32)b < lane) v = fp_fma_t<SMALL>(f, v, f.p - xb, tc[b]);
+                    const u32 lb = __builtin_amdgcn_readlane(v, b);
+                    if (lb != 0) x += SMALL ? (u64)lb * tc[b] : (u64)fp_mul(f, lb, tc[b]);
                 }
-                if (c0 < npiv) acc[c0] = 0;
+                v = fp_reduce_any(f, x);
+                if (c0 < npiv) a[c0] = 0;
             }
-            s_x[lane] = v;
+            s_x[wave][lane] = v;
             const u64 hit = wave_ballot(v != 0);
-            if (lane == 0) s_hit = hit;
+            if (lane == 0) s_hit[wave] = hit;
         }
         __syncthreads();
-        const u64 hit = s_hit;
-        if (hit) {
-            // each wave takes every fourth hit pivot row; lanes stride over the
-            // row's trailing entries (contiguous), LDS atomics merge columns
-            const u32 wave = tid / F4_WAVE;
-            const u32* tp = tptr + S.pb + kp * PANEL;
-            u64 hm = hit;
-            u32 rk = 0;
-            while (hm) {
-                const u32 b = __ffsll((long long)hm) - 1;
-                hm &= hm - 1;
-                if ((rk++ & (TR_THREADS / F4_WAVE - 1)) != wave) continue;
-                const u32 negx = f.p - s_x[b];
-                const u32 ea = tp[b], eb = tp[b + 1];
-                for (u32 e = ea + lane; e < eb; e += F4_WAVE) {
-                    const u64 t = tent[e];
-                    const u32 add = SMALL ? fp_reduce32(f, negx * (u32)(t >> 32))
-                                          : fp_reduce(f, (u64)negx * (u32)(t >> 32));
-                    atomicAdd(&acc[(u32)t & 0x3ffffffu], (AccT)add);
+        u64 anyhit = 0;
+        for (u32 r = 0; r < nr; ++r) anyhit |= s_hit[r];
+        if (anyhit) {
+            // apply every trailing entry to every row of the tile
+            for (u32 e0 = ea + tid;; e0 += TR_THREADS * TR_UNROLL) {
+#pragma unroll
+                for (int k = 0; k < TR_UNROLL; ++k) {
+                    if (!t[k]) continue;  // stored values are nonzero
+                    const u32 b = (u32)(t[k] >> 26) & (PANEL - 1), col = (u32)t[k] & 0x3ffffffu;
+                    const u32 tv = (u32)(t[k] >> 32);
+                    for (u32 r = 0; r < nr; ++r) {
+                        const u32 xb = s_x[r][b];
+                        if (!xb) continue;
+                        const u32 negx = f.p - xb;
+                        const u32 add = SMALL ? fp_reduce32(f, negx * tv) : fp_reduce(f, (u64)negx * tv);
+                        atomicAdd(&acc[r * N + col], (AccT)add);
+                    }
+                }
+                const u32 e1 = e0 + TR_THREADS * TR_UNROLL;
+                if (e1 - tid >= eb) break;  // no thread has entries left
+#pragma unroll
+                for (int k = 0; k < TR_UNROLL; ++k) {
+                    const u32 e = e1 + k * TR_THREADS;
+                    t[k] = e < eb ? tent[e] : 0ull;
                 }
             }
         }
         __syncthreads();
     }
-    // trailing block row: non-pivot part of the accumulator
+    // trailing block rows: non-pivot part of the accumulators
     const u32 c = S.c;
-    const u32 local = g - S.lb;
-    u32* out = Dp + S.dpb + (u64)local * c;
-    u32 first = 0xffffffffu;
-    for (u32 j = tid; j < c; j += TR_THREADS) {
-        const AccT a = acc[npiv + j];
-        const u32 v = SMALL ? fp_reduce32(f, (u32)a) : fp_reduce_any(f, (u64)a);
-        out[j] = v;
-        if (v && j < first) first = j;
+    for (u32 r = 0; r < nr; ++r) {
+        u32* out = Dp + S.dpb + (u64)(t0 + r) * c;
+        u32 first = 0xffffffffu;
+        for (u32 j = tid; j < c; j += TR_THREADS) {
+            const AccT a = acc[r * N + npiv + j];
+            const u32 v = SMALL ? fp_reduce32(f, (u32)a) : fp_reduce_any(f, (u64)a);
+            out[j] = v;
+            if (v && j < first) first = j;
+        }
+        if (first != 0xffffffffu) atomicMin(&s_lead[r], first);
     }
-    if (first != 0xffffffffu) atomicMin(&s_lead, first);
     __syncthreads();
-    if (tid == 0 && lead_out) lead_out[g] = s_lead;
+    if (tid < nr && lead_out) lead_out[S.lb + t0 + tid] = s_lead[tid];
 }
 
 // ---------------------------------------------------------------- echelon
@@ -275,98 +338,31 @@ struct EchRound {
 // the ECH_B remaining rows with the smallest (leading column, index).  The
 // workgroup finds the block's pivot columns by Gauss-Jordan elimination
 // recorded in a b x b transform Z: the block's columns are visited in chunks
-// of ECH_CH, each chunk is loaded and multiplied by Z (all threads), then one
-// wave eliminates on the chunk with the rows in registers (lane j < ECH_CH
-// holds column j of the chunk, lane ECH_CH + u holds column u of Z), so a
-// pivot costs one modular product per row and no block barrier.  The first
-// column where a non-pivot row is nonzero becomes the next pivot; every such
-// column is the leading column of a vector of the row space, hence a pivot
-// column of the RREF of the whole trailing block.  Scanning stops once every
-// block row is a pivot or the columns are exhausted (the other rows are then
-// zero), so all block rows are consumed; the new pivot rows Z * (block rows),
-// formed by k_ech_update, are reduced on all pivot columns of the round.
+// of ECH_CH, each chunk is loaded and multiplied by Z, and the rows of
+// [chunk | Z] (LDS, ECH_CH + ECH_B = 64 columns, one per lane) are eliminated
+// with every wave owning two rows.  The first column where a non-pivot row is
+// nonzero becomes the next pivot; every such column is the leading column of a
+// vector of the row space, hence a pivot column of the RREF of the whole
+// trailing block.  Row operations are fraction-free (row_k <- piv * row_k -
+// row_k[jp] * row_kp), so no inverse is taken per pivot; each pivot row's value
+// at its pivot column is tracked and divided out at the end.  Scanning stops
+// once every block row is a pivot or the columns are exhausted (the other rows
+// are then zero), so all block rows are consumed; the new pivot rows
+// Z * (block rows), formed by k_ech_update, are reduced on all pivot columns
+// of the round.
 #define ECH_CH 32
+#define ECH_W (ECH_CH + ECH_B)  // row width of [chunk | Z]: one lane per column
 
 template <bool SMALL>
 __device__ __forceinline__ u32 fp_mul_t(const Fp& f, u32 a, u32 b) {
     return SMALL ? fp_reduce32(f, a * b) : fp_reduce(f, (u64)a * b);  // SMALL: a*b < p^2 < 2^32
 }
 
+// (piv * a - fk * b) mod p
 template <bool SMALL>
-__device__ __forceinline__ u32 fp_inv_t(const Fp& f, u32 a) {
-    u32 e = f.p - 2, r = 1;
-    while (e) {
-        if (e & 1) r = fp_mul_t<SMALL>(f, r, a);
-        a = fp_mul_t<SMALL>(f, a, a);
-        e >>= 1;
-    }
-    return r;
-}
-
-// Gauss-Jordan on one chunk by the calling wave.  s_R: b x ECH_CH chunk of
-// Z * B; s_Z: the transform (row stride ECH_B); *s_q / *s_pmask: pivots so far
-// and the bit mask of block rows that are pivots.  Appends the new pivots'
-// columns and rows to s_pcol / s_prow and writes Z back.
-template <bool SMALL>
-__device__ void ech_chunk_gj(const Fp& f, u32 b, u32 w, u32 j0, const u32* s_R, u32* s_Z, u32* s_q, u32* s_pmask,
-                             u32* s_pcol, u32* s_prow) {
-    const u32 lane = lane_id();
-    u32 r[ECH_B];
-#pragma unroll
-    for (int k = 0; k < ECH_B; ++k)
-        r[k] = (u32)k < b ? (lane < ECH_CH ? s_R[k * ECH_CH + lane] : s_Z[k * ECH_B + lane - ECH_CH]) : 0u;
-    const u32 live = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
-    u32 q = *s_q, pmask = *s_pmask, jstart = 0;
-    while (q < b) {
-        const u32 np = live & ~pmask;
-        u32 nz = 0;
-#pragma unroll
-        for (int k = 0; k < ECH_B; ++k)
-            if ((np >> k) & 1u) nz |= r[k];
-        const u64 m = wave_ballot(nz != 0 && lane >= jstart && lane < w);
-        if (!m) break;
-        const u32 jp = __ffsll((long long)m) - 1;
-        u32 kp = ECH_B, piv = 0;
-#pragma unroll
-        for (int k = 0; k < ECH_B; ++k) {
-            const u32 v = __builtin_amdgcn_readlane(r[k], jp);
-            if (kp == ECH_B && ((np >> k) & 1u) && v) {
-                kp = k;
-                piv = v;
-            }
-        }
-        const u32 inv = fp_inv_t<SMALL>(f, piv);
-        u32 prow = 0;
-#pragma unroll
-        for (int k = 0; k < ECH_B; ++k)
-            if ((u32)k == kp) {
-                r[k] = fp_mul_t<SMALL>(f, r[k], inv);
-                prow = r[k];
-            }
-#pragma unroll
-        for (int k = 0; k < ECH_B; ++k) {
-            if ((u32)k == kp) continue;
-            const u32 fk = __builtin_amdgcn_readlane(r[k], jp);
-            if (fk) {
-                const u32 x = r[k] + fp_mul_t<SMALL>(f, f.p - fk, prow);
-                r[k] = x >= f.p ? x - f.p : x;
-            }
-        }
-        if (lane == 0) {
-            s_pcol[q] = j0 + jp;
-            s_prow[q] = kp;
-        }
-        pmask |= 1u << kp;
-        ++q;
-        jstart = jp + 1;
-    }
-#pragma unroll
-    for (int k = 0; k < ECH_B; ++k)
-        if ((u32)k < b && lane >= ECH_CH) s_Z[k * ECH_B + lane - ECH_CH] = r[k];
-    if (lane == 0) {
-        *s_q = q;
-        *s_pmask = pmask;
-    }
+__device__ __forceinline__ u32 fp_ff(const Fp& f, u32 piv, u32 a, u32 fk, u32 b) {
+    const u32 x = fp_mul_t<SMALL>(f, piv, a), y = fp_mul_t<SMALL>(f, fk, b);
+    return x >= y ? x - y : x + f.p - y;
 }
 
 __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead, u32* status, const u32* Dp,
@@ -375,11 +371,11 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     extern __shared__ u32 scnt[];
     __shared__ u32 s_wave[33];
     __shared__ u32 s_rows[ECH_B];
-    __shared__ u32 s_Z[ECH_B * ECH_B];
-    __shared__ u32 s_R[ECH_B * ECH_CH];
+    __shared__ u32 s_RZ[ECH_B * ECH_W];
     __shared__ u32 s_B[ECH_B * ECH_CH];
-    __shared__ u32 s_pcol[ECH_B], s_prow[ECH_B];
-    __shared__ u32 s_thr, s_need, s_q, s_pmask, s_cmin;
+    __shared__ u32 s_pcol[ECH_B], s_prow[ECH_B], s_pv[ECH_B], s_inv[ECH_B];
+    __shared__ u64 s_nz[2];
+    __shared__ u32 s_thr, s_need, s_cmin;
     EchRound* R = rounds + blockIdx.y;
     if (R->done) return;
     const SegR S = segs[blockIdx.y];
@@ -443,54 +439,94 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         }
         return;
     }
-    for (u32 x = tid; x < ECH_B * ECH_B; x += 1024) s_Z[x] = (x / ECH_B == x % ECH_B) ? 1u : 0u;
-    if (tid == 0) {
-        s_q = 0;
-        s_pmask = 0;
+    static_assert(ECH_W == F4_WAVE && ECH_B * ECH_CH == 1024 && 2 * 16 == ECH_B, "echelon block layout");
+    for (u32 x = tid; x < ECH_B * ECH_W; x += 1024) {
+        const u32 k = x / ECH_W, j = x % ECH_W;
+        s_RZ[x] = (j >= ECH_CH && j - ECH_CH == k) ? 1u : 0u;
     }
+    if (tid < 2) s_nz[tid] = 0;
     __syncthreads();
     const bool small = S.small != 0;
+    const u32 lane = tid % F4_WAVE, wave = tid / F4_WAVE;
+    const u32 r0 = 2 * wave, r1 = 2 * wave + 1;  // block rows of this wave
+    u32 q = 0, pmask = 0, par = 0;
     // chunks of ECH_CH columns from the smallest leading column of the block
-    for (u32 j0 = s_cmin; j0 < c && s_q < b; j0 += ECH_CH) {
+    for (u32 j0 = s_cmin; j0 < c && q < b; j0 += ECH_CH) {
         const u32 w = min((u32)ECH_CH, c - j0);
-        for (u32 x = tid; x < b * ECH_CH; x += 1024) {
-            const u32 k = x / ECH_CH, j = x % ECH_CH;
-            s_B[x] = j < w ? D[(u64)s_rows[k] * c + j0 + j] : 0u;
+        {
+            const u32 k = tid / ECH_CH, j = tid % ECH_CH;
+            s_B[tid] = (k < b && j < w) ? D[(u64)s_rows[k] * c + j0 + j] : 0u;
         }
         __syncthreads();
-        // R = Z * B_chunk: the block rows as transformed so far, on this chunk
-        const bool ident = s_q == 0;
-        for (u32 x = tid; x < b * ECH_CH; x += 1024) {
-            const u32 k = x / ECH_CH, j = x % ECH_CH;
-            if (ident) {
-                s_R[x] = s_B[x];
-                continue;
+        // chunk part of the rows: Z * B_chunk (B itself while Z is the identity)
+        {
+            const u32 k = tid / ECH_CH, j = tid % ECH_CH;
+            u32 v = s_B[tid];
+            if (q && k < b) {
+                u64 acc = 0;
+                for (u32 u = 0; u < b; ++u) {
+                    const u32 z = s_RZ[k * ECH_W + ECH_CH + u];
+                    if (z) acc += small ? (u64)z * s_B[u * ECH_CH + j] : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
+                }
+                v = fp_reduce_any(f, acc);
             }
-            u64 acc = 0;
-            for (u32 u = 0; u < b; ++u) {
-                const u32 z = s_Z[k * ECH_B + u];
-                if (z) acc += small ? (u64)z * s_B[u * ECH_CH + j] : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
+            s_RZ[k * ECH_W + j] = v;
+        }
+        __syncthreads();
+        u32 jstart = 0;
+        while (q < b) {
+            // columns where a non-pivot row is nonzero, merged over the waves
+            bool nz = false;
+            if (r0 < b && !((pmask >> r0) & 1u)) nz |= s_RZ[r0 * ECH_W + lane] != 0;
+            if (r1 < b && !((pmask >> r1) & 1u)) nz |= s_RZ[r1 * ECH_W + lane] != 0;
+            const u64 m = wave_ballot(nz && lane >= jstart && lane < w);
+            if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[par], (unsigned long long)m);
+            __syncthreads();
+            const u64 all = s_nz[par];
+            if (tid == 0) s_nz[par ^ 1] = 0;
+            if (!all) break;
+            const u32 jp = __ffsll((long long)all) - 1;
+            // pivot row: the first non-pivot row nonzero at jp (row kp and the
+            // rows before it do not change in this step, so every wave agrees)
+            const u32 cand = (lane < b && !((pmask >> lane) & 1u)) ? s_RZ[lane * ECH_W + jp] : 0u;
+            const u32 kp = __ffsll((long long)wave_ballot(cand != 0)) - 1;
+            const u32 piv = s_RZ[kp * ECH_W + jp];
+            const u32 prow = s_RZ[kp * ECH_W + lane];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const u32 r = h ? r1 : r0;
+                if (r >= b || r == kp) continue;
+                const u32 fk = s_RZ[r * ECH_W + jp];
+                if (!fk) continue;
+                const u32 old = s_RZ[r * ECH_W + lane];
+                s_RZ[r * ECH_W + lane] =
+                    small ? fp_ff<true>(f, piv, old, fk, prow) : fp_ff<false>(f, piv, old, fk, prow);
+                if (lane == 0 && ((pmask >> r) & 1u)) s_pv[r] = fp_mul(f, s_pv[r], piv);
             }
-            s_R[x] = fp_reduce_any(f, acc);
+            if (tid == 0) {
+                s_pcol[q] = j0 + jp;
+                s_prow[q] = kp;
+                s_pv[kp] = piv;
+            }
+            pmask |= 1u << kp;
+            ++q;
+            jstart = jp + 1;
+            par ^= 1;
+            __syncthreads();
         }
-        __syncthreads();
-        if (tid < F4_WAVE) {
-            if (small)
-                ech_chunk_gj<true>(f, b, w, j0, s_R, s_Z, &s_q, &s_pmask, s_pcol, s_prow);
-            else
-                ech_chunk_gj<false>(f, b, w, j0, s_R, s_Z, &s_q, &s_pmask, s_pcol, s_prow);
-        }
-        __syncthreads();
     }
-    const u32 q = s_q, npr = R->npr;
-    // round record: pivot columns, block rows and Z rows of the pivots
+    // each pivot row is s_pv times its normalised form
+    if (tid < q) s_inv[tid] = fp_inv(f, s_pv[s_prow[tid]]);
+    __syncthreads();
+    const u32 npr = R->npr;
+    // round record: pivot columns, block rows and normalised Z rows of the pivots
     if (tid < q) {
         R->cols[tid] = s_pcol[tid];
         prlead[S.capb + npr + tid] = s_pcol[tid];
     }
     for (u32 x = tid; x < q * ECH_B; x += 1024) {
         const u32 t = x / ECH_B, u = x % ECH_B;
-        R->Z[t * ECH_B + u] = u < b ? s_Z[s_prow[t] * ECH_B + u] : 0u;
+        R->Z[t * ECH_B + u] = u < b ? fp_mul(f, s_RZ[s_prow[t] * ECH_W + ECH_CH + u], s_inv[t]) : 0u;
     }
     if (tid < b) {
         R->rows[tid] = s_rows[tid];
@@ -719,7 +755,7 @@ struct SplitState {
     DBuf<SegR> dsegs;
     DBuf<u32> perm, prow, pivot_cols, nonpiv, lower, tptr;
     DBuf<u64> tent;
-    DBuf<u32> T;
+    DBuf<u32> T, Tinv;
     u32 P = 0, Ltot = 0, C = 0;
 };
 
@@ -832,60 +868,72 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
                            X.tent.ptr, X.T.ptr);
         F4_LAUNCH_CHECK();
     }
+    X.Tinv.reset(&c.pool, (u64)std::max<u32>(tb, 1) * PANEL * PANEL);
+    if (tb) {
+        u32 maxpan = 1;
+        for (auto& g : X.segs) maxpan = std::max(maxpan, (g.npiv + PANEL - 1) / PANEL);
+        hipLaunchKernelGGL(k_tinv, dim3(std::min<u32>(1024, ceil_div((u64)maxpan * PANEL, 4)), S), dim3(256), 0, s,
+                           X.dsegs.ptr, X.T.ptr, X.Tinv.ptr);
+        F4_LAUNCH_CHECK();
+    }
 }
 
-// Reduce rows list[0..n) (batch row indices) by the pivot rows of their
-// systems; dense trailing rows go to Dp at segs[s].dpb + (g - segs[s].lb) * c.
-static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* list, u32 n, int skip_lead, u32* Dp,
+// Reduce the listed rows of every system by its pivot rows: list[lb ..
+// lb + cnt) are the system's rows (cnt = L, or r for the tail reduction);
+// dense trailing rows go to Dp at segs[s].dpb + local * c.
+static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* list, int tail, int skip_lead, u32* Dp,
                      u32* lead_out) {
-    if (!n) return;
     hipStream_t s = c.stream;
-    bool any_small = false, any_large = false;
-    size_t max_small = 0, max_large = 0;
-    for (const SegR& g : X.segs) {
-        if (!g.c) continue;
-        if (g.small) {
-            any_small = true;
-            max_small = std::max<size_t>(max_small, (size_t)g.N * 4);
-        } else {
-            any_large = true;
-            max_large = std::max<size_t>(max_large, (size_t)g.N * 8);
-        }
-    }
+    const u32 S = X.S;
     for (int cls = 0; cls < 2; ++cls) {
         const bool small = cls == 0;
-        if (small ? !any_small : !any_large) continue;
-        const size_t acc_bytes = small ? max_small : max_large;
-        const bool lds = acc_bytes + 1024 <= c.dev.max_lds;
-        if (lds) {
+        const size_t accb = small ? 4 : 8;
+        u32 nmax = 0, cmax = 0;
+        for (const SegR& g : X.segs)
+            if (g.c && (g.small != 0) == small) {
+                nmax = std::max(nmax, g.N);
+                cmax = std::max(cmax, tail ? g.r : g.L);
+            }
+        if (!cmax) continue;
+        const size_t row_bytes = (size_t)nmax * accb;
+        const size_t budget = c.dev.max_lds > 4096 ? c.dev.max_lds - 4096 : 0;
+        if (row_bytes <= budget) {
+            const u32 rr = (u32)std::min<size_t>(TR_MAXR, budget / row_bytes);
+            const u32 tiles = ceil_div(cmax, rr);
             if (small)
-                hipLaunchKernelGGL((k_trsm<true, true>), dim3(n), dim3(TR_THREADS), acc_bytes, s, X.dsegs.ptr,
-                                   A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, A.row_sys.ptr, list, 0u, n, skip_lead,
-                                   X.perm.ptr, X.T.ptr, X.tptr.ptr, X.tent.ptr, (u32*)nullptr, 0u, Dp, lead_out);
+                hipLaunchKernelGGL((k_trsm<true, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
+                                   X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
+                                   skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)nullptr, Dp,
+                                   lead_out);
             else
-                hipLaunchKernelGGL((k_trsm<false, true>), dim3(n), dim3(TR_THREADS), acc_bytes, s, X.dsegs.ptr,
-                                   A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, A.row_sys.ptr, list, 0u, n, skip_lead,
-                                   X.perm.ptr, X.T.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, 0u, Dp, lead_out);
+                hipLaunchKernelGGL((k_trsm<false, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
+                                   X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
+                                   skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, Dp,
+                                   lead_out);
             F4_LAUNCH_CHECK();
             continue;
         }
-        // accumulators in global memory, rows in batches
-        const u32 stride = (u32)(acc_bytes / (small ? 4 : 8));
-        const u32 batch = (u32)std::max<u64>(1, std::min<u64>(n, (u64)(1u << 30) / acc_bytes));
-        DBuf<u8> gacc(&c.pool, (u64)batch * acc_bytes);
-        for (u32 b0 = 0; b0 < n; b0 += batch) {
-            const u32 nb = std::min(batch, n - b0);
-            if (small)
-                hipLaunchKernelGGL((k_trsm<true, false>), dim3(nb), dim3(TR_THREADS), 0, s, X.dsegs.ptr,
-                                   A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, A.row_sys.ptr, list, b0, n, skip_lead,
-                                   X.perm.ptr, X.T.ptr, X.tptr.ptr, X.tent.ptr, (u32*)gacc.ptr, stride, Dp,
-                                   lead_out);
-            else
-                hipLaunchKernelGGL((k_trsm<false, false>), dim3(nb), dim3(TR_THREADS), 0, s, X.dsegs.ptr,
-                                   A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, A.row_sys.ptr, list, b0, n, skip_lead,
-                                   X.perm.ptr, X.T.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, stride, Dp,
-                                   lead_out);
-            F4_LAUNCH_CHECK();
+        // accumulators in global memory (one row per tile), one system and a
+        // bounded number of tiles per launch
+        const size_t slot = (size_t)TR_MAXR * row_bytes;
+        const u32 batch = (u32)std::max<size_t>(1, std::min<size_t>(cmax, ((size_t)1 << 30) / slot));
+        DBuf<u8> gacc(&c.pool, (u64)batch * slot);
+        for (u32 sy = 0; sy < S; ++sy) {
+            const SegR& g = X.segs[sy];
+            const u32 cnt = tail ? g.r : g.L;
+            if (!g.c || (g.small != 0) != small || !cnt) continue;
+            for (u32 b0 = 0; b0 < cnt; b0 += batch) {
+                const u32 nb = std::min(batch, cnt - b0);
+                if (small)
+                    hipLaunchKernelGGL((k_trsm<true, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
+                                       A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
+                                       X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)gacc.ptr, Dp, lead_out);
+                else
+                    hipLaunchKernelGGL((k_trsm<false, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
+                                       A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
+                                       X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, Dp, lead_out);
+                F4_LAUNCH_CHECK();
+            }
         }
     }
 }
@@ -909,7 +957,7 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
         maxc = std::max(maxc, g.c);
     }
     DBuf<u32> Dp(&c.pool, std::max<u64>(Dtot, 1)), lead(&c.pool, std::max<u32>(X.Ltot, 1));
-    run_trsm(c, A, X, X.lower.ptr, X.Ltot, 0, Dp.ptr, lead.ptr);
+    run_trsm(c, A, X, X.lower.ptr, 0, 0, Dp.ptr, lead.ptr);
     hipEvent_t e2 = stage_event(c);
 
     // echelon of every system's D' (L x c)
@@ -1047,7 +1095,7 @@ void tail_reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, DBuf<
     // system of each row as a key (for the wave kernels below)
     hipLaunchKernelGGL(k_row_sys_keys, dim3(grid_of(R, 256, 1024)), dim3(256), 0, s, A.row_sys.ptr, R, keys.ptr);
     F4_LAUNCH_CHECK();
-    run_trsm(c, A, X, rows.ptr, R, 1, Dp.ptr, nullptr);
+    run_trsm(c, A, X, rows.ptr, 1, 1, Dp.ptr, nullptr);
     hipLaunchKernelGGL(k_count_nz, dim3(grid_of(R, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, 32u, rows.ptr, R,
                        0, Dp.ptr, Dp.ptr, cnt.ptr);
     F4_LAUNCH_CHECK();
