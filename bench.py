@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--dict", choices=["rank", "radix"], default=None)
     ap.add_argument("--batch-systems", type=int, default=256, help="systems in the batched leg (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg (0: skip)")
+    ap.add_argument("--sparse-repeats", type=int, default=3, help="timed runs of the n=14 sparse step (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (reference kernel for HBM byte counters)")
     return ap.parse_args()
@@ -52,6 +53,51 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_bytes": n, "launches": 5}))
 
 
+# int32 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+# a modular product needs at least a 24-bit multiply and an add (reductions
+# amortised over lazy accumulation)
+MODMUL_PEAK = VALU_OPS_PER_S / 2
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/hbm_counters_n10.md), or None when it has none for the kernel."""
+    path = os.path.join(ROOT, "profiles", "hbm_counters_n10.md")
+    try:
+        for line in open(path):
+            if line.startswith("traffic_bytes_per_launch") and kernel in line:
+                return float(line.split()[-1])
+    except OSError:
+        pass
+    return None
+
+
+def roofline_of(allsteps):
+    """Roofline of the kernel with the largest total time over the timed runs
+    (HIP events around each launch): the triangular solve or the echelon block
+    step, both bound by integer vector arithmetic.  achieved = modular products
+    the kernel performed / its summed launch time."""
+    cand = {
+        "k_trsm": (sum(s["t_k_trsm_ms"] for run in allsteps for s in run),
+                   sum(s["trsm_ops"] for run in allsteps for s in run),
+                   sum(s["n_k_trsm"] for run in allsteps for s in run)),
+        "k_ech_block": (sum(s["t_k_block_ms"] for run in allsteps for s in run),
+                        sum(s["block_ops"] for run in allsteps for s in run),
+                        sum(s["n_k_block"] for run in allsteps for s in run)),
+    }
+    name = max(cand, key=lambda k: cand[k][0])
+    ms, ops, launches = cand[name]
+    achieved = ops / (ms / 1000.0) / 1e12 if ms > 0 else 0.0
+    peak = MODMUL_PEAK / 1e12
+    traffic = recorded_traffic(name)
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 3), "unit": "Tmodmul/s",
+            "frac": round(achieved / peak, 5), "traffic": traffic, "kernel": name,
+            "launches_per_run": launches / len(allsteps), "ms_per_launch": ms / max(1, launches),
+            "ops_per_launch": ops / max(1, launches),
+            "other_kernel_ms_per_run": {k: round(v[0] / len(allsteps), 4) for k, v in cand.items()}}
+
+
 def cpu_baseline(n, p, polys, seconds):
     """The oracle as it is (textbook F4, one thread) on whole runs of the same system."""
     import oracle
@@ -66,6 +112,35 @@ def cpu_baseline(n, p, polys, seconds):
     dt = time.perf_counter() - t0
     return {"value": nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
             "sample": "%d full F4 run(s) of the same n=10 m=12 system, single thread, %.1f s" % (runs, dt)}
+
+
+def sparse_step_leg(f4, repeats):
+    """Workload 3: 15 sparse quadratics in n=14 over F_(2^31-1) (20 monomials
+    each, seed 3); F4 on the GPU up to and including the first step of degree
+    5, whose preprocessing (DictBuild + RowAssemble) and elimination
+    (NumericCore) are reported separately."""
+    import synth
+    n, p, polys = synth.config_system(3)
+    ctx = f4.Context(0, timing=True, stop_deg=5)
+    ctx.groebner(p, n, polys)  # warm-up
+    runs = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        _, steps = ctx.groebner(p, n, polys)
+        runs.append((time.perf_counter() - t0, steps[-1]))
+    ctx.close()
+    s = runs[0][1]
+    avg = lambda key: sum(r[1][key] for r in runs) / len(runs)
+    sp = avg("t_dict_ms") + avg("t_assemble_ms")
+    el = avg("t_numeric_ms")
+    return {"workload": "n=14, m=15 sparse quadratics (20 monomials), F_(2^31-1), seed 3: first degree-5 step",
+            "deg": s["deg"], "r": s["r"], "N": s["N"], "nnz": s["nnz"], "npivot": s["npivot"],
+            "lower": s["lower"], "rho": s["rho"],
+            "t_preprocess_ms": round(sp, 4), "t_elimination_ms": round(el, 4),
+            "t_trsm_ms": round(avg("t_trsm_ms"), 4), "t_echelon_ms": round(avg("t_echelon_ms"), 4),
+            "nnz_per_s_preprocess": s["nnz"] / (sp / 1000.0), "nnz_per_s_step": s["nnz"] / ((sp + el) / 1000.0),
+            "rows_per_s_step": s["r"] / ((sp + el) / 1000.0),
+            "run_to_step_ms": round(1000.0 * sum(r[0] for r in runs) / len(runs), 3)}
 
 
 def batch_leg(ctx, count):
@@ -185,36 +260,31 @@ def main():
     # per F4 step (averaged over runs): GPU stage times from HIP events
     per_step = []
     nsteps = len(allsteps[0])
+    avg = lambda k, key: sum(run[k][key] for run in allsteps) / len(allsteps)
     for k in range(nsteps):
-        ss = [run[k] for run in allsteps]
-        s0 = ss[0]
-        gpu_ms = sum(s["t_dict_ms"] + s["t_assemble_ms"] + s["t_numeric_ms"] for s in ss) / len(ss)
-        wall_ms = sum(s["t_step_ms"] for s in ss) / len(ss)
+        s0 = allsteps[0][k]
+        gpu_ms = avg(k, "t_dict_ms") + avg(k, "t_assemble_ms") + avg(k, "t_numeric_ms")
+        c = s0["N"] - s0["npivot"]
+        # algorithmic bytes of the step (unit: one nonzero of A): build writes
+        # the CSR (8 B per nonzero, 16 per row, 8 per column), the elimination
+        # reads it once and writes the trailing block and its echelon rows
+        alg = (8 * s0["nnz"] + 16 * s0["r"] + 8 * s0["N"]) + (8 * s0["nnz"] + 4 * s0["r"]
+                                                               + 4 * s0["lower"] * c + 4 * s0["rho"] * c)
         per_step.append({
             "deg": s0["deg"], "r": s0["r"], "N": s0["N"], "nnz": s0["nnz"], "npivot": s0["npivot"],
             "lower": s0["lower"], "rho": s0["rho"],
-            "t_dict_ms": round(sum(s["t_dict_ms"] for s in ss) / len(ss), 4),
-            "t_assemble_ms": round(sum(s["t_assemble_ms"] for s in ss) / len(ss), 4),
-            "t_numeric_ms": round(sum(s["t_numeric_ms"] for s in ss) / len(ss), 4),
-            "t_trsm_ms": round(sum(s["t_trsm_ms"] for s in ss) / len(ss), 4),
-            "t_echelon_ms": round(sum(s["t_echelon_ms"] for s in ss) / len(ss), 4),
-            "wall_ms": round(wall_ms, 4),
+            "t_dict_ms": round(avg(k, "t_dict_ms"), 4),
+            "t_assemble_ms": round(avg(k, "t_assemble_ms"), 4),
+            "t_numeric_ms": round(avg(k, "t_numeric_ms"), 4),
+            "t_trsm_ms": round(avg(k, "t_trsm_ms"), 4),
+            "t_echelon_ms": round(avg(k, "t_echelon_ms"), 4),
+            "wall_ms": round(avg(k, "t_step_ms"), 4),
             "nnz_per_s_gpu": s0["nnz"] / (gpu_ms / 1000.0) if gpu_ms > 0 else None,
             "rows_per_s_gpu": s0["r"] / (gpu_ms / 1000.0) if gpu_ms > 0 else None,
+            "hbm_frac_alg": alg / (gpu_ms / 1000.0) / (HBM_PEAK_GBS * 1e9) if gpu_ms > 0 else None,
         })
 
-    # dominant kernel: the sparse triangular solve (largest stage time).  Its
-    # algorithmic bytes per launch: the lower rows and the pivot rows read
-    # once (8 B per entry), the dense trailing block written (4 B per entry).
-    big = max(range(nsteps), key=lambda k: per_step[k]["t_trsm_ms"])
-    sb = per_step[big]
-    trsm_ms = sb["t_trsm_ms"]
-    alg_bytes = 8 * sb["nnz"] + 4 * sb["lower"] * (sb["N"] - sb["npivot"])
-    achieved = alg_bytes / (trsm_ms / 1000.0) / 1e9 if trsm_ms > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "k_trsm", "step_deg": sb["deg"], "launch_ms": trsm_ms}
-
+    out_roof = roofline_of(allsteps)
     out = {
         "metric": "Macaulay nnz/s built+reduced per F4 step; systems/sec batched vs plain",
         "value": value,
@@ -234,8 +304,10 @@ def main():
         "rows_per_s": rows_run * args.steps / dt,
         "systems_per_s_plain": args.steps / dt,
         "per_f4_step": per_step,
-        "roofline": roofline,
+        "roofline": out_roof,
     }
+    if args.sparse_repeats:
+        out["sparse_step"] = sparse_step_leg(f4, args.sparse_repeats)
     if args.batch_systems:
         out["batch"] = batch_leg(ctx, args.batch_systems)
         out["systems_per_s_batched"] = out["batch"]["systems_per_s_batched"]

@@ -71,7 +71,11 @@ enum {
 };
 typedef struct f4_opts {
     uint32_t flags;
-    uint32_t reserved;
+    /* 0: run F4 to the end.  d > 0: f4_groebner / f4_groebner_batch stop each
+     * system after its first step of degree d (the step statistics are kept;
+     * the returned basis of such a system is empty) - for timing one step of
+     * a system at its real shape. */
+    uint32_t stop_deg;
 } f4_opts;
 
 /* Create a context on HIP device `device` (opts may be NULL).  The context owns
@@ -211,6 +215,18 @@ typedef struct f4_step_stats {
     float t_echelon_ms;   /* of which the trailing-block echelon */
     float t_step_ms;      /* host wall time of the whole step */
     float t_pairs_ms;     /* host time of pair selection and Gebauer-Moeller updates */
+    /* per kernel (timing option only; for a batch, the batch's launches):
+     * the triangular-solve kernel and the echelon block-step kernel, summed
+     * over their launches (HIP events around each launch on the call's
+     * stream), their launch counts, and the modular products they performed
+     * (triangular solve: panel products and trailing-entry updates; block
+     * step: the transform products and the row-operation products). */
+    float t_k_trsm_ms;
+    uint32_t n_k_trsm;
+    uint64_t trsm_ops;
+    float t_k_block_ms;
+    uint32_t n_k_block;
+    uint64_t block_ops;
 } f4_step_stats;
 
 /* Reduced Groebner basis of <F> under grevlex (unique: monic, minimal,
@@ -244,7 +260,9 @@ int f4_server_footprint(uint32_t n, uint32_t m, uint64_t* bytes);
 
 /* A serving engine on a context.  Systems are admitted while their estimated
  * footprint fits in hbm_budget bytes and fewer than max_slots are resident;
- * their bases and pair sets stay on the device.  Each f4_server_step advances
+ * their bases stay on the device between steps (the pair sets and leading
+ * monomials are host state: the Gebauer-Moeller update runs on the host).
+ * Each f4_server_step advances
  * every resident unfinished system by one F4 iteration with one batched
  * launch sequence (continuous batching: systems admitted between steps join
  * the next one), and systems whose pairs are exhausted get their reduced

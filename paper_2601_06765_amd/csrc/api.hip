@@ -95,6 +95,8 @@ void readback(Ctx& c, void* dst, const void* src, size_t bytes) {
     c.pinned_used = 0;
 }
 
+bool timing_on(const Ctx& c) { return (c.flags & F4_OPT_TIMING) != 0; }
+
 hipEvent_t stage_event(Ctx& c) {
     if (!(c.flags & F4_OPT_TIMING)) return nullptr;
     if (c.ev_used == c.events.size()) {
@@ -528,6 +530,12 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             st.t_numeric_ms = R.t_split + R.t_trsm + R.t_echelon + R.t_emit;
             st.t_trsm_ms = R.t_trsm;
             st.t_echelon_ms = R.t_echelon;
+            st.t_k_trsm_ms = R.t_k_trsm;
+            st.n_k_trsm = (u32)R.ev_trsm.size();
+            st.trsm_ops = R.trsm_ops;
+            st.t_k_block_ms = R.t_k_block;
+            st.n_k_block = (u32)R.ev_block.size();
+            st.block_ops = R.block_ops;
             const auto tg0 = std::chrono::steady_clock::now();
             for (u32 t = 0; t < P.rho && !S.unit; ++t) {
                 const u32 h = (u32)S.lm.size();
@@ -543,6 +551,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             st.t_pairs_ms = S.tpairs + std::chrono::duration<float, std::milli>(tg1 - tg0).count();
             st.t_step_ms = std::chrono::duration<float, std::milli>(tg1 - S.t0).count();
             S.steps.push_back(st);
+            if (c.stop_deg && S.d == c.stop_deg && !S.unit) S.done = true;  // stopped: no basis
         }
         c.ev_used = 0;
         return work.size();
@@ -681,6 +690,7 @@ int f4_create(f4_ctx** out, int device, const f4_opts* opts) {
         X->c.dev.cus = prop.multiProcessorCount;
         X->c.dev.max_lds = prop.sharedMemPerBlock;
         X->c.flags = opts ? opts->flags : 0;
+        X->c.stop_deg = opts ? opts->stop_deg : 0;
         F4_HIP_TRY(hipStreamCreateWithFlags(&X->c.own_stream, hipStreamNonBlocking));
         X->c.stream = X->c.own_stream;
         F4_HIP_TRY(hipEventCreateWithFlags(&X->c.staging_done, hipEventDisableTiming));

@@ -31,6 +31,7 @@ struct Fp {
     u32 mu;  // floor(2^(2s) / p)  (< 2^32 for odd p)
     u32 mu32; // floor(2^32 / p): single-word Barrett for any x < 2^32
     u32 r32;  // 2^32 mod p
+    float finv;  // 1/p rounded to float (quotient estimate for p < 2^16)
 };
 
 static inline Fp make_fp(u32 p) {
@@ -42,6 +43,7 @@ static inline Fp make_fp(u32 p) {
     f.mu = (u32)(num / p);
     f.mu32 = (u32)((1ull << 32) / p);
     f.r32 = (u32)((1ull << 32) % p);
+    f.finv = 1.0f / (float)p;
     return f;
 }
 
@@ -71,6 +73,23 @@ __host__ __device__ __forceinline__ u32 fp_reduce_any(const Fp& f, u64 x) {
     if ((x >> (2 * f.s)) == 0) return fp_reduce(f, x);
     u32 h = fp_reduce32(f, (u32)(x >> 32)), l = fp_reduce32(f, (u32)x);
     return fp_reduce(f, (u64)h * f.r32 + l);
+}
+
+// low 32 bits of the product of the low 24 bits of a and b, unsigned (the
+// runtime's __umul24 returns int, which would sign-extend when widened)
+__device__ __forceinline__ u32 mul24(u32 a, u32 b) { return (u32)__umul24(a, b); }
+
+// a*b mod p for p < 2^16 and a, b < p, with full-rate 24-bit multiplies: the
+// product x < 2^32 is exact in the low word; the float estimate of x/p has
+// relative error below 2^-22, so with x/p < 2^16 its truncation q is off by at
+// most one and x - q*p lies in [-p, 2p); two unsigned min steps (an add that
+// wraps picks the corrected value) bring it to [0, p).
+__device__ __forceinline__ u32 fp_mul16(const Fp& f, u32 a, u32 b) {
+    const u32 x = mul24(a, b);
+    const u32 q = (u32)((float)x * f.finv);
+    u32 r = x - mul24(q, f.p);
+    r = min(r, r + f.p);
+    return min(r, r - f.p);
 }
 
 // (a + b*c) mod p for canonical a, b, c: equation "mod-fma"

@@ -144,6 +144,7 @@ struct Ctx {
     hipStream_t stream = nullptr;  // stream of the current call
     Pool pool;
     u32 flags = 0;
+    u32 stop_deg = 0;  // stop a system after its first step of this degree (0: never)
     std::string last_error;
     // pinned host arena for small uploads / readbacks: uploads take successive
     // regions (no wait while the arena has room); a readback drains the
@@ -169,6 +170,8 @@ void upload(Ctx& c, void* dst, const void* src, size_t bytes);
 void readback(Ctx& c, void* dst, const void* src, size_t bytes);
 // Event for stage timing (nullptr when timing is off).
 hipEvent_t stage_event(Ctx& c);
+// Whether the context records timings (the timing option).
+bool timing_on(const Ctx& c);
 float event_ms(hipEvent_t a, hipEvent_t b);
 
 // Binomial table C(x, y), x <= n+D+1, y <= min(n, 15), on the device.
@@ -246,6 +249,12 @@ struct Reduced {
     DBuf<u32> pivot_cols, row_ptr, col_ind, val;  // row_ptr holds batch-global offsets
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_split = 0, t_trsm = 0, t_echelon = 0, t_emit = 0;
+    // per-kernel timing (timing option): event pairs around each launch of the
+    // triangular-solve and echelon block-step kernels, and their product counts
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_trsm, ev_block;
+    DBuf<u64> ops;  // [0] triangular solve, [1] block step
+    float t_k_trsm = 0, t_k_block = 0;
+    u64 trsm_ops = 0, block_ops = 0;
     void read_times() {
         if (!ev[0]) return;
         (void)hipEventSynchronize(ev[4]);
@@ -253,6 +262,13 @@ struct Reduced {
         t_trsm = event_ms(ev[1], ev[2]);
         t_echelon = event_ms(ev[2], ev[3]);
         t_emit = event_ms(ev[3], ev[4]);
+        t_k_trsm = t_k_block = 0;
+        for (auto& e : ev_trsm) t_k_trsm += event_ms(e.first, e.second);
+        for (auto& e : ev_block) t_k_block += event_ms(e.first, e.second);
+        u64 h[2] = {0, 0};
+        if (ops.ptr) (void)hipMemcpy(h, ops.ptr, sizeof(h), hipMemcpyDeviceToHost);
+        trsm_ops = h[0];
+        block_ops = h[1];
     }
 };
 // Elimination of every system of a batched matrix (p[i] for system i).

@@ -214,10 +214,11 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
                                                      int tail, u32 rr, u32 tile_base, int skip_lead,
                                                      const u32* perm, const u32* Tinv, const u32* tptr,
                                                      const u64* tent, typename AccOf<SMALL>::T* gacc, u32* Dp,
-                                                     u32* lead_out) {
+                                                     u32* lead_out, unsigned long long* ops) {
     typedef typename AccOf<SMALL>::T AccT;
     extern __shared__ unsigned char smraw[];
     __shared__ u32 s_x[TR_MAXR][PANEL];
+    __shared__ u64 s_xs[2][TR_MAXR][PANEL];  // partial sums of x = l T^-1 (double buffered)
     __shared__ u64 s_hit[TR_MAXR];
     __shared__ u32 s_lead[TR_MAXR];
     const SegR S = segs[sys_base + blockIdx.y];
@@ -241,58 +242,89 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
     }
     __syncthreads();
     const u32 npanels = (npiv + PANEL - 1) / PANEL;
-    for (u32 kp = 0; kp < npanels; ++kp) {
-        // the panel's first TR_THREADS * TR_UNROLL trailing entries are loaded
-        // before the panel solve, so their latency overlaps it
-        const u32 qa = kp * PANEL, qb = min(npiv, qa + PANEL);
-        const u32 ea = tptr[S.pb + qa], eb = tptr[S.pb + qb];
-        u64 t[TR_UNROLL];
+    // Per panel: (A) every wave w forms, for each row of the tile, the partial
+    // products of rows 4w..4w+3 of T^-1 with the row's panel values and adds
+    // them into s_xs; (B) the tile's waves finish x = l T^-1; (C) every
+    // thread applies its trailing entries.  The next panel's T^-1 slice and
+    // trailing entries are loaded during the current one (neither depends on
+    // the accumulators), so memory latency stays off the critical path.
+    constexpr u32 BW = PANEL / (TR_THREADS / F4_WAVE);  // T^-1 rows per wave
+    static_assert(BW * (TR_THREADS / F4_WAVE) == PANEL, "panel split");
+    u32 tin[BW];
+    u64 t[TR_UNROLL];
+    u32 ea = 0, eb = 0;
+    u32 nops = 0;  // modular products of this thread (reported with the timing option)
+    auto load_panel = [&](u32 kq, u32* tin_, u64* t_, u32& ea_, u32& eb_) {
+        const u32* Tk = Tinv + (u64)(S.tb + kq) * PANEL * PANEL;
+#pragma unroll
+        for (u32 i = 0; i < BW; ++i) tin_[i] = Tk[(wave * BW + i) * PANEL + lane];
+        const u32 qa = kq * PANEL, qb = min(npiv, qa + PANEL);
+        ea_ = tptr[S.pb + qa];
+        eb_ = tptr[S.pb + qb];
 #pragma unroll
         for (int k = 0; k < TR_UNROLL; ++k) {
-            const u32 e = ea + tid + k * TR_THREADS;
-            t[k] = e < eb ? tent[e] : 0ull;
+            const u32 e = ea_ + tid + k * TR_THREADS;
+            t_[k] = e < eb_ ? tent[e] : 0ull;
         }
-        if (wave < nr) {
-            AccT* a = acc + wave * N;
-            const u32 c0 = qa + lane;
-            u32 v = 0;
-            if (c0 < npiv) v = SMALL ? fp_reduce32(f, (u32)a[c0]) : fp_reduce_any(f, (u64)a[c0]);
-            if (wave_ballot(v != 0)) {
-                // x = l T^-1 (T^-1 upper triangular: lane j sums rows b <= j)
-                const u32* Tk = Tinv + (u64)(S.tb + kp) * PANEL * PANEL;
-                u32 tc[PANEL];
+    };
+    if (tid < 2 * TR_MAXR * PANEL) (&s_xs[0][0][0])[tid] = 0;
+    if (npanels) load_panel(0, tin, t, ea, eb);
+    __syncthreads();
+    for (u32 kp = 0; kp < npanels; ++kp) {
+        const u32 qa = kp * PANEL, wk = min((u32)PANEL, npiv - qa), buf = kp & 1;
+        // (A) partial products
+        for (u32 r = 0; r < nr; ++r) {
+            u64 part = 0;
 #pragma unroll
-                for (int b = 0; b < PANEL; ++b) tc[b] = Tk[b * PANEL + lane];
-                u64 x = 0;
-#pragma unroll
-                for (int b = 0; b < PANEL; ++b) {
-                    const u32 lb = __builtin_amdgcn_readlane(v, b);
-                    if (lb != 0) x += SMALL ? (u64)lb * tc[b] : (u64)fp_mul(f, lb, tc[b]);
+            for (u32 i = 0; i < BW; ++i) {
+                const u32 b = wave * BW + i;
+                if (b >= wk) continue;
+                const AccT ab = acc[r * N + qa + b];  // same address in every lane
+                const u32 lb = SMALL ? fp_reduce32(f, (u32)ab) : fp_reduce_any(f, (u64)ab);
+                if (lb) {
+                    part += SMALL ? (u64)mul24(lb, tin[i]) : (u64)fp_mul(f, lb, tin[i]);
+                    ++nops;
                 }
-                v = fp_reduce_any(f, x);
-                if (c0 < npiv) a[c0] = 0;
             }
-            s_x[wave][lane] = v;
-            const u64 hit = wave_ballot(v != 0);
-            if (lane == 0) s_hit[wave] = hit;
+            if (part) atomicAdd((unsigned long long*)&s_xs[buf][r][lane], (unsigned long long)part);
+        }
+        // the next panel's loads go out now
+        u32 tin2[BW] = {};
+        u64 t2[TR_UNROLL] = {};
+        u32 ea2 = 0, eb2 = 0;
+        if (kp + 1 < npanels) load_panel(kp + 1, tin2, t2, ea2, eb2);
+        __syncthreads();
+        // (B) x of every row; the panel's pivot columns of the accumulators are done
+        if (wave < nr) {
+            const u32 r = wave;
+            const u32 x = fp_reduce_any(f, s_xs[buf][r][lane]);
+            s_xs[buf][r][lane] = 0;
+            s_x[r][lane] = x;
+            const u64 hit = wave_ballot(x != 0);
+            if (lane == 0) s_hit[r] = hit;
+            if (lane < wk) acc[r * N + qa + lane] = 0;
         }
         __syncthreads();
         u64 anyhit = 0;
         for (u32 r = 0; r < nr; ++r) anyhit |= s_hit[r];
         if (anyhit) {
-            // apply every trailing entry to every row of the tile
+            // (C) apply every trailing entry to every row of the tile
             for (u32 e0 = ea + tid;; e0 += TR_THREADS * TR_UNROLL) {
 #pragma unroll
                 for (int k = 0; k < TR_UNROLL; ++k) {
                     if (!t[k]) continue;  // stored values are nonzero
                     const u32 b = (u32)(t[k] >> 26) & (PANEL - 1), col = (u32)t[k] & 0x3ffffffu;
                     const u32 tv = (u32)(t[k] >> 32);
-                    for (u32 r = 0; r < nr; ++r) {
-                        const u32 xb = s_x[r][b];
-                        if (!xb) continue;
-                        const u32 negx = f.p - xb;
-                        const u32 add = SMALL ? fp_reduce32(f, negx * tv) : fp_reduce(f, (u64)negx * tv);
+                    u32 xs[TR_MAXR];
+#pragma unroll
+                    for (int r = 0; r < TR_MAXR; ++r) xs[r] = (u32)r < nr ? s_x[r][b] : 0u;
+#pragma unroll
+                    for (int r = 0; r < TR_MAXR; ++r) {
+                        if (!xs[r]) continue;
+                        const u32 negx = f.p - xs[r];
+                        const u32 add = SMALL ? fp_mul16(f, negx, tv) : fp_reduce(f, (u64)negx * tv);
                         atomicAdd(&acc[r * N + col], (AccT)add);
+                        ++nops;
                     }
                 }
                 const u32 e1 = e0 + TR_THREADS * TR_UNROLL;
@@ -304,6 +336,12 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
                 }
             }
         }
+#pragma unroll
+        for (u32 i = 0; i < BW; ++i) tin[i] = tin2[i];
+#pragma unroll
+        for (int k = 0; k < TR_UNROLL; ++k) t[k] = t2[k];
+        ea = ea2;
+        eb = eb2;
         __syncthreads();
     }
     // trailing block rows: non-pivot part of the accumulators
@@ -321,6 +359,11 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
     }
     __syncthreads();
     if (tid < nr && lead_out) lead_out[S.lb + t0 + tid] = s_lead[tid];
+    if (ops) {
+        u64 v = nops;
+        for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, F4_WAVE);
+        if (lane == 0 && v) atomicAdd(ops, (unsigned long long)v);
+    }
 }
 
 // ---------------------------------------------------------------- echelon
@@ -355,7 +398,7 @@ struct EchRound {
 
 template <bool SMALL>
 __device__ __forceinline__ u32 fp_mul_t(const Fp& f, u32 a, u32 b) {
-    return SMALL ? fp_reduce32(f, a * b) : fp_reduce(f, (u64)a * b);  // SMALL: a*b < p^2 < 2^32
+    return SMALL ? fp_mul16(f, a, b) : fp_reduce(f, (u64)a * b);  // SMALL: p < 2^16
 }
 
 // (piv * a - fk * b) mod p
@@ -367,14 +410,14 @@ __device__ __forceinline__ u32 fp_ff(const Fp& f, u32 piv, u32 a, u32 fk, u32 b)
 
 __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead, u32* status, const u32* Dp,
                                                     u32* cnt_g, int cnt_lds, EchRound* rounds, u32* prlead,
-                                                    u32* ndone) {
+                                                    u32* ndone, unsigned long long* ops) {
     extern __shared__ u32 scnt[];
     __shared__ u32 s_wave[33];
     __shared__ u32 s_rows[ECH_B];
     __shared__ u32 s_RZ[ECH_B * ECH_W];
     __shared__ u32 s_B[ECH_B * ECH_CH];
     __shared__ u32 s_pcol[ECH_B], s_prow[ECH_B], s_pv[ECH_B], s_inv[ECH_B];
-    __shared__ u64 s_nz[2];
+    __shared__ u64 s_nz[3];
     __shared__ u32 s_thr, s_need, s_cmin;
     EchRound* R = rounds + blockIdx.y;
     if (R->done) return;
@@ -444,12 +487,13 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         const u32 k = x / ECH_W, j = x % ECH_W;
         s_RZ[x] = (j >= ECH_CH && j - ECH_CH == k) ? 1u : 0u;
     }
-    if (tid < 2) s_nz[tid] = 0;
+    if (tid < 3) s_nz[tid] = 0;
     __syncthreads();
     const bool small = S.small != 0;
     const u32 lane = tid % F4_WAVE, wave = tid / F4_WAVE;
     const u32 r0 = 2 * wave, r1 = 2 * wave + 1;  // block rows of this wave
-    u32 q = 0, pmask = 0, par = 0;
+    u32 q = 0, pmask = 0, it = 0;
+    u64 nops = 0;  // modular products (counted by lane 0 of each wave; timing option)
     // chunks of ECH_CH columns from the smallest leading column of the block
     for (u32 j0 = s_cmin; j0 < c && q < b; j0 += ECH_CH) {
         const u32 w = min((u32)ECH_CH, c - j0);
@@ -469,49 +513,63 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
                     if (z) acc += small ? (u64)z * s_B[u * ECH_CH + j] : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
                 }
                 v = fp_reduce_any(f, acc);
+                if (j == 0) nops += (u64)b * ECH_CH;  // the row's products, counted once
             }
             s_RZ[k * ECH_W + j] = v;
         }
         __syncthreads();
+        // columns where a non-pivot row is nonzero, merged over the waves into
+        // s_nz[it % 3]; each step computes the next step's mask right after
+        // its own row updates, so a step needs one block barrier (three
+        // buffers: one read, one written, one cleared)
         u32 jstart = 0;
-        while (q < b) {
-            // columns where a non-pivot row is nonzero, merged over the waves
+        {
             bool nz = false;
             if (r0 < b && !((pmask >> r0) & 1u)) nz |= s_RZ[r0 * ECH_W + lane] != 0;
             if (r1 < b && !((pmask >> r1) & 1u)) nz |= s_RZ[r1 * ECH_W + lane] != 0;
-            const u64 m = wave_ballot(nz && lane >= jstart && lane < w);
-            if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[par], (unsigned long long)m);
-            __syncthreads();
-            const u64 all = s_nz[par];
-            if (tid == 0) s_nz[par ^ 1] = 0;
+            const u64 m = wave_ballot(nz && lane < w);
+            if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[it % 3], (unsigned long long)m);
+        }
+        __syncthreads();
+        while (q < b) {
+            const u64 all = s_nz[it % 3];
+            if (tid == 0) s_nz[(it + 2) % 3] = 0;
             if (!all) break;
             const u32 jp = __ffsll((long long)all) - 1;
             // pivot row: the first non-pivot row nonzero at jp (row kp and the
-            // rows before it do not change in this step, so every wave agrees)
+            // rows before it do not change in this step, so every wave agrees
+            // while the others update their rows)
             const u32 cand = (lane < b && !((pmask >> lane) & 1u)) ? s_RZ[lane * ECH_W + jp] : 0u;
             const u32 kp = __ffsll((long long)wave_ballot(cand != 0)) - 1;
             const u32 piv = s_RZ[kp * ECH_W + jp];
             const u32 prow = s_RZ[kp * ECH_W + lane];
+            const u32 pm2 = pmask | (1u << kp);
+            bool nz = false;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const u32 r = h ? r1 : r0;
                 if (r >= b || r == kp) continue;
                 const u32 fk = s_RZ[r * ECH_W + jp];
-                if (!fk) continue;
-                const u32 old = s_RZ[r * ECH_W + lane];
-                s_RZ[r * ECH_W + lane] =
-                    small ? fp_ff<true>(f, piv, old, fk, prow) : fp_ff<false>(f, piv, old, fk, prow);
-                if (lane == 0 && ((pmask >> r) & 1u)) s_pv[r] = fp_mul(f, s_pv[r], piv);
+                u32 val = s_RZ[r * ECH_W + lane];
+                if (fk) {
+                    val = small ? fp_ff<true>(f, piv, val, fk, prow) : fp_ff<false>(f, piv, val, fk, prow);
+                    s_RZ[r * ECH_W + lane] = val;
+                    if (lane == 0) nops += 2 * ECH_W;
+                    if (lane == 0 && ((pmask >> r) & 1u)) s_pv[r] = fp_mul(f, s_pv[r], piv);
+                }
+                if (!((pm2 >> r) & 1u)) nz |= val != 0;
             }
             if (tid == 0) {
                 s_pcol[q] = j0 + jp;
                 s_prow[q] = kp;
                 s_pv[kp] = piv;
             }
-            pmask |= 1u << kp;
+            pmask = pm2;
             ++q;
             jstart = jp + 1;
-            par ^= 1;
+            const u64 m = wave_ballot(nz && lane >= jstart && lane < w);
+            if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[(it + 1) % 3], (unsigned long long)m);
+            ++it;
             __syncthreads();
         }
     }
@@ -532,6 +590,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         R->rows[tid] = s_rows[tid];
         st[s_rows[tid]] = 1;
     }
+    if (ops && nops) atomicAdd(ops, (unsigned long long)nops);
     __syncthreads();
     if (tid == 0) {
         R->q = q;
@@ -882,7 +941,8 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
 // lb + cnt) are the system's rows (cnt = L, or r for the tail reduction);
 // dense trailing rows go to Dp at segs[s].dpb + local * c.
 static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* list, int tail, int skip_lead, u32* Dp,
-                     u32* lead_out) {
+                     u32* lead_out, Reduced* kt) {
+    unsigned long long* ops = kt && kt->ops.ptr ? (unsigned long long*)kt->ops.ptr : nullptr;
     hipStream_t s = c.stream;
     const u32 S = X.S;
     for (int cls = 0; cls < 2; ++cls) {
@@ -896,21 +956,24 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
             }
         if (!cmax) continue;
         const size_t row_bytes = (size_t)nmax * accb;
-        const size_t budget = c.dev.max_lds > 4096 ? c.dev.max_lds - 4096 : 0;
+        // the kernel's static LDS (panel vectors, partial sums) is below 8 KB
+        const size_t budget = c.dev.max_lds > 8192 ? c.dev.max_lds - 8192 : 0;
         if (row_bytes <= budget) {
             const u32 rr = (u32)std::min<size_t>(TR_MAXR, budget / row_bytes);
             const u32 tiles = ceil_div(cmax, rr);
+            hipEvent_t ka = kt ? stage_event(c) : nullptr;
             if (small)
                 hipLaunchKernelGGL((k_trsm<true, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
                                    X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
                                    skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)nullptr, Dp,
-                                   lead_out);
+                                   lead_out, ops);
             else
                 hipLaunchKernelGGL((k_trsm<false, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
                                    X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
                                    skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, Dp,
-                                   lead_out);
+                                   lead_out, ops);
             F4_LAUNCH_CHECK();
+            if (ka) kt->ev_trsm.push_back({ka, stage_event(c)});
             continue;
         }
         // accumulators in global memory (one row per tile), one system and a
@@ -927,11 +990,13 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
                 if (small)
                     hipLaunchKernelGGL((k_trsm<true, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
                                        A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
-                                       X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)gacc.ptr, Dp, lead_out);
+                                       X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)gacc.ptr, Dp, lead_out,
+                                       ops);
                 else
                     hipLaunchKernelGGL((k_trsm<false, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
                                        A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
-                                       X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, Dp, lead_out);
+                                       X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, Dp, lead_out,
+                                       ops);
                 F4_LAUNCH_CHECK();
             }
         }
@@ -957,7 +1022,11 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
         maxc = std::max(maxc, g.c);
     }
     DBuf<u32> Dp(&c.pool, std::max<u64>(Dtot, 1)), lead(&c.pool, std::max<u32>(X.Ltot, 1));
-    run_trsm(c, A, X, X.lower.ptr, 0, 0, Dp.ptr, lead.ptr);
+    if (timing_on(c)) {
+        out.ops.reset(&c.pool, 2);
+        fill_u64(out.ops.ptr, 2, 0, s);
+    }
+    run_trsm(c, A, X, X.lower.ptr, 0, 0, Dp.ptr, lead.ptr, &out);
     hipEvent_t e2 = stage_event(c);
 
     // echelon of every system's D' (L x c)
@@ -985,10 +1054,13 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
         u32 done = 0, r = 0;
         while (done < active) {
             for (int k = 0; k < 4; ++k) {
+                hipEvent_t ka = stage_event(c);
                 hipLaunchKernelGGL(k_ech_block, dim3(1, S), dim3(1024), cnt_lds ? (size_t)maxc * 4 : 0, s,
                                    X.dsegs.ptr, lead.ptr, status.ptr, Dp.ptr, cnt.ptr, cnt_lds, rounds.ptr,
-                                   prlead.ptr, ndone.ptr);
+                                   prlead.ptr, ndone.ptr,
+                                   out.ops.ptr ? (unsigned long long*)out.ops.ptr + 1 : nullptr);
                 F4_LAUNCH_CHECK();
+                if (ka) out.ev_block.push_back({ka, stage_event(c)});
                 hipLaunchKernelGGL(k_ech_update, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s, X.dsegs.ptr, S, ub.ptr,
                                    Dp.ptr, status.ptr, lead.ptr, rounds.ptr, PR.ptr);
                 F4_LAUNCH_CHECK();
@@ -1095,7 +1167,7 @@ void tail_reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, DBuf<
     // system of each row as a key (for the wave kernels below)
     hipLaunchKernelGGL(k_row_sys_keys, dim3(grid_of(R, 256, 1024)), dim3(256), 0, s, A.row_sys.ptr, R, keys.ptr);
     F4_LAUNCH_CHECK();
-    run_trsm(c, A, X, rows.ptr, 1, 1, Dp.ptr, nullptr);
+    run_trsm(c, A, X, rows.ptr, 1, 1, Dp.ptr, nullptr, nullptr);
     hipLaunchKernelGGL(k_count_nz, dim3(grid_of(R, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, 32u, rows.ptr, R,
                        0, Dp.ptr, Dp.ptr, cnt.ptr);
     F4_LAUNCH_CHECK();

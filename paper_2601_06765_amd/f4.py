@@ -27,7 +27,7 @@ P = ctypes.POINTER
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("flags", c_u32), ("reserved", c_u32)]
+    _fields_ = [("flags", c_u32), ("stop_deg", c_u32)]
 
 
 class Polys(ctypes.Structure):
@@ -61,7 +61,9 @@ class StepStats(ctypes.Structure):
                 ("t_dict_ms", ctypes.c_float), ("t_assemble_ms", ctypes.c_float),
                 ("t_numeric_ms", ctypes.c_float), ("t_trsm_ms", ctypes.c_float),
                 ("t_echelon_ms", ctypes.c_float), ("t_step_ms", ctypes.c_float),
-                ("t_pairs_ms", ctypes.c_float)]
+                ("t_pairs_ms", ctypes.c_float),
+                ("t_k_trsm_ms", ctypes.c_float), ("n_k_trsm", c_u32), ("trsm_ops", c_u64),
+                ("t_k_block_ms", ctypes.c_float), ("n_k_block", c_u32), ("block_ops", c_u64)]
 
 
 def _sig(name, res, args):
@@ -183,14 +185,14 @@ class _PolysArg:
 
 # --------------------------------------------------------------- context
 class Context:
-    def __init__(self, device=0, timing=False, dict_path=None):
+    def __init__(self, device=0, timing=False, dict_path=None, stop_deg=0):
         flags = F4_OPT_TIMING if timing else 0
         if dict_path == "rank":
             flags |= F4_OPT_DICT_RANK
         elif dict_path == "radix":
             flags |= F4_OPT_DICT_RADIX
         self._h = c_vp()
-        rc = _lib.f4_create(ctypes.byref(self._h), device, ctypes.byref(Opts(flags, 0)))
+        rc = _lib.f4_create(ctypes.byref(self._h), device, ctypes.byref(Opts(flags, stop_deg)))
         if rc:
             raise F4Error(rc, "f4_create failed")
 

@@ -304,3 +304,20 @@ def test_determinism_repeated_runs(f4, ctx):
         R = ctx.reduce(p, A).to_host()
         outs.append((h["col_ind"].tobytes(), h["val"].tobytes(), R["col_ind"].tobytes(), R["val"].tobytes()))
     assert outs[0] == outs[1] == outs[2]
+
+
+@pytest.mark.gpu
+def test_stop_degree_keeps_leading_steps(f4):
+    """A context with a stop degree runs the same steps as a full run up to
+    and including the first step of that degree, then stops (empty basis)."""
+    n, p, polys = synth.config_system(1)
+    full = f4.Context(0)
+    B, steps = full.groebner(p, n, polys)
+    full.close()
+    stop = f4.Context(0, stop_deg=3)
+    B3, steps3 = stop.groebner(p, n, polys)
+    stop.close()
+    first3 = next(i for i, s in enumerate(steps) if s["deg"] == 3)
+    key = lambda s: (s["deg"], s["r"], s["N"], s["nnz"], s["npivot"], s["rank"], s["rho"])
+    assert [key(s) for s in steps3] == [key(s) for s in steps[:first3 + 1]]
+    assert B3 == []
