@@ -151,7 +151,7 @@ static u32 gridn(u64 items, u32 per, u32 cap) {
 
 static void devg_reserve(Ctx& c, DevG& G, u64 terms, u32 polys) {
     if (terms > G.cap_terms) {
-        u64 cap = std::max<u64>(terms, 2 * G.cap_terms);
+        u64 cap = std::max<u64>(terms, 4 * G.cap_terms);  // few regrowths: each copies the basis
         DBuf<u64> m2(&c.pool, cap);
         DBuf<u32> c2(&c.pool, cap);
         if (G.nterms) {
@@ -163,7 +163,7 @@ static void devg_reserve(Ctx& c, DevG& G, u64 terms, u32 polys) {
         G.cap_terms = cap;
     }
     if ((u64)polys + 1 > G.cap_polys) {
-        u64 cap = std::max<u64>((u64)polys + 1, 2 * G.cap_polys);
+        u64 cap = std::max<u64>((u64)polys + 1, 4 * G.cap_polys);
         DBuf<u64> o2(&c.pool, cap), l2(&c.pool, cap);
         DBuf<u32> n2(&c.pool, cap);
         if (G.npolys) {
@@ -414,7 +414,7 @@ static void init_system(Ctx& c, SysState& S, u32 p, const f4_polys* F) {
         }
         off.push_back(mon.size());
     }
-    devg_reserve(c, D, mon.size(), (u32)inputs.size());
+    devg_reserve(c, D, 16 * mon.size(), 16 * (u32)inputs.size());
     upload(c, D.mon.ptr, mon.data(), mon.size() * 8);
     upload(c, D.coeff.ptr, coeff.data(), coeff.size() * 4);
     upload(c, D.off.ptr, off.data(), off.size() * 8);

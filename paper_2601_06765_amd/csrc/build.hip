@@ -506,37 +506,43 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     if (W >= (1ull << 31) || RC >= (1ull << 31) || CM >= (1ull << 31)) throw F4Error{2, "batch too large"};
     const bool closure = args[0].closure;
 
-    DBuf<SegSP> dsegs(&c.pool, S);
-    upload(c, dsegs.ptr, segs.data(), S * sizeof(SegSP));
-    DBuf<u32> present(&c.pool, W), done(&c.pool, W);
-    fill_u32(present.ptr, W, 0, s);
-    fill_u32(done.ptr, W, 0, s);
+    // descriptors, active lists, initial rows and counters: one upload
+    u64 I = 0;
+    for (u32 i = 0; i < S; ++i) I += args[i].r0;
+    std::vector<u8> pack;
+    auto put = [&](const void* src, size_t bytes) {
+        const size_t off = (pack.size() + 255) & ~(size_t)255;
+        pack.resize(off + std::max<size_t>(bytes, 1));
+        if (bytes) std::memcpy(pack.data() + off, src, bytes);
+        return off;
+    };
+    std::vector<u32> hc(CTR * S, 0);
+    for (u32 i = 0; i < S; ++i) hc[CTR * i + 1] = args[i].r0;
+    const size_t o_segs = put(segs.data(), S * sizeof(SegSP));
+    const size_t o_act = put(actv.data(), actv.size() * 4);
+    const size_t o_ctr = put(hc.data(), hc.size() * 4);
+    const size_t o_t0 = put(nullptr, I * 8), o_k0 = put(nullptr, I * 4);
+    for (u32 i = 0; i < S; ++i) {
+        const BuildArgs& a = args[i];
+        std::memcpy(pack.data() + o_t0 + (size_t)segs[i].ibase * 8, a.rows_t_host, (size_t)a.r0 * 8);
+        std::memcpy(pack.data() + o_k0 + (size_t)segs[i].ibase * 4, a.rows_k_host, (size_t)a.r0 * 4);
+    }
+    DBuf<u8> params(&c.pool, pack.size());
+    upload(c, params.ptr, pack.data(), pack.size());
+    SegSP* const dsegs = (SegSP*)(params.ptr + o_segs);
+    const u32* const active = (const u32*)(params.ptr + o_act);
+    u32* const ctr = (u32*)(params.ptr + o_ctr);  // counters live in the parameter block
+    DBuf<u32> pd(&c.pool, 2 * W);                 // present and done bitmaps, cleared together
+    fill_u32(pd.ptr, 2 * W, 0, s);
+    u32* const present = pd.ptr;
+    u32* const done = pd.ptr + W;
     DBuf<u64> rows_t(&c.pool, RC);
-    DBuf<u32> rows_k(&c.pool, RC), row_lmrank(&c.pool, RC), active(&c.pool, std::max<size_t>(actv.size(), 1));
-    DBuf<u32> ctr(&c.pool, CTR * S);
-    upload(c, active.ptr, actv.data(), actv.size() * 4);
+    DBuf<u32> rows_k(&c.pool, RC), row_lmrank(&c.pool, RC);
     {
-        // initial rows of every system, packed once on the host
-        u64 I = 0;
-        for (u32 i = 0; i < S; ++i) I += args[i].r0;
-        std::vector<u64> t(I);
-        std::vector<u32> k(I);
-        std::vector<u32> hc(CTR * S, 0);
-        for (u32 i = 0; i < S; ++i) {
-            const BuildArgs& a = args[i];
-            std::memcpy(t.data() + segs[i].ibase, a.rows_t_host, (size_t)a.r0 * 8);
-            std::memcpy(k.data() + segs[i].ibase, a.rows_k_host, (size_t)a.r0 * 4);
-            hc[CTR * i + 1] = a.r0;
-        }
-        DBuf<u64> t0(&c.pool, I);
-        DBuf<u32> k0(&c.pool, I);
-        upload(c, t0.ptr, t.data(), I * 8);
-        upload(c, k0.ptr, k.data(), I * 4);
-        upload(c, ctr.ptr, hc.data(), hc.size() * 4);
         u32 mr = 1;
         for (u32 i = 0; i < S; ++i) mr = std::max(mr, args[i].r0);
-        hipLaunchKernelGGL(k_init_rows, dim3(std::min<u32>(64, ceil_div(mr, 256)), S), dim3(256), 0, s, dsegs.ptr,
-                           t0.ptr, k0.ptr, rows_t.ptr, rows_k.ptr);
+        hipLaunchKernelGGL(k_init_rows, dim3(std::min<u32>(64, ceil_div(mr, 256)), S), dim3(256), 0, s, dsegs,
+                           (const u64*)(params.ptr + o_t0), (const u32*)(params.ptr + o_k0), rows_t.ptr, rows_k.ptr);
         F4_LAUNCH_CHECK();
     }
     DBuf<unsigned long long> Mdev(&c.pool, S);
@@ -545,8 +551,8 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     const size_t mark_lds = (max_tabn + (local_bitmap ? max_words : 0)) * 4;
     const u32 bx = std::max<u32>(1, std::min<u32>((u32)std::max(1, c.dev.cus), ceil_div(2048, S)));
     auto mark = [&]() {
-        hipLaunchKernelGGL(k_mark_rows, dim3(bx, S), dim3(MB_THREADS), mark_lds, s, dsegs.ptr, rows_t.ptr,
-                           rows_k.ptr, row_lmrank.ptr, ctr.ptr, present.ptr, done.ptr, local_bitmap);
+        hipLaunchKernelGGL(k_mark_rows, dim3(bx, S), dim3(MB_THREADS), mark_lds, s, dsegs, rows_t.ptr,
+                           rows_k.ptr, row_lmrank.ptr, ctr, present, done, local_bitmap);
         F4_LAUNCH_CHECK();
     };
     mark();
@@ -566,21 +572,21 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         if (closure) {
             // two speculative rounds per host check: dense systems converge in two
             for (int k = 0; k < 2; ++k) {
-                hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present.ptr, done.ptr, (u32)W,
+                hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present, done, (u32)W,
                                    fcnt.ptr);
                 F4_LAUNCH_CHECK();
                 exclusive_scan_u32(fcnt.ptr, fcnt.ptr, W, c.pool, s);
-                hipLaunchKernelGGL(k_frontier_write, dim3(wbx, S), dim3(256), 0, s, dsegs.ptr, present.ptr, done.ptr,
-                                   fcnt.ptr, list_q.ptr, list_s.ptr, ctr.ptr);
+                hipLaunchKernelGGL(k_frontier_write, dim3(wbx, S), dim3(256), 0, s, dsegs, present, done,
+                                   fcnt.ptr, list_q.ptr, list_s.ptr, ctr);
                 F4_LAUNCH_CHECK();
                 hipLaunchKernelGGL(k_reducers, dim3(rbx_red, S), dim3(MB_THREADS), lds_active ? max_act * 8 : 0, s,
-                                   dsegs.ptr, list_q.ptr, fcnt.ptr, active.ptr, lds_active, rows_t.ptr, rows_k.ptr,
-                                   row_lmrank.ptr, ctr.ptr);
+                                   dsegs, list_q.ptr, fcnt.ptr, active, lds_active, rows_t.ptr, rows_k.ptr,
+                                   row_lmrank.ptr, ctr);
                 F4_LAUNCH_CHECK();
                 mark();
                 ++rounds;
             }
-            hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present.ptr, done.ptr, (u32)W,
+            hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present, done, (u32)W,
                                fcnt.ptr);
             F4_LAUNCH_CHECK();
             exclusive_scan_u32(fcnt.ptr, fcnt.ptr, W, c.pool, s);
@@ -588,13 +594,13 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
             fill_u32(fcnt.ptr, W + 1, 0, s);
         }
         // dictionary sizes and M alongside the convergence check: one readback
-        hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, present.ptr, (u32)W, pcnt.ptr);
+        hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, present, (u32)W, pcnt.ptr);
         F4_LAUNCH_CHECK();
         exclusive_scan_u32(pcnt.ptr, pcnt.ptr, W, c.pool, s);
         fill_u64((u64*)Mdev.ptr, S, 0, s);
-        hipLaunchKernelGGL(k_sum_len, dim3(bx, S), dim3(256), 0, s, dsegs.ptr, rows_k.ptr, ctr.ptr, Mdev.ptr);
+        hipLaunchKernelGGL(k_sum_len, dim3(bx, S), dim3(256), 0, s, dsegs, rows_k.ptr, ctr, Mdev.ptr);
         F4_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sp_summary, dim3(grid_for(S, 256, 64)), dim3(256), 0, s, dsegs.ptr, S, ctr.ptr, fcnt.ptr,
+        hipLaunchKernelGGL(k_sp_summary, dim3(grid_for(S, 256, 64)), dim3(256), 0, s, dsegs, S, ctr, fcnt.ptr,
                            pcnt.ptr, Mdev.ptr, summary.ptr);
         F4_LAUNCH_CHECK();
         readback(c, hs.data(), summary.ptr, hs.size() * 4);
@@ -631,13 +637,13 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         Mtot += P.nnz;
     }
     if (Mtot >= (1ull << 32) || R >= (1ull << 31)) throw F4Error{2, "batch matrix has 2^32 or more entries"};
-    upload(c, dsegs.ptr, segs.data(), S * sizeof(SegSP));
+    upload(c, dsegs, segs.data(), S * sizeof(SegSP));
     hipEvent_t ev1 = stage_event(c);
 
     // dictionary (dense rank): popcount prefix of the seen bitmap
     DBuf<u32> colmap(&c.pool, CM);
     out.dict_keys.reset(&c.pool, CM);
-    hipLaunchKernelGGL(k_dict, dim3(wbx, S), dim3(256), 0, s, dsegs.ptr, present.ptr, pcnt.ptr, colmap.ptr,
+    hipLaunchKernelGGL(k_dict, dim3(wbx, S), dim3(256), 0, s, dsegs, present, pcnt.ptr, colmap.ptr,
                        out.dict_keys.ptr);
     F4_LAUNCH_CHECK();
 
@@ -650,7 +656,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     DBuf<u64> keys(&c.pool, R);
     DBuf<u32> perm(&c.pool, R);
     const u32 rbx = std::max<u32>(1, std::min<u32>(64, ceil_div(ceil_div(R, S), 256)));
-    hipLaunchKernelGGL(k_row_keys, dim3(rbx, S), dim3(256), 0, s, dsegs.ptr, row_lmrank.ptr, rows_k.ptr, sshift, kbits,
+    hipLaunchKernelGGL(k_row_keys, dim3(rbx, S), dim3(256), 0, s, dsegs, row_lmrank.ptr, rows_k.ptr, sshift, kbits,
                        keys.ptr, perm.ptr);
     F4_LAUNCH_CHECK();
     radix_sort_pairs(keys.ptr, perm.ptr, R, 0, sshift + sbits, c.pool, s);
@@ -658,7 +664,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     out.row_k.reset(&c.pool, R);
     out.row_sys.reset(&c.pool, R);
     out.row_ptr.reset(&c.pool, R + 1);
-    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(R, 256, 4096)), dim3(256), 0, s, dsegs.ptr, perm.ptr, keys.ptr,
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(R, 256, 4096)), dim3(256), 0, s, dsegs, perm.ptr, keys.ptr,
                        S > 1 ? sshift : 64u, rows_t.ptr, rows_k.ptr, (u32)R, out.row_t.ptr, out.row_k.ptr,
                        out.row_ptr.ptr, out.row_sys.ptr);
     F4_LAUNCH_CHECK();
@@ -671,7 +677,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     const u32 fbx =
         std::max<u32>(1, std::min<u32>(8 * (u32)std::max(1, c.dev.cus), ceil_div(ceil_div(R, S), MB_WAVES)));
     if (path == 0) {
-        hipLaunchKernelGGL(k_fill_rank, dim3(fbx, S), dim3(MB_THREADS), max_tabn * 4, s, dsegs.ptr, out.row_t.ptr,
+        hipLaunchKernelGGL(k_fill_rank, dim3(fbx, S), dim3(MB_THREADS), max_tabn * 4, s, dsegs, out.row_t.ptr,
                            out.row_k.ptr, out.row_ptr.ptr, colmap.ptr, out.col_ind.ptr, out.val.ptr);
         F4_LAUNCH_CHECK();
     } else {
@@ -681,7 +687,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         const u32 kshift = S > 1 ? kb : 64u;
         DBuf<u64> row_key(&c.pool, std::max<u64>(Mtot, 1)), cand(&c.pool, std::max<u64>(Mtot, 1)),
             dictc(&c.pool, std::max<u64>(Mtot, 1));
-        hipLaunchKernelGGL(k_fill_keys, dim3(fbx, S), dim3(MB_THREADS), 0, s, dsegs.ptr, out.row_t.ptr, out.row_k.ptr,
+        hipLaunchKernelGGL(k_fill_keys, dim3(fbx, S), dim3(MB_THREADS), 0, s, dsegs, out.row_t.ptr, out.row_k.ptr,
                            out.row_ptr.ptr, kshift, row_key.ptr, out.val.ptr);
         F4_LAUNCH_CHECK();
         F4_HIP_TRY(hipMemcpyAsync(cand.ptr, row_key.ptr, Mtot * 8, hipMemcpyDeviceToDevice, s));
@@ -697,7 +703,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
                            dim3(MB_THREADS), lds_dict ? (size_t)N0 * 8 : 0, s, row_key.ptr, Mtot, dictc.ptr,
                            dstart.ptr, kshift, lds_dict, N0, out.col_ind.ptr);
         F4_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_dict_from_compact, dim3(grid_for(Mtot, 256, 2048)), dim3(256), 0, s, dsegs.ptr,
+        hipLaunchKernelGGL(k_dict_from_compact, dim3(grid_for(Mtot, 256, 2048)), dim3(256), 0, s, dsegs,
                            dictc.ptr, ncount.ptr, dstart.ptr, kshift, S, out.dict_keys.ptr);
         F4_LAUNCH_CHECK();
     }

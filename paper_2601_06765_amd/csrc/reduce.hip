@@ -1031,24 +1031,26 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
 
     // echelon of every system's D' (L x c)
     DBuf<u32> PR(&c.pool, std::max<u64>(PRtot, 1)), prlead(&c.pool, std::max<u32>(CAP, 1));
-    DBuf<EchRound> rounds(&c.pool, S);
-    fill_u32((u32*)rounds.ptr, (u64)S * sizeof(EchRound) / 4, 0, s);
     std::vector<u32> npr(S, 0);
     u32 active = 0;
     for (const SegR& g : X.segs) active += (g.L && g.c) ? 1 : 0;
+    // round records, the done counter and the update-grid bases: one upload
+    // (systems with nothing to eliminate are done from the start)
+    const size_t rbytes = ((size_t)S * sizeof(EchRound) + 255) & ~(size_t)255;
+    std::vector<u8> pack(rbytes + 256 + (size_t)(S + 1) * 4, 0);
+    EchRound* init = (EchRound*)pack.data();
+    for (u32 i = 0; i < S; ++i) init[i].done = (X.segs[i].L && X.segs[i].c) ? 0u : 1u;
+    u32* hub = (u32*)(pack.data() + rbytes + 256);
+    for (u32 i = 0; i < S; ++i) hub[i] = X.segs[i].ub;
+    hub[S] = UB;
+    DBuf<u8> eparams(&c.pool, pack.size());
+    EchRound* const rounds = (EchRound*)eparams.ptr;
+    u32* const ndone = (u32*)(eparams.ptr + rbytes);
+    u32* const ubp = (u32*)(eparams.ptr + rbytes + 256);
     if (active) {
-        // systems with nothing to eliminate are done from the start
-        std::vector<EchRound> init(S);
-        std::memset(init.data(), 0, S * sizeof(EchRound));
-        for (u32 i = 0; i < S; ++i) init[i].done = (X.segs[i].L && X.segs[i].c) ? 0u : 1u;
-        upload(c, rounds.ptr, init.data(), S * sizeof(EchRound));
-        DBuf<u32> status(&c.pool, std::max<u32>(X.Ltot, 1)), ndone(&c.pool, 1), ub(&c.pool, S + 1);
+        upload(c, eparams.ptr, pack.data(), pack.size());
+        DBuf<u32> status(&c.pool, std::max<u32>(X.Ltot, 1));
         fill_u32(status.ptr, X.Ltot, 0, s);
-        fill_u32(ndone.ptr, 1, 0, s);
-        std::vector<u32> hub(S + 1);
-        for (u32 i = 0; i < S; ++i) hub[i] = X.segs[i].ub;
-        hub[S] = UB;
-        upload(c, ub.ptr, hub.data(), (S + 1) * 4);
         const int cnt_lds = (size_t)maxc * 4 + 32768 <= c.dev.max_lds;
         DBuf<u32> cnt(&c.pool, cnt_lds ? 1 : std::max<u64>(X.C, 1));
         u32 done = 0, r = 0;
@@ -1056,21 +1058,21 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
             for (int k = 0; k < 4; ++k) {
                 hipEvent_t ka = stage_event(c);
                 hipLaunchKernelGGL(k_ech_block, dim3(1, S), dim3(1024), cnt_lds ? (size_t)maxc * 4 : 0, s,
-                                   X.dsegs.ptr, lead.ptr, status.ptr, Dp.ptr, cnt.ptr, cnt_lds, rounds.ptr,
-                                   prlead.ptr, ndone.ptr,
+                                   X.dsegs.ptr, lead.ptr, status.ptr, Dp.ptr, cnt.ptr, cnt_lds, rounds,
+                                   prlead.ptr, ndone,
                                    out.ops.ptr ? (unsigned long long*)out.ops.ptr + 1 : nullptr);
                 F4_LAUNCH_CHECK();
                 if (ka) out.ev_block.push_back({ka, stage_event(c)});
-                hipLaunchKernelGGL(k_ech_update, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s, X.dsegs.ptr, S, ub.ptr,
-                                   Dp.ptr, status.ptr, lead.ptr, rounds.ptr, PR.ptr);
+                hipLaunchKernelGGL(k_ech_update, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s, X.dsegs.ptr, S, ubp,
+                                   Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr);
                 F4_LAUNCH_CHECK();
                 ++r;
             }
-            readback(c, &done, ndone.ptr, 4);
+            readback(c, &done, ndone, 4);
             if (r > CAP + 8 + 4 * (X.Ltot / ECH_B + 1)) throw F4Error{5, "echelon did not converge"};
         }
         DBuf<u32> dnpr(&c.pool, S);
-        hipLaunchKernelGGL(k_ech_npr, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, rounds.ptr, S, dnpr.ptr);
+        hipLaunchKernelGGL(k_ech_npr, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, rounds, S, dnpr.ptr);
         F4_LAUNCH_CHECK();
         readback(c, npr.data(), dnpr.ptr, S * 4);
     }
