@@ -239,18 +239,31 @@ def main():
 
     torch.cuda.init()
     n, p, polys = synth.config_system(2)
+    # the headline: the timed runs without instrumentation
+    plain = f4.Context(0, dict_path=args.dict)
+    for _ in range(args.warmup):
+        plain.groebner(p, n, polys)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        basis, _ = plain.groebner(p, n, polys)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plain.close()
+    assert basis == [[((0,) * n, 1)]], "unexpected basis"
+    # the same runs again with HIP events around every stage and around each
+    # launch of the two elimination kernels (stage times, roofline)
     ctx = f4.Context(0, timing=True, dict_path=args.dict)
     for _ in range(args.warmup):
         ctx.groebner(p, n, polys)
     torch.cuda.synchronize()
     allsteps = []
-    t0 = time.perf_counter()
+    t1 = time.perf_counter()
     for _ in range(args.steps):
         basis, steps = ctx.groebner(p, n, polys)
         allsteps.append(steps)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert basis == [[((0,) * n, 1)]], "unexpected basis"
+    dt_instr = time.perf_counter() - t1
 
     nnz_run = sum(s["nnz"] for s in allsteps[0])
     rows_run = sum(s["r"] for s in allsteps[0])
@@ -302,6 +315,7 @@ def main():
                    "n": n, "m": len(polys), "p": p, "f4_steps": nsteps, "nnz_per_run": nnz_run,
                    "rows_per_run": rows_run, "dict_path": args.dict or "auto"},
         "rows_per_s": rows_run * args.steps / dt,
+        "ms_per_step_instrumented": dt_instr * 1000.0 / args.steps,
         "systems_per_s_plain": args.steps / dt,
         "per_f4_step": per_step,
         "roofline": out_roof,

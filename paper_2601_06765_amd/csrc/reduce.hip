@@ -104,6 +104,76 @@ __global__ void k_split_summary(const SegR* segs, u32 S, const u32* ppos, const 
     }
 }
 
+// The whole split of a small batch in one workgroup (C <= SPLIT_SMALL_C
+// columns): best row per leading column in LDS, the pivot-column scan, the
+// column renumbering, the lower-row compaction and the per-system counts, with
+// the results of k_lead_best ... k_split_summary.
+#define SPLIT_SMALL_C 8192
+#define SPLIT_SMALL_R 65536
+__global__ __launch_bounds__(1024) void k_split_small(const SegR* segs, u32 S, const u32* row_ptr,
+                                                      const u32* col_ind, const u32* row_sys, u32 R, u32 C,
+                                                      u32* ppos, u32* lpos, u32* perm, u32* prow, u32* pivot_cols,
+                                                      u32* nonpiv, u32* lower, u32* summ) {
+    extern __shared__ unsigned long long sbest[];
+    __shared__ u32 s_wave[33];
+    const u32 tid = threadIdx.x;
+    for (u32 c = tid; c < C; c += 1024) sbest[c] = ~0ull;
+    __syncthreads();
+    for (u32 i = tid; i < R; i += 1024) {
+        const u32 len = row_ptr[i + 1] - row_ptr[i];
+        if (len) atomicMin(&sbest[segs[row_sys[i]].cb + col_ind[row_ptr[i]]], ((unsigned long long)len << 32) | i);
+    }
+    __syncthreads();
+    u32 carry = 0;
+    for (u32 base = 0; base < C; base += 1024) {
+        const u32 c = base + tid;
+        u32 tot;
+        const u32 pre = block_exclusive_scan(c < C && sbest[c] != ~0ull ? 1u : 0u, s_wave, &tot);
+        if (c < C) ppos[c] = carry + pre;
+        carry += tot;
+    }
+    if (tid == 0) ppos[C] = carry;
+    __syncthreads();
+    for (u32 sy = 0; sy < S; ++sy) {
+        const SegR G = segs[sy];
+        const u32 p0 = ppos[G.cb];
+        const u32 npiv = ppos[G.cb + G.N] - p0;
+        for (u32 c = tid; c < G.N; c += 1024) {
+            const u32 g = G.cb + c;
+            const u32 q = ppos[g] - p0;
+            if (sbest[g] != ~0ull) {
+                perm[g] = q;
+                prow[p0 + q] = (u32)(sbest[g] & 0xffffffffu);
+                pivot_cols[p0 + q] = c;
+            } else {
+                perm[g] = npiv + (c - q);
+                nonpiv[(G.cb - p0) + (c - q)] = c;
+            }
+        }
+    }
+    carry = 0;
+    for (u32 base = 0; base < R; base += 1024) {
+        const u32 i = base + tid;
+        bool fl = false;
+        if (i < R) {
+            const u32 len = row_ptr[i + 1] - row_ptr[i];
+            fl = len == 0 || (u32)(sbest[segs[row_sys[i]].cb + col_ind[row_ptr[i]]] & 0xffffffffu) != i;
+        }
+        u32 tot;
+        const u32 pre = block_exclusive_scan(fl ? 1u : 0u, s_wave, &tot);
+        if (i < R) lpos[i] = carry + pre;
+        if (fl) lower[carry + pre] = i;
+        carry += tot;
+    }
+    if (tid == 0) lpos[R] = carry;
+    __syncthreads();
+    for (u32 sy = tid; sy < S; sy += 1024) {
+        const SegR& G = segs[sy];
+        summ[2 * sy] = ppos[G.cb + G.N] - ppos[G.cb];
+        summ[2 * sy + 1] = lpos[G.rb + G.r] - lpos[G.rb];
+    }
+}
+
 // Trailing-entry count of each pivot row (entries beyond its own panel).
 __global__ void k_upper_count(const SegR* segs, const u32* row_ptr, const u32* col_ind, const u32* prow,
                               const u32* perm, u32* tcnt) {
@@ -838,45 +908,52 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
     X.C = (u32)C;
     X.dsegs.reset(&c.pool, S);
     upload(c, X.dsegs.ptr, X.segs.data(), S * sizeof(SegR));
-    DBuf<unsigned long long> best(&c.pool, std::max<u64>(C, 1));
-    fill_u64((u64*)best.ptr, C, ~0ull, s);
-    if (R) {
-        hipLaunchKernelGGL(k_lead_best, dim3(grid_of(R, 256, 4096)), dim3(256), 0, s, X.dsegs.ptr, A.row_ptr.ptr,
-                           A.col_ind.ptr, A.row_sys.ptr, R, best.ptr);
-        F4_LAUNCH_CHECK();
-    }
     DBuf<u32> ppos(&c.pool, C + 1);
-    if (C) {
-        hipLaunchKernelGGL(k_pivflag, dim3(grid_of(C, 256, 4096)), dim3(256), 0, s, best.ptr, (u32)C, ppos.ptr);
-        F4_LAUNCH_CHECK();
-    }
-    exclusive_scan_u32(ppos.ptr, ppos.ptr, C, c.pool, s);
     X.perm.reset(&c.pool, std::max<u64>(C, 1));
     X.prow.reset(&c.pool, std::max<u64>(C, 1));
     X.pivot_cols.reset(&c.pool, std::max<u64>(C, 1));
     X.nonpiv.reset(&c.pool, std::max<u64>(C, 1));
-    u32 maxN = 1;
-    for (auto& g : X.segs) maxN = std::max(maxN, g.N);
-    hipLaunchKernelGGL(k_perm, dim3(std::min<u32>(64, ceil_div(maxN, 256)), S), dim3(256), 0, s, X.dsegs.ptr, best.ptr,
-                       ppos.ptr, X.perm.ptr, X.prow.ptr, X.pivot_cols.ptr, X.nonpiv.ptr);
-    F4_LAUNCH_CHECK();
     DBuf<u32> lf(&c.pool, (u64)R + 1), lpos(&c.pool, (u64)R + 1);
-    if (R) {
-        hipLaunchKernelGGL(k_lower_flags, dim3(grid_of(R, 256, 4096)), dim3(256), 0, s, X.dsegs.ptr, A.row_ptr.ptr,
-                           A.col_ind.ptr, A.row_sys.ptr, R, best.ptr, lf.ptr);
-        F4_LAUNCH_CHECK();
-    }
-    exclusive_scan_u32(lf.ptr, lpos.ptr, R, c.pool, s);
     X.lower.reset(&c.pool, std::max<u32>(R, 1));
-    if (R) {
-        hipLaunchKernelGGL(k_compact_idx, dim3(grid_of(R, 256, 4096)), dim3(256), 0, s, lf.ptr, lpos.ptr, R,
-                           X.lower.ptr);
+    DBuf<u32> summ(&c.pool, 2 * S);
+    if (C <= SPLIT_SMALL_C && R <= SPLIT_SMALL_R) {
+        hipLaunchKernelGGL(k_split_small, dim3(1), dim3(1024), (size_t)std::max<u64>(C, 1) * 8, s, X.dsegs.ptr, S,
+                           A.row_ptr.ptr, A.col_ind.ptr, A.row_sys.ptr, R, (u32)C, ppos.ptr, lpos.ptr, X.perm.ptr,
+                           X.prow.ptr, X.pivot_cols.ptr, X.nonpiv.ptr, X.lower.ptr, summ.ptr);
+        F4_LAUNCH_CHECK();
+    } else {
+        DBuf<unsigned long long> best(&c.pool, std::max<u64>(C, 1));
+        fill_u64((u64*)best.ptr, C, ~0ull, s);
+        if (R) {
+            hipLaunchKernelGGL(k_lead_best, dim3(grid_of(R, 256, 4096)), dim3(256), 0, s, X.dsegs.ptr, A.row_ptr.ptr,
+                               A.col_ind.ptr, A.row_sys.ptr, R, best.ptr);
+            F4_LAUNCH_CHECK();
+        }
+        if (C) {
+            hipLaunchKernelGGL(k_pivflag, dim3(grid_of(C, 256, 4096)), dim3(256), 0, s, best.ptr, (u32)C, ppos.ptr);
+            F4_LAUNCH_CHECK();
+        }
+        exclusive_scan_u32(ppos.ptr, ppos.ptr, C, c.pool, s);
+        u32 maxN = 1;
+        for (auto& g : X.segs) maxN = std::max(maxN, g.N);
+        hipLaunchKernelGGL(k_perm, dim3(std::min<u32>(64, ceil_div(maxN, 256)), S), dim3(256), 0, s, X.dsegs.ptr,
+                           best.ptr, ppos.ptr, X.perm.ptr, X.prow.ptr, X.pivot_cols.ptr, X.nonpiv.ptr);
+        F4_LAUNCH_CHECK();
+        if (R) {
+            hipLaunchKernelGGL(k_lower_flags, dim3(grid_of(R, 256, 4096)), dim3(256), 0, s, X.dsegs.ptr,
+                               A.row_ptr.ptr, A.col_ind.ptr, A.row_sys.ptr, R, best.ptr, lf.ptr);
+            F4_LAUNCH_CHECK();
+        }
+        exclusive_scan_u32(lf.ptr, lpos.ptr, R, c.pool, s);
+        if (R) {
+            hipLaunchKernelGGL(k_compact_idx, dim3(grid_of(R, 256, 4096)), dim3(256), 0, s, lf.ptr, lpos.ptr, R,
+                               X.lower.ptr);
+            F4_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_split_summary, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, X.dsegs.ptr, S, ppos.ptr,
+                           lpos.ptr, summ.ptr);
         F4_LAUNCH_CHECK();
     }
-    DBuf<u32> summ(&c.pool, 2 * S);
-    hipLaunchKernelGGL(k_split_summary, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, X.dsegs.ptr, S, ppos.ptr,
-                       lpos.ptr, summ.ptr);
-    F4_LAUNCH_CHECK();
     std::vector<u32> hs(2 * S);
     readback(c, hs.data(), summ.ptr, hs.size() * 4);
     // per-system layout of the elimination
