@@ -193,6 +193,52 @@ __global__ void k_frontier_write(const SegSP* segs, const u32* present, u32* don
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr[CTR * s] = ctr[CTR * s + 1];
 }
 
+// Small bitmaps (W <= WORDS_SMALL words) in one workgroup: per word the count
+// of its set bits (mode 2: present; modes 0, 1: present and not done), the
+// exclusive offsets off[0..W] and, in mode 0, the frontier list in word and
+// bit order with the words marked done - k_frontier_count + scan +
+// k_frontier_write (or k_word_popc + scan) in one launch.
+#define WORDS_SMALL 8192
+__global__ __launch_bounds__(1024) void k_words_small(const SegSP* segs, u32 S, const u32* present, u32* done,
+                                                      u32 W, int mode, u32* off, u32* list_q, u32* list_s,
+                                                      u32* ctr) {
+    __shared__ u32 s_wave[33];
+    const u32 tid = threadIdx.x;
+    u32 carry = 0;
+    for (u32 base = 0; base < W; base += 1024) {
+        const u32 wi = base + tid;
+        u32 f = 0;
+        if (wi < W) f = mode == 2 ? present[wi] : (present[wi] & ~done[wi]);
+        u32 tot;
+        const u32 pre = block_exclusive_scan(__popc(f), s_wave, &tot);
+        if (wi < W) off[wi] = carry + pre;
+        if (mode == 0 && f) {
+            done[wi] |= f;
+            u32 lo = 0, hi = S;  // system of the word: last s with wbase <= wi
+            while (hi - lo > 1) {
+                const u32 mid = (lo + hi) >> 1;
+                if (segs[mid].wbase <= wi)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const u32 i = wi - segs[lo].wbase;
+            u32 pos = carry + pre;
+            while (f) {
+                const u32 b = __ffs(f) - 1;
+                list_q[pos] = i * 32 + b;
+                list_s[pos] = lo;
+                ++pos;
+                f &= f - 1;
+            }
+        }
+        carry += tot;
+    }
+    if (tid == 0) off[W] = carry;
+    if (mode == 0)
+        for (u32 sy = tid; sy < S; sy += 1024) ctr[CTR * sy] = ctr[CTR * sy + 1];
+}
+
 // One reducer per frontier monomial m: the active element with the largest
 // index whose leading monomial divides m; the new row is (m / LM(g), g).
 // Grid (blocks, systems): a system's frontier entries are contiguous in the
@@ -568,17 +614,24 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     const u32 rbx_red = std::max<u32>(1, std::min<u32>(256, ceil_div(ceil_div(max_nmax, MB_THREADS), 1)));
     u32 rounds = 0;
     std::vector<u32> hs(8 * S);
+    const bool small_words = W <= WORDS_SMALL;
     for (;;) {
         if (closure) {
             // two speculative rounds per host check: dense systems converge in two
             for (int k = 0; k < 2; ++k) {
-                hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present, done, (u32)W,
-                                   fcnt.ptr);
-                F4_LAUNCH_CHECK();
-                exclusive_scan_u32(fcnt.ptr, fcnt.ptr, W, c.pool, s);
-                hipLaunchKernelGGL(k_frontier_write, dim3(wbx, S), dim3(256), 0, s, dsegs, present, done,
-                                   fcnt.ptr, list_q.ptr, list_s.ptr, ctr);
-                F4_LAUNCH_CHECK();
+                if (small_words) {
+                    hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 0,
+                                       fcnt.ptr, list_q.ptr, list_s.ptr, ctr);
+                    F4_LAUNCH_CHECK();
+                } else {
+                    hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present, done, (u32)W,
+                                       fcnt.ptr);
+                    F4_LAUNCH_CHECK();
+                    exclusive_scan_u32(fcnt.ptr, fcnt.ptr, W, c.pool, s);
+                    hipLaunchKernelGGL(k_frontier_write, dim3(wbx, S), dim3(256), 0, s, dsegs, present, done,
+                                       fcnt.ptr, list_q.ptr, list_s.ptr, ctr);
+                    F4_LAUNCH_CHECK();
+                }
                 hipLaunchKernelGGL(k_reducers, dim3(rbx_red, S), dim3(MB_THREADS), lds_active ? max_act * 8 : 0, s,
                                    dsegs, list_q.ptr, fcnt.ptr, active, lds_active, rows_t.ptr, rows_k.ptr,
                                    row_lmrank.ptr, ctr);
@@ -586,17 +639,29 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
                 mark();
                 ++rounds;
             }
-            hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present, done, (u32)W,
-                               fcnt.ptr);
-            F4_LAUNCH_CHECK();
-            exclusive_scan_u32(fcnt.ptr, fcnt.ptr, W, c.pool, s);
+            if (small_words) {
+                hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 1,
+                                   fcnt.ptr, list_q.ptr, list_s.ptr, ctr);
+                F4_LAUNCH_CHECK();
+            } else {
+                hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present, done, (u32)W,
+                                   fcnt.ptr);
+                F4_LAUNCH_CHECK();
+                exclusive_scan_u32(fcnt.ptr, fcnt.ptr, W, c.pool, s);
+            }
         } else {
             fill_u32(fcnt.ptr, W + 1, 0, s);
         }
         // dictionary sizes and M alongside the convergence check: one readback
-        hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, present, (u32)W, pcnt.ptr);
-        F4_LAUNCH_CHECK();
-        exclusive_scan_u32(pcnt.ptr, pcnt.ptr, W, c.pool, s);
+        if (small_words) {
+            hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 2,
+                               pcnt.ptr, list_q.ptr, list_s.ptr, ctr);
+            F4_LAUNCH_CHECK();
+        } else {
+            hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, present, (u32)W, pcnt.ptr);
+            F4_LAUNCH_CHECK();
+            exclusive_scan_u32(pcnt.ptr, pcnt.ptr, W, c.pool, s);
+        }
         fill_u64((u64*)Mdev.ptr, S, 0, s);
         hipLaunchKernelGGL(k_sum_len, dim3(bx, S), dim3(256), 0, s, dsegs, rows_k.ptr, ctr, Mdev.ptr);
         F4_LAUNCH_CHECK();

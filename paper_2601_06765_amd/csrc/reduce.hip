@@ -667,6 +667,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         R->b = b;
         R->npr0 = npr;
         R->npr = npr + q;
+        ndone[1 + blockIdx.y] = npr + q;  // pivot rows so far, read back with the done count
         R->cmin = q ? s_pcol[0] : c;
     }
 }
@@ -783,9 +784,6 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
     }
 }
 
-__global__ void k_ech_npr(const EchRound* rounds, u32 S, u32* out) {
-    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) out[s] = rounds[s].npr;
-}
 
 // ------------------------------------------------------------------- emit
 // keys of the pivot rows: (system, leading column); value: store row index
@@ -1114,25 +1112,32 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
     // round records, the done counter and the update-grid bases: one upload
     // (systems with nothing to eliminate are done from the start)
     const size_t rbytes = ((size_t)S * sizeof(EchRound) + 255) & ~(size_t)255;
-    std::vector<u8> pack(rbytes + 256 + (size_t)(S + 1) * 4, 0);
+    const size_t nbytes = (((size_t)S + 1) * 4 + 255) & ~(size_t)255;  // done count, then pivot rows per system
+    std::vector<u8> pack(rbytes + nbytes + (size_t)(S + 1) * 4, 0);
     EchRound* init = (EchRound*)pack.data();
     for (u32 i = 0; i < S; ++i) init[i].done = (X.segs[i].L && X.segs[i].c) ? 0u : 1u;
-    u32* hub = (u32*)(pack.data() + rbytes + 256);
+    u32* hub = (u32*)(pack.data() + rbytes + nbytes);
     for (u32 i = 0; i < S; ++i) hub[i] = X.segs[i].ub;
     hub[S] = UB;
     DBuf<u8> eparams(&c.pool, pack.size());
     EchRound* const rounds = (EchRound*)eparams.ptr;
     u32* const ndone = (u32*)(eparams.ptr + rbytes);
-    u32* const ubp = (u32*)(eparams.ptr + rbytes + 256);
+    u32* const ubp = (u32*)(eparams.ptr + rbytes + nbytes);
     if (active) {
         upload(c, eparams.ptr, pack.data(), pack.size());
         DBuf<u32> status(&c.pool, std::max<u32>(X.Ltot, 1));
         fill_u32(status.ptr, X.Ltot, 0, s);
         const int cnt_lds = (size_t)maxc * 4 + 32768 <= c.dev.max_lds;
         DBuf<u32> cnt(&c.pool, cnt_lds ? 1 : std::max<u64>(X.C, 1));
-        u32 done = 0, r = 0;
-        while (done < active) {
-            for (int k = 0; k < 4; ++k) {
+        // rounds per readback: the first batch from min(L, c) (each round yields
+        // up to ECH_B pivots), later ones four at a time
+        u32 maxlc = 0;
+        for (const SegR& g : X.segs) maxlc = std::max(maxlc, std::min(g.L, g.c));
+        u32 batch = std::min<u32>(8, std::max<u32>(2, ceil_div(maxlc, ECH_B) + 1));
+        std::vector<u32> hd(S + 1, 0);
+        u32 r = 0;
+        while (hd[0] < active) {
+            for (u32 k = 0; k < batch; ++k) {
                 hipEvent_t ka = stage_event(c);
                 hipLaunchKernelGGL(k_ech_block, dim3(1, S), dim3(1024), cnt_lds ? (size_t)maxc * 4 : 0, s,
                                    X.dsegs.ptr, lead.ptr, status.ptr, Dp.ptr, cnt.ptr, cnt_lds, rounds,
@@ -1145,13 +1150,11 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
                 F4_LAUNCH_CHECK();
                 ++r;
             }
-            readback(c, &done, ndone, 4);
+            batch = 4;
+            readback(c, hd.data(), ndone, (S + 1) * 4);
             if (r > CAP + 8 + 4 * (X.Ltot / ECH_B + 1)) throw F4Error{5, "echelon did not converge"};
         }
-        DBuf<u32> dnpr(&c.pool, S);
-        hipLaunchKernelGGL(k_ech_npr, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, rounds, S, dnpr.ptr);
-        F4_LAUNCH_CHECK();
-        readback(c, npr.data(), dnpr.ptr, S * 4);
+        for (u32 i = 0; i < S; ++i) npr[i] = hd[1 + i];
     }
     hipEvent_t e3 = stage_event(c);
 
@@ -1172,10 +1175,9 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
         DBuf<u32> ids(&c.pool, E), cnt(&c.pool, (u64)E + 1);
         u32 maxr = 1;
         for (u32 v : npr) maxr = std::max(maxr, v);
-        DBuf<u32> dnpr(&c.pool, S);
-        upload(c, dnpr.ptr, npr.data(), S * 4);
+        const u32* dnpr = ndone + 1;  // pivot rows per system, on the device since the echelon
         hipLaunchKernelGGL(k_emit_keys, dim3(std::min<u32>(16, ceil_div(maxr, 256)), S), dim3(256), 0, s, X.dsegs.ptr,
-                           dnpr.ptr, debase.ptr, prlead.ptr, cbits, keys.ptr, ids.ptr);
+                           dnpr, debase.ptr, prlead.ptr, cbits, keys.ptr, ids.ptr);
         F4_LAUNCH_CHECK();
         radix_sort_pairs(keys.ptr, ids.ptr, E, 0, cbits + sbits, c.pool, s);
         const u32 kc = S > 1 ? cbits : 64u;
