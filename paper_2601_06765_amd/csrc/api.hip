@@ -537,15 +537,17 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             st.n_k_block = (u32)R.ev_block.size();
             st.block_ops = R.block_ops;
             const auto tg0 = std::chrono::steady_clock::now();
-            for (u32 t = 0; t < P.rho && !S.unit; ++t) {
-                const u32 h = (u32)S.lm.size();
-                S.lm.push_back(newlm[lmbase[i] + t]);
-                S.active.push_back(0);
-                if (deg_of(newlm[lmbase[i] + t]) == 0) {
-                    S.unit = true;
-                    break;
+            // a constant among the new elements ends the computation ({1});
+            // otherwise the step's elements enter the pair set together
+            for (u32 t = 0; t < P.rho; ++t)
+                if (deg_of(newlm[lmbase[i] + t]) == 0) S.unit = true;
+            if (!S.unit && P.rho) {
+                const u32 h0 = (u32)S.lm.size();
+                for (u32 t = 0; t < P.rho; ++t) {
+                    S.lm.push_back(newlm[lmbase[i] + t]);
+                    S.active.push_back(0);
                 }
-                gm_insert(S.mo, S.gm, S.lm, S.active, S.P, h);
+                gm_insert_step(S.mo, S.gm, S.lm, S.active, S.P, h0, h0 + P.rho);
             }
             const auto tg1 = std::chrono::steady_clock::now();
             st.t_pairs_ms = S.tpairs + std::chrono::duration<float, std::milli>(tg1 - tg0).count();

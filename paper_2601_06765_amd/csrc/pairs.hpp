@@ -234,3 +234,127 @@ static void gm_insert(const MonoOps& mo, GmScratch& X, std::vector<u64>& lm, std
     C.push_back(h);
     active[h] = 1;
 }
+
+// All new elements of one F4 step, h0 .. h1-1 in insertion order, with the
+// result of gm_insert on each in turn.  The pairs (h_t, g) are formed per
+// element as there (they depend on the active set at t only); the removal of
+// existing pairs is order-independent (a pair present before the step is
+// removed iff some new LM(h_t) witnesses it; a pair born at t iff some later
+// one does), so it runs once per step over the pair set instead of once per
+// element.
+static void gm_insert_step(const MonoOps& mo, GmScratch& X, std::vector<u64>& lm, std::vector<u8>& active,
+                           std::vector<HPair>& P, u32 h0, u32 h1) {
+    const u32 wmax = 1u << mo.w;
+    for (u32 h = h0; h < h1 && !X.generic; ++h)
+        if (!mo.clean(lm[h]) || (u32)(lm[h] >> 56) >= wmax) X.generic = true;
+    if (X.generic) {
+        for (u32 h = h0; h < h1; ++h) gm_update(mo, lm, active, P, h);
+        return;
+    }
+    const size_t p0 = P.size();
+    std::vector<u32> born;  // insertion index of each pair created in this step
+    std::vector<HPair> keep_old;
+    for (u32 h = h0; h < h1; ++h) {
+        const u64 lh = lm[h];
+        const u32 dh = (u32)(lh >> 56);
+        const u64 lhl = lh & mo.lanes;
+        std::vector<u32>& C = X.act;
+        const size_t nc = C.size();
+        X.L.resize(nc);
+        X.E.resize(nc);
+        X.de.resize(nc);
+        X.cop.resize(nc);
+        X.order.resize(nc);
+        X.cnt.assign(wmax + 1, 0);
+        for (size_t a = 0; a < nc; ++a) {
+            const u64 g = lm[C[a]];
+            const u64 l = mo.lcm_c(lh, g);
+            const u64 e = l - lhl;
+            const u32 d = mo.lane_sum(e);
+            X.L[a] = l | ((u64)(dh + d) << 56);
+            X.E[a] = e;
+            X.de[a] = d;
+            X.cop[a] = d == (u32)(g >> 56);
+            ++X.cnt[d];
+        }
+        for (u32 d = 0, run = 0; d <= wmax; ++d) {
+            const u32 k = X.cnt[d];
+            X.cnt[d] = run;
+            run += k;
+        }
+        for (size_t a = 0; a < nc; ++a) X.order[X.cnt[X.de[a]]++] = (u32)a;
+        X.M.clear();
+        u64 m1 = 0;
+        size_t m2 = 0;
+        bool zero = false;
+        for (size_t o = 0; o < nc; ++o) {
+            const u32 a = X.order[o];
+            const u64 e = X.E[a];
+            const u32 d = X.de[a];
+            if (zero && d >= 1) continue;
+            if (d >= 2 && (mo.nonzero_lanes(e) & m1)) continue;
+            bool cov = false;
+            long eq = -1;
+            for (size_t k = (d >= 2 ? m2 : 0); k < X.M.size(); ++k) {
+                const GmScratch::Min& m = X.M[k];
+                if (m.de < d) {
+                    if (mo.divides_c(m.e, e)) {
+                        cov = true;
+                        break;
+                    }
+                } else if (m.e == e) {
+                    eq = (long)k;
+                    break;
+                }
+            }
+            if (cov) continue;
+            if (eq >= 0) {
+                X.M[eq].a = a;
+                X.M[eq].coprime |= X.cop[a];
+                continue;
+            }
+            X.M.push_back({e, d, a, X.cop[a]});
+            if (d == 0) zero = true;
+            if (d <= 1) {
+                m1 |= mo.nonzero_lanes(e);
+                m2 = X.M.size();
+            }
+        }
+        for (const GmScratch::Min& m : X.M)
+            if (!m.coprime) {
+                P.push_back({C[m.a], h, X.L[m.a]});
+                born.push_back(h - h0);
+            }
+        size_t k = 0;
+        for (size_t a = 0; a < nc; ++a) {
+            const u32 g = C[a];
+            if (mo.divides_c(lh, lm[g]))
+                active[g] = 0;
+            else
+                C[k++] = g;
+        }
+        C.resize(k);
+        C.push_back(h);
+        active[h] = 1;
+    }
+    // removals: a pair is dropped when some new LM(h_t) inserted after it
+    // (all of them for the pairs that predate the step) divides its lcm
+    // without being one of the two lcms it is formed of
+    const u32 nh = h1 - h0;
+    auto witnessed = [&](const HPair& q, u32 from) {
+        const u64 ql = q.lcm & mo.lanes;
+        for (u32 t = from; t < nh; ++t) {
+            const u64 lh = lm[h0 + t];
+            if (mo.divides_c(lh, q.lcm) && mo.lcm_c(lm[q.i], lh) != ql && mo.lcm_c(lh, lm[q.j]) != ql) return true;
+        }
+        return false;
+    };
+    std::vector<HPair>& Pn = X.Pn;
+    Pn.clear();
+    Pn.reserve(P.size());
+    for (size_t a = 0; a < p0; ++a)
+        if (!witnessed(P[a], 0)) Pn.push_back(P[a]);
+    for (size_t a = p0; a < P.size(); ++a)
+        if (!witnessed(P[a], born[a - p0] + 1)) Pn.push_back(P[a]);
+    P.swap(Pn);
+}

@@ -1,7 +1,9 @@
 // Host-only replay of the pair-set updates along a leading-monomial insertion
 // sequence: the generic Gebauer-Moeller update and the fast one run side by
-// side and must hold the same pair set after every insertion; at each step
-// boundary the pairs of least degree are selected and counted.
+// side and must hold the same pair set after every insertion; a third state
+// inserts each step's elements at once (gm_insert_step) and must agree with
+// them at every step boundary; there the pairs of least degree are selected
+// and counted.
 //
 // Input (text): n, then lines "I a_1 .. a_n" (insert an element with this
 // leading monomial) and "S d nsel" (select; expect nsel pairs of degree d).
@@ -43,21 +45,41 @@ int main(int argc, char** argv) {
     std::getline(in, line);
     MonoOps mo;
     mo.init(n);
-    std::vector<u64> lm1, lm2;
-    std::vector<u8> act1, act2;
-    std::vector<HPair> P1, P2;
-    GmScratch X;
+    std::vector<u64> lm1, lm2, lm3;
+    std::vector<u8> act1, act2, act3;
+    std::vector<HPair> P1, P2, P3;
+    GmScratch X, X3;
+    u32 pending = 0;  // elements of the current step not yet given to state 3
+    auto flush3 = [&]() {
+        const u32 h1 = (u32)lm1.size(), h0 = h1 - pending;
+        for (u32 h = h0; h < h1; ++h) {
+            lm3.push_back(lm1[h]);
+            act3.push_back(0);
+        }
+        gm_insert_step(mo, X3, lm3, act3, P3, h0, h1);
+        pending = 0;
+        return as_set(P3) == as_set(P1) && act3 == act1;
+    };
     size_t ins = 0, steps = 0;
     while (std::getline(in, line)) {
         std::istringstream ss(line);
         char kind;
         if (!(ss >> kind)) continue;
         if (kind == 'S') {
-            u32 d, nsel, d1, d2;
-            size_t k1, k2;
+            u32 d, nsel, d1, d2, d3;
+            size_t k1, k2, k3;
             ss >> d >> nsel;
+            if (!flush3()) {
+                printf("FAIL step %zu: the step-batched insertion differs\n", steps);
+                return 1;
+            }
             select_min(P1, d1, k1);
             select_min(P2, d2, k2);
+            select_min(P3, d3, k3);
+            if (k3 != k1 || d3 != d1) {
+                printf("FAIL step %zu: step-batched selection %zu/%u\n", steps, k3, d3);
+                return 1;
+            }
             if (d1 != d || k1 != nsel || d2 != d || k2 != nsel) {
                 printf("FAIL step %zu: expected %u pairs of degree %u, generic %zu/%u, fast %zu/%u\n", steps, nsel, d,
                        k1, d1, k2, d2);
@@ -86,7 +108,12 @@ int main(int argc, char** argv) {
                 return 1;
             }
             ++ins;
+            ++pending;
         }
+    }
+    if (!flush3()) {
+        printf("FAIL final: the step-batched insertion differs\n");
+        return 1;
     }
     printf("OK %zu insertions %zu steps generic=%d\n", ins, steps, (int)X.generic);
     return 0;
