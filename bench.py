@@ -60,17 +60,42 @@ VALU_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 MODMUL_PEAK = VALU_OPS_PER_S / 2
 
 
+KERNEL_HEADS = {
+    "k_ech_block": "__global__ __launch_bounds__(1024) void k_ech_block(",
+    "k_trsm": "__global__ __launch_bounds__(TR_THREADS) void k_trsm(",
+}
+
+
+def kernel_fingerprint(kernel):
+    """SHA-1 of the kernel's source text (its function in csrc/reduce.hip plus
+    csrc/common.hpp): counters taken on another version do not apply."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2601_06765_amd", "csrc")
+    src = open(os.path.join(csrc, "reduce.hip")).read()
+    a = src.index(KERNEL_HEADS[kernel])
+    b = src.index("\n}\n", a)
+    common = open(os.path.join(csrc, "common.hpp")).read()
+    return hashlib.sha1((src[a:b] + common).encode()).hexdigest()
+
+
 def recorded_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/hbm_counters_n10.md), or None when it has none for the kernel."""
+    (profiles/hbm_counters_n10.md), or None when it has none for the kernel
+    or the kernel's source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_counters_n10.md")
+    value, sha = None, None
     try:
         for line in open(path):
-            if line.startswith("traffic_bytes_per_launch") and kernel in line:
-                return float(line.split()[-1])
+            f = line.split()
+            if len(f) == 3 and f[1] == kernel and f[0] == "traffic_bytes_per_launch":
+                value = float(f[2])
+            if len(f) == 3 and f[1] == kernel and f[0] == "kernel_source_sha1":
+                sha = f[2]
     except OSError:
-        pass
-    return None
+        return None
+    if value is None or sha != kernel_fingerprint(kernel):
+        return None
+    return value
 
 
 def roofline_of(allsteps):

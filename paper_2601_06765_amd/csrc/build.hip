@@ -254,22 +254,42 @@ __global__ __launch_bounds__(MB_THREADS) void k_reducers(const SegSP* segs, cons
         for (u32 a = threadIdx.x; a < S.nactive; a += MB_THREADS) slm[a] = S.lm[act[a]];
         __syncthreads();
     }
+    // lane-parallel divisibility (valid while every exponent is below 2^(w-1))
+    const u32 n = S.n, w = S.w, lane = lane_id();
+    u64 H = 0;
+    for (u32 i = 0; i < n; ++i) H |= 1ull << (w * i + w - 1);
+    const u64 lanes = (n * w >= 64) ? ~0ull : ((1ull << (n * w)) - 1);
+    // one wave per frontier monomial, lanes over the active list (descending
+    // index): the first divisor in list order is the reducer (largest index)
     const u32 f0 = fscan[S.wbase], f1 = fscan[S.wbase + S.nwords];
-    for (u32 i = f0 + blockIdx.x * MB_THREADS + threadIdx.x; i < f1; i += gridDim.x * MB_THREADS) {
+    const u32 nwaves = gridDim.x * MB_WAVES;
+    for (u32 i = f0 + blockIdx.x * MB_WAVES + threadIdx.x / F4_WAVE; i < f1; i += nwaves) {
         const u32 q = list_q[i];
         const u64 m = S.montab[q];
-        for (u32 a = 0; a < S.nactive; ++a) {
-            const u64 l = lds_active ? slm[a] : S.lm[act[a]];
-            if (mono_divides(l, m, S.n, S.w)) {
-                const u32 slot = atomicAdd(&ctr[CTR * s + 1], 1u);
-                if (slot >= S.rcap) {
-                    ctr[CTR * s + 3] = 2u;
-                    break;
-                }
-                rows_t[S.rbase + slot] = m - l;
-                rows_k[S.rbase + slot] = act[a];
-                row_lmrank[S.rbase + slot] = q;
+        const bool mclean = (m & H) == 0;
+        u32 found = 0xffffffffu;
+        for (u32 a0 = 0; a0 < S.nactive; a0 += F4_WAVE) {
+            const u32 a = a0 + lane;
+            bool d = false;
+            if (a < S.nactive) {
+                const u64 l = lds_active ? slm[a] : S.lm[act[a]];
+                d = (mclean && !(l & H)) ? (((((m & lanes) | H) - (l & lanes)) & H) == H) : mono_divides(l, m, n, w);
+            }
+            const u64 hit = wave_ballot(d);
+            if (hit) {
+                found = a0 + __ffsll((long long)hit) - 1;
                 break;
+            }
+        }
+        if (found != 0xffffffffu && lane == 0) {
+            const u64 l = lds_active ? slm[found] : S.lm[act[found]];
+            const u32 slot = atomicAdd(&ctr[CTR * s + 1], 1u);
+            if (slot >= S.rcap) {
+                ctr[CTR * s + 3] = 2u;
+            } else {
+                rows_t[S.rbase + slot] = m - l;
+                rows_k[S.rbase + slot] = act[found];
+                row_lmrank[S.rbase + slot] = q;
             }
         }
     }
@@ -611,7 +631,10 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     u32 max_act = 0;
     for (u32 i = 0; i < S; ++i) max_act = std::max(max_act, segs[i].nactive);
     const int lds_active = (size_t)max_act * 8 <= 64 * 1024;
-    const u32 rbx_red = std::max<u32>(1, std::min<u32>(256, ceil_div(ceil_div(max_nmax, MB_THREADS), 1)));
+    // reducer search: a wave per frontier monomial, about four per wave at the
+    // largest frontier, at most 4096 workgroups over the batch
+    const u32 rbx_red = std::max<u32>(1, std::min<u32>(std::max<u32>(4, 4096 / std::max<u32>(S, 1)),
+                                                       ceil_div(max_nmax, MB_WAVES * 4)));
     u32 rounds = 0;
     std::vector<u32> hs(8 * S);
     const bool small_words = W <= WORDS_SMALL;

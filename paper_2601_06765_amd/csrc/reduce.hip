@@ -465,6 +465,7 @@ struct EchRound {
 // of the round.
 #define ECH_CH 32
 #define ECH_W (ECH_CH + ECH_B)  // row width of [chunk | Z]: one lane per column
+#define ECH_RS (ECH_W + 1)      // LDS row stride: a column of the rows spans all banks
 
 template <bool SMALL>
 __device__ __forceinline__ u32 fp_mul_t(const Fp& f, u32 a, u32 b) {
@@ -484,7 +485,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     extern __shared__ u32 scnt[];
     __shared__ u32 s_wave[33];
     __shared__ u32 s_rows[ECH_B];
-    __shared__ u32 s_RZ[ECH_B * ECH_W];
+    __shared__ u32 s_RZ[ECH_B * ECH_RS];
     __shared__ u32 s_B[ECH_B * ECH_CH];
     __shared__ u32 s_pcol[ECH_B], s_prow[ECH_B], s_pv[ECH_B], s_inv[ECH_B];
     __shared__ u64 s_nz[3];
@@ -554,8 +555,8 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     }
     static_assert(ECH_W == F4_WAVE && ECH_B * ECH_CH == 1024 && 2 * 16 == ECH_B, "echelon block layout");
     for (u32 x = tid; x < ECH_B * ECH_W; x += 1024) {
-        const u32 k = x / ECH_W, j = x % ECH_W;
-        s_RZ[x] = (j >= ECH_CH && j - ECH_CH == k) ? 1u : 0u;
+        const u32 k = x / ECH_W, j = x % ECH_W;  // element (k, j) lives at k * ECH_RS + j
+        s_RZ[k * ECH_RS + j] = (j >= ECH_CH && j - ECH_CH == k) ? 1u : 0u;
     }
     if (tid < 3) s_nz[tid] = 0;
     __syncthreads();
@@ -579,13 +580,13 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
             if (q && k < b) {
                 u64 acc = 0;
                 for (u32 u = 0; u < b; ++u) {
-                    const u32 z = s_RZ[k * ECH_W + ECH_CH + u];
+                    const u32 z = s_RZ[k * ECH_RS + ECH_CH + u];
                     if (z) acc += small ? (u64)z * s_B[u * ECH_CH + j] : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
                 }
                 v = fp_reduce_any(f, acc);
                 if (j == 0) nops += (u64)b * ECH_CH;  // the row's products, counted once
             }
-            s_RZ[k * ECH_W + j] = v;
+            s_RZ[k * ECH_RS + j] = v;
         }
         __syncthreads();
         // columns where a non-pivot row is nonzero, merged over the waves into
@@ -595,8 +596,8 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         u32 jstart = 0;
         {
             bool nz = false;
-            if (r0 < b && !((pmask >> r0) & 1u)) nz |= s_RZ[r0 * ECH_W + lane] != 0;
-            if (r1 < b && !((pmask >> r1) & 1u)) nz |= s_RZ[r1 * ECH_W + lane] != 0;
+            if (r0 < b && !((pmask >> r0) & 1u)) nz |= s_RZ[r0 * ECH_RS + lane] != 0;
+            if (r1 < b && !((pmask >> r1) & 1u)) nz |= s_RZ[r1 * ECH_RS + lane] != 0;
             const u64 m = wave_ballot(nz && lane < w);
             if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[it % 3], (unsigned long long)m);
         }
@@ -609,21 +610,21 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
             // pivot row: the first non-pivot row nonzero at jp (row kp and the
             // rows before it do not change in this step, so every wave agrees
             // while the others update their rows)
-            const u32 cand = (lane < b && !((pmask >> lane) & 1u)) ? s_RZ[lane * ECH_W + jp] : 0u;
+            const u32 cand = (lane < b && !((pmask >> lane) & 1u)) ? s_RZ[lane * ECH_RS + jp] : 0u;
             const u32 kp = __ffsll((long long)wave_ballot(cand != 0)) - 1;
-            const u32 piv = s_RZ[kp * ECH_W + jp];
-            const u32 prow = s_RZ[kp * ECH_W + lane];
+            const u32 piv = s_RZ[kp * ECH_RS + jp];
+            const u32 prow = s_RZ[kp * ECH_RS + lane];
             const u32 pm2 = pmask | (1u << kp);
             bool nz = false;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const u32 r = h ? r1 : r0;
                 if (r >= b || r == kp) continue;
-                const u32 fk = s_RZ[r * ECH_W + jp];
-                u32 val = s_RZ[r * ECH_W + lane];
+                const u32 fk = s_RZ[r * ECH_RS + jp];
+                u32 val = s_RZ[r * ECH_RS + lane];
                 if (fk) {
                     val = small ? fp_ff<true>(f, piv, val, fk, prow) : fp_ff<false>(f, piv, val, fk, prow);
-                    s_RZ[r * ECH_W + lane] = val;
+                    s_RZ[r * ECH_RS + lane] = val;
                     if (lane == 0) nops += 2 * ECH_W;
                     if (lane == 0 && ((pmask >> r) & 1u)) s_pv[r] = fp_mul(f, s_pv[r], piv);
                 }
@@ -654,7 +655,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     }
     for (u32 x = tid; x < q * ECH_B; x += 1024) {
         const u32 t = x / ECH_B, u = x % ECH_B;
-        R->Z[t * ECH_B + u] = u < b ? fp_mul(f, s_RZ[s_prow[t] * ECH_W + ECH_CH + u], s_inv[t]) : 0u;
+        R->Z[t * ECH_B + u] = u < b ? fp_mul(f, s_RZ[s_prow[t] * ECH_RS + ECH_CH + u], s_inv[t]) : 0u;
     }
     if (tid < b) {
         R->rows[tid] = s_rows[tid];
