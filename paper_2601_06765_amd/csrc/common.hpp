@@ -31,7 +31,8 @@ struct Fp {
     u32 mu;  // floor(2^(2s) / p)  (< 2^32 for odd p)
     u32 mu32; // floor(2^32 / p): single-word Barrett for any x < 2^32
     u32 r32;  // 2^32 mod p
-    float finv;  // 1/p rounded to float (quotient estimate for p < 2^16)
+    float finv;   // 1/p rounded to float (quotient estimate for p < 2^16)
+    double dinv;  // 1/p rounded to double (quotient estimate in double arithmetic)
 };
 
 static inline Fp make_fp(u32 p) {
@@ -44,6 +45,7 @@ static inline Fp make_fp(u32 p) {
     f.mu32 = (u32)((1ull << 32) / p);
     f.r32 = (u32)((1ull << 32) % p);
     f.finv = 1.0f / (float)p;
+    f.dinv = 1.0 / (double)p;
     return f;
 }
 

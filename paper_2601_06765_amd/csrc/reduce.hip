@@ -478,6 +478,18 @@ __device__ __forceinline__ u32 fp_ff(const Fp& f, u32 piv, u32 a, u32 fk, u32 b)
     const u32 x = fp_mul_t<SMALL>(f, piv, a), y = fp_mul_t<SMALL>(f, fk, b);
     return x >= y ? x - y : x + f.p - y;
 }
+// p < 2^16: piv * a - fk * b is an integer below 2^32 in magnitude, exact in
+// double (full-rate fma); the quotient estimate floor(t / p) from the rounded
+// 1/p is off by at most one, so the remainder needs two corrections
+template <>
+__device__ __forceinline__ u32 fp_ff<true>(const Fp& f, u32 piv, u32 a, u32 fk, u32 b) {
+    const double pd = (double)f.p;
+    const double t = fma((double)piv, (double)a, -((double)fk * (double)b));
+    double r = fma(-floor(t * f.dinv), pd, t);
+    r = r < 0.0 ? r + pd : r;
+    r = r >= pd ? r - pd : r;
+    return (u32)r;
+}
 
 __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead, u32* status, const u32* Dp,
                                                     u32* cnt_g, int cnt_lds, EchRound* rounds, u32* prlead,
@@ -581,7 +593,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
                 u64 acc = 0;
                 for (u32 u = 0; u < b; ++u) {
                     const u32 z = s_RZ[k * ECH_RS + ECH_CH + u];
-                    if (z) acc += small ? (u64)z * s_B[u * ECH_CH + j] : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
+                    if (z) acc += small ? (u64)mul24(z, s_B[u * ECH_CH + j]) : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
                 }
                 v = fp_reduce_any(f, acc);
                 if (j == 0) nops += (u64)b * ECH_CH;  // the row's products, counted once
@@ -727,7 +739,7 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
                     const u32 z = s_w[v];
                     if (z) {
                         const u32 x = D[(u64)s_rows[v] * c + j];
-                        acc += small ? (u64)z * x : (u64)fp_mul(f, z, x);
+                        acc += small ? (u64)mul24(z, x) : (u64)fp_mul(f, z, x);
                     }
                 }
                 row[j] = fp_reduce_any(f, acc);
@@ -754,7 +766,7 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
             const u32 cf = s_coef[t];
             if (cf) {
                 const u32 z = R->Z[t * ECH_B + tid];
-                acc += small ? (u64)cf * z : (u64)fp_mul(f, cf, z);
+                acc += small ? (u64)mul24(cf, z) : (u64)fp_mul(f, cf, z);
             }
         }
         s_w[tid] = fp_reduce_any(f, acc);
@@ -768,7 +780,7 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
             const u32 w = s_w[v];
             if (w) {
                 const u32 x = D[(u64)s_rows[v] * c + j];
-                acc += small ? (u64)w * x : (u64)fp_mul(f, w, x);
+                acc += small ? (u64)mul24(w, x) : (u64)fp_mul(f, w, x);
             }
         }
         const u32 sub = fp_reduce_any(f, acc);
