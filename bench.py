@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--batch-systems", type=int, default=256, help="systems in the batched leg (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg (0: skip)")
     ap.add_argument("--sparse-repeats", type=int, default=3, help="timed runs of the n=14 sparse step (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="fixed schedules instead of the autotuner's measured picks (tuned during warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (reference kernel for HBM byte counters)")
     return ap.parse_args()
@@ -139,15 +141,15 @@ def cpu_baseline(n, p, polys, seconds):
             "sample": "%d full F4 run(s) of the same n=10 m=12 system, single thread, %.1f s" % (runs, dt)}
 
 
-def sparse_step_leg(f4, repeats):
+def sparse_step_leg(f4, repeats, autotune):
     """Workload 3: 15 sparse quadratics in n=14 over F_(2^31-1) (20 monomials
     each, seed 3); F4 on the GPU up to and including the first step of degree
     5, whose preprocessing (DictBuild + RowAssemble) and elimination
     (NumericCore) are reported separately."""
     import synth
     n, p, polys = synth.config_system(3)
-    ctx = f4.Context(0, timing=True, stop_deg=5)
-    ctx.groebner(p, n, polys)  # warm-up
+    ctx = f4.Context(0, timing=True, stop_deg=5, autotune=autotune)
+    ctx.groebner(p, n, polys)  # warm-up (and tuning)
     runs = []
     for _ in range(repeats):
         t0 = time.perf_counter()
@@ -265,7 +267,8 @@ def main():
     torch.cuda.init()
     n, p, polys = synth.config_system(2)
     # the headline: the timed runs without instrumentation
-    plain = f4.Context(0, dict_path=args.dict)
+    tune = not args.no_autotune
+    plain = f4.Context(0, dict_path=args.dict, autotune=tune)
     for _ in range(args.warmup):
         plain.groebner(p, n, polys)
     torch.cuda.synchronize()
@@ -274,11 +277,13 @@ def main():
         basis, _ = plain.groebner(p, n, polys)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    table = plain.tune_table()
     plain.close()
     assert basis == [[((0,) * n, 1)]], "unexpected basis"
     # the same runs again with HIP events around every stage and around each
     # launch of the two elimination kernels (stage times, roofline)
-    ctx = f4.Context(0, timing=True, dict_path=args.dict)
+    ctx = f4.Context(0, timing=True, dict_path=args.dict, autotune=tune)
+    ctx.load_tune_table(table)  # the headline runs' schedules
     for _ in range(args.warmup):
         ctx.groebner(p, n, polys)
     torch.cuda.synchronize()
@@ -344,17 +349,22 @@ def main():
         "systems_per_s_plain": args.steps / dt,
         "per_f4_step": per_step,
         "roofline": out_roof,
+        "autotune": {"on": tune, "table": table.splitlines()},
     }
+    ctx.close()
     if args.sparse_repeats:
-        out["sparse_step"] = sparse_step_leg(f4, args.sparse_repeats)
+        out["sparse_step"] = sparse_step_leg(f4, args.sparse_repeats, tune)
     if args.batch_systems:
-        out["batch"] = batch_leg(ctx, args.batch_systems)
+        bctx = f4.Context(0, autotune=tune)
+        out["batch"] = batch_leg(bctx, args.batch_systems)
+        bctx.close()
         out["systems_per_s_batched"] = out["batch"]["systems_per_s_batched"]
     if args.serve_seconds > 0:
-        out["serve"] = serve_leg(f4, f4.Context(0), args.serve_seconds)
+        sctx = f4.Context(0, autotune=tune)
+        out["serve"] = serve_leg(f4, sctx, args.serve_seconds)
+        sctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, p, polys, args.cpu_seconds)
-    ctx.close()
     print(json.dumps(out))
 
 

@@ -67,7 +67,8 @@ typedef struct f4_basis f4_basis;
 enum {
     F4_OPT_TIMING = 1u << 0,     /* record per-stage HIP-event timings in f4_step_stats */
     F4_OPT_DICT_RANK = 1u << 1,  /* force the dense-rank dictionary (bitmap sort/unique) */
-    F4_OPT_DICT_RADIX = 1u << 2  /* force the radix-sort dictionary (sort + unique + join) */
+    F4_OPT_DICT_RADIX = 1u << 2, /* force the radix-sort dictionary (sort + unique + join) */
+    F4_OPT_AUTOTUNE = 1u << 3    /* pick schedules by measurement (see f4_tune_export) */
 };
 typedef struct f4_opts {
     uint32_t flags;
@@ -76,6 +77,12 @@ typedef struct f4_opts {
      * the returned basis of such a system is empty) - for timing one step of
      * a system at its real shape. */
     uint32_t stop_deg;
+    /* 0: tuned or default.  1..4: rows of D' per workgroup tile of the sparse
+     * triangular solve (capped by what the LDS holds).  Schedules never change
+     * results. */
+    uint32_t trsm_rows;
+    /* 0: tuned or default (8).  1..8: bits per digit pass of the radix sorts. */
+    uint32_t radix_bits;
 } f4_opts;
 
 /* Create a context on HIP device `device` (opts may be NULL).  The context owns
@@ -84,6 +91,27 @@ int f4_create(f4_ctx** out, int device, const f4_opts* opts);
 int f4_destroy(f4_ctx* ctx);
 /* Text of the last error on this context (static storage owned by the context). */
 const char* f4_last_error(const f4_ctx* ctx);
+/* Autotuner (F4_OPT_AUTOTUNE).  The paper leaves the schedule of its bulk
+ * primitives open (section "Batching, scheduling, and GPU/accelerator
+ * considerations": tile sizes and radix passes are tuning choices); with the
+ * option set, the first call that meets an (operation, shape bucket) times
+ * every candidate schedule on its live data with HIP events (best of two runs)
+ * and keeps the fastest in the context's table; later calls reuse it.  Tuned
+ * operations: the sparse triangular solve (rows per tile, 1..4) and the radix
+ * sorts of more than 8 key bits (digit width 5..8, keys per thread 8 or 16).
+ * All candidates compute identical outputs.
+ *
+ * f4_tune_export writes the table as text, one entry per line:
+ *   "trsm <small p> <lg2 rows> <lg2 N> <rows per tile>"
+ *   "sort <with values> <lg2 n> <key bits> <digit bits> <keys per thread>"
+ * *len receives the text length (without the terminating NUL).  buf == NULL
+ * is a size query; otherwise the text and a NUL are copied when cap > *len,
+ * and F4_E_RANGE is returned (nothing copied) when the buffer is too small.
+ * f4_tune_import merges such text into the table (entries are used by later
+ * calls when they are valid for the shape at hand, otherwise re-tuned); a
+ * malformed line gives F4_E_ARG and leaves the table unchanged. */
+int f4_tune_export(f4_ctx* ctx, char* buf, size_t cap, size_t* len);
+int f4_tune_import(f4_ctx* ctx, const char* text);
 /* Copy `bytes` from device memory (e.g. a view pointer) to host memory `dst`
  * on the context's current stream and wait for it. */
 int f4_download(f4_ctx* ctx, void* dst, const void* src, size_t bytes);

@@ -693,6 +693,11 @@ int f4_create(f4_ctx** out, int device, const f4_opts* opts) {
         X->c.dev.max_lds = prop.sharedMemPerBlock;
         X->c.flags = opts ? opts->flags : 0;
         X->c.stop_deg = opts ? opts->stop_deg : 0;
+        X->c.tune.on = (X->c.flags & F4_OPT_AUTOTUNE) != 0;
+        X->c.tune.force_rr = opts ? opts->trsm_rows : 0;
+        X->c.tune.force_digit = opts ? opts->radix_bits : 0;
+        if (X->c.tune.force_rr > 4 || X->c.tune.force_digit > 8)
+            throw F4Error{F4_E_ARG, "trsm_rows must be at most 4 and radix_bits at most 8"};
         F4_HIP_TRY(hipStreamCreateWithFlags(&X->c.own_stream, hipStreamNonBlocking));
         X->c.stream = X->c.own_stream;
         F4_HIP_TRY(hipEventCreateWithFlags(&X->c.staging_done, hipEventDisableTiming));
@@ -731,6 +736,25 @@ int f4_destroy(f4_ctx* X) {
 }
 
 const char* f4_last_error(const f4_ctx* X) { return X ? X->c.last_error.c_str() : "null context"; }
+
+int f4_tune_export(f4_ctx* X, char* buf, size_t cap, size_t* len) {
+    F4_API_BEGIN(X)
+    if (!len) throw F4Error{F4_E_ARG, "null length pointer"};
+    const std::string t = tune_text(X->c);
+    *len = t.size();
+    if (buf) {
+        if (cap <= t.size()) throw F4Error{F4_E_RANGE, "tune table: buffer too small"};
+        memcpy(buf, t.c_str(), t.size() + 1);
+    }
+    F4_API_END(X)
+}
+
+int f4_tune_import(f4_ctx* X, const char* text) {
+    F4_API_BEGIN(X)
+    if (!text) throw F4Error{F4_E_ARG, "null text"};
+    tune_parse(X->c, text);
+    F4_API_END(X)
+}
 
 uint32_t f4_lane_bits(uint32_t n) { return lane_bits(n); }
 

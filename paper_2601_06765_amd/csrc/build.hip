@@ -747,7 +747,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     hipLaunchKernelGGL(k_row_keys, dim3(rbx, S), dim3(256), 0, s, dsegs, row_lmrank.ptr, rows_k.ptr, sshift, kbits,
                        keys.ptr, perm.ptr);
     F4_LAUNCH_CHECK();
-    radix_sort_pairs(keys.ptr, perm.ptr, R, 0, sshift + sbits, c.pool, s);
+    tuned_sort(c, keys.ptr, perm.ptr, R, 0, sshift + sbits);
     out.row_t.reset(&c.pool, R);
     out.row_k.reset(&c.pool, R);
     out.row_sys.reset(&c.pool, R);
@@ -779,7 +779,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
                            out.row_ptr.ptr, kshift, row_key.ptr, out.val.ptr);
         F4_LAUNCH_CHECK();
         F4_HIP_TRY(hipMemcpyAsync(cand.ptr, row_key.ptr, Mtot * 8, hipMemcpyDeviceToDevice, s));
-        radix_sort_keys(cand.ptr, Mtot, 0, kb + sbits, c.pool, s);
+        tuned_sort(c, cand.ptr, nullptr, Mtot, 0, kb + sbits);
         DBuf<u32> ncount(&c.pool, 1), dstart(&c.pool, S + 1);
         unique_sorted_u64(cand.ptr, Mtot, dictc.ptr, ncount.ptr, c.pool, s);
         hipLaunchKernelGGL(k_seg_bounds, dim3(grid_for(S + 1, 256, 64)), dim3(256), 0, s, dictc.ptr, ncount.ptr, S,

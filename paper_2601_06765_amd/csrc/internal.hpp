@@ -1,6 +1,7 @@
 // Internal host-side interfaces shared by the library's translation units.
 #pragma once
 
+#include <functional>
 #include <map>
 #include <unordered_map>
 #include <vector>
@@ -120,11 +121,20 @@ void fill_u64(u64* p, u64 n, u64 v, hipStream_t s);
 // Exclusive scan of n u32 values into out (may alias in); out[n] = total.
 // out must have room for n + 1 values.
 void exclusive_scan_u32(const u32* in, u32* out, u64 n, Pool& pool, hipStream_t s);
+// Schedule of an LSD radix sort: bits per digit pass (1..8) and keys per
+// thread in a tile of the multi-workgroup passes (sorts of at most
+// SORT_SMALL_MAX keys run in one workgroup and use the digit width only).
+struct SortPlan {
+    u32 digit = 8, items = 16;
+};
+#define SORT_SMALL_MAX 5120
 // Stable LSD radix sort of (key, val) pairs on key bits [lo_bit, hi_bit).
 // keys/vals hold the input and receive the output; tmp buffers come from pool.
-void radix_sort_pairs(u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s);
+void radix_sort_pairs(u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s,
+                      SortPlan plan = SortPlan());
 // Sort keys only (vals unused)
-void radix_sort_keys(u64* keys, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s);
+void radix_sort_keys(u64* keys, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s,
+                     SortPlan plan = SortPlan());
 // Unique of sorted keys: writes distinct keys to out, count to *d_count (device).
 void unique_sorted_u64(const u64* keys, u64 n, u64* out, u32* d_count, Pool& pool, hipStream_t s);
 
@@ -159,7 +169,36 @@ struct Ctx {
     // timing events (F4_OPT_TIMING)
     std::vector<hipEvent_t> events;
     u32 ev_used = 0;
+    // autotuner (F4_OPT_AUTOTUNE): the measured choice per (operation, shape
+    // bucket); a forced value (nonzero) overrides both the table and the rule
+    struct Tuner {
+        bool on = false;
+        u32 force_rr = 0, force_digit = 0;
+        std::map<u64, u32> table;
+    } tune;
 };
+
+// ------------------------------------------------------------- autotuner
+// (tune.hip)  Operations with a tuned schedule; every candidate computes the
+// same result, so a choice changes time only.
+enum TuneOp : u32 { TUNE_TRSM = 1, TUNE_SORT = 2 };
+// Table key of an operation and its shape bucket (three 16-bit fields).
+u64 tune_key(TuneOp op, u32 a, u32 b, u32 c);
+// ceil(log2(x)) (0 for x <= 1): shape buckets are powers of two.
+u32 tune_lg(u64 x);
+// The tuned choice for `key`: the table entry when it is one of `cands`, else
+// every candidate is run (`prep` then `run`, `prep` outside the timed region)
+// twice on the live data, the fastest (by HIP events, best of two) is stored
+// and returned.  Waits for the context stream while measuring.
+u32 tune_pick(Ctx& c, u64 key, const std::vector<u32>& cands, const std::function<void(u32)>& prep,
+              const std::function<void(u32)>& run);
+// Radix sort with the context's schedule: a forced digit width, else the
+// tuned plan (autotuner on and more than 8 key bits), else the default plan.
+void tuned_sort(Ctx& c, u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit);
+// Text form of the tuning table (one line per entry) and its parser, which
+// merges well-formed entries into the table and throws on anything else.
+std::string tune_text(const Ctx& c);
+void tune_parse(Ctx& c, const char* text);
 
 // Next free region (>= bytes) of the pinned arena; waits for the copies in
 // flight only when the arena has to wrap around.

@@ -114,39 +114,39 @@ void exclusive_scan_u32(const u32* in, u32* out, u64 n, Pool& pool, hipStream_t 
 
 // ------------------------------------------------------------- radix sort
 #define RS_THREADS 256
-#define RS_ITEMS 16
-#define RS_TILE (RS_THREADS * RS_ITEMS)
 #define RS_WAVES (RS_THREADS / F4_WAVE)
 
-__global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const u64* keys, u64 n, u32 shift, u32 mask, u32* hist,
-                                                            u32 nblocks) {
+// Digit counts of a tile of RS_THREADS * items keys; hist is digit-major
+// (digit d of tile b at d * nblocks + b) over the mask + 1 digits.
+__global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const u64* keys, u64 n, u32 shift, u32 mask, u32 items,
+                                                            u32* hist, u32 nblocks) {
     __shared__ u32 h[256];
-    for (u32 i = threadIdx.x; i < 256; i += RS_THREADS) h[i] = 0;
+    for (u32 i = threadIdx.x; i <= mask; i += RS_THREADS) h[i] = 0;
     __syncthreads();
-    u64 base = (u64)blockIdx.x * RS_TILE;
+    u64 base = (u64)blockIdx.x * RS_THREADS * items;
 #pragma unroll 4
-    for (int j = 0; j < RS_ITEMS; ++j) {
+    for (u32 j = 0; j < items; ++j) {
         u64 i = base + (u64)j * RS_THREADS + threadIdx.x;
         if (i < n) atomicAdd(&h[(u32)(keys[i] >> shift) & mask], 1u);
     }
     __syncthreads();
-    for (u32 d = threadIdx.x; d < 256; d += RS_THREADS) hist[(u64)d * nblocks + blockIdx.x] = h[d];
+    for (u32 d = threadIdx.x; d <= mask; d += RS_THREADS) hist[(u64)d * nblocks + blockIdx.x] = h[d];
 }
 
-// Scatter with stable ranks.  A tile is consumed in RS_ITEMS sub-rounds of
+// Scatter with stable ranks.  A tile is consumed in `items` sub-rounds of
 // RS_THREADS consecutive keys; inside a wave, lanes holding the same digit are
 // found with 8 ballots (one per digit bit), which gives each key its rank among
 // equal digits of lower lanes; per-wave digit counts in LDS order the waves.
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const u64* kin, const u32* vin, u64* kout, u32* vout,
-                                                               u64 n, u32 shift, u32 mask, const u32* offs,
-                                                               u32 nblocks) {
+                                                               u64 n, u32 shift, u32 mask, u32 items,
+                                                               const u32* offs, u32 nblocks) {
     __shared__ u32 run[256];
     __shared__ u32 wcnt[RS_WAVES][256];
     const u32 tid = threadIdx.x, wave = tid / F4_WAVE, lane = lane_id();
-    for (u32 d = tid; d < 256; d += RS_THREADS) run[d] = offs[(u64)d * nblocks + blockIdx.x];
-    const u64 base = (u64)blockIdx.x * RS_TILE;
+    for (u32 d = tid; d <= mask; d += RS_THREADS) run[d] = offs[(u64)d * nblocks + blockIdx.x];
+    const u64 base = (u64)blockIdx.x * RS_THREADS * items;
     const u64 lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    for (int j = 0; j < RS_ITEMS; ++j) {
+    for (u32 j = 0; j < items; ++j) {
         for (u32 q = tid; q < RS_WAVES * 256; q += RS_THREADS) (&wcnt[0][0])[q] = 0;
         __syncthreads();
         const u64 i = base + (u64)j * RS_THREADS + tid;
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const u64* kin, co
             if (vout) vout[pos] = vin[i];
         }
         __syncthreads();
-        for (u32 dd = tid; dd < 256; dd += RS_THREADS) {
+        for (u32 dd = tid; dd <= mask; dd += RS_THREADS) {
             u32 t = 0;
             for (u32 w2 = 0; w2 < RS_WAVES; ++w2) t += wcnt[w2][dd];
             run[dd] += t;
@@ -181,12 +181,13 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const u64* kin, co
 
 // Sorts of at most SS_MAX pairs in one workgroup: keys and values stay in LDS
 // (double buffered) for every digit pass; each pass is a digit histogram, a
-// scan of the 256 counts, then the keys in order in sub-rounds of SS_THREADS
+// scan of the digit counts, then the keys in order in sub-rounds of SS_THREADS
 // with the same stable in-wave ranks (8 ballots) as k_radix_scatter.
 #define SS_THREADS 1024
 #define SS_WAVES (SS_THREADS / F4_WAVE)
-#define SS_MAX 5120
-__global__ __launch_bounds__(SS_THREADS) void k_sort_small(u64* keys, u32* vals, u32 n, u32 lo_bit, u32 hi_bit) {
+#define SS_MAX SORT_SMALL_MAX
+__global__ __launch_bounds__(SS_THREADS) void k_sort_small(u64* keys, u32* vals, u32 n, u32 lo_bit, u32 hi_bit,
+                                                           u32 digit) {
     extern __shared__ u64 ss_mem[];
     u64* ka = ss_mem;
     u64* kb = ka + SS_MAX;
@@ -201,8 +202,8 @@ __global__ __launch_bounds__(SS_THREADS) void k_sort_small(u64* keys, u32* vals,
         ka[i] = keys[i];
         if (vals) va[i] = vals[i];
     }
-    for (u32 shift = lo_bit; shift < hi_bit; shift += 8) {
-        const u32 bits = (hi_bit - shift) < 8 ? (hi_bit - shift) : 8;
+    for (u32 shift = lo_bit; shift < hi_bit; shift += digit) {
+        const u32 bits = (hi_bit - shift) < digit ? (hi_bit - shift) : digit;
         const u32 mask = (1u << bits) - 1;
         if (tid < 256) run[tid] = 0;
         __syncthreads();
@@ -259,29 +260,35 @@ __global__ __launch_bounds__(SS_THREADS) void k_sort_small(u64* keys, u32* vals,
     }
 }
 
-static void radix_sort_impl(u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s) {
+static void radix_sort_impl(u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s,
+                            SortPlan plan) {
     if (n <= 1 || hi_bit <= lo_bit) return;
+    if (plan.digit < 1 || plan.digit > 8 || plan.items < 1 || plan.items > 64)
+        throw F4Error{1, "radix sort plan out of range"};
+    const u32 digit = plan.digit;
     if (n <= SS_MAX) {
         const size_t lds = (size_t)SS_MAX * (2 * sizeof(u64) + 2 * sizeof(u32));
-        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(SS_THREADS), lds, s, keys, vals, (u32)n, lo_bit, hi_bit);
+        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(SS_THREADS), lds, s, keys, vals, (u32)n, lo_bit, hi_bit,
+                           digit);
         F4_LAUNCH_CHECK();
         return;
     }
-    const u32 nblocks = ceil_div(n, RS_TILE);
+    const u32 nblocks = ceil_div(n, (u64)RS_THREADS * plan.items);
     DBuf<u64> k2(&pool, n);
     DBuf<u32> v2;
     if (vals) v2.reset(&pool, n);
-    DBuf<u32> hist(&pool, (u64)256 * nblocks + 1);
+    DBuf<u32> hist(&pool, ((u64)1 << digit) * nblocks + 1);
     u64 *ka = keys, *kb = k2.ptr;
     u32 *va = vals, *vb = v2.ptr;
-    for (u32 shift = lo_bit; shift < hi_bit; shift += 8) {
-        const u32 bits = (hi_bit - shift) < 8 ? (hi_bit - shift) : 8;
+    for (u32 shift = lo_bit; shift < hi_bit; shift += digit) {
+        const u32 bits = (hi_bit - shift) < digit ? (hi_bit - shift) : digit;
         const u32 mask = (1u << bits) - 1;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(RS_THREADS), 0, s, ka, n, shift, mask, hist.ptr, nblocks);
-        F4_LAUNCH_CHECK();
-        exclusive_scan_u32(hist.ptr, hist.ptr, (u64)256 * nblocks, pool, s);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, ka, va, kb, vb, n, shift, mask,
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(RS_THREADS), 0, s, ka, n, shift, mask, plan.items,
                            hist.ptr, nblocks);
+        F4_LAUNCH_CHECK();
+        exclusive_scan_u32(hist.ptr, hist.ptr, ((u64)mask + 1) * nblocks, pool, s);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, ka, va, kb, vb, n, shift, mask,
+                           plan.items, hist.ptr, nblocks);
         F4_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -292,11 +299,54 @@ static void radix_sort_impl(u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit,
     }
 }
 
-void radix_sort_pairs(u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s) {
-    radix_sort_impl(keys, vals, n, lo_bit, hi_bit, pool, s);
+void radix_sort_pairs(u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s,
+                      SortPlan plan) {
+    radix_sort_impl(keys, vals, n, lo_bit, hi_bit, pool, s, plan);
 }
-void radix_sort_keys(u64* keys, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s) {
-    radix_sort_impl(keys, nullptr, n, lo_bit, hi_bit, pool, s);
+void radix_sort_keys(u64* keys, u64 n, u32 lo_bit, u32 hi_bit, Pool& pool, hipStream_t s, SortPlan plan) {
+    radix_sort_impl(keys, nullptr, n, lo_bit, hi_bit, pool, s, plan);
+}
+
+// Candidates: digit widths 5..8 (pass count and histogram size), and for the
+// multi-workgroup passes 8 or 16 keys per thread (tile size against grid
+// size).  A sort of at most 8 bits is one pass whatever the width.
+void tuned_sort(Ctx& c, u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit) {
+    if (n <= 1 || hi_bit <= lo_bit) return;
+    SortPlan plan;
+    const u32 bits = hi_bit - lo_bit;
+    if (c.tune.force_digit) {
+        plan.digit = c.tune.force_digit;
+    } else if (c.tune.on && bits > 8) {
+        const bool multi = n > SS_MAX;
+        std::vector<u32> cands;
+        for (u32 d = 5; d <= 8; ++d) {
+            if (multi) cands.push_back(d | (8u << 8));
+            cands.push_back(d | (16u << 8));
+        }
+        const u64 key = tune_key(TUNE_SORT, vals ? 1 : 0, tune_lg(n), bits);
+        DBuf<u64> kc;
+        DBuf<u32> vc;
+        const u32 pick = tune_pick(
+            c, key, cands,
+            [&](u32) {
+                if (!kc.ptr) {
+                    kc.reset(&c.pool, n);
+                    if (vals) vc.reset(&c.pool, n);
+                }
+                F4_HIP_TRY(hipMemcpyAsync(kc.ptr, keys, n * sizeof(u64), hipMemcpyDeviceToDevice, c.stream));
+                if (vals)
+                    F4_HIP_TRY(hipMemcpyAsync(vc.ptr, vals, n * sizeof(u32), hipMemcpyDeviceToDevice, c.stream));
+            },
+            [&](u32 ch) {
+                SortPlan pl;
+                pl.digit = ch & 0xffu;
+                pl.items = ch >> 8;
+                radix_sort_impl(kc.ptr, vals ? vc.ptr : nullptr, n, lo_bit, hi_bit, c.pool, c.stream, pl);
+            });
+        plan.digit = pick & 0xffu;
+        plan.items = pick >> 8;
+    }
+    radix_sort_impl(keys, vals, n, lo_bit, hi_bit, c.pool, c.stream, plan);
 }
 
 // ------------------------------------------------------------------ unique

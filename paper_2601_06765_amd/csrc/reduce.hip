@@ -1047,20 +1047,39 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
         // the kernel's static LDS (panel vectors, partial sums) is below 8 KB
         const size_t budget = c.dev.max_lds > 8192 ? c.dev.max_lds - 8192 : 0;
         if (row_bytes <= budget) {
-            const u32 rr = (u32)std::min<size_t>(TR_MAXR, budget / row_bytes);
-            const u32 tiles = ceil_div(cmax, rr);
+            // rows per tile: as many as the LDS holds (at most TR_MAXR), unless
+            // forced or tuned; fewer rows per tile give more, smaller tiles
+            const u32 rmax = (u32)std::min<size_t>(TR_MAXR, budget / row_bytes);
+            auto launch = [&](u32 rr, unsigned long long* op) {
+                const u32 tiles = ceil_div(cmax, rr);
+                if (small)
+                    hipLaunchKernelGGL((k_trsm<true, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
+                                       X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
+                                       skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)nullptr, Dp,
+                                       lead_out, op);
+                else
+                    hipLaunchKernelGGL((k_trsm<false, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
+                                       X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
+                                       skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, Dp,
+                                       lead_out, op);
+                F4_LAUNCH_CHECK();
+            };
+            u32 rr = rmax;
+            if (c.tune.force_rr) {
+                rr = std::min(rmax, c.tune.force_rr);
+            } else if (c.tune.on && rmax > 1) {
+                // the solve rewrites its outputs completely, so candidates can
+                // run on the live data
+                u64 rows = 0;
+                for (const SegR& g : X.segs)
+                    if (g.c && (g.small != 0) == small) rows += tail ? g.r : g.L;
+                std::vector<u32> cands;
+                for (u32 v = 1; v <= rmax; ++v) cands.push_back(v);
+                rr = tune_pick(c, tune_key(TUNE_TRSM, small ? 1 : 0, tune_lg(rows), tune_lg(nmax)), cands,
+                               [](u32) {}, [&](u32 v) { launch(v, nullptr); });
+            }
             hipEvent_t ka = kt ? stage_event(c) : nullptr;
-            if (small)
-                hipLaunchKernelGGL((k_trsm<true, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
-                                   X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
-                                   skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)nullptr, Dp,
-                                   lead_out, ops);
-            else
-                hipLaunchKernelGGL((k_trsm<false, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
-                                   X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
-                                   skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, Dp,
-                                   lead_out, ops);
-            F4_LAUNCH_CHECK();
+            launch(rr, ops);
             if (ka) kt->ev_trsm.push_back({ka, stage_event(c)});
             continue;
         }
@@ -1192,7 +1211,7 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
         hipLaunchKernelGGL(k_emit_keys, dim3(std::min<u32>(16, ceil_div(maxr, 256)), S), dim3(256), 0, s, X.dsegs.ptr,
                            dnpr, debase.ptr, prlead.ptr, cbits, keys.ptr, ids.ptr);
         F4_LAUNCH_CHECK();
-        radix_sort_pairs(keys.ptr, ids.ptr, E, 0, cbits + sbits, c.pool, s);
+        tuned_sort(c, keys.ptr, ids.ptr, E, 0, cbits + sbits);
         const u32 kc = S > 1 ? cbits : 64u;
         hipLaunchKernelGGL(k_count_nz, dim3(grid_of(E, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, kc,
                            ids.ptr, E, 1, Dp.ptr, PR.ptr, cnt.ptr);

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libf4.so")
 
 F4_OK, F4_E_ARG, F4_E_RANGE, F4_E_NOMEM, F4_E_BUSY, F4_E_DEVICE, F4_E_STATE = range(7)
-F4_OPT_TIMING, F4_OPT_DICT_RANK, F4_OPT_DICT_RADIX = 1, 2, 4
+F4_OPT_TIMING, F4_OPT_DICT_RANK, F4_OPT_DICT_RADIX, F4_OPT_AUTOTUNE = 1, 2, 4, 8
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libf4.so is not built: run `python -m paper_2601_06765_amd.build` "
@@ -27,7 +27,7 @@ P = ctypes.POINTER
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("flags", c_u32), ("stop_deg", c_u32)]
+    _fields_ = [("flags", c_u32), ("stop_deg", c_u32), ("trsm_rows", c_u32), ("radix_bits", c_u32)]
 
 
 class Polys(ctypes.Structure):
@@ -77,6 +77,8 @@ _sig("f4_create", c_int, [P(c_vp), c_int, P(Opts)])
 _sig("f4_destroy", c_int, [c_vp])
 _sig("f4_last_error", ctypes.c_char_p, [c_vp])
 _sig("f4_download", c_int, [c_vp, c_vp, c_vp, ctypes.c_size_t])
+_sig("f4_tune_export", c_int, [c_vp, ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_size_t)])
+_sig("f4_tune_import", c_int, [c_vp, ctypes.c_char_p])
 _sig("f4_lane_bits", c_u32, [c_u32])
 _sig("f4_pack", c_int, [c_u32, P(c_u32), P(c_u64)])
 _sig("f4_unpack", c_int, [c_u32, c_u64, P(c_u32)])
@@ -185,16 +187,32 @@ class _PolysArg:
 
 # --------------------------------------------------------------- context
 class Context:
-    def __init__(self, device=0, timing=False, dict_path=None, stop_deg=0):
+    def __init__(self, device=0, timing=False, dict_path=None, stop_deg=0, autotune=False, trsm_rows=0,
+                 radix_bits=0):
         flags = F4_OPT_TIMING if timing else 0
         if dict_path == "rank":
             flags |= F4_OPT_DICT_RANK
         elif dict_path == "radix":
             flags |= F4_OPT_DICT_RADIX
+        if autotune:
+            flags |= F4_OPT_AUTOTUNE
         self._h = c_vp()
-        rc = _lib.f4_create(ctypes.byref(self._h), device, ctypes.byref(Opts(flags, stop_deg)))
+        rc = _lib.f4_create(ctypes.byref(self._h), device,
+                            ctypes.byref(Opts(flags, stop_deg, trsm_rows, radix_bits)))
         if rc:
             raise F4Error(rc, "f4_create failed")
+
+    def tune_table(self):
+        """The autotuner's table as text (f4_tune_export)."""
+        n = ctypes.c_size_t(0)
+        self._check(_lib.f4_tune_export(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        self._check(_lib.f4_tune_export(self._h, buf, n.value + 1, ctypes.byref(n)))
+        return buf.value.decode()
+
+    def load_tune_table(self, text):
+        """Merge a table in the text form of tune_table() (f4_tune_import)."""
+        self._check(_lib.f4_tune_import(self._h, text.encode()))
 
     def close(self):
         if self._h:
