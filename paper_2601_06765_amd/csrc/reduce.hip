@@ -577,13 +577,18 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     const u32 r0 = 2 * wave, r1 = 2 * wave + 1;  // block rows of this wave
     u32 q = 0, pmask = 0, it = 0;
     u64 nops = 0;  // modular products (counted by lane 0 of each wave; timing option)
-    // chunks of ECH_CH columns from the smallest leading column of the block
-    for (u32 j0 = s_cmin; j0 < c && q < b; j0 += ECH_CH) {
+    // chunks of ECH_CH columns from the smallest leading column of the block;
+    // each thread holds one entry of the next chunk in a register (its load is
+    // in flight while the current chunk is eliminated)
+    const u32 kB = tid / ECH_CH, jB = tid % ECH_CH;
+    const u64 boff = kB < b ? (u64)s_rows[kB] * c : 0;
+    auto load_b = [&](u32 j0) -> u32 { return (kB < b && j0 + jB < c) ? D[boff + j0 + jB] : 0u; };
+    const u32 cmin0 = s_cmin;
+    u32 bnext = load_b(cmin0);
+    for (u32 j0 = cmin0; j0 < c && q < b; j0 += ECH_CH) {
         const u32 w = min((u32)ECH_CH, c - j0);
-        {
-            const u32 k = tid / ECH_CH, j = tid % ECH_CH;
-            s_B[tid] = (k < b && j < w) ? D[(u64)s_rows[k] * c + j0 + j] : 0u;
-        }
+        s_B[tid] = bnext;
+        bnext = load_b(j0 + ECH_CH);
         __syncthreads();
         // chunk part of the rows: Z * B_chunk (B itself while Z is the identity)
         {
@@ -691,9 +696,12 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
 // rows NP_t = sum_u Z[t][u] * (block row u).  Every other live row r loses its
 // entries on the round's pivot columns: with coef_t = r[col_t],
 // r - sum_t coef_t NP_t = r - sum_u w_u (block row u), w = coef * Z, so the
-// update reads the block rows directly and does not wait for NP.
+// update reads the block rows directly and does not wait for NP.  The round's
+// Z goes to LDS in one cooperative load, and each column's block-row entries
+// are loaded together (no load waits behind another).
 __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, const u32* ubase, u32* Dp, u32* status,
                                                     u32* lead, const EchRound* rounds, u32* PR) {
+    __shared__ u32 s_Z[ECH_B * ECH_B];
     __shared__ u32 s_coef[ECH_B], s_w[ECH_B], s_rows[ECH_B];
     __shared__ u32 s_any, s_lead;
     const u32 u = blockIdx.x;
@@ -716,7 +724,8 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
     const u32 tid = threadIdx.x;
     const u32* D = Dp + G.dpb;
     u32* row;
-    bool is_rem;
+    bool is_rem, form = false;
+    u32 t = 0;
     if (local < G.L) {
         if (status[G.lb + local] != 0 || lead[G.lb + local] >= c) return;
         row = Dp + G.dpb + (u64)local * c;
@@ -727,32 +736,32 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
         row = PR + G.prb + (u64)k * c;
         is_rem = false;
         if (k >= npr0) {
-            const u32 t = k - npr0;
-            if (tid < b) {
-                s_w[tid] = R->Z[t * ECH_B + tid];
-                s_rows[tid] = R->rows[tid];
-            }
-            __syncthreads();
-            for (u32 j = tid; j < c; j += 256) {
-                u64 acc = 0;
-                for (u32 v = 0; v < b; ++v) {
-                    const u32 z = s_w[v];
-                    if (z) {
-                        const u32 x = D[(u64)s_rows[v] * c + j];
-                        acc += small ? (u64)mul24(z, x) : (u64)fp_mul(f, z, x);
-                    }
-                }
-                row[j] = fp_reduce_any(f, acc);
-            }
-            return;
+            form = true;
+            t = k - npr0;
         }
+    }
+    // sum_v s_w[v] * (block row v)[j]; s_w is zero past b
+    auto combo = [&](u32 j) -> u32 {
+        u32 x[ECH_B];
+#pragma unroll
+        for (u32 v = 0; v < ECH_B; ++v) x[v] = v < b ? D[(u64)s_rows[v] * c + j] : 0u;
+        u64 acc = 0;
+#pragma unroll
+        for (u32 v = 0; v < ECH_B; ++v) acc += small ? (u64)mul24(s_w[v], x[v]) : (u64)fp_mul(f, s_w[v], x[v]);
+        return fp_reduce_any(f, acc);
+    };
+    if (tid < b) s_rows[tid] = R->rows[tid];
+    if (form) {
+        if (tid < ECH_B) s_w[tid] = tid < b ? R->Z[t * ECH_B + tid] : 0u;
+        __syncthreads();
+        for (u32 j = tid; j < c; j += 256) row[j] = combo(j);
+        return;
     }
     if (tid == 0) {
         s_any = 0;
         s_lead = 0xffffffffu;
     }
-    if (tid < b) s_rows[tid] = R->rows[tid];
-    __syncthreads();
+    for (u32 x = tid; x < q * ECH_B; x += 256) s_Z[x] = R->Z[x];
     if (tid < q) {
         const u32 v = row[R->cols[tid]];
         s_coef[tid] = v;
@@ -760,30 +769,20 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
     }
     __syncthreads();
     if (!s_any) return;
-    if (tid < b) {
+    if (tid < ECH_B) {
         u64 acc = 0;
-        for (u32 t = 0; t < q; ++t) {
-            const u32 cf = s_coef[t];
-            if (cf) {
-                const u32 z = R->Z[t * ECH_B + tid];
+        if (tid < b)
+            for (u32 t2 = 0; t2 < q; ++t2) {
+                const u32 cf = s_coef[t2], z = s_Z[t2 * ECH_B + tid];
                 acc += small ? (u64)mul24(cf, z) : (u64)fp_mul(f, cf, z);
             }
-        }
         s_w[tid] = fp_reduce_any(f, acc);
     }
     __syncthreads();
     const u32 cmin = R->cmin;
     u32 first = 0xffffffffu;
     for (u32 j = cmin + tid; j < c; j += 256) {
-        u64 acc = 0;
-        for (u32 v = 0; v < b; ++v) {
-            const u32 w = s_w[v];
-            if (w) {
-                const u32 x = D[(u64)s_rows[v] * c + j];
-                acc += small ? (u64)mul24(w, x) : (u64)fp_mul(f, w, x);
-            }
-        }
-        const u32 sub = fp_reduce_any(f, acc);
+        const u32 sub = combo(j);
         const u32 old = row[j];
         const u32 nv = old >= sub ? old - sub : old + f.p - sub;
         row[j] = nv;
