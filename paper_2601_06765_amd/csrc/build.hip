@@ -105,7 +105,7 @@ struct SegSP {
 // nonzero word.
 __global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, const u64* rows_t, const u32* rows_k,
                                                            u32* row_lmrank, u32* ctr, u32* present, u32* done,
-                                                           int local_bitmap) {
+                                                           u32* lead, int local_bitmap) {
     extern __shared__ u32 sm[];
     const SegSP S = segs[blockIdx.y];
     u32* tab = sm;
@@ -117,6 +117,7 @@ __global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, con
     u32* C = ctr + CTR * blockIdx.y;
     u32* P = present + S.wbase;
     u32* Dn = done + S.wbase;
+    u32* Ld = lead + S.wbase;
     const u32 n = S.n, w = S.w, D = S.D, lane = lane_id();
     const u32 rb = C[0], re = C[1];
     const u32 nw_total = gridDim.x * MB_WAVES;
@@ -131,6 +132,7 @@ __global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, con
             }
             row_lmrank[S.rbase + row] = q;
             atomicOr(&Dn[q >> 5], 1u << (q & 31));
+            atomicOr(&Ld[q >> 5], 1u << (q & 31));
         }
         const u64 off = S.off[k];
         const u32 len = S.len[k];
@@ -194,17 +196,18 @@ __global__ void k_frontier_write(const SegSP* segs, const u32* present, u32* don
 }
 
 // Small bitmaps (W <= WORDS_SMALL words) in one workgroup: per word the count
-// of its set bits (mode 2: present; modes 0, 1: present and not done), the
-// exclusive offsets off[0..W] and, in mode 0, the frontier list in word and
-// bit order with the words marked done - k_frontier_count + scan +
-// k_frontier_write (or k_word_popc + scan) in one launch.
+// of its set bits (mode 2: present, and the leading-monomial bitmap into
+// loff; modes 0, 1: present and not done), the exclusive offsets off[0..W]
+// and, in mode 0, the frontier list in word and bit order with the words
+// marked done - k_frontier_count + scan + k_frontier_write (or k_word_popc +
+// scan) in one launch.
 #define WORDS_SMALL 8192
 __global__ __launch_bounds__(1024) void k_words_small(const SegSP* segs, u32 S, const u32* present, u32* done,
                                                       u32 W, int mode, u32* off, u32* list_q, u32* list_s,
-                                                      u32* ctr) {
+                                                      u32* ctr, const u32* lead, u32* loff) {
     __shared__ u32 s_wave[33];
     const u32 tid = threadIdx.x;
-    u32 carry = 0;
+    u32 carry = 0, lcarry = 0;
     for (u32 base = 0; base < W; base += 1024) {
         const u32 wi = base + tid;
         u32 f = 0;
@@ -212,6 +215,12 @@ __global__ __launch_bounds__(1024) void k_words_small(const SegSP* segs, u32 S, 
         u32 tot;
         const u32 pre = block_exclusive_scan(__popc(f), s_wave, &tot);
         if (wi < W) off[wi] = carry + pre;
+        if (mode == 2) {
+            u32 ltot;
+            const u32 lpre = block_exclusive_scan(wi < W ? __popc(lead[wi]) : 0u, s_wave, &ltot);
+            if (wi < W) loff[wi] = lcarry + lpre;
+            lcarry += ltot;
+        }
         if (mode == 0 && f) {
             done[wi] |= f;
             u32 lo = 0, hi = S;  // system of the word: last s with wbase <= wi
@@ -234,7 +243,10 @@ __global__ __launch_bounds__(1024) void k_words_small(const SegSP* segs, u32 S, 
         }
         carry += tot;
     }
-    if (tid == 0) off[W] = carry;
+    if (tid == 0) {
+        off[W] = carry;
+        if (mode == 2) loff[W] = lcarry;
+    }
     if (mode == 0)
         for (u32 sy = tid; sy < S; sy += 1024) ctr[CTR * sy] = ctr[CTR * sy + 1];
 }
@@ -333,7 +345,7 @@ __global__ void k_sum_len(const SegSP* segs, const u32* rows_k, const u32* ctr, 
 
 // summary per system: rows, remaining frontier, error, N, M lo, M hi
 __global__ void k_sp_summary(const SegSP* segs, u32 S, const u32* ctr, const u32* fscan, const u32* pscan,
-                             const unsigned long long* M, u32* out) {
+                             const u32* lscan, const unsigned long long* M, u32* out) {
     for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
         const SegSP& G = segs[s];
         out[8 * s + 0] = ctr[CTR * s + 1];
@@ -342,6 +354,7 @@ __global__ void k_sp_summary(const SegSP* segs, u32 S, const u32* ctr, const u32
         out[8 * s + 3] = pscan[G.wbase + G.nwords] - pscan[G.wbase];
         out[8 * s + 4] = (u32)M[s];
         out[8 * s + 5] = (u32)(M[s] >> 32);
+        out[8 * s + 6] = lscan[G.wbase + G.nwords] - lscan[G.wbase];  // distinct leading monomials
     }
 }
 
@@ -598,10 +611,12 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     SegSP* const dsegs = (SegSP*)(params.ptr + o_segs);
     const u32* const active = (const u32*)(params.ptr + o_act);
     u32* const ctr = (u32*)(params.ptr + o_ctr);  // counters live in the parameter block
-    DBuf<u32> pd(&c.pool, 2 * W);                 // present and done bitmaps, cleared together
-    fill_u32(pd.ptr, 2 * W, 0, s);
+    // present, done and leading-monomial bitmaps, cleared together
+    DBuf<u32> pd(&c.pool, 3 * W);
+    fill_u32(pd.ptr, 3 * W, 0, s);
     u32* const present = pd.ptr;
     u32* const done = pd.ptr + W;
+    u32* const leadmap = pd.ptr + 2 * W;
     DBuf<u64> rows_t(&c.pool, RC);
     DBuf<u32> rows_k(&c.pool, RC), row_lmrank(&c.pool, RC);
     {
@@ -618,12 +633,12 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     const u32 bx = std::max<u32>(1, std::min<u32>((u32)std::max(1, c.dev.cus), ceil_div(2048, S)));
     auto mark = [&]() {
         hipLaunchKernelGGL(k_mark_rows, dim3(bx, S), dim3(MB_THREADS), mark_lds, s, dsegs, rows_t.ptr,
-                           rows_k.ptr, row_lmrank.ptr, ctr, present, done, local_bitmap);
+                           rows_k.ptr, row_lmrank.ptr, ctr, present, done, leadmap, local_bitmap);
         F4_LAUNCH_CHECK();
     };
     mark();
 
-    DBuf<u32> fcnt(&c.pool, W + 1), pcnt(&c.pool, W + 1);
+    DBuf<u32> fcnt(&c.pool, W + 1), pcnt(&c.pool, W + 1), lcnt(&c.pool, W + 1);
     DBuf<u32> list_q(&c.pool, closure ? CM : 1), list_s(&c.pool, closure ? CM : 1);
     DBuf<u32> summary(&c.pool, 8 * S);
     const u32 wgrid = grid_for(W, 256, 2048);
@@ -644,7 +659,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
             for (int k = 0; k < 2; ++k) {
                 if (small_words) {
                     hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 0,
-                                       fcnt.ptr, list_q.ptr, list_s.ptr, ctr);
+                                       fcnt.ptr, list_q.ptr, list_s.ptr, ctr, leadmap, lcnt.ptr);
                     F4_LAUNCH_CHECK();
                 } else {
                     hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present, done, (u32)W,
@@ -664,7 +679,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
             }
             if (small_words) {
                 hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 1,
-                                   fcnt.ptr, list_q.ptr, list_s.ptr, ctr);
+                                   fcnt.ptr, list_q.ptr, list_s.ptr, ctr, leadmap, lcnt.ptr);
                 F4_LAUNCH_CHECK();
             } else {
                 hipLaunchKernelGGL(k_frontier_count, dim3(wgrid), dim3(256), 0, s, present, done, (u32)W,
@@ -678,18 +693,21 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         // dictionary sizes and M alongside the convergence check: one readback
         if (small_words) {
             hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 2,
-                               pcnt.ptr, list_q.ptr, list_s.ptr, ctr);
+                               pcnt.ptr, list_q.ptr, list_s.ptr, ctr, leadmap, lcnt.ptr);
             F4_LAUNCH_CHECK();
         } else {
             hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, present, (u32)W, pcnt.ptr);
             F4_LAUNCH_CHECK();
             exclusive_scan_u32(pcnt.ptr, pcnt.ptr, W, c.pool, s);
+            hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, leadmap, (u32)W, lcnt.ptr);
+            F4_LAUNCH_CHECK();
+            exclusive_scan_u32(lcnt.ptr, lcnt.ptr, W, c.pool, s);
         }
         fill_u64((u64*)Mdev.ptr, S, 0, s);
         hipLaunchKernelGGL(k_sum_len, dim3(bx, S), dim3(256), 0, s, dsegs, rows_k.ptr, ctr, Mdev.ptr);
         F4_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_sp_summary, dim3(grid_for(S, 256, 64)), dim3(256), 0, s, dsegs, S, ctr, fcnt.ptr,
-                           pcnt.ptr, Mdev.ptr, summary.ptr);
+                           pcnt.ptr, lcnt.ptr, Mdev.ptr, summary.ptr);
         F4_LAUNCH_CHECK();
         readback(c, hs.data(), summary.ptr, hs.size() * 4);
         bool more = false;
@@ -715,6 +733,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         P.r = hs[8 * i + 0];
         P.N = hs[8 * i + 3];
         P.nnz = (u64)hs[8 * i + 4] | ((u64)hs[8 * i + 5] << 32);
+        P.npiv = hs[8 * i + 6];
         P.row_base = (u32)R;
         P.nnz_base = Mtot;
         P.dict_base = segs[i].cmbase;

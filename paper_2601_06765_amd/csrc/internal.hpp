@@ -236,6 +236,7 @@ struct DevBasis {
 // the system.  A single matrix is the batch of one.
 struct SysPart {
     u32 n = 0, deg = 0, r = 0, N = 0;
+    u32 npiv = 0xffffffffu;  // distinct leading columns of the rows (unknown: all ones)
     u64 nnz = 0;
     u32 row_base = 0;
     u64 nnz_base = 0;

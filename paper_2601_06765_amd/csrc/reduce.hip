@@ -798,25 +798,47 @@ __global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, con
 
 
 // ------------------------------------------------------------------- emit
-// keys of the pivot rows: (system, leading column); value: store row index
-__global__ void k_emit_keys(const SegR* segs, const u32* npr, const u32* ebase, const u32* prlead, u32 cbits,
-                            u64* keys, u32* vals) {
+// keys of the pivot-row store slots: (system, leading column) for the system's
+// first npr[s] slots, `sent` (sorts after every real key) for the rest; value:
+// store row index
+__global__ void k_emit_keys(const SegR* segs, const u32* npr, const u32* prlead, u32 cbits, u64 sent, u64* keys,
+                            u32* vals) {
     const u32 s = blockIdx.y;
     const SegR G = segs[s];
     const u32 n = npr[s];
-    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        keys[ebase[s] + t] = ((u64)s << cbits) | prlead[G.capb + t];
-        vals[ebase[s] + t] = G.capb + t;
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < G.cap; t += gridDim.x * blockDim.x) {
+        keys[G.capb + t] = t < n ? (((u64)s << cbits) | prlead[G.capb + t]) : sent;
+        vals[G.capb + t] = G.capb + t;
+    }
+}
+
+// Row offsets of the emitted rows end where the real rows end: system s owns
+// sorted rows [eb[s], eb[s] + npr[s]) with eb the exclusive scan of npr, and
+// emits pos[eb[s] + npr[s]] - pos[eb[s]] nonzeros.  One workgroup.
+__global__ __launch_bounds__(1024) void k_emit_totals(const u32* npr, u32 S, const u32* pos, u32* tot) {
+    __shared__ u32 s_wave[33];
+    u32 carry = 0;
+    for (u32 base = 0; base < S; base += 1024) {
+        const u32 i = base + threadIdx.x;
+        const u32 v = i < S ? npr[i] : 0u;
+        u32 t;
+        const u32 pre = block_exclusive_scan(v, s_wave, &t);
+        if (i < S) tot[i] = pos[carry + pre + v] - pos[carry + pre];
+        carry += t;
     }
 }
 
 // nonzero count of each listed row (wave per row); row `id` of system s lives
 // at base + (id - idbase) * c
-__global__ void k_count_nz(const SegR* segs, const u64* keys, u32 cbits, const u32* ids, u32 n, int from_pr,
-                           const u32* Dp, const u32* PR, u32* cnt) {
+__global__ void k_count_nz(const SegR* segs, const u64* keys, u32 cbits, u64 sent, const u32* ids, u32 n,
+                           int from_pr, const u32* Dp, const u32* PR, u32* cnt) {
     const u32 lane = lane_id();
     const u32 nw = gridDim.x * (blockDim.x / F4_WAVE);
     for (u32 t = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; t < n; t += nw) {
+        if (keys[t] == sent) {  // unused store slot
+            if (lane == 0) cnt[t] = 0;
+            continue;
+        }
         const u32 s = cbits >= 64 ? 0u : (u32)(keys[t] >> cbits);
         const SegR G = segs[s];
         const u32* row = from_pr ? PR + G.prb + (u64)(ids[t] - G.capb) * G.c : Dp + G.dpb + (u64)(ids[t] - G.lb) * G.c;
@@ -828,12 +850,13 @@ __global__ void k_count_nz(const SegR* segs, const u64* keys, u32 cbits, const u
 }
 
 // row t of the listed rows -> CSR row t over the system's original columns
-__global__ void k_emit(const SegR* segs, const u64* keys, u32 cbits, const u32* ids, u32 n, int from_pr,
+__global__ void k_emit(const SegR* segs, const u64* keys, u32 cbits, u64 sent, const u32* ids, u32 n, int from_pr,
                        const u32* Dp, const u32* PR, const u32* nonpiv, const u32* optr, u32* ocol, u32* oval) {
     const u32 lane = lane_id();
     const u64 lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const u32 nw = gridDim.x * (blockDim.x / F4_WAVE);
     for (u32 t = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; t < n; t += nw) {
+        if (keys[t] == sent) continue;
         const u32 s = cbits >= 64 ? 0u : (u32)(keys[t] >> cbits);
         const SegR G = segs[s];
         const u32* row = from_pr ? PR + G.prb + (u64)(ids[t] - G.capb) * G.c : Dp + G.dpb + (u64)(ids[t] - G.lb) * G.c;
@@ -865,12 +888,6 @@ __global__ void k_iota(u32* out, u32 n) {
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = i;
 }
 
-// per-system sums of a count array laid out by system: out[s] = pos[end_s] - pos[begin_s]
-__global__ void k_seg_total(const u32* pos, const u32* ebase, u32 S, u32* out) {
-    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x)
-        out[s] = pos[ebase[s + 1]] - pos[ebase[s]];
-}
-
 static u32 grid_of(u64 items, u32 per, u32 cap) {
     u64 g = (items + per - 1) / per;
     if (g < 1) g = 1;
@@ -896,9 +913,49 @@ struct SplitState {
     DBuf<u64> tent;
     DBuf<u32> T, Tinv;
     u32 P = 0, Ltot = 0, C = 0;
+    bool known = false;  // layout from the build's pivot counts (split summary checked later)
 };
 
-static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitState& X) {
+// Elimination layout of every system from its pivot count: lower rows,
+// trailing columns, pivot-row store capacity and the offsets of each
+// system's slices in the batched buffers.
+static void split_layout(SplitState& X, const std::vector<u32>& p, const std::vector<u32>& npiv,
+                         const std::vector<u32>& L) {
+    u32 P = 0, Lb = 0, nbase = 0, tb = 0, capb = 0, ub = 0;
+    u64 dpb = 0, prb = 0;
+    for (u32 i = 0; i < X.S; ++i) {
+        SegR& g = X.segs[i];
+        g.npiv = npiv[i];
+        g.L = L[i];
+        g.small = (p[i] < 65536 && g.npiv < 65536) ? 1u : 0u;
+        g.pb = P;
+        g.lb = Lb;
+        g.c = g.N - g.npiv;
+        g.nb = nbase;
+        g.tb = tb;
+        g.cap = std::min(g.L, g.c);
+        g.capb = capb;
+        g.ub = ub;
+        g.dpb = dpb;
+        g.prb = prb;
+        P += g.npiv;
+        Lb += g.L;
+        nbase += g.c;
+        tb += (g.npiv + PANEL - 1) / PANEL;
+        capb += g.cap;
+        ub += g.L + g.cap;
+        dpb += (u64)g.L * g.c;
+        prb += (u64)g.cap * g.c;
+    }
+    X.P = P;
+    X.Ltot = Lb;
+}
+
+// The pivot / non-pivot split.  With `summ_out` (2 words per system, device)
+// and pivot counts known from the build, the layout is fixed before the split
+// kernels run and their own counts are left in summ_out for the caller to
+// check with a later readback; otherwise the counts are read back here.
+static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitState& X, u32* summ_out = nullptr) {
     hipStream_t s = c.stream;
     const u32 S = A.S, R = A.R;
     X.S = S;
@@ -916,6 +973,17 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
     }
     if (C >= (1ull << 31)) throw F4Error{2, "batch has too many columns"};
     X.C = (u32)C;
+    X.known = summ_out != nullptr;
+    for (u32 i = 0; i < S; ++i)
+        if (A.sys[i].npiv > A.sys[i].r || A.sys[i].npiv > A.sys[i].N) X.known = false;
+    if (X.known) {
+        std::vector<u32> np(S), L(S);
+        for (u32 i = 0; i < S; ++i) {
+            np[i] = A.sys[i].npiv;
+            L[i] = A.sys[i].r - np[i];
+        }
+        split_layout(X, p, np, L);
+    }
     X.dsegs.reset(&c.pool, S);
     upload(c, X.dsegs.ptr, X.segs.data(), S * sizeof(SegR));
     DBuf<u32> ppos(&c.pool, C + 1);
@@ -925,11 +993,13 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
     X.nonpiv.reset(&c.pool, std::max<u64>(C, 1));
     DBuf<u32> lf(&c.pool, (u64)R + 1), lpos(&c.pool, (u64)R + 1);
     X.lower.reset(&c.pool, std::max<u32>(R, 1));
-    DBuf<u32> summ(&c.pool, 2 * S);
+    DBuf<u32> summ_own;
+    if (!X.known) summ_own.reset(&c.pool, 2 * S);
+    u32* const summ = X.known ? summ_out : summ_own.ptr;
     if (C <= SPLIT_SMALL_C && R <= SPLIT_SMALL_R) {
         hipLaunchKernelGGL(k_split_small, dim3(1), dim3(1024), (size_t)std::max<u64>(C, 1) * 8, s, X.dsegs.ptr, S,
                            A.row_ptr.ptr, A.col_ind.ptr, A.row_sys.ptr, R, (u32)C, ppos.ptr, lpos.ptr, X.perm.ptr,
-                           X.prow.ptr, X.pivot_cols.ptr, X.nonpiv.ptr, X.lower.ptr, summ.ptr);
+                           X.prow.ptr, X.pivot_cols.ptr, X.nonpiv.ptr, X.lower.ptr, summ);
         F4_LAUNCH_CHECK();
     } else {
         DBuf<unsigned long long> best(&c.pool, std::max<u64>(C, 1));
@@ -961,41 +1031,23 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
             F4_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(k_split_summary, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, X.dsegs.ptr, S, ppos.ptr,
-                           lpos.ptr, summ.ptr);
+                           lpos.ptr, summ);
         F4_LAUNCH_CHECK();
     }
-    std::vector<u32> hs(2 * S);
-    readback(c, hs.data(), summ.ptr, hs.size() * 4);
-    // per-system layout of the elimination
-    u32 P = 0, Lb = 0, nbase = 0, tb = 0, capb = 0, ub = 0;
-    u64 dpb = 0, prb = 0;
-    for (u32 i = 0; i < S; ++i) {
-        SegR& g = X.segs[i];
-        g.npiv = hs[2 * i];
-        g.L = hs[2 * i + 1];
-        g.small = (p[i] < 65536 && g.npiv < 65536) ? 1u : 0u;
-        g.pb = P;
-        g.lb = Lb;
-        g.c = g.N - g.npiv;
-        g.nb = nbase;
-        g.tb = tb;
-        g.cap = std::min(g.L, g.c);
-        g.capb = capb;
-        g.ub = ub;
-        g.dpb = dpb;
-        g.prb = prb;
-        P += g.npiv;
-        Lb += g.L;
-        nbase += g.c;
-        tb += (g.npiv + PANEL - 1) / PANEL;
-        capb += g.cap;
-        ub += g.L + g.cap;
-        dpb += (u64)g.L * g.c;
-        prb += (u64)g.cap * g.c;
+    if (!X.known) {
+        std::vector<u32> hs(2 * S);
+        readback(c, hs.data(), summ, hs.size() * 4);
+        std::vector<u32> np(S), L(S);
+        for (u32 i = 0; i < S; ++i) {
+            np[i] = hs[2 * i];
+            L[i] = hs[2 * i + 1];
+        }
+        split_layout(X, p, np, L);
+        upload(c, X.dsegs.ptr, X.segs.data(), S * sizeof(SegR));
     }
-    X.P = P;
-    X.Ltot = Lb;
-    upload(c, X.dsegs.ptr, X.segs.data(), S * sizeof(SegR));
+    u32 tb = 0;
+    for (const SegR& g : X.segs) tb += (g.npiv + PANEL - 1) / PANEL;
+    const u32 P = X.P;
     X.tptr.reset(&c.pool, (u64)P + 1);
     X.T.reset(&c.pool, (u64)std::max<u32>(tb, 1) * PANEL * PANEL);
     fill_u32(X.T.ptr, (u64)tb * PANEL * PANEL, 0, s);
@@ -1114,18 +1166,33 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
     for (const SysPart& P : A.sys)
         if (P.N >= (1u << 26)) throw F4Error{2, "matrix has 2^26 or more columns"};
     hipEvent_t e0 = stage_event(c);
+    // one parameter block: round records, update-grid bases and the done
+    // counter (uploaded), followed by what the host reads back in one copy
+    // per echelon batch: the done count, pivot rows per system, the split's
+    // own counts (2 per system, written by the split kernels) and the emitted
+    // nonzeros per system
+    const u32 S = A.S;
+    const size_t rbytes = ((size_t)S * sizeof(EchRound) + 255) & ~(size_t)255;
+    const size_t o_nd = (rbytes + ((size_t)S + 1) * 4 + 255) & ~(size_t)255;
+    const size_t nback = (size_t)(S + 1) + 2 * (size_t)S + S;  // words read back
+    DBuf<u8> eparams(&c.pool, o_nd + nback * 4);
+    EchRound* const rounds = (EchRound*)eparams.ptr;
+    u32* const ubp = (u32*)(eparams.ptr + rbytes);
+    u32* const ndone = (u32*)(eparams.ptr + o_nd);  // [0] done count, [1 + s] pivot rows of system s
+    u32* const dsumm = ndone + S + 1;               // split counts: pivots, lower rows
+    u32* const dtot = dsumm + 2 * S;                // emitted nonzeros per system
     SplitState X;
-    do_split(c, p, A, X);
-    const u32 S = X.S;
+    do_split(c, p, A, X, dsumm);
     hipEvent_t e1 = stage_event(c);
     u64 Dtot = 0, PRtot = 0;
-    u32 CAP = 0, UB = 0, maxc = 0;
+    u32 CAP = 0, UB = 0, maxc = 0, maxcap = 1;
     for (const SegR& g : X.segs) {
         Dtot += (u64)g.L * g.c;
         PRtot += (u64)g.cap * g.c;
         CAP += g.cap;
         UB += g.L + g.cap;
         maxc = std::max(maxc, g.c);
+        maxcap = std::max(maxcap, g.cap);
     }
     DBuf<u32> Dp(&c.pool, std::max<u64>(Dtot, 1)), lead(&c.pool, std::max<u32>(X.Ltot, 1));
     if (timing_on(c)) {
@@ -1137,41 +1204,52 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
 
     // echelon of every system's D' (L x c)
     DBuf<u32> PR(&c.pool, std::max<u64>(PRtot, 1)), prlead(&c.pool, std::max<u32>(CAP, 1));
-    std::vector<u32> npr(S, 0);
+    std::vector<u32> npr(S, 0), rnnz(S, 0);
     u32 active = 0;
     for (const SegR& g : X.segs) active += (g.L && g.c) ? 1 : 0;
-    // round records, the done counter and the update-grid bases: one upload
-    // (systems with nothing to eliminate are done from the start)
-    const size_t rbytes = ((size_t)S * sizeof(EchRound) + 255) & ~(size_t)255;
-    const size_t nbytes = (((size_t)S + 1) * 4 + 255) & ~(size_t)255;  // done count, then pivot rows per system
-    std::vector<u8> pack(rbytes + nbytes + (size_t)(S + 1) * 4, 0);
-    EchRound* init = (EchRound*)pack.data();
-    for (u32 i = 0; i < S; ++i) init[i].done = (X.segs[i].L && X.segs[i].c) ? 0u : 1u;
-    u32* hub = (u32*)(pack.data() + rbytes + nbytes);
-    for (u32 i = 0; i < S; ++i) hub[i] = X.segs[i].ub;
-    hub[S] = UB;
-    DBuf<u8> eparams(&c.pool, pack.size());
-    EchRound* const rounds = (EchRound*)eparams.ptr;
-    u32* const ndone = (u32*)(eparams.ptr + rbytes);
-    u32* const ubp = (u32*)(eparams.ptr + rbytes + nbytes);
-    if (active) {
+    // systems with nothing to eliminate are done from the start
+    {
+        std::vector<u8> pack(o_nd + (size_t)(S + 1) * 4, 0);
+        EchRound* init = (EchRound*)pack.data();
+        for (u32 i = 0; i < S; ++i) init[i].done = (X.segs[i].L && X.segs[i].c) ? 0u : 1u;
+        u32* hub = (u32*)(pack.data() + rbytes);
+        for (u32 i = 0; i < S; ++i) hub[i] = X.segs[i].ub;
+        hub[S] = UB;
         upload(c, eparams.ptr, pack.data(), pack.size());
+    }
+    out.S = S;
+    out.sys.assign(S, RedPart());
+    // emit plan, speculative: after each echelon batch the pivot-row keys
+    // (system, leading column) of every store slot (slots past a system's
+    // pivot-row count get a key that sorts last), their sort, the nonzero
+    // count of each row, the row offsets and the per-system totals - so one
+    // readback tells whether every system is done and how large the output is
+    const u32 cbits = std::max<u32>(1, bitlen(std::max<u32>(maxc, 1)));
+    const u32 sbits = S > 1 ? bitlen(S - 1) : 0;
+    const u32 kc = S > 1 ? cbits : 64u;
+    const u64 sent = (cbits + sbits >= 64) ? ~0ull : ((1ull << (cbits + sbits)) - 1);
+    out.row_ptr.reset(&c.pool, (u64)CAP + 1);
+    DBuf<u64> keys(&c.pool, std::max<u32>(CAP, 1));
+    DBuf<u32> ids(&c.pool, std::max<u32>(CAP, 1)), cnt(&c.pool, (u64)CAP + 1);
+    hipEvent_t e3 = nullptr;
+    std::vector<u32> hb(nback, 0);
+    if (active) {
         DBuf<u32> status(&c.pool, std::max<u32>(X.Ltot, 1));
         fill_u32(status.ptr, X.Ltot, 0, s);
         const int cnt_lds = (size_t)maxc * 4 + 32768 <= c.dev.max_lds;
-        DBuf<u32> cnt(&c.pool, cnt_lds ? 1 : std::max<u64>(X.C, 1));
+        DBuf<u32> ccnt(&c.pool, cnt_lds ? 1 : std::max<u64>(X.C, 1));
         // rounds per readback: the first batch from min(L, c) (each round yields
         // up to ECH_B pivots), later ones four at a time
         u32 maxlc = 0;
         for (const SegR& g : X.segs) maxlc = std::max(maxlc, std::min(g.L, g.c));
         u32 batch = std::min<u32>(8, std::max<u32>(2, ceil_div(maxlc, ECH_B) + 1));
-        std::vector<u32> hd(S + 1, 0);
         u32 r = 0;
-        while (hd[0] < active) {
+        bool first = true;
+        for (;;) {
             for (u32 k = 0; k < batch; ++k) {
                 hipEvent_t ka = stage_event(c);
                 hipLaunchKernelGGL(k_ech_block, dim3(1, S), dim3(1024), cnt_lds ? (size_t)maxc * 4 : 0, s,
-                                   X.dsegs.ptr, lead.ptr, status.ptr, Dp.ptr, cnt.ptr, cnt_lds, rounds,
+                                   X.dsegs.ptr, lead.ptr, status.ptr, Dp.ptr, ccnt.ptr, cnt_lds, rounds,
                                    prlead.ptr, ndone,
                                    out.ops.ptr ? (unsigned long long*)out.ops.ptr + 1 : nullptr);
                 F4_LAUNCH_CHECK();
@@ -1182,56 +1260,55 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
                 ++r;
             }
             batch = 4;
-            readback(c, hd.data(), ndone, (S + 1) * 4);
+            e3 = stage_event(c);
+            hipLaunchKernelGGL(k_emit_keys, dim3(std::min<u32>(16, ceil_div(maxcap, 256)), S), dim3(256), 0, s,
+                               X.dsegs.ptr, ndone + 1, prlead.ptr, cbits, sent, keys.ptr, ids.ptr);
+            F4_LAUNCH_CHECK();
+            tuned_sort(c, keys.ptr, ids.ptr, CAP, 0, cbits + sbits);
+            hipLaunchKernelGGL(k_count_nz, dim3(grid_of(CAP, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, kc,
+                               sent, ids.ptr, CAP, 1, Dp.ptr, PR.ptr, cnt.ptr);
+            F4_LAUNCH_CHECK();
+            exclusive_scan_u32(cnt.ptr, out.row_ptr.ptr, CAP, c.pool, s);
+            hipLaunchKernelGGL(k_emit_totals, dim3(1), dim3(1024), 0, s, ndone + 1, S, out.row_ptr.ptr, dtot);
+            F4_LAUNCH_CHECK();
+            readback(c, hb.data(), ndone, nback * 4);
+            if (first && X.known)
+                for (u32 i = 0; i < S; ++i)
+                    if (hb[S + 1 + 2 * i] != X.segs[i].npiv || hb[S + 2 + 2 * i] != X.segs[i].L)
+                        throw F4Error{5, "pivot split disagrees with the symbolic preprocessing"};
+            first = false;
+            if (hb[0] >= active) break;
             if (r > CAP + 8 + 4 * (X.Ltot / ECH_B + 1)) throw F4Error{5, "echelon did not converge"};
         }
-        for (u32 i = 0; i < S; ++i) npr[i] = hd[1 + i];
+        for (u32 i = 0; i < S; ++i) {
+            npr[i] = hb[1 + i];
+            rnnz[i] = hb[1 + 3 * S + i];
+        }
+    } else {
+        if (X.known) {
+            readback(c, hb.data(), ndone, nback * 4);
+            for (u32 i = 0; i < S; ++i)
+                if (hb[S + 1 + 2 * i] != X.segs[i].npiv || hb[S + 2 + 2 * i] != X.segs[i].L)
+                    throw F4Error{5, "pivot split disagrees with the symbolic preprocessing"};
+        }
+        fill_u32(out.row_ptr.ptr, 1, 0, s);
     }
-    hipEvent_t e3 = stage_event(c);
+    if (!e3) e3 = stage_event(c);
 
-    // emit RREF(D') over the original columns, rows by (system, leading column)
-    out.S = S;
-    out.sys.assign(S, RedPart());
+    // emit RREF(D') over the original columns, rows by (system, leading column):
+    // the sorted keys put the E real pivot rows first
     std::vector<u32> eb(S + 1, 0);
     for (u32 i = 0; i < S; ++i) eb[i + 1] = eb[i] + npr[i];
     const u32 E = eb[S];
-    out.row_ptr.reset(&c.pool, (u64)E + 1);
-    std::vector<u32> rnnz(S, 0);
+    u64 nnz = 0;
+    for (u32 v : rnnz) nnz += v;
+    out.col_ind.reset(&c.pool, std::max<u64>(nnz, 1));
+    out.val.reset(&c.pool, std::max<u64>(nnz, 1));
     if (E) {
-        const u32 cbits = std::max<u32>(1, bitlen(std::max<u32>(maxc, 1)));
-        const u32 sbits = S > 1 ? bitlen(S - 1) : 0;
-        DBuf<u32> debase(&c.pool, S + 1);
-        upload(c, debase.ptr, eb.data(), (S + 1) * 4);
-        DBuf<u64> keys(&c.pool, E);
-        DBuf<u32> ids(&c.pool, E), cnt(&c.pool, (u64)E + 1);
-        u32 maxr = 1;
-        for (u32 v : npr) maxr = std::max(maxr, v);
-        const u32* dnpr = ndone + 1;  // pivot rows per system, on the device since the echelon
-        hipLaunchKernelGGL(k_emit_keys, dim3(std::min<u32>(16, ceil_div(maxr, 256)), S), dim3(256), 0, s, X.dsegs.ptr,
-                           dnpr, debase.ptr, prlead.ptr, cbits, keys.ptr, ids.ptr);
+        hipLaunchKernelGGL(k_emit, dim3(grid_of(E, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, kc, sent,
+                           ids.ptr, E, 1, Dp.ptr, PR.ptr, X.nonpiv.ptr, out.row_ptr.ptr, out.col_ind.ptr,
+                           out.val.ptr);
         F4_LAUNCH_CHECK();
-        tuned_sort(c, keys.ptr, ids.ptr, E, 0, cbits + sbits);
-        const u32 kc = S > 1 ? cbits : 64u;
-        hipLaunchKernelGGL(k_count_nz, dim3(grid_of(E, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, kc,
-                           ids.ptr, E, 1, Dp.ptr, PR.ptr, cnt.ptr);
-        F4_LAUNCH_CHECK();
-        exclusive_scan_u32(cnt.ptr, out.row_ptr.ptr, E, c.pool, s);
-        DBuf<u32> tot(&c.pool, S);
-        hipLaunchKernelGGL(k_seg_total, dim3(grid_of(S, 256, 64)), dim3(256), 0, s, out.row_ptr.ptr, debase.ptr, S,
-                           tot.ptr);
-        F4_LAUNCH_CHECK();
-        readback(c, rnnz.data(), tot.ptr, S * 4);
-        u64 nnz = 0;
-        for (u32 v : rnnz) nnz += v;
-        out.col_ind.reset(&c.pool, std::max<u64>(nnz, 1));
-        out.val.reset(&c.pool, std::max<u64>(nnz, 1));
-        hipLaunchKernelGGL(k_emit, dim3(grid_of(E, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, kc, ids.ptr, E,
-                           1, Dp.ptr, PR.ptr, X.nonpiv.ptr, out.row_ptr.ptr, out.col_ind.ptr, out.val.ptr);
-        F4_LAUNCH_CHECK();
-    } else {
-        fill_u32(out.row_ptr.ptr, 1, 0, s);
-        out.col_ind.reset(&c.pool, 1);
-        out.val.reset(&c.pool, 1);
     }
     u64 nb = 0;
     for (u32 i = 0; i < S; ++i) {
@@ -1280,8 +1357,8 @@ void tail_reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, DBuf<
     hipLaunchKernelGGL(k_row_sys_keys, dim3(grid_of(R, 256, 1024)), dim3(256), 0, s, A.row_sys.ptr, R, keys.ptr);
     F4_LAUNCH_CHECK();
     run_trsm(c, A, X, rows.ptr, 1, 1, Dp.ptr, nullptr, nullptr);
-    hipLaunchKernelGGL(k_count_nz, dim3(grid_of(R, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, 32u, rows.ptr, R,
-                       0, Dp.ptr, Dp.ptr, cnt.ptr);
+    hipLaunchKernelGGL(k_count_nz, dim3(grid_of(R, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, 32u, ~0ull,
+                       rows.ptr, R, 0, Dp.ptr, Dp.ptr, cnt.ptr);
     F4_LAUNCH_CHECK();
     tptr.reset(&c.pool, (u64)R + 1);
     exclusive_scan_u32(cnt.ptr, tptr.ptr, R, c.pool, s);
@@ -1289,7 +1366,7 @@ void tail_reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, DBuf<
     readback(c, &nnz, tptr.ptr + R, 4);
     tcol.reset(&c.pool, std::max<u32>(nnz, 1));
     tval.reset(&c.pool, std::max<u32>(nnz, 1));
-    hipLaunchKernelGGL(k_emit, dim3(grid_of(R, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, 32u, rows.ptr, R, 0,
-                       Dp.ptr, Dp.ptr, X.nonpiv.ptr, tptr.ptr, tcol.ptr, tval.ptr);
+    hipLaunchKernelGGL(k_emit, dim3(grid_of(R, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, 32u, ~0ull,
+                       rows.ptr, R, 0, Dp.ptr, Dp.ptr, X.nonpiv.ptr, tptr.ptr, tcol.ptr, tval.ptr);
     F4_LAUNCH_CHECK();
 }
