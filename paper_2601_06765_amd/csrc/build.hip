@@ -24,6 +24,7 @@
 #include <cstring>
 
 #include "internal.hpp"
+#include "sort_lds.hpp"
 
 #define MB_THREADS 256
 #define MB_WAVES (MB_THREADS / F4_WAVE)
@@ -157,13 +158,21 @@ __global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, con
     }
 }
 
-// scatter the packed initial rows of every system into its row segment
-__global__ void k_init_rows(const SegSP* segs, const u64* t0, const u32* k0, u64* rows_t, u32* rows_k) {
+// scatter the packed initial rows of every system into its row segment and
+// clear the system's three bitmaps (W words apart) and its M counter
+__global__ void k_init_rows(const SegSP* segs, const u64* t0, const u32* k0, u64* rows_t, u32* rows_k, u32* bitmaps,
+                            u32 W, unsigned long long* M) {
     const SegSP S = segs[blockIdx.y];
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < S.r0; i += gridDim.x * blockDim.x) {
         rows_t[S.rbase + i] = t0[S.ibase + i];
         rows_k[S.rbase + i] = k0[S.ibase + i];
     }
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < S.nwords; i += gridDim.x * blockDim.x) {
+        bitmaps[S.wbase + i] = 0;
+        bitmaps[W + S.wbase + i] = 0;
+        bitmaps[2 * (u64)W + S.wbase + i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) M[blockIdx.y] = 0;
 }
 
 // frontier = seen and not processed (flat over all bitmap words)
@@ -358,6 +367,117 @@ __global__ void k_sp_summary(const SegSP* segs, u32 S, const u32* ctr, const u32
     }
 }
 
+// End of the closure of a small batch in one workgroup: the frontier scan
+// (convergence; empty without closure), the seen and leading-monomial scans
+// (dictionary offsets, pivot counts), M per system and the summary -
+// k_words_small modes 1 and 2, k_sum_len and k_sp_summary in one launch.
+#define SUMMARY_SMALL_S 256
+#define SUMMARY_SMALL_ROWS 65536
+__global__ __launch_bounds__(1024) void k_summary_small(const SegSP* segs, u32 S, const u32* present,
+                                                        const u32* done, const u32* lead, u32 W, int closure,
+                                                        const u32* rows_k, const u32* ctr, u32* fcnt, u32* pcnt,
+                                                        u32* lcnt, u32* out) {
+    __shared__ u32 s_wave[33];
+    __shared__ unsigned long long s_M[SUMMARY_SMALL_S];
+    const u32 tid = threadIdx.x;
+    for (u32 sy = tid; sy < S; sy += 1024) s_M[sy] = 0;
+    u32 cf = 0, cp = 0, cl = 0;
+    for (u32 base = 0; base < W; base += 1024) {
+        const u32 wi = base + tid;
+        const u32 pw = wi < W ? present[wi] : 0u;
+        const u32 f = (wi < W && closure) ? (pw & ~done[wi]) : 0u;
+        const u32 l = wi < W ? lead[wi] : 0u;
+        u32 tf, tp, tl;
+        const u32 pf = block_exclusive_scan(__popc(f), s_wave, &tf);
+        const u32 pp = block_exclusive_scan(__popc(pw), s_wave, &tp);
+        const u32 pl = block_exclusive_scan(__popc(l), s_wave, &tl);
+        if (wi < W) {
+            fcnt[wi] = cf + pf;
+            pcnt[wi] = cp + pp;
+            lcnt[wi] = cl + pl;
+        }
+        cf += tf;
+        cp += tp;
+        cl += tl;
+    }
+    if (tid == 0) {
+        fcnt[W] = cf;
+        pcnt[W] = cp;
+        lcnt[W] = cl;
+    }
+    __syncthreads();
+    // M = sum of the row lengths of each system
+    for (u32 sy = 0; sy < S; ++sy) {
+        const SegSP& G = segs[sy];
+        const u32 r = ctr[CTR * sy + 1];
+        u32 acc = 0;
+        for (u32 i = tid; i < r; i += 1024) acc += G.len[rows_k[G.rbase + i]];
+        for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, F4_WAVE);
+        if (lane_id() == 0 && acc) atomicAdd(&s_M[sy], (unsigned long long)acc);
+    }
+    __syncthreads();
+    for (u32 sy = tid; sy < S; sy += 1024) {
+        const SegSP& G = segs[sy];
+        const unsigned long long M = s_M[sy];
+        out[8 * sy + 0] = ctr[CTR * sy + 1];
+        out[8 * sy + 1] = fcnt[G.wbase + G.nwords] - fcnt[G.wbase];
+        out[8 * sy + 2] = ctr[CTR * sy + 3];
+        out[8 * sy + 3] = pcnt[G.wbase + G.nwords] - pcnt[G.wbase];
+        out[8 * sy + 4] = (u32)M;
+        out[8 * sy + 5] = (u32)(M >> 32);
+        out[8 * sy + 6] = lcnt[G.wbase + G.nwords] - lcnt[G.wbase];
+    }
+}
+
+// Row order of a small batch (at most SORT_SMALL_MAX rows) in one workgroup:
+// the keys of k_row_keys sorted in LDS, then k_gather_rows and the scan of
+// the row lengths (row_ptr) - four launches in one.
+__global__ __launch_bounds__(1024) void k_rows_small(const SegSP* segs, u32 S, const u32* row_lmrank,
+                                                     const u64* rows_t, const u32* rows_k, u32 R, u32 sshift,
+                                                     u32 kbits, u32 hi_bit, u32 digit, u64* out_t, u32* out_k,
+                                                     u32* row_ptr, u32* row_sys) {
+    extern __shared__ u64 rs_mem[];
+    u64* ka = rs_mem;
+    u64* kb = ka + SORT_SMALL_MAX;
+    u32* va = (u32*)(kb + SORT_SMALL_MAX);
+    u32* vb = va + SORT_SMALL_MAX;
+    __shared__ u32 run[256];
+    __shared__ u32 wcnt[16 * 256];
+    __shared__ u32 s_wave[33];
+    const u32 tid = threadIdx.x;
+    for (u32 sy = 0; sy < S; ++sy) {
+        const SegSP& G = segs[sy];
+        for (u32 i = tid; i < G.r; i += 1024) {
+            const u32 src = G.rbase + i;
+            ka[G.obase + i] = ((u64)sy << sshift) | ((u64)row_lmrank[src] << kbits) | rows_k[src];
+            va[G.obase + i] = src;
+        }
+    }
+    const bool sw = lds_radix_sort(ka, kb, va, vb, R, 0, hi_bit, digit, 1024, run, wcnt, s_wave);
+    const u64* rk = sw ? kb : ka;
+    const u32* rv = sw ? vb : va;
+    __syncthreads();
+    u32 carry = 0;
+    for (u32 base = 0; base < R; base += 1024) {
+        const u32 i = base + tid;
+        u32 len = 0;
+        if (i < R) {
+            const u32 src = rv[i];
+            const u32 sy = S > 1 ? (u32)(rk[i] >> sshift) : 0u;
+            const u32 k = rows_k[src];
+            out_t[i] = rows_t[src];
+            out_k[i] = k;
+            len = segs[sy].len[k];
+            row_sys[i] = sy;
+        }
+        u32 tot;
+        const u32 pre = block_exclusive_scan(len, s_wave, &tot);
+        if (i < R) row_ptr[i] = carry + pre;
+        carry += tot;
+    }
+    if (tid == 0) row_ptr[R] = carry;
+}
+
 // Row order: system, then leading monomial descending (= rank ascending), then
 // basis index.
 __global__ void k_row_keys(const SegSP* segs, const u32* row_lmrank, const u32* rows_k, u32 sshift, u32 kbits,
@@ -475,8 +595,11 @@ __global__ void k_seg_bounds(const u64* dict, const u32* N_ptr, u32 S, u32 kshif
 
 // Join: position of every row key in its system's part of the sorted
 // dictionary (binary search; in LDS when the batch has one system and fits).
+// Every key is in the dictionary by construction; the system index and the
+// position are still clamped into range so that no later kernel can index
+// outside its arrays.
 __global__ __launch_bounds__(MB_THREADS) void k_join(const u64* row_key, u64 M, const u64* dict, const u32* dstart,
-                                                      u32 kshift, int lds_dict, u32 Ncap, u32* col_ind) {
+                                                      u32 kshift, u32 S, int lds_dict, u32 Ncap, u32* col_ind) {
     extern __shared__ u64 sd[];
     if (lds_dict) {
         const u32 N = min(dstart[1] - dstart[0], Ncap);
@@ -485,10 +608,11 @@ __global__ __launch_bounds__(MB_THREADS) void k_join(const u64* row_key, u64 M, 
     }
     for (u64 e = (u64)blockIdx.x * MB_THREADS + threadIdx.x; e < M; e += (u64)gridDim.x * MB_THREADS) {
         const u64 key = row_key[e];
-        const u32 s = kshift >= 64 ? 0u : (u32)(key >> kshift);
-        const u32 a = dstart[s], bnd = dstart[s + 1];
+        const u32 s = kshift >= 64 ? 0u : min((u32)(key >> kshift), S - 1);
+        const u32 a = dstart[s], bnd = max(dstart[s + 1], a);
         const u64* Dd = lds_dict ? sd : dict + a;
-        u32 lo = 0, hi = lds_dict ? min(bnd - a, Ncap) : bnd - a;
+        const u32 n = lds_dict ? min(bnd - a, Ncap) : bnd - a;
+        u32 lo = 0, hi = n;
         while (lo < hi) {
             const u32 mid = (lo + hi) >> 1;
             if (Dd[mid] < key)
@@ -496,7 +620,7 @@ __global__ __launch_bounds__(MB_THREADS) void k_join(const u64* row_key, u64 M, 
             else
                 hi = mid;
         }
-        col_ind[e] = lo;
+        col_ind[e] = lo < n ? lo : (n ? n - 1 : 0);
     }
 }
 
@@ -611,22 +735,22 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     SegSP* const dsegs = (SegSP*)(params.ptr + o_segs);
     const u32* const active = (const u32*)(params.ptr + o_act);
     u32* const ctr = (u32*)(params.ptr + o_ctr);  // counters live in the parameter block
-    // present, done and leading-monomial bitmaps, cleared together
+    // present, done and leading-monomial bitmaps (cleared by k_init_rows)
     DBuf<u32> pd(&c.pool, 3 * W);
-    fill_u32(pd.ptr, 3 * W, 0, s);
     u32* const present = pd.ptr;
     u32* const done = pd.ptr + W;
     u32* const leadmap = pd.ptr + 2 * W;
     DBuf<u64> rows_t(&c.pool, RC);
     DBuf<u32> rows_k(&c.pool, RC), row_lmrank(&c.pool, RC);
+    DBuf<unsigned long long> Mdev(&c.pool, S);
     {
         u32 mr = 1;
-        for (u32 i = 0; i < S; ++i) mr = std::max(mr, args[i].r0);
+        for (u32 i = 0; i < S; ++i) mr = std::max(mr, std::max(args[i].r0, segs[i].nwords));
         hipLaunchKernelGGL(k_init_rows, dim3(std::min<u32>(64, ceil_div(mr, 256)), S), dim3(256), 0, s, dsegs,
-                           (const u64*)(params.ptr + o_t0), (const u32*)(params.ptr + o_k0), rows_t.ptr, rows_k.ptr);
+                           (const u64*)(params.ptr + o_t0), (const u32*)(params.ptr + o_k0), rows_t.ptr, rows_k.ptr,
+                           pd.ptr, (u32)W, Mdev.ptr);
         F4_LAUNCH_CHECK();
     }
-    DBuf<unsigned long long> Mdev(&c.pool, S);
 
     const int local_bitmap = (max_tabn + max_words) * 4 <= 48 * 1024;
     const size_t mark_lds = (max_tabn + (local_bitmap ? max_words : 0)) * 4;
@@ -653,6 +777,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     u32 rounds = 0;
     std::vector<u32> hs(8 * S);
     const bool small_words = W <= WORDS_SMALL;
+    const bool fused_summary = small_words && S <= SUMMARY_SMALL_S && RC <= SUMMARY_SMALL_ROWS;
     for (;;) {
         if (closure) {
             // two speculative rounds per host check: dense systems converge in two
@@ -677,7 +802,17 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
                 mark();
                 ++rounds;
             }
-            if (small_words) {
+        }
+        // dictionary sizes, pivot counts and M alongside the convergence check:
+        // one readback (small batches: one launch)
+        if (fused_summary) {
+            hipLaunchKernelGGL(k_summary_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, leadmap, (u32)W,
+                               closure ? 1 : 0, rows_k.ptr, ctr, fcnt.ptr, pcnt.ptr, lcnt.ptr, summary.ptr);
+            F4_LAUNCH_CHECK();
+        } else {
+            if (!closure) {
+                fill_u32(fcnt.ptr, W + 1, 0, s);
+            } else if (small_words) {
                 hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 1,
                                    fcnt.ptr, list_q.ptr, list_s.ptr, ctr, leadmap, lcnt.ptr);
                 F4_LAUNCH_CHECK();
@@ -687,28 +822,25 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
                 F4_LAUNCH_CHECK();
                 exclusive_scan_u32(fcnt.ptr, fcnt.ptr, W, c.pool, s);
             }
-        } else {
-            fill_u32(fcnt.ptr, W + 1, 0, s);
+            if (small_words) {
+                hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 2,
+                                   pcnt.ptr, list_q.ptr, list_s.ptr, ctr, leadmap, lcnt.ptr);
+                F4_LAUNCH_CHECK();
+            } else {
+                hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, present, (u32)W, pcnt.ptr);
+                F4_LAUNCH_CHECK();
+                exclusive_scan_u32(pcnt.ptr, pcnt.ptr, W, c.pool, s);
+                hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, leadmap, (u32)W, lcnt.ptr);
+                F4_LAUNCH_CHECK();
+                exclusive_scan_u32(lcnt.ptr, lcnt.ptr, W, c.pool, s);
+            }
+            fill_u64((u64*)Mdev.ptr, S, 0, s);
+            hipLaunchKernelGGL(k_sum_len, dim3(bx, S), dim3(256), 0, s, dsegs, rows_k.ptr, ctr, Mdev.ptr);
+            F4_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_sp_summary, dim3(grid_for(S, 256, 64)), dim3(256), 0, s, dsegs, S, ctr, fcnt.ptr,
+                               pcnt.ptr, lcnt.ptr, Mdev.ptr, summary.ptr);
+            F4_LAUNCH_CHECK();
         }
-        // dictionary sizes and M alongside the convergence check: one readback
-        if (small_words) {
-            hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 2,
-                               pcnt.ptr, list_q.ptr, list_s.ptr, ctr, leadmap, lcnt.ptr);
-            F4_LAUNCH_CHECK();
-        } else {
-            hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, present, (u32)W, pcnt.ptr);
-            F4_LAUNCH_CHECK();
-            exclusive_scan_u32(pcnt.ptr, pcnt.ptr, W, c.pool, s);
-            hipLaunchKernelGGL(k_word_popc, dim3(wgrid), dim3(256), 0, s, leadmap, (u32)W, lcnt.ptr);
-            F4_LAUNCH_CHECK();
-            exclusive_scan_u32(lcnt.ptr, lcnt.ptr, W, c.pool, s);
-        }
-        fill_u64((u64*)Mdev.ptr, S, 0, s);
-        hipLaunchKernelGGL(k_sum_len, dim3(bx, S), dim3(256), 0, s, dsegs, rows_k.ptr, ctr, Mdev.ptr);
-        F4_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sp_summary, dim3(grid_for(S, 256, 64)), dim3(256), 0, s, dsegs, S, ctr, fcnt.ptr,
-                           pcnt.ptr, lcnt.ptr, Mdev.ptr, summary.ptr);
-        F4_LAUNCH_CHECK();
         readback(c, hs.data(), summary.ptr, hs.size() * 4);
         bool more = false;
         for (u32 i = 0; i < S; ++i) {
@@ -760,22 +892,31 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     const u32 sshift = rbits + kbits;
     const u32 sbits = S > 1 ? bitlen(S - 1) : 0;
     if (sshift + sbits > 64) throw F4Error{2, "row key does not fit 64 bits"};
-    DBuf<u64> keys(&c.pool, R);
-    DBuf<u32> perm(&c.pool, R);
-    const u32 rbx = std::max<u32>(1, std::min<u32>(64, ceil_div(ceil_div(R, S), 256)));
-    hipLaunchKernelGGL(k_row_keys, dim3(rbx, S), dim3(256), 0, s, dsegs, row_lmrank.ptr, rows_k.ptr, sshift, kbits,
-                       keys.ptr, perm.ptr);
-    F4_LAUNCH_CHECK();
-    tuned_sort(c, keys.ptr, perm.ptr, R, 0, sshift + sbits);
     out.row_t.reset(&c.pool, R);
     out.row_k.reset(&c.pool, R);
     out.row_sys.reset(&c.pool, R);
     out.row_ptr.reset(&c.pool, R + 1);
-    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(R, 256, 4096)), dim3(256), 0, s, dsegs, perm.ptr, keys.ptr,
-                       S > 1 ? sshift : 64u, rows_t.ptr, rows_k.ptr, (u32)R, out.row_t.ptr, out.row_k.ptr,
-                       out.row_ptr.ptr, out.row_sys.ptr);
-    F4_LAUNCH_CHECK();
-    exclusive_scan_u32(out.row_ptr.ptr, out.row_ptr.ptr, R, c.pool, s);
+    if (R <= SORT_SMALL_MAX) {
+        const size_t lds = (size_t)SORT_SMALL_MAX * (2 * sizeof(u64) + 2 * sizeof(u32));
+        const u32 digit = c.tune.force_digit ? c.tune.force_digit : 8u;
+        hipLaunchKernelGGL(k_rows_small, dim3(1), dim3(1024), lds, s, dsegs, S, row_lmrank.ptr, rows_t.ptr,
+                           rows_k.ptr, (u32)R, sshift, kbits, sshift + sbits, digit, out.row_t.ptr,
+                           out.row_k.ptr, out.row_ptr.ptr, out.row_sys.ptr);
+        F4_LAUNCH_CHECK();
+    } else {
+        DBuf<u64> keys(&c.pool, R);
+        DBuf<u32> perm(&c.pool, R);
+        const u32 rbx = std::max<u32>(1, std::min<u32>(64, ceil_div(ceil_div(R, S), 256)));
+        hipLaunchKernelGGL(k_row_keys, dim3(rbx, S), dim3(256), 0, s, dsegs, row_lmrank.ptr, rows_k.ptr, sshift, kbits,
+                           keys.ptr, perm.ptr);
+        F4_LAUNCH_CHECK();
+        tuned_sort(c, keys.ptr, perm.ptr, R, 0, sshift + sbits);
+        hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(R, 256, 4096)), dim3(256), 0, s, dsegs, perm.ptr, keys.ptr,
+                           S > 1 ? sshift : 64u, rows_t.ptr, rows_k.ptr, (u32)R, out.row_t.ptr, out.row_k.ptr,
+                           out.row_ptr.ptr, out.row_sys.ptr);
+        F4_LAUNCH_CHECK();
+        exclusive_scan_u32(out.row_ptr.ptr, out.row_ptr.ptr, R, c.pool, s);
+    }
 
     out.col_ind.reset(&c.pool, std::max<u64>(Mtot, 1));
     out.val.reset(&c.pool, std::max<u64>(Mtot, 1));
@@ -808,7 +949,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         const int lds_dict = S == 1 && (u64)N0 * 8 <= c.dev.max_lds;
         hipLaunchKernelGGL(k_join, dim3(grid_for(Mtot, MB_THREADS, 16 * (u32)std::max(1, c.dev.cus))),
                            dim3(MB_THREADS), lds_dict ? (size_t)N0 * 8 : 0, s, row_key.ptr, Mtot, dictc.ptr,
-                           dstart.ptr, kshift, lds_dict, N0, out.col_ind.ptr);
+                           dstart.ptr, kshift, S, lds_dict, N0, out.col_ind.ptr);
         F4_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_dict_from_compact, dim3(grid_for(Mtot, 256, 2048)), dim3(256), 0, s, dsegs,
                            dictc.ptr, ncount.ptr, dstart.ptr, kshift, S, out.dict_keys.ptr);

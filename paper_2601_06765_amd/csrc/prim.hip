@@ -5,6 +5,7 @@
 //     ballot-based digit matching for the in-tile stable ranks
 //   - unique of a sorted key stream
 #include "internal.hpp"
+#include "sort_lds.hpp"
 
 // ------------------------------------------------------------------ fills
 __global__ void k_fill_u32(u32* p, u64 n, u32 v) {
@@ -194,69 +195,20 @@ __global__ __launch_bounds__(SS_THREADS) void k_sort_small(u64* keys, u32* vals,
     u32* va = (u32*)(kb + SS_MAX);
     u32* vb = va + SS_MAX;
     __shared__ u32 run[256];
-    __shared__ u32 wcnt[SS_WAVES][256];
+    __shared__ u32 wcnt[SS_WAVES * 256];
     __shared__ u32 s_wave[33];
-    const u32 tid = threadIdx.x, wave = tid / F4_WAVE, lane = lane_id();
-    const u64 lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const u32 tid = threadIdx.x;
     for (u32 i = tid; i < n; i += SS_THREADS) {
         ka[i] = keys[i];
         if (vals) va[i] = vals[i];
     }
-    for (u32 shift = lo_bit; shift < hi_bit; shift += digit) {
-        const u32 bits = (hi_bit - shift) < digit ? (hi_bit - shift) : digit;
-        const u32 mask = (1u << bits) - 1;
-        if (tid < 256) run[tid] = 0;
-        __syncthreads();
-        for (u32 i = tid; i < n; i += SS_THREADS) atomicAdd(&run[(u32)(ka[i] >> shift) & mask], 1u);
-        __syncthreads();
-        {
-            u32 tot;
-            const u32 c = tid < 256 ? run[tid] : 0u;
-            const u32 pre = block_exclusive_scan(c, s_wave, &tot);
-            if (tid < 256) run[tid] = pre;
-        }
-        __syncthreads();
-        for (u32 j0 = 0; j0 < n; j0 += SS_THREADS) {
-            for (u32 q = tid; q < SS_WAVES * 256; q += SS_THREADS) (&wcnt[0][0])[q] = 0;
-            __syncthreads();
-            const u32 i = j0 + tid;
-            const bool valid = i < n;
-            const u64 key = valid ? ka[i] : 0;
-            const u32 d = (u32)(key >> shift) & mask;
-            u64 m = wave_ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bool bit = (d >> b) & 1;
-                const u64 bb = wave_ballot(bit);
-                m &= bit ? bb : ~bb;
-            }
-            const u32 rank = __popcll(m & lt);
-            if (valid && rank == 0) wcnt[wave][d] = __popcll(m);
-            __syncthreads();
-            if (valid) {
-                u32 pos = run[d] + rank;
-                for (u32 w2 = 0; w2 < wave; ++w2) pos += wcnt[w2][d];
-                kb[pos] = key;
-                if (vals) vb[pos] = va[i];
-            }
-            __syncthreads();
-            if (tid < 256) {
-                u32 t = 0;
-                for (u32 w2 = 0; w2 < SS_WAVES; ++w2) t += wcnt[w2][tid];
-                run[tid] += t;
-            }
-            __syncthreads();
-        }
-        u64* tk = ka;
-        ka = kb;
-        kb = tk;
-        u32* tv = va;
-        va = vb;
-        vb = tv;
-    }
+    const bool sw = lds_radix_sort(ka, kb, vals ? va : nullptr, vb, n, lo_bit, hi_bit, digit, SS_THREADS, run, wcnt,
+                                   s_wave);
+    const u64* rk = sw ? kb : ka;
+    const u32* rv = sw ? vb : va;
     for (u32 i = tid; i < n; i += SS_THREADS) {
-        keys[i] = ka[i];
-        if (vals) vals[i] = va[i];
+        keys[i] = rk[i];
+        if (vals) vals[i] = rv[i];
     }
 }
 

@@ -26,6 +26,7 @@
 #include <cstring>
 
 #include "internal.hpp"
+#include "sort_lds.hpp"
 
 #define PANEL 64
 #define TR_THREADS 1024
@@ -175,10 +176,16 @@ __global__ __launch_bounds__(1024) void k_split_small(const SegR* segs, u32 S, c
 }
 
 // Trailing-entry count of each pivot row (entries beyond its own panel).
+// (also clears the system's dense panels T, filled by k_upper_fill)
 __global__ void k_upper_count(const SegR* segs, const u32* row_ptr, const u32* col_ind, const u32* prow,
-                              const u32* perm, u32* tcnt) {
+                              const u32* perm, u32* tcnt, u32* T) {
     const SegR S = segs[blockIdx.y];
     const u32 lane = lane_id();
+    {
+        u32* Ts = T + (u64)S.tb * PANEL * PANEL;
+        const u64 nT = (u64)((S.npiv + PANEL - 1) / PANEL) * PANEL * PANEL;
+        for (u64 x = (u64)blockIdx.x * blockDim.x + threadIdx.x; x < nT; x += (u64)gridDim.x * blockDim.x) Ts[x] = 0;
+    }
     const u32 nw = gridDim.x * (blockDim.x / F4_WAVE);
     for (u32 q = blockIdx.x * (blockDim.x / F4_WAVE) + threadIdx.x / F4_WAVE; q < S.npiv; q += nw) {
         const u32 i = prow[S.pb + q];
@@ -284,7 +291,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
                                                      int tail, u32 rr, u32 tile_base, int skip_lead,
                                                      const u32* perm, const u32* Tinv, const u32* tptr,
                                                      const u64* tent, typename AccOf<SMALL>::T* gacc, u32* Dp,
-                                                     u32* lead_out, unsigned long long* ops) {
+                                                     u32* lead_out, u32* status, unsigned long long* ops) {
     typedef typename AccOf<SMALL>::T AccT;
     extern __shared__ unsigned char smraw[];
     __shared__ u32 s_x[TR_MAXR][PANEL];
@@ -429,6 +436,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
     }
     __syncthreads();
     if (tid < nr && lead_out) lead_out[S.lb + t0 + tid] = s_lead[tid];
+    if (tid < nr && status) status[S.lb + t0 + tid] = 0;  // echelon row status: live
     if (ops) {
         u64 v = nops;
         for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, F4_WAVE);
@@ -812,6 +820,66 @@ __global__ void k_emit_keys(const SegR* segs, const u32* npr, const u32* prlead,
     }
 }
 
+// k_emit_keys and their sort for at most SORT_SMALL_MAX store slots in one
+// workgroup (keys and values in LDS).
+__global__ __launch_bounds__(1024) void k_emit_keys_small(const SegR* segs, u32 S, const u32* npr, const u32* prlead,
+                                                          u32 cbits, u64 sent, u32 n, u32 hi_bit, u32 digit,
+                                                          u64* keys, u32* vals) {
+    extern __shared__ u64 ek_mem[];
+    u64* ka = ek_mem;
+    u64* kb = ka + SORT_SMALL_MAX;
+    u32* va = (u32*)(kb + SORT_SMALL_MAX);
+    u32* vb = va + SORT_SMALL_MAX;
+    __shared__ u32 run[256];
+    __shared__ u32 wcnt[16 * 256];
+    __shared__ u32 s_wave[33];
+    const u32 tid = threadIdx.x;
+    for (u32 sy = 0; sy < S; ++sy) {
+        const SegR& G = segs[sy];
+        const u32 m = npr[sy];
+        for (u32 t = tid; t < G.cap; t += 1024) {
+            ka[G.capb + t] = t < m ? (((u64)sy << cbits) | prlead[G.capb + t]) : sent;
+            va[G.capb + t] = G.capb + t;
+        }
+    }
+    const bool sw = lds_radix_sort(ka, kb, va, vb, n, 0, hi_bit, digit, 1024, run, wcnt, s_wave);
+    const u64* rk = sw ? kb : ka;
+    const u32* rv = sw ? vb : va;
+    __syncthreads();
+    for (u32 i = tid; i < n; i += 1024) {
+        keys[i] = rk[i];
+        vals[i] = rv[i];
+    }
+}
+
+// Exclusive scan of the per-row counts (pos[0..n]) and the per-system totals
+// of k_emit_totals, in one workgroup (n up to a few tens of thousands).
+__global__ __launch_bounds__(1024) void k_emit_scan_totals(const u32* cnt, u32 n, const u32* npr, u32 S, u32* pos,
+                                                           u32* tot) {
+    __shared__ u32 s_wave[33];
+    const u32 tid = threadIdx.x;
+    u32 carry = 0;
+    for (u32 base = 0; base < n; base += 1024) {
+        const u32 i = base + tid;
+        const u32 v = i < n ? cnt[i] : 0u;
+        u32 t;
+        const u32 pre = block_exclusive_scan(v, s_wave, &t);
+        if (i < n) pos[i] = carry + pre;
+        carry += t;
+    }
+    if (tid == 0) pos[n] = carry;
+    __syncthreads();
+    u32 ecarry = 0;
+    for (u32 base = 0; base < S; base += 1024) {
+        const u32 i = base + tid;
+        const u32 v = i < S ? npr[i] : 0u;
+        u32 t;
+        const u32 pre = block_exclusive_scan(v, s_wave, &t);
+        if (i < S) tot[i] = pos[ecarry + pre + v] - pos[ecarry + pre];
+        ecarry += t;
+    }
+}
+
 // Row offsets of the emitted rows end where the real rows end: system s owns
 // sorted rows [eb[s], eb[s] + npr[s]) with eb the exclusive scan of npr, and
 // emits pos[eb[s] + npr[s]] - pos[eb[s]] nonzeros.  One workgroup.
@@ -1050,12 +1118,11 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
     const u32 P = X.P;
     X.tptr.reset(&c.pool, (u64)P + 1);
     X.T.reset(&c.pool, (u64)std::max<u32>(tb, 1) * PANEL * PANEL);
-    fill_u32(X.T.ptr, (u64)tb * PANEL * PANEL, 0, s);
     u32 maxP = 1;
     for (auto& g : X.segs) maxP = std::max(maxP, g.npiv);
     if (P) {
         hipLaunchKernelGGL(k_upper_count, dim3(std::min<u32>(256, ceil_div(maxP, 4)), S), dim3(256), 0, s,
-                           X.dsegs.ptr, A.row_ptr.ptr, A.col_ind.ptr, X.prow.ptr, X.perm.ptr, X.tptr.ptr);
+                           X.dsegs.ptr, A.row_ptr.ptr, A.col_ind.ptr, X.prow.ptr, X.perm.ptr, X.tptr.ptr, X.T.ptr);
         F4_LAUNCH_CHECK();
     }
     exclusive_scan_u32(X.tptr.ptr, X.tptr.ptr, P, c.pool, s);
@@ -1080,7 +1147,7 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
 // lb + cnt) are the system's rows (cnt = L, or r for the tail reduction);
 // dense trailing rows go to Dp at segs[s].dpb + local * c.
 static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* list, int tail, int skip_lead, u32* Dp,
-                     u32* lead_out, Reduced* kt) {
+                     u32* lead_out, u32* status, Reduced* kt) {
     unsigned long long* ops = kt && kt->ops.ptr ? (unsigned long long*)kt->ops.ptr : nullptr;
     hipStream_t s = c.stream;
     const u32 S = X.S;
@@ -1107,12 +1174,12 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
                     hipLaunchKernelGGL((k_trsm<true, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
                                        X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
                                        skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)nullptr, Dp,
-                                       lead_out, op);
+                                       lead_out, status, op);
                 else
                     hipLaunchKernelGGL((k_trsm<false, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
                                        X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
                                        skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, Dp,
-                                       lead_out, op);
+                                       lead_out, status, op);
                 F4_LAUNCH_CHECK();
             };
             u32 rr = rmax;
@@ -1149,12 +1216,12 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
                     hipLaunchKernelGGL((k_trsm<true, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
                                        A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
                                        X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)gacc.ptr, Dp, lead_out,
-                                       ops);
+                                       status, ops);
                 else
                     hipLaunchKernelGGL((k_trsm<false, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
                                        A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
                                        X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, Dp, lead_out,
-                                       ops);
+                                       status, ops);
                 F4_LAUNCH_CHECK();
             }
         }
@@ -1195,11 +1262,12 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
         maxcap = std::max(maxcap, g.cap);
     }
     DBuf<u32> Dp(&c.pool, std::max<u64>(Dtot, 1)), lead(&c.pool, std::max<u32>(X.Ltot, 1));
+    DBuf<u32> status(&c.pool, std::max<u32>(X.Ltot, 1));  // cleared by the solve
     if (timing_on(c)) {
         out.ops.reset(&c.pool, 2);
         fill_u64(out.ops.ptr, 2, 0, s);
     }
-    run_trsm(c, A, X, X.lower.ptr, 0, 0, Dp.ptr, lead.ptr, &out);
+    run_trsm(c, A, X, X.lower.ptr, 0, 0, Dp.ptr, lead.ptr, status.ptr, &out);
     hipEvent_t e2 = stage_event(c);
 
     // echelon of every system's D' (L x c)
@@ -1234,8 +1302,6 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
     hipEvent_t e3 = nullptr;
     std::vector<u32> hb(nback, 0);
     if (active) {
-        DBuf<u32> status(&c.pool, std::max<u32>(X.Ltot, 1));
-        fill_u32(status.ptr, X.Ltot, 0, s);
         const int cnt_lds = (size_t)maxc * 4 + 32768 <= c.dev.max_lds;
         DBuf<u32> ccnt(&c.pool, cnt_lds ? 1 : std::max<u64>(X.C, 1));
         // rounds per readback: the first batch from min(L, c) (each round yields
@@ -1261,16 +1327,30 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
             }
             batch = 4;
             e3 = stage_event(c);
-            hipLaunchKernelGGL(k_emit_keys, dim3(std::min<u32>(16, ceil_div(maxcap, 256)), S), dim3(256), 0, s,
-                               X.dsegs.ptr, ndone + 1, prlead.ptr, cbits, sent, keys.ptr, ids.ptr);
-            F4_LAUNCH_CHECK();
-            tuned_sort(c, keys.ptr, ids.ptr, CAP, 0, cbits + sbits);
+            if (CAP <= SORT_SMALL_MAX) {
+                const size_t lds = (size_t)SORT_SMALL_MAX * (2 * sizeof(u64) + 2 * sizeof(u32));
+                const u32 digit = c.tune.force_digit ? c.tune.force_digit : 8u;
+                hipLaunchKernelGGL(k_emit_keys_small, dim3(1), dim3(1024), lds, s, X.dsegs.ptr, S, ndone + 1,
+                                   prlead.ptr, cbits, sent, CAP, cbits + sbits, digit, keys.ptr, ids.ptr);
+                F4_LAUNCH_CHECK();
+            } else {
+                hipLaunchKernelGGL(k_emit_keys, dim3(std::min<u32>(16, ceil_div(maxcap, 256)), S), dim3(256), 0, s,
+                                   X.dsegs.ptr, ndone + 1, prlead.ptr, cbits, sent, keys.ptr, ids.ptr);
+                F4_LAUNCH_CHECK();
+                tuned_sort(c, keys.ptr, ids.ptr, CAP, 0, cbits + sbits);
+            }
             hipLaunchKernelGGL(k_count_nz, dim3(grid_of(CAP, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, kc,
                                sent, ids.ptr, CAP, 1, Dp.ptr, PR.ptr, cnt.ptr);
             F4_LAUNCH_CHECK();
-            exclusive_scan_u32(cnt.ptr, out.row_ptr.ptr, CAP, c.pool, s);
-            hipLaunchKernelGGL(k_emit_totals, dim3(1), dim3(1024), 0, s, ndone + 1, S, out.row_ptr.ptr, dtot);
-            F4_LAUNCH_CHECK();
+            if (CAP <= 65536) {
+                hipLaunchKernelGGL(k_emit_scan_totals, dim3(1), dim3(1024), 0, s, cnt.ptr, CAP, ndone + 1, S,
+                                   out.row_ptr.ptr, dtot);
+                F4_LAUNCH_CHECK();
+            } else {
+                exclusive_scan_u32(cnt.ptr, out.row_ptr.ptr, CAP, c.pool, s);
+                hipLaunchKernelGGL(k_emit_totals, dim3(1), dim3(1024), 0, s, ndone + 1, S, out.row_ptr.ptr, dtot);
+                F4_LAUNCH_CHECK();
+            }
             readback(c, hb.data(), ndone, nback * 4);
             if (first && X.known)
                 for (u32 i = 0; i < S; ++i)
@@ -1356,7 +1436,7 @@ void tail_reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, DBuf<
     // system of each row as a key (for the wave kernels below)
     hipLaunchKernelGGL(k_row_sys_keys, dim3(grid_of(R, 256, 1024)), dim3(256), 0, s, A.row_sys.ptr, R, keys.ptr);
     F4_LAUNCH_CHECK();
-    run_trsm(c, A, X, rows.ptr, 1, 1, Dp.ptr, nullptr, nullptr);
+    run_trsm(c, A, X, rows.ptr, 1, 1, Dp.ptr, nullptr, nullptr, nullptr);
     hipLaunchKernelGGL(k_count_nz, dim3(grid_of(R, 4, 4096)), dim3(256), 0, s, X.dsegs.ptr, keys.ptr, 32u, ~0ull,
                        rows.ptr, R, 0, Dp.ptr, Dp.ptr, cnt.ptr);
     F4_LAUNCH_CHECK();
