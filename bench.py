@@ -322,6 +322,7 @@ def main():
             "t_trsm_ms": round(avg(k, "t_trsm_ms"), 4),
             "t_echelon_ms": round(avg(k, "t_echelon_ms"), 4),
             "wall_ms": round(avg(k, "t_step_ms"), 4),
+            "t_pairs_host_ms": round(avg(k, "t_pairs_ms"), 4),
             "nnz_per_s_gpu": s0["nnz"] / (gpu_ms / 1000.0) if gpu_ms > 0 else None,
             "rows_per_s_gpu": s0["r"] / (gpu_ms / 1000.0) if gpu_ms > 0 else None,
             "hbm_frac_alg": alg / (gpu_ms / 1000.0) / (HBM_PEAK_GBS * 1e9) if gpu_ms > 0 else None,
