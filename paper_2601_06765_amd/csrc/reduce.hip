@@ -499,6 +499,24 @@ __device__ __forceinline__ u32 fp_ff<true>(const Fp& f, u32 piv, u32 a, u32 fk, 
     return (u32)r;
 }
 
+// a^-1 mod p by Fermat's little theorem with the modular product of the class
+template <bool SMALL>
+__device__ __forceinline__ u32 fp_inv_t(const Fp& f, u32 a) {
+    u32 e = f.p - 2, r = 1, x = a;
+    while (e) {
+        if (e & 1) r = fp_mul_t<SMALL>(f, r, x);
+        x = fp_mul_t<SMALL>(f, x, x);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Rows of the block per working wave in the pivot loop: ECH_B / ECH_RPW waves
+// own the rows, the others only keep the loop count (fewer copies of the
+// per-pivot bookkeeping).
+#define ECH_RPW 2
+
+template <bool SMALL>
 __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead, u32* status, const u32* Dp,
                                                     u32* cnt_g, int cnt_lds, EchRound* rounds, u32* prlead,
                                                     u32* ndone, unsigned long long* ops) {
@@ -513,6 +531,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     EchRound* R = rounds + blockIdx.y;
     if (R->done) return;
     const SegR S = segs[blockIdx.y];
+    if ((S.small != 0) != SMALL) return;  // the other class has its own launch
     const Fp f = S.f;
     const u32 L = S.L, c = S.c;
     const u32 tid = threadIdx.x;
@@ -580,9 +599,9 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     }
     if (tid < 3) s_nz[tid] = 0;
     __syncthreads();
-    const bool small = S.small != 0;
     const u32 lane = tid % F4_WAVE, wave = tid / F4_WAVE;
-    const u32 r0 = 2 * wave, r1 = 2 * wave + 1;  // block rows of this wave
+    const bool worker = wave < ECH_B / ECH_RPW;
+    const u32 rw = ECH_RPW * wave;  // block rows rw .. rw + ECH_RPW - 1 of a working wave
     u32 q = 0, pmask = 0, it = 0;
     u64 nops = 0;  // modular products (counted by lane 0 of each wave; timing option)
     // chunks of ECH_CH columns from the smallest leading column of the block;
@@ -606,7 +625,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
                 u64 acc = 0;
                 for (u32 u = 0; u < b; ++u) {
                     const u32 z = s_RZ[k * ECH_RS + ECH_CH + u];
-                    if (z) acc += small ? (u64)mul24(z, s_B[u * ECH_CH + j]) : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
+                    if (z) acc += SMALL ? (u64)mul24(z, s_B[u * ECH_CH + j]) : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
                 }
                 v = fp_reduce_any(f, acc);
                 if (j == 0) nops += (u64)b * ECH_CH;  // the row's products, counted once
@@ -618,11 +637,13 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         // s_nz[it % 3]; each step computes the next step's mask right after
         // its own row updates, so a step needs one block barrier (three
         // buffers: one read, one written, one cleared)
-        u32 jstart = 0;
-        {
+        if (worker) {
             bool nz = false;
-            if (r0 < b && !((pmask >> r0) & 1u)) nz |= s_RZ[r0 * ECH_RS + lane] != 0;
-            if (r1 < b && !((pmask >> r1) & 1u)) nz |= s_RZ[r1 * ECH_RS + lane] != 0;
+#pragma unroll
+            for (u32 h = 0; h < ECH_RPW; ++h) {
+                const u32 r = rw + h;
+                if (r < b && !((pmask >> r) & 1u)) nz |= s_RZ[r * ECH_RS + lane] != 0;
+            }
             const u64 m = wave_ballot(nz && lane < w);
             if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[it % 3], (unsigned long long)m);
         }
@@ -632,45 +653,46 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
             if (tid == 0) s_nz[(it + 2) % 3] = 0;
             if (!all) break;
             const u32 jp = __ffsll((long long)all) - 1;
-            // pivot row: the first non-pivot row nonzero at jp (row kp and the
-            // rows before it do not change in this step, so every wave agrees
-            // while the others update their rows)
-            const u32 cand = (lane < b && !((pmask >> lane) & 1u)) ? s_RZ[lane * ECH_RS + jp] : 0u;
-            const u32 kp = __ffsll((long long)wave_ballot(cand != 0)) - 1;
-            const u32 piv = s_RZ[kp * ECH_RS + jp];
-            const u32 prow = s_RZ[kp * ECH_RS + lane];
-            const u32 pm2 = pmask | (1u << kp);
-            bool nz = false;
+            if (worker) {
+                // pivot row: the first non-pivot row nonzero at jp (row kp and
+                // the rows before it do not change in this step, so every wave
+                // agrees while the others update their rows)
+                const u32 cand = (lane < b && !((pmask >> lane) & 1u)) ? s_RZ[lane * ECH_RS + jp] : 0u;
+                const u32 kp = __ffsll((long long)wave_ballot(cand != 0)) - 1;
+                const u32 piv = s_RZ[kp * ECH_RS + jp];
+                const u32 prow = s_RZ[kp * ECH_RS + lane];
+                const u32 pm2 = pmask | (1u << kp);
+                bool nz = false;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const u32 r = h ? r1 : r0;
-                if (r >= b || r == kp) continue;
-                const u32 fk = s_RZ[r * ECH_RS + jp];
-                u32 val = s_RZ[r * ECH_RS + lane];
-                if (fk) {
-                    val = small ? fp_ff<true>(f, piv, val, fk, prow) : fp_ff<false>(f, piv, val, fk, prow);
-                    s_RZ[r * ECH_RS + lane] = val;
-                    if (lane == 0) nops += 2 * ECH_W;
-                    if (lane == 0 && ((pmask >> r) & 1u)) s_pv[r] = fp_mul(f, s_pv[r], piv);
+                for (u32 h = 0; h < ECH_RPW; ++h) {
+                    const u32 r = rw + h;
+                    if (r >= b || r == kp) continue;
+                    const u32 fk = s_RZ[r * ECH_RS + jp];
+                    u32 val = s_RZ[r * ECH_RS + lane];
+                    if (fk) {
+                        val = fp_ff<SMALL>(f, piv, val, fk, prow);
+                        s_RZ[r * ECH_RS + lane] = val;
+                        if (lane == 0) nops += 2 * ECH_W;
+                        if (lane == 0 && ((pmask >> r) & 1u)) s_pv[r] = fp_mul_t<SMALL>(f, s_pv[r], piv);
+                    }
+                    if (!((pm2 >> r) & 1u)) nz |= val != 0;
                 }
-                if (!((pm2 >> r) & 1u)) nz |= val != 0;
+                if (tid == 0) {
+                    s_pcol[q] = j0 + jp;
+                    s_prow[q] = kp;
+                    s_pv[kp] = piv;
+                }
+                pmask = pm2;
+                const u64 m = wave_ballot(nz && lane > jp && lane < w);
+                if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[(it + 1) % 3], (unsigned long long)m);
             }
-            if (tid == 0) {
-                s_pcol[q] = j0 + jp;
-                s_prow[q] = kp;
-                s_pv[kp] = piv;
-            }
-            pmask = pm2;
             ++q;
-            jstart = jp + 1;
-            const u64 m = wave_ballot(nz && lane >= jstart && lane < w);
-            if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[(it + 1) % 3], (unsigned long long)m);
             ++it;
             __syncthreads();
         }
     }
     // each pivot row is s_pv times its normalised form
-    if (tid < q) s_inv[tid] = fp_inv(f, s_pv[s_prow[tid]]);
+    if (tid < q) s_inv[tid] = fp_inv_t<SMALL>(f, s_pv[s_prow[tid]]);
     __syncthreads();
     const u32 npr = R->npr;
     // round record: pivot columns, block rows and normalised Z rows of the pivots
@@ -680,7 +702,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     }
     for (u32 x = tid; x < q * ECH_B; x += 1024) {
         const u32 t = x / ECH_B, u = x % ECH_B;
-        R->Z[t * ECH_B + u] = u < b ? fp_mul(f, s_RZ[s_prow[t] * ECH_RS + ECH_CH + u], s_inv[t]) : 0u;
+        R->Z[t * ECH_B + u] = u < b ? fp_mul_t<SMALL>(f, s_RZ[s_prow[t] * ECH_RS + ECH_CH + u], s_inv[t]) : 0u;
     }
     if (tid < b) {
         R->rows[tid] = s_rows[tid];
@@ -1309,15 +1331,23 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
         u32 maxlc = 0;
         for (const SegR& g : X.segs) maxlc = std::max(maxlc, std::min(g.L, g.c));
         u32 batch = std::min<u32>(8, std::max<u32>(2, ceil_div(maxlc, ECH_B) + 1));
+        // the block step is compiled per prime class; a mixed batch runs both
+        bool any_small = false, any_large = false;
+        for (const SegR& g : X.segs)
+            if (g.L && g.c) (g.small ? any_small : any_large) = true;
         u32 r = 0;
         bool first = true;
         for (;;) {
             for (u32 k = 0; k < batch; ++k) {
                 hipEvent_t ka = stage_event(c);
-                hipLaunchKernelGGL(k_ech_block, dim3(1, S), dim3(1024), cnt_lds ? (size_t)maxc * 4 : 0, s,
-                                   X.dsegs.ptr, lead.ptr, status.ptr, Dp.ptr, ccnt.ptr, cnt_lds, rounds,
-                                   prlead.ptr, ndone,
-                                   out.ops.ptr ? (unsigned long long*)out.ops.ptr + 1 : nullptr);
+                unsigned long long* bops = out.ops.ptr ? (unsigned long long*)out.ops.ptr + 1 : nullptr;
+                const size_t blds = cnt_lds ? (size_t)maxc * 4 : 0;
+                if (any_small)
+                    hipLaunchKernelGGL(k_ech_block<true>, dim3(1, S), dim3(1024), blds, s, X.dsegs.ptr, lead.ptr,
+                                       status.ptr, Dp.ptr, ccnt.ptr, cnt_lds, rounds, prlead.ptr, ndone, bops);
+                if (any_large)
+                    hipLaunchKernelGGL(k_ech_block<false>, dim3(1, S), dim3(1024), blds, s, X.dsegs.ptr, lead.ptr,
+                                       status.ptr, Dp.ptr, ccnt.ptr, cnt_lds, rounds, prlead.ptr, ndone, bops);
                 F4_LAUNCH_CHECK();
                 if (ka) out.ev_block.push_back({ka, stage_event(c)});
                 hipLaunchKernelGGL(k_ech_update, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s, X.dsegs.ptr, S, ubp,
