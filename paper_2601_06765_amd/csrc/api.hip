@@ -348,7 +348,7 @@ __global__ void k_append(const AppendSeg* segs, const u32* rptr, const u32* rcol
             const u64 l = dict_keys[A.dict_base + rcol[rptr[A.row_base + t]]];
             A.lm[A.poly_base + t] = l;
             A.len[A.poly_base + t] = rptr[A.row_base + t + 1] - rptr[A.row_base + t];
-            lm_out[A.lm_out + t] = l;
+            if (lm_out) lm_out[A.lm_out + t] = l;
         }
     }
 }
@@ -494,15 +494,16 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             nl += P.rho;
             maxr = std::max<u32>(maxr, std::max<u32>(P.rho, (u32)std::min<u64>(P.nnz, 1u << 30)));
         }
-        std::vector<u64> newlm(nl);
+        // the new leading monomials came back with the echelon's sizes: the
+        // rows are appended on the device while the host updates the pairs
+        if (R.newlm.size() != nl) throw F4Error{5, "echelon rows and their leading monomials disagree"};
+        const std::vector<u64>& newlm = R.newlm;
         if (!ap.empty()) {
             DBuf<AppendSeg> dap(&c.pool, ap.size());
-            DBuf<u64> dlm(&c.pool, nl);
             upload(c, dap.ptr, ap.data(), ap.size() * sizeof(AppendSeg));
             hipLaunchKernelGGL(k_append, dim3(gridn(maxr, 256, 64), (u32)ap.size()), dim3(256), 0, c.stream, dap.ptr,
-                               R.row_ptr.ptr, R.col_ind.ptr, R.val.ptr, A.dict_keys.ptr, dlm.ptr);
+                               R.row_ptr.ptr, R.col_ind.ptr, R.val.ptr, A.dict_keys.ptr, (u64*)nullptr);
             F4_LAUNCH_CHECK();
-            readback(c, newlm.data(), dlm.ptr, (u64)nl * 8);
         }
         A.read_times();
         R.read_times();

@@ -286,6 +286,9 @@ struct RedPart {
 struct Reduced {
     u32 S = 0;
     std::vector<RedPart> sys;
+    // leading monomial of every echelon row (row order), when the matrix
+    // carries its dictionary: read back with the echelon's sizes
+    std::vector<u64> newlm;
     DBuf<u32> pivot_cols, row_ptr, col_ind, val;  // row_ptr holds batch-global offsets
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_split = 0, t_trsm = 0, t_echelon = 0, t_emit = 0;

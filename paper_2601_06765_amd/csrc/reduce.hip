@@ -47,6 +47,7 @@ struct SegR {
     u32 ub;        // first block of the system in the echelon update grid
     u64 dpb;       // D' base (u32 entries, row stride c)
     u64 prb;       // pivot-row store base (u32 entries, row stride c)
+    u32 db;        // dictionary base of the system in the matrix's dict_keys
 };
 
 // ------------------------------------------------------------------ split
@@ -874,10 +875,30 @@ __global__ __launch_bounds__(1024) void k_emit_keys_small(const SegR* segs, u32 
     }
 }
 
+// Leading monomial of every sorted pivot-row slot: the dictionary key of its
+// leading column (0 for unused slots, or when the matrix has no dictionary).
+__device__ __forceinline__ u64 emit_lm(const SegR* segs, const u64* keys, u32 i, u32 kc, u64 sent, const u32* nonpiv,
+                                       const u64* dict_keys) {
+    const u64 key = keys[i];
+    if (key == sent || !dict_keys) return 0;
+    const u32 s = kc >= 64 ? 0u : (u32)(key >> kc);
+    const u32 lead = kc >= 64 ? (u32)key : (u32)(key & ((1ull << kc) - 1));
+    const SegR& G = segs[s];
+    return dict_keys[G.db + nonpiv[G.nb + lead]];
+}
+__global__ void k_emit_lms(const SegR* segs, const u64* keys, u32 n, u32 kc, u64 sent, const u32* nonpiv,
+                           const u64* dict_keys, u64* lm) {
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        lm[i] = emit_lm(segs, keys, i, kc, sent, nonpiv, dict_keys);
+}
+
 // Exclusive scan of the per-row counts (pos[0..n]) and the per-system totals
-// of k_emit_totals, in one workgroup (n up to a few tens of thousands).
+// of k_emit_totals, in one workgroup (n up to a few tens of thousands), and
+// the leading monomials of k_emit_lms.
 __global__ __launch_bounds__(1024) void k_emit_scan_totals(const u32* cnt, u32 n, const u32* npr, u32 S, u32* pos,
-                                                           u32* tot) {
+                                                           u32* tot, const SegR* segs, const u64* keys, u32 kc,
+                                                           u64 sent, const u32* nonpiv, const u64* dict_keys,
+                                                           u64* lm) {
     __shared__ u32 s_wave[33];
     const u32 tid = threadIdx.x;
     u32 carry = 0;
@@ -900,6 +921,7 @@ __global__ __launch_bounds__(1024) void k_emit_scan_totals(const u32* cnt, u32 n
         if (i < S) tot[i] = pos[ecarry + pre + v] - pos[ecarry + pre];
         ecarry += t;
     }
+    for (u32 i = tid; i < n; i += 1024) lm[i] = emit_lm(segs, keys, i, kc, sent, nonpiv, dict_keys);
 }
 
 // Row offsets of the emitted rows end where the real rows end: system s owns
@@ -1058,6 +1080,7 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
         g.N = A.sys[i].N;
         g.cb = (u32)C;
         g.rb = A.sys[i].row_base;
+        g.db = A.sys[i].dict_base;
         g.r = A.sys[i].r;
         C += g.N;
     }
@@ -1263,13 +1286,17 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
     const u32 S = A.S;
     const size_t rbytes = ((size_t)S * sizeof(EchRound) + 255) & ~(size_t)255;
     const size_t o_nd = (rbytes + ((size_t)S + 1) * 4 + 255) & ~(size_t)255;
-    const size_t nback = (size_t)(S + 1) + 2 * (size_t)S + S;  // words read back
-    DBuf<u8> eparams(&c.pool, o_nd + nback * 4);
+    const size_t nback = (size_t)(S + 1) + 2 * (size_t)S + S;  // words read back, then the leading monomials
+    u32 CAP0 = 0;  // pivot-row store slots: sum of min(L, c) <= sum of min(r, N)
+    for (const SysPart& P : A.sys) CAP0 += std::min(P.r, P.N);
+    const size_t o_lm = (o_nd + nback * 4 + 7) & ~(size_t)7;
+    DBuf<u8> eparams(&c.pool, o_lm + (size_t)CAP0 * 8);
     EchRound* const rounds = (EchRound*)eparams.ptr;
     u32* const ubp = (u32*)(eparams.ptr + rbytes);
     u32* const ndone = (u32*)(eparams.ptr + o_nd);  // [0] done count, [1 + s] pivot rows of system s
     u32* const dsumm = ndone + S + 1;               // split counts: pivots, lower rows
     u32* const dtot = dsumm + 2 * S;                // emitted nonzeros per system
+    u64* const dlm = (u64*)(eparams.ptr + o_lm);    // leading monomial per sorted pivot-row slot
     SplitState X;
     do_split(c, p, A, X, dsumm);
     hipEvent_t e1 = stage_event(c);
@@ -1322,7 +1349,7 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
     DBuf<u64> keys(&c.pool, std::max<u32>(CAP, 1));
     DBuf<u32> ids(&c.pool, std::max<u32>(CAP, 1)), cnt(&c.pool, (u64)CAP + 1);
     hipEvent_t e3 = nullptr;
-    std::vector<u32> hb(nback, 0);
+    std::vector<u32> hb((o_lm - o_nd) / 4 + 2 * (size_t)CAP0, 0);
     if (active) {
         const int cnt_lds = (size_t)maxc * 4 + 32768 <= c.dev.max_lds;
         DBuf<u32> ccnt(&c.pool, cnt_lds ? 1 : std::max<u64>(X.C, 1));
@@ -1374,14 +1401,19 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
             F4_LAUNCH_CHECK();
             if (CAP <= 65536) {
                 hipLaunchKernelGGL(k_emit_scan_totals, dim3(1), dim3(1024), 0, s, cnt.ptr, CAP, ndone + 1, S,
-                                   out.row_ptr.ptr, dtot);
+                                   out.row_ptr.ptr, dtot, X.dsegs.ptr, keys.ptr, kc, sent, X.nonpiv.ptr,
+                                   A.dict_keys.ptr, dlm);
                 F4_LAUNCH_CHECK();
             } else {
                 exclusive_scan_u32(cnt.ptr, out.row_ptr.ptr, CAP, c.pool, s);
                 hipLaunchKernelGGL(k_emit_totals, dim3(1), dim3(1024), 0, s, ndone + 1, S, out.row_ptr.ptr, dtot);
                 F4_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_emit_lms, dim3(grid_of(CAP, 256, 4096)), dim3(256), 0, s, X.dsegs.ptr,
+                                   keys.ptr, CAP, kc, sent, X.nonpiv.ptr, A.dict_keys.ptr, dlm);
+                F4_LAUNCH_CHECK();
             }
-            readback(c, hb.data(), ndone, nback * 4);
+            // counts and the leading monomials of the sorted slots, one copy
+            readback(c, hb.data(), ndone, o_lm + (size_t)CAP * 8 - o_nd);
             if (first && X.known)
                 for (u32 i = 0; i < S; ++i)
                     if (hb[S + 1 + 2 * i] != X.segs[i].npiv || hb[S + 2 + 2 * i] != X.segs[i].L)
@@ -1390,10 +1422,15 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
             if (hb[0] >= active) break;
             if (r > CAP + 8 + 4 * (X.Ltot / ECH_B + 1)) throw F4Error{5, "echelon did not converge"};
         }
+        u32 etot = 0;
         for (u32 i = 0; i < S; ++i) {
             npr[i] = hb[1 + i];
             rnnz[i] = hb[1 + 3 * S + i];
+            etot += npr[i];
         }
+        // leading monomials of the emitted rows, in row order
+        const u64* hl = (const u64*)(hb.data() + (o_lm - o_nd) / 4);
+        out.newlm.assign(hl, hl + etot);
     } else {
         if (X.known) {
             readback(c, hb.data(), ndone, nback * 4);
