@@ -9,6 +9,8 @@
 // SP on the device (build.hip), the elimination (reduce.hip), and appends the
 // reduced trailing rows to G on the device (pipeline step "Reconstruction").
 #include <algorithm>
+#include <exception>
+#include <mutex>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -116,6 +118,33 @@ float event_ms(hipEvent_t a, hipEvent_t b) {
 }
 
 #include "pairs.hpp"
+#include "workpool.hpp"
+
+// Per-system host work of a batch iteration (pair selection, pair updates):
+// independent per system, so large batches spread it over the context's
+// host threads (up to 8 with the caller); the first error is rethrown.
+static void for_systems(Ctx& c, size_t n, const std::function<void(size_t)>& f) {
+    if (n < 8) {
+        for (size_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    if (!c.cpu) {
+        unsigned hw = std::thread::hardware_concurrency();
+        if (hw == 0) hw = 1;
+        c.cpu = new WorkPool(std::min(hw, 8u) - 1);
+    }
+    std::mutex em;
+    std::exception_ptr first;
+    c.cpu->run((unsigned)n, [&](unsigned i) {
+        try {
+            f(i);
+        } catch (...) {
+            std::lock_guard<std::mutex> g(em);
+            if (!first) first = std::current_exception();
+        }
+    });
+    if (first) std::rethrow_exception(first);
+}
 
 struct DevG {
     u32 n = 0, npolys = 0;
@@ -439,9 +468,10 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
         for (SysState* S : sys)
             if (!S->done && !S->unit && !S->P.empty()) work.push_back(S);
         if (work.empty()) return 0;
-        std::vector<BuildArgs> args;
-        std::vector<u32> primes;
-        for (SysState* S : work) {
+        std::vector<BuildArgs> args(work.size());
+        std::vector<u32> primes(work.size());
+        for_systems(c, work.size(), [&](size_t wi) {
+            SysState* S = work[wi];
             S->t0 = std::chrono::steady_clock::now();
             const auto tp0 = S->t0;
             u32 d = 255;
@@ -459,9 +489,9 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             S->d = d;
             S->nsel = (u32)sel.size();
             S->tpairs = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - tp0).count();
-            args.push_back(args_of(*S, true));
-            primes.push_back(S->p);
-        }
+            args[wi] = args_of(*S, true);
+            primes[wi] = S->p;
+        });
         Matrix A;
         build_batch(c, args, A);
         Reduced R;
@@ -507,7 +537,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
         }
         A.read_times();
         R.read_times();
-        for (size_t i = 0; i < work.size(); ++i) {
+        for_systems(c, work.size(), [&](size_t i) {
             SysState& S = *work[i];
             const RedPart& P = R.sys[i];
             const SysPart& M = A.sys[i];
@@ -555,7 +585,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             st.t_step_ms = std::chrono::duration<float, std::milli>(tg1 - S.t0).count();
             S.steps.push_back(st);
             if (c.stop_deg && S.d == c.stop_deg && !S.unit) S.done = true;  // stopped: no basis
-        }
+        });
         c.ev_used = 0;
         return work.size();
     }
@@ -732,6 +762,7 @@ int f4_destroy(f4_ctx* X) {
     if (X->c.staging_done) (void)hipEventDestroy(X->c.staging_done);
     if (X->c.pinned) (void)hipHostFree(X->c.pinned);
     if (X->c.own_stream) (void)hipStreamDestroy(X->c.own_stream);
+    delete X->c.cpu;
     delete X;
     return F4_OK;
 }

@@ -140,6 +140,7 @@ void unique_sorted_u64(const u64* keys, u64 n, u64* out, u32* d_count, Pool& poo
 
 // ----------------------------------------------------------------- context
 struct StepTimer;
+struct WorkPool;  // host threads for per-system work of a batch (workpool.hpp)
 
 struct DevInfo {
     int device = 0;
@@ -176,6 +177,7 @@ struct Ctx {
         u32 force_rr = 0, force_digit = 0;
         std::map<u64, u32> table;
     } tune;
+    WorkPool* cpu = nullptr;  // created on first use, joined by f4_destroy
 };
 
 // ------------------------------------------------------------- autotuner
