@@ -392,7 +392,65 @@ __global__ void k_tail_words(const u32* tptr, const u32* tcol, const u32* row_sy
 }
 
 // Normalise one input system and insert its polynomials (Gebauer-Moeller).
-static void init_system(Ctx& c, SysState& S, u32 p, const f4_polys* F) {
+// Input bases of one or more systems staged for one upload: per system its
+// device arrays and its slice of the packed terms (offsets local to the
+// system); k_init_bases copies every slice and forms the leading monomials
+// and lengths.
+struct InitSeg {
+    u64* mon;
+    u32* coeff;
+    u64* off;
+    u64* lm;
+    u32* len;
+    u64 t0, o0;  // first term and first offset of the system in the pack
+    u32 nt, np;
+};
+struct InitPack {
+    std::vector<InitSeg> segs;
+    std::vector<u64> mon, off;
+    std::vector<u32> coeff;
+};
+
+__global__ void k_init_bases(const InitSeg* segs, const u64* mon, const u32* coeff, const u64* off) {
+    const InitSeg g = segs[blockIdx.y];
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nt; t += gridDim.x * blockDim.x) {
+        g.mon[t] = mon[g.t0 + t];
+        g.coeff[t] = coeff[g.t0 + t];
+    }
+    for (u32 k = blockIdx.x * blockDim.x + threadIdx.x; k <= g.np; k += gridDim.x * blockDim.x) {
+        const u64 o = off[g.o0 + k];
+        g.off[k] = o;
+        if (k < g.np) {
+            g.lm[k] = mon[g.t0 + o];
+            g.len[k] = (u32)(off[g.o0 + k + 1] - o);
+        }
+    }
+}
+
+// One upload and one launch for every staged system.
+static void init_flush(Ctx& c, InitPack& pk) {
+    if (pk.segs.empty()) return;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_mon = al(pk.segs.size() * sizeof(InitSeg));
+    const size_t o_coeff = o_mon + al(pk.mon.size() * 8);
+    const size_t o_off = o_coeff + al(pk.coeff.size() * 4);
+    std::vector<u8> buf(o_off + pk.off.size() * 8);
+    std::memcpy(buf.data(), pk.segs.data(), pk.segs.size() * sizeof(InitSeg));
+    std::memcpy(buf.data() + o_mon, pk.mon.data(), pk.mon.size() * 8);
+    std::memcpy(buf.data() + o_coeff, pk.coeff.data(), pk.coeff.size() * 4);
+    std::memcpy(buf.data() + o_off, pk.off.data(), pk.off.size() * 8);
+    DBuf<u8> d(&c.pool, buf.size());
+    upload(c, d.ptr, buf.data(), buf.size());
+    u32 mx = 1;
+    for (const InitSeg& g : pk.segs) mx = std::max(mx, std::max(g.nt, g.np + 1));
+    hipLaunchKernelGGL(k_init_bases, dim3(gridn(mx, 256, 64), (u32)pk.segs.size()), dim3(256), 0, c.stream,
+                       (const InitSeg*)d.ptr, (const u64*)(d.ptr + o_mon), (const u32*)(d.ptr + o_coeff),
+                       (const u64*)(d.ptr + o_off));
+    F4_LAUNCH_CHECK();
+    pk = InitPack();
+}
+
+static void init_system(Ctx& c, SysState& S, u32 p, const f4_polys* F, InitPack& pk) {
     if (!F || F->on_device || F->n == 0 || F->n > 14 || !is_odd_prime(p) || p >= (1u << 31))
         throw F4Error{F4_E_ARG, "bad argument"};
     const u32 n = F->n;
@@ -444,14 +502,14 @@ static void init_system(Ctx& c, SysState& S, u32 p, const f4_polys* F) {
         off.push_back(mon.size());
     }
     devg_reserve(c, D, 16 * mon.size(), 16 * (u32)inputs.size());
-    upload(c, D.mon.ptr, mon.data(), mon.size() * 8);
-    upload(c, D.coeff.ptr, coeff.data(), coeff.size() * 4);
-    upload(c, D.off.ptr, off.data(), off.size() * 8);
     D.npolys = (u32)inputs.size();
     D.nterms = mon.size();
-    hipLaunchKernelGGL(k_basis_meta, dim3(gridn(D.npolys, 256, 1024)), dim3(256), 0, c.stream, D.mon.ptr, D.off.ptr,
-                       0u, D.npolys, D.lm.ptr, D.len.ptr);
-    F4_LAUNCH_CHECK();
+    if (mon.size() >= (1ull << 32)) throw F4Error{F4_E_RANGE, "input too large"};
+    pk.segs.push_back({D.mon.ptr, D.coeff.ptr, D.off.ptr, D.lm.ptr, D.len.ptr, pk.mon.size(), pk.off.size(),
+                       (u32)mon.size(), D.npolys});
+    pk.mon.insert(pk.mon.end(), mon.begin(), mon.end());
+    pk.coeff.insert(pk.coeff.end(), coeff.begin(), coeff.end());
+    pk.off.insert(pk.off.end(), off.begin(), off.end());
     for (u32 k = 0; k < D.npolys; ++k) {
         S.lm.push_back(inputs[k][0].first);
         S.active.push_back(0);
@@ -1051,7 +1109,9 @@ int f4_groebner(f4_ctx* X, uint32_t p, const f4_polys* F, f4_basis** gb, void* s
     *gb = nullptr;
     set_stream(X, stream);
     SysState S;
-    init_system(X->c, S, p, F);
+    InitPack pk;
+    init_system(X->c, S, p, F, pk);
+    init_flush(X->c, pk);
     std::vector<SysState*> v{&S};
     run_f4(X->c, v);
     f4_basis* B = basis_of(X, S);
@@ -1068,11 +1128,13 @@ int f4_groebner_batch(f4_ctx* X, uint32_t nsys, const uint32_t* p, const f4_poly
     set_stream(X, stream);
     std::vector<std::unique_ptr<SysState>> own(nsys);
     std::vector<SysState*> v;
+    InitPack pk;
     for (u32 i = 0; i < nsys; ++i) {
         own[i].reset(new SysState());
-        init_system(X->c, *own[i], p[i], &F[i]);
+        init_system(X->c, *own[i], p[i], &F[i], pk);
         v.push_back(own[i].get());
     }
+    init_flush(X->c, pk);
     run_f4(X->c, v);
     for (u32 i = 0; i < nsys; ++i) {
         gb[i] = basis_of(X, *own[i]);
@@ -1161,7 +1223,9 @@ int f4_server_submit(f4_server* srv, uint32_t p, const f4_polys* F, uint64_t* ti
     ServerReq r;
     r.footprint = fp;
     r.st.reset(new SysState());
-    init_system(X->c, *r.st, p, F);
+    InitPack pk;
+    init_system(X->c, *r.st, p, F, pk);
+    init_flush(X->c, pk);
     srv->used += fp;
     const u64 t = srv->next_ticket++;
     srv->reqs.emplace(t, std::move(r));
