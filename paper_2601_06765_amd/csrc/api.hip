@@ -178,14 +178,60 @@ static u32 gridn(u64 items, u32 per, u32 cap) {
     return (u32)std::max<u64>(1, std::min<u64>(g, cap));
 }
 
-static void devg_reserve(Ctx& c, DevG& G, u64 terms, u32 polys) {
+// Device copies deferred to one launch (k_copy_jobs): the basis arrays of
+// many systems regrow in the same iteration.  The replaced buffers are kept
+// until the copies are enqueued, so the pool cannot hand them out before.
+struct CopyJob {
+    const u32* src;
+    u32* dst;
+    u64 words;
+};
+struct CopyBatch {
+    std::vector<CopyJob> jobs;
+    std::vector<DBuf<u64>> keep64;
+    std::vector<DBuf<u32>> keep32;
+};
+
+__global__ void k_copy_jobs(const CopyJob* jobs) {
+    const CopyJob J = jobs[blockIdx.y];
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < J.words; i += (u64)gridDim.x * blockDim.x)
+        J.dst[i] = J.src[i];
+}
+
+static void copy_flush(Ctx& c, CopyBatch& cb) {
+    if (!cb.jobs.empty()) {
+        if (cb.jobs.size() > 65535) throw F4Error{2, "too many deferred copies"};
+        DBuf<u8> d(&c.pool, cb.jobs.size() * sizeof(CopyJob));
+        upload(c, d.ptr, cb.jobs.data(), cb.jobs.size() * sizeof(CopyJob));
+        u64 mx = 1;
+        for (const CopyJob& j : cb.jobs) mx = std::max(mx, j.words);
+        hipLaunchKernelGGL(k_copy_jobs, dim3(gridn(mx, 256, 256), (u32)cb.jobs.size()), dim3(256), 0, c.stream,
+                           (const CopyJob*)d.ptr);
+        F4_LAUNCH_CHECK();
+    }
+    cb = CopyBatch();  // the replaced buffers go back to the pool after the copies were enqueued
+}
+
+// Grow the basis arrays to hold `terms` terms and `polys` polynomials (4x
+// steps).  With `cb`, the copies of the existing contents are deferred to
+// copy_flush; otherwise they are enqueued at once.
+static void devg_reserve(Ctx& c, DevG& G, u64 terms, u32 polys, CopyBatch* cb = nullptr) {
+    auto copy = [&](const void* src, void* dst, u64 bytes) {
+        if (!bytes) return;
+        if (cb)
+            cb->jobs.push_back({(const u32*)src, (u32*)dst, bytes / 4});
+        else
+            F4_HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.stream));
+    };
     if (terms > G.cap_terms) {
         u64 cap = std::max<u64>(terms, 4 * G.cap_terms);  // few regrowths: each copies the basis
         DBuf<u64> m2(&c.pool, cap);
         DBuf<u32> c2(&c.pool, cap);
-        if (G.nterms) {
-            F4_HIP_TRY(hipMemcpyAsync(m2.ptr, G.mon.ptr, G.nterms * 8, hipMemcpyDeviceToDevice, c.stream));
-            F4_HIP_TRY(hipMemcpyAsync(c2.ptr, G.coeff.ptr, G.nterms * 4, hipMemcpyDeviceToDevice, c.stream));
+        copy(G.mon.ptr, m2.ptr, G.nterms * 8);
+        copy(G.coeff.ptr, c2.ptr, G.nterms * 4);
+        if (cb) {
+            cb->keep64.push_back(std::move(G.mon));
+            cb->keep32.push_back(std::move(G.coeff));
         }
         G.mon = std::move(m2);
         G.coeff = std::move(c2);
@@ -196,9 +242,14 @@ static void devg_reserve(Ctx& c, DevG& G, u64 terms, u32 polys) {
         DBuf<u64> o2(&c.pool, cap), l2(&c.pool, cap);
         DBuf<u32> n2(&c.pool, cap);
         if (G.npolys) {
-            F4_HIP_TRY(hipMemcpyAsync(o2.ptr, G.off.ptr, ((u64)G.npolys + 1) * 8, hipMemcpyDeviceToDevice, c.stream));
-            F4_HIP_TRY(hipMemcpyAsync(l2.ptr, G.lm.ptr, (u64)G.npolys * 8, hipMemcpyDeviceToDevice, c.stream));
-            F4_HIP_TRY(hipMemcpyAsync(n2.ptr, G.len.ptr, (u64)G.npolys * 4, hipMemcpyDeviceToDevice, c.stream));
+            copy(G.off.ptr, o2.ptr, ((u64)G.npolys + 1) * 8);
+            copy(G.lm.ptr, l2.ptr, (u64)G.npolys * 8);
+            copy(G.len.ptr, n2.ptr, (u64)G.npolys * 4);
+        }
+        if (cb) {
+            cb->keep64.push_back(std::move(G.off));
+            cb->keep64.push_back(std::move(G.lm));
+            cb->keep32.push_back(std::move(G.len));
         }
         G.off = std::move(o2);
         G.lm = std::move(l2);
@@ -556,6 +607,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
         reduce_batch(c, primes, A, R);
         // ---- new elements: append the echelon rows to each basis on the device
         std::vector<AppendSeg> ap;
+        CopyBatch grow;  // basis regrowths of this iteration, copied in one launch
         std::vector<u32> lmbase(work.size(), 0);
         u32 nl = 0, maxr = 1;
         for (size_t i = 0; i < work.size(); ++i) {
@@ -563,7 +615,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             const RedPart& P = R.sys[i];
             lmbase[i] = nl;
             if (!P.rho) continue;
-            devg_reserve(c, S.D, S.D.nterms + P.nnz, S.D.npolys + P.rho);
+            devg_reserve(c, S.D, S.D.nterms + P.nnz, S.D.npolys + P.rho, &grow);
             AppendSeg g;
             std::memset(&g, 0, sizeof(g));
             g.row_base = P.row_base;
@@ -586,6 +638,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
         // rows are appended on the device while the host updates the pairs
         if (R.newlm.size() != nl) throw F4Error{5, "echelon rows and their leading monomials disagree"};
         const std::vector<u64>& newlm = R.newlm;
+        copy_flush(c, grow);
         if (!ap.empty()) {
             DBuf<AppendSeg> dap(&c.pool, ap.size());
             upload(c, dap.ptr, ap.data(), ap.size() * sizeof(AppendSeg));
