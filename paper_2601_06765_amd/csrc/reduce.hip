@@ -721,7 +721,111 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     }
 }
 
-// One kernel per round after the block step, one workgroup per row slot of a
+// The same update for many rows (large batches): one wave per row slot of a
+// system (remaining rows of D': the first L slots; the pivot-row store: the
+// next cap slots), ECH_UPW slots per workgroup.  Store slots npr0 ..
+// npr0+q-1 form this round's new pivot rows NP_t = sum_u Z[t][u] * (block row
+// u).  Every other live row r loses its entries on the round's pivot columns:
+// with coef_t = r[col_t], r - sum_t coef_t NP_t = r - sum_u w_u (block row u),
+// w = coef * Z, so the update reads the block rows directly and does not wait
+// for NP.  Lane u of the wave holds block row u and its weight w_u (read
+// across the wave with shuffles), and the 32 block-row entries of a column
+// are loaded together; no LDS and no workgroup barrier.
+#define ECH_UPW 4
+__global__ __launch_bounds__(64 * ECH_UPW) void k_ech_update_wave(const SegR* segs, u32 S, const u32* ubase, u32* Dp,
+                                                             u32* status, u32* lead, const EchRound* rounds,
+                                                             u32* PR) {
+    const u32 lane = lane_id();
+    const u32 u = blockIdx.x * ECH_UPW + threadIdx.x / F4_WAVE;
+    if (u >= ubase[S]) return;
+    u32 lo = 0, hi = S;  // system: last s with ubase[s] <= u
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (ubase[mid] <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const u32 s = lo;
+    const EchRound* R = rounds + s;
+    if (R->done) return;
+    const SegR G = segs[s];
+    const Fp f = G.f;
+    const bool small = G.small != 0;
+    const u32 c = G.c, q = R->q, b = R->b, npr0 = R->npr0;
+    const u32 local = u - G.ub;
+    const u32* D = Dp + G.dpb;
+    u32* row;
+    bool is_rem, form = false;
+    u32 t = 0;
+    if (local < G.L) {
+        if (status[G.lb + local] != 0 || lead[G.lb + local] >= c) return;
+        row = Dp + G.dpb + (u64)local * c;
+        is_rem = true;
+    } else {
+        const u32 k = local - G.L;
+        if (k >= npr0 + q) return;
+        row = PR + G.prb + (u64)k * c;
+        is_rem = false;
+        if (k >= npr0) {
+            form = true;
+            t = k - npr0;
+        }
+    }
+    // block rows and weights of lanes 0 .. b-1 broadcast to every lane once,
+    // while the whole wave is active (the column loops below may not be)
+    const u32 brow = lane < b ? R->rows[lane] : 0u;
+    u64 rbase[ECH_B];
+#pragma unroll
+    for (u32 v = 0; v < ECH_B; ++v) rbase[v] = (u64)(u32)__shfl((int)brow, (int)v, F4_WAVE) * c;
+    u32 wv[ECH_B];
+    auto spread = [&](u32 w) {
+#pragma unroll
+        for (u32 v = 0; v < ECH_B; ++v) wv[v] = (u32)__shfl((int)w, (int)v, F4_WAVE);
+    };
+    // sum_v w_v * (block row v)[j] (w is zero past b)
+    auto combo = [&](u32 j) -> u32 {
+        u32 x[ECH_B];
+#pragma unroll
+        for (u32 v = 0; v < ECH_B; ++v) x[v] = v < b ? D[rbase[v] + j] : 0u;
+        u64 acc = 0;
+#pragma unroll
+        for (u32 v = 0; v < ECH_B; ++v) acc += small ? (u64)mul24(wv[v], x[v]) : (u64)fp_mul(f, wv[v], x[v]);
+        return fp_reduce_any(f, acc);
+    };
+    if (form) {
+        spread(lane < b ? R->Z[t * ECH_B + lane] : 0u);
+        for (u32 j = lane; j < c; j += F4_WAVE) row[j] = combo(j);
+        return;
+    }
+    const u32 coef = lane < q ? row[R->cols[lane]] : 0u;  // coef_t in lane t
+    if (!wave_ballot(coef != 0)) return;
+    u64 acc = 0;
+    for (u32 t2 = 0; t2 < q; ++t2) {
+        const u32 cf = (u32)__shfl((int)coef, (int)t2, F4_WAVE);
+        const u32 z = lane < b ? R->Z[t2 * ECH_B + lane] : 0u;
+        acc += small ? (u64)mul24(cf, z) : (u64)fp_mul(f, cf, z);
+    }
+    spread(lane < b ? fp_reduce_any(f, acc) : 0u);
+    const u32 cmin = R->cmin;
+    u32 first = 0xffffffffu;
+    for (u32 j = cmin + lane; j < c; j += F4_WAVE) {
+        const u32 sub = combo(j);
+        const u32 old = row[j];
+        const u32 nv = old >= sub ? old - sub : old + f.p - sub;
+        row[j] = nv;
+        if (nv && j < first) first = j;
+    }
+    if (is_rem) {
+        // columns below cmin are zero for remaining rows (their lead is >= cmin)
+        for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) first = min(first, (u32)__shfl_xor((int)first, (int)d, F4_WAVE));
+        if (lane == 0) lead[G.lb + local] = first;
+    }
+}
+
+
+// One kernel per round after the block step (the form for few rows: a
+// workgroup per row slot spreads each row over 256 threads), one workgroup per row slot of a
 // system (remaining rows of D': the first L slots; the pivot-row store: the
 // next cap slots).  Store slots npr0 .. npr0+q-1 form this round's new pivot
 // rows NP_t = sum_u Z[t][u] * (block row u).  Every other live row r loses its
@@ -730,7 +834,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
 // update reads the block rows directly and does not wait for NP.  The round's
 // Z goes to LDS in one cooperative load, and each column's block-row entries
 // are loaded together (no load waits behind another).
-__global__ __launch_bounds__(256) void k_ech_update(const SegR* segs, u32 S, const u32* ubase, u32* Dp, u32* status,
+__global__ __launch_bounds__(256) void k_ech_update_row(const SegR* segs, u32 S, const u32* ubase, u32* Dp, u32* status,
                                                     u32* lead, const EchRound* rounds, u32* PR) {
     __shared__ u32 s_Z[ECH_B * ECH_B];
     __shared__ u32 s_coef[ECH_B], s_w[ECH_B], s_rows[ECH_B];
@@ -1377,8 +1481,15 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
                                        status.ptr, Dp.ptr, ccnt.ptr, cnt_lds, rounds, prlead.ptr, ndone, bops);
                 F4_LAUNCH_CHECK();
                 if (ka) out.ev_block.push_back({ka, stage_event(c)});
-                hipLaunchKernelGGL(k_ech_update, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s, X.dsegs.ptr, S, ubp,
-                                   Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr);
+                // a workgroup per row while rows are few (each row spread over
+                // 256 threads and the rows over the CUs), a wave per row for
+                // a few thousand rows and more
+                if (UB >= 2048)
+                    hipLaunchKernelGGL(k_ech_update_wave, dim3(ceil_div(UB, ECH_UPW)), dim3(64 * ECH_UPW), 0, s,
+                                       X.dsegs.ptr, S, ubp, Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr);
+                else
+                    hipLaunchKernelGGL(k_ech_update_row, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s, X.dsegs.ptr, S,
+                                       ubp, Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr);
                 F4_LAUNCH_CHECK();
                 ++r;
             }
