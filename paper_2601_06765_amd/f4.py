@@ -150,23 +150,40 @@ def grevlex_unrank(n, D, rank):
     return out.value
 
 
+def pack_many(n, exps):
+    """P words of many exponent vectors at once (rows of an integer array of
+    width n), the same words as pack(): degree in the top byte, exponent i in
+    lane i of width lane_bits(n)."""
+    w = lane_bits(n)
+    if not w:
+        raise F4Error(F4_E_ARG, "bad number of variables %d" % n)
+    e = np.asarray(exps, dtype=np.int64).reshape(-1, n)
+    if e.size and (e.min() < 0 or e.max() >= (1 << w) or e.sum(axis=1).max() > 255):
+        raise F4Error(F4_E_RANGE, "an exponent or the degree does not fit its field")
+    shifts = (np.arange(n, dtype=np.uint64) * np.uint64(w))
+    words = (e.astype(np.uint64) << shifts).sum(axis=1, dtype=np.uint64)
+    return words | (e.sum(axis=1).astype(np.uint64) << np.uint64(56))
+
+
 def polys_to_arrays(n, polys, sort=False):
     """List of polys [(exps, coeff), ...] -> (mon u64, coeff u32, offset u64) host arrays.
     With sort=True the terms of each polynomial are ordered by the library's
     order key (largest monomial first), as f4_build_matrix requires."""
     w = lane_bits(n)
     lanes = (1 << (n * w)) - 1
-    mons, coeffs, offs = [], [], [0]
-    for f in polys:
-        words = [(pack(n, e), c) for e, c in f]
-        if sort:
-            words.sort(key=lambda t: t[0] ^ lanes, reverse=True)
-        for wd, c in words:
-            mons.append(wd)
-            coeffs.append(c)
-        offs.append(len(mons))
-    return (np.array(mons, dtype=np.uint64), np.array(coeffs, dtype=np.uint32),
-            np.array(offs, dtype=np.uint64))
+    terms = [t for f in polys for t in f]
+    offs = np.zeros(len(polys) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(f) for f in polys])
+    mons = pack_many(n, [e for e, _ in terms]) if terms else np.zeros(0, dtype=np.uint64)
+    coeffs = np.array([c for _, c in terms], dtype=np.uint32)
+    if sort:
+        for a in range(len(polys)):
+            lo, hi = int(offs[a]), int(offs[a + 1])
+            keys = mons[lo:hi] ^ np.uint64(lanes)
+            order = sorted(range(hi - lo), key=lambda k: int(keys[k]), reverse=True)
+            mons[lo:hi] = mons[lo:hi][order]
+            coeffs[lo:hi] = coeffs[lo:hi][order]
+    return mons, coeffs, offs
 
 
 def _ptr(a):
@@ -256,12 +273,19 @@ class Context:
             steps.append({name: getattr(s, name) for name, _ in StepStats._fields_})
         return basis, steps
 
+    def prepare(self, p, n, polys):
+        """Marshal one system once; the result feeds groebner_prepared."""
+        mon, coeff, off = polys_to_arrays(n, [[(e, c % p) for e, c in f] for f in polys])
+        return (p, n, _PolysArg(n, mon, coeff, off))
+
     def groebner(self, p, n, polys, stream=None):
         """Reduced Groebner basis of a system given as lists of (exps, coeff).
         Returns (basis, steps): basis as lists of (exps, coeff), leading term
         first, sorted by leading monomial (largest first); steps as dicts."""
-        mon, coeff, off = polys_to_arrays(n, [[(e, c % p) for e, c in f] for f in polys])
-        arg = _PolysArg(n, mon, coeff, off)
+        return self.groebner_prepared(self.prepare(p, n, polys), stream)
+
+    def groebner_prepared(self, prep, stream=None):
+        p, n, arg = prep
         h = c_vp()
         self._check(_lib.f4_groebner(self._h, p, ctypes.byref(arg.s), ctypes.byref(h), c_vp(stream)))
         try:

@@ -83,3 +83,27 @@ def test_dense_rank_large_n_samples(f4):
         ka, kb = bb.grevlex_key(a), bb.grevlex_key(b)
         assert (ra < rb) == (ka > kb) and (ra == rb) == (a == b)
         assert f4.unpack(n, f4.grevlex_unrank(n, D, ra)) == a
+
+
+@pytest.mark.parametrize("n", [1, 3, 6, 10, 14])
+def test_vectorised_packing_matches_the_library(f4, n):
+    """The binding's bulk packer gives the library's words (f4_pack), and the
+    same range errors."""
+    import numpy as np
+    rng = np.random.default_rng(100 + n)
+    w = f4.lane_bits(n)
+    exps = rng.integers(0, min(1 << w, 256 // n + 1), size=(200, n))
+    exps = exps[exps.sum(axis=1) <= 255]
+    got = f4.pack_many(n, exps)
+    assert [int(x) for x in got] == [f4.pack(n, tuple(int(v) for v in e)) for e in exps]
+    with pytest.raises(f4.F4Error) as e:
+        f4.pack_many(n, [[1 << w] + [0] * (n - 1)])
+    assert e.value.code == f4.F4_E_RANGE
+    polys = [[(tuple(int(v) for v in exps[i]), i + 1) for i in range(k, k + 5)] for k in (0, 5, 10)]
+    mon, coeff, off = f4.polys_to_arrays(n, polys, sort=True)
+    assert off.tolist() == [0, 5, 10, 15]
+    for a, f in enumerate(polys):
+        want = sorted(((f4.pack(n, e), c) for e, c in f), key=lambda t: t[0] ^ ((1 << (n * w)) - 1),
+                      reverse=True)
+        got_a = list(zip(mon[5 * a:5 * a + 5].tolist(), coeff[5 * a:5 * a + 5].tolist()))
+        assert got_a == [(int(m), int(c)) for m, c in want]
