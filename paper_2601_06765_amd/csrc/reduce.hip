@@ -605,6 +605,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     const u32 rw = ECH_RPW * wave;  // block rows rw .. rw + ECH_RPW - 1 of a working wave
     u32 q = 0, pmask = 0, it = 0;
     u64 nops = 0;  // modular products (counted by lane 0 of each wave; timing option)
+    const bool count_ops = ops != nullptr;
     // chunks of ECH_CH columns from the smallest leading column of the block;
     // each thread holds one entry of the next chunk in a register (its load is
     // in flight while the current chunk is eliminated)
@@ -673,15 +674,13 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
                     if (fk) {
                         val = fp_ff<SMALL>(f, piv, val, fk, prow);
                         s_RZ[r * ECH_RS + lane] = val;
-                        if (lane == 0) nops += 2 * ECH_W;
-                        if (lane == 0 && ((pmask >> r) & 1u)) s_pv[r] = fp_mul_t<SMALL>(f, s_pv[r], piv);
+                        if (count_ops && lane == 0) nops += 2 * ECH_W;
                     }
                     if (!((pm2 >> r) & 1u)) nz |= val != 0;
                 }
                 if (tid == 0) {
                     s_pcol[q] = j0 + jp;
                     s_prow[q] = kp;
-                    s_pv[kp] = piv;
                 }
                 pmask = pm2;
                 const u64 m = wave_ballot(nz && lane > jp && lane < w);
@@ -692,8 +691,19 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
             __syncthreads();
         }
     }
-    // each pivot row is s_pv times its normalised form
-    if (tid < q) s_inv[tid] = fp_inv_t<SMALL>(f, s_pv[s_prow[tid]]);
+    // each pivot row is its value at its own pivot column times its normalised
+    // form; that value is (Z B) at the column (the rows stay Z B throughout),
+    // formed here once instead of being tracked through the pivot steps
+    {
+        const u32 t = tid / ECH_B, u = tid % ECH_B;  // a half-wave per pivot
+        u64 acc = 0;
+        if (t < q && u < b)
+            acc = fp_mul_t<SMALL>(f, s_RZ[s_prow[t] * ECH_RS + ECH_CH + u], D[(u64)s_rows[u] * c + s_pcol[t]]);
+        for (u32 d = ECH_B / 2; d > 0; d >>= 1) acc += (u64)__shfl_xor((unsigned long long)acc, d, F4_WAVE);
+        if (u == 0 && t < q) s_pv[t] = fp_reduce_any(f, acc);
+    }
+    __syncthreads();
+    if (tid < q) s_inv[tid] = fp_inv_t<SMALL>(f, s_pv[tid]);
     __syncthreads();
     const u32 npr = R->npr;
     // round record: pivot columns, block rows and normalised Z rows of the pivots
