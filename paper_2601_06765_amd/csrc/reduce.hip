@@ -350,19 +350,18 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
     __syncthreads();
     for (u32 kp = 0; kp < npanels; ++kp) {
         const u32 qa = kp * PANEL, wk = min((u32)PANEL, npiv - qa), buf = kp & 1;
-        // (A) partial products
+        // (A) partial products: lane j reduces the row's panel value l_j once
+        // (contiguous LDS reads), and the wave takes its BW values from those
+        // lanes with readlane
         for (u32 r = 0; r < nr; ++r) {
+            const AccT aj = lane < wk ? acc[r * N + qa + lane] : (AccT)0;
+            const u32 lj = SMALL ? fp_reduce32(f, (u32)aj) : fp_reduce_any(f, (u64)aj);
             u64 part = 0;
 #pragma unroll
             for (u32 i = 0; i < BW; ++i) {
-                const u32 b = wave * BW + i;
-                if (b >= wk) continue;
-                const AccT ab = acc[r * N + qa + b];  // same address in every lane
-                const u32 lb = SMALL ? fp_reduce32(f, (u32)ab) : fp_reduce_any(f, (u64)ab);
-                if (lb) {
-                    part += SMALL ? (u64)mul24(lb, tin[i]) : (u64)fp_mul(f, lb, tin[i]);
-                    ++nops;
-                }
+                const u32 lb = (u32)__builtin_amdgcn_readlane((int)lj, (int)(wave * BW + i));  // 0 past wk
+                part += SMALL ? (u64)mul24(lb, tin[i]) : (u64)fp_mul(f, lb, tin[i]);
+                nops += lb != 0;
             }
             if (part) atomicAdd((unsigned long long*)&s_xs[buf][r][lane], (unsigned long long)part);
         }
