@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--batch-systems", type=int, default=256, help="systems in the batched leg (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg (0: skip)")
     ap.add_argument("--sparse-repeats", type=int, default=3, help="timed runs of the n=14 sparse step (0: skip)")
+    ap.add_argument("--modloop-chains", type=int, default=1 << 21,
+                    help="chains of the modular inner-loop microbenchmark (0: skip)")
+    ap.add_argument("--modloop-iters", type=int, default=4096)
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed schedules instead of the autotuner's measured picks (tuned during warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -168,6 +171,27 @@ def sparse_step_leg(f4, repeats, autotune):
             "nnz_per_s_preprocess": s["nnz"] / (sp / 1000.0), "nnz_per_s_step": s["nnz"] / ((sp + el) / 1000.0),
             "rows_per_s_step": s["r"] / ((sp + el) / 1000.0),
             "run_to_step_ms": round(1000.0 * sum(r[0] for r in runs) / len(runs), 3)}
+
+
+def modloop_leg(f4, nchains, iters):
+    """Modular inner-loop microbenchmark (randomized residues, seed 5): the
+    update rate of each arithmetic form, its registers and spill bytes per
+    lane, and the rate as a fraction of the derived modular-product peak."""
+    import synth
+    res = {"workload": "%d chains x %d updates x <- b + x*a mod p, uniform residues (splitmix64 seed 5)"
+                       % (nchains, iters), "forms": []}
+    cases = [("mul24", synth.P16), ("barrett32", synth.P16), ("barrett64", synth.P16), ("barrett64", synth.P31),
+             ("montgomery", synth.P16), ("montgomery", synth.P31)]
+    ctx = f4.Context(0)
+    for form, p in cases:
+        x0, a, b = (synth.residues(p, nchains, 5 * 2**32 + k) for k in range(3))
+        _, st = ctx.modloop(p, form, x0, a, b, iters)
+        res["forms"].append({"form": form, "p": p, "updates_per_s": st["updates_per_s"],
+                             "kernel_ms": round(st["kernel_ms"], 4), "regs": st["regs"],
+                             "private_bytes": st["private_bytes"],
+                             "frac_of_peak": round(st["updates_per_s"] / MODMUL_PEAK, 4)})
+    ctx.close()
+    return res
 
 
 def batch_leg(ctx, count):
@@ -360,6 +384,15 @@ def main():
     ctx.close()
     if args.sparse_repeats:
         out["sparse_step"] = sparse_step_leg(f4, args.sparse_repeats, tune)
+    if args.modloop_chains:
+        out["modloop"] = modloop_leg(f4, args.modloop_chains, args.modloop_iters)
+        # the kernels' own small-prime form (one-word Barrett) at the workload's prime
+        e3 = [x for x in out["modloop"]["forms"] if x["form"] == "barrett32" and x["p"] == p]
+        if e3:
+            mp = e3[0]["updates_per_s"] / 1e12
+            out_roof["measured_peak"] = {"value": round(mp, 3), "unit": "Tmodmul/s",
+                                         "source": "modular inner-loop microbenchmark, one-word Barrett, p = %d" % p,
+                                         "frac": round(out_roof["achieved"] / mp, 5)}
     if args.batch_systems:
         bctx = f4.Context(0, autotune=tune)
         out["batch"] = batch_leg(bctx, args.batch_systems)

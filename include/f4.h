@@ -310,6 +310,44 @@ int f4_server_poll(f4_server* srv, uint64_t ticket, f4_basis** gb, int* done);
 int f4_server_load(const f4_server* srv, uint32_t* resident, uint32_t* running, uint64_t* used);
 int f4_server_destroy(f4_server* srv);
 
+/* ---------------------------------------------- modular inner loop */
+/* The modular-arithmetic microbenchmark of the benchmark protocol
+ * ("Microbenchmarks": randomized residues, Barrett against Montgomery update
+ * kernels; updates/s, register count, spill rate).  Chain i runs
+ *     x <- (b[i] + x * a[i]) mod p,   x = x0[i] at the start,
+ * `iters` times (an update of the form of equation "mod-fma" whose product
+ * takes the running value), and out[i] receives the final x as a standard
+ * residue.  Forms:
+ *   F4_MODLOOP_MUL24      p < 2^16: 24-bit product, float quotient estimate,
+ *                         then a modular add (the elimination's small-p form);
+ *   F4_MODLOOP_BARRETT32  p < 2^16: one-word Barrett of b + x*a < 2^32;
+ *   F4_MODLOOP_BARRETT64  two-word Barrett (section "Barrett reduction as
+ *                         reciprocal multiplication"), any p;
+ *   F4_MODLOOP_MONTGOMERY R = 2^32 (section "Montgomery multiplication and
+ *                         domain reuse"), any p; values enter the Montgomery
+ *                         domain once and leave it once.
+ * x0, a, b and out are host arrays of nchains residues (< p) owned by the
+ * caller.  One untimed warm-up launch, then one launch timed with HIP events
+ * on the context's stream.  st receives updates/s (nchains * iters / kernel
+ * time), the kernel time, and the kernel's registers per lane and private
+ * (spill) bytes per lane as the runtime reports them.  F4_E_ARG: p not an odd
+ * prime < 2^31, an unknown form, p >= 2^16 for the 16-bit forms, nchains 0
+ * or above 2^26, iters 0, a null pointer, or an input value >= p. */
+enum {
+    F4_MODLOOP_MUL24 = 0,
+    F4_MODLOOP_BARRETT32 = 1,
+    F4_MODLOOP_BARRETT64 = 2,
+    F4_MODLOOP_MONTGOMERY = 3
+};
+typedef struct {
+    double updates_per_s;
+    double kernel_ms;
+    uint32_t regs;
+    uint32_t private_bytes;
+} f4_modloop_stats;
+int f4_modloop(f4_ctx* ctx, uint32_t p, uint32_t form, uint32_t nchains, uint32_t iters, const uint32_t* x0,
+               const uint32_t* a, const uint32_t* b, uint32_t* out, f4_modloop_stats* st);
+
 #ifdef __cplusplus
 }
 #endif

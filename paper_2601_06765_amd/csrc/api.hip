@@ -899,6 +899,24 @@ int f4_tune_import(f4_ctx* X, const char* text) {
     F4_API_END(X)
 }
 
+int f4_modloop(f4_ctx* X, uint32_t p, uint32_t form, uint32_t nchains, uint32_t iters, const uint32_t* x0,
+               const uint32_t* a, const uint32_t* b, uint32_t* out, f4_modloop_stats* st) {
+    F4_API_BEGIN(X)
+    if (!x0 || !a || !b || !out || !st) throw F4Error{F4_E_ARG, "null pointer"};
+    if (!is_odd_prime(p) || p >= (1u << 31) || form > F4_MODLOOP_MONTGOMERY) throw F4Error{F4_E_ARG, "bad argument"};
+    if (form <= F4_MODLOOP_BARRETT32 && p >= 65536) throw F4Error{F4_E_ARG, "16-bit form needs p < 2^16"};
+    if (nchains == 0 || nchains > (1u << 26) || iters == 0) throw F4Error{F4_E_ARG, "bad chain count or length"};
+    for (u32 i = 0; i < nchains; ++i)
+        if (x0[i] >= p || a[i] >= p || b[i] >= p) throw F4Error{F4_E_ARG, "input value is not a residue"};
+    ModloopResult r;
+    modloop_run(X->c, p, form, nchains, iters, x0, a, b, out, r);
+    st->updates_per_s = r.updates_per_s;
+    st->kernel_ms = r.kernel_ms;
+    st->regs = r.regs;
+    st->private_bytes = r.private_bytes;
+    F4_API_END(X)
+}
+
 uint32_t f4_lane_bits(uint32_t n) { return lane_bits(n); }
 
 int f4_download(f4_ctx* X, void* dst, const void* src, size_t bytes) {

@@ -32,7 +32,6 @@ struct Fp {
     u32 mu32; // floor(2^32 / p): single-word Barrett for any x < 2^32
     u32 r32;  // 2^32 mod p
     float finv;   // 1/p rounded to float (quotient estimate for p < 2^16)
-    double dinv;  // 1/p rounded to double (quotient estimate in double arithmetic)
 };
 
 static inline Fp make_fp(u32 p) {
@@ -45,7 +44,6 @@ static inline Fp make_fp(u32 p) {
     f.mu32 = (u32)((1ull << 32) / p);
     f.r32 = (u32)((1ull << 32) % p);
     f.finv = 1.0f / (float)p;
-    f.dinv = 1.0 / (double)p;
     return f;
 }
 
@@ -94,6 +92,12 @@ __device__ __forceinline__ u32 fp_mul16(const Fp& f, u32 a, u32 b) {
     return min(r, r - f.p);
 }
 
+// a*b mod p for p < 2^16 and a, b < p: the product is exact in one word and
+// the one-word Barrett step reduces it (six full-rate instructions on gfx950,
+// where 32-bit integer multiplies issue at the full vector rate; the modular
+// inner-loop microbenchmark measures it well ahead of the 24-bit form above).
+__host__ __device__ __forceinline__ u32 fp_mul32(const Fp& f, u32 a, u32 b) { return fp_reduce32(f, a * b); }
+
 // (a + b*c) mod p for canonical a, b, c: equation "mod-fma"
 __host__ __device__ __forceinline__ u32 fp_fma(const Fp& f, u32 a, u32 b, u32 c) {
     return fp_reduce(f, (u64)a + (u64)b * c);
@@ -122,7 +126,9 @@ __host__ __device__ inline u32 fp_inv(const Fp& f, u32 a) {
 
 // Montgomery multiplication (section "Montgomery multiplication and domain
 // reuse") with R = 2^32, pinv = -p^-1 mod 2^32: REDC(a*b) = a*b*R^-1 mod p with
-// one conditional subtraction.  Used by the modular inner-loop microbenchmark.
+// one conditional subtraction (any odd p < 2^31: t + q*p < 2^63 + 2^62 and the
+// quotient by R is below 2p).  Measured against the Barrett forms by the modular
+// inner-loop microbenchmark; the elimination kernels keep standard residues.
 struct Mont {
     u32 p, pinv, r2;  // r2 = R^2 mod p
 };

@@ -202,6 +202,16 @@ void tuned_sort(Ctx& c, u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit);
 std::string tune_text(const Ctx& c);
 void tune_parse(Ctx& c, const char* text);
 
+// Modular inner-loop microbenchmark (micro.hip): uploads the chains' start
+// values, times one launch of `iters` updates per chain with HIP events and
+// reads the final values back.  Arguments are checked by the caller.
+struct ModloopResult {
+    double updates_per_s = 0, kernel_ms = 0;
+    u32 regs = 0, private_bytes = 0;
+};
+void modloop_run(Ctx& c, u32 p, u32 form, u32 nchains, u32 iters, const u32* x0, const u32* a0, const u32* b0, u32* out,
+                 ModloopResult& res);
+
 // Next free region (>= bytes) of the pinned arena; waits for the copies in
 // flight only when the arena has to wrap around.
 u8* staging(Ctx& c, size_t bytes);

@@ -399,7 +399,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
                     for (int r = 0; r < TR_MAXR; ++r) {
                         if (!xs[r]) continue;
                         const u32 negx = f.p - xs[r];
-                        const u32 add = SMALL ? fp_mul16(f, negx, tv) : fp_reduce(f, (u64)negx * tv);
+                        const u32 add = SMALL ? fp_mul32(f, negx, tv) : fp_reduce(f, (u64)negx * tv);
                         atomicAdd(&acc[r * N + col], (AccT)add);
                         ++nops;
                     }
@@ -477,7 +477,7 @@ struct EchRound {
 
 template <bool SMALL>
 __device__ __forceinline__ u32 fp_mul_t(const Fp& f, u32 a, u32 b) {
-    return SMALL ? fp_mul16(f, a, b) : fp_reduce(f, (u64)a * b);  // SMALL: p < 2^16
+    return SMALL ? fp_mul32(f, a, b) : fp_reduce(f, (u64)a * b);  // SMALL: p < 2^16
 }
 
 // (piv * a - fk * b) mod p
@@ -486,17 +486,11 @@ __device__ __forceinline__ u32 fp_ff(const Fp& f, u32 piv, u32 a, u32 fk, u32 b)
     const u32 x = fp_mul_t<SMALL>(f, piv, a), y = fp_mul_t<SMALL>(f, fk, b);
     return x >= y ? x - y : x + f.p - y;
 }
-// p < 2^16: piv * a - fk * b is an integer below 2^32 in magnitude, exact in
-// double (full-rate fma); the quotient estimate floor(t / p) from the rounded
-// 1/p is off by at most one, so the remainder needs two corrections
+// p < 2^16: (piv * a mod p) + (p - fk) * b < p + (p - 1) p = p^2 < 2^32, so
+// two one-word Barrett reductions finish it in 32-bit integer arithmetic
 template <>
 __device__ __forceinline__ u32 fp_ff<true>(const Fp& f, u32 piv, u32 a, u32 fk, u32 b) {
-    const double pd = (double)f.p;
-    const double t = fma((double)piv, (double)a, -((double)fk * (double)b));
-    double r = fma(-floor(t * f.dinv), pd, t);
-    r = r < 0.0 ? r + pd : r;
-    r = r >= pd ? r - pd : r;
-    return (u32)r;
+    return fp_reduce32(f, fp_mul32(f, piv, a) + (f.p - fk) * b);
 }
 
 // a^-1 mod p by Fermat's little theorem with the modular product of the class

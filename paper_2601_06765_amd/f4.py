@@ -106,6 +106,17 @@ _sig("f4_server_load", c_int, [c_vp, P(c_u32), P(c_u32), P(c_u64)])
 _sig("f4_server_destroy", c_int, [c_vp])
 
 
+class ModloopStats(ctypes.Structure):
+    _fields_ = [("updates_per_s", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("regs", c_u32), ("private_bytes", c_u32)]
+
+
+_sig("f4_modloop", c_int, [c_vp, c_u32, c_u32, c_u32, c_u32, P(c_u32), P(c_u32), P(c_u32), P(c_u32),
+                           P(ModloopStats)])
+
+MODLOOP_FORMS = {"mul24": 0, "barrett32": 1, "barrett64": 2, "montgomery": 3}
+
+
 class F4Error(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("f4 error %d: %s" % (code, msg))
@@ -230,6 +241,22 @@ class Context:
     def load_tune_table(self, text):
         """Merge a table in the text form of tune_table() (f4_tune_import)."""
         self._check(_lib.f4_tune_import(self._h, text.encode()))
+
+    def modloop(self, p, form, x0, a, b, iters):
+        """Modular inner-loop microbenchmark (f4_modloop): chain i runs
+        x <- (b[i] + x * a[i]) mod p `iters` times from x0[i] in the named
+        form; returns (final values, stats dict)."""
+        x0, a, b = (np.ascontiguousarray(v, dtype=np.uint32) for v in (x0, a, b))
+        if not (len(x0) == len(a) == len(b)):
+            raise ValueError("x0, a and b differ in length")
+        out = np.empty(len(x0), dtype=np.uint32)
+        st = ModloopStats()
+        u = P(c_u32)
+        self._check(_lib.f4_modloop(self._h, p, MODLOOP_FORMS[form], len(x0), iters, x0.ctypes.data_as(u),
+                                    a.ctypes.data_as(u), b.ctypes.data_as(u), out.ctypes.data_as(u),
+                                    ctypes.byref(st)))
+        return out, {"updates_per_s": st.updates_per_s, "kernel_ms": st.kernel_ms, "regs": st.regs,
+                     "private_bytes": st.private_bytes}
 
     def close(self):
         if self._h:

@@ -51,6 +51,31 @@ class SplitMix64:
         return (self.next() >> 11) * (1.0 / (1 << 53))
 
 
+def residues(p, count, seed):
+    """``count`` uniform residues in [0, p): exactly the values that successive
+    ``SplitMix64(seed).below(p)`` calls return, drawn in bulk with numpy (the
+    i-th raw output is the mix of seed + i * gamma; outputs at or above the
+    top multiple of p are skipped, as ``below`` skips them)."""
+    import numpy as np
+    if p <= 0:
+        raise ValueError("p must be positive")
+    limit = np.uint64(((1 << 64) // p) * p - 1)  # largest accepted raw value
+    gamma = np.uint64(0x9E3779B97F4A7C15)
+    parts, have, start = [], 0, 0
+    while have < count:
+        m = count - have + 16
+        i = np.arange(start + 1, start + m + 1, dtype=np.uint64)
+        z = np.uint64(seed & MASK64) + i * gamma
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+        z = z[z <= limit] % np.uint64(p)
+        parts.append(z[:count - have])
+        have += len(parts[-1])
+        start += m
+    return np.concatenate(parts).astype(np.uint32) if parts else np.zeros(0, dtype=np.uint32)
+
+
 def quadratic_support(n):
     """All monomials of degree <= 2 in n variables, as exponent tuples.
 

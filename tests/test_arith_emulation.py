@@ -1,11 +1,17 @@
-"""The 16-bit modular product used by the elimination kernels for p < 2^16:
-x = a*b (exact in 32 bits), q = trunc(float(x) * float(1/p)), r = x - q*p,
-then r <- min(r, r + p), r <- min(r, r - p) in wrapping 32-bit unsigned
-arithmetic.  numpy's float32 multiply rounds to nearest even and its
-float32 -> uint32 conversion truncates, like the device instructions, so
-this emulation pins the claim that the result is a*b mod p for every product
-of residues (the full range is swept off-line; here a dense sample and the
-values next to every multiple of p near the top of the range)."""
+"""The modular forms of the kernels, emulated in numpy with the device's word
+sizes, against Python's exact residues.
+
+* One-word Barrett (any p < 2^31, x < 2^32): q = high word of x * floor(2^32/p),
+  r = x - q*p wrapping, r <- min(r, r - p).  The elimination kernels' products
+  for p < 2^16 (a*b and the fraction-free update piv*a - fk*b) use it.
+* The 24-bit form of the modular inner-loop microbenchmark (p < 2^16):
+  x = a*b, q = trunc(float(x) * float(1/p)), r = x - q*p, then
+  r <- min(r, r + p), r <- min(r, r - p).  numpy's float32 multiply rounds to
+  nearest even and its float32 -> uint32 conversion truncates, like the device
+  instructions.
+
+Each is checked on a dense random sample and on the values next to multiples
+of p and at the top of the word."""
 
 import numpy as np
 import pytest
@@ -34,16 +40,47 @@ def test_mul16_exact(p):
     assert np.array_equal(mul16(a2, b2, p).astype(np.uint64), (a2 * b2) % np.uint64(p))
 
 
-def ff64(piv, a, fk, b, p):
+def red32(x, p):
+    """One-word Barrett step: q = high word of x * floor(2^32 / p), r = x - q*p
+    (wrapping 32-bit), then r <- min(r, r - p)."""
+    mu = np.uint64((1 << 32) // p)
+    x = x.astype(np.uint64)
+    q = (x * mu) >> np.uint64(32)
+    r = ((x - q * np.uint64(p)) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    return np.minimum(r, r - np.uint32(p))
+
+
+def mul32(a, b, p):
+    return red32((a.astype(np.uint64) * b.astype(np.uint64)) & np.uint64(0xFFFFFFFF), p)
+
+
+def ff32(piv, a, fk, b, p):
     """(piv*a - fk*b) mod p as the echelon block step computes it for p < 2^16:
-    t is exact in double (|t| < 2^33), q = floor(t * fl(1/p)) rounds once, and
-    t - q*p is exact; two corrections bring it into [0, p)."""
-    dinv = np.float64(1.0) / np.float64(p)
-    t = piv.astype(np.int64) * a.astype(np.int64) - fk.astype(np.int64) * b.astype(np.int64)
-    q = np.floor(t.astype(np.float64) * dinv).astype(np.int64)
-    r = t - q * p
-    r = np.where(r < 0, r + p, r)
-    return np.where(r >= p, r - p, r)
+    (piv*a mod p) + (p - fk)*b stays below p^2 < 2^32, then one more step."""
+    t = mul32(piv, a, p).astype(np.uint64) + (np.uint64(p) - fk.astype(np.uint64)) * b.astype(np.uint64)
+    assert int(t.max(initial=0)) < 1 << 32
+    return red32(t, p)
+
+
+@pytest.mark.parametrize("p", [2147483647, 2147483629, 65521, 257, 3])
+def test_one_word_barrett_exact(p):
+    rng = np.random.default_rng(p + 2)
+    x = rng.integers(0, 1 << 32, 2_000_000, dtype=np.uint64)
+    # the top of the word and the values next to multiples of p
+    top = np.arange((1 << 32) - 3000, 1 << 32, dtype=np.uint64)
+    mult = (np.arange(1, 2000, dtype=np.uint64) * np.uint64(p))
+    mult = mult[mult < (1 << 32) - 1]
+    near = np.concatenate([mult - 1, mult, mult + 1])
+    for v in (x, top, near):
+        assert np.array_equal(red32(v, p).astype(np.uint64), v % np.uint64(p))
+
+
+@pytest.mark.parametrize("p", [65521, 65519, 32749, 257, 3])
+def test_mul32_exact(p):
+    rng = np.random.default_rng(p + 3)
+    a = rng.integers(0, p, 2_000_000, dtype=np.uint64)
+    b = rng.integers(0, p, 2_000_000, dtype=np.uint64)
+    assert np.array_equal(mul32(a, b, p).astype(np.uint64), (a * b) % np.uint64(p))
 
 
 @pytest.mark.parametrize("p", [65521, 65519, 32749, 257, 3])
@@ -52,8 +89,8 @@ def test_fraction_free_update_exact(p):
     k = 1_000_000
     piv, a, fk, b = (rng.integers(0, p, k, dtype=np.int64) for _ in range(4))
     want = (piv * a - fk * b) % p
-    assert np.array_equal(ff64(piv, a, fk, b, p), want)
+    assert np.array_equal(ff32(piv, a, fk, b, p).astype(np.int64), want)
     # extremes: largest products of either sign, and exact multiples of p
     e = np.array([p - 1, p - 2, 1, 0], dtype=np.int64)
     P, A, F, B = (x.ravel() for x in np.meshgrid(e, e, e, e))
-    assert np.array_equal(ff64(P, A, F, B, p), (P * A - F * B) % p)
+    assert np.array_equal(ff32(P, A, F, B, p).astype(np.int64), (P * A - F * B) % p)

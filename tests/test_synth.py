@@ -89,3 +89,11 @@ def test_planted_point_is_a_root():
                 t = t * pow(s[i], a, p) % p
             v = (v + t) % p
         assert v == 0
+
+
+def test_bulk_residues_equal_the_sequential_stream():
+    for p, seed in [(3, 0), (65521, 12345), (synth.P31, 2**64 - 1), (2**31 + 11, 7)]:
+        got = synth.residues(p, 2000, seed)
+        g = synth.SplitMix64(seed)
+        assert [int(v) for v in got] == [g.below(p) for _ in range(2000)]
+    assert len(synth.residues(65521, 0, 1)) == 0
