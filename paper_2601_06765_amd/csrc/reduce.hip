@@ -461,12 +461,12 @@ struct EchRound {
 // recorded in a b x b transform Z: the block's columns are visited in chunks
 // of ECH_CH, each chunk is loaded and multiplied by Z, and the rows of
 // [chunk | Z] (LDS, ECH_CH + ECH_B = 64 columns, one per lane) are eliminated
-// with every wave owning two rows.  The first column where a non-pivot row is
+// by ECH_PW waves owning ECH_RPW rows each.  The first column where a non-pivot row is
 // nonzero becomes the next pivot; every such column is the leading column of a
 // vector of the row space, hence a pivot column of the RREF of the whole
 // trailing block.  Row operations are fraction-free (row_k <- piv * row_k -
 // row_k[jp] * row_kp), so no inverse is taken per pivot; each pivot row's value
-// at its pivot column is tracked and divided out at the end.  Scanning stops
+// at its pivot column is formed at the end and divided out.  Scanning stops
 // once every block row is a pivot or the columns are exhausted (the other rows
 // are then zero), so all block rows are consumed; the new pivot rows
 // Z * (block rows), formed by k_ech_update, are reduced on all pivot columns
@@ -505,10 +505,17 @@ __device__ __forceinline__ u32 fp_inv_t(const Fp& f, u32 a) {
     return r;
 }
 
-// Rows of the block per working wave in the pivot loop: ECH_B / ECH_RPW waves
-// own the rows, the others only keep the loop count (fewer copies of the
-// per-pivot bookkeeping).
-#define ECH_RPW 2
+// Pivot loop: ECH_PW working waves (two per SIMD) own ECH_RPW block rows each
+// and keep them in registers; the LDS copy of [chunk | Z] is written through
+// on every update, so the pivot row is read from it by the other waves.  Per
+// column every working wave publishes the lowest of its non-pivot rows that is
+// nonzero there, which gives the next pivot column and pivot row together, in
+// one exchange and one block barrier per pivot.  The other waves only follow
+// the loop control.  (Measured on the n = 10 workload: 4 waves of 8 rows and
+// 16 waves of 2 rows were both slower; one wave per SIMD leaves the latency
+// of the pivot chain exposed, four per SIMD issue the loop control 4 times.)
+#define ECH_PW 8
+#define ECH_RPW (ECH_B / ECH_PW)
 
 template <bool SMALL>
 __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead, u32* status, const u32* Dp,
@@ -520,7 +527,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     __shared__ u32 s_RZ[ECH_B * ECH_RS];
     __shared__ u32 s_B[ECH_B * ECH_CH];
     __shared__ u32 s_pcol[ECH_B], s_prow[ECH_B], s_pv[ECH_B], s_inv[ECH_B];
-    __shared__ u64 s_nz[3];
+    __shared__ uint4 s_first[2][F4_WAVE][ECH_PW / 4];  // [buffer][column]: per working wave, its lowest live row there
     __shared__ u32 s_thr, s_need, s_cmin;
     EchRound* R = rounds + blockIdx.y;
     if (R->done) return;
@@ -578,7 +585,7 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         nb += tsel;
         neq += teq;
     }
-    const u32 b = nb < ECH_B ? nb : ECH_B;
+    const u32 b = __builtin_amdgcn_readfirstlane(nb < ECH_B ? nb : ECH_B);  // uniform: lets row tests branch on scalars
     if (b == 0) {
         if (tid == 0) {
             R->done = 1;
@@ -586,18 +593,19 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         }
         return;
     }
-    static_assert(ECH_W == F4_WAVE && ECH_B * ECH_CH == 1024 && 2 * 16 == ECH_B, "echelon block layout");
+    static_assert(ECH_W == F4_WAVE && ECH_B * ECH_CH == 1024 && ECH_PW % 4 == 0 && ECH_RPW * ECH_PW == ECH_B,
+                  "echelon block layout");
     for (u32 x = tid; x < ECH_B * ECH_W; x += 1024) {
         const u32 k = x / ECH_W, j = x % ECH_W;  // element (k, j) lives at k * ECH_RS + j
         s_RZ[k * ECH_RS + j] = (j >= ECH_CH && j - ECH_CH == k) ? 1u : 0u;
     }
-    if (tid < 3) s_nz[tid] = 0;
     __syncthreads();
-    const u32 lane = tid % F4_WAVE, wave = tid / F4_WAVE;
-    const bool worker = wave < ECH_B / ECH_RPW;
+    const u32 lane = tid % F4_WAVE, wave = __builtin_amdgcn_readfirstlane(tid / F4_WAVE);
+    const bool worker = wave < ECH_PW;
     const u32 rw = ECH_RPW * wave;  // block rows rw .. rw + ECH_RPW - 1 of a working wave
     u32 q = 0, pmask = 0, it = 0;
     u64 nops = 0;  // modular products (counted by lane 0 of each wave; timing option)
+    u32 nupd = 0;  // row updates of this working wave in the pivot loop (2 ECH_W products each)
     const bool count_ops = ops != nullptr;
     // chunks of ECH_CH columns from the smallest leading column of the block;
     // each thread holds one entry of the next chunk in a register (its load is
@@ -628,62 +636,66 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
             s_RZ[k * ECH_RS + j] = v;
         }
         __syncthreads();
-        // columns where a non-pivot row is nonzero, merged over the waves into
-        // s_nz[it % 3]; each step computes the next step's mask right after
-        // its own row updates, so a step needs one block barrier (three
-        // buffers: one read, one written, one cleared)
+        // working waves: own rows into registers, and the first publication
+        u32 rv[ECH_RPW];
         if (worker) {
-            bool nz = false;
 #pragma unroll
-            for (u32 h = 0; h < ECH_RPW; ++h) {
+            for (u32 h = 0; h < ECH_RPW; ++h) rv[h] = s_RZ[(rw + h) * ECH_RS + lane];
+            u32 fr = ECH_B;
+#pragma unroll
+            for (int h = ECH_RPW - 1; h >= 0; --h) {
                 const u32 r = rw + h;
-                if (r < b && !((pmask >> r) & 1u)) nz |= s_RZ[r * ECH_RS + lane] != 0;
+                if (r < b && !((pmask >> r) & 1u) && rv[h] != 0) fr = r;
             }
-            const u64 m = wave_ballot(nz && lane < w);
-            if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[it % 3], (unsigned long long)m);
+            reinterpret_cast<u32*>(&s_first[it & 1][lane][0])[wave] = fr;
         }
         __syncthreads();
         while (q < b) {
-            const u64 all = s_nz[it % 3];
-            if (tid == 0) s_nz[(it + 2) % 3] = 0;
+            // next pivot column: the first column of the chunk where a live
+            // (not yet pivot) row is nonzero; pivot row: the lowest such row
+            u32 fmin = ECH_B;
+#pragma unroll
+            for (u32 g = 0; g < ECH_PW / 4; ++g) {
+                const uint4 fw = s_first[it & 1][lane][g];
+                fmin = min(fmin, min(min(fw.x, fw.y), min(fw.z, fw.w)));
+            }
+            const u64 all = wave_ballot(fmin < ECH_B && lane < w);
             if (!all) break;
             const u32 jp = __ffsll((long long)all) - 1;
+            const u32 kp = (u32)__builtin_amdgcn_readlane((int)fmin, (int)jp);
             if (worker) {
-                // pivot row: the first non-pivot row nonzero at jp (row kp and
-                // the rows before it do not change in this step, so every wave
-                // agrees while the others update their rows)
-                const u32 cand = (lane < b && !((pmask >> lane) & 1u)) ? s_RZ[lane * ECH_RS + jp] : 0u;
-                const u32 kp = __ffsll((long long)wave_ballot(cand != 0)) - 1;
-                const u32 piv = s_RZ[kp * ECH_RS + jp];
                 const u32 prow = s_RZ[kp * ECH_RS + lane];
+                const u32 piv = (u32)__builtin_amdgcn_readlane((int)prow, (int)jp);
                 const u32 pm2 = pmask | (1u << kp);
-                bool nz = false;
 #pragma unroll
                 for (u32 h = 0; h < ECH_RPW; ++h) {
                     const u32 r = rw + h;
-                    if (r >= b || r == kp) continue;
-                    const u32 fk = s_RZ[r * ECH_RS + jp];
-                    u32 val = s_RZ[r * ECH_RS + lane];
-                    if (fk) {
-                        val = fp_ff<SMALL>(f, piv, val, fk, prow);
-                        s_RZ[r * ECH_RS + lane] = val;
-                        if (count_ops && lane == 0) nops += 2 * ECH_W;
+                    const u32 fk = (u32)__builtin_amdgcn_readlane((int)rv[h], (int)jp);
+                    if (r < b && r != kp && fk) {
+                        rv[h] = fp_ff<SMALL>(f, piv, rv[h], fk, prow);
+                        s_RZ[r * ECH_RS + lane] = rv[h];
+                        ++nupd;
                     }
-                    if (!((pm2 >> r) & 1u)) nz |= val != 0;
                 }
+                u32 fr = ECH_B;
+#pragma unroll
+                for (int h = ECH_RPW - 1; h >= 0; --h) {
+                    const u32 r = rw + h;
+                    if (r < b && !((pm2 >> r) & 1u) && rv[h] != 0) fr = r;
+                }
+                reinterpret_cast<u32*>(&s_first[(it + 1) & 1][lane][0])[wave] = fr;
                 if (tid == 0) {
                     s_pcol[q] = j0 + jp;
                     s_prow[q] = kp;
                 }
                 pmask = pm2;
-                const u64 m = wave_ballot(nz && lane > jp && lane < w);
-                if (lane == 0 && m) atomicOr((unsigned long long*)&s_nz[(it + 1) % 3], (unsigned long long)m);
             }
             ++q;
             ++it;
             __syncthreads();
         }
     }
+    if (count_ops && lane == 0) nops += (u64)nupd * 2 * ECH_W;
     // each pivot row is its value at its own pivot column times its normalised
     // form; that value is (Z B) at the column (the rows stay Z B throughout),
     // formed here once instead of being tracked through the pivot steps
