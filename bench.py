@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--modloop-chains", type=int, default=1 << 21,
                     help="chains of the modular inner-loop microbenchmark (0: skip)")
     ap.add_argument("--modloop-iters", type=int, default=4096)
+    ap.add_argument("--spmm-shift-deg", type=int, default=8,
+                    help="shift degree of the Macaulay operator of the SpMM leg (0: skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed schedules instead of the autotuner's measured picks (tuned during warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -171,6 +173,46 @@ def sparse_step_leg(f4, repeats, autotune):
             "nnz_per_s_preprocess": s["nnz"] / (sp / 1000.0), "nnz_per_s_step": s["nnz"] / ((sp + el) / 1000.0),
             "rows_per_s_step": s["r"] / ((sp + el) / 1000.0),
             "run_to_step_ms": round(1000.0 * sum(r[0] for r in runs) / len(runs), 3)}
+
+
+def spmm_leg(f4, shift_deg, b, reps):
+    """Block operator application of the Krylov solvers (Y = A X, Y = A^T X)
+    on the Macaulay matrix of workload 3's input: rows t*f_i for every monomial
+    t of degree <= shift_deg and each of the 15 sparse quadratics over
+    F_(2^31-1), built by the symbolic preprocessing; b random vectors.  Each
+    product is timed with HIP events on the stream it runs on (the library's
+    timed call: mean of `reps` after a warm-up that also builds the transpose)."""
+    import numpy as np
+    import synth
+    n, p, polys = synth.config_system(3)
+    t = f4.pack_many(n, synth.monomials_upto(n, shift_deg))
+    ctx = f4.Context(0)
+    A = ctx.build_matrix_rows_packed(p, n, polys, np.repeat(t, len(polys)),
+                                     np.tile(np.arange(len(polys), dtype=np.uint32), len(t)))
+    r, N, nnz = A.view.r, A.view.N, A.view.nnz
+    rng = np.random.default_rng(7)
+    X = ctx.to_device(rng.integers(0, p, size=(N, b), dtype=np.int64))
+    W = ctx.to_device(rng.integers(0, p, size=(r, b), dtype=np.int64))
+    Y, YT = ctx.device_array((r, b)), ctx.device_array((N, b))
+    res = {"workload": "Macaulay matrix of the n=14 sparse quadratics (15 x 20 terms, F_(2^31-1), seed 3), "
+                       "shifts of degree <= %d; b = %d random vectors" % (shift_deg, b),
+           "r": r, "N": N, "nnz": nnz, "b": b}
+    for name, trans, src, dst, nout in (("ax", False, X, Y, r), ("atx", True, W, YT, N)):
+        ctx.spmm(p, A, src, trans=trans, out=dst)  # warm-up (builds the transpose once)
+        _, ms = ctx.spmm_timed(p, A, src, trans=trans, out=dst, reps=reps)
+        nin = N if not trans else r
+        byts = 4 * (nout + 1) + 8 * nnz + 4 * b * (nin + nout)  # pointers, entries, X once, Y once
+        gbs = byts / (ms * 1e-3) / 1e9
+        gather = 4 * b * nnz  # every stored entry gathers its b words of X (cache traffic beyond the first touch)
+        res[name] = {"ms": round(ms, 4), "alg_bytes": byts, "achieved_GBs": round(gbs, 1),
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "gather_bytes": gather,
+                     "with_gathers_GBs": round((byts - 4 * b * nin + gather) / (ms * 1e-3) / 1e9, 1),
+                     "entries_x_vectors_per_s": nnz * b / (ms * 1e-3)}
+    for d in (X, W, Y, YT):
+        d.free()
+    A.free()
+    ctx.close()
+    return res
 
 
 def modloop_leg(f4, nchains, iters):
@@ -384,6 +426,8 @@ def main():
     ctx.close()
     if args.sparse_repeats:
         out["sparse_step"] = sparse_step_leg(f4, args.sparse_repeats, tune)
+    if args.spmm_shift_deg:
+        out["spmm"] = spmm_leg(f4, args.spmm_shift_deg, 8, 20)
     if args.modloop_chains:
         out["modloop"] = modloop_leg(f4, args.modloop_chains, args.modloop_iters)
         # the kernels' own small-prime form (one-word Barrett) at the workload's prime

@@ -208,6 +208,34 @@ int f4_matrix_from_csr(f4_ctx* ctx, uint32_t r, uint32_t N, const uint32_t* row_
 int f4_matrix_get(const f4_matrix* A, f4_matrix_view* out);
 int f4_matrix_free(f4_matrix* A);
 
+/* Block operator application for Krylov solvers (section "Block Wiedemann
+ * and Block Lanczos"): Y = A X (trans = 0) or Y = A^T X (trans = 1) over F_p,
+ * A the r x N matrix of a handle of one system (f4_build_matrix,
+ * f4_build_matrix_rows or f4_matrix_from_csr), X and Y device arrays owned by
+ * the caller, row-major with b columns (1 <= b <= 64): X is N x b and Y is
+ * r x b for A X; X is r x b and Y is N x b for A^T X.  Stored values and the
+ * words of X are read modulo p; Y receives canonical residues.  The first
+ * transposed call on a handle builds the transpose's CSR on the device (kept
+ * with the handle, freed with it).  Asynchronous on `stream` (NULL: the
+ * context's stream); Y must not overlap X.  F4_E_ARG: p not an odd prime
+ * < 2^31, b out of range, trans not 0/1, a null block with a nonempty side,
+ * or a handle of a batch; F4_E_STATE: a handle not of this context. */
+int f4_spmm(f4_ctx* ctx, uint32_t p, f4_matrix* A, int trans, uint32_t b, const uint32_t* X, uint32_t* Y,
+            void* stream);
+/* f4_spmm repeated `reps` times on the context's stream between one pair of
+ * HIP events; *ms_per_call receives the mean time of one call (a transposed
+ * call on a handle without its transpose builds it first, outside the timed
+ * pair).  Same arguments and errors as f4_spmm, plus F4_E_ARG for reps = 0
+ * or a null ms_per_call. */
+int f4_spmm_timed(f4_ctx* ctx, uint32_t p, f4_matrix* A, int trans, uint32_t b, const uint32_t* X, uint32_t* Y,
+                  uint32_t reps, double* ms_per_call);
+/* Device memory from the context's cache (freed with the context at the
+ * latest), for blocks passed to f4_spmm; f4_upload copies host bytes to it
+ * and waits (f4_download copies back). */
+int f4_device_alloc(f4_ctx* ctx, size_t bytes, void** ptr);
+int f4_device_free(f4_ctx* ctx, void* ptr);
+int f4_upload(f4_ctx* ctx, void* dst, const void* src, size_t bytes);
+
 /* ------------------------------------------------- reduce (elimination) */
 typedef struct f4_reduced_view {
     uint32_t N;          /* columns of A */

@@ -8,6 +8,7 @@
 // selection strategy (all pairs of minimal lcm degree).  Each step then runs
 // SP on the device (build.hip), the elimination (reduce.hip), and appends the
 // reduced trailing rows to G on the device (pipeline step "Reconstruction").
+#include <functional>
 #include <algorithm>
 #include <exception>
 #include <mutex>
@@ -35,6 +36,9 @@ struct f4_ctx {
 struct f4_matrix {
     f4_ctx* owner;
     Matrix m;
+    // CSR of the transpose, built by the first transposed f4_spmm call
+    DBuf<u32> t_ptr, t_idx, t_val;
+    bool has_t = false;
 };
 struct f4_reduced {
     f4_ctx* owner;
@@ -1105,6 +1109,97 @@ int f4_matrix_from_csr(f4_ctx* X, uint32_t r, uint32_t N, const uint32_t* row_pt
     upload(c, m.val.ptr, val, (u64)nnz * 4);
     X->matrices.insert(M);
     *A = M;
+    F4_API_END(X)
+}
+
+// Checks f4_spmm's arguments, builds the transpose when asked for the first
+// time, and returns the launch of one product.
+static std::function<void()> spmm_call(f4_ctx* X, uint32_t p, f4_matrix* A, int trans, uint32_t b,
+                                       const uint32_t* Xin, uint32_t* Y) {
+    if (!A || A->owner != X || X->matrices.count(A) == 0) throw F4Error{F4_E_STATE, "unknown matrix handle"};
+    if (!is_odd_prime(p) || p >= (1u << 31) || b == 0 || b > 64 || (trans != 0 && trans != 1))
+        throw F4Error{F4_E_ARG, "bad argument"};
+    if (A->m.S != 1) throw F4Error{F4_E_ARG, "matrix of a batch"};
+    const SysPart& P = A->m.sys[0];
+    const u32 nout = trans ? P.N : P.r, nin = trans ? P.r : P.N;
+    if ((nout && !Y) || (nin && P.nnz && !Xin)) throw F4Error{F4_E_ARG, "null block"};
+    Ctx& c = X->c;
+    if (!trans) {
+        const u32* ptr = A->m.row_ptr.ptr;
+        const u32* idx = A->m.col_ind.ptr;
+        const u32* val = A->m.val.ptr;
+        const u32 r = P.r;
+        return [&c, p, r, b, ptr, idx, val, Xin, Y]() { spmm_run(c, p, r, b, ptr, idx, val, Xin, Y); };
+    }
+    if (!A->has_t) {
+        csr_transpose(c, P.r, P.N, P.nnz, A->m.row_ptr.ptr, A->m.col_ind.ptr, A->m.val.ptr, A->t_ptr, A->t_idx,
+                      A->t_val);
+        A->has_t = true;
+    }
+    const u32* ptr = A->t_ptr.ptr;
+    const u32* idx = A->t_idx.ptr;
+    const u32* val = A->t_val.ptr;
+    const u32 N = P.N;
+    return [&c, p, N, b, ptr, idx, val, Xin, Y]() { spmm_run(c, p, N, b, ptr, idx, val, Xin, Y); };
+}
+
+int f4_spmm(f4_ctx* X, uint32_t p, f4_matrix* A, int trans, uint32_t b, const uint32_t* Xin, uint32_t* Y,
+            void* stream) {
+    F4_API_BEGIN(X)
+    set_stream(X, stream);
+    spmm_call(X, p, A, trans, b, Xin, Y)();
+    F4_API_END(X)
+}
+
+int f4_spmm_timed(f4_ctx* X, uint32_t p, f4_matrix* A, int trans, uint32_t b, const uint32_t* Xin, uint32_t* Y,
+                  uint32_t reps, double* ms_per_call) {
+    F4_API_BEGIN(X)
+    if (reps == 0 || !ms_per_call) throw F4Error{F4_E_ARG, "bad argument"};
+    set_stream(X, nullptr);
+    Ctx& c = X->c;
+    auto run = spmm_call(X, p, A, trans, b, Xin, Y);
+    hipEvent_t e[2] = {nullptr, nullptr};
+    try {
+        F4_HIP_TRY(hipEventCreate(&e[0]));
+        F4_HIP_TRY(hipEventCreate(&e[1]));
+        F4_HIP_TRY(hipEventRecord(e[0], c.stream));
+        for (u32 i = 0; i < reps; ++i) run();
+        F4_HIP_TRY(hipEventRecord(e[1], c.stream));
+        F4_HIP_TRY(hipEventSynchronize(e[1]));
+        float ms = 0.f;
+        F4_HIP_TRY(hipEventElapsedTime(&ms, e[0], e[1]));
+        *ms_per_call = (double)ms / reps;
+    } catch (...) {
+        for (hipEvent_t v : e)
+            if (v) (void)hipEventDestroy(v);
+        throw;
+    }
+    for (hipEvent_t v : e) (void)hipEventDestroy(v);
+    F4_API_END(X)
+}
+
+int f4_device_alloc(f4_ctx* X, size_t bytes, void** ptr) {
+    F4_API_BEGIN(X)
+    if (!ptr) throw F4Error{F4_E_ARG, "null pointer"};
+    *ptr = X->c.pool.alloc(bytes ? bytes : 1);
+    F4_API_END(X)
+}
+
+int f4_device_free(f4_ctx* X, void* ptr) {
+    F4_API_BEGIN(X)
+    // blocks go back to the cache in stream order: wait for the work that may still use it
+    F4_HIP_TRY(hipStreamSynchronize(X->c.stream));
+    X->c.pool.release(ptr);
+    F4_API_END(X)
+}
+
+int f4_upload(f4_ctx* X, void* dst, const void* src, size_t bytes) {
+    F4_API_BEGIN(X)
+    if ((!dst || !src) && bytes) throw F4Error{F4_E_ARG, "null pointer"};
+    if (bytes) {
+        F4_HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, X->c.stream));
+        F4_HIP_TRY(hipStreamSynchronize(X->c.stream));
+    }
     F4_API_END(X)
 }
 

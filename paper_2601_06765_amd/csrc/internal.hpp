@@ -202,6 +202,14 @@ void tuned_sort(Ctx& c, u64* keys, u32* vals, u64 n, u32 lo_bit, u32 hi_bit);
 std::string tune_text(const Ctx& c);
 void tune_parse(Ctx& c, const char* text);
 
+// Block operator application (krylov.hip): Y = A X over F_p for a CSR matrix
+// (nrows rows) and a row-major block X of b <= 64 columns; words of the
+// matrix values and of X are read modulo p.  Enqueued on c.stream.
+void spmm_run(Ctx& c, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X, u32* Y);
+// CSR of the transpose (the CSC of A): column pointers, row indices, values.
+void csr_transpose(Ctx& c, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx, const u32* val,
+                   DBuf<u32>& tptr, DBuf<u32>& tidx, DBuf<u32>& tval);
+
 // Modular inner-loop microbenchmark (micro.hip): uploads the chains' start
 // values, times one launch of `iters` updates per chain with HIP events and
 // reads the final values back.  Arguments are checked by the caller.

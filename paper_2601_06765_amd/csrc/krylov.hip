@@ -1,0 +1,128 @@
+// Block operator application for Krylov solvers over F_p (section "Block
+// Wiedemann and Block Lanczos": the hot loop applies the matrix Pi, and often
+// its transpose, to a small block of b vectors; the block form turns SpMV into
+// SpMM).  Y = A X for a CSR matrix A and a row-major block X of b columns.
+// A transposed product runs the same kernel on the transpose's CSR (the CSC
+// of A), built once per matrix by a counting sort on the columns.
+//
+// Layout: a group of G lanes per output row (several rows per wave for small
+// b).  The group loads G consecutive stored entries of its row with one
+// coalesced access per lane, then broadcasts them inside the group: BP lanes
+// per entry (BP a power of two >= b; lane k reads X[col][k], so the b words of
+// a gathered row of X form one contiguous request) and G / BP entries per
+// broadcast step, BP steps per chunk of G entries, unrolled so that the
+// gathers of a chunk are in flight together.  Sums are exact integers (u64),
+// reduced once per output.
+#include "internal.hpp"
+
+#define SPMM_WG 256
+
+template <int BP, int G, bool SMALL>
+__global__ __launch_bounds__(SPMM_WG) void k_spmm(Fp f, u32 nrows, u32 b, const u32* __restrict__ ptr,
+                                                   const u32* __restrict__ idx, const u32* __restrict__ val,
+                                                   const u32* __restrict__ X, u32* __restrict__ Y) {
+    constexpr u32 SLOTS = G / BP;
+    static_assert(G <= F4_WAVE && G % BP == 0, "group layout");
+    const u64 g = ((u64)blockIdx.x * SPMM_WG + threadIdx.x) / G;  // output row of the group
+    const u32 gl = threadIdx.x % G, k = gl % BP, slot = gl / BP;
+    const bool live = g < nrows;
+    const u32 e0 = live ? ptr[g] : 0u, e1 = live ? ptr[g + 1] : 0u;
+    u64 acc = 0;
+    // the trip count is the same for every lane of a group, so a group's
+    // lanes are active or idle together in the exchanges below
+    for (u32 c0 = e0; c0 < e1; c0 += G) {
+        const u32 cnt = min((u32)G, e1 - c0);
+        const bool mine = gl < cnt;
+        const u32 mc = mine ? idx[c0 + gl] : 0u;
+        const u32 mv = mine ? val[c0 + gl] : 0u;
+#pragma unroll
+        for (u32 j = 0; j < BP; ++j) {
+            const u32 src = j * SLOTS + slot;  // entry of this step for this lane's slot
+            const u32 cj = (u32)__shfl((int)mc, (int)src, G);
+            const u32 vj = (u32)__shfl((int)mv, (int)src, G);
+            if (src < cnt && k < b) {
+                // stored words and X words are read modulo p
+                const u32 a = fp_reduce32(f, vj);
+                const u32 x = fp_reduce32(f, X[(u64)cj * b + k]);
+                acc += SMALL ? (u64)(a * x) : (u64)fp_reduce(f, (u64)a * x);  // SMALL: a*x < p^2 < 2^32
+            }
+        }
+    }
+    // the slots of a group hold partial sums of the same output column
+#pragma unroll
+    for (u32 d = BP; d < G; d <<= 1) acc += (u64)__shfl_xor((unsigned long long)acc, (int)d, G);
+    if (live && slot == 0 && k < b) Y[g * b + k] = fp_reduce_any(f, acc);
+}
+
+template <int BP, int G>
+static void spmm_launch(Ctx& c, const Fp& f, bool small, u32 nrows, u32 b, const u32* ptr, const u32* idx,
+                        const u32* val, const u32* X, u32* Y) {
+    const u32 grid = ceil_div((u64)nrows * G, SPMM_WG);
+    if (small)
+        hipLaunchKernelGGL((k_spmm<BP, G, true>), dim3(grid), dim3(SPMM_WG), 0, c.stream, f, nrows, b, ptr, idx, val,
+                           X, Y);
+    else
+        hipLaunchKernelGGL((k_spmm<BP, G, false>), dim3(grid), dim3(SPMM_WG), 0, c.stream, f, nrows, b, ptr, idx,
+                           val, X, Y);
+    F4_LAUNCH_CHECK();
+}
+
+void spmm_run(Ctx& c, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X, u32* Y) {
+    if (nrows == 0) return;
+    const Fp f = make_fp(p);
+    const bool small = p < 65536;
+    if (b <= 1)
+        spmm_launch<1, 8>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+    else if (b <= 2)
+        spmm_launch<2, 8>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+    else if (b <= 4)
+        spmm_launch<4, 8>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+    else if (b <= 8)
+        spmm_launch<8, 8>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+    else if (b <= 16)
+        spmm_launch<16, 16>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+    else if (b <= 32)
+        spmm_launch<32, 32>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+    else
+        spmm_launch<64, 64>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+}
+
+// ------------------------------------------------------------ transpose
+__global__ void k_col_count(const u32* __restrict__ idx, u64 nnz, u32* __restrict__ cnt) {
+    const u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) atomicAdd(&cnt[idx[e]], 1u);
+}
+
+// one thread per row of A: its entries go to the next free places of their
+// columns (the order inside a column is not fixed; sums over it are exact)
+__global__ void k_col_scatter(const u32* __restrict__ ptr, u32 nrows, const u32* __restrict__ idx,
+                              const u32* __restrict__ val, u32* __restrict__ cur, u32* __restrict__ tidx,
+                              u32* __restrict__ tval) {
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    for (u32 e = ptr[i]; e < ptr[i + 1]; ++e) {
+        const u32 pos = atomicAdd(&cur[idx[e]], 1u);
+        tidx[pos] = i;
+        tval[pos] = val[e];
+    }
+}
+
+void csr_transpose(Ctx& c, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx, const u32* val,
+                   DBuf<u32>& tptr, DBuf<u32>& tidx, DBuf<u32>& tval) {
+    tptr.reset(&c.pool, (u64)ncols + 1);
+    tidx.reset(&c.pool, std::max<u64>(nnz, 1));
+    tval.reset(&c.pool, std::max<u64>(nnz, 1));
+    DBuf<u32> cnt(&c.pool, (u64)ncols + 1);
+    fill_u32(cnt.ptr, (u64)ncols + 1, 0, c.stream);
+    if (nnz) {
+        hipLaunchKernelGGL(k_col_count, dim3(ceil_div(nnz, 256)), dim3(256), 0, c.stream, idx, nnz, cnt.ptr);
+        F4_LAUNCH_CHECK();
+    }
+    exclusive_scan_u32(cnt.ptr, tptr.ptr, ncols, c.pool, c.stream);
+    if (nnz && nrows) {
+        F4_HIP_TRY(hipMemcpyAsync(cnt.ptr, tptr.ptr, (u64)ncols * 4, hipMemcpyDeviceToDevice, c.stream));
+        hipLaunchKernelGGL(k_col_scatter, dim3(ceil_div(nrows, 256)), dim3(256), 0, c.stream, ptr, nrows, idx, val,
+                           cnt.ptr, tidx.ptr, tval.ptr);
+        F4_LAUNCH_CHECK();
+    }
+}

@@ -111,6 +111,11 @@ class ModloopStats(ctypes.Structure):
                 ("regs", c_u32), ("private_bytes", c_u32)]
 
 
+_sig("f4_spmm", c_int, [c_vp, c_u32, c_vp, c_int, c_u32, c_vp, c_vp, c_vp])
+_sig("f4_spmm_timed", c_int, [c_vp, c_u32, c_vp, c_int, c_u32, c_vp, c_vp, c_u32, P(ctypes.c_double)])
+_sig("f4_device_alloc", c_int, [c_vp, ctypes.c_size_t, P(c_vp)])
+_sig("f4_device_free", c_int, [c_vp, c_vp])
+_sig("f4_upload", c_int, [c_vp, c_vp, c_vp, ctypes.c_size_t])
 _sig("f4_modloop", c_int, [c_vp, c_u32, c_u32, c_u32, c_u32, P(c_u32), P(c_u32), P(c_u32), P(c_u32),
                            P(ModloopStats)])
 
@@ -373,6 +378,58 @@ class Context:
                                               c_vp(stream)))
         return Matrix(self, h, n)
 
+    def build_matrix_rows_packed(self, p, n, G, t_words, ks, stream=None):
+        """build_matrix_rows with the shifts given as arrays: t_words (P words,
+        e.g. from pack_many) and ks (basis indices), marshalled in bulk."""
+        arg = _PolysArg(n, *polys_to_arrays(n, G, sort=True))
+        t_words = np.asarray(t_words, dtype=np.uint64)
+        rs = np.zeros(len(t_words), dtype=np.dtype([("t", "<u8"), ("k", "<u4"), ("pad", "<u4")]))
+        rs["t"] = t_words
+        rs["k"] = np.asarray(ks, dtype=np.uint32)
+        h = c_vp()
+        self._check(_lib.f4_build_matrix_rows(self._h, p, ctypes.byref(arg.s), rs.ctypes.data_as(P(RowSpec)),
+                                              len(rs), ctypes.byref(h), c_vp(stream)))
+        return Matrix(self, h, n)
+
+    def device_array(self, shape):
+        """A block of u32 words in device memory from this context's cache."""
+        return DeviceArray(self, shape)
+
+    def to_device(self, arr):
+        """Upload a host array of words (taken modulo 2^32) as a DeviceArray."""
+        a = np.ascontiguousarray(np.asarray(arr, dtype=np.uint64).astype(np.uint32))
+        d = DeviceArray(self, a.shape)
+        if a.size:
+            self._check(_lib.f4_upload(self._h, c_vp(d.ptr), a.ctypes.data_as(c_vp), a.nbytes))
+        return d
+
+    def _spmm_args(self, A, X, trans, out):
+        b = 1 if len(X.shape) == 1 else X.shape[1]
+        nin, nout = (A.view.r, A.view.N) if trans else (A.view.N, A.view.r)
+        if X.shape[0] != nin:
+            raise ValueError("block rows do not match the matrix")
+        if out is None:
+            out = DeviceArray(self, (nout, b) if len(X.shape) == 2 else (nout,))
+        elif out.size != nout * b:
+            raise ValueError("output block does not match")
+        return b, out
+
+    def spmm(self, p, A, X, trans=False, out=None, stream=None):
+        """Y = A X (or A^T X) over F_p on the device (f4_spmm); X a DeviceArray
+        of shape (rows, b) or (rows,); returns Y as a DeviceArray."""
+        b, out = self._spmm_args(A, X, trans, out)
+        self._check(_lib.f4_spmm(self._h, p, A._h, 1 if trans else 0, b, c_vp(X.ptr), c_vp(out.ptr), c_vp(stream)))
+        return out
+
+    def spmm_timed(self, p, A, X, trans=False, out=None, reps=10):
+        """spmm repeated `reps` times between HIP events on the context's
+        stream (f4_spmm_timed); returns (Y, mean milliseconds per call)."""
+        b, out = self._spmm_args(A, X, trans, out)
+        ms = ctypes.c_double(0.0)
+        self._check(_lib.f4_spmm_timed(self._h, p, A._h, 1 if trans else 0, b, c_vp(X.ptr), c_vp(out.ptr), reps,
+                                       ctypes.byref(ms)))
+        return out, ms.value
+
     def matrix_from_csr(self, r, N, row_ptr, col_ind, val, stream=None):
         rp = np.ascontiguousarray(row_ptr, dtype=np.uint32)
         ci = np.ascontiguousarray(col_ind, dtype=np.uint32)
@@ -388,6 +445,32 @@ class Context:
         h = c_vp()
         self._check(_lib.f4_reduce(self._h, p, A._h, ctypes.byref(h), c_vp(stream)))
         return Reduced(self, h)
+
+
+class DeviceArray:
+    """u32 words in device memory owned by a context (f4_device_alloc)."""
+
+    def __init__(self, ctx, shape):
+        self.ctx = ctx
+        self.shape = tuple(int(x) for x in (shape if isinstance(shape, (tuple, list)) else (shape,)))
+        self.size = int(np.prod(self.shape, dtype=np.int64)) if self.shape else 1
+        h = c_vp()
+        ctx._check(_lib.f4_device_alloc(ctx._h, max(1, self.size) * 4, ctypes.byref(h)))
+        self.ptr = h.value
+
+    def to_host(self):
+        return self.ctx.download(self.ptr, self.size, np.uint32).reshape(self.shape)
+
+    def free(self):
+        if self.ptr and self.ctx._h:
+            _lib.f4_device_free(self.ctx._h, c_vp(self.ptr))
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Matrix:

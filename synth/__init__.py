@@ -76,6 +76,22 @@ def residues(p, count, seed):
     return np.concatenate(parts).astype(np.uint32) if parts else np.zeros(0, dtype=np.uint32)
 
 
+def monomials_upto(n, d):
+    """Every exponent vector of degree <= d in n variables, as rows of an int
+    array (degree 0 first; inside a degree, the order of
+    itertools.combinations_with_replacement over the variable indices)."""
+    import itertools
+    import numpy as np
+    rows = []
+    for k in range(d + 1):
+        for c in itertools.combinations_with_replacement(range(n), k):
+            e = [0] * n
+            for i in c:
+                e[i] += 1
+            rows.append(e)
+    return np.array(rows, dtype=np.int64).reshape(-1, n)
+
+
 def quadratic_support(n):
     """All monomials of degree <= 2 in n variables, as exponent tuples.
 
