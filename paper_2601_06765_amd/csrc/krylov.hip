@@ -11,80 +11,92 @@
 // per entry (BP a power of two >= b; lane k reads X[col][k], so the b words of
 // a gathered row of X form one contiguous request) and G / BP entries per
 // broadcast step, BP steps per chunk of G entries, unrolled so that the
-// gathers of a chunk are in flight together.  Sums are exact integers (u64),
-// reduced once per output.
+// gathers of a chunk are in flight together.  Each lane sums the raw 64-bit
+// products of its words exactly in 96 bits (a 64-bit sum and a carry count:
+// at most 2^32 products of words below 2^32), so no product is reduced; the
+// sum is reduced modulo p once per output (stored words and words of X may
+// be any 32-bit values: they act as their residues).
 #include "internal.hpp"
 
 #define SPMM_WG 256
 
-template <int BP, int G, bool SMALL>
+template <int BP, int G>
 __global__ __launch_bounds__(SPMM_WG) void k_spmm(Fp f, u32 nrows, u32 b, const u32* __restrict__ ptr,
                                                    const u32* __restrict__ idx, const u32* __restrict__ val,
                                                    const u32* __restrict__ X, u32* __restrict__ Y) {
     constexpr u32 SLOTS = G / BP;
     static_assert(G <= F4_WAVE && G % BP == 0, "group layout");
-    const u64 g = ((u64)blockIdx.x * SPMM_WG + threadIdx.x) / G;  // output row of the group
+    // workgroups go to the eight XCDs in turn; give each XCD a contiguous range
+    // of rows (neighbouring rows gather neighbouring rows of X through the same
+    // L2): workgroup w runs logical block x*q + min(x, rem) + w/8, x = w mod 8
+    const u32 nb = gridDim.x, q = nb / 8, rem = nb % 8, x = blockIdx.x % 8;
+    const u32 lb = x * q + min(x, rem) + blockIdx.x / 8;
+    const u64 g = ((u64)lb * SPMM_WG + threadIdx.x) / G;  // output row of the group
     const u32 gl = threadIdx.x % G, k = gl % BP, slot = gl / BP;
     const bool live = g < nrows;
     const u32 e0 = live ? ptr[g] : 0u, e1 = live ? ptr[g + 1] : 0u;
-    u64 acc = 0;
+    u64 lo = 0;  // exact sum of this lane's products: hi * 2^64 + lo
+    u32 hi = 0;
     // the trip count is the same for every lane of a group, so a group's
     // lanes are active or idle together in the exchanges below
+    // chunk loads run one chunk ahead of the gathers
+    u32 cnt = e1 > e0 ? min((u32)G, e1 - e0) : 0u;
+    u32 mc = gl < cnt ? idx[e0 + gl] : 0u;
+    u32 mv = gl < cnt ? val[e0 + gl] : 0u;
     for (u32 c0 = e0; c0 < e1; c0 += G) {
-        const u32 cnt = min((u32)G, e1 - c0);
-        const bool mine = gl < cnt;
-        const u32 mc = mine ? idx[c0 + gl] : 0u;
-        const u32 mv = mine ? val[c0 + gl] : 0u;
+        const u32 c1 = c0 + G;
+        const u32 cnt1 = c1 < e1 ? min((u32)G, e1 - c1) : 0u;
+        const u32 nc = gl < cnt1 ? idx[c1 + gl] : 0u;
+        const u32 nv = gl < cnt1 ? val[c1 + gl] : 0u;
 #pragma unroll
         for (u32 j = 0; j < BP; ++j) {
             const u32 src = j * SLOTS + slot;  // entry of this step for this lane's slot
             const u32 cj = (u32)__shfl((int)mc, (int)src, G);
             const u32 vj = (u32)__shfl((int)mv, (int)src, G);
             if (src < cnt && k < b) {
-                // stored words and X words are read modulo p
-                const u32 a = fp_reduce32(f, vj);
-                const u32 x = fp_reduce32(f, X[(u64)cj * b + k]);
-                acc += SMALL ? (u64)(a * x) : (u64)fp_reduce(f, (u64)a * x);  // SMALL: a*x < p^2 < 2^32
+                const u64 nl = lo + (u64)vj * X[(u64)cj * b + k];
+                hi += nl < lo ? 1u : 0u;
+                lo = nl;
             }
         }
+        cnt = cnt1;
+        mc = nc;
+        mv = nv;
     }
-    // the slots of a group hold partial sums of the same output column
+    // residue of the lane's sum, then the slots of a group (partial sums of
+    // the same output column) are added
+    const u32 c64 = fp_reduce(f, (u64)f.r32 * f.r32);  // 2^64 mod p
+    u64 acc = (u64)fp_reduce_any(f, lo) + fp_reduce(f, (u64)fp_reduce32(f, hi) * c64);
 #pragma unroll
     for (u32 d = BP; d < G; d <<= 1) acc += (u64)__shfl_xor((unsigned long long)acc, (int)d, G);
     if (live && slot == 0 && k < b) Y[g * b + k] = fp_reduce_any(f, acc);
 }
 
 template <int BP, int G>
-static void spmm_launch(Ctx& c, const Fp& f, bool small, u32 nrows, u32 b, const u32* ptr, const u32* idx,
-                        const u32* val, const u32* X, u32* Y) {
+static void spmm_launch(Ctx& c, const Fp& f, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val,
+                        const u32* X, u32* Y) {
     const u32 grid = ceil_div((u64)nrows * G, SPMM_WG);
-    if (small)
-        hipLaunchKernelGGL((k_spmm<BP, G, true>), dim3(grid), dim3(SPMM_WG), 0, c.stream, f, nrows, b, ptr, idx, val,
-                           X, Y);
-    else
-        hipLaunchKernelGGL((k_spmm<BP, G, false>), dim3(grid), dim3(SPMM_WG), 0, c.stream, f, nrows, b, ptr, idx,
-                           val, X, Y);
+    hipLaunchKernelGGL((k_spmm<BP, G>), dim3(grid), dim3(SPMM_WG), 0, c.stream, f, nrows, b, ptr, idx, val, X, Y);
     F4_LAUNCH_CHECK();
 }
 
 void spmm_run(Ctx& c, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X, u32* Y) {
     if (nrows == 0) return;
     const Fp f = make_fp(p);
-    const bool small = p < 65536;
     if (b <= 1)
-        spmm_launch<1, 8>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<1, 8>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 2)
-        spmm_launch<2, 8>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<2, 8>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 4)
-        spmm_launch<4, 8>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<4, 8>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 8)
-        spmm_launch<8, 8>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<8, 8>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 16)
-        spmm_launch<16, 16>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<16, 16>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 32)
-        spmm_launch<32, 32>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<32, 32>(c, f, nrows, b, ptr, idx, val, X, Y);
     else
-        spmm_launch<64, 64>(c, f, small, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<64, 64>(c, f, nrows, b, ptr, idx, val, X, Y);
 }
 
 // ------------------------------------------------------------ transpose
