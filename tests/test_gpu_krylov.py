@@ -83,6 +83,15 @@ def test_spmm_edges(env):
         c.spmm(p, B, c.to_device(np.ones((2, 1))))
     Y, ms = c.spmm_timed(p, B, c.to_device([3]), reps=3)
     assert host(Y).tolist() == [(p - 1) * 3 % p] and ms > 0
+    with pytest.raises(f4.F4Error) as e:
+        c.spmm(p, B, c.to_device(np.ones((1, 65))))
+    assert e.value.code == f4.F4_E_ARG
+    say("spmm matrix without columns")
+    E = c.matrix_from_csr(3, 0, [0, 0, 0, 0], [], [])
+    Y = c.spmm(p, E, c.to_device(np.zeros((0, 2))))
+    YT = c.spmm(p, E, c.to_device(np.ones((3, 2))), trans=True)
+    assert host(Y).shape == (3, 2) and not host(Y).any() and host(YT).shape == (0, 2)
+    E.free()
     B.free()
 
 
