@@ -187,8 +187,13 @@ def spmm_leg(f4, shift_deg, b, reps):
     n, p, polys = synth.config_system(3)
     t = f4.pack_many(n, synth.monomials_upto(n, shift_deg))
     ctx = f4.Context(0)
-    A = ctx.build_matrix_rows_packed(p, n, polys, np.repeat(t, len(polys)),
-                                     np.tile(np.arange(len(polys), dtype=np.uint32), len(t)))
+    tw, ks = np.repeat(t, len(polys)), np.tile(np.arange(len(polys), dtype=np.uint32), len(t))
+    A = ctx.build_matrix_rows_packed(p, n, polys, tw, ks)  # warm-up build
+    A.free()
+    t0 = time.perf_counter()
+    A = ctx.build_matrix_rows_packed(p, n, polys, tw, ks)
+    ctx.download(A.view.row_ptr, 1, np.uint32)  # waits for the build's stream
+    t_build = time.perf_counter() - t0
     r, N, nnz = A.view.r, A.view.N, A.view.nnz
     rng = np.random.default_rng(7)
     X = ctx.to_device(rng.integers(0, p, size=(N, b), dtype=np.int64))
@@ -196,7 +201,11 @@ def spmm_leg(f4, shift_deg, b, reps):
     Y, YT = ctx.device_array((r, b)), ctx.device_array((N, b))
     res = {"workload": "Macaulay matrix of the n=14 sparse quadratics (15 x 20 terms, F_(2^31-1), seed 3), "
                        "shifts of degree <= %d; b = %d random vectors" % (shift_deg, b),
-           "r": r, "N": N, "nnz": nnz, "b": b}
+           "r": r, "N": N, "nnz": nnz, "b": b,
+           # symbolic preprocessing of the same operator (f4_build_matrix_rows, wall clock including
+           # its host-side row planning): algorithmic bytes 8 nnz + 16 r + 8 N (CSR out, row metadata, dictionary)
+           "build_ms": round(t_build * 1e3, 3), "build_nnz_per_s": nnz / t_build,
+           "build_alg_GBs": round((8 * nnz + 16 * r + 8 * N) / t_build / 1e9, 1)}
     for name, trans, src, dst, nout in (("ax", False, X, Y, r), ("atx", True, W, YT, N)):
         ctx.spmm(p, A, src, trans=trans, out=dst)  # warm-up (builds the transpose once)
         _, ms = ctx.spmm_timed(p, A, src, trans=trans, out=dst, reps=reps)

@@ -140,6 +140,28 @@ def test_spmm_full_size_macaulay_sampled(env):
     h = A.to_host()
     A.free()
     Yh, YTh = host(Y), host(YT)
+    # the operator itself (this size takes the symbolic preprocessing's global
+    # bitmap path): the dictionary is exactly the set of the products t*m over
+    # all rows and terms, and sampled rows re-expand to t * f_k
+    words = [f4.pack_many(n, np.array([e for e, _ in f], dtype=np.int64)) for f in polys]
+    coefs = [np.array([c0 % p for _, c0 in f], dtype=np.int64) for f in polys]
+    dk = h["dict_keys"]
+    order = np.argsort(dk)
+    sdk = dk[order]
+    hits = np.zeros(N, dtype=bool)
+    for kk in range(len(polys)):
+        rsel = np.nonzero(h["row_k"] == kk)[0]
+        prods = (h["row_t"][rsel][:, None] + words[kk][None, :]).ravel()
+        pos = np.searchsorted(sdk, prods)
+        assert (pos < N).all() and np.array_equal(sdk[np.minimum(pos, N - 1)], prods)
+        hits[pos] = True
+    assert hits.all()
+    ptr0 = h["row_ptr"].astype(np.int64)
+    for i in np.random.default_rng(9).choice(r, size=300, replace=False):
+        kk, t0 = int(h["row_k"][i]), h["row_t"][i]
+        got = {int(dk[j]): int(v) for j, v in zip(h["col_ind"][ptr0[i]:ptr0[i + 1]], h["val"][ptr0[i]:ptr0[i + 1]])}
+        want = {int(t0 + w0): int(c0) for w0, c0 in zip(words[kk], coefs[kk]) if c0}
+        assert got == want
     rng = np.random.default_rng(5)
     rows = np.sort(rng.choice(r, size=2000, replace=False))
     ptr = h["row_ptr"].astype(np.int64)
