@@ -757,7 +757,14 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
 
     const int local_bitmap = (max_tabn + max_words) * 4 <= 48 * 1024;
     const size_t mark_lds = (max_tabn + (local_bitmap ? max_words : 0)) * 4;
-    const u32 bx = std::max<u32>(1, std::min<u32>((u32)std::max(1, c.dev.cus), ceil_div(2048, S)));
+    u32 bx = std::max<u32>(1, std::min<u32>((u32)std::max(1, c.dev.cus), ceil_div(2048, S)));
+    {
+        // a large row set: enough waves in flight (up to 8 workgroups per CU)
+        // to hide the latency of each row's dependent loads
+        u32 r0max = 0;
+        for (u32 i = 0; i < S; ++i) r0max = std::max(r0max, args[i].r0);
+        bx = std::max<u32>(bx, std::min<u32>(8u * (u32)std::max(1, c.dev.cus) / S, ceil_div(r0max, MB_WAVES * 16)));
+    }
     auto mark = [&]() {
         hipLaunchKernelGGL(k_mark_rows, dim3(bx, S), dim3(MB_THREADS), mark_lds, s, dsegs, rows_t.ptr,
                            rows_k.ptr, row_lmrank.ptr, ctr, present, done, leadmap, local_bitmap);
