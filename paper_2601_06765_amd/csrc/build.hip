@@ -132,11 +132,8 @@ __global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, con
                 q = 0;
             }
             row_lmrank[S.rbase + row] = q;
-            // test before set: a word seen with the bit set needs no atomic
-            // (a stale read only costs a redundant one)
-            const u32 bit = 1u << (q & 31);
-            if (!(Dn[q >> 5] & bit)) atomicOr(&Dn[q >> 5], bit);
-            if (!(Ld[q >> 5] & bit)) atomicOr(&Ld[q >> 5], bit);
+            atomicOr(&Dn[q >> 5], 1u << (q & 31));
+            atomicOr(&Ld[q >> 5], 1u << (q & 31));
         }
         const u64 off = S.off[k];
         const u32 len = S.len[k];
@@ -148,7 +145,7 @@ __global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, con
             }
             if (local_bitmap)
                 atomicOr(&lbits[q >> 5], 1u << (q & 31));
-            else if (!(P[q >> 5] & (1u << (q & 31))))  // most monomials occur in many rows
+            else
                 atomicOr(&P[q >> 5], 1u << (q & 31));
         }
     }
