@@ -43,9 +43,9 @@ __global__ __launch_bounds__(SPMM_WG) void k_spmm(Fp f, u32 nrows, u32 b, const 
     u32 cnt = e1 > e0 ? min((u32)G, e1 - e0) : 0u;
     u32 mc = gl < cnt ? idx[e0 + gl] : 0u;
     u32 mv = gl < cnt ? val[e0 + gl] : 0u;
-    for (u32 c0 = e0; c0 < e1; c0 += G) {
-        const u32 c1 = c0 + G;
-        const u32 cnt1 = c1 < e1 ? min((u32)G, e1 - c1) : 0u;
+    for (u64 c0 = e0; c0 < e1; c0 += G) {  // 64-bit: c0 + G must not wrap near 2^32 entries
+        const u64 c1 = c0 + G;
+        const u32 cnt1 = c1 < e1 ? (u32)min((u64)G, e1 - c1) : 0u;
         const u32 nc = gl < cnt1 ? idx[c1 + gl] : 0u;
         const u32 nv = gl < cnt1 ? val[c1 + gl] : 0u;
 #pragma unroll
