@@ -7,6 +7,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
   dictionary, ``% p`` arithmetic), driven through ctypes by :class:`OracleRun`.
 * O2 ``buchberger.py``: Buchberger's algorithm with all pairs, in pure Python.
 * O3 ``dense.py``: dense Gaussian elimination over Python integers.
+* O4 ``modloop.py``: the iterated modular update of the arithmetic
+  microbenchmark, by ``%``.
+* O5 ``krylov.py``: the block operator application Y = A X / A^T X over F_p.
 
 Each is pinned in ``tests/test_oracle_*.py`` against facts fixed by the paper
 and by mathematics (uniqueness of the reduced Groebner basis, closed forms,
