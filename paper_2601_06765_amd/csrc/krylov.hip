@@ -8,8 +8,9 @@
 // Layout: a group of G lanes per output row (several rows per wave for small
 // b).  The group loads G consecutive stored entries of its row with one
 // coalesced access per lane, then broadcasts them inside the group: BP lanes
-// per entry (BP a power of two >= b; lane k reads X[col][k], so the b words of
-// a gathered row of X form one contiguous request) and G / BP entries per
+// per entry, lane k reading VW consecutive words of the gathered row of X
+// (BP * VW >= b, VW = 2 for even b), so that the b words form one contiguous
+// request, and G / BP entries per
 // broadcast step, BP steps per chunk of G entries, unrolled so that the
 // gathers of a chunk are in flight together.  Each lane sums the raw 64-bit
 // products of its words exactly in 96 bits (a 64-bit sum and a carry count:
@@ -20,26 +21,28 @@
 
 #define SPMM_WG 256
 
-template <int BP, int G>
+template <int BP, int G, int VW>
 __global__ __launch_bounds__(SPMM_WG) void k_spmm(Fp f, u32 nrows, u32 b, const u32* __restrict__ ptr,
                                                    const u32* __restrict__ idx, const u32* __restrict__ val,
                                                    const u32* __restrict__ X, u32* __restrict__ Y) {
     constexpr u32 SLOTS = G / BP;
-    static_assert(G <= F4_WAVE && G % BP == 0, "group layout");
+    static_assert(G <= F4_WAVE && G % BP == 0 && (VW == 1 || VW == 2), "group layout");
     // workgroups go to the eight XCDs in turn; give each XCD a contiguous range
     // of rows (neighbouring rows gather neighbouring rows of X through the same
     // L2): workgroup w runs logical block x*q + min(x, rem) + w/8, x = w mod 8
     const u32 nb = gridDim.x, q = nb / 8, rem = nb % 8, x = blockIdx.x % 8;
     const u32 lb = x * q + min(x, rem) + blockIdx.x / 8;
     const u64 g = ((u64)lb * SPMM_WG + threadIdx.x) / G;  // output row of the group
-    const u32 gl = threadIdx.x % G, k = gl % BP, slot = gl / BP;
+    // lane k of an entry covers the VW columns k*VW .. k*VW + VW - 1 (VW = 2
+    // needs an even b: a lane's two words are one aligned 8-byte access)
+    const u32 gl = threadIdx.x % G, k = (gl % BP) * VW, slot = gl / BP;
     const bool live = g < nrows;
     const u32 e0 = live ? ptr[g] : 0u, e1 = live ? ptr[g + 1] : 0u;
-    u64 lo = 0;  // exact sum of this lane's products: hi * 2^64 + lo
-    u32 hi = 0;
+    u64 lo[VW] = {};  // exact sums of this lane's products: hi * 2^64 + lo
+    u32 hi[VW] = {};
     // the trip count is the same for every lane of a group, so a group's
-    // lanes are active or idle together in the exchanges below
-    // chunk loads run one chunk ahead of the gathers
+    // lanes are active or idle together in the exchanges below; chunk loads
+    // run one chunk ahead of the gathers
     u32 cnt = e1 > e0 ? min((u32)G, e1 - e0) : 0u;
     u32 mc = gl < cnt ? idx[e0 + gl] : 0u;
     u32 mv = gl < cnt ? val[e0 + gl] : 0u;
@@ -54,49 +57,84 @@ __global__ __launch_bounds__(SPMM_WG) void k_spmm(Fp f, u32 nrows, u32 b, const 
             const u32 cj = (u32)__shfl((int)mc, (int)src, G);
             const u32 vj = (u32)__shfl((int)mv, (int)src, G);
             if (src < cnt && k < b) {
-                const u64 nl = lo + (u64)vj * X[(u64)cj * b + k];
-                hi += nl < lo ? 1u : 0u;
-                lo = nl;
+                u32 xv[VW];
+                if (VW == 2) {
+                    const uint2 w2 = *reinterpret_cast<const uint2*>(X + (u64)cj * b + k);
+                    xv[0] = w2.x;
+                    xv[VW - 1] = w2.y;
+                } else {
+                    xv[0] = X[(u64)cj * b + k];
+                }
+#pragma unroll
+                for (u32 v = 0; v < VW; ++v) {
+                    const u64 nl = lo[v] + (u64)vj * xv[v];
+                    hi[v] += nl < lo[v] ? 1u : 0u;
+                    lo[v] = nl;
+                }
             }
         }
         cnt = cnt1;
         mc = nc;
         mv = nv;
     }
-    // residue of the lane's sum, then the slots of a group (partial sums of
-    // the same output column) are added
+    // residue of each lane sum, then the slots of a group (partial sums of
+    // the same output columns) are added
     const u32 c64 = fp_reduce(f, (u64)f.r32 * f.r32);  // 2^64 mod p
-    u64 acc = (u64)fp_reduce_any(f, lo) + fp_reduce(f, (u64)fp_reduce32(f, hi) * c64);
+    u32 out[VW];
 #pragma unroll
-    for (u32 d = BP; d < G; d <<= 1) acc += (u64)__shfl_xor((unsigned long long)acc, (int)d, G);
-    if (live && slot == 0 && k < b) Y[g * b + k] = fp_reduce_any(f, acc);
+    for (u32 v = 0; v < VW; ++v) {
+        u64 acc = (u64)fp_reduce_any(f, lo[v]) + fp_reduce(f, (u64)fp_reduce32(f, hi[v]) * c64);
+#pragma unroll
+        for (u32 d = BP; d < G; d <<= 1) acc += (u64)__shfl_xor((unsigned long long)acc, (int)d, G);
+        out[v] = fp_reduce_any(f, acc);
+    }
+    if (live && slot == 0 && k < b) {
+        if (VW == 2)
+            *reinterpret_cast<uint2*>(Y + g * b + k) = make_uint2(out[0], out[VW - 1]);
+        else
+            Y[g * b + k] = out[0];
+    }
 }
 
-template <int BP, int G>
+template <int BP, int G, int VW>
 static void spmm_launch(Ctx& c, const Fp& f, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val,
                         const u32* X, u32* Y) {
     const u32 grid = ceil_div((u64)nrows * G, SPMM_WG);
-    hipLaunchKernelGGL((k_spmm<BP, G>), dim3(grid), dim3(SPMM_WG), 0, c.stream, f, nrows, b, ptr, idx, val, X, Y);
+    hipLaunchKernelGGL((k_spmm<BP, G, VW>), dim3(grid), dim3(SPMM_WG), 0, c.stream, f, nrows, b, ptr, idx, val, X,
+                       Y);
     F4_LAUNCH_CHECK();
 }
 
 void spmm_run(Ctx& c, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X, u32* Y) {
     if (nrows == 0) return;
     const Fp f = make_fp(p);
+    if (b % 2 == 0) {  // two words per lane
+        if (b <= 2)
+            spmm_launch<1, 8, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+        else if (b <= 4)
+            spmm_launch<2, 8, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+        else if (b <= 8)
+            spmm_launch<4, 8, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+        else if (b <= 16)
+            spmm_launch<8, 8, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+        else if (b <= 32)
+            spmm_launch<16, 16, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+        else
+            spmm_launch<32, 32, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+        return;
+    }
     if (b <= 1)
-        spmm_launch<1, 8>(c, f, nrows, b, ptr, idx, val, X, Y);
-    else if (b <= 2)
-        spmm_launch<2, 8>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<1, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 4)
-        spmm_launch<4, 8>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<4, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 8)
-        spmm_launch<8, 8>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<8, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 16)
-        spmm_launch<16, 16>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<16, 16, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 32)
-        spmm_launch<32, 32>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<32, 32, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
     else
-        spmm_launch<64, 64>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<64, 64, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
 }
 
 // ------------------------------------------------------------ transpose

@@ -46,7 +46,7 @@ def random_csr(r, N, seed, vmax, empty_every=7, maxlen=40):
 
 
 @pytest.mark.parametrize("p", [3, 65521, synth.P31])
-@pytest.mark.parametrize("b", [1, 2, 3, 5, 8, 13, 32, 64])
+@pytest.mark.parametrize("b", [1, 2, 3, 5, 6, 8, 12, 13, 32, 64])
 def test_spmm_random(env, p, b):
     f4, c = env
     r, N = 1037, 705
