@@ -219,6 +219,19 @@ def spmm_leg(f4, shift_deg, b, reps):
                      "entries_x_vectors_per_s": nnz * b / (ms * 1e-3)}
     for d in (X, W, Y, YT):
         d.free()
+    # other block widths, A X only: b = 1 (the scalar Wiedemann product) and 32
+    res["ax_other_b"] = {}
+    for bb in (1, 32):
+        Xb = ctx.to_device(rng.integers(0, p, size=(N, bb), dtype=np.int64))
+        Yb = ctx.device_array((r, bb))
+        ctx.spmm(p, A, Xb, out=Yb)
+        _, ms = ctx.spmm_timed(p, A, Xb, out=Yb, reps=reps)
+        byts = 4 * (r + 1) + 8 * nnz + 4 * bb * (N + r)
+        res["ax_other_b"][str(bb)] = {"ms": round(ms, 4), "achieved_GBs": round(byts / (ms * 1e-3) / 1e9, 1),
+                                      "frac_hbm": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                      "entries_x_vectors_per_s": nnz * bb / (ms * 1e-3)}
+        Xb.free()
+        Yb.free()
     A.free()
     ctx.close()
     return res
