@@ -1,11 +1,19 @@
-"""Benchmark: full F4 runs of the n=10, m=12 dense quadratic system over
-F_65521 (grevlex, seed 2) through the C-ABI on one MI355X.
+"""Benchmark of the F4 reduction step over F_p on one MI355X, through the C-ABI.
 
-One "step" of this benchmark is one complete pass of the hot path over one
-system: every F4 reduction step (symbolic preprocessing + elimination mod p)
-until the reduced Groebner basis is known.  The headline value is Macaulay
-nnz built+reduced per second: the sum over F4 steps of nnz(A) divided by the
-wall time of the run.  Per-degree figures use the HIP-event stage times.
+Headline ("step" of this benchmark): the first degree-5 F4 step of 15 sparse
+random quadratics in n=14 variables over F_(2^31-1) (20 monomials each,
+grevlex, seed 3): symbolic preprocessing of its Macaulay matrix
+(r = 7 169 rows, N = 9 482 columns, 3.28 million nonzeros) and its
+elimination mod p.  value = nnz(A) / (t_DictBuild + t_RowAssemble +
+t_NumericCore), the stage times of that step from HIP events on the
+library's stream, median over the timed runs (each run repeats the steps of
+lower degree untimed, to reach the step with its real basis).  The oracle
+(textbook F4, one host thread) on the same step is the CPU baseline.
+
+Secondary legs: full F4 runs of the n=10, m=12 dense system (nnz/s over all
+steps), the batched and served forms against the plain one-system-at-a-time
+path (systems/s), the block operator application of the Krylov branch, and
+the modular inner-loop microbenchmark.
 
 Prints one JSON line (rank 0, N=1).  `--gpus N` with N > 1 exits: this
 build measures one GPU.
@@ -14,6 +22,7 @@ build measures one GPU.
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -21,19 +30,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+STEP_DEG = 5  # the timed step of the headline workload
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10, help="timed runs of the headline step (median reported)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dict", choices=["rank", "radix"], default=None)
+    ap.add_argument("--full-runs", type=int, default=20, help="timed full F4 runs of the n=10 system (0: skip)")
     ap.add_argument("--batch-systems", type=int, default=256, help="systems in the batched leg (0: skip)")
+    ap.add_argument("--crt", type=int, default=1, help="run the 8-prime CRT leg (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg (0: skip)")
-    ap.add_argument("--sparse-repeats", type=int, default=3, help="timed runs of the n=14 sparse step (0: skip)")
     ap.add_argument("--modloop-chains", type=int, default=1 << 21,
                     help="chains of the modular inner-loop microbenchmark (0: skip)")
     ap.add_argument("--modloop-iters", type=int, default=4096)
@@ -43,6 +53,7 @@ def parse():
                     help="fixed schedules instead of the autotuner's measured picks (tuned during warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (reference kernel for HBM byte counters)")
+    ap.add_argument("--step-only", action="store_true", help="only the headline step (for profiling runs)")
     return ap.parse_args()
 
 
@@ -60,13 +71,7 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_bytes": n, "launches": 5}))
 
 
-# int32 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-VALU_OPS_PER_S = 256 * 4 * 16 * 2.4e9
-# a modular product needs at least a 24-bit multiply and an add (reductions
-# amortised over lazy accumulation)
-MODMUL_PEAK = VALU_OPS_PER_S / 2
-
-
+KERNEL_FILES = {"k_ech_block": "reduce.hip", "k_trsm": "reduce.hip"}
 KERNEL_HEADS = {
     "k_ech_block": "__global__ __launch_bounds__(1024) void k_ech_block(",
     "k_trsm": "__global__ __launch_bounds__(TR_THREADS) void k_trsm(",
@@ -74,22 +79,22 @@ KERNEL_HEADS = {
 
 
 def kernel_fingerprint(kernel):
-    """SHA-1 of the kernel's source text (its function in csrc/reduce.hip plus
-    csrc/common.hpp): counters taken on another version do not apply."""
+    """SHA-1 of the kernel's source text (its function plus csrc/common.hpp):
+    counters taken on another version do not apply."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2601_06765_amd", "csrc")
-    src = open(os.path.join(csrc, "reduce.hip")).read()
+    src = open(os.path.join(csrc, KERNEL_FILES[kernel])).read()
     a = src.index(KERNEL_HEADS[kernel])
     b = src.index("\n}\n", a)
     common = open(os.path.join(csrc, "common.hpp")).read()
     return hashlib.sha1((src[a:b] + common).encode()).hexdigest()
 
 
-def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/hbm_counters_n10.md), or None when it has none for the kernel
-    or the kernel's source has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "hbm_counters_n10.md")
+def recorded_traffic(kernel, summary):
+    """HBM bytes per launch of `kernel` from a committed counter summary under
+    profiles/, or None when it has none for the kernel or the kernel's source
+    has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", summary)
     value, sha = None, None
     try:
         for line in open(path):
@@ -105,74 +110,168 @@ def recorded_traffic(kernel):
     return value
 
 
-def roofline_of(allsteps):
-    """Roofline of the kernel with the largest total time over the timed runs
-    (HIP events around each launch): the triangular solve or the echelon block
-    step, both bound by integer vector arithmetic.  achieved = modular products
-    the kernel performed / its summed launch time."""
+def step_bytes(s):
+    """Algorithmic HBM bytes of one F4 step (unit: one nonzero of A).  Build:
+    the CSR written once (u32 column + u32 value per nonzero), 16 B of row
+    pointer and row metadata per row, the 8-byte dictionary; elimination: the
+    CSR read once, the reduced trailing block D' written once (L x c words)
+    and its echelon rows (rho x c words)."""
+    c = s["N"] - s["npivot"]
+    build = 8 * s["nnz"] + 16 * s["r"] + 8 * s["N"]
+    reduce = 8 * s["nnz"] + 4 * s["r"] + 4 * s["lower"] * c + 4 * s["rho"] * c
+    trsm = 8 * s["nnz"] + 4 * s["r"] + 4 * s["lower"] * c
+    return build, reduce, trsm
+
+
+def roofline_of(kstats, step, e3_peak):
+    """Roofline of the dominant elimination kernel of the timed step (largest
+    summed launch time, HIP events around each launch on the library's stream).
+    Triangular solve: bound by HBM; achieved = its algorithmic bytes (the CSR
+    read once, D' written once) / its launch time.  Echelon block step: bound by
+    integer vector arithmetic; achieved = its modular products / its launch
+    time, against the modular-product peak the inner-loop microbenchmark
+    measures for the kernel's arithmetic form."""
     cand = {
-        "k_trsm": (sum(s["t_k_trsm_ms"] for run in allsteps for s in run),
-                   sum(s["trsm_ops"] for run in allsteps for s in run),
-                   sum(s["n_k_trsm"] for run in allsteps for s in run)),
-        "k_ech_block": (sum(s["t_k_block_ms"] for run in allsteps for s in run),
-                        sum(s["block_ops"] for run in allsteps for s in run),
-                        sum(s["n_k_block"] for run in allsteps for s in run)),
+        "k_trsm": (sum(s["t_k_trsm_ms"] for s in kstats), sum(s["trsm_ops"] for s in kstats),
+                   sum(s["n_k_trsm"] for s in kstats)),
+        "k_ech_block": (sum(s["t_k_block_ms"] for s in kstats), sum(s["block_ops"] for s in kstats),
+                        sum(s["n_k_block"] for s in kstats)),
     }
     name = max(cand, key=lambda k: cand[k][0])
     ms, ops, launches = cand[name]
-    achieved = ops / (ms / 1000.0) / 1e12 if ms > 0 else 0.0
-    peak = MODMUL_PEAK / 1e12
-    traffic = recorded_traffic(name)
-    return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 3), "unit": "Tmodmul/s",
-            "frac": round(achieved / peak, 5), "traffic": traffic, "kernel": name,
-            "launches_per_run": launches / len(allsteps), "ms_per_launch": ms / max(1, launches),
-            "ops_per_launch": ops / max(1, launches),
-            "other_kernel_ms_per_run": {k: round(v[0] / len(allsteps), 4) for k, v in cand.items()}}
+    runs = len(kstats)
+    per = ms / max(1, launches)
+    traffic = recorded_traffic(name, "hbm_counters_n14_step.md")
+    other = {k: {"ms_per_run": round(v[0] / runs, 4), "launches_per_run": v[2] / runs,
+                 "modmul_per_run": v[1] / runs,
+                 "Tmodmul_per_s": round(v[1] / (v[0] / 1e3) / 1e12, 4) if v[0] else None}
+             for k, v in cand.items()}
+    if name == "k_trsm":
+        _, _, tb = step_bytes(step)
+        byts = tb / max(1, launches / runs)
+        achieved = byts / (per / 1e3) / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic, "kernel": name,
+                "alg_bytes_per_launch": byts, "ms_per_launch": round(per, 5), "kernels": other}
+    achieved = ops / (ms / 1e3) / 1e12 if ms > 0 else 0.0
+    return {"bound": "alu", "achieved": round(achieved, 5), "peak": e3_peak, "unit": "Tmodmul/s",
+            "frac": round(achieved / e3_peak, 6) if e3_peak else None, "traffic": traffic, "kernel": name,
+            "peak_source": "modular inner-loop microbenchmark, measured in this run",
+            "ms_per_launch": round(per, 5), "ops_per_launch": ops / max(1, launches), "kernels": other}
 
 
-def cpu_baseline(n, p, polys, seconds):
-    """The oracle as it is (textbook F4, one thread) on whole runs of the same system."""
-    import oracle
-    t0 = time.perf_counter()
-    runs, nnz = 0, 0
-    while True:
-        run = oracle.OracleRun(n, p, polys)
-        nnz += sum(s["M"] for s in run.steps())
-        runs += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full F4 run(s) of the same n=10 m=12 system, single thread, %.1f s" % (runs, dt)}
-
-
-def sparse_step_leg(f4, repeats, autotune):
-    """Workload 3: 15 sparse quadratics in n=14 over F_(2^31-1) (20 monomials
-    each, seed 3); F4 on the GPU up to and including the first step of degree
-    5, whose preprocessing (DictBuild + RowAssemble) and elimination
-    (NumericCore) are reported separately."""
+def headline_leg(f4, torch, steps, warmup, autotune, dict_path):
+    """The timed step: F4 on the n=14 sparse system up to and including its
+    first degree-5 step; stage times of that step from HIP events (median over
+    `steps` runs), then the same runs with HIP events around every launch of the
+    elimination kernels (roofline), and the autotuner's table."""
     import synth
     n, p, polys = synth.config_system(3)
-    ctx = f4.Context(0, timing=True, stop_deg=5, autotune=autotune)
-    ctx.groebner(p, n, polys)  # warm-up (and tuning)
-    runs = []
-    for _ in range(repeats):
-        t0 = time.perf_counter()
-        _, steps = ctx.groebner(p, n, polys)
-        runs.append((time.perf_counter() - t0, steps[-1]))
+    ctx = f4.Context(0, timing=True, stop_deg=STEP_DEG, autotune=autotune, dict_path=dict_path)
+    prep = ctx.prepare(p, n, polys)
+    for _ in range(warmup):
+        ctx.groebner_prepared(prep)
+    torch.cuda.synchronize()
+    runs, walls = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        _, st = ctx.groebner_prepared(prep)
+        walls.append(time.perf_counter() - t1)
+        runs.append(st[-1])
+    torch.cuda.synchronize()
+    timed_s = time.perf_counter() - t0
+    table = ctx.tune_table()
     ctx.close()
-    s = runs[0][1]
-    avg = lambda key: sum(r[1][key] for r in runs) / len(runs)
-    sp = avg("t_dict_ms") + avg("t_assemble_ms")
-    el = avg("t_numeric_ms")
-    return {"workload": "n=14, m=15 sparse quadratics (20 monomials), F_(2^31-1), seed 3: first degree-5 step",
-            "deg": s["deg"], "r": s["r"], "N": s["N"], "nnz": s["nnz"], "npivot": s["npivot"],
-            "lower": s["lower"], "rho": s["rho"],
-            "t_preprocess_ms": round(sp, 4), "t_elimination_ms": round(el, 4),
-            "t_trsm_ms": round(avg("t_trsm_ms"), 4), "t_echelon_ms": round(avg("t_echelon_ms"), 4),
-            "nnz_per_s_preprocess": s["nnz"] / (sp / 1000.0), "nnz_per_s_step": s["nnz"] / ((sp + el) / 1000.0),
-            "rows_per_s_step": s["r"] / ((sp + el) / 1000.0),
-            "run_to_step_ms": round(1000.0 * sum(r[0] for r in runs) / len(runs), 3)}
+    kctx = f4.Context(0, kernel_timing=True, stop_deg=STEP_DEG, autotune=autotune, dict_path=dict_path)
+    kctx.load_tune_table(table)
+    prep = kctx.prepare(p, n, polys)
+    kctx.groebner_prepared(prep)
+    kstats = [kctx.groebner_prepared(prep)[1][-1] for _ in range(steps)]
+    kctx.close()
+    s = runs[0]
+    assert s["deg"] == STEP_DEG, "the run did not reach a degree-%d step" % STEP_DEG
+    tot = [r["t_dict_ms"] + r["t_assemble_ms"] + r["t_numeric_ms"] for r in runs]
+    med = statistics.median(tot)
+    mid = lambda key: statistics.median(r[key] for r in runs)
+    build, reduce, _ = step_bytes(s)
+    return {
+        "n": n, "p": p, "m": len(polys), "step": s, "ms": med, "timed_s": timed_s, "table": table,
+        "kstats": kstats,
+        "stages": {"t_dict_ms": round(mid("t_dict_ms"), 4), "t_assemble_ms": round(mid("t_assemble_ms"), 4),
+                   "t_numeric_ms": round(mid("t_numeric_ms"), 4), "t_trsm_ms": round(mid("t_trsm_ms"), 4),
+                   "t_echelon_ms": round(mid("t_echelon_ms"), 4),
+                   "t_preprocess_ms": round(mid("t_dict_ms") + mid("t_assemble_ms"), 4),
+                   "stage_sum_min_ms": round(min(tot), 4), "stage_sum_max_ms": round(max(tot), 4),
+                   "host_wall_of_step_ms": round(mid("t_step_ms"), 4),
+                   "run_to_step_wall_ms": round(1e3 * statistics.median(walls), 3)},
+        "hbm_alg": {"build_bytes": build, "reduce_bytes": reduce,
+                    "frac_of_8TBs": (build + reduce) / (med / 1e3) / (HBM_PEAK_GBS * 1e9),
+                    "preprocess_frac": build / (((mid("t_dict_ms") + mid("t_assemble_ms")) / 1e3)
+                                                * HBM_PEAK_GBS * 1e9)},
+    }
+
+
+def cpu_baseline_step(n, p, polys, nnz):
+    """The oracle as it is (textbook F4, one host thread) run up to and
+    including the same degree-5 step; value = nnz of that step / the oracle's
+    own build + reduce time of the step."""
+    import oracle
+    t0 = time.perf_counter()
+    run = oracle.OracleRun(n, p, polys, stop_deg=STEP_DEG)
+    dt = time.perf_counter() - t0
+    st = run.steps()[-1]
+    assert st["d"] == STEP_DEG and st["M"] == nnz, "oracle step differs from the GPU step"
+    tb, tr = run.times_ns()[-1]
+    step_s = (tb + tr) * 1e-9
+    return {"value": nnz / step_s, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": "one oracle run to the first degree-5 step of the n=14 sparse system (%.1f s in all); "
+                      "that step's build %.2f s + elimination %.2f s, single thread" % (dt, tb * 1e-9, tr * 1e-9)}
+
+
+def full_f4_leg(f4, torch, runs, warmup, autotune, dict_path):
+    """Full F4 runs of the n=10, m=12 dense quadratics over F_65521 (seed 2):
+    nnz/s over all steps of a run, and the per-step stage times."""
+    import synth
+    n, p, polys = synth.config_system(2)
+    ctx = f4.Context(0, dict_path=dict_path, autotune=autotune)
+    prep = ctx.prepare(p, n, polys)
+    for _ in range(warmup):
+        ctx.groebner_prepared(prep)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        basis, _ = ctx.groebner_prepared(prep)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    table = ctx.tune_table()
+    ctx.close()
+    assert basis == [[((0,) * n, 1)]], "unexpected basis"
+    ictx = f4.Context(0, timing=True, dict_path=dict_path, autotune=autotune)
+    ictx.load_tune_table(table)
+    prep = ictx.prepare(p, n, polys)
+    ictx.groebner_prepared(prep)
+    allsteps = [ictx.groebner_prepared(prep)[1] for _ in range(runs)]
+    ictx.close()
+    nnz_run = sum(s["nnz"] for s in allsteps[0])
+    per_step = []
+    for k in range(len(allsteps[0])):
+        s0 = allsteps[0][k]
+        mid = lambda key: statistics.median(run[k][key] for run in allsteps)
+        gpu_ms = mid("t_dict_ms") + mid("t_assemble_ms") + mid("t_numeric_ms")
+        build, reduce, _ = step_bytes(s0)
+        per_step.append({"deg": s0["deg"], "r": s0["r"], "N": s0["N"], "nnz": s0["nnz"], "npivot": s0["npivot"],
+                         "lower": s0["lower"], "rho": s0["rho"], "t_dict_ms": round(mid("t_dict_ms"), 4),
+                         "t_assemble_ms": round(mid("t_assemble_ms"), 4),
+                         "t_numeric_ms": round(mid("t_numeric_ms"), 4), "t_trsm_ms": round(mid("t_trsm_ms"), 4),
+                         "t_echelon_ms": round(mid("t_echelon_ms"), 4),
+                         "t_pairs_host_ms": round(mid("t_pairs_ms"), 4),
+                         "nnz_per_s_gpu": s0["nnz"] / (gpu_ms / 1e3) if gpu_ms > 0 else None,
+                         "hbm_frac_alg": (build + reduce) / (gpu_ms / 1e3) / (HBM_PEAK_GBS * 1e9)
+                         if gpu_ms > 0 else None})
+    return {"workload": "full F4, n=10, m=12 dense quadratics over F_65521, grevlex, normal strategy (seed 2)",
+            "runs": runs, "f4_steps": len(allsteps[0]), "nnz_per_run": nnz_run, "ms_per_run": dt * 1e3 / runs,
+            "nnz_per_s": nnz_run * runs / dt, "systems_per_s_plain": runs / dt, "per_f4_step": per_step}
 
 
 def spmm_leg(f4, shift_deg, b, reps):
@@ -185,6 +284,7 @@ def spmm_leg(f4, shift_deg, b, reps):
     import numpy as np
     import synth
     n, p, polys = synth.config_system(3)
+    polys = f4.normalize(p, n, polys)
     t = f4.pack_many(n, synth.monomials_upto(n, shift_deg))
     ctx = f4.Context(0)
     tw, ks = np.repeat(t, len(polys)), np.tile(np.arange(len(polys), dtype=np.uint32), len(t))
@@ -258,11 +358,16 @@ def modloop_leg(f4, nchains, iters):
     return res
 
 
-def batch_leg(ctx, count):
+def same_bases(a, b):
+    return [x[0] for x in a] == [y[0] for y in b]
+
+
+def batch_leg(f4, torch, count, autotune):
     """Workload 4: `count` independent systems (n ~ U{6..9}, m = n+1 dense,
-    F_65521): one f4_groebner_batch call vs the same systems one by one."""
-    import torch
+    F_65521): one f4_groebner_batch call vs the same systems one by one; every
+    batched basis must equal its one-by-one basis (the bench fails otherwise)."""
     import synth
+    ctx = f4.Context(0, autotune=autotune)
     systems = [(p, n, polys) for n, p, polys in synth.batch_systems(count)]
     prep = ctx.prepare_batch(systems)
     ctx.groebner_batch_prepared(prep)  # warm-up
@@ -273,15 +378,47 @@ def batch_leg(ctx, count):
     tb = time.perf_counter() - t0
     preps = [ctx.prepare(p, n, polys) for p, n, polys in systems]  # marshalled once, as for the batch
     t0 = time.perf_counter()
-    for q in preps:
-        ctx.groebner_prepared(q)
+    plain = [ctx.groebner_prepared(q) for q in preps]
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    ctx.close()
+    bad = [j for j in range(count) if res[j][0] != plain[j][0]]
+    if bad:
+        raise SystemExit("batched bases differ from the one-by-one bases for systems %s" % bad[:10])
     nnz = sum(s["nnz"] for _, steps in res for s in steps)
     return {"workload": "%d dense systems, n ~ U{6..9}, m = n+1, F_65521 (seeds 4*2^32+j)" % count,
             "systems": count, "batched_s": tb, "plain_s": tp,
             "systems_per_s_batched": count / tb, "systems_per_s_plain": count / tp,
-            "speedup": tp / tb, "nnz_total": nnz, "nnz_per_s_batched": nnz / tb}
+            "speedup": tp / tb, "nnz_total": nnz, "nnz_per_s_batched": nnz / tb,
+            "checked": "all %d batched bases equal their one-by-one bases" % count}
+
+
+def crt_leg(f4, torch, autotune):
+    """Workload 4's CRT part: one n=9 dense system read modulo the 8 largest
+    primes below 2^31, as one batch of 8 against 8 plain runs; bases compared."""
+    import synth
+    n, polys = synth.crt_system()
+    systems = [(q, n, polys) for q in synth.CRT_PRIMES]
+    ctx = f4.Context(0, autotune=autotune)
+    prep = ctx.prepare_batch(systems)
+    ctx.groebner_batch_prepared(prep)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.groebner_batch_prepared(prep)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    preps = [ctx.prepare(q, n, polys) for q, n, polys in systems]
+    t0 = time.perf_counter()
+    plain = [ctx.groebner_prepared(q) for q in preps]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    ctx.close()
+    if not same_bases(res, plain):
+        raise SystemExit("CRT batch bases differ from the plain runs")
+    return {"workload": "one n=9, m=10 dense system under the 8 largest primes below 2^31",
+            "systems": len(systems), "systems_per_s_batched": len(systems) / tb,
+            "systems_per_s_plain": len(systems) / tp, "speedup": tp / tb,
+            "nnz_total": sum(s["nnz"] for _, st in res for s in st)}
 
 
 def serve_leg(f4, ctx, seconds):
@@ -352,124 +489,62 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     import torch
-    import synth
     import paper_2601_06765_amd.f4 as f4
 
     torch.cuda.init()
-    n, p, polys = synth.config_system(2)
-    # the headline: the timed runs without instrumentation
     tune = not args.no_autotune
-    plain = f4.Context(0, dict_path=args.dict, autotune=tune)
-    prep = plain.prepare(p, n, polys)  # host SoA arrays of the input, built once
-    for _ in range(args.warmup):
-        plain.groebner_prepared(prep)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        basis, _ = plain.groebner_prepared(prep)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    table = plain.tune_table()
-    plain.close()
-    assert basis == [[((0,) * n, 1)]], "unexpected basis"
-    # the same runs again with HIP events around every stage and around each
-    # launch of the two elimination kernels (stage times, roofline)
-    ctx = f4.Context(0, timing=True, dict_path=args.dict, autotune=tune)
-    ctx.load_tune_table(table)  # the headline runs' schedules
-    prep = ctx.prepare(p, n, polys)
-    for _ in range(args.warmup):
-        ctx.groebner_prepared(prep)
-    torch.cuda.synchronize()
-    allsteps = []
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        basis, steps = ctx.groebner_prepared(prep)
-        allsteps.append(steps)
-    torch.cuda.synchronize()
-    dt_instr = time.perf_counter() - t1
-
-    nnz_run = sum(s["nnz"] for s in allsteps[0])
-    rows_run = sum(s["r"] for s in allsteps[0])
-    ms_run = dt * 1000.0 / args.steps
-    value = nnz_run * args.steps / dt
-
-    # per F4 step (averaged over runs): GPU stage times from HIP events
-    per_step = []
-    nsteps = len(allsteps[0])
-    avg = lambda k, key: sum(run[k][key] for run in allsteps) / len(allsteps)
-    for k in range(nsteps):
-        s0 = allsteps[0][k]
-        gpu_ms = avg(k, "t_dict_ms") + avg(k, "t_assemble_ms") + avg(k, "t_numeric_ms")
-        c = s0["N"] - s0["npivot"]
-        # algorithmic bytes of the step (unit: one nonzero of A): build writes
-        # the CSR (8 B per nonzero, 16 per row, 8 per column), the elimination
-        # reads it once and writes the trailing block and its echelon rows
-        alg = (8 * s0["nnz"] + 16 * s0["r"] + 8 * s0["N"]) + (8 * s0["nnz"] + 4 * s0["r"]
-                                                               + 4 * s0["lower"] * c + 4 * s0["rho"] * c)
-        per_step.append({
-            "deg": s0["deg"], "r": s0["r"], "N": s0["N"], "nnz": s0["nnz"], "npivot": s0["npivot"],
-            "lower": s0["lower"], "rho": s0["rho"],
-            "t_dict_ms": round(avg(k, "t_dict_ms"), 4),
-            "t_assemble_ms": round(avg(k, "t_assemble_ms"), 4),
-            "t_numeric_ms": round(avg(k, "t_numeric_ms"), 4),
-            "t_trsm_ms": round(avg(k, "t_trsm_ms"), 4),
-            "t_echelon_ms": round(avg(k, "t_echelon_ms"), 4),
-            "wall_ms": round(avg(k, "t_step_ms"), 4),
-            "t_pairs_host_ms": round(avg(k, "t_pairs_ms"), 4),
-            "nnz_per_s_gpu": s0["nnz"] / (gpu_ms / 1000.0) if gpu_ms > 0 else None,
-            "rows_per_s_gpu": s0["r"] / (gpu_ms / 1000.0) if gpu_ms > 0 else None,
-            "hbm_frac_alg": alg / (gpu_ms / 1000.0) / (HBM_PEAK_GBS * 1e9) if gpu_ms > 0 else None,
-        })
-
-    out_roof = roofline_of(allsteps)
+    h = headline_leg(f4, torch, args.steps, args.warmup, tune, args.dict)
+    s = h["step"]
     out = {
         "metric": "Macaulay nnz/s built+reduced per F4 step; systems/sec batched vs plain",
-        "value": value,
+        "value": s["nnz"] / (h["ms"] / 1e3),
         "unit": "nnz/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_run,
+        "ms_per_step": h["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
-        "data": "synthetic (seeded dense random quadratics, splitmix64 seed 2)",
-        "config": {"workload": "full F4, n=10, m=12 dense quadratics over F_65521, grevlex, normal strategy",
-                   "n": n, "m": len(polys), "p": p, "f4_steps": nsteps, "nnz_per_run": nnz_run,
-                   "rows_per_run": rows_run, "dict_path": args.dict or "auto"},
-        "rows_per_s": rows_run * args.steps / dt,
-        "ms_per_step_instrumented": dt_instr * 1000.0 / args.steps,
-        "systems_per_s_plain": args.steps / dt,
-        "per_f4_step": per_step,
-        "roofline": out_roof,
-        "autotune": {"on": tune, "table": table.splitlines()},
+        "data": "synthetic (seeded sparse random quadratics, splitmix64 seed 3)",
+        "config": {"workload": "first degree-5 F4 step of 15 sparse random quadratics (20 monomials each) "
+                               "in n=14 variables over F_(2^31-1), grevlex",
+                   "n": h["n"], "m": h["m"], "p": h["p"], "deg": s["deg"], "r": s["r"], "N": s["N"],
+                   "nnz": s["nnz"], "npivot": s["npivot"], "lower": s["lower"], "rho": s["rho"],
+                   "rank": s["rank"], "dict_path": args.dict or "auto"},
+        "rows_per_s": s["r"] / (h["ms"] / 1e3),
+        "stat": "median of %d runs of the step (stage times from HIP events)" % args.steps,
+        "stages": h["stages"],
+        "hbm_alg": h["hbm_alg"],
+        "autotune": {"on": tune, "table": h["table"].splitlines()},
     }
-    ctx.close()
-    if args.sparse_repeats:
-        out["sparse_step"] = sparse_step_leg(f4, args.sparse_repeats, tune)
-    if args.spmm_shift_deg:
-        out["spmm"] = spmm_leg(f4, args.spmm_shift_deg, 8, 20)
-    if args.modloop_chains:
+    e3 = None
+    if args.modloop_chains and not args.step_only:
         out["modloop"] = modloop_leg(f4, args.modloop_chains, args.modloop_iters)
-        # the kernels' own small-prime form (one-word Barrett) at the workload's prime
-        e3 = [x for x in out["modloop"]["forms"] if x["form"] == "barrett32" and x["p"] == p]
-        if e3:
-            mp = e3[0]["updates_per_s"] / 1e12
-            out_roof["measured_peak"] = {"value": round(mp, 3), "unit": "Tmodmul/s",
-                                         "source": "modular inner-loop microbenchmark, one-word Barrett, p = %d" % p,
-                                         "frac": round(out_roof["achieved"] / mp, 5)}
-    if args.batch_systems:
-        bctx = f4.Context(0, autotune=tune)
-        out["batch"] = batch_leg(bctx, args.batch_systems)
-        bctx.close()
-        out["systems_per_s_batched"] = out["batch"]["systems_per_s_batched"]
-    if args.serve_seconds > 0:
-        sctx = f4.Context(0, autotune=tune)
-        out["serve"] = serve_leg(f4, sctx, args.serve_seconds)
-        sctx.close()
+        # the echelon's large-prime form (two-word Barrett) at the workload's prime
+        f = [x for x in out["modloop"]["forms"] if x["form"] == "barrett64" and x["p"] == h["p"]]
+        e3 = round(f[0]["updates_per_s"] / 1e12, 4) if f else None
+    out["roofline"] = roofline_of(h["kstats"], s, e3)
+    if not args.step_only:
+        if args.full_runs:
+            out["full_f4_n10"] = full_f4_leg(f4, torch, args.full_runs, args.warmup, tune, args.dict)
+        if args.spmm_shift_deg:
+            out["spmm"] = spmm_leg(f4, args.spmm_shift_deg, 8, 20)
+        if args.batch_systems:
+            out["batch"] = batch_leg(f4, torch, args.batch_systems, tune)
+            out["systems_per_s_batched"] = out["batch"]["systems_per_s_batched"]
+            out["systems_per_s_plain"] = out["batch"]["systems_per_s_plain"]
+        if args.crt:
+            out["crt"] = crt_leg(f4, torch, tune)
+        if args.serve_seconds > 0:
+            sctx = f4.Context(0, autotune=tune)
+            out["serve"] = serve_leg(f4, sctx, args.serve_seconds)
+            sctx.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, p, polys, args.cpu_seconds)
+        import synth
+        n, p, polys = synth.config_system(3)
+        out["cpu_baseline"] = cpu_baseline_step(n, p, polys, s["nnz"])
     print(json.dumps(out))
 
 

@@ -68,7 +68,9 @@ enum {
     F4_OPT_TIMING = 1u << 0,     /* record per-stage HIP-event timings in f4_step_stats */
     F4_OPT_DICT_RANK = 1u << 1,  /* force the dense-rank dictionary (bitmap sort/unique) */
     F4_OPT_DICT_RADIX = 1u << 2, /* force the radix-sort dictionary (sort + unique + join) */
-    F4_OPT_AUTOTUNE = 1u << 3    /* pick schedules by measurement (see f4_tune_export) */
+    F4_OPT_AUTOTUNE = 1u << 3,   /* pick schedules by measurement (see f4_tune_export) */
+    F4_OPT_KERNEL_TIMING = 1u << 4 /* also HIP events around every launch of the triangular-solve
+                                      and echelon block-step kernels, and their product counts */
 };
 typedef struct f4_opts {
     uint32_t flags;
@@ -83,6 +85,19 @@ typedef struct f4_opts {
     uint32_t trsm_rows;
     /* 0: tuned or default (8).  1..8: bits per digit pass of the radix sorts. */
     uint32_t radix_bits;
+    /* Device memory of the context (all of it: the block cache, matrices,
+     * bases, scratch).  NULL: hipMalloc / hipFree.  Otherwise alloc(user,
+     * bytes, stream) returns `bytes` of device memory on the context's device,
+     * 256-byte aligned, or NULL when it cannot (the call then fails with
+     * F4_E_NOMEM and the context stays usable); `stream` is the stream the
+     * context works on at that moment (the memory may be used on it at once).
+     * free(user, ptr, stream) returns a block; the context calls it only after
+     * the work that used the block has finished (it synchronizes its stream
+     * first), at the latest in f4_destroy.  The context caches blocks, so the
+     * callbacks see few, large requests.  Both or neither must be set. */
+    void* (*alloc)(void* user, size_t bytes, void* stream);
+    void (*free)(void* user, void* ptr, void* stream);
+    void* alloc_user;
 } f4_opts;
 
 /* Create a context on HIP device `device` (opts may be NULL).  The context owns
@@ -148,6 +163,26 @@ typedef struct f4_polys {
     int on_device;
 } f4_polys;
 
+/* Checks host polynomials against the form above (the input contract of
+ * f4_build_matrix and f4_build_matrix_rows): P words of n variables, terms in
+ * strictly decreasing grevlex order (unsorted or repeated terms fail),
+ * coefficients in [1, p), no zero polynomial, and with monic != 0 leading
+ * coefficients 1.  Host-side, no context needed.  Returns F4_OK or F4_E_ARG;
+ * *bits (may be NULL) receives the failed rules: 1 a word that is not a
+ * monomial of n variables, 2 order, 4 coefficient range, 8 not monic, 16 a
+ * zero polynomial. */
+int f4_check_polys(uint32_t p, const f4_polys* G, int monic, uint32_t* bits);
+/* Brings host polynomials into the form above: each polynomial's terms are
+ * sorted by decreasing grevlex, repeated monomials merged (coefficients added
+ * mod p), coefficients reduced mod p and zero terms dropped; monic != 0 also
+ * divides each polynomial by its leading coefficient.  mon_out / coeff_out
+ * have room for in->offset[in->npolys] terms, off_out for npolys + 1 offsets
+ * (a polynomial that cancels to zero keeps an empty range).  Host-side, no
+ * context.  F4_E_ARG: bad p or n, a word that is not a monomial of n
+ * variables, decreasing offsets, null arrays. */
+int f4_normalize_polys(uint32_t p, const f4_polys* in, int monic, uint64_t* mon_out, uint32_t* coeff_out,
+                       uint64_t* off_out);
+
 /* A critical pair of basis indices (i < j). */
 typedef struct f4_pair {
     uint32_t i, j;
@@ -187,15 +222,18 @@ typedef struct f4_matrix_view {
  *   active  : host array of G->npolys bytes, nonzero = usable as a reducer.
  *   sel     : host array of nsel pairs, all with the same lcm degree.
  *   A       : out, a context-owned matrix handle (free with f4_matrix_free).
- * Errors: F4_E_ARG (bad p, n, indices, empty selection), F4_E_RANGE (lane
- * overflow), F4_E_NOMEM, F4_E_DEVICE. */
+ * Errors: F4_E_ARG (bad p, n, indices, empty selection; a basis that breaks
+ * the f4_polys form - see f4_check_polys - or is not monic: host input is
+ * checked on the host, device input by a kernel before any use), F4_E_RANGE
+ * (lane overflow), F4_E_NOMEM, F4_E_DEVICE. */
 int f4_build_matrix(f4_ctx* ctx, uint32_t p, const f4_polys* G, const uint8_t* active,
                     const f4_pair* sel, uint32_t nsel, f4_matrix** A, void* stream);
 
 /* The same map for an explicit row list R (host, r entries) with no closure:
  * the matrix of Definition "Sparse Macaulay matrix for a batch" for
  * (T = union of supports, R).  Theorem "Matrix materialization correctness"
- * is stated for exactly this object. */
+ * is stated for exactly this object.  G must have the f4_polys form (checked
+ * as for f4_build_matrix; it need not be monic); F4_E_ARG otherwise. */
 int f4_build_matrix_rows(f4_ctx* ctx, uint32_t p, const f4_polys* G, const f4_rowspec* R, uint32_t r,
                          f4_matrix** A, void* stream);
 
@@ -217,7 +255,9 @@ int f4_matrix_free(f4_matrix* A);
  * words of X are read modulo p; Y receives canonical residues.  The first
  * transposed call on a handle builds the transpose's CSR on the device (kept
  * with the handle, freed with it).  Asynchronous on `stream` (NULL: the
- * context's stream); Y must not overlap X.  F4_E_ARG: p not an odd prime
+ * context's stream); Y must not overlap X.  X and Y need 4-byte alignment
+ * only (8-byte aligned blocks with an even b take a faster layout).
+ * F4_E_ARG: p not an odd prime
  * < 2^31, b out of range, trans not 0/1, a null block with a nonempty side,
  * or a handle of a batch; F4_E_STATE: a handle not of this context. */
 int f4_spmm(f4_ctx* ctx, uint32_t p, f4_matrix* A, int trans, uint32_t b, const uint32_t* X, uint32_t* Y,
@@ -253,7 +293,10 @@ typedef struct f4_reduced_view {
  * the rows; one pivot row per pivot column; the other rows are reduced by the
  * pivot rows on the pivot columns (sparse triangular solve), and the reduced
  * row echelon form of the remaining trailing block is returned as CSR over the
- * columns of A, rows ordered by leading column.  A is not modified. */
+ * columns of A, rows ordered by leading column.  A is not modified.
+ * F4_E_ARG: bad p, or stored values outside [1, p) (checked on the device for
+ * a matrix from f4_matrix_from_csr or built for another prime); F4_E_STATE: a
+ * handle not of this context. */
 int f4_reduce(f4_ctx* ctx, uint32_t p, const f4_matrix* A, f4_reduced** out, void* stream);
 int f4_reduced_get(const f4_reduced* R, f4_reduced_view* out);
 int f4_reduced_free(f4_reduced* R);
@@ -271,7 +314,7 @@ typedef struct f4_step_stats {
     float t_echelon_ms;   /* of which the trailing-block echelon */
     float t_step_ms;      /* host wall time of the whole step */
     float t_pairs_ms;     /* host time of pair selection and Gebauer-Moeller updates */
-    /* per kernel (timing option only; for a batch, the batch's launches):
+    /* per kernel (F4_OPT_KERNEL_TIMING only; for a batch, the batch's launches):
      * the triangular-solve kernel and the echelon block-step kernel, summed
      * over their launches (HIP events around each launch on the call's
      * stream), their launch counts, and the modular products they performed

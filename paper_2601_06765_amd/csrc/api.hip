@@ -102,6 +102,7 @@ void readback(Ctx& c, void* dst, const void* src, size_t bytes) {
 }
 
 bool timing_on(const Ctx& c) { return (c.flags & F4_OPT_TIMING) != 0; }
+bool kernel_timing_on(const Ctx& c) { return (c.flags & F4_OPT_KERNEL_TIMING) != 0; }
 
 hipEvent_t stage_event(Ctx& c) {
     if (!(c.flags & F4_OPT_TIMING)) return nullptr;
@@ -112,6 +113,21 @@ hipEvent_t stage_event(Ctx& c) {
     }
     hipEvent_t e = c.events[c.ev_used++];
     F4_HIP_TRY(hipEventRecord(e, c.stream));
+    return e;
+}
+
+hipEvent_t kernel_event(Ctx& c) {
+    if (!(c.flags & F4_OPT_KERNEL_TIMING)) return nullptr;
+    const u32 keep = c.flags;
+    c.flags |= F4_OPT_TIMING;
+    hipEvent_t e = nullptr;
+    try {
+        e = stage_event(c);
+    } catch (...) {
+        c.flags = keep;
+        throw;
+    }
+    c.flags = keep;
     return e;
 }
 
@@ -318,16 +334,103 @@ static int fail(f4_ctx* X, const F4Error& e) {
     }                                                        \
     return F4_OK;
 
-// A basis given through the C-ABI, moved into device SoA with metadata.
-static void load_polys(Ctx& c, const f4_polys* G, DevG& D) {
+// Input terms of a basis given to the matrix builders (the f4_polys contract):
+// every word a P word of n variables (no bits outside the lanes and the degree
+// field, lanes adding up to the degree), terms of a polynomial in strictly
+// decreasing grevlex order (so no monomial repeats), coefficients in [1, p),
+// and, when `monic`, leading coefficients 1.  Error bits of the check:
+enum : u32 { CHK_WORD = 1, CHK_ORDER = 2, CHK_COEFF = 4, CHK_MONIC = 8, CHK_EMPTY = 16 };
+
+static const char* check_message(u32 bits) {
+    if (bits & CHK_WORD) return "a term is not a monomial word of n variables";
+    if (bits & CHK_ORDER) return "terms not in strictly decreasing grevlex order (unsorted or repeated)";
+    if (bits & CHK_COEFF) return "a coefficient is 0 or not below p";
+    if (bits & CHK_MONIC) return "a basis element is not monic";
+    if (bits & CHK_EMPTY) return "zero polynomial in basis";
+    return "bad basis";
+}
+
+__host__ __device__ static u32 check_term(u64 P, u32 c, u32 n, u32 w, u64 lanes, u32 p) {
+    u32 bad = 0;
+    if (P & ~(lanes | (0xffull << 56))) bad |= CHK_WORD;
+    u32 d = 0;
+    for (u32 i = 0; i < n; ++i) d += mono_exp(P, i, w);
+    if (d != mono_deg(P)) bad |= CHK_WORD;
+    if (c == 0 || c >= p) bad |= CHK_COEFF;
+    return bad;
+}
+
+// host arrays: the error bits of every polynomial
+static u32 check_polys_host(u32 n, u32 p, u32 npolys, const u64* mon, const u32* coeff, const u64* off, bool monic) {
+    const u32 w = lane_bits(n);
+    const u64 lanes = (1ull << (n * w)) - 1;
+    u32 bad = 0;
+    for (u32 k = 0; k < npolys; ++k) {
+        if (off[k + 1] <= off[k]) {
+            bad |= CHK_EMPTY;
+            continue;
+        }
+        if (monic && coeff[off[k]] != 1) bad |= CHK_MONIC;
+        for (u64 e = off[k]; e < off[k + 1]; ++e) {
+            bad |= check_term(mon[e], coeff[e], n, w, lanes, p);
+            if (e > off[k] && (mon[e] ^ lanes) >= (mon[e - 1] ^ lanes)) bad |= CHK_ORDER;
+        }
+    }
+    return bad;
+}
+
+// device arrays: one wave per polynomial, error bits OR-ed into *flag
+__global__ void k_check_polys(const u64* mon, const u32* coeff, const u64* off, u32 npolys, u32 n, u32 p, int monic,
+                              u32* flag) {
+    const u32 w = lane_bits(n);
+    const u64 lanes = (1ull << (n * w)) - 1;
+    const u32 lane = lane_id();
+    u32 bad = 0;
+    for (u32 k = (blockIdx.x * blockDim.x + threadIdx.x) / F4_WAVE; k < npolys;
+         k += gridDim.x * blockDim.x / F4_WAVE) {
+        const u64 a = off[k], b = off[k + 1];
+        if (b <= a) {
+            bad |= CHK_EMPTY;
+            continue;
+        }
+        if (lane == 0 && monic && coeff[a] != 1) bad |= CHK_MONIC;
+        for (u64 e = a + lane; e < b; e += F4_WAVE) {
+            bad |= check_term(mon[e], coeff[e], n, w, lanes, p);
+            if (e > a && (mon[e] ^ lanes) >= (mon[e - 1] ^ lanes)) bad |= CHK_ORDER;
+        }
+    }
+    for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) bad |= __shfl_xor(bad, d, F4_WAVE);
+    if (lane == 0 && bad) atomicOr(flag, bad);
+}
+
+// stored matrix values outside [1, p) set *flag
+__global__ void k_check_vals(const u32* val, u64 nnz, u32 p, u32* flag) {
+    bool bad = false;
+    for (u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (u64)gridDim.x * blockDim.x)
+        bad |= val[e] == 0 || val[e] >= p;
+    if (__ballot(bad) && lane_id() == 0) atomicOr(flag, 1u);
+}
+
+// A basis given through the C-ABI, checked against the f4_polys contract and
+// moved into device SoA with metadata.
+static void load_polys(Ctx& c, u32 p, const f4_polys* G, DevG& D, bool monic) {
     if (!G || G->n == 0 || G->n > 14) throw F4Error{F4_E_ARG, "bad number of variables"};
+    if (!G->offset || (G->npolys && (!G->mon || !G->coeff))) throw F4Error{F4_E_ARG, "null basis array"};
     D.n = G->n;
     std::vector<u64> off(G->npolys + 1);
     if (G->on_device)
         readback(c, off.data(), G->offset, off.size() * 8);
     else
         std::memcpy(off.data(), G->offset, off.size() * 8);
+    if (off[0] != 0) throw F4Error{F4_E_ARG, "offsets must start at 0"};
+    for (u32 k = 0; k < G->npolys; ++k)
+        if (off[k + 1] <= off[k]) throw F4Error{F4_E_ARG, check_message(CHK_EMPTY)};
     const u64 nt = off[G->npolys];
+    if (nt >= (1ull << 32)) throw F4Error{F4_E_RANGE, "basis has 2^32 or more terms"};
+    if (!G->on_device) {
+        const u32 bad = check_polys_host(G->n, p, G->npolys, G->mon, G->coeff, off.data(), monic);
+        if (bad) throw F4Error{F4_E_ARG, check_message(bad)};
+    }
     devg_reserve(c, D, nt, G->npolys);
     if (G->on_device) {
         F4_HIP_TRY(hipMemcpyAsync(D.mon.ptr, G->mon, nt * 8, hipMemcpyDeviceToDevice, c.stream));
@@ -339,8 +442,16 @@ static void load_polys(Ctx& c, const f4_polys* G, DevG& D) {
     upload(c, D.off.ptr, off.data(), off.size() * 8);
     D.npolys = G->npolys;
     D.nterms = nt;
-    for (u32 k = 0; k < G->npolys; ++k)
-        if (off[k + 1] <= off[k]) throw F4Error{F4_E_ARG, "zero polynomial in basis"};
+    if (G->on_device && G->npolys) {
+        DBuf<u32> flag(&c.pool, 1);
+        fill_u32(flag.ptr, 1, 0, c.stream);
+        hipLaunchKernelGGL(k_check_polys, dim3(gridn((u64)G->npolys * F4_WAVE, 256, 1024)), dim3(256), 0, c.stream,
+                           D.mon.ptr, D.coeff.ptr, D.off.ptr, G->npolys, G->n, p, monic ? 1 : 0, flag.ptr);
+        F4_LAUNCH_CHECK();
+        u32 bad = 0;
+        readback(c, &bad, flag.ptr, 4);
+        if (bad) throw F4Error{F4_E_ARG, check_message(bad)};
+    }
     if (G->npolys) {
         hipLaunchKernelGGL(k_basis_meta, dim3(gridn(G->npolys, 256, 1024)), dim3(256), 0, c.stream, D.mon.ptr,
                            D.off.ptr, 0u, G->npolys, D.lm.ptr, D.len.ptr);
@@ -844,6 +955,13 @@ int f4_create(f4_ctx** out, int device, const f4_opts* opts) {
         X->c.tune.force_digit = opts ? opts->radix_bits : 0;
         if (X->c.tune.force_rr > 4 || X->c.tune.force_digit > 8)
             throw F4Error{F4_E_ARG, "trsm_rows must be at most 4 and radix_bits at most 8"};
+        if (opts && (!opts->alloc) != (!opts->free)) throw F4Error{F4_E_ARG, "alloc and free must be set together"};
+        X->c.pool.stream = &X->c.stream;
+        if (opts && opts->alloc) {
+            X->c.pool.ualloc = opts->alloc;
+            X->c.pool.ufree = opts->free;
+            X->c.pool.uuser = opts->alloc_user;
+        }
         F4_HIP_TRY(hipStreamCreateWithFlags(&X->c.own_stream, hipStreamNonBlocking));
         X->c.stream = X->c.own_stream;
         F4_HIP_TRY(hipEventCreateWithFlags(&X->c.staging_done, hipEventDisableTiming));
@@ -876,6 +994,8 @@ int f4_destroy(f4_ctx* X) {
     for (hipEvent_t e : X->c.events) (void)hipEventDestroy(e);
     if (X->c.staging_done) (void)hipEventDestroy(X->c.staging_done);
     if (X->c.pinned) (void)hipHostFree(X->c.pinned);
+    X->c.pool.trim();
+    X->c.pool.stream = nullptr;
     if (X->c.own_stream) (void)hipStreamDestroy(X->c.own_stream);
     delete X->c.cpu;
     delete X;
@@ -977,6 +1097,65 @@ int f4_pack(uint32_t n, const uint32_t* exps, uint64_t* out) {
     return F4_OK;
 }
 
+int f4_check_polys(uint32_t p, const f4_polys* G, int monic, uint32_t* bits) {
+    if (bits) *bits = 0;
+    if (!G || G->on_device || !G->offset || G->n == 0 || G->n > 14 || !is_odd_prime(p) || p >= (1u << 31))
+        return F4_E_ARG;
+    if (G->npolys && G->offset[G->npolys] && (!G->mon || !G->coeff)) return F4_E_ARG;
+    if (G->offset[0] != 0) return F4_E_ARG;
+    const u32 bad = check_polys_host(G->n, p, G->npolys, G->mon, G->coeff, G->offset, monic != 0);
+    if (bits) *bits = bad;
+    return bad ? F4_E_ARG : F4_OK;
+}
+
+int f4_normalize_polys(uint32_t p, const f4_polys* in, int monic, uint64_t* mon_out, uint32_t* coeff_out,
+                       uint64_t* off_out) {
+    if (!in || in->on_device || !in->offset || !off_out || in->n == 0 || in->n > 14 || !is_odd_prime(p) ||
+        p >= (1u << 31))
+        return F4_E_ARG;
+    const u32 n = in->n, w = lane_bits(n);
+    const u64 lanes = (1ull << (n * w)) - 1;
+    const u64 nt = in->offset[in->npolys];
+    if (nt && (!in->mon || !in->coeff || !mon_out || !coeff_out)) return F4_E_ARG;
+    try {
+        std::vector<std::pair<u64, u32>> f;
+        u64 o = 0;
+        off_out[0] = 0;
+        for (u32 k = 0; k < in->npolys; ++k) {
+            if (in->offset[k + 1] < in->offset[k]) return F4_E_ARG;
+            f.clear();
+            for (u64 e = in->offset[k]; e < in->offset[k + 1]; ++e) {
+                if (check_term(in->mon[e], 1, n, w, lanes, p) & CHK_WORD) return F4_E_ARG;
+                f.push_back({in->mon[e] ^ lanes, (u32)(in->coeff[e] % p)});  // order key
+            }
+            std::sort(f.begin(), f.end(), [](const std::pair<u64, u32>& a, const std::pair<u64, u32>& b) {
+                return a.first > b.first;
+            });
+            const u64 o0 = o;
+            for (size_t i = 0; i < f.size();) {
+                u64 sum = 0;
+                size_t j = i;
+                for (; j < f.size() && f[j].first == f[i].first; ++j) sum += f[j].second;
+                const u32 cf = (u32)(sum % p);
+                if (cf) {
+                    mon_out[o] = f[i].first ^ lanes;
+                    coeff_out[o] = cf;
+                    ++o;
+                }
+                i = j;
+            }
+            if (monic && o > o0 && coeff_out[o0] != 1) {
+                const u64 inv = powmod_host(coeff_out[o0], p - 2, p);
+                for (u64 e = o0; e < o; ++e) coeff_out[e] = (u32)(coeff_out[e] * inv % p);
+            }
+            off_out[k + 1] = o;
+        }
+    } catch (const std::bad_alloc&) {
+        return F4_E_NOMEM;
+    }
+    return F4_OK;
+}
+
 int f4_unpack(uint32_t n, uint64_t word, uint32_t* exps) {
     const u32 w = lane_bits(n);
     if (!w || !exps) return F4_E_ARG;
@@ -994,7 +1173,7 @@ int f4_build_matrix(f4_ctx* X, uint32_t p, const f4_polys* G, const uint8_t* act
     set_stream(X, stream);
     Ctx& c = X->c;
     DevG D;
-    load_polys(c, G, D);
+    load_polys(c, p, G, D, true);
     std::vector<u64> lm(D.npolys);
     readback(c, lm.data(), D.lm.ptr, (u64)D.npolys * 8);
     MonoOps mo;
@@ -1022,6 +1201,7 @@ int f4_build_matrix(f4_ctx* X, uint32_t p, const f4_polys* G, const uint8_t* act
     M->owner = X;
     try {
         build_batch(c, std::vector<BuildArgs>{args_of(st, true)}, M->m);
+        M->m.built_p = p;
     } catch (...) {
         delete M;
         throw;
@@ -1039,7 +1219,7 @@ int f4_build_matrix_rows(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_rows
     set_stream(X, stream);
     Ctx& c = X->c;
     DevG D;
-    load_polys(c, G, D);
+    load_polys(c, p, G, D, false);
     std::vector<u64> lm(D.npolys);
     readback(c, lm.data(), D.lm.ptr, (u64)D.npolys * 8);
     const u32 w = lane_bits(D.n);
@@ -1064,6 +1244,7 @@ int f4_build_matrix_rows(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_rows
     M->owner = X;
     try {
         build_batch(c, std::vector<BuildArgs>{args_of(st, false)}, M->m);
+        M->m.built_p = p;
     } catch (...) {
         delete M;
         throw;
@@ -1232,7 +1413,21 @@ int f4_reduce(f4_ctx* X, uint32_t p, const f4_matrix* A, f4_reduced** out, void*
     F4_API_BEGIN(X)
     if (!A || !out || !is_odd_prime(p) || p >= (1u << 31)) throw F4Error{F4_E_ARG, "bad argument"};
     *out = nullptr;
+    if (A->owner != X || X->matrices.count(const_cast<f4_matrix*>(A)) == 0)
+        throw F4Error{F4_E_STATE, "unknown matrix handle"};
     set_stream(X, stream);
+    if (A->m.built_p != p && A->m.nnz) {
+        // values not known to be residues mod p (a caller CSR, or a matrix
+        // built for another prime): every stored value must lie in [1, p)
+        DBuf<u32> flag(&X->c.pool, 1);
+        fill_u32(flag.ptr, 1, 0, X->c.stream);
+        hipLaunchKernelGGL(k_check_vals, dim3(gridn(A->m.nnz, 256, 1024)), dim3(256), 0, X->c.stream, A->m.val.ptr,
+                           A->m.nnz, p, flag.ptr);
+        F4_LAUNCH_CHECK();
+        u32 bad = 0;
+        readback(X->c, &bad, flag.ptr, 4);
+        if (bad) throw F4Error{F4_E_ARG, "a matrix value is not a nonzero residue mod p"};
+    }
     f4_reduced* R = new f4_reduced();
     R->owner = X;
     try {

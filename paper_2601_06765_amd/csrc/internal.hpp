@@ -16,6 +16,12 @@ struct Pool {
     std::multimap<size_t, void*> free_;
     std::unordered_map<void*, size_t> size_;
     size_t live_bytes = 0, cached_bytes = 0, peak_bytes = 0;
+    // caller allocator (f4_opts.alloc / .free): used instead of hipMalloc /
+    // hipFree when set; `stream` points at the context's current stream
+    void* (*ualloc)(void* user, size_t bytes, void* stream) = nullptr;
+    void (*ufree)(void* user, void* ptr, void* stream) = nullptr;
+    void* uuser = nullptr;
+    hipStream_t* stream = nullptr;
 
     static size_t round_size(size_t b) {
         if (b < 256) b = 256;
@@ -23,6 +29,21 @@ struct Pool {
         while (c < b) c <<= 1;
         if (c > (64u << 20)) c = (b + (4u << 20) - 1) & ~size_t((4u << 20) - 1);  // 4 MiB steps above 64 MiB
         return c;
+    }
+    void* raw_alloc(size_t want) {
+        if (ualloc) return ualloc(uuser, want, stream ? (void*)*stream : nullptr);
+        void* p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void raw_free(void* p) {
+        if (ufree)
+            ufree(uuser, p, stream ? (void*)*stream : nullptr);
+        else
+            (void)hipFree(p);
     }
     void* alloc(size_t bytes) {
         size_t want = round_size(bytes);
@@ -34,16 +55,11 @@ struct Pool {
             free_.erase(it);
             return p;
         }
-        void* p = nullptr;
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
+        void* p = raw_alloc(want);
+        if (!p) {
             trim();
-            e = hipMalloc(&p, want);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                throw F4Error{3, "device allocation of " + std::to_string(want) + " bytes failed"};
-            }
+            p = raw_alloc(want);
+            if (!p) throw F4Error{3, "device allocation of " + std::to_string(want) + " bytes failed"};
         }
         size_[p] = want;
         live_bytes += want;
@@ -58,16 +74,20 @@ struct Pool {
         cached_bytes += it->second;
         free_.insert({it->second, p});
     }
+    // hand the cached blocks back (work enqueued earlier may still read them:
+    // wait for the stream first)
     void trim() {
+        if (free_.empty()) return;
+        if (stream && *stream) (void)hipStreamSynchronize(*stream);
         for (auto& kv : free_) {
-            (void)hipFree(kv.second);
+            raw_free(kv.second);
             size_.erase(kv.second);
         }
         free_.clear();
         cached_bytes = 0;
     }
     ~Pool() {
-        for (auto& kv : size_) (void)hipFree(kv.first);
+        for (auto& kv : size_) raw_free(kv.first);
     }
 };
 
@@ -121,6 +141,10 @@ void fill_u64(u64* p, u64 n, u64 v, hipStream_t s);
 // Exclusive scan of n u32 values into out (may alias in); out[n] = total.
 // out must have room for n + 1 values.
 void exclusive_scan_u32(const u32* in, u32* out, u64 n, Pool& pool, hipStream_t s);
+// The same with a caller workspace of exclusive_scan_ws_words(n) words (none
+// for short inputs).
+u64 exclusive_scan_ws_words(u64 n);
+void exclusive_scan_u32_ws(const u32* in, u32* out, u64 n, u32* ws, hipStream_t s);
 // Schedule of an LSD radix sort: bits per digit pass (1..8) and keys per
 // thread in a tile of the multi-workgroup passes (sorts of at most
 // SORT_SMALL_MAX keys run in one workgroup and use the digit width only).
@@ -209,6 +233,11 @@ void spmm_run(Ctx& c, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, c
 // CSR of the transpose (the CSC of A): column pointers, row indices, values.
 void csr_transpose(Ctx& c, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx, const u32* val,
                    DBuf<u32>& tptr, DBuf<u32>& tidx, DBuf<u32>& tval);
+// The same into caller memory: tptr (ncols + 1), tidx and tval (nnz), and a
+// workspace of csr_transpose_ws_words(ncols) words; allocates nothing.
+u64 csr_transpose_ws_words(u32 ncols);
+void csr_transpose_into(hipStream_t s, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx,
+                        const u32* val, u32* tptr, u32* tidx, u32* tval, u32* ws);
 
 // Modular inner-loop microbenchmark (micro.hip): uploads the chains' start
 // values, times one launch of `iters` updates per chain with HIP events and
@@ -231,6 +260,10 @@ void readback(Ctx& c, void* dst, const void* src, size_t bytes);
 hipEvent_t stage_event(Ctx& c);
 // Whether the context records timings (the timing option).
 bool timing_on(const Ctx& c);
+// Per-launch events and product counters of the elimination kernels (the
+// kernel-timing option); nullptr / false when it is off.
+hipEvent_t kernel_event(Ctx& c);
+bool kernel_timing_on(const Ctx& c);
 float event_ms(hipEvent_t a, hipEvent_t b);
 
 // Binomial table C(x, y), x <= n+D+1, y <= min(n, 15), on the device.
@@ -265,6 +298,7 @@ struct SysPart {
 
 struct Matrix {
     u32 S = 0, R = 0;
+    u32 built_p = 0;  // prime the values were checked against (0: a caller CSR, not checked)
     u64 nnz = 0;
     std::vector<SysPart> sys;
     DBuf<u32> row_ptr, col_ind, val, row_k, row_sys;  // row_ptr holds batch-global offsets

@@ -108,7 +108,9 @@ static void spmm_launch(Ctx& c, const Fp& f, u32 nrows, u32 b, const u32* ptr, c
 void spmm_run(Ctx& c, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X, u32* Y) {
     if (nrows == 0) return;
     const Fp f = make_fp(p);
-    if (b % 2 == 0) {  // two words per lane
+    // two words per lane: an even b, and X and Y 8-byte aligned (caller
+    // blocks need not be; then one word per lane)
+    if (b % 2 == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 7) == 0) {
         if (b <= 2)
             spmm_launch<1, 8, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
         else if (b <= 4)
@@ -125,6 +127,8 @@ void spmm_run(Ctx& c, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, c
     }
     if (b <= 1)
         spmm_launch<1, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
+    else if (b <= 2)
+        spmm_launch<2, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 4)
         spmm_launch<4, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 8)
@@ -157,22 +161,30 @@ __global__ void k_col_scatter(const u32* __restrict__ ptr, u32 nrows, const u32*
     }
 }
 
+u64 csr_transpose_ws_words(u32 ncols) { return (u64)ncols + 1 + exclusive_scan_ws_words(ncols); }
+
+void csr_transpose_into(hipStream_t s, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx,
+                        const u32* val, u32* tptr, u32* tidx, u32* tval, u32* ws) {
+    u32* cnt = ws;  // ncols + 1 counters, then the scan's workspace
+    fill_u32(cnt, (u64)ncols + 1, 0, s);
+    if (nnz) {
+        hipLaunchKernelGGL(k_col_count, dim3(ceil_div(nnz, 256)), dim3(256), 0, s, idx, nnz, cnt);
+        F4_LAUNCH_CHECK();
+    }
+    exclusive_scan_u32_ws(cnt, tptr, ncols, ws + (u64)ncols + 1, s);
+    if (nnz && nrows) {
+        F4_HIP_TRY(hipMemcpyAsync(cnt, tptr, (u64)ncols * 4, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_col_scatter, dim3(ceil_div(nrows, 256)), dim3(256), 0, s, ptr, nrows, idx, val, cnt,
+                           tidx, tval);
+        F4_LAUNCH_CHECK();
+    }
+}
+
 void csr_transpose(Ctx& c, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx, const u32* val,
                    DBuf<u32>& tptr, DBuf<u32>& tidx, DBuf<u32>& tval) {
     tptr.reset(&c.pool, (u64)ncols + 1);
     tidx.reset(&c.pool, std::max<u64>(nnz, 1));
     tval.reset(&c.pool, std::max<u64>(nnz, 1));
-    DBuf<u32> cnt(&c.pool, (u64)ncols + 1);
-    fill_u32(cnt.ptr, (u64)ncols + 1, 0, c.stream);
-    if (nnz) {
-        hipLaunchKernelGGL(k_col_count, dim3(ceil_div(nnz, 256)), dim3(256), 0, c.stream, idx, nnz, cnt.ptr);
-        F4_LAUNCH_CHECK();
-    }
-    exclusive_scan_u32(cnt.ptr, tptr.ptr, ncols, c.pool, c.stream);
-    if (nnz && nrows) {
-        F4_HIP_TRY(hipMemcpyAsync(cnt.ptr, tptr.ptr, (u64)ncols * 4, hipMemcpyDeviceToDevice, c.stream));
-        hipLaunchKernelGGL(k_col_scatter, dim3(ceil_div(nrows, 256)), dim3(256), 0, c.stream, ptr, nrows, idx, val,
-                           cnt.ptr, tidx.ptr, tval.ptr);
-        F4_LAUNCH_CHECK();
-    }
+    DBuf<u32> ws(&c.pool, csr_transpose_ws_words(ncols));
+    csr_transpose_into(c.stream, nrows, ncols, nnz, ptr, idx, val, tptr.ptr, tidx.ptr, tval.ptr, ws.ptr);
 }

@@ -97,20 +97,28 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const u32* in, u32*
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = offs[gridDim.x];
 }
 
-void exclusive_scan_u32(const u32* in, u32* out, u64 n, Pool& pool, hipStream_t s) {
+u64 exclusive_scan_ws_words(u64 n) { return n <= (u64)SCAN_TILE * 16 ? 0 : (u64)ceil_div(n, SCAN_TILE) + 1; }
+
+void exclusive_scan_u32_ws(const u32* in, u32* out, u64 n, u32* ws, hipStream_t s) {
     if (n <= (u64)SCAN_TILE * 16) {
         hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN_THREADS), 0, s, in, out, n);
         F4_LAUNCH_CHECK();
         return;
     }
     u32 tiles = ceil_div(n, SCAN_TILE);
-    DBuf<u32> sums(&pool, tiles + 1);
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(SCAN_THREADS), 0, s, in, n, sums.ptr);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(SCAN_THREADS), 0, s, in, n, ws);
     F4_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN_THREADS), 0, s, sums.ptr, sums.ptr, (u64)tiles);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN_THREADS), 0, s, ws, ws, (u64)tiles);
     F4_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(SCAN_THREADS), 0, s, in, out, n, sums.ptr);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(SCAN_THREADS), 0, s, in, out, n, ws);
     F4_LAUNCH_CHECK();
+}
+
+void exclusive_scan_u32(const u32* in, u32* out, u64 n, Pool& pool, hipStream_t s) {
+    const u64 w = exclusive_scan_ws_words(n);
+    DBuf<u32> sums;
+    if (w) sums.reset(&pool, w);
+    exclusive_scan_u32_ws(in, out, n, sums.ptr, s);
 }
 
 // ------------------------------------------------------------- radix sort

@@ -1360,9 +1360,9 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
                 rr = tune_pick(c, tune_key(TUNE_TRSM, small ? 1 : 0, tune_lg(rows), tune_lg(nmax)), cands,
                                [](u32) {}, [&](u32 v) { launch(v, nullptr); });
             }
-            hipEvent_t ka = kt ? stage_event(c) : nullptr;
+            hipEvent_t ka = kt ? kernel_event(c) : nullptr;
             launch(rr, ops);
-            if (ka) kt->ev_trsm.push_back({ka, stage_event(c)});
+            if (ka) kt->ev_trsm.push_back({ka, kernel_event(c)});
             continue;
         }
         // accumulators in global memory (one row per tile), one system and a
@@ -1431,7 +1431,7 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
     }
     DBuf<u32> Dp(&c.pool, std::max<u64>(Dtot, 1)), lead(&c.pool, std::max<u32>(X.Ltot, 1));
     DBuf<u32> status(&c.pool, std::max<u32>(X.Ltot, 1));  // cleared by the solve
-    if (timing_on(c)) {
+    if (kernel_timing_on(c)) {
         out.ops.reset(&c.pool, 2);
         fill_u64(out.ops.ptr, 2, 0, s);
     }
@@ -1485,7 +1485,7 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
         bool first = true;
         for (;;) {
             for (u32 k = 0; k < batch; ++k) {
-                hipEvent_t ka = stage_event(c);
+                hipEvent_t ka = kernel_event(c);
                 unsigned long long* bops = out.ops.ptr ? (unsigned long long*)out.ops.ptr + 1 : nullptr;
                 const size_t blds = cnt_lds ? (size_t)maxc * 4 : 0;
                 if (any_small)
@@ -1495,7 +1495,7 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
                     hipLaunchKernelGGL(k_ech_block<false>, dim3(1, S), dim3(1024), blds, s, X.dsegs.ptr, lead.ptr,
                                        status.ptr, Dp.ptr, ccnt.ptr, cnt_lds, rounds, prlead.ptr, ndone, bops);
                 F4_LAUNCH_CHECK();
-                if (ka) out.ev_block.push_back({ka, stage_event(c)});
+                if (ka) out.ev_block.push_back({ka, kernel_event(c)});
                 // a workgroup per row while rows are few (each row spread over
                 // 256 threads and the rows over the CUs), a wave per row for
                 // a few thousand rows and more

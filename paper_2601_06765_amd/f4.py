@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libf4.so")
 
 F4_OK, F4_E_ARG, F4_E_RANGE, F4_E_NOMEM, F4_E_BUSY, F4_E_DEVICE, F4_E_STATE = range(7)
-F4_OPT_TIMING, F4_OPT_DICT_RANK, F4_OPT_DICT_RADIX, F4_OPT_AUTOTUNE = 1, 2, 4, 8
+F4_OPT_TIMING, F4_OPT_DICT_RANK, F4_OPT_DICT_RADIX, F4_OPT_AUTOTUNE, F4_OPT_KERNEL_TIMING = 1, 2, 4, 8, 16
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libf4.so is not built: run `python -m paper_2601_06765_amd.build` "
@@ -26,8 +26,13 @@ c_u32, c_u64, c_int, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctyp
 P = ctypes.POINTER
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_vp, c_vp, ctypes.c_size_t, c_vp)
+FREE_FN = ctypes.CFUNCTYPE(None, c_vp, c_vp, c_vp)
+
+
 class Opts(ctypes.Structure):
-    _fields_ = [("flags", c_u32), ("stop_deg", c_u32), ("trsm_rows", c_u32), ("radix_bits", c_u32)]
+    _fields_ = [("flags", c_u32), ("stop_deg", c_u32), ("trsm_rows", c_u32), ("radix_bits", c_u32),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", c_vp)]
 
 
 class Polys(ctypes.Structure):
@@ -82,6 +87,8 @@ _sig("f4_tune_import", c_int, [c_vp, ctypes.c_char_p])
 _sig("f4_lane_bits", c_u32, [c_u32])
 _sig("f4_pack", c_int, [c_u32, P(c_u32), P(c_u64)])
 _sig("f4_unpack", c_int, [c_u32, c_u64, P(c_u32)])
+_sig("f4_check_polys", c_int, [c_u32, P(Polys), c_int, P(c_u32)])
+_sig("f4_normalize_polys", c_int, [c_u32, P(Polys), c_int, P(c_u64), P(c_u32), P(c_u64)])
 _sig("f4_grevlex_rank", c_int, [c_u32, c_u32, c_u64, P(c_u32)])
 _sig("f4_grevlex_unrank", c_int, [c_u32, c_u32, c_u32, P(c_u64)])
 _sig("f4_build_matrix", c_int, [c_vp, c_u32, P(Polys), P(ctypes.c_uint8), P(Pair), c_u32, P(c_vp), c_vp])
@@ -181,30 +188,63 @@ def pack_many(n, exps):
     return words | (e.sum(axis=1).astype(np.uint64) << np.uint64(56))
 
 
-def polys_to_arrays(n, polys, sort=False):
-    """List of polys [(exps, coeff), ...] -> (mon u64, coeff u32, offset u64) host arrays.
-    With sort=True the terms of each polynomial are ordered by the library's
-    order key (largest monomial first), as f4_build_matrix requires."""
-    w = lane_bits(n)
-    lanes = (1 << (n * w)) - 1
+def polys_to_arrays(n, polys):
+    """List of polys [(exps, coeff), ...] -> (mon u64, coeff u32, offset u64)
+    host arrays, terms in the given order (no sorting: see normalize)."""
     terms = [t for f in polys for t in f]
     offs = np.zeros(len(polys) + 1, dtype=np.uint64)
     offs[1:] = np.cumsum([len(f) for f in polys])
     mons = pack_many(n, [e for e, _ in terms]) if terms else np.zeros(0, dtype=np.uint64)
-    coeffs = np.array([c for _, c in terms], dtype=np.uint32)
-    if sort:
-        for a in range(len(polys)):
-            lo, hi = int(offs[a]), int(offs[a + 1])
-            keys = mons[lo:hi] ^ np.uint64(lanes)
-            order = sorted(range(hi - lo), key=lambda k: int(keys[k]), reverse=True)
-            mons[lo:hi] = mons[lo:hi][order]
-            coeffs[lo:hi] = coeffs[lo:hi][order]
+    cs = [c for _, c in terms]
+    if cs and (min(cs) < 0 or max(cs) >= 1 << 32):
+        raise F4Error(F4_E_RANGE, "a coefficient does not fit a 32-bit word")
+    coeffs = np.array(cs, dtype=np.uint64).astype(np.uint32) if terms else np.zeros(0, dtype=np.uint32)
     return mons, coeffs, offs
+
+
+def check_arrays(p, n, mon, coeff, off, monic=False):
+    """f4_check_polys on host arrays: (status, failed-rule bits)."""
+    arg = _PolysArg(n, mon, coeff, off)
+    bits = c_u32()
+    rc = _lib.f4_check_polys(p, ctypes.byref(arg.s), 1 if monic else 0, ctypes.byref(bits))
+    return rc, bits.value
+
+
+def normalize_arrays(p, n, mon, coeff, off, monic=False):
+    """f4_normalize_polys on host arrays: terms sorted by decreasing grevlex,
+    repeats merged, coefficients reduced mod p, zero terms dropped (and each
+    polynomial made monic with monic=True)."""
+    mon = np.ascontiguousarray(mon, dtype=np.uint64)
+    coeff = np.ascontiguousarray(coeff, dtype=np.uint32)
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    arg = _PolysArg(n, mon, coeff, off)
+    mo = np.zeros(max(1, len(mon)), dtype=np.uint64)
+    co = np.zeros(max(1, len(mon)), dtype=np.uint32)
+    oo = np.zeros(len(off), dtype=np.uint64)
+    rc = _lib.f4_normalize_polys(p, ctypes.byref(arg.s), 1 if monic else 0, mo.ctypes.data_as(P(c_u64)),
+                                 co.ctypes.data_as(P(c_u32)), oo.ctypes.data_as(P(c_u64)))
+    if rc:
+        raise F4Error(rc, "f4_normalize_polys")
+    return mo[:int(oo[-1])], co[:int(oo[-1])], oo
+
+
+def normalize(p, n, polys, monic=False):
+    """Polynomials [(exps, coeff), ...] in the library's input form (see
+    normalize_arrays); polynomials that cancel to zero are dropped."""
+    mo, co, oo = normalize_arrays(p, n, *polys_to_arrays(n, polys), monic=monic)
+    out = []
+    for a in range(len(oo) - 1):
+        f = [(unpack(n, int(mo[q])), int(co[q])) for q in range(int(oo[a]), int(oo[a + 1]))]
+        if f:
+            out.append(f)
+    return out
 
 
 def _ptr(a):
     if a is None:
         return None
+    if isinstance(a, DeviceArray):
+        return c_vp(a.ptr)
     if hasattr(a, "data_ptr"):  # torch tensor (device or host)
         return c_vp(a.data_ptr())
     return a.ctypes.data_as(c_vp)
@@ -213,16 +253,21 @@ def _ptr(a):
 class _PolysArg:
     """Keeps the arrays alive while the struct is in use."""
 
-    def __init__(self, n, mon, coeff, off, on_device=False):
+    def __init__(self, n, mon, coeff, off, on_device=False, npolys=None):
         self.keep = (mon, coeff, off)
-        self.s = Polys(n, len(off) - 1, _ptr(mon), _ptr(coeff), _ptr(off), 1 if on_device else 0)
+        k = len(off) - 1 if npolys is None else npolys
+        self.s = Polys(n, k, _ptr(mon), _ptr(coeff), _ptr(off), 1 if on_device else 0)
 
 
 # --------------------------------------------------------------- context
 class Context:
     def __init__(self, device=0, timing=False, dict_path=None, stop_deg=0, autotune=False, trsm_rows=0,
-                 radix_bits=0):
+                 radix_bits=0, kernel_timing=False, alloc=None, free=None):
+        """alloc(bytes, stream) -> device pointer or 0, free(ptr, stream):
+        optional device allocator of the context (f4_opts.alloc / .free)."""
         flags = F4_OPT_TIMING if timing else 0
+        if kernel_timing:
+            flags |= F4_OPT_TIMING | F4_OPT_KERNEL_TIMING
         if dict_path == "rank":
             flags |= F4_OPT_DICT_RANK
         elif dict_path == "radix":
@@ -230,8 +275,13 @@ class Context:
         if autotune:
             flags |= F4_OPT_AUTOTUNE
         self._h = c_vp()
-        rc = _lib.f4_create(ctypes.byref(self._h), device,
-                            ctypes.byref(Opts(flags, stop_deg, trsm_rows, radix_bits)))
+        opts = Opts(flags, stop_deg, trsm_rows, radix_bits)
+        if alloc is not None:
+            # the callbacks must outlive the context: keep them on it
+            self._cb = (ALLOC_FN(lambda user, nbytes, stream: alloc(nbytes, stream) or None),
+                        FREE_FN(lambda user, ptr, stream: free(ptr, stream)))
+            opts.alloc, opts.free = self._cb
+        rc = _lib.f4_create(ctypes.byref(self._h), device, ctypes.byref(opts))
         if rc:
             raise F4Error(rc, "f4_create failed")
 
@@ -355,13 +405,16 @@ class Context:
 
     # -- one step
     def build_matrix(self, p, n, G, active, sel, stream=None, device_arrays=None):
-        """Symbolic preprocessing for the selected pairs.  G: list of polys
-        (monic, any term order) or, with device_arrays=(mon, coeff, off) torch
-        tensors, a device-resident basis."""
+        """Symbolic preprocessing for the selected pairs.  G: list of polys in
+        the library's input form (monic, terms by decreasing grevlex; see
+        normalize) or, with device_arrays=(mon, coeff, off, npolys) (three
+        DeviceArray blocks holding the u64 / u32 / u64 arrays), a
+        device-resident basis."""
         if device_arrays is not None:
-            arg = _PolysArg(n, *device_arrays, on_device=True)
+            mon, coeff, off, k = device_arrays
+            arg = _PolysArg(n, mon, coeff, off, on_device=True, npolys=k)
         else:
-            arg = _PolysArg(n, *polys_to_arrays(n, G, sort=True))
+            arg = _PolysArg(n, *polys_to_arrays(n, G))
         act = np.array([1 if a else 0 for a in active], dtype=np.uint8)
         pairs = (Pair * len(sel))(*[Pair(i, j) for i, j in sel])
         h = c_vp()
@@ -371,7 +424,9 @@ class Context:
         return Matrix(self, h, n)
 
     def build_matrix_rows(self, p, n, G, rows, stream=None):
-        arg = _PolysArg(n, *polys_to_arrays(n, G, sort=True))
+        """Matrix of an explicit row list [(t exps, k), ...]; G in the
+        library's input form (see normalize)."""
+        arg = _PolysArg(n, *polys_to_arrays(n, G))
         rs = (RowSpec * len(rows))(*[RowSpec(pack(n, t), k, 0) for t, k in rows])
         h = c_vp()
         self._check(_lib.f4_build_matrix_rows(self._h, p, ctypes.byref(arg.s), rs, len(rows), ctypes.byref(h),
@@ -381,7 +436,7 @@ class Context:
     def build_matrix_rows_packed(self, p, n, G, t_words, ks, stream=None):
         """build_matrix_rows with the shifts given as arrays: t_words (P words,
         e.g. from pack_many) and ks (basis indices), marshalled in bulk."""
-        arg = _PolysArg(n, *polys_to_arrays(n, G, sort=True))
+        arg = _PolysArg(n, *polys_to_arrays(n, G))
         t_words = np.asarray(t_words, dtype=np.uint64)
         rs = np.zeros(len(t_words), dtype=np.dtype([("t", "<u8"), ("k", "<u4"), ("pad", "<u4")]))
         rs["t"] = t_words
@@ -461,7 +516,22 @@ class DeviceArray:
     def to_host(self):
         return self.ctx.download(self.ptr, self.size, np.uint32).reshape(self.shape)
 
+    def sub(self, offset, shape):
+        """A view of `shape` words starting `offset` words in (no copy; the
+        block must outlive it)."""
+        v = DeviceArray.__new__(DeviceArray)
+        v.ctx, v.owner = self.ctx, self
+        v.shape = tuple(int(x) for x in (shape if isinstance(shape, (tuple, list)) else (shape,)))
+        v.size = int(np.prod(v.shape, dtype=np.int64)) if v.shape else 1
+        if offset < 0 or offset + v.size > self.size:
+            raise ValueError("view outside the block")
+        v.ptr = self.ptr + 4 * offset
+        return v
+
     def free(self):
+        if getattr(self, "owner", None) is not None:  # a view frees nothing
+            self.ptr = None
+            return
         if self.ptr and self.ctx._h:
             _lib.f4_device_free(self.ctx._h, c_vp(self.ptr))
         self.ptr = None

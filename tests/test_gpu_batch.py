@@ -100,3 +100,25 @@ def test_batch_workload_sample_radix_dictionary(f4):
             assert shapes_of(steps) == oracle_shapes(run)
     finally:
         c.close()
+
+
+def test_batch_workload_sample_and_all_crt_primes(f4, ctx):
+    """One batch holding two systems of each n = 6..9 of the batch workload
+    (seeds 4*2^32 + j) and the workload's n = 9 system under all 8 CRT primes:
+    every basis and every step's shapes equal the oracle's."""
+    sample, seen = [], {}
+    for j, (n, p, polys) in enumerate(synth.batch_systems(256)):
+        if seen.get(n, 0) < 2:
+            seen[n] = seen.get(n, 0) + 1
+            sample.append((j, p, n, polys))
+    assert sorted(seen) == [6, 7, 8, 9]
+    n9, polys9 = synth.crt_system()
+    systems = [(p, n, polys) for _, p, n, polys in sample]
+    systems += [(q, n9, synth.reduce_coeffs(polys9, q)) for q in synth.CRT_PRIMES]
+    say("batch: workload sample", [j for j, _, _, _ in sample], "+ 8 CRT primes")
+    batch = ctx.groebner_batch(systems)
+    for (p, n, polys), (B, steps) in zip(systems, batch):
+        say("oracle n=%d p=%d" % (n, p))
+        run = oracle.OracleRun(n, p, polys)
+        assert canon(B) == canon(run.basis())
+        assert shapes_of(steps) == oracle_shapes(run)

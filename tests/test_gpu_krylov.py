@@ -46,7 +46,7 @@ def random_csr(r, N, seed, vmax, empty_every=7, maxlen=40):
 
 
 @pytest.mark.parametrize("p", [3, 65521, synth.P31])
-@pytest.mark.parametrize("b", [1, 2, 3, 5, 6, 8, 12, 13, 32, 64])
+@pytest.mark.parametrize("b", [1, 2, 3, 4, 5, 6, 8, 12, 13, 17, 32, 33, 63, 64])
 def test_spmm_random(env, p, b):
     f4, c = env
     r, N = 1037, 705
@@ -61,6 +61,28 @@ def test_spmm_random(env, p, b):
     YT = c.spmm(p, A, c.to_device(W), trans=True)
     assert np.array_equal(host(Y), o5.spmm(ptr, idx, val, N, X, p))
     assert np.array_equal(host(YT), o5.spmm(ptr, idx, val, N, W, p, trans=True))
+    A.free()
+
+
+@pytest.mark.parametrize("b", [2, 6, 12])
+def test_spmm_unaligned_blocks(env, b):
+    """Even b with X or Y starting 4 bytes past an 8-byte boundary (one word
+    per lane then): the same results."""
+    f4, c = env
+    p = synth.P31
+    r, N = 301, 257
+    ptr, idx, val = random_csr(r, N, 7 + b, p)
+    A = c.matrix_from_csr(r, N, ptr, idx, val)
+    rng = np.random.default_rng(50 + b)
+    X = rng.integers(0, p, size=(N, b), dtype=np.int64)
+    want = o5.spmm(ptr, idx, val, N, X, p)
+    Xb = c.to_device(np.concatenate([[0], X.ravel()]))
+    Yb = c.device_array(r * b + 1)
+    say("spmm unaligned X and Y, b", b)
+    Y = c.spmm(p, A, Xb.sub(1, (N, b)), out=Yb.sub(1, (r, b)))
+    assert np.array_equal(host(Y), want)
+    Y2 = c.spmm(p, A, c.to_device(X), out=Yb.sub(1, (r, b)))
+    assert np.array_equal(host(Y2), want)
     A.free()
 
 
@@ -104,6 +126,7 @@ def test_spmm_macaulay_planted_root(env):
     f4, c = env
     n, p = 6, 65521
     polys, s = synth.planted_system(n, 7, p, 21)
+    polys = f4.normalize(p, n, polys)
     tw, ks = macaulay_rows(f4, n, 3, len(polys))
     say("spmm Macaulay planted n=6 shift degree 3, rows", len(tw))
     A = c.build_matrix_rows_packed(p, n, polys, tw, ks)
@@ -127,6 +150,7 @@ def test_spmm_full_size_macaulay_sampled(env):
     # sparse n=14 system over F_(2^31-1), b = 8
     f4, c = env
     n, p, polys = synth.config_system(3)
+    polys = f4.normalize(p, n, polys)
     tw, ks = macaulay_rows(f4, n, 8, len(polys))
     say("spmm full-size Macaulay n=14 shift degree 8, rows", len(tw))
     A = c.build_matrix_rows_packed(p, n, polys, tw, ks)

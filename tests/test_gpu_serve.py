@@ -92,3 +92,56 @@ def test_server_busy_and_unknown_ticket(f4):
         srv.close()
     finally:
         ctx.close()
+
+
+def test_server_mix_with_large_requests(f4):
+    """Requests of the serving workload with n = 9..12 under both primes (the
+    ones that dominate its GPU time), served four at a time next to small
+    ones: each result equals the system's run alone; the n = 9 requests of
+    both primes and an n = 10 request also equal the oracle's basis."""
+    ctx = f4.Context(0)
+    try:
+        stream = synth.serve_stream(duration=0.2)
+        picked, seen = [], {}
+        for j, (_, n, p, polys) in enumerate(stream):
+            key = (n, p)
+            if n >= 9 and seen.get(key, 0) < 1:
+                seen[key] = 1
+                picked.append((j, p, n, polys))
+            elif n <= 6 and seen.get(key, 0) < 2:
+                seen[key] = seen.get(key, 0) + 1
+                picked.append((j, p, n, polys))
+        assert {(n, p) for _, p, n, _ in picked if n >= 9} == {(n, p) for n in (9, 10, 11, 12)
+                                                                  for p in (synth.P16, synth.P31)}
+        srv = f4.Server(ctx, hbm_budget=64 << 30, max_slots=4)
+        say("serve", len(picked), "requests (n = 5..12, both primes), 4 slots")
+        pending = list(range(len(picked)))
+        tickets, results, steps = {}, {}, 0
+        while len(results) < len(picked):
+            while pending:
+                _, p, n, polys = picked[pending[0]]
+                t = srv.submit(p, n, polys)
+                if t is None:
+                    break
+                tickets[t] = pending.pop(0)
+            srv.step()
+            steps += 1
+            for t in list(tickets):
+                r = srv.poll(t)
+                if r is not None:
+                    results[tickets.pop(t)] = r
+            assert steps < 100000
+        srv.close()
+        for i, (j, p, n, polys) in enumerate(picked):
+            say("alone request", j, "n=%d p=%d" % (n, p))
+            B, st = results[i]
+            B1, st1 = ctx.groebner(p, n, polys)
+            assert canon(B) == canon(B1)
+            assert [(s["deg"], s["r"], s["N"], s["nnz"], s["npivot"], s["rank"]) for s in st] == \
+                   [(s["deg"], s["r"], s["N"], s["nnz"], s["npivot"], s["rank"]) for s in st1]
+        for i, (j, p, n, polys) in enumerate(picked):
+            if n == 9 or (n == 10 and p == synth.P16):
+                say("oracle request", j, "n=%d p=%d" % (n, p))
+                assert canon(results[i][0]) == canon(oracle.OracleRun(n, p, polys).basis())
+    finally:
+        ctx.close()

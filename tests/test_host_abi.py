@@ -7,6 +7,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 from oracle import buchberger as bb
@@ -100,10 +101,70 @@ def test_vectorised_packing_matches_the_library(f4, n):
         f4.pack_many(n, [[1 << w] + [0] * (n - 1)])
     assert e.value.code == f4.F4_E_RANGE
     polys = [[(tuple(int(v) for v in exps[i]), i + 1) for i in range(k, k + 5)] for k in (0, 5, 10)]
-    mon, coeff, off = f4.polys_to_arrays(n, polys, sort=True)
+    mon, coeff, off = f4.polys_to_arrays(n, polys)
     assert off.tolist() == [0, 5, 10, 15]
-    for a, f in enumerate(polys):
-        want = sorted(((f4.pack(n, e), c) for e, c in f), key=lambda t: t[0] ^ ((1 << (n * w)) - 1),
-                      reverse=True)
-        got_a = list(zip(mon[5 * a:5 * a + 5].tolist(), coeff[5 * a:5 * a + 5].tolist()))
-        assert got_a == [(int(m), int(c)) for m, c in want]
+    assert [int(x) for x in mon] == [f4.pack(n, e) for f in polys for e, _ in f]
+
+
+@pytest.mark.parametrize("n,p", [(3, 7), (6, 65521), (14, 2147483647)])
+def test_normalize_polys(f4, n, p):
+    """f4_normalize_polys against a plain normalisation with O2's grevlex key:
+    terms sorted largest first, repeated monomials merged mod p, zero terms
+    dropped, and with monic=True divided by the leading coefficient."""
+    import random
+    rnd = random.Random(n * 1000 + p % 997)
+    mons = [tuple(rnd.randrange(0, 3) for _ in range(n)) for _ in range(12)]
+    polys = [[(rnd.choice(mons), rnd.randrange(0, min(3 * p, 1 << 32))) for _ in range(rnd.randrange(1, 15))]
+             for _ in range(6)]
+    polys.append([(mons[0], 1), (mons[0], p - 1)])  # cancels to zero
+    for monic in (False, True):
+        got = f4.normalize(p, n, polys, monic=monic)
+        want = []
+        for f in polys:
+            acc = {}
+            for e, c in f:
+                acc[e] = (acc.get(e, 0) + c) % p
+            g = sorted(((e, c) for e, c in acc.items() if c), key=lambda t: bb.grevlex_key(t[0]), reverse=True)
+            if not g:
+                continue
+            if monic:
+                inv = pow(g[0][1], p - 2, p)
+                g = [(e, c * inv % p) for e, c in g]
+            want.append(g)
+        assert got == want
+
+
+def test_check_polys_rejects_malformed_input(f4):
+    """The input contract of the matrix builders (F4_E_ARG with the failed
+    rule): unsorted terms, repeated terms, a zero or too large coefficient, a
+    non-monic element when monic input is required, a word whose lanes do not
+    add up to its degree field, an empty polynomial."""
+    n, p = 4, 65521
+    good = f4.normalize(p, n, [[((1, 0, 0, 1), 5), ((0, 1, 0, 0), 3), ((0, 0, 0, 0), 2)],
+                               [((0, 2, 0, 0), 1), ((1, 0, 0, 0), 7)]], monic=True)
+    mon, coeff, off = f4.polys_to_arrays(n, good)
+    assert f4.check_arrays(p, n, mon, coeff, off, monic=True) == (f4.F4_OK, 0)
+
+    def bits(m, c, o, monic=False):
+        rc, b = f4.check_arrays(p, n, m, c, o, monic=monic)
+        assert rc == (f4.F4_E_ARG if b else f4.F4_OK)
+        return b
+
+    sw = mon.copy()
+    sw[[0, 1]] = sw[[1, 0]]
+    assert bits(sw, coeff, off) & 2  # unsorted
+    rep = mon.copy()
+    rep[1] = rep[0]
+    assert bits(rep, coeff, off) & 2  # repeated
+    for bad in (0, p, p + 5):
+        cf = coeff.copy()
+        cf[2] = bad
+        assert bits(mon, cf, off) & 4  # coefficient not in [1, p)
+    cf = coeff.copy()
+    cf[0] = 2
+    assert bits(mon, cf, off, monic=True) & 8 and bits(mon, cf, off) == 0  # non-monic
+    w = f4.lane_bits(n)
+    word = mon.copy()
+    word[0] = int(word[0]) + (1 << w)  # an exponent more than the degree field says
+    assert bits(word, coeff, off) & 1
+    assert bits(mon, coeff, np.array([0, 3, 3, 5], dtype=np.uint64)) & 16  # empty polynomial

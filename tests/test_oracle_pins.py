@@ -244,7 +244,10 @@ def test_step_objects_planted_and_kernel(n, p, seed):
         A, ids = check_step(n, p, rec)
         if len(A) <= 60:
             # Proposition: v^T A = 0  <=>  sum v_i t_i g_{k_i} = 0 as polynomials
-            for v in dense.left_kernel(A, len(rec["T"]), p)[:5]:
+            K = dense.left_kernel(A, len(rec["T"]), p)
+            # dimension of the left kernel: rows minus O1's rank (pivots + rho)
+            assert len(K) == len(A) - (len(rec["pivot_cols"]) + len(rec["rref_ptr"]) - 1)
+            for v in K[:5]:
                 acc = {}
                 for vi, (t, kk) in zip(v, ids):
                     if vi:
@@ -254,3 +257,28 @@ def test_step_objects_planted_and_kernel(n, p, seed):
                 assert all(c == 0 for c in acc.values())
         G0 = rec
     assert G0 is not None
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_left_kernel_by_brute_force(seed):
+    """O3's left kernel on tiny matrices over F_3 and F_5, against brute force:
+    the vectors returned satisfy v^T A = 0 (by direct products), there are
+    exactly r - rank(A) of them, and they span every solution (the span has
+    p^(r - rank) elements, the count of all v with v^T A = 0)."""
+    import random
+    rnd = random.Random(seed)
+    p = (3, 5)[seed % 2]
+    r, ncols = rnd.randrange(1, 5), rnd.randrange(1, 4)
+    A = [[rnd.randrange(p) if rnd.random() < 0.7 else 0 for _ in range(ncols)] for _ in range(r)]
+    if seed == 0:
+        A = [[1, 2, 0], [2, 4 % p, 0], [0, 0, 0]]  # repeated and zero rows
+        r, ncols = 3, 3
+    sols = [v for v in itertools.product(range(p), repeat=r)
+            if all(sum(v[i] * A[i][j] for i in range(r)) % p == 0 for j in range(ncols))]
+    K = dense.left_kernel(A, ncols, p)
+    for v in K:
+        assert all(sum(v[i] * A[i][j] for i in range(r)) % p == 0 for j in range(ncols))
+    span = {tuple(sum(c * v[i] for c, v in zip(cs, K)) % p for i in range(r))
+            for cs in itertools.product(range(p), repeat=len(K))}
+    assert span == set(sols)
+    assert len(sols) == p ** len(K)  # so the vectors are independent: dim = r - rank(A)
