@@ -30,6 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# derived modular-product bound: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer
+# issue, at least two instructions (a multiply and an add) per modular product
+MODMUL_PEAK = 256 * 4 * 16 * 2.4e9 / 2
 STEP_DEG = 5  # the timed step of the headline workload
 
 

@@ -167,7 +167,8 @@ class HipBudget:
 
 
 def test_nomem_through_allocator_callbacks(f4):
-    n, p, polys = synth.config_system(1)
+    # the n = 10 system: its largest step alone holds about 5 MB of CSR
+    n, p, polys = synth.config_system(2)
     want = oracle.OracleRun(n, p, polys).basis()
     hb = HipBudget(1 << 20)  # 1 MiB: far too little for the run
     c = f4.Context(0, alloc=hb.alloc, free=hb.free)
