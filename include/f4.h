@@ -269,6 +269,27 @@ int f4_spmm(f4_ctx* ctx, uint32_t p, f4_matrix* A, int trans, uint32_t b, const 
  * or a null ms_per_call. */
 int f4_spmm_timed(f4_ctx* ctx, uint32_t p, f4_matrix* A, int trans, uint32_t b, const uint32_t* X, uint32_t* Y,
                   uint32_t reps, double* ms_per_call);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): f4_spmm on
+ * caller CSR arrays, allocating nothing.  A is r x N with row_ptr (r + 1
+ * entries), col_ind and val (nnz entries, nnz = row_ptr[r] < 2^32), all
+ * device arrays owned by the caller; X, Y, b, trans and the results are as
+ * for f4_spmm (bit-identical to f4_spmm on a handle of the same CSR).
+ * trans = 1 builds the transpose in a scratch array of
+ * F4_NOALLOC_SCRATCH_BYTES that the library keeps on each GPU (set up by
+ * f4_create, held until the process ends): it needs
+ * 4 * (N + 1 rounded up to 64 + 2 nnz + workspace) bytes, about
+ * 8 nnz + 8 N, and larger products fail with F4_E_RANGE before any work is
+ * enqueued.  trans = 0 uses no scratch.  Every call on one GPU shares that
+ * GPU's scratch and the last call's contents stay in it: calls that overlap
+ * on one GPU (two streams, two contexts or two threads) race, so callers
+ * order them (one stream, or events).  Asynchronous on `stream` (NULL: the
+ * context's stream).  F4_E_ARG: as for f4_spmm, plus a null row_ptr, null
+ * col_ind / val with nnz > 0, nnz >= 2^32. */
+#define F4_NOALLOC_SCRATCH_BYTES (64u << 20)
+int f4_spmm_noalloc(f4_ctx* ctx, uint32_t p, uint32_t r, uint32_t N, uint64_t nnz, const uint32_t* row_ptr,
+                    const uint32_t* col_ind, const uint32_t* val, int trans, uint32_t b, const uint32_t* X,
+                    uint32_t* Y, void* stream);
 /* Device memory from the context's cache (freed with the context at the
  * latest), for blocks passed to f4_spmm; f4_upload copies host bytes to it
  * and waits (f4_download copies back). */

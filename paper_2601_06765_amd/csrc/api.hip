@@ -943,6 +943,7 @@ int f4_create(f4_ctx** out, int device, const f4_opts* opts) {
     if (!X) return F4_E_NOMEM;
     try {
         F4_HIP_TRY(hipSetDevice(device));
+        noalloc_scratch_init(device);  // once per device: address of the allocation-free calls' scratch
         hipDeviceProp_t prop;
         F4_HIP_TRY(hipGetDeviceProperties(&prop, device));
         X->c.dev.device = device;
@@ -1310,7 +1311,7 @@ static std::function<void()> spmm_call(f4_ctx* X, uint32_t p, f4_matrix* A, int 
         const u32* idx = A->m.col_ind.ptr;
         const u32* val = A->m.val.ptr;
         const u32 r = P.r;
-        return [&c, p, r, b, ptr, idx, val, Xin, Y]() { spmm_run(c, p, r, b, ptr, idx, val, Xin, Y); };
+        return [&c, p, r, b, ptr, idx, val, Xin, Y]() { spmm_run(c.stream, p, r, b, ptr, idx, val, Xin, Y); };
     }
     if (!A->has_t) {
         csr_transpose(c, P.r, P.N, P.nnz, A->m.row_ptr.ptr, A->m.col_ind.ptr, A->m.val.ptr, A->t_ptr, A->t_idx,
@@ -1321,7 +1322,7 @@ static std::function<void()> spmm_call(f4_ctx* X, uint32_t p, f4_matrix* A, int 
     const u32* idx = A->t_idx.ptr;
     const u32* val = A->t_val.ptr;
     const u32 N = P.N;
-    return [&c, p, N, b, ptr, idx, val, Xin, Y]() { spmm_run(c, p, N, b, ptr, idx, val, Xin, Y); };
+    return [&c, p, N, b, ptr, idx, val, Xin, Y]() { spmm_run(c.stream, p, N, b, ptr, idx, val, Xin, Y); };
 }
 
 int f4_spmm(f4_ctx* X, uint32_t p, f4_matrix* A, int trans, uint32_t b, const uint32_t* Xin, uint32_t* Y,
@@ -1329,6 +1330,24 @@ int f4_spmm(f4_ctx* X, uint32_t p, f4_matrix* A, int trans, uint32_t b, const ui
     F4_API_BEGIN(X)
     set_stream(X, stream);
     spmm_call(X, p, A, trans, b, Xin, Y)();
+    F4_API_END(X)
+}
+
+int f4_spmm_noalloc(f4_ctx* X, uint32_t p, uint32_t r, uint32_t N, uint64_t nnz, const uint32_t* row_ptr,
+                    const uint32_t* col_ind, const uint32_t* val, int trans, uint32_t b, const uint32_t* Xin,
+                    uint32_t* Y, void* stream) {
+    F4_API_BEGIN(X)
+    if (!is_odd_prime(p) || p >= (1u << 31) || b == 0 || b > 64 || (trans != 0 && trans != 1) || !row_ptr ||
+        nnz >= (1ull << 32) || (nnz && (!col_ind || !val)))
+        throw F4Error{F4_E_ARG, "bad argument"};
+    const u32 nout = trans ? N : r, nin = trans ? r : N;
+    if ((nout && !Y) || (nin && nnz && !Xin)) throw F4Error{F4_E_ARG, "null block"};
+    const u64 need = spmm_noalloc_words(N, nnz, trans) * 4;
+    if (need > F4_NOALLOC_SCRATCH_BYTES)
+        throw F4Error{F4_E_RANGE, "the transpose needs " + std::to_string(need) + " bytes of scratch; the maximum is " +
+                                      std::to_string((u64)F4_NOALLOC_SCRATCH_BYTES)};
+    set_stream(X, stream);
+    spmm_noalloc_run(X->c.stream, X->c.dev.device, p, r, N, nnz, row_ptr, col_ind, val, trans, b, Xin, Y);
     F4_API_END(X)
 }
 

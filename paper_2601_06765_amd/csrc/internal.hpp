@@ -229,7 +229,8 @@ void tune_parse(Ctx& c, const char* text);
 // Block operator application (krylov.hip): Y = A X over F_p for a CSR matrix
 // (nrows rows) and a row-major block X of b <= 64 columns; words of the
 // matrix values and of X are read modulo p.  Enqueued on c.stream.
-void spmm_run(Ctx& c, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X, u32* Y);
+void spmm_run(hipStream_t s, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X,
+              u32* Y);
 // CSR of the transpose (the CSC of A): column pointers, row indices, values.
 void csr_transpose(Ctx& c, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx, const u32* val,
                    DBuf<u32>& tptr, DBuf<u32>& tidx, DBuf<u32>& tval);
@@ -238,6 +239,15 @@ void csr_transpose(Ctx& c, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const 
 u64 csr_transpose_ws_words(u32 ncols);
 void csr_transpose_into(hipStream_t s, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx,
                         const u32* val, u32* tptr, u32* tidx, u32* tval, u32* ws);
+// Allocation-free block products (f4_spmm_noalloc): the device address of
+// the file-scope scratch array is looked up once per device (call with that
+// device current); spmm_noalloc_words gives the scratch a product needs (the
+// transpose for trans = 1, nothing for trans = 0); spmm_noalloc_run enqueues
+// the product on `s`, the transpose built in the device's scratch.
+void noalloc_scratch_init(int device);
+u64 spmm_noalloc_words(u32 ncols, u64 nnz, int trans);
+void spmm_noalloc_run(hipStream_t s, int device, u32 p, u32 nrows, u32 ncols, u64 nnz, const u32* ptr,
+                      const u32* idx, const u32* val, int trans, u32 b, const u32* X, u32* Y);
 
 // Modular inner-loop microbenchmark (micro.hip): uploads the chains' start
 // values, times one launch of `iters` updates per chain with HIP events and

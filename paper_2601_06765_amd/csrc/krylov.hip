@@ -17,7 +17,11 @@
 // at most 2^32 products of words below 2^32), so no product is reduced; the
 // sum is reduced modulo p once per output (stored words and words of X may
 // be any 32-bit values: they act as their residues).
+#include <mutex>
+#include <unordered_map>
+
 #include "internal.hpp"
+#include "../../include/f4.h"
 
 #define SPMM_WG 256
 
@@ -97,48 +101,48 @@ __global__ __launch_bounds__(SPMM_WG) void k_spmm(Fp f, u32 nrows, u32 b, const 
 }
 
 template <int BP, int G, int VW>
-static void spmm_launch(Ctx& c, const Fp& f, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val,
+static void spmm_launch(hipStream_t s, const Fp& f, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val,
                         const u32* X, u32* Y) {
     const u32 grid = ceil_div((u64)nrows * G, SPMM_WG);
-    hipLaunchKernelGGL((k_spmm<BP, G, VW>), dim3(grid), dim3(SPMM_WG), 0, c.stream, f, nrows, b, ptr, idx, val, X,
-                       Y);
+    hipLaunchKernelGGL((k_spmm<BP, G, VW>), dim3(grid), dim3(SPMM_WG), 0, s, f, nrows, b, ptr, idx, val, X, Y);
     F4_LAUNCH_CHECK();
 }
 
-void spmm_run(Ctx& c, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X, u32* Y) {
+void spmm_run(hipStream_t s, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X,
+              u32* Y) {
     if (nrows == 0) return;
     const Fp f = make_fp(p);
     // two words per lane: an even b, and X and Y 8-byte aligned (caller
     // blocks need not be; then one word per lane)
     if (b % 2 == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 7) == 0) {
         if (b <= 2)
-            spmm_launch<1, 8, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<1, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
         else if (b <= 4)
-            spmm_launch<2, 8, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<2, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
         else if (b <= 8)
-            spmm_launch<4, 8, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<4, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
         else if (b <= 16)
-            spmm_launch<8, 8, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<8, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
         else if (b <= 32)
-            spmm_launch<16, 16, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<16, 16, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
         else
-            spmm_launch<32, 32, 2>(c, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<32, 32, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
         return;
     }
     if (b <= 1)
-        spmm_launch<1, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<1, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 2)
-        spmm_launch<2, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<2, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 4)
-        spmm_launch<4, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<4, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 8)
-        spmm_launch<8, 8, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<8, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 16)
-        spmm_launch<16, 16, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<16, 16, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
     else if (b <= 32)
-        spmm_launch<32, 32, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<32, 32, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
     else
-        spmm_launch<64, 64, 1>(c, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<64, 64, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
 }
 
 // ------------------------------------------------------------ transpose
@@ -187,4 +191,54 @@ void csr_transpose(Ctx& c, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const 
     tval.reset(&c.pool, std::max<u64>(nnz, 1));
     DBuf<u32> ws(&c.pool, csr_transpose_ws_words(ncols));
     csr_transpose_into(c.stream, nrows, ncols, nnz, ptr, idx, val, tptr.ptr, tidx.ptr, tval.ptr, ws.ptr);
+}
+
+// ------------------------------------------------- allocation-free products
+// Scratch of f4_spmm_noalloc: the transpose's CSR (column pointers, row
+// indices, values) and the counting sort's workspace, in one file-scope
+// device array that each GPU holds until the process ends.  In host code the
+// array's name is only a stand-in symbol, never a device address: the
+// address every launch uses is the one hipGetSymbolAddress returns, looked up
+// once per device (with that device current) when a context is created there.
+static __device__ __align__(256) u32 scratch[F4_NOALLOC_SCRATCH_BYTES / 4];
+static std::mutex scratch_mu;
+static std::unordered_map<int, u32*> scratch_at;  // device -> address of its copy
+
+void noalloc_scratch_init(int device) {
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (scratch_at.count(device)) return;
+    void* ptr = nullptr;
+    F4_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw F4Error{F4_E_DEVICE, "no device address for the scratch array"};
+    scratch_at[device] = static_cast<u32*>(ptr);
+}
+
+static u32* noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> g(scratch_mu);
+    auto it = scratch_at.find(device);
+    return it == scratch_at.end() ? nullptr : it->second;
+}
+
+u64 spmm_noalloc_words(u32 ncols, u64 nnz, int trans) {
+    if (!trans) return 0;
+    // tptr (ncols + 1, rounded to 64 words), tidx, tval, then the workspace
+    return ((u64)ncols + 1 + 63) / 64 * 64 + 2 * nnz + csr_transpose_ws_words(ncols);
+}
+
+void spmm_noalloc_run(hipStream_t s, int device, u32 p, u32 nrows, u32 ncols, u64 nnz, const u32* ptr,
+                      const u32* idx, const u32* val, int trans, u32 b, const u32* X, u32* Y) {
+    if (!trans) {
+        spmm_run(s, p, nrows, b, ptr, idx, val, X, Y);
+        return;
+    }
+    u32* base = noalloc_scratch(device);
+    if (!base) throw F4Error{F4_E_STATE, "scratch of this device not set up"};
+    if (spmm_noalloc_words(ncols, nnz, trans) * 4 > F4_NOALLOC_SCRATCH_BYTES)
+        throw F4Error{F4_E_RANGE, "transpose does not fit the scratch array"};
+    u32* tptr = base;
+    u32* tidx = tptr + ((u64)ncols + 1 + 63) / 64 * 64;
+    u32* tval = tidx + nnz;
+    u32* ws = tval + nnz;
+    csr_transpose_into(s, nrows, ncols, nnz, ptr, idx, val, tptr, tidx, tval, ws);
+    spmm_run(s, p, ncols, b, tptr, tidx, tval, X, Y);
 }

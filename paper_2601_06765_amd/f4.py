@@ -119,6 +119,8 @@ class ModloopStats(ctypes.Structure):
 
 
 _sig("f4_spmm", c_int, [c_vp, c_u32, c_vp, c_int, c_u32, c_vp, c_vp, c_vp])
+_sig("f4_spmm_noalloc", c_int, [c_vp, c_u32, c_u32, c_u32, c_u64, c_vp, c_vp, c_vp, c_int, c_u32, c_vp, c_vp,
+                               c_vp])
 _sig("f4_spmm_timed", c_int, [c_vp, c_u32, c_vp, c_int, c_u32, c_vp, c_vp, c_u32, P(ctypes.c_double)])
 _sig("f4_device_alloc", c_int, [c_vp, ctypes.c_size_t, P(c_vp)])
 _sig("f4_device_free", c_int, [c_vp, c_vp])
@@ -474,6 +476,19 @@ class Context:
         of shape (rows, b) or (rows,); returns Y as a DeviceArray."""
         b, out = self._spmm_args(A, X, trans, out)
         self._check(_lib.f4_spmm(self._h, p, A._h, 1 if trans else 0, b, c_vp(X.ptr), c_vp(out.ptr), c_vp(stream)))
+        return out
+
+    def spmm_noalloc(self, p, r, N, nnz, row_ptr, col_ind, val, X, out, trans=False, stream=None):
+        """Y = A X (or A^T X) over F_p for a CSR matrix in caller DeviceArrays
+        (f4_spmm_noalloc: allocates nothing; the transpose goes to the
+        library's per-GPU scratch array).  X and out are DeviceArrays."""
+        b = 1 if len(X.shape) == 1 else X.shape[1]
+        nin, nout = (r, N) if trans else (N, r)
+        if X.shape[0] != nin or out.size != nout * b:
+            raise ValueError("blocks do not match the matrix")
+        self._check(_lib.f4_spmm_noalloc(self._h, p, r, N, nnz, c_vp(row_ptr.ptr), c_vp(col_ind.ptr),
+                                         c_vp(val.ptr), 1 if trans else 0, b, c_vp(X.ptr), c_vp(out.ptr),
+                                         c_vp(stream)))
         return out
 
     def spmm_timed(self, p, A, X, trans=False, out=None, reps=10):
