@@ -450,6 +450,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
 // column, and the new pivot columns in the order of the new pivot rows.
 struct EchRound {
     u32 done, q, npr, npr0, cmin, b;
+    u32 pm;  // block rows (bits) that became pivot rows
     u32 cols[ECH_B];
     u32 rows[ECH_B];
     u32 Z[ECH_B * ECH_B];  // row t: coefficients of new pivot row t on the block rows
@@ -516,6 +517,8 @@ __device__ __forceinline__ u32 fp_inv_t(const Fp& f, u32 a) {
 // of the pivot chain exposed, four per SIMD issue the loop control 4 times.)
 #define ECH_PW 8
 #define ECH_RPW (ECH_B / ECH_PW)
+#define ECH_EMPTY 2       // chunks in a row without a pivot that end a block's scan early ...
+#define ECH_EMPTY_LEFT 8  // ... while more than this many chunks are left
 
 template <bool SMALL>
 __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead, u32* status, const u32* Dp,
@@ -615,7 +618,15 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     auto load_b = [&](u32 j0) -> u32 { return (kB < b && j0 + jB < c) ? D[boff + j0 + jB] : 0u; };
     const u32 cmin0 = s_cmin;
     u32 bnext = load_b(cmin0);
+    // the scan stops early after ECH_EMPTY chunks in a row without a new
+    // pivot: the block rows that are not pivots then go back to the remaining
+    // rows (they are zero on the scanned columns after the elimination, and
+    // the round's update reduces them like any other row, to zero when they
+    // are dependent), instead of being followed to the last column
+    u32 empty = 0;
+    bool early = false;
     for (u32 j0 = cmin0; j0 < c && q < b; j0 += ECH_CH) {
+        const u32 q_before = q;
         const u32 w = min((u32)ECH_CH, c - j0);
         s_B[tid] = bnext;
         bnext = load_b(j0 + ECH_CH);
@@ -694,6 +705,11 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
             ++it;
             __syncthreads();
         }
+        empty = q == q_before ? empty + 1 : 0;
+        if (empty >= ECH_EMPTY && q < b && c - j0 > ECH_EMPTY_LEFT * ECH_CH) {
+            early = true;
+            break;
+        }
     }
     if (count_ops && lane == 0) nops += (u64)nupd * 2 * ECH_W;
     // each pivot row is its value at its own pivot column times its normalised
@@ -720,15 +736,20 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
         const u32 t = x / ECH_B, u = x % ECH_B;
         R->Z[t * ECH_B + u] = u < b ? fp_mul_t<SMALL>(f, s_RZ[s_prow[t] * ECH_RS + ECH_CH + u], s_inv[t]) : 0u;
     }
+    u32 pmk = 0;  // block rows that became pivot rows
+    for (u32 t = 0; t < q; ++t) pmk |= 1u << s_prow[t];
     if (tid < b) {
         R->rows[tid] = s_rows[tid];
-        st[s_rows[tid]] = 1;
+        // consumed: pivot rows, and after a complete scan the other block rows
+        // too (they are zero)
+        st[s_rows[tid]] = (!early || ((pmk >> tid) & 1u)) ? 1u : 0u;
     }
     if (ops && nops) atomicAdd(ops, (unsigned long long)nops);
     __syncthreads();
     if (tid == 0) {
         R->q = q;
         R->b = b;
+        R->pm = pmk;
         R->npr0 = npr;
         R->npr = npr + q;
         ndone[1 + blockIdx.y] = npr + q;  // pivot rows so far, read back with the done count
@@ -736,6 +757,243 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
     }
 }
 
+// Exact modular dot products in double precision.  A double holds every
+// integer below 2^53, and a fused multiply-add whose exact result is an
+// integer below 2^53 in magnitude returns it exactly, so a sum of products of
+// residues costs one full-rate FMA per product and a single reduction:
+//   p < 2^16: 32 products below 2^32 sum to less than 2^37;
+//   otherwise the left factor w is split as w_hi 2^16 + w_lo (w_hi < 2^15,
+//   w_lo < 2^16), giving sums below 2^51 and 2^52 that recombine as
+//   (S_hi mod p) 2^16 + S_lo < 2^53.
+// x mod p for an integer-valued double with |x| < 2^53: the estimate
+// floor(x / p) from the rounded reciprocal has relative error below 2^-52 and
+// |x| / p < 2^52, so it is off by at most one, and x - q p, an integer of
+// magnitude below 2p, is formed exactly by the fused multiply-add.
+__device__ __forceinline__ double dmod(double x, double pd, double pinv) {
+    const double q = floor(x * pinv);
+    double r = fma(-q, pd, x);
+    r = r < 0.0 ? r + pd : r;
+    return r >= pd ? r - pd : r;
+}
+
+// One round's update of a tile of ECH_RT row slots x ECH_CT columns (one
+// column per thread), per prime class.  Row slots of a system: its L
+// remaining rows of D', then its pivot-row store.  Store slots npr0 ..
+// npr0+q-1 become this round's new pivot rows NP_t = sum_u Z[t][u] (block row
+// u); every other live row r (remaining rows, earlier pivot rows) loses its
+// entries on the round's pivot columns: with coef_t = r[col_t],
+// r - sum_t coef_t NP_t = r + sum_u w_u (block row u), w = -coef Z.  This is a
+// product of the tile's weights (ECH_RT x 32) with the block rows (32 x
+// ECH_CT), formed with the exact double-precision sums above.  Only block
+// rows that became pivot rows are read (the others have weight zero in every
+// row and may be updated in the same launch).  The round's pivot columns of
+// the updated rows are left as they are - other tiles read them as the
+// coefficients - and are cleared by k_ech_lead afterwards.  Columns left of
+// the round's first pivot column are unchanged (the block rows are zero
+// there), except in new pivot rows, which are written whole.
+#define ECH_RT 16
+#define ECH_CT 256
+#define ECH_SPAN_MAX 1024  // most columns of one tile (passes of ECH_CT columns)
+#define ECH_SHORT 1024     // rows of at most this many trailing columns use the per-row update forms
+template <bool SMALL>
+__global__ __launch_bounds__(ECH_CT) void k_ech_gemm(const SegR* segs, u32 S, const u32* tbase, u32* Dp,
+                                                     const u32* status, u32* lead, const EchRound* rounds, u32* PR,
+                                                     u32 span) {
+    __shared__ double2 s_w[ECH_RT][ECH_B];  // weights: (high half, low half); SMALL: (weight, 0)
+    __shared__ u32 s_coef[ECH_RT][ECH_B];
+    __shared__ u32 s_Z[ECH_B][ECH_B + 1];
+    __shared__ u32 s_cols[ECH_B], s_rows[ECH_B];
+    __shared__ u32 s_kind[ECH_RT], s_any[ECH_RT];
+    __shared__ u32 s_pc[ECH_SPAN_MAX / 32];  // the round's pivot columns inside this column tile
+    __shared__ u32 s_lead[ECH_RT];     // whole-row tiles: new leading column of each remaining row
+    const u32 tile = blockIdx.x;
+    u32 lo = 0, hi = S;  // system: last s with tbase[s] <= tile
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (tbase[mid] <= tile)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const u32 s = lo;
+    const EchRound* R = rounds + s;
+    if (R->done) return;
+    const SegR G = segs[s];
+    if ((G.small != 0) != SMALL) return;
+    const u32 c = G.c, j0 = blockIdx.y * span;
+    if (j0 >= c) return;
+    const Fp f = G.f;
+    const u32 q = R->q, b = R->b, npr0 = R->npr0, cmin = R->cmin, pm = R->pm;
+    const u32 l0 = (tile - tbase[s]) * ECH_RT;
+    const u32 tid = threadIdx.x;
+    const bool left = j0 + span <= cmin;  // only new pivot rows have work left of cmin
+    auto row_of = [&](u32 local) -> u32* {
+        return local < G.L ? Dp + G.dpb + (u64)local * c : PR + G.prb + (u64)(local - G.L) * c;
+    };
+    // kinds: 0 no work, 1 update (live remaining row or earlier pivot row),
+    // 2 + t new pivot row t
+    if (tid < ECH_RT) {
+        const u32 local = l0 + tid;
+        u32 kind = 0;
+        if (local < G.L) {
+            if (!left && status[G.lb + local] == 0 && lead[G.lb + local] < c) kind = 1;
+        } else if (local - G.L < npr0) {
+            if (!left) kind = 1;
+        } else if (local - G.L < npr0 + q) {
+            kind = 2 + (local - G.L - npr0);
+        }
+        s_kind[tid] = kind;
+        s_any[tid] = 0;
+        s_lead[tid] = 0xffffffffu;
+    }
+    if (tid < ECH_B) {
+        s_cols[tid] = tid < q ? R->cols[tid] : 0u;
+        s_rows[tid] = tid < b ? R->rows[tid] : 0u;
+    }
+    if (tid < ECH_SPAN_MAX / 32) s_pc[tid] = 0;
+    for (u32 x = tid; x < q * ECH_B; x += ECH_CT) s_Z[x / ECH_B][x % ECH_B] = R->Z[x];
+    __syncthreads();
+    if (tid < q && s_cols[tid] >= j0 && s_cols[tid] < j0 + span)
+        atomicOr(&s_pc[(s_cols[tid] - j0) / 32], 1u << ((s_cols[tid] - j0) % 32));
+    // coefficients of the update rows on the round's pivot columns
+    for (u32 x = tid; x < ECH_RT * ECH_B; x += ECH_CT) {
+        const u32 r = x / ECH_B, t = x % ECH_B;
+        u32 v = 0;
+        if (s_kind[r] == 1 && t < q) v = row_of(l0 + r)[s_cols[t]];
+        s_coef[r][t] = v;
+        if (v) s_any[r] = 1;
+    }
+    __syncthreads();
+    const double pd = (double)f.p, pinv = 1.0 / pd;
+    // weights w_u = -(sum_t coef_t Z[t][u]) of update rows, Z[t][u] of new pivot row t
+    for (u32 x = tid; x < ECH_RT * ECH_B; x += ECH_CT) {
+        const u32 r = x / ECH_B, u = x % ECH_B, kind = s_kind[r];
+        u32 w = 0;
+        if (kind >= 2) {
+            w = u < b ? s_Z[kind - 2][u] : 0u;
+        } else if (kind == 1 && s_any[r] && u < b) {
+            double sh = 0.0, sl = 0.0;
+            for (u32 t = 0; t < q; ++t) {
+                const u32 cf = s_coef[r][t];
+                const double z = (double)s_Z[t][u];
+                if (SMALL) {
+                    sh = fma((double)cf, z, sh);
+                } else {
+                    sh = fma((double)(cf >> 16), z, sh);
+                    sl = fma((double)(cf & 0xffffu), z, sl);
+                }
+            }
+            const double v = SMALL ? dmod(sh, pd, pinv) : dmod(fma(dmod(sh, pd, pinv), 65536.0, sl), pd, pinv);
+            w = fp_neg(f, (u32)v);
+        }
+        s_w[r][u] = SMALL ? make_double2((double)w, 0.0) : make_double2((double)(w >> 16), (double)(w & 0xffffu));
+    }
+    __syncthreads();
+    // a row that fits in one tile has its coefficients read by this workgroup
+    // only, so it clears the pivot columns and finds the new leading columns
+    // itself (k_ech_lead then finds nothing left to do)
+    const bool whole = j0 == 0 && c <= span;
+    for (u32 j = j0 + tid; j < min(c, j0 + span); j += ECH_CT) {
+        const u32* D = Dp + G.dpb;
+        double xb[ECH_B];  // this column of the block rows that became pivot rows
+#pragma unroll
+        for (u32 u = 0; u < ECH_B; ++u) xb[u] = ((pm >> u) & 1u) ? (double)D[(u64)s_rows[u] * c + j] : 0.0;
+        const bool pcol = (s_pc[(j - j0) / 32] >> ((j - j0) % 32)) & 1u;
+        for (u32 r = 0; r < ECH_RT; ++r) {
+            const u32 kind = s_kind[r];
+            if (kind == 0 || (kind == 1 && !s_any[r])) continue;
+            if (kind == 1 && j < cmin) continue;
+            u32* row = row_of(l0 + r);
+            if (kind == 1 && pcol) {
+                if (whole) row[j] = 0;
+                continue;
+            }
+            double sh = 0.0, sl = 0.0;
+#pragma unroll
+            for (u32 u = 0; u < ECH_B; ++u) {
+                const double2 w = s_w[r][u];
+                sh = fma(w.x, xb[u], sh);
+                if (!SMALL) sl = fma(w.y, xb[u], sl);
+            }
+            const u32 v = (u32)(SMALL ? dmod(sh, pd, pinv) : dmod(fma(dmod(sh, pd, pinv), 65536.0, sl), pd, pinv));
+            if (kind >= 2) {
+                row[j] = v;
+            } else {
+                u32 nv = row[j] + v;  // both below p < 2^31
+                nv = nv >= f.p ? nv - f.p : nv;
+                row[j] = nv;
+                if (whole && nv && l0 + r < G.L) atomicMin(&s_lead[r], j);
+            }
+        }
+    }
+    if (whole) {
+        __syncthreads();
+        if (tid < ECH_RT && s_kind[tid] == 1 && s_any[tid] && l0 + tid < G.L) lead[G.lb + l0 + tid] = s_lead[tid];
+    }
+}
+
+// After a round's update, one wave per row slot: an updated row (one with a
+// nonzero coefficient on the round's pivot columns) gets zeros on those
+// columns (exact: the update subtracts coef_t times a row that is 1 at col_t
+// and 0 at the other pivot columns), and an updated remaining row gets its
+// new leading column (none: the row is zero and leaves the elimination).
+#define ECH_LW 4
+__global__ __launch_bounds__(64 * ECH_LW) void k_ech_lead(const SegR* segs, u32 S, const u32* ubase, u32* Dp,
+                                                          const u32* status, u32* lead, const EchRound* rounds,
+                                                          u32* PR) {
+    const u32 lane = lane_id();
+    const u32 u = blockIdx.x * ECH_LW + threadIdx.x / F4_WAVE;
+    if (u >= ubase[S]) return;
+    u32 lo = 0, hi = S;  // system: last s with ubase[s] <= u
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (ubase[mid] <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const EchRound* R = rounds + lo;
+    if (R->done) return;
+    const SegR G = segs[lo];
+    const u32 c = G.c, q = R->q, npr0 = R->npr0;
+    const u32 local = u - G.ub;
+    u32* row;
+    bool rem;
+    if (local < G.L) {
+        if (status[G.lb + local] != 0 || lead[G.lb + local] >= c) return;
+        row = Dp + G.dpb + (u64)local * c;
+        rem = true;
+    } else {
+        if (local - G.L >= npr0) return;
+        row = PR + G.prb + (u64)(local - G.L) * c;
+        rem = false;
+    }
+    const u32 col = lane < q ? R->cols[lane] : 0u;
+    const u32 coef = lane < q ? row[col] : 0u;
+    if (!wave_ballot(coef != 0)) return;  // not touched by the update
+    if (coef) row[col] = 0;
+    if (!rem) return;
+    // first nonzero at or after cmin that is not one of the round's pivot
+    // columns (the zeros just written are not read back)
+    u32 first = 0xffffffffu;
+    for (u32 j0 = R->cmin; j0 < c; j0 += F4_WAVE) {
+        const u32 j = j0 + lane;
+        bool nz = j < c && row[j] != 0;
+        for (u32 t = 0; t < q; ++t) nz = nz && j != (u32)__builtin_amdgcn_readlane((int)col, (int)t);
+        const u64 m = wave_ballot(nz);
+        if (m) {
+            first = j0 + (u32)__ffsll((long long)m) - 1;
+            break;
+        }
+    }
+    if (lane == 0) lead[G.lb + local] = first;
+}
+
+
+// Update forms for short rows (at most ECH_SHORT trailing columns), where
+// per-row parallelism matters more than operand reuse.  Only block rows that
+// became pivot rows are read (the others have weight zero in every row and
+// may be updated by the same launch).
 // The same update for many rows (large batches): one wave per row slot of a
 // system (remaining rows of D': the first L slots; the pivot-row store: the
 // next cap slots), ECH_UPW slots per workgroup.  Store slots npr0 ..
@@ -790,6 +1048,7 @@ __global__ __launch_bounds__(64 * ECH_UPW) void k_ech_update_wave(const SegR* se
     // block rows and weights of lanes 0 .. b-1 broadcast to every lane once,
     // while the whole wave is active (the column loops below may not be)
     const u32 brow = lane < b ? R->rows[lane] : 0u;
+    const u32 pm = R->pm;
     u64 rbase[ECH_B];
 #pragma unroll
     for (u32 v = 0; v < ECH_B; ++v) rbase[v] = (u64)(u32)__shfl((int)brow, (int)v, F4_WAVE) * c;
@@ -802,7 +1061,7 @@ __global__ __launch_bounds__(64 * ECH_UPW) void k_ech_update_wave(const SegR* se
     auto combo = [&](u32 j) -> u32 {
         u32 x[ECH_B];
 #pragma unroll
-        for (u32 v = 0; v < ECH_B; ++v) x[v] = v < b ? D[rbase[v] + j] : 0u;
+        for (u32 v = 0; v < ECH_B; ++v) x[v] = ((pm >> v) & 1u) ? D[rbase[v] + j] : 0u;
         u64 acc = 0;
 #pragma unroll
         for (u32 v = 0; v < ECH_B; ++v) acc += small ? (u64)mul24(wv[v], x[v]) : (u64)fp_mul(f, wv[v], x[v]);
@@ -869,7 +1128,7 @@ __global__ __launch_bounds__(256) void k_ech_update_row(const SegR* segs, u32 S,
     const SegR G = segs[s];
     const Fp f = G.f;
     const bool small = G.small != 0;
-    const u32 c = G.c, q = R->q, b = R->b, npr0 = R->npr0;
+    const u32 c = G.c, q = R->q, b = R->b, npr0 = R->npr0, pm = R->pm;
     const u32 local = u - G.ub;
     const u32 tid = threadIdx.x;
     const u32* D = Dp + G.dpb;
@@ -894,7 +1153,7 @@ __global__ __launch_bounds__(256) void k_ech_update_row(const SegR* segs, u32 S,
     auto combo = [&](u32 j) -> u32 {
         u32 x[ECH_B];
 #pragma unroll
-        for (u32 v = 0; v < ECH_B; ++v) x[v] = v < b ? D[(u64)s_rows[v] * c + j] : 0u;
+        for (u32 v = 0; v < ECH_B; ++v) x[v] = ((pm >> v) & 1u) ? D[(u64)s_rows[v] * c + j] : 0u;
         u64 acc = 0;
 #pragma unroll
         for (u32 v = 0; v < ECH_B; ++v) acc += small ? (u64)mul24(s_w[v], x[v]) : (u64)fp_mul(f, s_w[v], x[v]);
@@ -1404,14 +1663,14 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
     // nonzeros per system
     const u32 S = A.S;
     const size_t rbytes = ((size_t)S * sizeof(EchRound) + 255) & ~(size_t)255;
-    const size_t o_nd = (rbytes + ((size_t)S + 1) * 4 + 255) & ~(size_t)255;
+    const size_t o_nd = (rbytes + 2 * ((size_t)S + 1) * 4 + 255) & ~(size_t)255;
     const size_t nback = (size_t)(S + 1) + 2 * (size_t)S + S;  // words read back, then the leading monomials
     u32 CAP0 = 0;  // pivot-row store slots: sum of min(L, c) <= sum of min(r, N)
     for (const SysPart& P : A.sys) CAP0 += std::min(P.r, P.N);
     const size_t o_lm = (o_nd + nback * 4 + 7) & ~(size_t)7;
     DBuf<u8> eparams(&c.pool, o_lm + (size_t)CAP0 * 8);
     EchRound* const rounds = (EchRound*)eparams.ptr;
-    u32* const ubp = (u32*)(eparams.ptr + rbytes);
+    u32* const ubp = (u32*)(eparams.ptr + rbytes);  // row-slot bases, then update-tile bases (S + 1 each)
     u32* const ndone = (u32*)(eparams.ptr + o_nd);  // [0] done count, [1 + s] pivot rows of system s
     u32* const dsumm = ndone + S + 1;               // split counts: pivots, lower rows
     u32* const dtot = dsumm + 2 * S;                // emitted nonzeros per system
@@ -1441,7 +1700,7 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
     // echelon of every system's D' (L x c)
     DBuf<u32> PR(&c.pool, std::max<u64>(PRtot, 1)), prlead(&c.pool, std::max<u32>(CAP, 1));
     std::vector<u32> npr(S, 0), rnnz(S, 0);
-    u32 active = 0;
+    u32 active = 0, TT = 0;
     for (const SegR& g : X.segs) active += (g.L && g.c) ? 1 : 0;
     // systems with nothing to eliminate are done from the start
     {
@@ -1451,6 +1710,13 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
         u32* hub = (u32*)(pack.data() + rbytes);
         for (u32 i = 0; i < S; ++i) hub[i] = X.segs[i].ub;
         hub[S] = UB;
+        u32 tt = 0;
+        for (u32 i = 0; i < S; ++i) {
+            hub[S + 1 + i] = tt;
+            tt += ceil_div((u64)X.segs[i].L + X.segs[i].cap, ECH_RT);
+        }
+        hub[2 * S + 1] = tt;
+        TT = tt;
         upload(c, eparams.ptr, pack.data(), pack.size());
     }
     out.S = S;
@@ -1496,16 +1762,33 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
                                        status.ptr, Dp.ptr, ccnt.ptr, cnt_lds, rounds, prlead.ptr, ndone, bops);
                 F4_LAUNCH_CHECK();
                 if (ka) out.ev_block.push_back({ka, kernel_event(c)});
-                // a workgroup per row while rows are few (each row spread over
-                // 256 threads and the rows over the CUs), a wave per row for
-                // a few thousand rows and more
-                if (UB >= 2048)
-                    hipLaunchKernelGGL(k_ech_update_wave, dim3(ceil_div(UB, ECH_UPW)), dim3(64 * ECH_UPW), 0, s,
-                                       X.dsegs.ptr, S, ubp, Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr);
-                else
-                    hipLaunchKernelGGL(k_ech_update_row, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s, X.dsegs.ptr, S,
-                                       ubp, Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr);
-                F4_LAUNCH_CHECK();
+                if (maxc <= ECH_SHORT) {
+                    // short rows: a workgroup per row while rows are few (each
+                    // row spread over 256 threads and the rows over the CUs), a
+                    // wave per row for a few thousand rows and more
+                    if (UB >= 2048)
+                        hipLaunchKernelGGL(k_ech_update_wave, dim3(ceil_div(UB, ECH_UPW)), dim3(64 * ECH_UPW), 0, s,
+                                           X.dsegs.ptr, S, ubp, Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr);
+                    else
+                        hipLaunchKernelGGL(k_ech_update_row, dim3(std::max<u32>(UB, 1)), dim3(256), 0, s,
+                                           X.dsegs.ptr, S, ubp, Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr);
+                    F4_LAUNCH_CHECK();
+                } else {
+                    // long rows: tiles of row slots x ECH_CT columns (block-row
+                    // operands reused across the tile's rows), then the cleared
+                    // pivot columns and the new leading columns
+                    const dim3 ug(std::max<u32>(TT, 1), ceil_div(maxc, ECH_CT));
+                    if (any_small)
+                        hipLaunchKernelGGL(k_ech_gemm<true>, ug, dim3(ECH_CT), 0, s, X.dsegs.ptr, S, ubp + S + 1,
+                                           Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr, (u32)ECH_CT);
+                    if (any_large)
+                        hipLaunchKernelGGL(k_ech_gemm<false>, ug, dim3(ECH_CT), 0, s, X.dsegs.ptr, S, ubp + S + 1,
+                                           Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr, (u32)ECH_CT);
+                    F4_LAUNCH_CHECK();
+                    hipLaunchKernelGGL(k_ech_lead, dim3(std::max<u32>(ceil_div(UB, ECH_LW), 1)), dim3(64 * ECH_LW), 0,
+                                       s, X.dsegs.ptr, S, ubp, Dp.ptr, status.ptr, lead.ptr, rounds, PR.ptr);
+                    F4_LAUNCH_CHECK();
+                }
                 ++r;
             }
             batch = 4;

@@ -94,3 +94,72 @@ def test_fraction_free_update_exact(p):
     e = np.array([p - 1, p - 2, 1, 0], dtype=np.int64)
     P, A, F, B = (x.ravel() for x in np.meshgrid(e, e, e, e))
     assert np.array_equal(ff32(P, A, F, B, p).astype(np.int64), (P * A - F * B) % p)
+
+
+# ------------------------------------------------ exact double-precision sums
+# The echelon update forms sum_u w_u x_u mod p for 32 residue pairs with
+# double-precision multiply-adds: p < 2^16 directly (sum < 2^37), otherwise w
+# split into 16-bit halves (sums below 2^51 and 2^52) recombined as
+# (S_hi mod p) 2^16 + S_lo, and x mod p as x - floor(x * (1/p)) p with one
+# correction each way.  Every product and partial sum here is an integer below
+# 2^53, so numpy's separate multiply and add give what the fused multiply-add
+# gives on the device.
+
+def dmod(x, p):
+    pd = np.float64(p)
+    pinv = np.float64(1.0) / pd
+    q = np.floor(x * pinv)
+    r = x - q * pd  # |r| < 2p: exact, as the device's fused form
+    r = np.where(r < 0, r + pd, r)
+    return np.where(r >= pd, r - pd, r)
+
+
+def dot_mod(w, x, p, small):
+    """w, x: (n, 32) residues; returns sum_u w x mod p per row, as the kernel forms it."""
+    xd = x.astype(np.float64)
+    if small:
+        s = np.zeros(len(w))
+        for u in range(w.shape[1]):
+            s = s + w[:, u].astype(np.float64) * xd[:, u]
+        return dmod(s, p)
+    sh, sl = np.zeros(len(w)), np.zeros(len(w))
+    for u in range(w.shape[1]):
+        sh = sh + (w[:, u] >> 16).astype(np.float64) * xd[:, u]
+        sl = sl + (w[:, u] & 0xffff).astype(np.float64) * xd[:, u]
+    return dmod(dmod(sh, p) * 65536.0 + sl, p)
+
+
+@pytest.mark.parametrize("p,small", [(3, True), (257, True), (65521, True), (65519, True), (3, False),
+                                     (65521, False), (2147483647, False), (2147483629, False),
+                                     (2147483497, False), (1000003, False)])
+def test_double_split_dot_exact(p, small):
+    rng = np.random.default_rng(p + small)
+    n = 200_000
+    w = rng.integers(0, p, (n, 32), dtype=np.uint64)
+    x = rng.integers(0, p, (n, 32), dtype=np.uint64)
+    # the largest sums: every factor p - 1, and rows of mixed extremes
+    w[:1000] = p - 1
+    x[:1000] = p - 1
+    w[1000:2000, ::2] = p - 1
+    x[1000:2000, 1::2] = p - 1
+    want = np.array([sum(int(a) * int(b) for a, b in zip(wr, xr)) % p for wr, xr in zip(w[:3000], x[:3000])],
+                    dtype=np.uint64)
+    got = dot_mod(w, x, p, small).astype(np.uint64)
+    assert np.array_equal(got[:3000], want)
+    # the rest against exact object-integer sums, vectorised
+    ws, xs = w[3000:].astype(object), x[3000:].astype(object)
+    want2 = np.array((ws * xs).sum(axis=1) % p, dtype=np.uint64)
+    assert np.array_equal(got[3000:], want2)
+
+
+@pytest.mark.parametrize("p", [3, 65521, 2147483647, 2147483497])
+def test_dmod_near_multiples(p):
+    # integers next to multiples of p across the range the kernels reduce (< 2^53)
+    k = np.unique(np.concatenate([np.arange(0, 4000), (np.float64(2) ** 53 // p) - np.arange(0, 4000)]))
+    k = k[k >= 0]
+    base = k * np.float64(p)
+    for d in (-1, 0, 1, p - 1):
+        x = base + d
+        x = x[(x >= 0) & (x < 2.0 ** 53)]
+        want = np.array([int(v) % p for v in x], dtype=np.float64)
+        assert np.array_equal(dmod(x, p), want)
