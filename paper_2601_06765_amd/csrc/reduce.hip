@@ -48,7 +48,13 @@ struct SegR {
     u64 dpb;       // D' base (u32 entries, row stride c)
     u64 prb;       // pivot-row store base (u32 entries, row stride c)
     u32 db;        // dictionary base of the system in the matrix's dict_keys
+    u32 pk;        // p = 2^31 - pk with 1 <= pk < 2^8 (and npiv < 2^24), else 0
 };
+
+// Triangular-solve arithmetic class of a system: 0 p < 2^16 (u32 lazy
+// accumulators), 1 p = 2^31 - k with small k (u64 accumulators of folded
+// products), 2 any other p (u64 accumulators of Barrett-reduced products).
+__host__ __device__ inline int trsm_class(const SegR& g) { return g.small ? 0 : (g.pk ? 1 : 2); }
 
 // ------------------------------------------------------------------ split
 __global__ void k_lead_best(const SegR* segs, const u32* row_ptr, const u32* col_ind, const u32* row_sys, u32 R,
@@ -273,34 +279,41 @@ __global__ __launch_bounds__(256) void k_tinv(const SegR* segs, const u32* T, u3
 // is solved for every row of the tile at once (wave r solves row r), then the
 // panel's trailing entries are read once and applied to all rows of the tile,
 // so the upper block is streamed once per tile rather than once per row.
-// SMALL: p < 2^16 and npiv < 2^16 (u32 lazy accumulator: a column receives at
-// most npiv additions of values below p); otherwise u64.  Systems of the other
-// class return at once.
+// Arithmetic classes (MODE): 0, p < 2^16 and npiv < 2^16: each product
+// reduced by the one-word Barrett step into a u32 accumulator (a column
+// receives at most npiv additions of values below p); 1, p = 2^31 - k with
+// k < 2^8 (the large prime of the workloads and the CRT primes): the product
+// t < 2^62 is only folded, t = h 2^31 + l == k h + l (mod p), a value below
+// 2^39 + 2^31 added to a u64 accumulator (at most 2^24 additions fit, so this
+// class needs npiv < 2^24), which costs a multiply-add instead of a full
+// reduction; 2, any other p: Barrett-reduced products into u64.  Systems of
+// another class return at once.
 #define TR_MAXR 4
-template <bool SMALL>
+template <int MODE>
 struct AccOf {
     typedef u64 T;
 };
 template <>
-struct AccOf<true> {
+struct AccOf<0> {
     typedef u32 T;
 };
 
-template <bool SMALL, bool LDS>
+template <int MODE, bool LDS>
 __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_base, const u32* row_ptr,
                                                      const u32* col_ind, const u32* val, const u32* list,
                                                      int tail, u32 rr, u32 tile_base, int skip_lead,
                                                      const u32* perm, const u32* Tinv, const u32* tptr,
-                                                     const u64* tent, typename AccOf<SMALL>::T* gacc, u32* Dp,
+                                                     const u64* tent, typename AccOf<MODE>::T* gacc, u32* Dp,
                                                      u32* lead_out, u32* status, unsigned long long* ops) {
-    typedef typename AccOf<SMALL>::T AccT;
+    constexpr bool SMALL = MODE == 0;
+    typedef typename AccOf<MODE>::T AccT;
     extern __shared__ unsigned char smraw[];
     __shared__ u32 s_x[TR_MAXR][PANEL];
     __shared__ u64 s_xs[2][TR_MAXR][PANEL];  // partial sums of x = l T^-1 (double buffered)
     __shared__ u64 s_hit[TR_MAXR];
     __shared__ u32 s_lead[TR_MAXR];
     const SegR S = segs[sys_base + blockIdx.y];
-    if ((S.small != 0) != SMALL || S.c == 0) return;
+    if (trsm_class(S) != MODE || S.c == 0) return;
     const u32 cnt = tail ? S.r : S.L;  // rows of this system in the list
     const u32 t0 = (tile_base + blockIdx.x) * rr;
     if (t0 >= cnt) return;
@@ -376,7 +389,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
             const u32 r = wave;
             const u32 x = fp_reduce_any(f, s_xs[buf][r][lane]);
             s_xs[buf][r][lane] = 0;
-            s_x[r][lane] = x;
+            s_x[r][lane] = x ? f.p - x : 0u;  // the multiplier -x, kept as a residue (0: nothing to apply)
             const u64 hit = wave_ballot(x != 0);
             if (lane == 0) s_hit[r] = hit;
             if (lane < wk) acc[r * N + qa + lane] = 0;
@@ -398,9 +411,17 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
 #pragma unroll
                     for (int r = 0; r < TR_MAXR; ++r) {
                         if (!xs[r]) continue;
-                        const u32 negx = f.p - xs[r];
-                        const u32 add = SMALL ? fp_mul32(f, negx, tv) : fp_reduce(f, (u64)negx * tv);
-                        atomicAdd(&acc[r * N + col], (AccT)add);
+                        const u32 negx = xs[r];
+                        AccT add;
+                        if (MODE == 0) {
+                            add = fp_mul32(f, negx, tv);
+                        } else if (MODE == 1) {
+                            const u64 t = (u64)negx * tv;  // < 2^62
+                            add = (u64)S.pk * (u32)(t >> 31) + ((u32)t & 0x7fffffffu);
+                        } else {
+                            add = fp_reduce(f, (u64)negx * tv);
+                        }
+                        atomicAdd(&acc[r * N + col], add);
                         ++nops;
                     }
                 }
@@ -1418,6 +1439,7 @@ static void split_layout(SplitState& X, const std::vector<u32>& p, const std::ve
         g.npiv = npiv[i];
         g.L = L[i];
         g.small = (p[i] < 65536 && g.npiv < 65536) ? 1u : 0u;
+        g.pk = (!g.small && p[i] > (1u << 31) - 256 && g.npiv < (1u << 24)) ? (1u << 31) - p[i] : 0u;
         g.pb = P;
         g.lb = Lb;
         g.c = g.N - g.npiv;
@@ -1574,12 +1596,12 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
     unsigned long long* ops = kt && kt->ops.ptr ? (unsigned long long*)kt->ops.ptr : nullptr;
     hipStream_t s = c.stream;
     const u32 S = X.S;
-    for (int cls = 0; cls < 2; ++cls) {
+    for (int cls = 0; cls < 3; ++cls) {
         const bool small = cls == 0;
         const size_t accb = small ? 4 : 8;
         u32 nmax = 0, cmax = 0;
         for (const SegR& g : X.segs)
-            if (g.c && (g.small != 0) == small) {
+            if (g.c && trsm_class(g) == cls) {
                 nmax = std::max(nmax, g.N);
                 cmax = std::max(cmax, tail ? g.r : g.L);
             }
@@ -1593,13 +1615,18 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
             const u32 rmax = (u32)std::min<size_t>(TR_MAXR, budget / row_bytes);
             auto launch = [&](u32 rr, unsigned long long* op) {
                 const u32 tiles = ceil_div(cmax, rr);
-                if (small)
-                    hipLaunchKernelGGL((k_trsm<true, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
+                if (cls == 0)
+                    hipLaunchKernelGGL((k_trsm<0, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
                                        X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
                                        skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)nullptr, Dp,
                                        lead_out, status, op);
+                else if (cls == 1)
+                    hipLaunchKernelGGL((k_trsm<1, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
+                                       X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
+                                       skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, Dp,
+                                       lead_out, status, op);
                 else
-                    hipLaunchKernelGGL((k_trsm<false, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
+                    hipLaunchKernelGGL((k_trsm<2, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
                                        X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
                                        skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, Dp,
                                        lead_out, status, op);
@@ -1613,7 +1640,7 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
                 // run on the live data
                 u64 rows = 0;
                 for (const SegR& g : X.segs)
-                    if (g.c && (g.small != 0) == small) rows += tail ? g.r : g.L;
+                    if (g.c && trsm_class(g) == cls) rows += tail ? g.r : g.L;
                 std::vector<u32> cands;
                 for (u32 v = 1; v <= rmax; ++v) cands.push_back(v);
                 rr = tune_pick(c, tune_key(TUNE_TRSM, small ? 1 : 0, tune_lg(rows), tune_lg(nmax)), cands,
@@ -1632,16 +1659,21 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
         for (u32 sy = 0; sy < S; ++sy) {
             const SegR& g = X.segs[sy];
             const u32 cnt = tail ? g.r : g.L;
-            if (!g.c || (g.small != 0) != small || !cnt) continue;
+            if (!g.c || trsm_class(g) != cls || !cnt) continue;
             for (u32 b0 = 0; b0 < cnt; b0 += batch) {
                 const u32 nb = std::min(batch, cnt - b0);
-                if (small)
-                    hipLaunchKernelGGL((k_trsm<true, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
+                if (cls == 0)
+                    hipLaunchKernelGGL((k_trsm<0, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
                                        A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
                                        X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)gacc.ptr, Dp, lead_out,
                                        status, ops);
+                else if (cls == 1)
+                    hipLaunchKernelGGL((k_trsm<1, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
+                                       A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
+                                       X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, Dp, lead_out,
+                                       status, ops);
                 else
-                    hipLaunchKernelGGL((k_trsm<false, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
+                    hipLaunchKernelGGL((k_trsm<2, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
                                        A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
                                        X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, Dp, lead_out,
                                        status, ops);

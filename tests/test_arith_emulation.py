@@ -163,3 +163,37 @@ def test_dmod_near_multiples(p):
         x = x[(x >= 0) & (x < 2.0 ** 53)]
         want = np.array([int(v) % p for v in x], dtype=np.float64)
         assert np.array_equal(dmod(x, p), want)
+
+
+# --------------------------------------- folded products of the triangular solve
+# For p = 2^31 - k with k < 2^8, the solve adds fold(t) = k h + l for each
+# product t = h 2^31 + l < 2^62 to a 64-bit accumulator (fold(t) == t mod p,
+# fold(t) < 2^39 + 2^31) and reduces the accumulator once at the end; with at
+# most 2^24 additions the accumulator stays below 2^64.
+
+def fold(t, k):
+    return k * (t >> 31) + (t & 0x7fffffff)
+
+
+@pytest.mark.parametrize("p", [2147483647, 2147483629, 2147483587, 2147483579, 2147483563, 2147483549,
+                               2147483543, 2147483497])
+def test_pseudo_mersenne_fold(p):
+    k = (1 << 31) - p
+    assert 1 <= k < 256
+    rng = np.random.default_rng(k)
+    a = rng.integers(0, p, 500_000, dtype=np.uint64)
+    b = rng.integers(1, p, 500_000, dtype=np.uint64)
+    a[:1000], b[:1000] = p - 1, p - 1  # the largest product
+    t = a * b  # < 2^62: exact in uint64
+    f = fold(t, np.uint64(k))
+    assert int(f.max()) < (1 << 39) + (1 << 31)
+    assert np.array_equal(f % np.uint64(p), t % np.uint64(p))
+    # the accumulator bound: 2^24 additions of the largest fold on top of a residue
+    worst = (p - 1) + (1 << 24) * (k * ((p - 1) * (p - 1) >> 31) + 0x7fffffff)
+    assert worst < 1 << 64
+    # a long accumulation reduced once equals the sum of the exact residues
+    acc = np.uint64(p - 1)
+    chunk = f[:200_000]
+    acc = int(acc) + int(chunk.astype(object).sum())
+    assert acc < 1 << 64
+    assert acc % p == (p - 1 + int((t[:200_000] % np.uint64(p)).astype(object).sum())) % p
