@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void k_tinv(const SegR* segs, const u32* T, u3
 // class needs npiv < 2^24), which costs a multiply-add instead of a full
 // reduction; 2, any other p: Barrett-reduced products into u64.  Systems of
 // another class return at once.
-#define TR_MAXR 4
+#define TR_MAXR 4  // the multipliers of a panel column are one uint4 in LDS
 template <int MODE>
 struct AccOf {
     typedef u64 T;
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
     constexpr bool SMALL = MODE == 0;
     typedef typename AccOf<MODE>::T AccT;
     extern __shared__ unsigned char smraw[];
-    __shared__ u32 s_x[TR_MAXR][PANEL];
+    __shared__ uint4 s_x[PANEL];  // per panel column b: the multipliers -x_b of the tile's rows (0 past nr)
     __shared__ u64 s_xs[2][TR_MAXR][PANEL];  // partial sums of x = l T^-1 (double buffered)
     __shared__ u64 s_hit[TR_MAXR];
     __shared__ u32 s_lead[TR_MAXR];
@@ -324,6 +324,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
     AccT* acc = LDS ? (AccT*)smraw : gacc + ((u64)blockIdx.y * gridDim.x + blockIdx.x) * TR_MAXR * (u64)N;
     for (u32 j = tid; j < nr * N; j += TR_THREADS) acc[j] = 0;
     if (tid < TR_MAXR) s_lead[tid] = 0xffffffffu;
+    if (tid < PANEL) s_x[tid] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const u32* pm = perm + S.cb;
     for (u32 r = 0; r < nr; ++r) {
@@ -389,7 +390,10 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
             const u32 r = wave;
             const u32 x = fp_reduce_any(f, s_xs[buf][r][lane]);
             s_xs[buf][r][lane] = 0;
-            s_x[r][lane] = x ? f.p - x : 0u;  // the multiplier -x, kept as a residue (0: nothing to apply)
+            reinterpret_cast<u32*>(&s_x[lane])[r] = x ? f.p - x : 0u;  // -x as a residue (0: nothing to apply)
+            // with the timing option: the trailing-entry products this row
+            // gets in (C), from the pivot rows' entry counts
+            if (ops && x && lane < wk) nops += tptr[S.pb + qa + lane + 1] - tptr[S.pb + qa + lane];
             const u64 hit = wave_ballot(x != 0);
             if (lane == 0) s_hit[r] = hit;
             if (lane < wk) acc[r * N + qa + lane] = 0;
@@ -405,9 +409,8 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
                     if (!t[k]) continue;  // stored values are nonzero
                     const u32 b = (u32)(t[k] >> 26) & (PANEL - 1), col = (u32)t[k] & 0x3ffffffu;
                     const u32 tv = (u32)(t[k] >> 32);
-                    u32 xs[TR_MAXR];
-#pragma unroll
-                    for (int r = 0; r < TR_MAXR; ++r) xs[r] = (u32)r < nr ? s_x[r][b] : 0u;
+                    const uint4 xv = s_x[b];  // one LDS read for the tile's rows
+                    const u32 xs[TR_MAXR] = {xv.x, xv.y, xv.z, xv.w};
 #pragma unroll
                     for (int r = 0; r < TR_MAXR; ++r) {
                         if (!xs[r]) continue;
@@ -422,7 +425,6 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
                             add = fp_reduce(f, (u64)negx * tv);
                         }
                         atomicAdd(&acc[r * N + col], add);
-                        ++nops;
                     }
                 }
                 const u32 e1 = e0 + TR_THREADS * TR_UNROLL;
