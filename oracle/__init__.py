@@ -10,6 +10,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * O4 ``modloop.py``: the iterated modular update of the arithmetic
   microbenchmark, by ``%``.
 * O5 ``krylov.py``: the block operator application Y = A X / A^T X over F_p.
+* O6 ``wiedemann.py``: block Wiedemann left-kernel vectors (projected Krylov
+  sequence, sigma-basis generator, kernel-vector evaluation).
 
 Each is pinned in ``tests/test_oracle_*.py`` against facts fixed by the paper
 and by mathematics (uniqueness of the reduced Groebner basis, closed forms,
