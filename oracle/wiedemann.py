@@ -22,7 +22,8 @@ references, not its steps):
   shifts (0^b, 1^b): at order k the residual coefficient of every row is
   eliminated row by row in the order of (shift, index), each nonzero row
   pivoting on its first nonzero column and clearing that column from the rows
-  after it, and the pivot rows are then multiplied by x.  A row (g, h) of the
+  after it (fraction-free: row_j <- piv row_j - D_j[c] row_i, no inverses),
+  and the pivot rows are then multiplied by x.  A row (g, h) of the
   result has deg g <= s and deg h < s for its shift s, so f_m = g_{s-m}
   satisfies sum_m S_{t+m} f_m = 0 for t = 0 .. L-1-s: a right generator of
   the sequence.  Rows with g != 0 and 2 s + 2 <= L are kept.
@@ -106,13 +107,15 @@ def mbasis(S, b, p, sigma=None):
             if c is None:
                 continue
             pivots.append(i)
-            inv = pow(D[i][c], p - 2, p)
+            piv = D[i][c]
             for j in order[a + 1:]:
                 if D[j][c]:
-                    f = D[j][c] * inv % p
-                    D[j] = [(x - f * y) % p for x, y in zip(D[j], D[i])]
+                    # fraction-free: row_j <- piv row_j - D_j[c] row_i (a nonzero
+                    # multiple of a row stays an approximant of the same degree)
+                    f = D[j][c]
+                    D[j] = [(piv * x - f * y) % p for x, y in zip(D[j], D[i])]
                     for col in range(m):
-                        P[j][col] = [(x - f * y) % p for x, y in zip(P[j][col], P[i][col])]
+                        P[j][col] = [(piv * x - f * y) % p for x, y in zip(P[j][col], P[i][col])]
         for i in pivots:
             for col in range(m):
                 P[i][col] = [0] + P[i][col][:-1]
