@@ -269,6 +269,54 @@ int f4_spmm(f4_ctx* ctx, uint32_t p, f4_matrix* A, int trans, uint32_t b, const 
  * or a null ms_per_call. */
 int f4_spmm_timed(f4_ctx* ctx, uint32_t p, f4_matrix* A, int trans, uint32_t b, const uint32_t* X, uint32_t* Y,
                   uint32_t reps, double* ms_per_call);
+/* Block Wiedemann over F_p (section "Block Wiedemann and Block Lanczos":
+ * kernel vectors by black-box linear algebra, the block form of Wiedemann's
+ * method; Remark "Syzygies, revisited"): left-kernel vectors v != 0,
+ * v^T A = 0, of the r x N matrix of a handle of one system - by Proposition
+ * "Kernel equals syzygies under dictionary closure" the syzygies among the
+ * shifted reducers - using only products with A and A^T on blocks of b
+ * vectors.  The square operator is B = A D A^T (r x r) for a caller diagonal
+ * d of N nonzero elements (device array); ker A^T is contained in ker B, and
+ * every vector returned is checked against A^T v = 0.  X and Y are device
+ * blocks (r x b, row-major) of random elements: projection and start.
+ * 1 <= b <= F4_BW_MAX_B.  Words of d, X and Y are read modulo p. */
+#define F4_BW_MAX_B 16
+/* The projected block Krylov sequence S_t = X^T B^t (B Y), t = 0 .. L-1, into
+ * S (device, L x b x b, S[t][k][l] at (t b + k) b + l, canonical residues). */
+int f4_bw_sequence(f4_ctx* ctx, uint32_t p, f4_matrix* A, uint32_t b, const uint32_t* d, const uint32_t* X,
+                   const uint32_t* Y, uint32_t L, uint32_t* S, void* stream);
+/* The generator step: an M-Basis sigma-basis, to order L, of the matrix power
+ * series [S(x)^T ; -I_b] (2b x b) with shifts (0^b, 1^b).  At each order the
+ * residual coefficient of every row is eliminated in the order of (shift,
+ * row index): a row whose residual is nonzero pivots on its first nonzero
+ * column and clears it from the later rows fraction-free
+ * (row_j <- piv row_j - r_j row_i); the pivot rows are then multiplied by x
+ * and their shifts raised by one.  Output P (device, 2b x 2b x (L + 2):
+ * coefficient l of entry (i, j) at (i 2b + j)(L + 2) + l) and shifts (device,
+ * 2b).  A row (g, h) with shift s has deg g <= s, deg h < s, and
+ * f_m = g_{s-m} is a right generator of the sequence for t <= L - 1 - s. */
+int f4_bw_mbasis(f4_ctx* ctx, uint32_t p, uint32_t b, uint32_t L, const uint32_t* S, uint32_t* P,
+                 uint32_t* shifts, void* stream);
+typedef struct f4_bw_stats {
+    uint32_t L;            /* sequence length 2 ceil(r / b) + 4 */
+    uint32_t generators;   /* sigma-basis rows used as generators */
+    double t_sequence_ms;  /* host wall time of each phase (device work waited for) */
+    double t_mbasis_ms;
+    double t_vectors_ms;
+} f4_bw_stats;
+/* The whole method on the context's stream: the sequence with
+ * L = 2 ceil(r / b) + 4; the sigma-basis; as generators the rows with g != 0
+ * and 2 s + 2 <= L, in the order of (shift, index); for each, with m0 its
+ * lowest nonzero coefficient, u = sum_{m >= m0} B^(m - m0) Y f_m (Horner, all
+ * generators at once) and the first iterate B^e u (e <= s + 1) that B sends
+ * to zero; kept when A^T v = 0.  V (host, cap x r) receives the vectors found
+ * (vector i at V + i r, canonical residues), *nvec their number (which may
+ * exceed cap; only cap are written).  st may be NULL.  F4_E_ARG: bad p, b,
+ * null arguments, a handle of a batch; F4_E_STATE: a handle not of this
+ * context. */
+int f4_block_wiedemann(f4_ctx* ctx, uint32_t p, f4_matrix* A, uint32_t b, const uint32_t* d, const uint32_t* X,
+                       const uint32_t* Y, uint32_t* V, uint32_t cap, uint32_t* nvec, f4_bw_stats* st);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): f4_spmm on
  * caller CSR arrays, allocating nothing.  A is r x N with row_ptr (r + 1

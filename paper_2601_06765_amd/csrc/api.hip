@@ -1333,6 +1333,178 @@ int f4_spmm(f4_ctx* X, uint32_t p, f4_matrix* A, int trans, uint32_t b, const ui
     F4_API_END(X)
 }
 
+// Block Wiedemann: the handle's CSR and its transpose (built on first use, kept
+// with the handle) and the transpose's values times d (a diagonal of N
+// elements, device).
+static BwCsr bw_prepare(f4_ctx* X, uint32_t p, f4_matrix* A, const uint32_t* d, DBuf<u32>& tval_d) {
+    if (!A || A->owner != X || X->matrices.count(A) == 0) throw F4Error{F4_E_STATE, "unknown matrix handle"};
+    if (A->m.S != 1) throw F4Error{F4_E_ARG, "matrix of a batch"};
+    const SysPart& P = A->m.sys[0];
+    if (P.N && !d) throw F4Error{F4_E_ARG, "null diagonal"};
+    Ctx& c = X->c;
+    if (!A->has_t) {
+        csr_transpose(c, P.r, P.N, P.nnz, A->m.row_ptr.ptr, A->m.col_ind.ptr, A->m.val.ptr, A->t_ptr, A->t_idx,
+                      A->t_val);
+        A->has_t = true;
+    }
+    BwCsr B;
+    B.r = P.r;
+    B.N = P.N;
+    B.nnz = P.nnz;
+    B.ptr = A->m.row_ptr.ptr;
+    B.idx = A->m.col_ind.ptr;
+    B.val = A->m.val.ptr;
+    B.tptr = A->t_ptr.ptr;
+    B.tidx = A->t_idx.ptr;
+    B.tval = A->t_val.ptr;
+    tval_d.reset(&c.pool, std::max<u64>(P.nnz, 1));
+    B.tval_d = tval_d.ptr;
+    bw_scale_transpose(c, p, B, d, tval_d.ptr);
+    return B;
+}
+
+static void bw_check(uint32_t p, uint32_t b, uint32_t L) {
+    if (!is_odd_prime(p) || p >= (1u << 31) || b == 0 || b > F4_BW_MAX_B || L == 0)
+        throw F4Error{F4_E_ARG, "bad argument"};
+}
+
+int f4_bw_sequence(f4_ctx* X, uint32_t p, f4_matrix* A, uint32_t b, const uint32_t* d, const uint32_t* Xp,
+                   const uint32_t* Yp, uint32_t L, uint32_t* S, void* stream) {
+    F4_API_BEGIN(X)
+    bw_check(p, b, L);
+    if (!S || !Xp || !Yp) throw F4Error{F4_E_ARG, "null block"};
+    set_stream(X, stream);
+    DBuf<u32> tvd;
+    const BwCsr B = bw_prepare(X, p, A, d, tvd);
+    bw_sequence(X->c, p, B, b, Xp, Yp, L, S);
+    F4_API_END(X)
+}
+
+int f4_bw_mbasis(f4_ctx* X, uint32_t p, uint32_t b, uint32_t L, const uint32_t* S, uint32_t* P, uint32_t* shifts,
+                 void* stream) {
+    F4_API_BEGIN(X)
+    bw_check(p, b, L);
+    if (!S || !P || !shifts) throw F4Error{F4_E_ARG, "null array"};
+    set_stream(X, stream);
+    bw_mbasis(X->c, p, b, L, S, P, shifts);
+    F4_API_END(X)
+}
+
+int f4_block_wiedemann(f4_ctx* X, uint32_t p, f4_matrix* A, uint32_t b, const uint32_t* d, const uint32_t* Xp,
+                       const uint32_t* Yp, uint32_t* V, uint32_t cap, uint32_t* nvec, f4_bw_stats* st) {
+    F4_API_BEGIN(X)
+    if (!A || A->owner != X || X->matrices.count(A) == 0) throw F4Error{F4_E_STATE, "unknown matrix handle"};
+    if (A->m.S != 1) throw F4Error{F4_E_ARG, "matrix of a batch"};
+    const u32 r = A->m.sys[0].r;
+    const u32 L = 2 * ceil_div(r, std::max<u32>(b, 1)) + 4;
+    bw_check(p, b, L);
+    if (!nvec || !Xp || !Yp || (cap && !V)) throw F4Error{F4_E_ARG, "null argument"};
+    *nvec = 0;
+    set_stream(X, nullptr);
+    Ctx& c = X->c;
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point z) {
+        return std::chrono::duration<double, std::milli>(z - a).count();
+    };
+    const auto t0 = now();
+    DBuf<u32> tvd;
+    const BwCsr B = bw_prepare(X, p, A, d, tvd);
+    const u32 m = 2 * b, W = L + 2;
+    DBuf<u32> S(&c.pool, (u64)L * b * b), P(&c.pool, (u64)m * m * W), sh(&c.pool, m);
+    bw_sequence(c, p, B, b, Xp, Yp, L, S.ptr);
+    F4_HIP_TRY(hipStreamSynchronize(c.stream));
+    const auto t1 = now();
+    bw_mbasis(c, p, b, L, S.ptr, P.ptr, sh.ptr);
+    std::vector<u32> hP((u64)m * m * W), hs(m);
+    F4_HIP_TRY(hipMemcpyAsync(hP.data(), P.ptr, hP.size() * 4, hipMemcpyDeviceToHost, c.stream));
+    F4_HIP_TRY(hipMemcpyAsync(hs.data(), sh.ptr, m * 4, hipMemcpyDeviceToHost, c.stream));
+    F4_HIP_TRY(hipStreamSynchronize(c.stream));
+    const auto t2 = now();
+    // generators: rows (g, h) with g != 0 and 2 s + 2 <= L, in the order of
+    // (shift, index); f_m = g_{s - m}, shifted down past its zero low
+    // coefficients (m0), so column j evaluates sum_m B^m Y f_{m + m0}
+    std::vector<u32> rows(m);
+    for (u32 i = 0; i < m; ++i) rows[i] = i;
+    std::stable_sort(rows.begin(), rows.end(), [&](u32 a, u32 z) { return hs[a] < hs[z]; });
+    struct Gen {
+        u32 s, m0;
+        std::vector<u32> f;  // (s + 1) x b: f[m * b + k] = g_k at s - m
+    };
+    std::vector<Gen> gens;
+    for (u32 i : rows) {
+        const u32 sdeg = hs[i];
+        if (2 * (u64)sdeg + 2 > L) continue;
+        Gen g;
+        g.s = sdeg;
+        g.f.assign((u64)(sdeg + 1) * b, 0);
+        bool any = false;
+        for (u32 mm = 0; mm <= sdeg; ++mm)
+            for (u32 k = 0; k < b; ++k) {
+                const u32 v = hP[((u64)i * m + k) * W + (sdeg - mm)];
+                g.f[(u64)mm * b + k] = v;
+                any = any || v;
+            }
+        if (!any) continue;
+        g.m0 = 0;
+        while (g.m0 <= sdeg) {
+            bool nz = false;
+            for (u32 k = 0; k < b; ++k) nz = nz || g.f[(u64)g.m0 * b + k];
+            if (nz) break;
+            ++g.m0;
+        }
+        gens.push_back(std::move(g));
+    }
+    const u32 w = (u32)gens.size();
+    u32 found = 0;
+    if (w) {
+        u32 Dmax = 0, smax = 0;
+        for (const Gen& g : gens) {
+            Dmax = std::max(Dmax, g.s - g.m0);
+            smax = std::max(smax, g.s);
+        }
+        const u32 E = smax + 3;  // iterates v_0 .. v_{s+2}: the first zero one is at most v_{s+2}
+        std::vector<u32> hF((u64)(Dmax + 1) * b * w, 0);
+        for (u32 j = 0; j < w; ++j) {
+            const Gen& g = gens[j];
+            for (u32 mm = 0; mm + g.m0 <= g.s; ++mm)
+                for (u32 k = 0; k < b; ++k) hF[((u64)mm * b + k) * w + j] = g.f[(u64)(mm + g.m0) * b + k];
+        }
+        DBuf<u32> F(&c.pool, hF.size()), K(&c.pool, std::max<u64>((u64)r * w, 1)), nzh(&c.pool, (u64)E * w),
+            nzc(&c.pool, w);
+        F4_HIP_TRY(hipMemcpyAsync(F.ptr, hF.data(), hF.size() * 4, hipMemcpyHostToDevice, c.stream));
+        bw_kernel_vectors(c, p, B, b, Yp, w, Dmax, F.ptr, E, K.ptr, nzh.ptr, nzc.ptr);
+        std::vector<u32> hK((u64)r * w), hz((u64)E * w), hc(w);
+        F4_HIP_TRY(hipMemcpyAsync(hK.data(), K.ptr, hK.size() * 4, hipMemcpyDeviceToHost, c.stream));
+        F4_HIP_TRY(hipMemcpyAsync(hz.data(), nzh.ptr, hz.size() * 4, hipMemcpyDeviceToHost, c.stream));
+        F4_HIP_TRY(hipMemcpyAsync(hc.data(), nzc.ptr, w * 4, hipMemcpyDeviceToHost, c.stream));
+        F4_HIP_TRY(hipStreamSynchronize(c.stream));
+        for (u32 j = 0; j < w; ++j) {
+            // first zero iterate: the one before it is in ker B
+            u32 z = E;
+            for (u32 e = 0; e < E; ++e)
+                if (!hz[(u64)e * w + j]) {
+                    z = e;
+                    break;
+                }
+            if (z == 0 || z > gens[j].s + 2 || z == E) continue;
+            if (hc[j]) continue;  // in ker B but A^T v != 0: not a syzygy
+            if (found < cap)
+                for (u32 g = 0; g < r; ++g) V[(u64)found * r + g] = hK[(u64)g * w + j];
+            ++found;
+        }
+    }
+    const auto t3 = now();
+    *nvec = found;
+    if (st) {
+        st->L = L;
+        st->generators = w;
+        st->t_sequence_ms = ms(t0, t1);
+        st->t_mbasis_ms = ms(t1, t2);
+        st->t_vectors_ms = ms(t2, t3);
+    }
+    F4_API_END(X)
+}
+
 int f4_spmm_noalloc(f4_ctx* X, uint32_t p, uint32_t r, uint32_t N, uint64_t nnz, const uint32_t* row_ptr,
                     const uint32_t* col_ind, const uint32_t* val, int trans, uint32_t b, const uint32_t* Xin,
                     uint32_t* Y, void* stream) {

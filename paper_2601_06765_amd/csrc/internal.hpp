@@ -239,6 +239,29 @@ void csr_transpose(Ctx& c, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const 
 u64 csr_transpose_ws_words(u32 ncols);
 void csr_transpose_into(hipStream_t s, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx,
                         const u32* val, u32* tptr, u32* tidx, u32* tval, u32* ws);
+// Block Wiedemann (wiedemann.hip).  The matrix A (r x N) as CSR, its
+// transpose's CSR, and the transpose's values times D (the diagonal of the
+// operator B = A D A^T).
+struct BwCsr {
+    u32 r = 0, N = 0;
+    u64 nnz = 0;
+    const u32 *ptr = nullptr, *idx = nullptr, *val = nullptr;
+    const u32 *tptr = nullptr, *tidx = nullptr, *tval = nullptr;
+    const u32* tval_d = nullptr;
+};
+// tval_d = the transpose's values of row j times d[j]
+void bw_scale_transpose(Ctx& c, u32 p, const BwCsr& A, const u32* d, u32* tval_d);
+// S_t = X^T B^t (B Y), t < L: S (L x b x b, device)
+void bw_sequence(Ctx& c, u32 p, const BwCsr& A, u32 b, const u32* X, const u32* Y, u32 L, u32* S);
+// M-Basis of [S(x)^T ; -I_b] to order L: P (2b x 2b x (L + 2), device), shifts (2b, device)
+void bw_mbasis(Ctx& c, u32 p, u32 b, u32 L, const u32* S, u32* P, u32* shifts);
+// For w generator columns (F: (Dmax + 1) x b x w, coefficients of B^m Y):
+// K = sum_m B^m Y F_m by Horner, then the iterates B^e K for e < E with their
+// nonzero-column flags (nzhist, E x w); K ends as each column's last nonzero
+// iterate; nzcheck (w) flags the columns with A^T K != 0.
+void bw_kernel_vectors(Ctx& c, u32 p, const BwCsr& A, u32 b, const u32* Y, u32 w, u32 Dmax, const u32* F, u32 E,
+                       u32* K, u32* nzhist, u32* nzcheck);
+
 // Allocation-free block products (f4_spmm_noalloc): the device address of
 // the file-scope scratch array is looked up once per device (call with that
 // device current); spmm_noalloc_words gives the scratch a product needs (the

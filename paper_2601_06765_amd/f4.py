@@ -128,6 +128,16 @@ _sig("f4_upload", c_int, [c_vp, c_vp, c_vp, ctypes.c_size_t])
 _sig("f4_modloop", c_int, [c_vp, c_u32, c_u32, c_u32, c_u32, P(c_u32), P(c_u32), P(c_u32), P(c_u32),
                            P(ModloopStats)])
 
+class BwStats(ctypes.Structure):
+    _fields_ = [("L", c_u32), ("generators", c_u32), ("t_sequence_ms", ctypes.c_double),
+                ("t_mbasis_ms", ctypes.c_double), ("t_vectors_ms", ctypes.c_double)]
+
+
+_sig("f4_bw_sequence", c_int, [c_vp, c_u32, c_vp, c_u32, c_vp, c_vp, c_vp, c_u32, c_vp, c_vp])
+_sig("f4_bw_mbasis", c_int, [c_vp, c_u32, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp])
+_sig("f4_block_wiedemann", c_int, [c_vp, c_u32, c_vp, c_u32, c_vp, c_vp, c_vp, P(c_u32), c_u32, P(c_u32),
+                                   P(BwStats)])
+
 MODLOOP_FORMS = {"mul24": 0, "barrett32": 1, "barrett64": 2, "montgomery": 3}
 
 
@@ -499,6 +509,48 @@ class Context:
         self._check(_lib.f4_spmm_timed(self._h, p, A._h, 1 if trans else 0, b, c_vp(X.ptr), c_vp(out.ptr), reps,
                                        ctypes.byref(ms)))
         return out, ms.value
+
+    def bw_sequence(self, p, A, d, X, Y, L):
+        """Projected block Krylov sequence S_t = X^T B^t (B Y), B = A D A^T
+        (f4_bw_sequence); d, X, Y are DeviceArrays.  Returns an L x b x b array."""
+        b = X.shape[1]
+        S = DeviceArray(self, (L, b, b))
+        try:
+            self._check(_lib.f4_bw_sequence(self._h, p, A._h, b, c_vp(d.ptr), c_vp(X.ptr), c_vp(Y.ptr), L,
+                                            c_vp(S.ptr), None))
+            return S.to_host().astype(np.int64)
+        finally:
+            S.free()
+
+    def bw_mbasis(self, p, b, S):
+        """Sigma-basis of [S(x)^T ; -I_b] to order L = len(S) (f4_bw_mbasis).
+        Returns (P, shifts): P[i, j, l] is coefficient l of entry (i, j)."""
+        S = np.asarray(S)
+        L = S.shape[0]
+        Sd = self.to_device(S.reshape(-1))
+        Pd = DeviceArray(self, (2 * b, 2 * b, L + 2))
+        sd = DeviceArray(self, (2 * b,))
+        try:
+            self._check(_lib.f4_bw_mbasis(self._h, p, b, L, c_vp(Sd.ptr), c_vp(Pd.ptr), c_vp(sd.ptr), None))
+            return Pd.to_host().astype(np.int64), [int(x) for x in sd.to_host()]
+        finally:
+            for a in (Sd, Pd, sd):
+                a.free()
+
+    def block_wiedemann(self, p, A, d, X, Y):
+        """Left-kernel vectors of A by block Wiedemann (f4_block_wiedemann);
+        returns (list of vectors as int64 arrays of length r, stats dict)."""
+        b = X.shape[1]
+        r = A.view.r
+        cap = 2 * b
+        V = np.zeros(max(1, cap * r), dtype=np.uint32)
+        n = c_u32(0)
+        st = BwStats()
+        self._check(_lib.f4_block_wiedemann(self._h, p, A._h, b, c_vp(d.ptr), c_vp(X.ptr), c_vp(Y.ptr),
+                                            V.ctypes.data_as(P(c_u32)), cap, ctypes.byref(n), ctypes.byref(st)))
+        vecs = [V[i * r:(i + 1) * r].astype(np.int64) for i in range(min(n.value, cap))]
+        return vecs, {"L": st.L, "generators": st.generators, "t_sequence_ms": st.t_sequence_ms,
+                      "t_mbasis_ms": st.t_mbasis_ms, "t_vectors_ms": st.t_vectors_ms}
 
     def matrix_from_csr(self, r, N, row_ptr, col_ind, val, stream=None):
         rp = np.ascontiguousarray(row_ptr, dtype=np.uint32)
