@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--modloop-iters", type=int, default=4096)
     ap.add_argument("--spmm-shift-deg", type=int, default=8,
                     help="shift degree of the Macaulay operator of the SpMM leg (0: skip)")
+    ap.add_argument("--wiedemann-shift-deg", type=int, default=3,
+                    help="shift degree of the Macaulay matrix of the block Wiedemann leg (-1: skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed schedules instead of the autotuner's measured picks (tuned during warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -340,6 +342,42 @@ def spmm_leg(f4, shift_deg, b, reps):
     return res
 
 
+def wiedemann_leg(f4, shift_deg, b):
+    """Block Wiedemann (left-kernel vectors = syzygies) on the Macaulay matrix of
+    workload 3's input at degree shift_deg + 2: rows t*f_i for every monomial t
+    of degree <= shift_deg and each of the 15 sparse quadratics over
+    F_(2^31-1), built by the symbolic preprocessing; the diagonal D and the
+    blocks X, Y from splitmix64 (seed 6).  Reports the three phases' times
+    and the vectors found (each checked on the device against A^T v = 0)."""
+    import numpy as np
+    import synth
+    n, p, polys = synth.config_system(3)
+    polys = f4.normalize(p, n, polys)
+    t = f4.pack_many(n, synth.monomials_upto(n, shift_deg))
+    tw, ks = np.repeat(t, len(polys)), np.tile(np.arange(len(polys), dtype=np.uint32), len(t))
+    ctx = f4.Context(0)
+    A = ctx.build_matrix_rows_packed(p, n, polys, tw, ks)
+    r, N, nnz = A.view.r, A.view.N, A.view.nnz
+    d = ctx.to_device(synth.residues(p, N, 6 * 2**32 + 0) % (p - 1) + 1)
+    X = ctx.to_device(synth.residues(p, r * b, 6 * 2**32 + 1).reshape(r, b))
+    Y = ctx.to_device(synth.residues(p, r * b, 6 * 2**32 + 2).reshape(r, b))
+    ctx.block_wiedemann(p, A, d, X, Y)  # warm-up (transpose, code objects)
+    t0 = time.perf_counter()
+    vecs, st = ctx.block_wiedemann(p, A, d, X, Y)
+    wall = time.perf_counter() - t0
+    for a in (d, X, Y, A):
+        a.free()
+    ctx.close()
+    L = st["L"]
+    # each sequence term applies A^T and A to b vectors: 2 nnz b products
+    return {"workload": "degree-%d Macaulay matrix of the n=14 sparse quadratics (F_(2^31-1)): r = %d, N = %d, "
+                        "%d nonzeros; b = %d" % (shift_deg + 2, r, N, nnz, b),
+            "r": r, "N": N, "nnz": nnz, "b": b, "L": L, "generators": st["generators"], "vectors": len(vecs),
+            "wall_ms": round(wall * 1e3, 2), "t_sequence_ms": round(st["t_sequence_ms"], 2),
+            "t_mbasis_ms": round(st["t_mbasis_ms"], 2), "t_vectors_ms": round(st["t_vectors_ms"], 2),
+            "sequence_entry_vector_products_per_s": 2.0 * nnz * b * L / (st["t_sequence_ms"] * 1e-3)}
+
+
 def modloop_leg(f4, nchains, iters):
     """Modular inner-loop microbenchmark (randomized residues, seed 5): the
     update rate of each arithmetic form, its registers and spill bytes per
@@ -534,6 +572,8 @@ def main():
             out["full_f4_n10"] = full_f4_leg(f4, torch, args.full_runs, args.warmup, tune, args.dict)
         if args.spmm_shift_deg:
             out["spmm"] = spmm_leg(f4, args.spmm_shift_deg, 8, 20)
+        if args.wiedemann_shift_deg >= 0:
+            out["block_wiedemann"] = wiedemann_leg(f4, args.wiedemann_shift_deg, 8)
         if args.batch_systems:
             out["batch"] = batch_leg(f4, torch, args.batch_systems, tune)
             out["systems_per_s_batched"] = out["batch"]["systems_per_s_batched"]
