@@ -1212,6 +1212,59 @@ int f4_build_matrix(f4_ctx* X, uint32_t p, const f4_polys* G, const uint8_t* act
     F4_API_END(X)
 }
 
+// Device planning of an explicit row list (f4_build_matrix_rows): checks of
+// every (t, k), the largest row degree, then the distinct rows by sorting the
+// keys rank(t) npolys + k (rank: the dense grevlex rank of t among the
+// monomials up to the largest shift degree) and dropping repeats.
+// info: [0] error bits (1 bad index or shift word, 2 lane overflow),
+// [1] largest degree of t LM(g_k), [2] largest degree of t.
+__global__ void k_rows_check(const f4_rowspec* __restrict__ R, u32 r, const u64* __restrict__ lm, u32 npolys,
+                             u32 n, u32 w, u32* info) {
+    u32 err = 0, dmax = 0, tmax = 0;
+    const u64 lanes = (1ull << (n * w)) - 1;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x) {
+        const u64 t = R[i].t;
+        const u32 k = R[i].k;
+        u32 sum = 0;
+        for (u32 v = 0; v < n; ++v) sum += mono_exp(t, v, w);
+        if (k >= npolys || (t & ~lanes & ((1ull << 56) - 1)) || sum != mono_deg(t)) {
+            err |= 1;
+            continue;
+        }
+        const u64 g = lm[k];
+        for (u32 v = 0; v < n; ++v)
+            if (mono_exp(t, v, w) + mono_exp(g, v, w) >= (1u << w)) err |= 2;
+        dmax = max(dmax, mono_deg(t) + mono_deg(g));
+        tmax = max(tmax, mono_deg(t));
+    }
+    for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) {
+        err |= (u32)__shfl_xor((int)err, (int)d, F4_WAVE);
+        dmax = max(dmax, (u32)__shfl_xor((int)dmax, (int)d, F4_WAVE));
+        tmax = max(tmax, (u32)__shfl_xor((int)tmax, (int)d, F4_WAVE));
+    }
+    if (lane_id() == 0) {
+        if (err) atomicOr(&info[0], err);
+        atomicMax(&info[1], dmax);
+        atomicMax(&info[2], tmax);
+    }
+}
+
+__global__ void k_rows_keys(const f4_rowspec* __restrict__ R, u32 r, u32 n, u32 w, u32 Dt, const u32* __restrict__ B,
+                            u32 npolys, u64* __restrict__ keys) {
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x)
+        keys[i] = (u64)mono_rank(R[i].t, n, w, Dt, B) * npolys + R[i].k;
+}
+
+__global__ void k_rows_decode(const u64* __restrict__ keys, const u32* __restrict__ cnt, u32 npolys,
+                              const u64* __restrict__ montab, u64* __restrict__ rows_t, u32* __restrict__ rows_k) {
+    const u32 m = *cnt;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        const u64 key = keys[i];
+        rows_t[i] = montab[key / npolys];
+        rows_k[i] = (u32)(key % npolys);
+    }
+}
+
 int f4_build_matrix_rows(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_rowspec* R, uint32_t r, f4_matrix** A,
                          void* stream) {
     F4_API_BEGIN(X)
@@ -1219,32 +1272,58 @@ int f4_build_matrix_rows(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_rows
     *A = nullptr;
     set_stream(X, stream);
     Ctx& c = X->c;
+    hipStream_t s = c.stream;
     DevG D;
     load_polys(c, p, G, D, false);
-    std::vector<u64> lm(D.npolys);
-    readback(c, lm.data(), D.lm.ptr, (u64)D.npolys * 8);
+    if (D.npolys == 0) throw F4Error{F4_E_ARG, "row basis index out of range"};
     const u32 w = lane_bits(D.n);
-    std::vector<std::pair<u64, u32>> rows;
-    u32 deg = 0;
-    for (u32 i = 0; i < r; ++i) {
-        if (R[i].k >= D.npolys) throw F4Error{F4_E_ARG, "row basis index out of range"};
-        // t * LM(g): every lane must stay below 2^w
-        for (u32 v = 0; v < D.n; ++v)
-            if (mono_exp(R[i].t, v, w) + mono_exp(lm[R[i].k], v, w) >= (1u << w))
-                throw F4Error{F4_E_RANGE, "exponent lane overflow"};
-        deg = std::max(deg, deg_of(R[i].t + lm[R[i].k]));
-        rows.push_back({R[i].t, R[i].k});
-    }
+    // the row list on the device, checked there
+    DBuf<u8> Rd(&c.pool, (u64)r * sizeof(f4_rowspec));
+    upload(c, Rd.ptr, R, (u64)r * sizeof(f4_rowspec));
+    const f4_rowspec* Rdev = (const f4_rowspec*)Rd.ptr;
+    DBuf<u32> info(&c.pool, 4);
+    fill_u32(info.ptr, 4, 0, s);
+    const u32 grid = std::min<u32>(4096, ceil_div(r, 256));
+    hipLaunchKernelGGL(k_rows_check, dim3(grid), dim3(256), 0, s, Rdev, r, D.lm.ptr, D.npolys, D.n, w, info.ptr);
+    F4_LAUNCH_CHECK();
+    u32 hi[4];
+    readback(c, hi, info.ptr, 16);
+    if (hi[0] & 1) throw F4Error{F4_E_ARG, "row basis index out of range or shift not a monomial"};
+    if (hi[0] & 2) throw F4Error{F4_E_RANGE, "exponent lane overflow"};
+    const u32 deg = hi[1], Dt = hi[2];
     if (deg >= (1u << w)) throw F4Error{F4_E_RANGE, "degree overflows an exponent lane"};
-    SysState st;
-    st.D = std::move(D);
-    st.d = deg;
-    prepare_rows(st, rows);
-    st.act.clear();
+    const u64 nt = binom_host(D.n + Dt, D.n);
+    if (nt * D.npolys >= (1ull << 63)) throw F4Error{F4_E_RANGE, "row keys do not fit 64 bits"};
+    // distinct rows: sort the keys, drop repeats, decode
+    const u32* B = rank_table(c, D.n, Dt);
+    const u64* montab = unrank_table(c, D.n, Dt);
+    DBuf<u64> keys(&c.pool, r), ukeys(&c.pool, r);
+    DBuf<u32> cnt(&c.pool, 1);
+    hipLaunchKernelGGL(k_rows_keys, dim3(grid), dim3(256), 0, s, Rdev, r, D.n, w, Dt, B, D.npolys, keys.ptr);
+    F4_LAUNCH_CHECK();
+    u32 bits = 1;
+    while (bits < 64 && (nt * D.npolys - 1) >> bits) ++bits;
+    radix_sort_keys(keys.ptr, r, 0, bits, c.pool, s);
+    unique_sorted_u64(keys.ptr, r, ukeys.ptr, cnt.ptr, c.pool, s);
+    u32 r0 = 0;
+    readback(c, &r0, cnt.ptr, 4);
+    DBuf<u64> rt(&c.pool, std::max<u32>(r0, 1));
+    DBuf<u32> rk(&c.pool, std::max<u32>(r0, 1));
+    hipLaunchKernelGGL(k_rows_decode, dim3(std::min<u32>(4096, ceil_div(r0, 256))), dim3(256), 0, s, ukeys.ptr,
+                       cnt.ptr, D.npolys, montab, rt.ptr, rk.ptr);
+    F4_LAUNCH_CHECK();
+    BuildArgs a;
+    a.G = devg_view(D);
+    a.rows_t_dev = rt.ptr;
+    a.rows_k_dev = rk.ptr;
+    a.r0 = r0;
+    a.nactive = 0;
+    a.D = deg;
+    a.closure = false;
     f4_matrix* M = new f4_matrix();
     M->owner = X;
     try {
-        build_batch(c, std::vector<BuildArgs>{args_of(st, false)}, M->m);
+        build_batch(c, std::vector<BuildArgs>{a}, M->m);
         M->m.built_p = p;
     } catch (...) {
         delete M;

@@ -711,7 +711,9 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
 
     // descriptors, active lists, initial rows and counters: one upload
     u64 I = 0;
-    for (u32 i = 0; i < S; ++i) I += args[i].r0;
+    for (u32 i = 0; i < S; ++i) I += args[i].rows_t_dev ? 0 : args[i].r0;
+    const bool dev_rows = args[0].rows_t_dev != nullptr;
+    if (dev_rows && S != 1) throw F4Error{1, "device row lists are for one system"};
     std::vector<u8> pack;
     auto put = [&](const void* src, size_t bytes) {
         const size_t off = (pack.size() + 255) & ~(size_t)255;
@@ -725,7 +727,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     const size_t o_act = put(actv.data(), actv.size() * 4);
     const size_t o_ctr = put(hc.data(), hc.size() * 4);
     const size_t o_t0 = put(nullptr, I * 8), o_k0 = put(nullptr, I * 4);
-    for (u32 i = 0; i < S; ++i) {
+    for (u32 i = 0; i < S && !dev_rows; ++i) {
         const BuildArgs& a = args[i];
         std::memcpy(pack.data() + o_t0 + (size_t)segs[i].ibase * 8, a.rows_t_host, (size_t)a.r0 * 8);
         std::memcpy(pack.data() + o_k0 + (size_t)segs[i].ibase * 4, a.rows_k_host, (size_t)a.r0 * 4);
@@ -746,9 +748,10 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     {
         u32 mr = 1;
         for (u32 i = 0; i < S; ++i) mr = std::max(mr, std::max(args[i].r0, segs[i].nwords));
-        hipLaunchKernelGGL(k_init_rows, dim3(std::min<u32>(64, ceil_div(mr, 256)), S), dim3(256), 0, s, dsegs,
-                           (const u64*)(params.ptr + o_t0), (const u32*)(params.ptr + o_k0), rows_t.ptr, rows_k.ptr,
-                           pd.ptr, (u32)W, Mdev.ptr);
+        const u64* t0 = dev_rows ? args[0].rows_t_dev : (const u64*)(params.ptr + o_t0);
+        const u32* k0 = dev_rows ? args[0].rows_k_dev : (const u32*)(params.ptr + o_k0);
+        hipLaunchKernelGGL(k_init_rows, dim3(std::min<u32>(dev_rows ? 4096 : 64, ceil_div(mr, 256)), S), dim3(256), 0,
+                           s, dsegs, t0, k0, rows_t.ptr, rows_k.ptr, pd.ptr, (u32)W, Mdev.ptr);
         F4_LAUNCH_CHECK();
     }
 

@@ -351,6 +351,8 @@ struct BuildArgs {
     DevBasis G;
     const u64* rows_t_host = nullptr;  // r0 initial rows (distinct (t, k)), host
     const u32* rows_k_host = nullptr;
+    const u64* rows_t_dev = nullptr;   // or on the device (a batch of one system only)
+    const u32* rows_k_dev = nullptr;
     u32 r0 = 0;
     const u32* active_host = nullptr;  // active basis indices in descending order, host
     u32 nactive = 0;

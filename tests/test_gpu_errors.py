@@ -105,6 +105,32 @@ def test_build_rows_rejects_unsorted(f4, ctx):
     assert A["nnz"] == 2 and A["val"].tolist() == [5, 1]
 
 
+def test_build_rows_checks_rows_on_device(f4, ctx):
+    import numpy as np
+    n, p = 4, 65521
+    G = f4.normalize(p, n, [[((0, 1, 0, 0), 1), ((0, 0, 0, 1), 3)], [((1, 0, 0, 0), 1), ((0, 0, 0, 0), 2)]])
+    t_ok = f4.pack(n, (0, 0, 1, 0))
+    say("build_matrix_rows: basis index out of range")
+    with pytest.raises(f4.F4Error) as e:
+        ctx.build_matrix_rows_packed(p, n, G, np.array([t_ok, t_ok], dtype=np.uint64), np.array([0, 2]))
+    assert e.value.code == f4.F4_E_ARG
+    say("build_matrix_rows: a shift word whose lanes do not add up to its degree")
+    bad = (1 << 56) | f4.pack(n, (0, 0, 2, 0))  # degree field 1 + 2 = 3, lanes 2
+    with pytest.raises(f4.F4Error) as e:
+        ctx.build_matrix_rows_packed(p, n, G, np.array([bad], dtype=np.uint64), np.array([0]))
+    assert e.value.code == f4.F4_E_ARG
+    say("build_matrix_rows: exponent lane overflow")
+    w = f4.lane_bits(n)
+    big = f4.pack(n, (0, (1 << w) - 1, 0, 0))  # times x2 overflows the lane
+    with pytest.raises(f4.F4Error) as e:
+        ctx.build_matrix_rows_packed(p, n, G, np.array([big], dtype=np.uint64), np.array([0]))
+    assert e.value.code == f4.F4_E_RANGE
+    say("build_matrix_rows: repeated rows collapse, context still usable")
+    ts = np.array([t_ok, t_ok, f4.pack(n, (0, 0, 0, 0)), t_ok], dtype=np.uint64)
+    A = ctx.build_matrix_rows_packed(p, n, G, ts, np.array([1, 1, 0, 0])).to_host()
+    assert A["r"] == 3 and A["nnz"] == 6
+
+
 def test_reduce_rejects_values_not_residues(f4, ctx):
     p = 65521
     rp = [0, 2, 3]
