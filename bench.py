@@ -33,6 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # derived modular-product bound: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer
 # issue, at least two instructions (a multiply and an add) per modular product
 MODMUL_PEAK = 256 * 4 * 16 * 2.4e9 / 2
+VALU_ISSUE = 256 * 4 * 16 * 2.4e9  # vector lane-instructions per second
 STEP_DEG = 5  # the timed step of the headline workload
 
 
@@ -128,14 +129,29 @@ def step_bytes(s):
     return build, reduce, trsm
 
 
-def roofline_of(kstats, step, e3_peak):
+def trsm_instr_per_product(p):
+    """Fewest vector instructions per modular product of the triangular
+    solve's arithmetic class: p < 2^16, the one-word Barrett product (multiply,
+    high multiply, multiply, subtract, min: 5); p = 2^31 - k with k < 2^8, the
+    fold k h + l of the 64-bit product (low and high multiply, shift, mask,
+    multiply-add: 5); any other p, the two-word Barrett product (12)."""
+    if p < 65536:
+        return 5
+    if p > (1 << 31) - 256:
+        return 5
+    return 12
+
+
+def roofline_of(kstats, step, e3_peak, p):
     """Roofline of the dominant elimination kernel of the timed step (largest
     summed launch time, HIP events around each launch on the library's stream).
-    Triangular solve: bound by HBM; achieved = its algorithmic bytes (the CSR
-    read once, D' written once) / its launch time.  Echelon block step: bound by
-    integer vector arithmetic; achieved = its modular products / its launch
-    time, against the modular-product peak the inner-loop microbenchmark
-    measures for the kernel's arithmetic form."""
+    Both candidates are bound by vector-integer arithmetic (their algorithmic
+    bytes are far below what HBM moves in their time).  Triangular solve:
+    achieved = its modular products / its launch time, against the integer
+    issue rate divided by the fewest instructions per product of its
+    arithmetic class (its HBM view, algorithmic bytes over time, is reported
+    beside it).  Echelon block step: the same products against the rate the
+    inner-loop microbenchmark measures for its arithmetic form."""
     cand = {
         "k_trsm": (sum(s["t_k_trsm_ms"] for s in kstats), sum(s["trsm_ops"] for s in kstats),
                    sum(s["n_k_trsm"] for s in kstats)),
@@ -152,12 +168,23 @@ def roofline_of(kstats, step, e3_peak):
                  "Tmodmul_per_s": round(v[1] / (v[0] / 1e3) / 1e12, 4) if v[0] else None}
              for k, v in cand.items()}
     if name == "k_trsm":
+        # bound by vector-integer issue (the counters show the vector ALUs busy
+        # most of the kernel): achieved = its modular products / its launch time,
+        # against the issue rate of the fewest instructions its arithmetic class
+        # needs per product
         _, _, tb = step_bytes(step)
         byts = tb / max(1, launches / runs)
-        achieved = byts / (per / 1e3) / 1e9
-        return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic, "kernel": name,
-                "alg_bytes_per_launch": byts, "ms_per_launch": round(per, 5), "kernels": other}
+        achieved = ops / (ms / 1e3) / 1e12 if ms > 0 else 0.0
+        ipp = trsm_instr_per_product(p)
+        peak = VALU_ISSUE / ipp / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4), "unit": "Tmodmul/s",
+                "frac": round(achieved / peak, 5), "traffic": traffic, "kernel": name,
+                "peak_source": "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer issue / %d instructions per "
+                               "product (the arithmetic class of the solve for this p)" % ipp,
+                "ops_per_launch": ops / max(1, launches), "ms_per_launch": round(per, 5),
+                "hbm_view": {"alg_bytes_per_launch": byts, "achieved_GBs": round(byts / (per / 1e3) / 1e9, 2),
+                             "frac_of_8TBs": round(byts / (per / 1e3) / 1e9 / HBM_PEAK_GBS, 6)},
+                "kernels": other}
     achieved = ops / (ms / 1e3) / 1e12 if ms > 0 else 0.0
     return {"bound": "alu", "achieved": round(achieved, 5), "peak": e3_peak, "unit": "Tmodmul/s",
             "frac": round(achieved / e3_peak, 6) if e3_peak else None, "traffic": traffic, "kernel": name,
@@ -566,7 +593,7 @@ def main():
         # the echelon's large-prime form (two-word Barrett) at the workload's prime
         f = [x for x in out["modloop"]["forms"] if x["form"] == "barrett64" and x["p"] == h["p"]]
         e3 = round(f[0]["updates_per_s"] / 1e12, 4) if f else None
-    out["roofline"] = roofline_of(h["kstats"], s, e3)
+    out["roofline"] = roofline_of(h["kstats"], s, e3, h["p"])
     if not args.step_only:
         if args.full_runs:
             out["full_f4_n10"] = full_f4_leg(f4, torch, args.full_runs, args.warmup, tune, args.dict)
