@@ -814,7 +814,7 @@ __device__ __forceinline__ double dmod(double x, double pd, double pinv) {
 // coefficients - and are cleared by k_ech_lead afterwards.  Columns left of
 // the round's first pivot column are unchanged (the block rows are zero
 // there), except in new pivot rows, which are written whole.
-#define ECH_RT 16
+#define ECH_RT 32
 #define ECH_CT 256
 #define ECH_SPAN_MAX 1024  // most columns of one tile (passes of ECH_CT columns)
 #define ECH_SHORT 1024     // rows of at most this many trailing columns use the per-row update forms
