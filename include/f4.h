@@ -69,8 +69,11 @@ enum {
     F4_OPT_DICT_RANK = 1u << 1,  /* force the dense-rank dictionary (bitmap sort/unique) */
     F4_OPT_DICT_RADIX = 1u << 2, /* force the radix-sort dictionary (sort + unique + join) */
     F4_OPT_AUTOTUNE = 1u << 3,   /* pick schedules by measurement (see f4_tune_export) */
-    F4_OPT_KERNEL_TIMING = 1u << 4 /* also HIP events around every launch of the triangular-solve
+    F4_OPT_KERNEL_TIMING = 1u << 4, /* also HIP events around every launch of the triangular-solve
                                       and echelon block-step kernels, and their product counts */
+    F4_OPT_HOST_PAIRS = 1u << 5   /* keep pair sets and activity flags on the host (the
+                                      Gebauer-Moeller update and the normal selection in host
+                                      code) instead of on the device; same results */
 };
 typedef struct f4_opts {
     uint32_t flags;
@@ -382,7 +385,10 @@ typedef struct f4_step_stats {
     float t_trsm_ms;      /* of which the sparse triangular solve */
     float t_echelon_ms;   /* of which the trailing-block echelon */
     float t_step_ms;      /* host wall time of the whole step */
-    float t_pairs_ms;     /* host time of pair selection and Gebauer-Moeller updates */
+    float t_pairs_ms;     /* pair selection and Gebauer-Moeller update of the step: device
+                             pair sets - HIP events with F4_OPT_TIMING (for a batch, the
+                             batch's launches), else host wall time of the calls including
+                             the wait for the summary; host pair sets - host time */
     /* per kernel (F4_OPT_KERNEL_TIMING only; for a batch, the batch's launches):
      * the triangular-solve kernel and the echelon block-step kernel, summed
      * over their launches (HIP events around each launch on the call's
@@ -399,7 +405,11 @@ typedef struct f4_step_stats {
 
 /* Reduced Groebner basis of <F> under grevlex (unique: monic, minimal,
  * inter-reduced), computed by F4 with the Gebauer-Moeller pair update and the
- * normal selection strategy.  F: host SoA polynomials (any coefficients < p,
+ * normal selection strategy (section "Pair management and the normal
+ * strategy"; both on the device unless F4_OPT_HOST_PAIRS is set: the pair set
+ * and the activity flags then never leave the device between steps, and the
+ * halves of the selected pairs go to the symbolic preprocessing as device
+ * arrays).  F: host SoA polynomials (any coefficients < p,
  * terms sorted as above; zero polynomials allowed).  gb: out handle. */
 int f4_groebner(f4_ctx* ctx, uint32_t p, const f4_polys* F, f4_basis** gb, void* stream);
 /* The same for nsys independent systems (prime p[i], input F[i]) processed
@@ -428,9 +438,10 @@ int f4_server_footprint(uint32_t n, uint32_t m, uint64_t* bytes);
 
 /* A serving engine on a context.  Systems are admitted while their estimated
  * footprint fits in hbm_budget bytes and fewer than max_slots are resident;
- * their bases stay on the device between steps (the pair sets and leading
- * monomials are host state: the Gebauer-Moeller update runs on the host).
- * Each f4_server_step advances
+ * their bases, pair sets and activity flags stay on the device between steps
+ * (the Gebauer-Moeller update and the normal selection run on the device; a
+ * few summary words per system come back each step; with F4_OPT_HOST_PAIRS
+ * the pair sets are host state instead).  Each f4_server_step advances
  * every resident unfinished system by one F4 iteration with one batched
  * launch sequence (continuous batching: systems admitted between steps join
  * the next one), and systems whose pairs are exhausted get their reduced

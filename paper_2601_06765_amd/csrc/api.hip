@@ -171,6 +171,7 @@ struct DevG {
     u64 nterms = 0;
     DBuf<u64> mon, off, lm;
     DBuf<u32> coeff, len;
+    DBuf<u32> act;  // activity flags (pair sets on the device)
     u64 cap_terms = 0, cap_polys = 0;
 };
 
@@ -260,20 +261,23 @@ static void devg_reserve(Ctx& c, DevG& G, u64 terms, u32 polys, CopyBatch* cb = 
     if ((u64)polys + 1 > G.cap_polys) {
         u64 cap = std::max<u64>((u64)polys + 1, 4 * G.cap_polys);
         DBuf<u64> o2(&c.pool, cap), l2(&c.pool, cap);
-        DBuf<u32> n2(&c.pool, cap);
+        DBuf<u32> n2(&c.pool, cap), a2(&c.pool, cap);
         if (G.npolys) {
             copy(G.off.ptr, o2.ptr, ((u64)G.npolys + 1) * 8);
             copy(G.lm.ptr, l2.ptr, (u64)G.npolys * 8);
             copy(G.len.ptr, n2.ptr, (u64)G.npolys * 4);
+            if (G.act.ptr) copy(G.act.ptr, a2.ptr, (u64)G.npolys * 4);
         }
         if (cb) {
             cb->keep64.push_back(std::move(G.off));
             cb->keep64.push_back(std::move(G.lm));
             cb->keep32.push_back(std::move(G.len));
+            cb->keep32.push_back(std::move(G.act));
         }
         G.off = std::move(o2);
         G.lm = std::move(l2);
         G.len = std::move(n2);
+        G.act = std::move(a2);
         G.cap_polys = cap;
     }
 }
@@ -461,8 +465,10 @@ static void load_polys(Ctx& c, u32 p, const f4_polys* G, DevG& D, bool monic) {
 
 static u32 deg_of(u64 P) { return (u32)(P >> 56); }
 
-// Per-system state of the F4 loop.  The basis lives on the device; the host
-// keeps leading monomials, activity flags and the pair set.
+// Per-system state of the F4 loop.  The basis lives on the device, and so do
+// the pair set and the activity flags (DevPairs, D.act); with the host-pairs
+// option the host keeps them instead (P, active).  The host keeps a copy of
+// the leading monomials either way (they come back with each step's sizes).
 struct SysState {
     u32 n = 0, p = 0;
     MonoOps mo;
@@ -471,6 +477,9 @@ struct SysState {
     std::vector<u8> active;
     std::vector<HPair> P;
     GmScratch gm;
+    bool host_pairs = false;
+    bool pairs_pending = false;  // inputs not yet in the device pair set
+    DevPairs dp;
     bool unit = false, done = false;
     std::vector<f4_step_stats> steps;
     // reduced basis (host), filled at the end
@@ -483,6 +492,8 @@ struct SysState {
     float tpairs = 0;
     std::chrono::steady_clock::time_point t0;
 };
+
+static bool has_pairs(const SysState& S) { return S.host_pairs ? !S.P.empty() : S.dp.kept > 0; }
 
 // halves (t, k) deduplicated and sorted, active list (descending index)
 static void prepare_rows(SysState& S, std::vector<std::pair<u64, u32>>& rows) {
@@ -676,11 +687,26 @@ static void init_system(Ctx& c, SysState& S, u32 p, const f4_polys* F, InitPack&
     pk.mon.insert(pk.mon.end(), mon.begin(), mon.end());
     pk.coeff.insert(pk.coeff.end(), coeff.begin(), coeff.end());
     pk.off.insert(pk.off.end(), off.begin(), off.end());
+    S.host_pairs = (c.flags & F4_OPT_HOST_PAIRS) != 0;
+    S.pairs_pending = !S.host_pairs;
     for (u32 k = 0; k < D.npolys; ++k) {
         S.lm.push_back(inputs[k][0].first);
         S.active.push_back(0);
-        gm_insert(S.mo, S.gm, S.lm, S.active, S.P, k);
+        if (S.host_pairs) gm_insert(S.mo, S.gm, S.lm, S.active, S.P, k);
     }
+}
+
+// The inputs of every system initialised since (init_flush done) enter its
+// device pair set: one update step with all of them as new elements, for all
+// such systems together.
+static void init_pairs(Ctx& c, const std::vector<SysState*>& sys) {
+    std::vector<GmInsert> v;
+    for (SysState* S : sys)
+        if (S->pairs_pending) {
+            S->pairs_pending = false;
+            if (!S->done && !S->unit) v.push_back({&S->dp, S->D.lm.ptr, S->D.act.ptr, S->n, 0u, S->D.npolys});
+        }
+    gm_insert_batch(c, v);
 }
 
 // One F4 iteration for a batch of systems: every system that still has pairs
@@ -688,13 +714,60 @@ static void init_system(Ctx& c, SysState& S, u32 p, const f4_polys* F, InitPack&
 // in one batched launch sequence).  Returns the number of systems advanced.
 static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
     {
+        init_pairs(c, sys);
         std::vector<SysState*> work;
         for (SysState* S : sys)
-            if (!S->done && !S->unit && !S->P.empty()) work.push_back(S);
+            if (!S->done && !S->unit && has_pairs(*S)) work.push_back(S);
         if (work.empty()) return 0;
         std::vector<BuildArgs> args(work.size());
         std::vector<u32> primes(work.size());
-        for_systems(c, work.size(), [&](size_t wi) {
+        // device pair sets: the normal selection of every system in one launch;
+        // the halves and active lists stay on the device for the build
+        const bool dev = !work[0]->host_pairs;
+        DBuf<u64> grt;
+        DBuf<u32> grk, gact, gout;
+        float tsel_ms = 0;
+        hipEvent_t es0 = nullptr, es1 = nullptr;
+        if (dev) {
+            const auto ts0 = std::chrono::steady_clock::now();
+            std::vector<GmSelect> gsel;
+            u64 rows_room = 0, act_room = 0;
+            for (SysState* S : work) {
+                S->t0 = ts0;
+                const u32 d = S->dp.dmin;
+                if (d >= (1u << S->mo.w)) throw F4Error{F4_E_RANGE, "step degree overflows an exponent lane"};
+                S->d = d;
+                S->nsel = S->dp.nsel;
+                gsel.push_back({&S->dp, S->D.lm.ptr, S->D.act.ptr, S->n, S->D.npolys, d, (u32)rows_room,
+                                (u32)act_room});
+                rows_room += 2ull * S->dp.nsel;
+                act_room += S->dp.nact;
+            }
+            if (rows_room >= (1ull << 31) || act_room >= (1ull << 31)) throw F4Error{F4_E_RANGE, "batch too large"};
+            grt.reset(&c.pool, rows_room);
+            grk.reset(&c.pool, rows_room);
+            gact.reset(&c.pool, std::max<u64>(act_room, 1));
+            gout.reset(&c.pool, 4 * work.size());
+            es0 = stage_event(c);
+            for (size_t wi = 0; wi < work.size(); ++wi) {
+                SysState* S = work[wi];
+                BuildArgs& a = args[wi];
+                a.G = devg_view(S->D);
+                a.rows_t_dev = grt.ptr;
+                a.rows_k_dev = grk.ptr;
+                a.r0 = 2 * S->dp.nsel;
+                a.r0_dev = gout.ptr + 4 * wi;
+                a.active_dev = gact.ptr;
+                a.nactive = S->dp.nact;
+                a.D = S->d;
+                a.closure = true;
+                primes[wi] = S->p;
+            }
+            gm_select_batch(c, gsel, grt.ptr, grk.ptr, gout.ptr, gact.ptr);
+            es1 = stage_event(c);
+            tsel_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - ts0).count();
+        }
+        for_systems(c, dev ? 0 : work.size(), [&](size_t wi) {
             SysState* S = work[wi];
             S->t0 = std::chrono::steady_clock::now();
             const auto tp0 = S->t0;
@@ -804,7 +877,7 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
                     S.lm.push_back(newlm[lmbase[i] + t]);
                     S.active.push_back(0);
                 }
-                gm_insert_step(S.mo, S.gm, S.lm, S.active, S.P, h0, h0 + P.rho);
+                if (S.host_pairs) gm_insert_step(S.mo, S.gm, S.lm, S.active, S.P, h0, h0 + P.rho);
             }
             const auto tg1 = std::chrono::steady_clock::now();
             st.t_pairs_ms = S.tpairs + std::chrono::duration<float, std::milli>(tg1 - tg0).count();
@@ -812,6 +885,31 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             S.steps.push_back(st);
             if (c.stop_deg && S.d == c.stop_deg && !S.unit) S.done = true;  // stopped: no basis
         });
+        if (dev) {
+            // the step's elements enter the device pair sets (every system
+            // still running: also those without new elements, whose
+            // summary the selection consumed)
+            const auto tg0 = std::chrono::steady_clock::now();
+            std::vector<GmInsert> gi;
+            for (size_t i = 0; i < work.size(); ++i) {
+                SysState& S = *work[i];
+                if (S.unit || S.done) continue;
+                gi.push_back({&S.dp, S.D.lm.ptr, S.D.act.ptr, S.n, S.D.npolys - R.sys[i].rho, R.sys[i].rho});
+            }
+            hipEvent_t eg0 = stage_event(c);
+            gm_insert_batch(c, gi);
+            hipEvent_t eg1 = stage_event(c);
+            const auto tg1 = std::chrono::steady_clock::now();
+            float tp = tsel_ms + std::chrono::duration<float, std::milli>(tg1 - tg0).count();
+            if (es0 && eg0) {
+                (void)hipEventSynchronize(eg1);
+                tp = event_ms(es0, es1) + (gi.empty() ? 0.f : event_ms(eg0, eg1));
+            }
+            for (SysState* S : work) {
+                S->steps.back().t_pairs_ms = tp;
+                S->steps.back().t_step_ms = std::chrono::duration<float, std::milli>(tg1 - S->t0).count();
+            }
+        }
         c.ev_used = 0;
         return work.size();
     }
@@ -824,8 +922,35 @@ static void f4_finish(Ctx& c, const std::vector<SysState*>& sys) {
     std::vector<BuildArgs> args;
     std::vector<u32> primes;
     std::vector<std::set<u32>> minimal;
+    {
+        // activity flags of the device pair sets, fetched in one readback
+        std::vector<SysState*> dl;
+        u64 words = 0;
+        for (SysState* S : sys)
+            if (!S->done && !S->unit && !S->host_pairs && !has_pairs(*S)) {
+                dl.push_back(S);
+                words += S->D.npolys;
+            }
+        if (words) {
+            DBuf<u32> pack(&c.pool, words);
+            CopyBatch cb;
+            u64 o = 0;
+            for (SysState* S : dl) {
+                if (S->D.npolys) cb.jobs.push_back({S->D.act.ptr, pack.ptr + o, S->D.npolys});
+                o += S->D.npolys;
+            }
+            copy_flush(c, cb);
+            std::vector<u32> h(words);
+            readback(c, h.data(), pack.ptr, words * 4);
+            o = 0;
+            for (SysState* S : dl) {
+                S->active.assign(h.begin() + o, h.begin() + o + S->D.npolys);
+                o += S->D.npolys;
+            }
+        }
+    }
     for (SysState* S : sys) {
-        if (S->done || (!S->unit && !S->P.empty())) continue;
+        if (S->done || (!S->unit && has_pairs(*S))) continue;
         S->done = true;
         if (S->unit) continue;
         std::vector<u32> mins;

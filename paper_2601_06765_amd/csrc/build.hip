@@ -91,7 +91,8 @@ struct SegSP {
     u32 tabn, npolys;
     u32 cmbase;          // colmap / dictionary capacity base
     u32 obase, r;        // ordered rows [obase, obase + r) (after the closure)
-    u32 ibase, r0;       // initial rows in the packed upload
+    u32 ibase, r0;       // initial rows in the packed upload (or the device rows: room)
+    const u32* r0p;      // device rows: the actual count, on the device (else nullptr)
 };
 
 // counters per system: [0] row range begin, [1] row range end (= rows so
@@ -161,9 +162,11 @@ __global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, con
 // scatter the packed initial rows of every system into its row segment and
 // clear the system's three bitmaps (W words apart) and its M counter
 __global__ void k_init_rows(const SegSP* segs, const u64* t0, const u32* k0, u64* rows_t, u32* rows_k, u32* bitmaps,
-                            u32 W, unsigned long long* M) {
+                            u32 W, unsigned long long* M, u32* ctr) {
     const SegSP S = segs[blockIdx.y];
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < S.r0; i += gridDim.x * blockDim.x) {
+    const u32 r0 = S.r0p ? min(*S.r0p, S.r0) : S.r0;
+    if (S.r0p && blockIdx.x == 0 && threadIdx.x == 0) ctr[CTR * blockIdx.y + 1] = r0;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r0; i += gridDim.x * blockDim.x) {
         rows_t[S.rbase + i] = t0[S.ibase + i];
         rows_k[S.rbase + i] = k0[S.ibase + i];
     }
@@ -664,7 +667,15 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     // ---- per-system layout (host)
     std::vector<SegSP> segs(S);
     std::vector<u32> actv;
-    u64 W = 0, RC = 0, CM = 0, IB = 0;
+    u64 W = 0, RC = 0, CM = 0, IB = 0, AB = 0;
+    const bool dev_rows = args[0].rows_t_dev != nullptr, dev_act = args[0].active_dev != nullptr;
+    for (u32 i = 0; i < S; ++i) {
+        // device rows and active lists: one buffer for the batch
+        if (args[i].rows_t_dev != args[0].rows_t_dev || args[i].rows_k_dev != args[0].rows_k_dev ||
+            args[i].active_dev != args[0].active_dev || (dev_rows && !args[i].rows_k_dev))
+            throw F4Error{1, "device row lists and active lists are shared by the whole batch"};
+        if (args[i].r0_dev && !dev_rows) throw F4Error{1, "a device row count without device rows"};
+    }
     u32 max_tabn = 0, max_words = 0, max_nmax = 0, max_np = 1;
     for (u32 i = 0; i < S; ++i) {
         const BuildArgs& a = args[i];
@@ -689,14 +700,17 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         g.wbase = (u32)W;
         g.rcap = a.r0 + (a.closure ? g.nmax : 0);
         g.rbase = (u32)RC;
-        g.abase = (u32)actv.size();
+        g.abase = (u32)AB;
         g.nactive = a.nactive;
-        for (u32 k = 0; k < a.nactive; ++k) actv.push_back(a.active_host[k]);
+        AB += a.nactive;
+        if (!a.active_dev)
+            for (u32 k = 0; k < a.nactive; ++k) actv.push_back(a.active_host[k]);
         g.tabn = (n + D + 2) * F4_BSTRIDE;
         g.npolys = a.G.npolys;
         g.cmbase = (u32)CM;
         g.ibase = (u32)IB;
         g.r0 = a.r0;
+        g.r0p = a.r0_dev;
         IB += a.r0;
         W += g.nwords;
         RC += g.rcap;
@@ -710,10 +724,8 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     const bool closure = args[0].closure;
 
     // descriptors, active lists, initial rows and counters: one upload
-    u64 I = 0;
-    for (u32 i = 0; i < S; ++i) I += args[i].rows_t_dev ? 0 : args[i].r0;
-    const bool dev_rows = args[0].rows_t_dev != nullptr;
-    if (dev_rows && S != 1) throw F4Error{1, "device row lists are for one system"};
+    if (AB >= (1ull << 31)) throw F4Error{2, "batch too large"};
+    const u64 I = dev_rows ? 0 : IB;
     std::vector<u8> pack;
     auto put = [&](const void* src, size_t bytes) {
         const size_t off = (pack.size() + 255) & ~(size_t)255;
@@ -735,7 +747,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     DBuf<u8> params(&c.pool, pack.size());
     upload(c, params.ptr, pack.data(), pack.size());
     SegSP* const dsegs = (SegSP*)(params.ptr + o_segs);
-    const u32* const active = (const u32*)(params.ptr + o_act);
+    const u32* const active = dev_act ? args[0].active_dev : (const u32*)(params.ptr + o_act);
     u32* const ctr = (u32*)(params.ptr + o_ctr);  // counters live in the parameter block
     // present, done and leading-monomial bitmaps (cleared by k_init_rows)
     DBuf<u32> pd(&c.pool, 3 * W);
@@ -751,7 +763,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         const u64* t0 = dev_rows ? args[0].rows_t_dev : (const u64*)(params.ptr + o_t0);
         const u32* k0 = dev_rows ? args[0].rows_k_dev : (const u32*)(params.ptr + o_k0);
         hipLaunchKernelGGL(k_init_rows, dim3(std::min<u32>(dev_rows ? 4096 : 64, ceil_div(mr, 256)), S), dim3(256), 0,
-                           s, dsegs, t0, k0, rows_t.ptr, rows_k.ptr, pd.ptr, (u32)W, Mdev.ptr);
+                           s, dsegs, t0, k0, rows_t.ptr, rows_k.ptr, pd.ptr, (u32)W, Mdev.ptr, ctr);
         F4_LAUNCH_CHECK();
     }
 

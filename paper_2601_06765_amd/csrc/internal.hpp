@@ -351,10 +351,15 @@ struct BuildArgs {
     DevBasis G;
     const u64* rows_t_host = nullptr;  // r0 initial rows (distinct (t, k)), host
     const u32* rows_k_host = nullptr;
-    const u64* rows_t_dev = nullptr;   // or on the device (a batch of one system only)
+    // or on the device: one buffer for the whole batch (every system passes
+    // the same base), system i's rows at the sum of the r0 of the systems
+    // before it
+    const u64* rows_t_dev = nullptr;
     const u32* rows_k_dev = nullptr;
-    u32 r0 = 0;
+    u32 r0 = 0;                        // rows (with r0_dev: the room for them)
+    const u32* r0_dev = nullptr;       // device rows only: the actual count, on the device
     const u32* active_host = nullptr;  // active basis indices in descending order, host
+    const u32* active_dev = nullptr;   // or on the device, batched like the device rows
     u32 nactive = 0;
     u32 D = 0;                         // largest degree of any row
     bool closure = true;
@@ -362,6 +367,49 @@ struct BuildArgs {
 };
 // SP for every system of the batch (one launch per kernel for the batch).
 void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out);
+
+// ------------------------------------------------------ pair set (device)
+// The pair set of one system on the device (Gebauer-Moeller update, normal
+// selection): pairs (i, j, lcm) in one of two buffers (the selection moves the
+// pairs it leaves into the other), and the summary of the last update.
+struct DevPairs {
+    DBuf<u64> lcm[2];
+    DBuf<u32> ij[2];  // i, j of each pair
+    DBuf<u32> born;   // element of the current step that created the pair
+    u32 cur = 0;
+    u64 cap = 0;
+    u32 count = 0;                               // pairs in the current buffer
+    u32 kept = 0, dmin = 0, nsel = 0, nact = 0;  // pairs, least lcm degree, pairs of it, active elements
+};
+
+// Insertion of basis elements h0 .. h0+rho-1 (their leading monomials already
+// in lm) into a system's pair set, with the removals they cause and the
+// retirement of the active elements they divide (act: one flag per element).
+struct GmInsert {
+    DevPairs* P;
+    const u64* lm;
+    u32* act;
+    u32 n, h0, rho;
+};
+// Every system's insertion in one launch sequence, then one readback of the
+// summaries into the DevPairs (count, kept, dmin, nsel, nact).
+void gm_insert_batch(Ctx& c, const std::vector<GmInsert>& v);
+
+// Normal selection of a system whose least lcm degree is d: the pairs of
+// degree d leave the set, their halves (lcm / LM(k), k), deduplicated, go to
+// rows at row_base, and the active elements, in descending index order, to
+// the active list at act_base.  outs: 4 words per system, written on the
+// device: rows, pairs left, active elements, halves (the rows count is what
+// the build reads as the system's row count).
+struct GmSelect {
+    DevPairs* P;
+    const u64* lm;
+    const u32* act;
+    u32 n, npolys, d;
+    u32 row_base, act_base;
+};
+void gm_select_batch(Ctx& c, const std::vector<GmSelect>& v, u64* rows_t, u32* rows_k, u32* outs,
+                     u32* active_out);
 
 // ----------------------------------------------------------- elimination
 struct RedPart {

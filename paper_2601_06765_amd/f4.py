@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libf4.so")
 
 F4_OK, F4_E_ARG, F4_E_RANGE, F4_E_NOMEM, F4_E_BUSY, F4_E_DEVICE, F4_E_STATE = range(7)
 F4_OPT_TIMING, F4_OPT_DICT_RANK, F4_OPT_DICT_RADIX, F4_OPT_AUTOTUNE, F4_OPT_KERNEL_TIMING = 1, 2, 4, 8, 16
+F4_OPT_HOST_PAIRS = 32
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libf4.so is not built: run `python -m paper_2601_06765_amd.build` "
@@ -274,10 +275,13 @@ class _PolysArg:
 # --------------------------------------------------------------- context
 class Context:
     def __init__(self, device=0, timing=False, dict_path=None, stop_deg=0, autotune=False, trsm_rows=0,
-                 radix_bits=0, kernel_timing=False, alloc=None, free=None):
+                 radix_bits=0, kernel_timing=False, alloc=None, free=None, host_pairs=False):
         """alloc(bytes, stream) -> device pointer or 0, free(ptr, stream):
-        optional device allocator of the context (f4_opts.alloc / .free)."""
+        optional device allocator of the context (f4_opts.alloc / .free).
+        host_pairs: pair sets on the host (F4_OPT_HOST_PAIRS)."""
         flags = F4_OPT_TIMING if timing else 0
+        if host_pairs:
+            flags |= F4_OPT_HOST_PAIRS
         if kernel_timing:
             flags |= F4_OPT_TIMING | F4_OPT_KERNEL_TIMING
         if dict_path == "rank":

@@ -1,0 +1,213 @@
+"""Pair sets on the device (Gebauer-Moeller update and normal selection in
+csrc/gm.hip) against the host pair sets (F4_OPT_HOST_PAIRS, the update that
+tests/test_host_pairs.py pins to the plain sequential rule): every F4 step
+has the same selection (degree, pairs selected) and the same matrix and
+elimination shapes, and the bases are equal, for single systems, batches and
+the server; on the n=14 workload the steps also equal the oracle's.  Exact
+comparisons throughout.  Every test prints its case first."""
+
+import sys
+
+import pytest
+
+import oracle
+import synth
+from oracle import buchberger as bb
+
+pytestmark = pytest.mark.gpu
+
+STEP_KEYS = ("deg", "nsel", "r", "N", "nnz", "npivot", "lower", "rho", "rank")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def f4():
+    import paper_2601_06765_amd.f4 as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def dev(f4):
+    c = f4.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def host(f4):
+    c = f4.Context(0, host_pairs=True)
+    yield c
+    c.close()
+
+
+def canon(basis):
+    out = []
+    for f in basis:
+        d = {tuple(e): c for e, c in f}
+        out.append(tuple((e, d[e]) for e in sorted(d, key=bb.grevlex_key, reverse=True)))
+    return tuple(out)
+
+
+def shapes(steps):
+    return [tuple(s[k] for k in STEP_KEYS) for s in steps]
+
+
+def same_run(dev, host, p, n, polys, label):
+    say("device vs host pairs", label, "n", n, "p", p, "m", len(polys))
+    bd, sd = dev.groebner(p, n, polys)
+    bh, sh = host.groebner(p, n, polys)
+    assert shapes(sd) == shapes(sh), "step shapes differ"
+    assert canon(bd) == canon(bh), "bases differ"
+    return bd, sd
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_configs(dev, host, cfg):
+    n, p, polys = synth.config_system(cfg)
+    same_run(dev, host, p, n, polys, "config %d" % cfg)
+
+
+RANDOM = [  # n, m, p, seed, density, max_deg
+    (5, 6, 65521, 11, 1.0, 2),
+    (6, 6, synth.P31, 12, 0.5, 3),
+    (7, 9, 65521, 13, 0.3, 2),
+    (4, 5, 7, 14, 1.0, 3),
+    (8, 9, 2147483629, 15, 0.4, 2),
+    (3, 6, 65521, 16, 1.0, 4),
+    (9, 10, 65521, 17, 0.25, 2),
+]
+
+
+@pytest.mark.parametrize("case", RANDOM)
+def test_random_systems(dev, host, case):
+    n, m, p, seed, dens, dmax = case
+    polys = synth.random_system(n, m, p, seed, density=dens, max_deg=dmax)
+    same_run(dev, host, p, n, polys, "random seed %d" % seed)
+
+
+@pytest.mark.parametrize("n,p,seed", [(5, 65521, 31), (7, synth.P31, 32), (9, 65521, 33)])
+def test_planted_systems(dev, host, n, p, seed):
+    polys, _ = synth.planted_system(n, n + 1, p, seed)
+    same_run(dev, host, p, n, polys, "planted seed %d" % seed)
+
+
+def test_dividing_and_repeated_leading_monomials(dev, host):
+    """Inputs whose leading monomials divide each other or repeat (elements
+    retired within the insertion step, excess 1, equal excesses)."""
+    p, n = 65521, 5
+    x = lambda *e: tuple(e)
+    polys = [
+        [(x(2, 1, 0, 0, 0), 1), (x(0, 0, 1, 0, 0), 3)],
+        [(x(1, 1, 0, 0, 0), 1), (x(0, 0, 0, 1, 0), 2)],
+        [(x(2, 1, 0, 0, 0), 1), (x(0, 0, 0, 0, 1), 5)],
+        [(x(1, 0, 0, 0, 0), 1), (x(0, 1, 0, 0, 0), 7), (x(0, 0, 0, 0, 0), 1)],
+        [(x(0, 1, 1, 0, 0), 1), (x(0, 0, 0, 1, 1), 4)],
+        [(x(0, 0, 2, 0, 0), 1), (x(0, 0, 0, 2, 0), 9), (x(0, 0, 0, 0, 1), 1)],
+    ]
+    bd, _ = same_run(dev, host, p, n, polys, "dividing leading monomials")
+    assert canon(bd) == canon(oracle.OracleRun(n, p, polys).basis())
+
+
+def test_wide_exponent_lanes(dev, host):
+    """n = 12 (4-bit exponent lanes): exponents of 8 and more set a lane's top
+    bit, where the lane-parallel forms of the update do not hold; the device
+    compares those lane by lane (the host switches to the plain update)."""
+    p, n = 65521, 12
+    def mono(**kw):
+        e = [0] * n
+        for k, v in kw.items():
+            e[int(k[1:]) - 1] = v
+        return tuple(e)
+    polys = [
+        [(mono(x1=8), 1), (mono(x1=1, x2=1), 3), (mono(), 5)],
+        [(mono(x2=2), 1), (mono(x1=1, x3=1), 1), (mono(), 1)],
+        [(mono(x3=2), 1), (mono(x2=1), 2), (mono(), 3)],
+    ] + [[(mono(**{"x%d" % i: 1}), 1), (mono(x1=1), 1), (mono(), i)] for i in range(4, n + 1)]
+    bd, _ = same_run(dev, host, p, n, polys, "exponents >= 8 in 4-bit lanes")
+    assert canon(bd) == canon(oracle.OracleRun(n, p, polys).basis())
+
+
+def test_n14_steps_equal_oracle(f4, host):
+    """The n=14 workload up to its first degree-5 step: the device pair sets
+    give the oracle's selections and step shapes, and the host pair sets'."""
+    n, p, polys = synth.config_system(3)
+    say("n=14 sparse quadratics to degree 5: device pairs vs oracle and host pairs")
+    c = f4.Context(0, stop_deg=5)
+    try:
+        _, sd = c.groebner(p, n, polys)
+    finally:
+        c.close()
+    hc = f4.Context(0, stop_deg=5, host_pairs=True)
+    try:
+        _, sh = hc.groebner(p, n, polys)
+    finally:
+        hc.close()
+    assert shapes(sd) == shapes(sh)
+    run = oracle.OracleRun(n, p, polys, stop_deg=5)
+    want = [(s["d"], s["r"], s["N"], s["M"], s["npiv"], s["rank"], s["rho"]) for s in run.steps()]
+    got = [(s["deg"], s["r"], s["N"], s["nnz"], s["npivot"], s["rank"], s["rho"]) for s in sd]
+    assert got == want
+
+
+def test_batch_equals_host_single(dev, host):
+    systems = []
+    for j in range(24):
+        n = 4 + j % 5
+        p = (65521, synth.P31, 7919)[j % 3]
+        systems.append((p, n, synth.random_system(n, n + 1 + j % 2, p, 500 + j, density=0.6, max_deg=2)))
+    say("batch of", len(systems), "systems with device pair sets vs host pair sets one by one")
+    got = dev.groebner_batch(systems)
+    for (p, n, polys), (b, st) in zip(systems, got):
+        bh, sh = host.groebner(p, n, polys)
+        assert shapes(st) == shapes(sh)
+        assert canon(b) == canon(bh)
+
+
+def test_server_equals_host(f4, host):
+    reqs = []
+    for j in range(12):
+        n = 5 + j % 4
+        p = (65521, synth.P31)[j % 2]
+        reqs.append((p, n, synth.random_system(n, n + 1, p, 900 + j, density=0.5, max_deg=2)))
+    say("server with device pair sets,", len(reqs), "requests, 4 slots, vs host pair sets")
+    c = f4.Context(0)
+    try:
+        srv = f4.Server(c, hbm_budget=1 << 36, max_slots=4)
+        pending = list(range(len(reqs)))
+        tickets, results, steps = {}, {}, 0
+        while len(results) < len(reqs):
+            while pending:
+                t = srv.submit(*reqs[pending[0]])
+                if t is None:
+                    break
+                tickets[t] = pending.pop(0)
+            srv.step()
+            steps += 1
+            for t in list(tickets):
+                r = srv.poll(t)
+                if r is not None:
+                    results[tickets.pop(t)] = r
+            assert steps < 10000
+        for i, (p, n, polys) in enumerate(reqs):
+            b, st = results[i]
+            bh, sh = host.groebner(p, n, polys)
+            assert shapes(st) == shapes(sh)
+            assert canon(b) == canon(bh)
+        srv.close()
+    finally:
+        c.close()
+
+
+def test_pair_time_is_recorded(f4):
+    n, p, polys = synth.config_system(2)
+    say("timing of the device pair update")
+    c = f4.Context(0, timing=True)
+    try:
+        _, st = c.groebner(p, n, polys)
+    finally:
+        c.close()
+    assert all(s["t_pairs_ms"] > 0 for s in st)
