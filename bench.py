@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 MODMUL_PEAK = 256 * 4 * 16 * 2.4e9 / 2
 VALU_ISSUE = 256 * 4 * 16 * 2.4e9  # vector lane-instructions per second
 STEP_DEG = 5  # the timed step of the headline workload
+BATCH_RUNS = 5
 
 
 def parse():
@@ -440,10 +441,13 @@ def batch_leg(f4, torch, count, autotune):
     prep = ctx.prepare_batch(systems)
     ctx.groebner_batch_prepared(prep)  # warm-up
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = ctx.groebner_batch_prepared(prep)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
+    tbs = []
+    for _ in range(BATCH_RUNS):
+        t0 = time.perf_counter()
+        res = ctx.groebner_batch_prepared(prep)
+        torch.cuda.synchronize()
+        tbs.append(time.perf_counter() - t0)
+    tb = statistics.median(tbs)
     preps = [ctx.prepare(p, n, polys) for p, n, polys in systems]  # marshalled once, as for the batch
     t0 = time.perf_counter()
     plain = [ctx.groebner_prepared(q) for q in preps]
@@ -455,7 +459,8 @@ def batch_leg(f4, torch, count, autotune):
         raise SystemExit("batched bases differ from the one-by-one bases for systems %s" % bad[:10])
     nnz = sum(s["nnz"] for _, steps in res for s in steps)
     return {"workload": "%d dense systems, n ~ U{6..9}, m = n+1, F_65521 (seeds 4*2^32+j)" % count,
-            "systems": count, "batched_s": tb, "plain_s": tp,
+            "systems": count, "batched_s": tb, "batched_s_min": min(tbs),
+            "stat": "batched: median of %d runs after a warm-up; plain: one pass" % BATCH_RUNS, "plain_s": tp,
             "systems_per_s_batched": count / tb, "systems_per_s_plain": count / tp,
             "speedup": tp / tb, "nnz_total": nnz, "nnz_per_s_batched": nnz / tb,
             "checked": "all %d batched bases equal their one-by-one bases" % count}
@@ -471,10 +476,13 @@ def crt_leg(f4, torch, autotune):
     prep = ctx.prepare_batch(systems)
     ctx.groebner_batch_prepared(prep)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = ctx.groebner_batch_prepared(prep)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
+    tbs = []
+    for _ in range(BATCH_RUNS):
+        t0 = time.perf_counter()
+        res = ctx.groebner_batch_prepared(prep)
+        torch.cuda.synchronize()
+        tbs.append(time.perf_counter() - t0)
+    tb = statistics.median(tbs)
     preps = [ctx.prepare(q, n, polys) for q, n, polys in systems]
     t0 = time.perf_counter()
     plain = [ctx.groebner_prepared(q) for q in preps]
@@ -484,7 +492,8 @@ def crt_leg(f4, torch, autotune):
     if not same_bases(res, plain):
         raise SystemExit("CRT batch bases differ from the plain runs")
     return {"workload": "one n=9, m=10 dense system under the 8 largest primes below 2^31",
-            "systems": len(systems), "systems_per_s_batched": len(systems) / tb,
+            "systems": len(systems), "stat": "batched: median of %d runs after a warm-up" % BATCH_RUNS,
+            "systems_per_s_batched": len(systems) / tb,
             "systems_per_s_plain": len(systems) / tp, "speedup": tp / tb,
             "nnz_total": sum(s["nnz"] for _, st in res for s in st)}
 

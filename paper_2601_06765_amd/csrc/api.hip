@@ -724,46 +724,43 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
         // device pair sets: the normal selection of every system in one launch;
         // the halves and active lists stay on the device for the build
         const bool dev = !work[0]->host_pairs;
-        DBuf<u64> grt;
-        DBuf<u32> grk, gact, gout;
+        DBuf<u64> grt, gkeep;
+        DBuf<u32> grk;
+        u32* gout = nullptr;
         float tsel_ms = 0;
         hipEvent_t es0 = nullptr, es1 = nullptr;
         if (dev) {
             const auto ts0 = std::chrono::steady_clock::now();
             std::vector<GmSelect> gsel;
-            u64 rows_room = 0, act_room = 0;
+            u64 rows_room = 0;
             for (SysState* S : work) {
                 S->t0 = ts0;
                 const u32 d = S->dp.dmin;
                 if (d >= (1u << S->mo.w)) throw F4Error{F4_E_RANGE, "step degree overflows an exponent lane"};
                 S->d = d;
                 S->nsel = S->dp.nsel;
-                gsel.push_back({&S->dp, S->D.lm.ptr, S->D.act.ptr, S->n, S->D.npolys, d, (u32)rows_room,
-                                (u32)act_room});
+                gsel.push_back({&S->dp, S->D.lm.ptr, S->n, S->D.npolys, d, (u32)rows_room});
                 rows_room += 2ull * S->dp.nsel;
-                act_room += S->dp.nact;
             }
-            if (rows_room >= (1ull << 31) || act_room >= (1ull << 31)) throw F4Error{F4_E_RANGE, "batch too large"};
+            if (rows_room >= (1ull << 31)) throw F4Error{F4_E_RANGE, "batch too large"};
             grt.reset(&c.pool, rows_room);
             grk.reset(&c.pool, rows_room);
-            gact.reset(&c.pool, std::max<u64>(act_room, 1));
-            gout.reset(&c.pool, 4 * work.size());
             es0 = stage_event(c);
+            gout = gm_select_batch(c, gsel, grt.ptr, grk.ptr, gkeep);
             for (size_t wi = 0; wi < work.size(); ++wi) {
                 SysState* S = work[wi];
                 BuildArgs& a = args[wi];
                 a.G = devg_view(S->D);
                 a.rows_t_dev = grt.ptr;
                 a.rows_k_dev = grk.ptr;
-                a.r0 = 2 * S->dp.nsel;
-                a.r0_dev = gout.ptr + 4 * wi;
-                a.active_dev = gact.ptr;
+                a.r0 = 2 * S->nsel;
+                a.r0_dev = gout + 4 * wi;
+                a.active_dev = S->dp.alist.ptr;
                 a.nactive = S->dp.nact;
                 a.D = S->d;
                 a.closure = true;
                 primes[wi] = S->p;
             }
-            gm_select_batch(c, gsel, grt.ptr, grk.ptr, gout.ptr, gact.ptr);
             es1 = stage_event(c);
             tsel_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - ts0).count();
         }
@@ -894,7 +891,8 @@ static size_t f4_iterate(Ctx& c, const std::vector<SysState*>& sys) {
             for (size_t i = 0; i < work.size(); ++i) {
                 SysState& S = *work[i];
                 if (S.unit || S.done) continue;
-                gi.push_back({&S.dp, S.D.lm.ptr, S.D.act.ptr, S.n, S.D.npolys - R.sys[i].rho, R.sys[i].rho});
+                gi.push_back({&S.dp, S.D.lm.ptr, S.D.act.ptr, S.n, S.D.npolys - R.sys[i].rho, R.sys[i].rho,
+                              gout + 4 * i, 2 * S.nsel});
             }
             hipEvent_t eg0 = stage_event(c);
             gm_insert_batch(c, gi);

@@ -93,6 +93,7 @@ struct SegSP {
     u32 obase, r;        // ordered rows [obase, obase + r) (after the closure)
     u32 ibase, r0;       // initial rows in the packed upload (or the device rows: room)
     const u32* r0p;      // device rows: the actual count, on the device (else nullptr)
+    const u32* actp;     // the system's own device active list (else nullptr: the batch's list at abase)
 };
 
 // counters per system: [0] row range begin, [1] row range end (= rows so
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(MB_THREADS) void k_reducers(const SegSP* segs, cons
     extern __shared__ u64 slm[];
     const u32 s = blockIdx.y;
     const SegSP S = segs[s];
-    const u32* act = active + S.abase;
+    const u32* act = S.actp ? S.actp : active + S.abase;
     if (lds_active) {
         for (u32 a = threadIdx.x; a < S.nactive; a += MB_THREADS) slm[a] = S.lm[act[a]];
         __syncthreads();
@@ -668,12 +669,12 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     std::vector<SegSP> segs(S);
     std::vector<u32> actv;
     u64 W = 0, RC = 0, CM = 0, IB = 0, AB = 0;
-    const bool dev_rows = args[0].rows_t_dev != nullptr, dev_act = args[0].active_dev != nullptr;
+    const bool dev_rows = args[0].rows_t_dev != nullptr;
     for (u32 i = 0; i < S; ++i) {
         // device rows and active lists: one buffer for the batch
         if (args[i].rows_t_dev != args[0].rows_t_dev || args[i].rows_k_dev != args[0].rows_k_dev ||
-            args[i].active_dev != args[0].active_dev || (dev_rows && !args[i].rows_k_dev))
-            throw F4Error{1, "device row lists and active lists are shared by the whole batch"};
+            (dev_rows && !args[i].rows_k_dev))
+            throw F4Error{1, "device row lists are shared by the whole batch"};
         if (args[i].r0_dev && !dev_rows) throw F4Error{1, "a device row count without device rows"};
     }
     u32 max_tabn = 0, max_words = 0, max_nmax = 0, max_np = 1;
@@ -702,9 +703,11 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         g.rbase = (u32)RC;
         g.abase = (u32)AB;
         g.nactive = a.nactive;
-        AB += a.nactive;
-        if (!a.active_dev)
+        g.actp = a.active_dev;
+        if (!a.active_dev) {
+            AB += a.nactive;
             for (u32 k = 0; k < a.nactive; ++k) actv.push_back(a.active_host[k]);
+        }
         g.tabn = (n + D + 2) * F4_BSTRIDE;
         g.npolys = a.G.npolys;
         g.cmbase = (u32)CM;
@@ -747,7 +750,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     DBuf<u8> params(&c.pool, pack.size());
     upload(c, params.ptr, pack.data(), pack.size());
     SegSP* const dsegs = (SegSP*)(params.ptr + o_segs);
-    const u32* const active = dev_act ? args[0].active_dev : (const u32*)(params.ptr + o_act);
+    const u32* const active = (const u32*)(params.ptr + o_act);
     u32* const ctr = (u32*)(params.ptr + o_ctr);  // counters live in the parameter block
     // present, done and leading-monomial bitmaps (cleared by k_init_rows)
     DBuf<u32> pd(&c.pool, 3 * W);

@@ -359,7 +359,7 @@ struct BuildArgs {
     u32 r0 = 0;                        // rows (with r0_dev: the room for them)
     const u32* r0_dev = nullptr;       // device rows only: the actual count, on the device
     const u32* active_host = nullptr;  // active basis indices in descending order, host
-    const u32* active_dev = nullptr;   // or on the device, batched like the device rows
+    const u32* active_dev = nullptr;   // or on the device (this system's own list)
     u32 nactive = 0;
     u32 D = 0;                         // largest degree of any row
     bool closure = true;
@@ -376,8 +376,9 @@ struct DevPairs {
     DBuf<u64> lcm[2];
     DBuf<u32> ij[2];  // i, j of each pair
     DBuf<u32> born;   // element of the current step that created the pair
+    DBuf<u32> alist;  // active elements, descending index (written by each update)
     u32 cur = 0;
-    u64 cap = 0;
+    u64 cap = 0, acap = 0;
     u32 count = 0;                               // pairs in the current buffer
     u32 kept = 0, dmin = 0, nsel = 0, nact = 0;  // pairs, least lcm degree, pairs of it, active elements
 };
@@ -390,26 +391,30 @@ struct GmInsert {
     const u64* lm;
     u32* act;
     u32 n, h0, rho;
+    // the selection of this step (its 4 output words) and the halves it had
+    // to find: checked on the device, reported by the readback (sel_out
+    // nullptr: nothing to check)
+    const u32* sel_out = nullptr;
+    u32 sel_halves = 0;
 };
 // Every system's insertion in one launch sequence, then one readback of the
 // summaries into the DevPairs (count, kept, dmin, nsel, nact).
 void gm_insert_batch(Ctx& c, const std::vector<GmInsert>& v);
 
 // Normal selection of a system whose least lcm degree is d: the pairs of
-// degree d leave the set, their halves (lcm / LM(k), k), deduplicated, go to
-// rows at row_base, and the active elements, in descending index order, to
-// the active list at act_base.  outs: 4 words per system, written on the
-// device: rows, pairs left, active elements, halves (the rows count is what
-// the build reads as the system's row count).
+// degree d leave the set and their halves (lcm / LM(k), k), deduplicated, go
+// to rows at row_base (at most 2 * nsel of them; the active list for the
+// reducer search is DevPairs::alist).  Returns the output words, 4 per
+// system, written on the device: rows (what the build reads as the system's
+// row count), unused, unused, halves; they live in `keep`, which the caller
+// holds until the build has run.
 struct GmSelect {
     DevPairs* P;
     const u64* lm;
-    const u32* act;
     u32 n, npolys, d;
-    u32 row_base, act_base;
+    u32 row_base;
 };
-void gm_select_batch(Ctx& c, const std::vector<GmSelect>& v, u64* rows_t, u32* rows_k, u32* outs,
-                     u32* active_out);
+u32* gm_select_batch(Ctx& c, const std::vector<GmSelect>& v, u64* rows_t, u32* rows_k, DBuf<u64>& keep);
 
 // ----------------------------------------------------------- elimination
 struct RedPart {
