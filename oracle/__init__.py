@@ -12,6 +12,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * O5 ``krylov.py``: the block operator application Y = A X / A^T X over F_p.
 * O6 ``wiedemann.py``: block Wiedemann left-kernel vectors (projected Krylov
   sequence, sigma-basis generator, kernel-vector evaluation).
+* O7 ``signatures.py``: signature admissibility of shifted reducers (syzygy
+  and rewrite tests), the filtered and bucketed row lists, and symbolic
+  preprocessing closed over the admissible reducers only.
 
 Each is pinned in ``tests/test_oracle_*.py`` against facts fixed by the paper
 and by mathematics (uniqueness of the reduced Groebner basis, closed forms,
