@@ -56,6 +56,8 @@ def parse():
                     help="shift degree of the Macaulay operator of the SpMM leg (0: skip)")
     ap.add_argument("--wiedemann-shift-deg", type=int, default=3,
                     help="shift degree of the Macaulay matrix of the block Wiedemann leg (-1: skip)")
+    ap.add_argument("--sig-shift-deg", type=int, default=8,
+                    help="shift degree of the rows of the signature-filter leg (0: skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed schedules instead of the autotuner's measured picks (tuned during warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -406,6 +408,68 @@ def wiedemann_leg(f4, shift_deg, b):
             "sequence_entry_vector_products_per_s": 2.0 * nnz * b * L / (st["t_sequence_ms"] * 1e-3)}
 
 
+def signature_leg(f4, shift_deg, build_shift_deg, reps):
+    """Signature admissibility in bulk on workload 3's input (the 15 sparse
+    quadratics in n=14 over F_(2^31-1)): f_i carries the signature 1 e_i and
+    index i lists the principal syzygies LM(f_j), j < i, so the filter is the
+    F5 syzygy criterion.  (1) f4_sig_filter over the Macaulay rows t*f_i for
+    every t of degree <= shift_deg: device time (HIP events around predicate,
+    scan, compaction; with the bucketed schedule separately), rows/s and
+    algorithmic bytes (read t and k, 12 B a row; write the flag, 1 B, and each
+    kept row, 12 B).  (2) f4_build_matrix_sig on the rows of degree <=
+    build_shift_deg + 2 against f4_build_matrix_rows of the same rows:
+    rows, nonzeros and device time of both."""
+    import numpy as np
+    import synth
+    n, p, polys = synth.config_system(3)
+    G = f4.normalize(p, n, polys, monic=True)
+    m = len(G)
+    lms = [tuple(g[0][0]) for g in G]
+    syz = [[lms[j] for j in range(i)] for i in range(m)]
+    sidx, smon = list(range(m)), [(0,) * n] * m
+    ctx = f4.Context(0)
+    sg = ctx._sigs(n, sidx, smon, syz)
+    t = f4.pack_many(n, synth.monomials_upto(n, shift_deg))
+    tw, ks = np.repeat(t, m), np.tile(np.arange(m, dtype=np.uint32), len(t))
+    r = len(tw)
+    res = {"workload": "F5 syzygy criterion on the Macaulay rows t*f_i of the n=14 sparse quadratics "
+                       "(15 x 20 terms, F_(2^31-1), seed 3), deg t <= %d; signatures 1 e_i, principal "
+                       "syzygies" % shift_deg, "rows": r}
+    for name, sched in (("filter", False), ("filter_and_schedule", True)):
+        ctx.sig_filter_packed(p, n, G, sg, tw, ks, schedule=sched)  # warm-up
+        ms = []
+        for _ in range(reps):
+            flags, nk, _, st = ctx.sig_filter_packed(p, n, G, sg, tw, ks, schedule=sched)
+            ms.append(st["t_device_ms"])
+        med = statistics.median(ms)
+        byts = 12 * r + r + 12 * nk
+        res[name] = {"device_ms": round(med, 4), "rows_per_s": r / (med * 1e-3),
+                     "alg_bytes": byts, "alg_GBs": round(byts / (med * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(byts / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "kept": nk, "syzygy": st["syzygy"], "rewritten": st["rewritten"]}
+    # (2) the closure over admissible reducers on a smaller matrix
+    t2 = synth.monomials_upto(n, build_shift_deg)
+    rows = [(tuple(int(x) for x in e), k) for e in t2 for k in range(m)]
+    A, st = ctx.build_matrix_sig(p, n, G, [1] * m, sidx, smon, syz, rows)
+    A.free()
+    A, st = ctx.build_matrix_sig(p, n, G, [1] * m, sidx, smon, syz, rows)
+    sig_view = (A.view.r, A.view.N, A.view.nnz)
+    A.free()
+    B = ctx.build_matrix_rows(p, n, G, rows)
+    B.free()
+    t0 = time.perf_counter()
+    B = ctx.build_matrix_rows(p, n, G, rows)
+    ctx.download(B.view.row_ptr, 1, np.uint32)
+    t_plain = time.perf_counter() - t0
+    res["build"] = {"rows_in": len(rows), "deg": build_shift_deg + 2,
+                    "sig": {"r": sig_view[0], "N": sig_view[1], "nnz": sig_view[2],
+                            "rejected_syzygy": st["syzygy"], "device_ms": round(st["t_device_ms"], 4)},
+                    "plain": {"r": B.view.r, "N": B.view.N, "nnz": B.view.nnz, "wall_ms": round(t_plain * 1e3, 3)}}
+    B.free()
+    ctx.close()
+    return res
+
+
 def modloop_leg(f4, nchains, iters):
     """Modular inner-loop microbenchmark (randomized residues, seed 5): the
     update rate of each arithmetic form, its registers and spill bytes per
@@ -610,6 +674,8 @@ def main():
             out["spmm"] = spmm_leg(f4, args.spmm_shift_deg, 8, 20)
         if args.wiedemann_shift_deg >= 0:
             out["block_wiedemann"] = wiedemann_leg(f4, args.wiedemann_shift_deg, 8)
+        if args.sig_shift_deg:
+            out["signatures"] = signature_leg(f4, args.sig_shift_deg, 3, 5)
         if args.batch_systems:
             out["batch"] = batch_leg(f4, torch, args.batch_systems, tune)
             out["systems_per_s_batched"] = out["batch"]["systems_per_s_batched"]

@@ -240,6 +240,74 @@ int f4_build_matrix(f4_ctx* ctx, uint32_t p, const f4_polys* G, const uint8_t* a
 int f4_build_matrix_rows(f4_ctx* ctx, uint32_t p, const f4_polys* G, const f4_rowspec* R, uint32_t r,
                          f4_matrix** A, void* stream);
 
+/* ------------------------------------------------------------ signatures */
+/* Signatures of a basis (section "Signature regime: correctness under
+ * admissibility predicates"; section "Discussion: Integrating Signatures,
+ * Admissibility, and GPU Scheduling"; the paper leaves the order and the
+ * rewrite rule open, the readings taken are these): element k carries the
+ * signature mon[k] e_{index[k]}, and the shifted reducer t * g_k the signature
+ * (t mon[k]) e_{index[k]}, ordered position over term.  For each index i,
+ * syz_mon[syz_off[i] .. syz_off[i+1]) are monomials u with u e_i the
+ * signature of a known syzygy (for instance LM(f_j), j < i, for the principal
+ * syzygies).  A row is admissible unless
+ *   - a syzygy monomial of its index divides its signature monomial
+ *     (F4_ADM_SYZYGY, tested first), or
+ *   - a newer element k' > k with index[k'] = index[k] has mon[k'] dividing
+ *     it (F4_ADM_REWRITTEN: the newest element whose signature divides a
+ *     signature is the one allowed to produce it).
+ * All arrays are host arrays, P words of the basis's n variables. */
+typedef struct f4_sigs {
+    uint32_t npolys;          /* the basis size */
+    const uint32_t* index;    /* npolys, each < nindex */
+    const uint64_t* mon;      /* npolys */
+    uint32_t nindex;          /* 1 .. 2^20 */
+    const uint32_t* syz_off;  /* nindex + 1, nondecreasing, syz_off[0] = 0 */
+    const uint64_t* syz_mon;  /* syz_off[nindex] */
+} f4_sigs;
+
+enum { F4_ADM_OK = 0, F4_ADM_SYZYGY = 1, F4_ADM_REWRITTEN = 2 };
+
+typedef struct f4_sig_stats {
+    uint32_t kept, syzygy, rewritten; /* rows admissible / rejected by each test */
+    uint32_t pad;
+    double t_device_ms;  /* HIP events around the device work of the call (predicate, scan,
+                            compaction, schedule; for f4_build_matrix_sig also the build) */
+} f4_sig_stats;
+
+/* The admissibility predicate over a row list, in bulk: the flag of every row
+ * (F4_ADM_*), the admissible rows compacted in input order, and a schedule
+ * of them bucketed by (degree of t * LM(g_k), number of terms of g_k,
+ * signature index), ties in input order.
+ *   p, G   : as for f4_build_matrix_rows (G host or device, f4_polys form).
+ *   S      : signatures of G (S->npolys = G->npolys).
+ *   R, r   : host rows, r >= 1.
+ *   flags  : host, r bytes out (may be NULL).
+ *   kept   : host, room for r rows out (may be NULL); *nkept = their count.
+ *   order  : host, room for r entries out (may be NULL): positions in kept,
+ *            scheduled (r < 2^28; the key saturates lengths at 2^16 - 1 and
+ *            indices at 2^12 - 1, ties then fall back to input order).
+ *   st     : out (may be NULL).
+ * Errors: F4_E_ARG (bad p, G, S, a row's k out of range or t not a
+ * monomial), F4_E_RANGE (t * LM(g_k) or a signature t mon[k] overflows an
+ * exponent lane), F4_E_NOMEM, F4_E_DEVICE. */
+int f4_sig_filter(f4_ctx* ctx, uint32_t p, const f4_polys* G, const f4_sigs* S, const f4_rowspec* R,
+                  uint32_t r, uint8_t* flags, f4_rowspec* kept, uint32_t* nkept, uint32_t* order,
+                  f4_sig_stats* st, void* stream);
+
+/* Symbolic preprocessing over the admissible reducers (Theorem
+ * "Signature-sound compilation"; the fixed point "propose rows, filter by
+ * signatures, close the dictionary for the filtered set, recheck coverage"):
+ * the rows R are deduplicated and filtered, then closed as in
+ * f4_build_matrix, except that a dictionary monomial m gets as reducer the
+ * active element g of largest index with LM(g) | m whose row (m / LM(g), g)
+ * is admissible, and no row when there is none.  Every row of the result is
+ * admissible.  G monic (as for f4_build_matrix), active: host bytes,
+ * S: signatures of G, R: host rows (r >= 1), A: out handle, st: out (may be
+ * NULL).  Errors as for f4_build_matrix and f4_sig_filter; F4_E_ARG also when
+ * no row of R is admissible. */
+int f4_build_matrix_sig(f4_ctx* ctx, uint32_t p, const f4_polys* G, const uint8_t* active, const f4_sigs* S,
+                        const f4_rowspec* R, uint32_t r, f4_matrix** A, f4_sig_stats* st, void* stream);
+
 /* A matrix from caller CSR arrays (host): r rows, N columns, entries sorted by
  * column within each row, values in [1, p).  Used to run f4_reduce on given
  * matrices.  dict_keys/row_t/row_k of the view are NULL for such a matrix. */

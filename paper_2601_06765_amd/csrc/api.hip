@@ -1341,22 +1341,29 @@ int f4_build_matrix(f4_ctx* X, uint32_t p, const f4_polys* G, const uint8_t* act
 // monomials up to the largest shift degree) and dropping repeats.
 // info: [0] error bits (1 bad index or shift word, 2 lane overflow),
 // [1] largest degree of t LM(g_k), [2] largest degree of t.
+#define ROWS_SLOTS 64
 __global__ void k_rows_check(const f4_rowspec* __restrict__ R, u32 r, const u64* __restrict__ lm, u32 npolys,
                              u32 n, u32 w, u32* info) {
     u32 err = 0, dmax = 0, tmax = 0;
     const u64 lanes = (1ull << (n * w)) - 1;
+    u64 H = 0;
+    for (u32 v = 0; v < n; ++v) H |= 1ull << (w * v + w - 1);
+    const u32 lmask = (1u << w) - 1;
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x) {
         const u64 t = R[i].t;
         const u32 k = R[i].k;
         u32 sum = 0;
-        for (u32 v = 0; v < n; ++v) sum += mono_exp(t, v, w);
+        u64 x = t & lanes;
+        for (u32 v = 0; v < n; ++v, x >>= w) sum += (u32)x & lmask;
         if (k >= npolys || (t & ~lanes & ((1ull << 56) - 1)) || sum != mono_deg(t)) {
             err |= 1;
             continue;
         }
         const u64 g = lm[k];
-        for (u32 v = 0; v < n; ++v)
-            if (mono_exp(t, v, w) + mono_exp(g, v, w) >= (1u << w)) err |= 2;
+        // lanes without their top bit cannot overflow when added
+        if ((t | g) & H)
+            for (u32 v = 0; v < n; ++v)
+                if (mono_exp(t, v, w) + mono_exp(g, v, w) >= (1u << w)) err |= 2;
         dmax = max(dmax, mono_deg(t) + mono_deg(g));
         tmax = max(tmax, mono_deg(t));
     }
@@ -1365,10 +1372,25 @@ __global__ void k_rows_check(const f4_rowspec* __restrict__ R, u32 r, const u64*
         dmax = max(dmax, (u32)__shfl_xor((int)dmax, (int)d, F4_WAVE));
         tmax = max(tmax, (u32)__shfl_xor((int)tmax, (int)d, F4_WAVE));
     }
+    // one of ROWS_SLOTS copies of the three words per block (atomics on one
+    // word serialise across the grid); the host combines the copies
     if (lane_id() == 0) {
-        if (err) atomicOr(&info[0], err);
-        atomicMax(&info[1], dmax);
-        atomicMax(&info[2], tmax);
+        u32* I = info + 4 * (blockIdx.x % ROWS_SLOTS);
+        if (err) atomicOr(&I[0], err);
+        if (dmax) atomicMax(&I[1], dmax);
+        if (tmax) atomicMax(&I[2], tmax);
+    }
+}
+
+// the copies of k_rows_check's words combined (err | ..., max, max)
+static void rows_info(Ctx& c, const u32* dinfo, u32 hi[4]) {
+    u32 slots[4 * ROWS_SLOTS];
+    readback(c, slots, dinfo, sizeof(slots));
+    hi[0] = hi[1] = hi[2] = hi[3] = 0;
+    for (int q = 0; q < ROWS_SLOTS; ++q) {
+        hi[0] |= slots[4 * q];
+        hi[1] = std::max(hi[1], slots[4 * q + 1]);
+        hi[2] = std::max(hi[2], slots[4 * q + 2]);
     }
 }
 
@@ -1388,32 +1410,29 @@ __global__ void k_rows_decode(const u64* __restrict__ keys, const u32* __restric
     }
 }
 
-int f4_build_matrix_rows(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_rowspec* R, uint32_t r, f4_matrix** A,
-                         void* stream) {
-    F4_API_BEGIN(X)
-    if (!A || !G || !R || !r || !is_odd_prime(p) || p >= (1u << 31)) throw F4Error{F4_E_ARG, "bad argument"};
-    *A = nullptr;
-    set_stream(X, stream);
-    Ctx& c = X->c;
+// An explicit row list planned on the device: checked, deduplicated and
+// decoded into (rt, rk) (r0 distinct rows); deg = the largest row degree.
+// Rd keeps the uploaded records.
+static void plan_rows(Ctx& c, const DevG& D, const f4_rowspec* R, u32 r, DBuf<u8>& Rd, DBuf<u64>& rt, DBuf<u32>& rk,
+                      u32& r0, u32& deg) {
     hipStream_t s = c.stream;
-    DevG D;
-    load_polys(c, p, G, D, false);
     if (D.npolys == 0) throw F4Error{F4_E_ARG, "row basis index out of range"};
     const u32 w = lane_bits(D.n);
     // the row list on the device, checked there
-    DBuf<u8> Rd(&c.pool, (u64)r * sizeof(f4_rowspec));
+    Rd.reset(&c.pool, (u64)r * sizeof(f4_rowspec));
     upload(c, Rd.ptr, R, (u64)r * sizeof(f4_rowspec));
     const f4_rowspec* Rdev = (const f4_rowspec*)Rd.ptr;
-    DBuf<u32> info(&c.pool, 4);
-    fill_u32(info.ptr, 4, 0, s);
+    DBuf<u32> info(&c.pool, 4 * ROWS_SLOTS);
+    fill_u32(info.ptr, 4 * ROWS_SLOTS, 0, s);
     const u32 grid = std::min<u32>(4096, ceil_div(r, 256));
     hipLaunchKernelGGL(k_rows_check, dim3(grid), dim3(256), 0, s, Rdev, r, D.lm.ptr, D.npolys, D.n, w, info.ptr);
     F4_LAUNCH_CHECK();
     u32 hi[4];
-    readback(c, hi, info.ptr, 16);
+    rows_info(c, info.ptr, hi);
     if (hi[0] & 1) throw F4Error{F4_E_ARG, "row basis index out of range or shift not a monomial"};
     if (hi[0] & 2) throw F4Error{F4_E_RANGE, "exponent lane overflow"};
-    const u32 deg = hi[1], Dt = hi[2];
+    deg = hi[1];
+    const u32 Dt = hi[2];
     if (deg >= (1u << w)) throw F4Error{F4_E_RANGE, "degree overflows an exponent lane"};
     const u64 nt = binom_host(D.n + Dt, D.n);
     if (nt * D.npolys >= (1ull << 63)) throw F4Error{F4_E_RANGE, "row keys do not fit 64 bits"};
@@ -1428,13 +1447,43 @@ int f4_build_matrix_rows(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_rows
     while (bits < 64 && (nt * D.npolys - 1) >> bits) ++bits;
     radix_sort_keys(keys.ptr, r, 0, bits, c.pool, s);
     unique_sorted_u64(keys.ptr, r, ukeys.ptr, cnt.ptr, c.pool, s);
-    u32 r0 = 0;
+    r0 = 0;
     readback(c, &r0, cnt.ptr, 4);
-    DBuf<u64> rt(&c.pool, std::max<u32>(r0, 1));
-    DBuf<u32> rk(&c.pool, std::max<u32>(r0, 1));
+    rt.reset(&c.pool, std::max<u32>(r0, 1));
+    rk.reset(&c.pool, std::max<u32>(r0, 1));
     hipLaunchKernelGGL(k_rows_decode, dim3(std::min<u32>(4096, ceil_div(r0, 256))), dim3(256), 0, s, ukeys.ptr,
                        cnt.ptr, D.npolys, montab, rt.ptr, rk.ptr);
     F4_LAUNCH_CHECK();
+}
+
+static f4_matrix* build_one(f4_ctx* X, u32 p, const BuildArgs& a) {
+    f4_matrix* M = new f4_matrix();
+    M->owner = X;
+    try {
+        build_batch(X->c, std::vector<BuildArgs>{a}, M->m);
+        M->m.built_p = p;
+    } catch (...) {
+        delete M;
+        throw;
+    }
+    X->matrices.insert(M);
+    return M;
+}
+
+int f4_build_matrix_rows(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_rowspec* R, uint32_t r, f4_matrix** A,
+                         void* stream) {
+    F4_API_BEGIN(X)
+    if (!A || !G || !R || !r || !is_odd_prime(p) || p >= (1u << 31)) throw F4Error{F4_E_ARG, "bad argument"};
+    *A = nullptr;
+    set_stream(X, stream);
+    Ctx& c = X->c;
+    DevG D;
+    load_polys(c, p, G, D, false);
+    DBuf<u8> Rd;
+    DBuf<u64> rt;
+    DBuf<u32> rk;
+    u32 r0 = 0, deg = 0;
+    plan_rows(c, D, R, r, Rd, rt, rk, r0, deg);
     BuildArgs a;
     a.G = devg_view(D);
     a.rows_t_dev = rt.ptr;
@@ -1443,17 +1492,155 @@ int f4_build_matrix_rows(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_rows
     a.nactive = 0;
     a.D = deg;
     a.closure = false;
-    f4_matrix* M = new f4_matrix();
-    M->owner = X;
-    try {
-        build_batch(c, std::vector<BuildArgs>{a}, M->m);
-        M->m.built_p = p;
-    } catch (...) {
-        delete M;
-        throw;
+    *A = build_one(X, p, a);
+    F4_API_END(X)
+}
+
+static void sig_of(Ctx& c, const DevG& D, const f4_sigs* S, SigBufs& out) {
+    if (!S || S->npolys != D.npolys) throw F4Error{F4_E_ARG, "signatures do not match the basis"};
+    sig_upload(c, D.n, D.npolys, S->index, S->mon, S->nindex, S->syz_off, S->syz_mon, out);
+}
+
+int f4_sig_filter(f4_ctx* X, uint32_t p, const f4_polys* G, const f4_sigs* S, const f4_rowspec* R, uint32_t r,
+                  uint8_t* flags, f4_rowspec* kept, uint32_t* nkept, uint32_t* order, f4_sig_stats* st,
+                  void* stream) {
+    F4_API_BEGIN(X)
+    if (!G || !R || !r || !nkept || !is_odd_prime(p) || p >= (1u << 31)) throw F4Error{F4_E_ARG, "bad argument"};
+    set_stream(X, stream);
+    Ctx& c = X->c;
+    hipStream_t s = c.stream;
+    DevG D;
+    load_polys(c, p, G, D, false);
+    if (D.npolys == 0) throw F4Error{F4_E_ARG, "row basis index out of range"};
+    SigBufs SB;
+    sig_of(c, D, S, SB);
+    const u32 w = lane_bits(D.n);
+    DBuf<u8> Rd(&c.pool, (u64)r * sizeof(f4_rowspec));
+    upload(c, Rd.ptr, R, (u64)r * sizeof(f4_rowspec));
+    u32 max_deg = 0;
+    {
+        DBuf<u32> info(&c.pool, 4 * ROWS_SLOTS);
+        fill_u32(info.ptr, 4 * ROWS_SLOTS, 0, s);
+        hipLaunchKernelGGL(k_rows_check, dim3(std::min<u32>(4096, ceil_div(r, 256))), dim3(256), 0, s,
+                           (const f4_rowspec*)Rd.ptr, r, D.lm.ptr, D.npolys, D.n, w, info.ptr);
+        F4_LAUNCH_CHECK();
+        u32 hi[4];
+        rows_info(c, info.ptr, hi);
+        if (hi[0] & 1) throw F4Error{F4_E_ARG, "row basis index out of range or shift not a monomial"};
+        if (hi[0] & 2) throw F4Error{F4_E_RANGE, "exponent lane overflow"};
+        max_deg = hi[1];
     }
-    X->matrices.insert(M);
-    *A = M;
+    u32 max_len = 1;
+    {
+        std::vector<u64> off(D.npolys + 1);
+        readback(c, off.data(), D.off.ptr, off.size() * 8);
+        for (u32 k = 0; k < D.npolys; ++k) max_len = std::max<u32>(max_len, (u32)(off[k + 1] - off[k]));
+    }
+    hipEvent_t e0, e1;
+    F4_HIP_TRY(hipEventCreate(&e0));
+    F4_HIP_TRY(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    DBuf<u8> fl(&c.pool, flags ? r : 1);
+    DBuf<u64> t2;
+    DBuf<u32> k2, cnt, ord;
+    u32 info[4];
+    F4_HIP_TRY(hipEventRecord(e0, s));
+    // the records are (t, k, pad): t every 2 words, k every 4 words from word 2
+    sig_filter_dev(c, SB, (const u64*)Rd.ptr, 2, (const u32*)Rd.ptr + 2, 4, r, flags ? fl.ptr : nullptr, t2, k2,
+                   cnt, info);
+    const u32 nk = info[1];
+    if (order) sig_schedule_dev(c, SB, t2.ptr, k2.ptr, cnt.ptr, nk, max_deg, max_len, D.lm.ptr, D.len.ptr, ord);
+    F4_HIP_TRY(hipEventRecord(e1, s));
+    if (flags) readback(c, flags, fl.ptr, r);
+    if (kept && nk) {
+        std::vector<u64> ht(nk);
+        std::vector<u32> hk(nk);
+        readback(c, ht.data(), t2.ptr, (u64)nk * 8);
+        readback(c, hk.data(), k2.ptr, (u64)nk * 4);
+        for (u32 q = 0; q < nk; ++q) {
+            kept[q].t = ht[q];
+            kept[q].k = hk[q];
+            kept[q].pad = 0;
+        }
+    }
+    if (order && nk) readback(c, order, ord.ptr, (u64)nk * 4);
+    F4_HIP_TRY(hipEventSynchronize(e1));
+    *nkept = nk;
+    if (st) {
+        st->kept = info[1];
+        st->syzygy = info[2];
+        st->rewritten = info[3];
+        st->pad = 0;
+        float ms = 0;
+        F4_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        st->t_device_ms = ms;
+    }
+    F4_API_END(X)
+}
+
+int f4_build_matrix_sig(f4_ctx* X, uint32_t p, const f4_polys* G, const uint8_t* active, const f4_sigs* S,
+                        const f4_rowspec* R, uint32_t r, f4_matrix** A, f4_sig_stats* st, void* stream) {
+    F4_API_BEGIN(X)
+    if (!A || !G || !active || !R || !r || !is_odd_prime(p) || p >= (1u << 31))
+        throw F4Error{F4_E_ARG, "bad argument"};
+    *A = nullptr;
+    set_stream(X, stream);
+    Ctx& c = X->c;
+    hipStream_t s = c.stream;
+    DevG D;
+    load_polys(c, p, G, D, true);
+    SigBufs SB;
+    sig_of(c, D, S, SB);
+    DBuf<u8> Rd;
+    DBuf<u64> rt, t2;
+    DBuf<u32> rk, k2, cnt;
+    u32 r0 = 0, deg = 0;
+    plan_rows(c, D, R, r, Rd, rt, rk, r0, deg);
+    hipEvent_t e0, e1;
+    F4_HIP_TRY(hipEventCreate(&e0));
+    F4_HIP_TRY(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    F4_HIP_TRY(hipEventRecord(e0, s));
+    u32 info[4];
+    sig_filter_dev(c, SB, rt.ptr, 1, rk.ptr, 1, r0, nullptr, t2, k2, cnt, info);
+    if (info[1] == 0) throw F4Error{F4_E_ARG, "no admissible row"};
+    std::vector<u32> act;
+    for (u32 g = D.npolys; g-- > 0;)
+        if (active[g]) act.push_back(g);
+    BuildArgs a;
+    a.G = devg_view(D);
+    a.rows_t_dev = t2.ptr;
+    a.rows_k_dev = k2.ptr;
+    a.r0 = info[1];
+    a.active_host = act.data();
+    a.nactive = (u32)act.size();
+    a.D = deg;
+    a.closure = true;
+    a.sig_dev = SB.dev;
+    *A = build_one(X, p, a);
+    F4_HIP_TRY(hipEventRecord(e1, s));
+    F4_HIP_TRY(hipEventSynchronize(e1));
+    if (st) {
+        st->kept = info[1];
+        st->syzygy = info[2];
+        st->rewritten = info[3];
+        st->pad = 0;
+        float ms = 0;
+        F4_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        st->t_device_ms = ms;
+    }
     F4_API_END(X)
 }
 

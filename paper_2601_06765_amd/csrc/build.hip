@@ -24,6 +24,7 @@
 #include <cstring>
 
 #include "internal.hpp"
+#include "sig.hpp"
 #include "sort_lds.hpp"
 
 #define MB_THREADS 256
@@ -94,10 +95,12 @@ struct SegSP {
     u32 ibase, r0;       // initial rows in the packed upload (or the device rows: room)
     const u32* r0p;      // device rows: the actual count, on the device (else nullptr)
     const u32* actp;     // the system's own device active list (else nullptr: the batch's list at abase)
+    const SigDev* sig;   // reducers restricted to admissible rows (else nullptr: any)
 };
 
 // counters per system: [0] row range begin, [1] row range end (= rows so
-// far), [2] unused, [3] error (1 bad monomial, 2 row capacity)
+// far), [2] unused, [3] error (1 bad monomial, 2 row capacity, 4 signature
+// overflow)
 #define CTR 4
 
 // ----------------------------------------------------------- row emission
@@ -266,6 +269,8 @@ __global__ __launch_bounds__(1024) void k_words_small(const SegSP* segs, u32 S, 
 
 // One reducer per frontier monomial m: the active element with the largest
 // index whose leading monomial divides m; the new row is (m / LM(g), g).
+// With signatures, the largest such index whose row is admissible (the
+// closure over the admissible reducers; m gets no row when there is none).
 // Grid (blocks, systems): a system's frontier entries are contiguous in the
 // list, and its active leading monomials are staged in LDS when they fit.
 __global__ __launch_bounds__(MB_THREADS) void k_reducers(const SegSP* segs, const u32* list_q, const u32* fscan,
@@ -300,11 +305,23 @@ __global__ __launch_bounds__(MB_THREADS) void k_reducers(const SegSP* segs, cons
                 const u64 l = lds_active ? slm[a] : S.lm[act[a]];
                 d = (mclean && !(l & H)) ? (((((m & lanes) | H) - (l & lanes)) & H) == H) : mono_divides(l, m, n, w);
             }
-            const u64 hit = wave_ballot(d);
-            if (hit) {
-                found = a0 + __ffsll((long long)hit) - 1;
-                break;
+            u64 hit = wave_ballot(d);
+            while (hit) {  // candidates in list order (descending index)
+                const u32 a = a0 + __ffsll((long long)hit) - 1;
+                if (!S.sig) {
+                    found = a;
+                    break;
+                }
+                const u64 l = lds_active ? slm[a] : S.lm[act[a]];
+                const u32 adm = sig_adm_wave(*S.sig, m - l, act[a]);
+                if (adm == SIG_OK) {
+                    found = a;
+                    break;
+                }
+                if (adm == SIG_OVERFLOW && lane == 0) ctr[CTR * s + 3] = 4u;
+                hit &= hit - 1;
             }
+            if (found != 0xffffffffu) break;
         }
         if (found != 0xffffffffu && lane == 0) {
             const u64 l = lds_active ? slm[found] : S.lm[act[found]];
@@ -714,6 +731,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         g.ibase = (u32)IB;
         g.r0 = a.r0;
         g.r0p = a.r0_dev;
+        g.sig = a.sig_dev;
         IB += a.r0;
         W += g.nwords;
         RC += g.rcap;
@@ -869,6 +887,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         readback(c, hs.data(), summary.ptr, hs.size() * 4);
         bool more = false;
         for (u32 i = 0; i < S; ++i) {
+            if (hs[8 * i + 2] == 4) throw F4Error{2, "a reducer's signature overflows an exponent lane"};
             if (hs[8 * i + 2])
                 throw F4Error{1, hs[8 * i + 2] == 1 ? "a row term is not a monomial of degree <= D (unsorted or "
                                                       "inconsistent input terms)"

@@ -360,6 +360,7 @@ struct BuildArgs {
     const u32* r0_dev = nullptr;       // device rows only: the actual count, on the device
     const u32* active_host = nullptr;  // active basis indices in descending order, host
     const u32* active_dev = nullptr;   // or on the device (this system's own list)
+    const struct SigDev* sig_dev = nullptr;  // device descriptor: closure over admissible reducers only
     u32 nactive = 0;
     u32 D = 0;                         // largest degree of any row
     bool closure = true;
@@ -415,6 +416,31 @@ struct GmSelect {
     u32 row_base;
 };
 u32* gm_select_batch(Ctx& c, const std::vector<GmSelect>& v, u64* rows_t, u32* rows_k, DBuf<u64>& keep);
+
+// ----------------------------------------------------------- signatures
+// Signatures of a basis on the device (one block: the descriptor and its
+// arrays); dev points at the descriptor.
+struct SigBufs {
+    DBuf<u8> blob;
+    const struct SigDev* dev = nullptr;
+    const u32* sidx = nullptr;  // signature index of each element (in blob)
+    size_t lds_bytes = 0;       // the tables' size (copied to LDS by the filter when small)
+    u32 nindex = 0;
+};
+// Checks and uploads signatures (element k: mon[k] e_index[k]; index i's
+// syzygy monomials syz_mon[syz_off[i] .. syz_off[i+1])).
+void sig_upload(Ctx& c, u32 n, u32 npolys, const u32* index, const u64* mon, u32 nindex, const u32* syz_off,
+                const u64* syz_mon, SigBufs& out);
+// Flags of r rows (t[q*ts], k[q*ks]) (flags may be nullptr), the admissible
+// ones compacted in input order into t2 / k2 with their count on the device;
+// info_out (read back): overflow, kept, syzygy, rewritten.
+void sig_filter_dev(Ctx& c, const SigBufs& S, const u64* t, u32 ts, const u32* k, u32 ks, u32 r, u8* flags,
+                    DBuf<u64>& t2, DBuf<u32>& k2, DBuf<u32>& count, u32 info_out[4]);
+// Schedule of the nkept survivors: positions sorted by (row degree, length of
+// g_k, signature index), ties in input order; max_deg / max_len bound the
+// row degrees and lengths (the key is as wide as they need).
+void sig_schedule_dev(Ctx& c, const SigBufs& S, const u64* t2, const u32* k2, const u32* count, u32 nkept,
+                      u32 max_deg, u32 max_len, const u64* lm, const u32* len, DBuf<u32>& order);
 
 // ----------------------------------------------------------- elimination
 struct RedPart {

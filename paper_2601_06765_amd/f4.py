@@ -49,6 +49,19 @@ class RowSpec(ctypes.Structure):
     _fields_ = [("t", c_u64), ("k", c_u32), ("pad", c_u32)]
 
 
+class Sigs(ctypes.Structure):
+    _fields_ = [("npolys", c_u32), ("index", c_vp), ("mon", c_vp), ("nindex", c_u32), ("syz_off", c_vp),
+                ("syz_mon", c_vp)]
+
+
+class SigStats(ctypes.Structure):
+    _fields_ = [("kept", c_u32), ("syzygy", c_u32), ("rewritten", c_u32), ("pad", c_u32),
+                ("t_device_ms", ctypes.c_double)]
+
+
+F4_ADM_OK, F4_ADM_SYZYGY, F4_ADM_REWRITTEN = 0, 1, 2
+
+
 class MatrixView(ctypes.Structure):
     _fields_ = [("n", c_u32), ("r", c_u32), ("N", c_u32), ("deg", c_u32), ("nnz", c_u64),
                 ("row_ptr", c_vp), ("col_ind", c_vp), ("val", c_vp), ("dict_keys", c_vp),
@@ -94,6 +107,10 @@ _sig("f4_grevlex_rank", c_int, [c_u32, c_u32, c_u64, P(c_u32)])
 _sig("f4_grevlex_unrank", c_int, [c_u32, c_u32, c_u32, P(c_u64)])
 _sig("f4_build_matrix", c_int, [c_vp, c_u32, P(Polys), P(ctypes.c_uint8), P(Pair), c_u32, P(c_vp), c_vp])
 _sig("f4_build_matrix_rows", c_int, [c_vp, c_u32, P(Polys), P(RowSpec), c_u32, P(c_vp), c_vp])
+_sig("f4_sig_filter", c_int, [c_vp, c_u32, P(Polys), P(Sigs), P(RowSpec), c_u32, c_vp, P(RowSpec), P(c_u32),
+                              P(c_u32), P(SigStats), c_vp])
+_sig("f4_build_matrix_sig", c_int, [c_vp, c_u32, P(Polys), c_vp, P(Sigs), P(RowSpec), c_u32, P(c_vp),
+                                    P(SigStats), c_vp])
 _sig("f4_matrix_from_csr", c_int, [c_vp, c_u32, c_u32, P(c_u32), P(c_u32), P(c_u32), P(c_vp), c_vp])
 _sig("f4_matrix_get", c_int, [c_vp, P(MatrixView)])
 _sig("f4_matrix_free", c_int, [c_vp])
@@ -270,6 +287,10 @@ class _PolysArg:
         self.keep = (mon, coeff, off)
         k = len(off) - 1 if npolys is None else npolys
         self.s = Polys(n, k, _ptr(mon), _ptr(coeff), _ptr(off), 1 if on_device else 0)
+
+
+def _sigstats(st):
+    return {"kept": st.kept, "syzygy": st.syzygy, "rewritten": st.rewritten, "t_device_ms": st.t_device_ms}
 
 
 # --------------------------------------------------------------- context
@@ -461,6 +482,85 @@ class Context:
         self._check(_lib.f4_build_matrix_rows(self._h, p, ctypes.byref(arg.s), rs.ctypes.data_as(P(RowSpec)),
                                               len(rs), ctypes.byref(h), c_vp(stream)))
         return Matrix(self, h, n)
+
+    # -- signatures
+    @staticmethod
+    def _sigs(n, sig_index, sig_mon, syz):
+        """Marshal signatures: sig_index[k], sig_mon[k] (exps) per element and
+        syz[i] (list of exps) per index.  Returns (Sigs, keep-alive arrays)."""
+        idx = np.ascontiguousarray(np.asarray(sig_index, dtype=np.uint32))
+        mon = np.ascontiguousarray(pack_many(n, [tuple(e) for e in sig_mon]) if len(sig_mon)
+                                   else np.zeros(0, dtype=np.uint64))
+        off = np.zeros(len(syz) + 1, dtype=np.uint32)
+        flat = []
+        for i, lst in enumerate(syz):
+            flat += [tuple(e) for e in lst]
+            off[i + 1] = len(flat)
+        smon = np.ascontiguousarray(pack_many(n, flat) if flat else np.zeros(1, dtype=np.uint64))
+        sg = Sigs(len(idx), idx.ctypes.data, mon.ctypes.data, len(syz), off.ctypes.data, smon.ctypes.data)
+        return sg, (idx, mon, off, smon)
+
+    @staticmethod
+    def _rows(n, rows):
+        rs = np.zeros(len(rows), dtype=np.dtype([("t", "<u8"), ("k", "<u4"), ("pad", "<u4")]))
+        if len(rows):
+            rs["t"] = pack_many(n, [tuple(t) for t, _ in rows])
+            rs["k"] = np.asarray([k for _, k in rows], dtype=np.uint32)
+        return rs
+
+    def sig_filter(self, p, n, G, sig_index, sig_mon, syz, rows, stream=None):
+        """f4_sig_filter: (flags, kept rows, schedule, stats) for rows
+        [(t exps, k), ...] of the basis G (library input form)."""
+        arg = _PolysArg(n, *polys_to_arrays(n, G))
+        sg, keep = self._sigs(n, sig_index, sig_mon, syz)
+        rs = self._rows(n, rows)
+        r = len(rs)
+        flags = np.zeros(r, dtype=np.uint8)
+        kept = np.zeros(r, dtype=rs.dtype)
+        order = np.zeros(r, dtype=np.uint32)
+        nk = c_u32()
+        st = SigStats()
+        self._check(_lib.f4_sig_filter(self._h, p, ctypes.byref(arg.s), ctypes.byref(sg),
+                                       rs.ctypes.data_as(P(RowSpec)), r, flags.ctypes.data_as(c_vp),
+                                       kept.ctypes.data_as(P(RowSpec)), ctypes.byref(nk),
+                                       order.ctypes.data_as(P(c_u32)), ctypes.byref(st), c_vp(stream)))
+        k = nk.value
+        kept_rows = [(unpack(n, int(kept["t"][q])), int(kept["k"][q])) for q in range(k)]
+        return flags, kept_rows, [int(x) for x in order[:k]], _sigstats(st)
+
+    def sig_filter_packed(self, p, n, G, sigs_packed, t_words, ks, schedule=True, stream=None):
+        """f4_sig_filter on rows given as arrays (P words, indices), with
+        signatures already marshalled by _sigs; returns (flags, nkept, order,
+        stats) without unpacking the kept rows (order None without the
+        schedule)."""
+        arg = _PolysArg(n, *polys_to_arrays(n, G))
+        sg, _keep = sigs_packed
+        rs = np.zeros(len(t_words), dtype=np.dtype([("t", "<u8"), ("k", "<u4"), ("pad", "<u4")]))
+        rs["t"] = np.asarray(t_words, dtype=np.uint64)
+        rs["k"] = np.asarray(ks, dtype=np.uint32)
+        r = len(rs)
+        flags = np.zeros(r, dtype=np.uint8)
+        order = np.zeros(r, dtype=np.uint32)
+        nk = c_u32()
+        st = SigStats()
+        self._check(_lib.f4_sig_filter(self._h, p, ctypes.byref(arg.s), ctypes.byref(sg),
+                                       rs.ctypes.data_as(P(RowSpec)), r, flags.ctypes.data_as(c_vp), None,
+                                       ctypes.byref(nk), order.ctypes.data_as(P(c_u32)) if schedule else None,
+                                       ctypes.byref(st), c_vp(stream)))
+        return flags, nk.value, (order[:nk.value] if schedule else None), _sigstats(st)
+
+    def build_matrix_sig(self, p, n, G, active, sig_index, sig_mon, syz, rows, stream=None):
+        """f4_build_matrix_sig: (Matrix, stats)."""
+        arg = _PolysArg(n, *polys_to_arrays(n, G))
+        sg, keep = self._sigs(n, sig_index, sig_mon, syz)
+        rs = self._rows(n, rows)
+        act = np.array([1 if a else 0 for a in active], dtype=np.uint8)
+        h = c_vp()
+        st = SigStats()
+        self._check(_lib.f4_build_matrix_sig(self._h, p, ctypes.byref(arg.s), act.ctypes.data_as(c_vp),
+                                             ctypes.byref(sg), rs.ctypes.data_as(P(RowSpec)), len(rs),
+                                             ctypes.byref(h), ctypes.byref(st), c_vp(stream)))
+        return Matrix(self, h, n), _sigstats(st)
 
     def device_array(self, shape):
         """A block of u32 words in device memory from this context's cache."""

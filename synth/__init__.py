@@ -267,3 +267,28 @@ def planted_system(n, m, p, seed):
         f.append((tuple([0] * n), (p - val) % p))
         polys.append(f)
     return polys, s
+
+
+def signatures(leads, m_index, seed, max_deg=2):
+    """Synthetic signatures for a basis whose elements have the exponent
+    vectors ``leads`` (one per element, e.g. its leading exponents): the
+    first ``m_index`` elements get index k and the exponent vector 0 (input
+    polynomials); every later element a uniform index below ``m_index`` and an
+    exponent vector obtained from its lead by removing uniformly chosen unit
+    exponents until at most ``max_deg`` remain (a divisor of the lead).
+    Returns (index list, exponent-vector list)."""
+    rng = SplitMix64((9 << 32) + seed)
+    idx, mon = [], []
+    for k, e in enumerate(leads):
+        n = len(e)
+        if k < m_index:
+            idx.append(k)
+            mon.append((0,) * n)
+            continue
+        idx.append(rng.below(m_index))
+        v = list(e)
+        while sum(v) > max_deg:
+            nz = [q for q in range(n) if v[q]]
+            v[nz[rng.below(len(nz))]] -= 1
+        mon.append(tuple(v))
+    return idx, mon

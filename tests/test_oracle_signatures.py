@@ -153,22 +153,7 @@ def test_unconstrained_closure_is_o1(cfg):
 
 def synthetic_signatures(G, n, m_index, seed):
     """Signature index and monomial per element (input-like elements first)."""
-    rng = random.Random(seed)
-    sidx, smon = [], []
-    for k, g in enumerate(G):
-        lm = o7.lead(g)
-        if k < m_index:
-            sidx.append(k)
-            smon.append((0,) * n)
-        else:
-            sidx.append(rng.randrange(m_index))
-            # a divisor of LM(g) of degree up to 2: signatures stay below the leading terms
-            e = list(lm)
-            while sum(e) > 2:
-                q = rng.choice([v for v in range(n) if e[v]])
-                e[q] -= 1
-            smon.append(tuple(e))
-    return sidx, smon
+    return synth.signatures([o7.lead(g) for g in G], m_index, seed)
 
 
 @pytest.mark.parametrize("cfg,m_index,seed", [(1, 7, 5), (1, 3, 6)])
