@@ -58,6 +58,9 @@ def parse():
                     help="shift degree of the Macaulay matrix of the block Wiedemann leg (-1: skip)")
     ap.add_argument("--sig-shift-deg", type=int, default=8,
                     help="shift degree of the rows of the signature-filter leg (0: skip)")
+    ap.add_argument("--mw-vars", type=int, default=20,
+                    help="variables of the two-word-key Macaulay leg (0: skip)")
+    ap.add_argument("--mw-shift-deg", type=int, default=5, help="shift degree of that leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed schedules instead of the autotuner's measured picks (tuned during warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -470,6 +473,52 @@ def signature_leg(f4, shift_deg, build_shift_deg, reps):
     return res
 
 
+def multiword_leg(f4, n, shift_deg, reps):
+    """Two-word monomial keys (f4_build_matrix_rows_mw): the Macaulay matrix of
+    n+1 sparse quadratics in n > 14 variables (20 terms each, F_65521, seeded)
+    with rows t*f_i for every t of degree <= shift_deg; wall time of the call
+    after a warm-up (median of `reps`), nonzeros per second and algorithmic
+    bytes (8 nnz for the CSR out, 24 r for the row records in and the row
+    metadata out, 16 N for the dictionary), then A X on 8 vectors with the
+    resulting handle (HIP events)."""
+    import numpy as np
+    import synth
+    p = 65521
+    G = f4.normalize_mw(p, n, synth.sparse_quadratics(n, n + 1, 11, p - 1, 20))
+    m = len(G)
+    t = f4.pack_many_mw(n, synth.monomials_upto(n, shift_deg))
+    tw = np.repeat(t, m, axis=0)
+    ks = np.tile(np.arange(m, dtype=np.uint32), len(t))
+    ctx = f4.Context(0)
+    A = ctx.build_matrix_rows_mw_packed(p, n, G, tw, ks)
+    A.free()
+    walls = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        A = ctx.build_matrix_rows_mw_packed(p, n, G, tw, ks)
+        ctx.download(A.view.row_ptr, 1, np.uint32)
+        walls.append(time.perf_counter() - t0)
+        r, N, nnz = A.view.r, A.view.N, A.view.nnz
+        A.free()
+    w = statistics.median(walls)
+    A = ctx.build_matrix_rows_mw_packed(p, n, G, tw, ks)
+    rng = np.random.default_rng(3)
+    X = ctx.to_device(rng.integers(0, p, size=(N, 8), dtype=np.int64))
+    Y = ctx.device_array((r, 8))
+    ctx.spmm(p, A, X, out=Y)
+    _, ms = ctx.spmm_timed(p, A, X, out=Y, reps=10)
+    X.free()
+    Y.free()
+    A.free()
+    ctx.close()
+    byts = 8 * nnz + 24 * r + 16 * N
+    return {"workload": "Macaulay matrix of %d sparse quadratics (20 terms each, F_65521, seed 11) in n=%d "
+                        "variables (two-word keys, %d-bit lanes), shifts of degree <= %d"
+                        % (m, n, f4._lib.f4_mw_lane_bits(n), shift_deg),
+            "r": r, "N": N, "nnz": nnz, "build_wall_ms": round(w * 1e3, 3), "build_nnz_per_s": nnz / w,
+            "build_alg_GBs": round(byts / w / 1e9, 1), "ax_b8_ms": round(ms, 4)}
+
+
 def modloop_leg(f4, nchains, iters):
     """Modular inner-loop microbenchmark (randomized residues, seed 5): the
     update rate of each arithmetic form, its registers and spill bytes per
@@ -676,6 +725,8 @@ def main():
             out["block_wiedemann"] = wiedemann_leg(f4, args.wiedemann_shift_deg, 8)
         if args.sig_shift_deg:
             out["signatures"] = signature_leg(f4, args.sig_shift_deg, 3, 5)
+        if args.mw_vars:
+            out["multiword"] = multiword_leg(f4, args.mw_vars, args.mw_shift_deg, 5)
         if args.batch_systems:
             out["batch"] = batch_leg(f4, torch, args.batch_systems, tune)
             out["systems_per_s_batched"] = out["batch"]["systems_per_s_batched"]

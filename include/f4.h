@@ -143,6 +143,24 @@ uint32_t f4_lane_bits(uint32_t n);
 int f4_pack(uint32_t n, const uint32_t* exps, uint64_t* out);
 /* Unpack a P word into n exponents. */
 int f4_unpack(uint32_t n, uint64_t word, uint32_t* exps);
+/* Two-word monomial keys for 1 <= n <= 30 variables (section "Monomial keys:
+ * order-refining encodings that make sorting feasible", multiword keys): a
+ * monomial is two words read as one 128-bit number, word 0 the high half.
+ * Bits 120..127 hold the degree; below it come the exponents of x_n, x_{n-1},
+ * ..., x_1 in lanes of w = f4_mw_lane_bits(n) bits, floor(56/w) lanes in
+ * word 0 (from bit 56 down) and the rest in word 1 (from bit 64 down), no
+ * lane split between the words, unused bits zero.  Complementing the lanes
+ * (not the degree) gives the order key: comparing keys as 128-bit numbers is
+ * grevlex (x_1 > ... > x_n), the key refines the order (no two monomials
+ * share one), and a product is the word-wise sum while no lane overflows. */
+/* w(n): 8 for n <= 15, 7 for n <= 17, 6 for n <= 19, 5 for n <= 23, 4 for
+ * n <= 30, 0 otherwise. */
+uint32_t f4_mw_lane_bits(uint32_t n);
+/* Pack n exponents into two words (out[0] high).  F4_E_RANGE if an exponent
+ * exceeds 2^w-1 or the degree 255; F4_E_ARG for a bad n. */
+int f4_pack_mw(uint32_t n, const uint32_t* exps, uint64_t* out);
+/* Unpack two words (in[0] high) into n exponents. */
+int f4_unpack_mw(uint32_t n, const uint64_t* in, uint32_t* exps);
 /* Dense grevlex rank of a monomial of degree <= D among the N(n, D) =
  * C(n+D, n) monomials of degree <= D (equation "monomial-count"): rank 0 is the
  * largest monomial x_1^D, and ranks increase as monomials decrease, so sorting
@@ -208,9 +226,11 @@ typedef struct f4_matrix_view {
     const uint32_t* row_ptr;   /* device, r + 1: exclusive scan of row lengths */
     const uint32_t* col_ind;   /* device, nnz: column of each entry, ascending per row */
     const uint32_t* val;       /* device, nnz: coefficient in [1, p) */
-    const uint64_t* dict_keys; /* device, N: P word of each column, descending grevlex */
-    const uint64_t* row_t;     /* device, r: shift monomial t_i (P word) */
+    const uint64_t* dict_keys; /* device, N * key_words: monomial of each column, descending grevlex */
+    const uint64_t* row_t;     /* device, r * key_words: shift monomial t_i */
     const uint32_t* row_k;     /* device, r: basis index k_i */
+    uint32_t key_words;        /* words per monomial: 1 (P words) or 2 (f4_build_matrix_rows_mw) */
+    uint32_t pad;
 } f4_matrix_view;
 
 /* Symbolic preprocessing of one F4 step (Definition "Symbolic preprocessing
@@ -307,6 +327,50 @@ int f4_sig_filter(f4_ctx* ctx, uint32_t p, const f4_polys* G, const f4_sigs* S, 
  * no row of R is admissible. */
 int f4_build_matrix_sig(f4_ctx* ctx, uint32_t p, const f4_polys* G, const uint8_t* active, const f4_sigs* S,
                         const f4_rowspec* R, uint32_t r, f4_matrix** A, f4_sig_stats* st, void* stream);
+
+/* ------------------------------------------------ multiword monomial keys */
+/* Host SoA polynomials with two-word monomials (f4_pack_mw): mon holds
+ * 2 words per term (high word first), terms of each polynomial in strictly
+ * decreasing grevlex, coefficients in [1, p), no zero polynomial. */
+typedef struct f4_polys_mw {
+    uint32_t n;               /* 1 .. 30 */
+    uint32_t npolys;
+    const uint64_t* mon;      /* 2 * offset[npolys] words */
+    const uint32_t* coeff;
+    const uint64_t* offset;   /* npolys + 1 entries */
+} f4_polys_mw;
+
+/* f4_normalize_polys for two-word monomials: terms sorted by decreasing
+ * grevlex (order keys as 128-bit numbers), repeats merged, coefficients
+ * reduced mod p, zero terms dropped.  mon_out has room for 2 words per input
+ * term, coeff_out for one, off_out for npolys + 1 offsets.  Host-side.
+ * F4_E_ARG: bad p or n, a word pair that is not a monomial, decreasing
+ * offsets, null arrays. */
+int f4_normalize_polys_mw(uint32_t p, const f4_polys_mw* in, uint64_t* mon_out, uint32_t* coeff_out,
+                          uint64_t* off_out);
+
+/* A shifted reducer t * g_k with a two-word shift (t[0] high). */
+typedef struct f4_rowspec_mw {
+    uint64_t t[2];
+    uint32_t k;
+    uint32_t pad;
+} f4_rowspec_mw;
+
+/* f4_build_matrix_rows for n up to 30 variables with two-word keys: the
+ * matrix of the explicit row list R (Definition "Sparse Macaulay matrix for a
+ * batch" for T = union of supports, R; no closure): every row's terms are
+ * shifted (word-wise sums), their order keys sorted as 128-bit numbers by two
+ * stable 64-bit radix sorts (low word, then high word), repeats dropped, and
+ * each term joined to its key's rank; rows in the usual order (leading
+ * monomial descending, then k; repeated (t, k) collapse).  The view has
+ * key_words = 2 (dict_keys and row_t two words per entry).  The matrix works
+ * with f4_reduce, f4_spmm and f4_block_wiedemann like any other.  G and R are
+ * host arrays checked on the host (G) and the device (R: k in range, t a
+ * monomial, t * LM(g_k) without lane overflow).  Errors: F4_E_ARG (bad p, G,
+ * a row), F4_E_RANGE (lane overflow, 2^32 or more nonzeros), F4_E_NOMEM,
+ * F4_E_DEVICE. */
+int f4_build_matrix_rows_mw(f4_ctx* ctx, uint32_t p, const f4_polys_mw* G, const f4_rowspec_mw* R, uint32_t r,
+                            f4_matrix** A, void* stream);
 
 /* A matrix from caller CSR arrays (host): r rows, N columns, entries sorted by
  * column within each row, values in [1, p).  Used to run f4_reduce on given

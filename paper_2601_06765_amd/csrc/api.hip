@@ -20,6 +20,7 @@
 
 #include "../../include/f4.h"
 #include "internal.hpp"
+#include "mw.hpp"
 
 // ------------------------------------------------------------ handles
 struct f4_matrix;
@@ -1280,6 +1281,123 @@ int f4_normalize_polys(uint32_t p, const f4_polys* in, int monic, uint64_t* mon_
     return F4_OK;
 }
 
+uint32_t f4_mw_lane_bits(uint32_t n) { return mw_lane_bits(n); }
+
+int f4_pack_mw(uint32_t n, const uint32_t* exps, uint64_t* out) {
+    if (!exps || !out) return F4_E_ARG;
+    const MwLayout L = mw_layout(n);
+    if (!L.w) return F4_E_ARG;
+    u64 m[2] = {0, 0};
+    u32 d = 0;
+    for (u32 v = 0; v < n; ++v) {
+        if (exps[v] >= (1u << L.w)) return F4_E_RANGE;
+        const u32 p = n - 1 - v;
+        if (p < L.a)
+            m[0] |= (u64)exps[v] << (56 - (p + 1) * L.w);
+        else
+            m[1] |= (u64)exps[v] << (64 - (p - L.a + 1) * L.w);
+        d += exps[v];
+    }
+    if (d > 255) return F4_E_RANGE;
+    out[0] = m[0] | ((u64)d << 56);
+    out[1] = m[1];
+    return F4_OK;
+}
+
+int f4_unpack_mw(uint32_t n, const uint64_t* in, uint32_t* exps) {
+    const MwLayout L = mw_layout(n);
+    if (!L.w || !in || !exps) return F4_E_ARG;
+    for (u32 v = 0; v < n; ++v) exps[v] = mw_exp(L, in[0], in[1], v);
+    return F4_OK;
+}
+
+int f4_normalize_polys_mw(uint32_t p, const f4_polys_mw* in, uint64_t* mon_out, uint32_t* coeff_out,
+                          uint64_t* off_out) {
+    if (!in || !in->offset || !off_out || !is_odd_prime(p) || p >= (1u << 31)) return F4_E_ARG;
+    const MwLayout L = mw_layout(in->n);
+    if (!L.w) return F4_E_ARG;
+    const u64 nt = in->offset[in->npolys];
+    if (nt && (!in->mon || !in->coeff || !mon_out || !coeff_out)) return F4_E_ARG;
+    struct Term {
+        u64 k0, k1;  // order key
+        u32 c;
+    };
+    try {
+        std::vector<Term> f;
+        u64 o = 0;
+        off_out[0] = 0;
+        for (u32 k = 0; k < in->npolys; ++k) {
+            if (in->offset[k + 1] < in->offset[k]) return F4_E_ARG;
+            f.clear();
+            for (u64 e = in->offset[k]; e < in->offset[k + 1]; ++e) {
+                const u64 m0 = in->mon[2 * e], m1 = in->mon[2 * e + 1];
+                if (!mw_valid(L, m0, m1)) return F4_E_ARG;
+                f.push_back({m0 ^ L.lanes0, m1 ^ L.lanes1, (u32)(in->coeff[e] % p)});
+            }
+            std::sort(f.begin(), f.end(), [](const Term& a, const Term& b) {
+                return a.k0 != b.k0 ? a.k0 > b.k0 : a.k1 > b.k1;
+            });
+            for (size_t i = 0; i < f.size();) {
+                u64 sum = 0;
+                size_t j = i;
+                for (; j < f.size() && f[j].k0 == f[i].k0 && f[j].k1 == f[i].k1; ++j) sum += f[j].c;
+                const u32 cf = (u32)(sum % p);
+                if (cf) {
+                    mon_out[2 * o] = f[i].k0 ^ L.lanes0;
+                    mon_out[2 * o + 1] = f[i].k1 ^ L.lanes1;
+                    coeff_out[o] = cf;
+                    ++o;
+                }
+                i = j;
+            }
+            off_out[k + 1] = o;
+        }
+    } catch (const std::bad_alloc&) {
+        return F4_E_NOMEM;
+    }
+    return F4_OK;
+}
+
+int f4_build_matrix_rows_mw(f4_ctx* X, uint32_t p, const f4_polys_mw* G, const f4_rowspec_mw* R, uint32_t r,
+                            f4_matrix** A, void* stream) {
+    F4_API_BEGIN(X)
+    if (!A || !G || !R || !r || !is_odd_prime(p) || p >= (1u << 31)) throw F4Error{F4_E_ARG, "bad argument"};
+    *A = nullptr;
+    const MwLayout L = mw_layout(G->n);
+    if (!L.w) throw F4Error{F4_E_ARG, "bad number of variables"};
+    if (!G->offset || !G->npolys || !G->mon || !G->coeff) throw F4Error{F4_E_ARG, "null basis array"};
+    set_stream(X, stream);
+    // the basis form, on the host: monomials, strictly decreasing order keys
+    // (high words, then low words), coefficients in [1, p), no empty polynomial
+    const u64* off = G->offset;
+    if (off[0] != 0) throw F4Error{F4_E_ARG, "offsets must start at 0"};
+    for (u32 k = 0; k < G->npolys; ++k) {
+        if (off[k + 1] <= off[k]) throw F4Error{F4_E_ARG, "a zero polynomial"};
+        for (u64 e = off[k]; e < off[k + 1]; ++e) {
+            const u64 m0 = G->mon[2 * e], m1 = G->mon[2 * e + 1];
+            if (!mw_valid(L, m0, m1)) throw F4Error{F4_E_ARG, "a word pair that is not a monomial of n variables"};
+            if (G->coeff[e] == 0 || G->coeff[e] >= p) throw F4Error{F4_E_ARG, "coefficient outside [1, p)"};
+            if (e > off[k]) {
+                const u64 a0 = G->mon[2 * e - 2] ^ L.lanes0, a1 = G->mon[2 * e - 1] ^ L.lanes1;
+                const u64 b0 = m0 ^ L.lanes0, b1 = m1 ^ L.lanes1;
+                if (!(a0 > b0 || (a0 == b0 && a1 > b1))) throw F4Error{F4_E_ARG, "terms not in decreasing grevlex"};
+            }
+        }
+    }
+    f4_matrix* M = new f4_matrix();
+    M->owner = X;
+    try {
+        build_rows_mw(X->c, G->n, G->npolys, G->mon, G->coeff, off, R, r, M->m);
+        M->m.built_p = p;
+    } catch (...) {
+        delete M;
+        throw;
+    }
+    X->matrices.insert(M);
+    *A = M;
+    F4_API_END(X)
+}
+
 int f4_unpack(uint32_t n, uint64_t word, uint32_t* exps) {
     const u32 w = lane_bits(n);
     if (!w || !exps) return F4_E_ARG;
@@ -1979,6 +2097,8 @@ int f4_matrix_get(const f4_matrix* A, f4_matrix_view* out) {
     out->dict_keys = m.dict_keys.ptr;
     out->row_t = m.row_t.ptr;
     out->row_k = m.row_k.ptr;
+    out->key_words = m.key_words;
+    out->pad = 0;
     return F4_OK;
 }
 

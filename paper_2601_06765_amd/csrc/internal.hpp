@@ -331,6 +331,7 @@ struct SysPart {
 
 struct Matrix {
     u32 S = 0, R = 0;
+    u32 key_words = 1;  // words per monomial in dict_keys / row_t (2: two-word keys)
     u32 built_p = 0;  // prime the values were checked against (0: a caller CSR, not checked)
     u64 nnz = 0;
     std::vector<SysPart> sys;
@@ -416,6 +417,12 @@ struct GmSelect {
     u32 row_base;
 };
 u32* gm_select_batch(Ctx& c, const std::vector<GmSelect>& v, u64* rows_t, u32* rows_k, DBuf<u64>& keep);
+
+// ------------------------------------------------- two-word monomial keys
+// The matrix of an explicit row list with two-word monomials (records of
+// f4_rowspec_mw), basis as host SoA arrays already checked; out: key_words 2.
+void build_rows_mw(Ctx& c, u32 n, u32 npolys, const u64* mon_h, const u32* coeff_h, const u64* off_h,
+                   const void* rows_h, u32 r, Matrix& out);
 
 // ----------------------------------------------------------- signatures
 // Signatures of a basis on the device (one block: the descriptor and its

@@ -65,7 +65,15 @@ F4_ADM_OK, F4_ADM_SYZYGY, F4_ADM_REWRITTEN = 0, 1, 2
 class MatrixView(ctypes.Structure):
     _fields_ = [("n", c_u32), ("r", c_u32), ("N", c_u32), ("deg", c_u32), ("nnz", c_u64),
                 ("row_ptr", c_vp), ("col_ind", c_vp), ("val", c_vp), ("dict_keys", c_vp),
-                ("row_t", c_vp), ("row_k", c_vp)]
+                ("row_t", c_vp), ("row_k", c_vp), ("key_words", c_u32), ("pad", c_u32)]
+
+
+class PolysMW(ctypes.Structure):
+    _fields_ = [("n", c_u32), ("npolys", c_u32), ("mon", c_vp), ("coeff", c_vp), ("offset", c_vp)]
+
+
+class RowSpecMW(ctypes.Structure):
+    _fields_ = [("t0", c_u64), ("t1", c_u64), ("k", c_u32), ("pad", c_u32)]
 
 
 class ReducedView(ctypes.Structure):
@@ -101,6 +109,11 @@ _sig("f4_tune_import", c_int, [c_vp, ctypes.c_char_p])
 _sig("f4_lane_bits", c_u32, [c_u32])
 _sig("f4_pack", c_int, [c_u32, P(c_u32), P(c_u64)])
 _sig("f4_unpack", c_int, [c_u32, c_u64, P(c_u32)])
+_sig("f4_mw_lane_bits", c_u32, [c_u32])
+_sig("f4_pack_mw", c_int, [c_u32, P(c_u32), P(c_u64)])
+_sig("f4_unpack_mw", c_int, [c_u32, P(c_u64), P(c_u32)])
+_sig("f4_build_matrix_rows_mw", c_int, [c_vp, c_u32, P(PolysMW), P(RowSpecMW), c_u32, P(c_vp), c_vp])
+_sig("f4_normalize_polys_mw", c_int, [c_u32, P(PolysMW), P(c_u64), P(c_u32), P(c_u64)])
 _sig("f4_check_polys", c_int, [c_u32, P(Polys), c_int, P(c_u32)])
 _sig("f4_normalize_polys", c_int, [c_u32, P(Polys), c_int, P(c_u64), P(c_u32), P(c_u64)])
 _sig("f4_grevlex_rank", c_int, [c_u32, c_u32, c_u64, P(c_u32)])
@@ -185,6 +198,84 @@ def unpack(n, word):
     if rc:
         raise F4Error(rc, "cannot unpack")
     return tuple(arr)
+
+
+def pack_mw(n, exps):
+    """Two-word monomial (high word first) of n <= 30 exponents (f4_pack_mw)."""
+    arr = (c_u32 * n)(*[int(x) for x in exps])
+    out = (c_u64 * 2)()
+    rc = _lib.f4_pack_mw(n, arr, out)
+    if rc:
+        raise F4Error(rc, "cannot pack %r in two words" % (tuple(exps),))
+    return int(out[0]), int(out[1])
+
+
+def unpack_mw(n, words):
+    arr = (c_u32 * n)()
+    w = (c_u64 * 2)(int(words[0]), int(words[1]))
+    rc = _lib.f4_unpack_mw(n, w, arr)
+    if rc:
+        raise F4Error(rc, "cannot unpack")
+    return tuple(arr)
+
+
+def _mw_positions(n):
+    """Bit position (in the 128-bit number) of each variable's lane, from
+    f4_pack_mw of the unit vectors."""
+    pos = []
+    for v in range(n):
+        e = [0] * n
+        e[v] = 1
+        hi, lo = pack_mw(n, e)
+        x = ((hi << 64) | lo) - (1 << 120)
+        pos.append(x.bit_length() - 1)
+    return pos
+
+
+def pack_many_mw(n, exps):
+    """Two-word monomials of many exponent vectors (rows of an integer array
+    of width n) as an (m, 2) uint64 array, the same words as pack_mw."""
+    e = np.asarray(exps, dtype=np.uint64).reshape(-1, n)
+    w = _lib.f4_mw_lane_bits(n)
+    if w == 0:
+        raise F4Error(F4_E_ARG, "bad number of variables %d" % n)
+    if e.size and (e.max() >= (1 << w) or e.sum(axis=1).max() > 255):
+        raise F4Error(F4_E_RANGE, "an exponent or the degree does not fit its field")
+    out = np.zeros((e.shape[0], 2), dtype=np.uint64)
+    for v, b in enumerate(_mw_positions(n)):
+        if b >= 64:
+            out[:, 0] |= e[:, v] << np.uint64(b - 64)
+        else:
+            out[:, 1] |= e[:, v] << np.uint64(b)
+    out[:, 0] |= e.sum(axis=1) << np.uint64(56)
+    return out
+
+
+def normalize_mw(p, n, polys):
+    """f4_normalize_polys_mw: [(exps, coeff), ...] per polynomial into the
+    input form of f4_build_matrix_rows_mw (terms by decreasing grevlex)."""
+    off = np.zeros(len(polys) + 1, dtype=np.uint64)
+    exps, coeff = [], []
+    for i, f in enumerate(polys):
+        for e, c in f:
+            exps.append(e)
+            coeff.append(int(c) % p)
+        off[i + 1] = len(coeff)
+    mon = np.ascontiguousarray(pack_many_mw(n, exps).reshape(-1))
+    coeff = np.ascontiguousarray(np.array(coeff, dtype=np.uint32))
+    mo = np.zeros(max(1, len(mon)), dtype=np.uint64)
+    co = np.zeros(max(1, len(coeff)), dtype=np.uint32)
+    oo = np.zeros(len(off), dtype=np.uint64)
+    arg = PolysMW(n, len(polys), mon.ctypes.data, coeff.ctypes.data, off.ctypes.data)
+    rc = _lib.f4_normalize_polys_mw(p, ctypes.byref(arg), mo.ctypes.data_as(P(c_u64)), co.ctypes.data_as(P(c_u32)),
+                                    oo.ctypes.data_as(P(c_u64)))
+    if rc:
+        raise F4Error(rc, "f4_normalize_polys_mw")
+    out = []
+    for i in range(len(polys)):
+        a, b = int(oo[i]), int(oo[i + 1])
+        out.append([(unpack_mw(n, (int(mo[2 * q]), int(mo[2 * q + 1]))), int(co[q])) for q in range(a, b)])
+    return out
 
 
 def grevlex_rank(n, D, word):
@@ -562,6 +653,53 @@ class Context:
                                              ctypes.byref(h), ctypes.byref(st), c_vp(stream)))
         return Matrix(self, h, n), _sigstats(st)
 
+    # -- two-word monomial keys
+    def build_matrix_rows_mw_packed(self, p, n, G, t_words, ks, stream=None):
+        """build_matrix_rows_mw with the shifts as an (r, 2) array of two-word
+        monomials (pack_many_mw) and ks the basis indices."""
+        off = np.zeros(len(G) + 1, dtype=np.uint64)
+        exps, coeff = [], []
+        for i, g in enumerate(G):
+            for e, c in g:
+                exps.append(e)
+                coeff.append(int(c) % p)
+            off[i + 1] = len(coeff)
+        mon = np.ascontiguousarray(pack_many_mw(n, exps).reshape(-1))
+        coeff = np.ascontiguousarray(np.array(coeff, dtype=np.uint32))
+        pg = PolysMW(n, len(G), mon.ctypes.data, coeff.ctypes.data, off.ctypes.data)
+        t_words = np.asarray(t_words, dtype=np.uint64).reshape(-1, 2)
+        rs = np.zeros(len(t_words), dtype=np.dtype([("t0", "<u8"), ("t1", "<u8"), ("k", "<u4"), ("pad", "<u4")]))
+        rs["t0"] = t_words[:, 0]
+        rs["t1"] = t_words[:, 1]
+        rs["k"] = np.asarray(ks, dtype=np.uint32)
+        h = c_vp()
+        self._check(_lib.f4_build_matrix_rows_mw(self._h, p, ctypes.byref(pg), rs.ctypes.data_as(P(RowSpecMW)),
+                                                 len(rs), ctypes.byref(h), c_vp(stream)))
+        return Matrix(self, h, n)
+
+    def build_matrix_rows_mw(self, p, n, G, rows, stream=None):
+        """f4_build_matrix_rows_mw: the matrix of rows [(t exps, k), ...] of a
+        basis G (polys [(exps, coeff), ...], terms by decreasing grevlex,
+        coefficients in [1, p)) for n <= 30 variables."""
+        off = np.zeros(len(G) + 1, dtype=np.uint64)
+        mon, coeff = [], []
+        for i, g in enumerate(G):
+            for e, c in g:
+                mon.extend(pack_mw(n, e))
+                coeff.append(int(c) % p)
+            off[i + 1] = len(coeff)
+        mon = np.ascontiguousarray(np.array(mon, dtype=np.uint64))
+        coeff = np.ascontiguousarray(np.array(coeff, dtype=np.uint32))
+        pg = PolysMW(n, len(G), mon.ctypes.data, coeff.ctypes.data, off.ctypes.data)
+        rs = (RowSpecMW * len(rows))()
+        for q, (t, k) in enumerate(rows):
+            t0, t1 = pack_mw(n, t)
+            rs[q] = RowSpecMW(t0, t1, k, 0)
+        h = c_vp()
+        self._check(_lib.f4_build_matrix_rows_mw(self._h, p, ctypes.byref(pg), rs, len(rows), ctypes.byref(h),
+                                                 c_vp(stream)))
+        return Matrix(self, h, n)
+
     def device_array(self, shape):
         """A block of u32 words in device memory from this context's cache."""
         return DeviceArray(self, shape)
@@ -739,9 +877,14 @@ class Matrix:
                "col_ind": d(v.col_ind, v.nnz, np.uint32),
                "val": d(v.val, v.nnz, np.uint32)}
         if v.dict_keys:
-            out["dict_keys"] = d(v.dict_keys, v.N, np.uint64)
-            out["row_t"] = d(v.row_t, v.r, np.uint64)
+            kw = max(1, v.key_words)
+            out["key_words"] = kw
+            out["dict_keys"] = d(v.dict_keys, v.N * kw, np.uint64)
+            out["row_t"] = d(v.row_t, v.r * kw, np.uint64)
             out["row_k"] = d(v.row_k, v.r, np.uint32)
+            if kw == 2:
+                out["dict_keys"] = out["dict_keys"].reshape(-1, 2)
+                out["row_t"] = out["row_t"].reshape(-1, 2)
         return out
 
 
