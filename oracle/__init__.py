@@ -15,6 +15,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * O7 ``signatures.py``: signature admissibility of shifted reducers (syzygy
   and rewrite tests), the filtered and bucketed row lists, and symbolic
   preprocessing closed over the admissible reducers only.
+* O8 ``schedule.py``: the block schedule of the plan (column panels, the
+  row-to-panel incidence, SELL-C-sigma windows and slices) and the padded
+  slice storage.
 
 Each is pinned in ``tests/test_oracle_*.py`` against facts fixed by the paper
 and by mathematics (uniqueness of the reduced Groebner basis, closed forms,
