@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SELL_W, SELL_SIGMA = 4096, 64  # block schedule of the operator: panel width, window of the length sort
 # derived modular-product bound: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz integer
 # issue, at least two instructions (a multiply and an add) per modular product
 MODMUL_PEAK = 256 * 4 * 16 * 2.4e9 / 2
@@ -370,9 +371,34 @@ def spmm_leg(f4, shift_deg, b, reps):
                                       "entries_x_vectors_per_s": nnz * bb / (ms * 1e-3)}
         Xb.free()
         Yb.free()
+    # the block schedule of the same operator (panels of SELL_W columns, slices of
+    # 64 rows, windows of SELL_SIGMA rows) and A X through its padded slices
+    t0 = time.perf_counter()
+    v = ctx.schedule_build(A, SELL_W, 64, SELL_SIGMA)
+    ctx.download(A.view.row_ptr, 1, np.uint32)  # waits for the schedule's stream
+    t_sched = time.perf_counter() - t0
+    res["sell"] = {"W": SELL_W, "C": 64, "sigma": SELL_SIGMA, "npanels": v["npanels"], "nslices": v["nslices"],
+                   "padded": v["padded"], "pad_ratio": round(v["padded"] / max(1, nnz), 4),
+                   "schedule_ms": round(t_sched * 1e3, 3)}
+    for bb in (1, 8):
+        Xb = ctx.to_device(rng.integers(0, p, size=(N, bb), dtype=np.int64))
+        Yb = ctx.device_array((r, bb))
+        ctx.spmm_sell(p, A, Xb, out=Yb)
+        _, ms = ctx.spmm_sell_timed(p, A, Xb, out=Yb, reps=reps)
+        _, ms_csr = ctx.spmm_timed(p, A, Xb, out=Yb, reps=reps)
+        # slice table (start, panel, width: 3 words, offset: 2), perm, padded entries, X once, Y once
+        byts = 20 * v["nslices"] + 4 * r + 8 * v["padded"] + 4 * bb * (N + r)
+        res["sell"]["ax_b%d" % bb] = {"ms": round(ms, 4), "csr_ms": round(ms_csr, 4),
+                                      "achieved_GBs": round(byts / (ms * 1e-3) / 1e9, 1),
+                                      "frac_hbm": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                      "entries_x_vectors_per_s": nnz * bb / (ms * 1e-3)}
+        Xb.free()
+        Yb.free()
     A.free()
     ctx.close()
     return res
+
+
 
 
 def wiedemann_leg(f4, shift_deg, b):

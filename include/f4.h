@@ -404,6 +404,51 @@ int f4_spmm(f4_ctx* ctx, uint32_t p, f4_matrix* A, int trans, uint32_t b, const 
  * or a null ms_per_call. */
 int f4_spmm_timed(f4_ctx* ctx, uint32_t p, f4_matrix* A, int trans, uint32_t b, const uint32_t* X, uint32_t* Y,
                   uint32_t reps, double* ms_per_call);
+/* ------------------------------------------------------ block schedule */
+/* The block schedule that enriches the plan Pi (section "PSGE:
+ * panel-structured Gaussian elimination", "Why Pi must be enriched": panel
+ * boundaries and the row-to-panel incidence; section "Row assembly as a
+ * dictionary join; divergence control via SELL-C-sigma bucketing"), built on
+ * the device and kept with the handle: panels are the column segments
+ * [l W, (l+1) W), l < npanels = max(1, ceil(N / W)); a row belongs to the
+ * panel of its leading column, empty rows to a last group npanels; perm lists
+ * the rows panel by panel, each panel's rows (in row order) cut into windows
+ * of sigma rows sorted longest first (ties by row index); slices are runs of
+ * C rows inside one group, padded to their longest row; the slice storage is
+ * column-major (entry k of the slice's row j at slice_off[s] + k C + j,
+ * padding column 0 and value 0).  All arrays device, owned by the handle
+ * (until the next f4_matrix_schedule or f4_matrix_free). */
+typedef struct f4_schedule_view {
+    uint32_t W, C, sigma;
+    uint32_t npanels;
+    uint32_t nslices;
+    uint32_t pad;
+    uint64_t padded;                /* slots of the slice storage */
+    const uint32_t* perm;           /* r */
+    const uint32_t* panel_ptr;      /* npanels + 2: positions in perm, the last group empty rows */
+    const uint32_t* slice_start;    /* nslices: positions in perm */
+    const uint32_t* slice_panel;    /* nslices */
+    const uint32_t* slice_width;    /* nslices */
+    const uint64_t* slice_off;      /* nslices + 1 */
+    const uint32_t* sell_col;       /* padded */
+    const uint32_t* sell_val;       /* padded */
+} f4_schedule_view;
+/* Build (or rebuild) the schedule of a handle of one system.  W >= 1,
+ * 1 <= C <= 64, sigma >= 1; out may be NULL.  F4_E_ARG: bad parameters or a
+ * batch handle; F4_E_STATE: unknown handle; F4_E_RANGE: key widths exceeded
+ * (more than 2^30 panels); F4_E_NOMEM. */
+int f4_matrix_schedule(f4_ctx* ctx, f4_matrix* A, uint32_t W, uint32_t C, uint32_t sigma, f4_schedule_view* out,
+                       void* stream);
+/* Y = A X over F_p through the schedule's slices (one wave per slice, a lane
+ * per row; b <= 8 device vectors, row-major as for f4_spmm; the same result
+ * as f4_spmm).  F4_E_STATE: no schedule built; F4_E_ARG: bad p, b, blocks. */
+int f4_spmm_sell(f4_ctx* ctx, uint32_t p, const f4_matrix* A, uint32_t b, const uint32_t* X, uint32_t* Y,
+                 void* stream);
+/* f4_spmm_sell repeated `reps` times between one pair of HIP events (mean
+ * time per call in *ms_per_call), as f4_spmm_timed. */
+int f4_spmm_sell_timed(f4_ctx* ctx, uint32_t p, const f4_matrix* A, uint32_t b, const uint32_t* X, uint32_t* Y,
+                       uint32_t reps, double* ms_per_call);
+
 /* Block Wiedemann over F_p (section "Block Wiedemann and Block Lanczos":
  * kernel vectors by black-box linear algebra, the block form of Wiedemann's
  * method; Remark "Syzygies, revisited"): left-kernel vectors v != 0,

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libf4.so")
-SOURCES = ["prim.hip", "build.hip", "reduce.hip", "api.hip", "tune.hip", "micro.hip", "krylov.hip", "wiedemann.hip", "gm.hip", "sig.hip", "mw.hip"]
+SOURCES = ["prim.hip", "build.hip", "reduce.hip", "api.hip", "tune.hip", "micro.hip", "krylov.hip", "wiedemann.hip", "gm.hip", "sig.hip", "mw.hip", "sched.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep the compiler from forming packed fp32 instructions

@@ -40,6 +40,7 @@ struct f4_matrix {
     // CSR of the transpose, built by the first transposed f4_spmm call
     DBuf<u32> t_ptr, t_idx, t_val;
     bool has_t = false;
+    SchedBufs sched;  // block schedule (f4_matrix_schedule)
 };
 struct f4_reduced {
     f4_ctx* owner;
@@ -2037,6 +2038,91 @@ int f4_spmm_timed(f4_ctx* X, uint32_t p, f4_matrix* A, int trans, uint32_t b, co
     set_stream(X, nullptr);
     Ctx& c = X->c;
     auto run = spmm_call(X, p, A, trans, b, Xin, Y);
+    hipEvent_t e[2] = {nullptr, nullptr};
+    try {
+        F4_HIP_TRY(hipEventCreate(&e[0]));
+        F4_HIP_TRY(hipEventCreate(&e[1]));
+        F4_HIP_TRY(hipEventRecord(e[0], c.stream));
+        for (u32 i = 0; i < reps; ++i) run();
+        F4_HIP_TRY(hipEventRecord(e[1], c.stream));
+        F4_HIP_TRY(hipEventSynchronize(e[1]));
+        float ms = 0.f;
+        F4_HIP_TRY(hipEventElapsedTime(&ms, e[0], e[1]));
+        *ms_per_call = (double)ms / reps;
+    } catch (...) {
+        for (hipEvent_t v : e)
+            if (v) (void)hipEventDestroy(v);
+        throw;
+    }
+    for (hipEvent_t v : e) (void)hipEventDestroy(v);
+    F4_API_END(X)
+}
+
+static f4_matrix* own_matrix(f4_ctx* X, const f4_matrix* A) {
+    if (!A || A->owner != X || X->matrices.count(const_cast<f4_matrix*>(A)) == 0)
+        throw F4Error{F4_E_STATE, "unknown matrix handle"};
+    if (A->m.S != 1) throw F4Error{F4_E_ARG, "matrix of a batch"};
+    return const_cast<f4_matrix*>(A);
+}
+
+static void schedule_view(const SchedBufs& S, f4_schedule_view* out) {
+    out->W = S.W;
+    out->C = S.C;
+    out->sigma = S.sigma;
+    out->npanels = S.npanels;
+    out->nslices = S.nslices;
+    out->pad = 0;
+    out->padded = S.padded;
+    out->perm = S.perm.ptr;
+    out->panel_ptr = S.panel_ptr.ptr;
+    out->slice_start = S.slice_start.ptr;
+    out->slice_panel = S.slice_panel.ptr;
+    out->slice_width = S.slice_width.ptr;
+    out->slice_off = S.slice_off.ptr;
+    out->sell_col = S.sell_col.ptr;
+    out->sell_val = S.sell_val.ptr;
+}
+
+int f4_matrix_schedule(f4_ctx* X, f4_matrix* A, uint32_t W, uint32_t C, uint32_t sigma, f4_schedule_view* out,
+                       void* stream) {
+    F4_API_BEGIN(X)
+    f4_matrix* M = own_matrix(X, A);
+    if (W == 0 || C == 0 || C > 64 || sigma == 0) throw F4Error{F4_E_ARG, "bad schedule parameters"};
+    set_stream(X, stream);
+    const SysPart& P = M->m.sys[0];
+    SchedBufs S;
+    sched_build(X->c, P.r, P.N, P.nnz, M->m.row_ptr.ptr, M->m.col_ind.ptr, M->m.val.ptr, W, C, sigma, S);
+    M->sched = std::move(S);
+    if (out) schedule_view(M->sched, out);
+    F4_API_END(X)
+}
+
+static std::function<void()> spmm_sell_call(f4_ctx* X, uint32_t p, const f4_matrix* A, uint32_t b,
+                                            const uint32_t* Xin, uint32_t* Y) {
+    f4_matrix* M = own_matrix(X, A);
+    if (!M->sched.has) throw F4Error{F4_E_STATE, "the matrix has no block schedule (f4_matrix_schedule)"};
+    if (!is_odd_prime(p) || p >= (1u << 31) || b == 0 || b > 8) throw F4Error{F4_E_ARG, "bad argument"};
+    const SysPart& P = M->m.sys[0];
+    if ((P.N && !Xin) || (P.r && !Y)) throw F4Error{F4_E_ARG, "null block"};
+    Ctx* c = &X->c;
+    return [c, p, M, b, Xin, Y]() { spmm_sell_run(c->stream, p, M->sched, b, Xin, Y); };
+}
+
+int f4_spmm_sell(f4_ctx* X, uint32_t p, const f4_matrix* A, uint32_t b, const uint32_t* Xin, uint32_t* Y,
+                 void* stream) {
+    F4_API_BEGIN(X)
+    set_stream(X, stream);
+    spmm_sell_call(X, p, A, b, Xin, Y)();
+    F4_API_END(X)
+}
+
+int f4_spmm_sell_timed(f4_ctx* X, uint32_t p, const f4_matrix* A, uint32_t b, const uint32_t* Xin, uint32_t* Y,
+                       uint32_t reps, double* ms_per_call) {
+    F4_API_BEGIN(X)
+    if (reps == 0 || !ms_per_call) throw F4Error{F4_E_ARG, "bad argument"};
+    set_stream(X, nullptr);
+    Ctx& c = X->c;
+    auto run = spmm_sell_call(X, p, A, b, Xin, Y);
     hipEvent_t e[2] = {nullptr, nullptr};
     try {
         F4_HIP_TRY(hipEventCreate(&e[0]));

@@ -418,6 +418,22 @@ struct GmSelect {
 };
 u32* gm_select_batch(Ctx& c, const std::vector<GmSelect>& v, u64* rows_t, u32* rows_k, DBuf<u64>& keep);
 
+// ------------------------------------------------------- block schedule
+// The block schedule of a matrix (column panels of width W, the rows grouped
+// by the panel of their leading column, SELL-C-sigma windows and slices) and
+// its padded slice storage, all on the device.
+struct SchedBufs {
+    bool has = false;
+    u32 W = 0, C = 0, sigma = 0, r = 0, npanels = 0, nslices = 0;
+    u64 padded = 0;
+    DBuf<u32> perm, panel_ptr, slice_start, slice_panel, slice_width, sell_col, sell_val;
+    DBuf<u64> slice_off;
+};
+void sched_build(Ctx& c, u32 r, u32 N, u64 nnz, const u32* ptr, const u32* col, const u32* val, u32 W, u32 C, u32 sigma,
+                 SchedBufs& S);
+// Y = A X (b <= 8) through the slices.
+void spmm_sell_run(hipStream_t s, u32 p, const SchedBufs& S, u32 b, const u32* X, u32* Y);
+
 // ------------------------------------------------- two-word monomial keys
 // The matrix of an explicit row list with two-word monomials (records of
 // f4_rowspec_mw), basis as host SoA arrays already checked; out: key_words 2.

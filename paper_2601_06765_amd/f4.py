@@ -68,6 +68,13 @@ class MatrixView(ctypes.Structure):
                 ("row_t", c_vp), ("row_k", c_vp), ("key_words", c_u32), ("pad", c_u32)]
 
 
+class ScheduleView(ctypes.Structure):
+    _fields_ = [("W", c_u32), ("C", c_u32), ("sigma", c_u32), ("npanels", c_u32), ("nslices", c_u32),
+                ("pad", c_u32), ("padded", c_u64), ("perm", c_vp), ("panel_ptr", c_vp), ("slice_start", c_vp),
+                ("slice_panel", c_vp), ("slice_width", c_vp), ("slice_off", c_vp), ("sell_col", c_vp),
+                ("sell_val", c_vp)]
+
+
 class PolysMW(ctypes.Structure):
     _fields_ = [("n", c_u32), ("npolys", c_u32), ("mon", c_vp), ("coeff", c_vp), ("offset", c_vp)]
 
@@ -114,6 +121,9 @@ _sig("f4_pack_mw", c_int, [c_u32, P(c_u32), P(c_u64)])
 _sig("f4_unpack_mw", c_int, [c_u32, P(c_u64), P(c_u32)])
 _sig("f4_build_matrix_rows_mw", c_int, [c_vp, c_u32, P(PolysMW), P(RowSpecMW), c_u32, P(c_vp), c_vp])
 _sig("f4_normalize_polys_mw", c_int, [c_u32, P(PolysMW), P(c_u64), P(c_u32), P(c_u64)])
+_sig("f4_matrix_schedule", c_int, [c_vp, c_vp, c_u32, c_u32, c_u32, P(ScheduleView), c_vp])
+_sig("f4_spmm_sell", c_int, [c_vp, c_u32, c_vp, c_u32, c_vp, c_vp, c_vp])
+_sig("f4_spmm_sell_timed", c_int, [c_vp, c_u32, c_vp, c_u32, c_vp, c_vp, c_u32, P(ctypes.c_double)])
 _sig("f4_check_polys", c_int, [c_u32, P(Polys), c_int, P(c_u32)])
 _sig("f4_normalize_polys", c_int, [c_u32, P(Polys), c_int, P(c_u64), P(c_u32), P(c_u64)])
 _sig("f4_grevlex_rank", c_int, [c_u32, c_u32, c_u64, P(c_u32)])
@@ -742,6 +752,42 @@ class Context:
                                          c_vp(val.ptr), 1 if trans else 0, b, c_vp(X.ptr), c_vp(out.ptr),
                                          c_vp(stream)))
         return out
+
+    def schedule(self, A, W, C, sigma, stream=None):
+        """f4_matrix_schedule: build the block schedule of A; returns its
+        arrays downloaded to the host (perm, panel_ptr, slices, storage)."""
+        v = ScheduleView()
+        self._check(_lib.f4_matrix_schedule(self._h, A._h, W, C, sigma, ctypes.byref(v), c_vp(stream)))
+        d = self.download
+        r = A.view.r
+        return {"W": v.W, "C": v.C, "sigma": v.sigma, "npanels": v.npanels, "nslices": v.nslices,
+                "padded": v.padded, "perm": d(v.perm, r, np.uint32),
+                "panel_ptr": d(v.panel_ptr, v.npanels + 2, np.uint32),
+                "slice_start": d(v.slice_start, v.nslices, np.uint32),
+                "slice_panel": d(v.slice_panel, v.nslices, np.uint32),
+                "slice_width": d(v.slice_width, v.nslices, np.uint32),
+                "slice_off": d(v.slice_off, v.nslices + 1, np.uint64),
+                "sell_col": d(v.sell_col, v.padded, np.uint32), "sell_val": d(v.sell_val, v.padded, np.uint32)}
+
+    def schedule_build(self, A, W, C, sigma, stream=None):
+        """f4_matrix_schedule without downloading any array; returns the
+        schedule's sizes (npanels, nslices, padded)."""
+        v = ScheduleView()
+        self._check(_lib.f4_matrix_schedule(self._h, A._h, W, C, sigma, ctypes.byref(v), c_vp(stream)))
+        return {"npanels": v.npanels, "nslices": v.nslices, "padded": v.padded}
+
+    def spmm_sell(self, p, A, X, out=None, stream=None):
+        """Y = A X through the block schedule's slices (f4_spmm_sell)."""
+        b, out = self._spmm_args(A, X, False, out)
+        self._check(_lib.f4_spmm_sell(self._h, p, A._h, b, c_vp(X.ptr), c_vp(out.ptr), c_vp(stream)))
+        return out
+
+    def spmm_sell_timed(self, p, A, X, out=None, reps=10):
+        b, out = self._spmm_args(A, X, False, out)
+        ms = ctypes.c_double(0.0)
+        self._check(_lib.f4_spmm_sell_timed(self._h, p, A._h, b, c_vp(X.ptr), c_vp(out.ptr), reps,
+                                            ctypes.byref(ms)))
+        return out, ms.value
 
     def spmm_timed(self, p, A, X, trans=False, out=None, reps=10):
         """spmm repeated `reps` times between HIP events on the context's
