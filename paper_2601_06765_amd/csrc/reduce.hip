@@ -30,7 +30,7 @@
 
 #define PANEL 64
 #define TR_THREADS 1024
-#define TR_UNROLL 8
+#define TR_UNROLL 4
 #define ECH_B 32
 
 // per-system elimination descriptor
@@ -298,7 +298,7 @@ struct AccOf<0> {
     typedef u32 T;
 };
 
-template <int MODE, bool LDS>
+template <int MODE, bool LDS, int RR>
 __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_base, const u32* row_ptr,
                                                      const u32* col_ind, const u32* val, const u32* list,
                                                      int tail, u32 rr, u32 tile_base, int skip_lead,
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
     const u32 cnt = tail ? S.r : S.L;  // rows of this system in the list
     const u32 t0 = (tile_base + blockIdx.x) * rr;
     if (t0 >= cnt) return;
-    const u32 nr = min(rr, cnt - t0);
+    const u32 nr = min(min(rr, (u32)RR), cnt - t0);
     const u32 tid = threadIdx.x, lane = lane_id(), wave = tid / F4_WAVE;
     const Fp f = S.f;
     const u32 N = S.N, npiv = S.npiv;
@@ -370,13 +370,20 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
         for (u32 r = 0; r < nr; ++r) {
             const AccT aj = lane < wk ? acc[r * N + qa + lane] : (AccT)0;
             const u32 lj = SMALL ? fp_reduce32(f, (u32)aj) : fp_reduce_any(f, (u64)aj);
+            // BW raw products: below BW p^2 < 2^64 (BW = 4, p < 2^31), one
+            // reduction (or fold) for the sum instead of one per product
+            static_assert(BW <= 4, "lazy panel sums");
             u64 part = 0;
 #pragma unroll
             for (u32 i = 0; i < BW; ++i) {
                 const u32 lb = (u32)__builtin_amdgcn_readlane((int)lj, (int)(wave * BW + i));  // 0 past wk
-                part += SMALL ? (u64)mul24(lb, tin[i]) : (u64)fp_mul(f, lb, tin[i]);
+                part += SMALL ? (u64)mul24(lb, tin[i]) : (u64)lb * tin[i];
                 nops += lb != 0;
             }
+            if (MODE == 1)  // p = 2^31 - k: 2^31 == k, a value below 2^41 + 2^31
+                part = (u64)S.pk * (part >> 31) + (part & 0x7fffffffull);
+            else if (MODE == 2)
+                part = fp_reduce_any(f, part);
             if (part) atomicAdd((unsigned long long*)&s_xs[buf][r][lane], (unsigned long long)part);
         }
         // the next panel's loads go out now
@@ -401,30 +408,53 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
         __syncthreads();
         u64 anyhit = 0;
         for (u32 r = 0; r < nr; ++r) anyhit |= s_hit[r];
-        if (anyhit) {
-            // (C) apply every trailing entry to every row of the tile
+        // (C) apply every trailing entry to every row of the tile; for
+        // p = 2^31 - 1 the folded product h + l stays below 2^32 and needs
+        // no multiply by k
+        auto apply = [&](auto mersenne) {
+            constexpr bool MERS = decltype(mersenne)::value;
             for (u32 e0 = ea + tid;; e0 += TR_THREADS * TR_UNROLL) {
+                // the multipliers of all TR_UNROLL entries are read from LDS
+                // before any product (no branch between the reads), then
+                // each product is added where both factors are nonzero
+                // (slots past the panel's entries hold 0; stored values are
+                // nonzero)
+                u32 xs[TR_UNROLL][RR];
 #pragma unroll
                 for (int k = 0; k < TR_UNROLL; ++k) {
-                    if (!t[k]) continue;  // stored values are nonzero
-                    const u32 b = (u32)(t[k] >> 26) & (PANEL - 1), col = (u32)t[k] & 0x3ffffffu;
-                    const u32 tv = (u32)(t[k] >> 32);
-                    const uint4 xv = s_x[b];  // one LDS read for the tile's rows
-                    const u32 xs[TR_MAXR] = {xv.x, xv.y, xv.z, xv.w};
+                    const u32 b = (u32)(t[k] >> 26) & (PANEL - 1);
+                    if (RR == 1) {
+                        xs[k][0] = reinterpret_cast<const u32*>(&s_x[b])[0];
+                    } else if (RR == 2) {
+                        const uint2 v = reinterpret_cast<const uint2*>(&s_x[b])[0];
+                        xs[k][0] = v.x;
+                        xs[k][RR - 1] = v.y;
+                    } else {
+                        const uint4 v = s_x[b];
+                        const u32 w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                    for (int r = 0; r < TR_MAXR; ++r) {
-                        if (!xs[r]) continue;
-                        const u32 negx = xs[r];
+                        for (int r = 0; r < RR; ++r) xs[k][r] = w[r];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < TR_UNROLL; ++k) {
+                    const u32 col = (u32)t[k] & 0x3ffffffu, tv = (u32)(t[k] >> 32);
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) {
+                        const u32 negx = xs[k][r];
                         AccT add;
                         if (MODE == 0) {
                             add = fp_mul32(f, negx, tv);
                         } else if (MODE == 1) {
                             const u64 t = (u64)negx * tv;  // < 2^62
-                            add = (u64)S.pk * (u32)(t >> 31) + ((u32)t & 0x7fffffffu);
+                            if (MERS)
+                                add = (u64)((u32)(t >> 31) + ((u32)t & 0x7fffffffu));
+                            else
+                                add = (u64)S.pk * (u32)(t >> 31) + ((u32)t & 0x7fffffffu);
                         } else {
                             add = fp_reduce(f, (u64)negx * tv);
                         }
-                        atomicAdd(&acc[r * N + col], add);
+                        if (tv && negx) atomicAdd(&acc[r * N + col], add);
                     }
                 }
                 const u32 e1 = e0 + TR_THREADS * TR_UNROLL;
@@ -435,6 +465,12 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
                     t[k] = e < eb ? tent[e] : 0ull;
                 }
             }
+        };
+        if (anyhit) {
+            if (MODE == 1 && S.pk == 1)
+                apply(std::true_type{});
+            else
+                apply(std::false_type{});
         }
 #pragma unroll
         for (u32 i = 0; i < BW; ++i) tin[i] = tin2[i];
@@ -1617,21 +1653,30 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
             const u32 rmax = (u32)std::min<size_t>(TR_MAXR, budget / row_bytes);
             auto launch = [&](u32 rr, unsigned long long* op) {
                 const u32 tiles = ceil_div(cmax, rr);
+                auto go = [&](auto mode, auto rows) {
+                    constexpr int MODE = decltype(mode)::value, RR = decltype(rows)::value;
+                    typedef typename AccOf<MODE>::T AccT;
+                    hipLaunchKernelGGL((k_trsm<MODE, true, RR>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
+                                       X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
+                                       skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (AccT*)nullptr, Dp,
+                                       lead_out, status, op);
+                };
+                auto by_rows = [&](auto mode) {
+                    if (rr == 1)
+                        go(mode, std::integral_constant<int, 1>{});
+                    else if (rr == 2)
+                        go(mode, std::integral_constant<int, 2>{});
+                    else if (rr == 3)
+                        go(mode, std::integral_constant<int, 3>{});
+                    else
+                        go(mode, std::integral_constant<int, 4>{});
+                };
                 if (cls == 0)
-                    hipLaunchKernelGGL((k_trsm<0, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
-                                       X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
-                                       skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)nullptr, Dp,
-                                       lead_out, status, op);
+                    by_rows(std::integral_constant<int, 0>{});
                 else if (cls == 1)
-                    hipLaunchKernelGGL((k_trsm<1, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
-                                       X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
-                                       skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, Dp,
-                                       lead_out, status, op);
+                    by_rows(std::integral_constant<int, 1>{});
                 else
-                    hipLaunchKernelGGL((k_trsm<2, true>), dim3(tiles, S), dim3(TR_THREADS), rr * row_bytes, s,
-                                       X.dsegs.ptr, 0u, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, rr, 0u,
-                                       skip_lead, X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)nullptr, Dp,
-                                       lead_out, status, op);
+                    by_rows(std::integral_constant<int, 2>{});
                 F4_LAUNCH_CHECK();
             };
             u32 rr = rmax;
@@ -1665,17 +1710,17 @@ static void run_trsm(Ctx& c, const Matrix& A, const SplitState& X, const u32* li
             for (u32 b0 = 0; b0 < cnt; b0 += batch) {
                 const u32 nb = std::min(batch, cnt - b0);
                 if (cls == 0)
-                    hipLaunchKernelGGL((k_trsm<0, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
+                    hipLaunchKernelGGL((k_trsm<0, false, 1>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
                                        A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
                                        X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u32*)gacc.ptr, Dp, lead_out,
                                        status, ops);
                 else if (cls == 1)
-                    hipLaunchKernelGGL((k_trsm<1, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
+                    hipLaunchKernelGGL((k_trsm<1, false, 1>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
                                        A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
                                        X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, Dp, lead_out,
                                        status, ops);
                 else
-                    hipLaunchKernelGGL((k_trsm<2, false>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
+                    hipLaunchKernelGGL((k_trsm<2, false, 1>), dim3(nb, 1), dim3(TR_THREADS), 0, s, X.dsegs.ptr, sy,
                                        A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, list, tail, 1u, b0, skip_lead,
                                        X.perm.ptr, X.Tinv.ptr, X.tptr.ptr, X.tent.ptr, (u64*)gacc.ptr, Dp, lead_out,
                                        status, ops);
