@@ -29,6 +29,8 @@
 
 #define MB_THREADS 256
 #define MB_WAVES (MB_THREADS / F4_WAVE)
+#define MK_THREADS 1024  // row marking: sixteen waves per workgroup share one LDS bitmap
+#define MK_WAVES (MK_THREADS / F4_WAVE)
 
 // ----------------------------------------------------------- rank tables
 u64 binom_host(u32 x, u32 y) {
@@ -109,25 +111,26 @@ struct SegSP {
 // t * m of the row as seen.  One wave per row, lanes over terms; seen-bits are
 // gathered in an LDS bitmap per workgroup, flushed with one atomic OR per
 // nonzero word.
-__global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, const u64* rows_t, const u32* rows_k,
+__global__ __launch_bounds__(MK_THREADS) void k_mark_rows(const SegSP* segs, const u64* rows_t, const u32* rows_k,
                                                            u32* row_lmrank, u32* ctr, u32* present, u32* done,
                                                            u32* lead, int local_bitmap) {
     extern __shared__ u32 sm[];
     const SegSP S = segs[blockIdx.y];
+    u32* C = ctr + CTR * blockIdx.y;
+    const u32 rb = C[0], re = C[1];
+    if (rb + blockIdx.x * MK_WAVES >= re) return;  // no row for this workgroup (uniform)
     u32* tab = sm;
     u32* lbits = sm + S.tabn;
-    for (u32 i = threadIdx.x; i < S.tabn; i += MB_THREADS) tab[i] = S.binom[i];
+    for (u32 i = threadIdx.x; i < S.tabn; i += MK_THREADS) tab[i] = S.binom[i];
     if (local_bitmap)
-        for (u32 i = threadIdx.x; i < S.nwords; i += MB_THREADS) lbits[i] = 0;
+        for (u32 i = threadIdx.x; i < S.nwords; i += MK_THREADS) lbits[i] = 0;
     __syncthreads();
-    u32* C = ctr + CTR * blockIdx.y;
     u32* P = present + S.wbase;
     u32* Dn = done + S.wbase;
     u32* Ld = lead + S.wbase;
     const u32 n = S.n, w = S.w, D = S.D, lane = lane_id();
-    const u32 rb = C[0], re = C[1];
-    const u32 nw_total = gridDim.x * MB_WAVES;
-    for (u32 row = rb + blockIdx.x * MB_WAVES + threadIdx.x / F4_WAVE; row < re; row += nw_total) {
+    const u32 nw_total = gridDim.x * MK_WAVES;
+    for (u32 row = rb + blockIdx.x * MK_WAVES + threadIdx.x / F4_WAVE; row < re; row += nw_total) {
         const u64 t = rows_t[S.rbase + row];
         const u32 k = rows_k[S.rbase + row];
         if (lane == 0) {
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(MB_THREADS) void k_mark_rows(const SegSP* segs, con
     }
     if (local_bitmap) {
         __syncthreads();
-        for (u32 i = threadIdx.x; i < S.nwords; i += MB_THREADS) {
+        for (u32 i = threadIdx.x; i < S.nwords; i += MK_THREADS) {
             const u32 v = lbits[i];
             if (v) atomicOr(&P[i], v);
         }
@@ -792,14 +795,14 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     const size_t mark_lds = (max_tabn + (local_bitmap ? max_words : 0)) * 4;
     u32 bx = std::max<u32>(1, std::min<u32>((u32)std::max(1, c.dev.cus), ceil_div(2048, S)));
     {
-        // a large row set: enough waves in flight (up to 8 workgroups per CU)
+        // a large row set: enough waves in flight (up to 2 workgroups per CU)
         // to hide the latency of each row's dependent loads
         u32 r0max = 0;
         for (u32 i = 0; i < S; ++i) r0max = std::max(r0max, args[i].r0);
-        bx = std::max<u32>(bx, std::min<u32>(8u * (u32)std::max(1, c.dev.cus) / S, ceil_div(r0max, MB_WAVES * 16)));
+        bx = std::max<u32>(bx, std::min<u32>(2u * (u32)std::max(1, c.dev.cus) / S, ceil_div(r0max, MK_WAVES * 4)));
     }
     auto mark = [&]() {
-        hipLaunchKernelGGL(k_mark_rows, dim3(bx, S), dim3(MB_THREADS), mark_lds, s, dsegs, rows_t.ptr,
+        hipLaunchKernelGGL(k_mark_rows, dim3(bx, S), dim3(MK_THREADS), mark_lds, s, dsegs, rows_t.ptr,
                            rows_k.ptr, row_lmrank.ptr, ctr, present, done, leadmap, local_bitmap);
         F4_LAUNCH_CHECK();
     };

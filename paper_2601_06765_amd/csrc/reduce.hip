@@ -1157,6 +1157,27 @@ __global__ __launch_bounds__(64 * ECH_UPW) void k_ech_update_wave(const SegR* se
 }
 
 
+// End of a batch of rounds: a system none of whose remaining rows is live
+// (every row a pivot row or zero) is done now, as the next round's block
+// step would find, so the batch's readback can end the elimination without
+// another batch of rounds.
+__global__ __launch_bounds__(256) void k_ech_check(const SegR* segs, const u32* lead, const u32* status,
+                                                   EchRound* rounds, u32* ndone) {
+    __shared__ u32 s_live;
+    EchRound* R = rounds + blockIdx.y;
+    if (R->done) return;
+    const SegR S = segs[blockIdx.y];
+    if (threadIdx.x == 0) s_live = 0;
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < S.L; i += blockDim.x)
+        if (status[S.lb + i] == 0 && lead[S.lb + i] < S.c) s_live = 1;  // every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0 && !s_live) {
+        R->done = 1;
+        atomicAdd(ndone, 1u);
+    }
+}
+
 // One kernel per round after the block step (the form for few rows: a
 // workgroup per row slot spreads each row over 256 threads), one workgroup per row slot of a
 // system (remaining rows of D': the first L slots; the pivot-row store: the
@@ -1604,14 +1625,14 @@ static void do_split(Ctx& c, const std::vector<u32>& p, const Matrix& A, SplitSt
     u32 maxP = 1;
     for (auto& g : X.segs) maxP = std::max(maxP, g.npiv);
     if (P) {
-        hipLaunchKernelGGL(k_upper_count, dim3(std::min<u32>(256, ceil_div(maxP, 4)), S), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_upper_count, dim3(std::min<u32>(4096, ceil_div(maxP, 4)), S), dim3(256), 0, s,
                            X.dsegs.ptr, A.row_ptr.ptr, A.col_ind.ptr, X.prow.ptr, X.perm.ptr, X.tptr.ptr, X.T.ptr);
         F4_LAUNCH_CHECK();
     }
     exclusive_scan_u32(X.tptr.ptr, X.tptr.ptr, P, c.pool, s);
     X.tent.reset(&c.pool, std::max<u64>(A.nnz, 1));
     if (P) {
-        hipLaunchKernelGGL(k_upper_fill, dim3(std::min<u32>(256, ceil_div(maxP, 4)), S), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_upper_fill, dim3(std::min<u32>(4096, ceil_div(maxP, 4)), S), dim3(256), 0, s,
                            X.dsegs.ptr, A.row_ptr.ptr, A.col_ind.ptr, A.val.ptr, X.prow.ptr, X.perm.ptr, X.tptr.ptr,
                            X.tent.ptr, X.T.ptr);
         F4_LAUNCH_CHECK();
@@ -1871,6 +1892,9 @@ void reduce_batch(Ctx& c, const std::vector<u32>& p, const Matrix& A, Reduced& o
                 ++r;
             }
             batch = 4;
+            hipLaunchKernelGGL(k_ech_check, dim3(1, S), dim3(256), 0, s, X.dsegs.ptr, lead.ptr, status.ptr, rounds,
+                               ndone);
+            F4_LAUNCH_CHECK();
             e3 = stage_event(c);
             if (CAP <= SORT_SMALL_MAX) {
                 const size_t lds = (size_t)SORT_SMALL_MAX * (2 * sizeof(u64) + 2 * sizeof(u32));
