@@ -29,6 +29,7 @@
 
 #define MB_THREADS 256
 #define MB_WAVES (MB_THREADS / F4_WAVE)
+#define RED_BUF 16      // reducer rows a wave buffers before one append
 #define MK_THREADS 1024  // row marking: sixteen waves per workgroup share one LDS bitmap
 #define MK_WAVES (MK_THREADS / F4_WAVE)
 
@@ -293,10 +294,34 @@ __global__ __launch_bounds__(MB_THREADS) void k_reducers(const SegSP* segs, cons
     for (u32 i = 0; i < n; ++i) H |= 1ull << (w * i + w - 1);
     const u64 lanes = (n * w >= 64) ? ~0ull : ((1ull << (n * w)) - 1);
     // one wave per frontier monomial, lanes over the active list (descending
-    // index): the first divisor in list order is the reducer (largest index)
+    // index): the first divisor in list order is the reducer (largest index).
+    // A wave keeps up to RED_BUF of its rows in LDS and appends them with one
+    // atomic on the row counter (the rows' order in the list is immaterial:
+    // the matrix orders its rows itself)
+    __shared__ u64 s_bt[MB_WAVES][RED_BUF];
+    __shared__ u32 s_bk[MB_WAVES][RED_BUF], s_bq[MB_WAVES][RED_BUF];
+    const u32 wv = threadIdx.x / F4_WAVE;
+    u32 nbuf = 0;  // rows buffered by this wave (the same in every lane)
+    auto flush = [&]() {
+        __builtin_amdgcn_wave_barrier();  // lane 0's buffer writes before the lanes' reads
+        u32 base = 0;
+        if (lane == 0) base = atomicAdd(&ctr[CTR * s + 1], nbuf);
+        base = (u32)__shfl((int)base, 0);
+        if (lane < nbuf) {
+            const u32 slot = base + lane;
+            if (slot >= S.rcap) {
+                ctr[CTR * s + 3] = 2u;
+            } else {
+                rows_t[S.rbase + slot] = s_bt[wv][lane];
+                rows_k[S.rbase + slot] = s_bk[wv][lane];
+                row_lmrank[S.rbase + slot] = s_bq[wv][lane];
+            }
+        }
+        nbuf = 0;
+    };
     const u32 f0 = fscan[S.wbase], f1 = fscan[S.wbase + S.nwords];
     const u32 nwaves = gridDim.x * MB_WAVES;
-    for (u32 i = f0 + blockIdx.x * MB_WAVES + threadIdx.x / F4_WAVE; i < f1; i += nwaves) {
+    for (u32 i = f0 + blockIdx.x * MB_WAVES + wv; i < f1; i += nwaves) {
         const u32 q = list_q[i];
         const u64 m = S.montab[q];
         const bool mclean = (m & H) == 0;
@@ -326,18 +351,17 @@ __global__ __launch_bounds__(MB_THREADS) void k_reducers(const SegSP* segs, cons
             }
             if (found != 0xffffffffu) break;
         }
-        if (found != 0xffffffffu && lane == 0) {
-            const u64 l = lds_active ? slm[found] : S.lm[act[found]];
-            const u32 slot = atomicAdd(&ctr[CTR * s + 1], 1u);
-            if (slot >= S.rcap) {
-                ctr[CTR * s + 3] = 2u;
-            } else {
-                rows_t[S.rbase + slot] = m - l;
-                rows_k[S.rbase + slot] = act[found];
-                row_lmrank[S.rbase + slot] = q;
+        if (found != 0xffffffffu) {  // the same in every lane (ballot results)
+            if (lane == 0) {
+                const u64 l = lds_active ? slm[found] : S.lm[act[found]];
+                s_bt[wv][nbuf] = m - l;
+                s_bk[wv][nbuf] = act[found];
+                s_bq[wv][nbuf] = q;
             }
+            if (++nbuf == RED_BUF) flush();
         }
     }
+    if (nbuf) flush();
 }
 
 __global__ void k_word_popc(const u32* present, u32 nwords, u32* cnt) {
@@ -793,14 +817,12 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
 
     const int local_bitmap = (max_tabn + max_words) * 4 <= 48 * 1024;
     const size_t mark_lds = (max_tabn + (local_bitmap ? max_words : 0)) * 4;
+    // two workgroups per CU over the batch: the later closure rounds add rows
+    // whose count the host does not see, and a workgroup past its system's
+    // rows exits before its setup; rows are latency-bound (dependent rank
+    // lookups), so the waves in flight set the rate
     u32 bx = std::max<u32>(1, std::min<u32>((u32)std::max(1, c.dev.cus), ceil_div(2048, S)));
-    {
-        // a large row set: enough waves in flight (up to 2 workgroups per CU)
-        // to hide the latency of each row's dependent loads
-        u32 r0max = 0;
-        for (u32 i = 0; i < S; ++i) r0max = std::max(r0max, args[i].r0);
-        bx = std::max<u32>(bx, std::min<u32>(2u * (u32)std::max(1, c.dev.cus) / S, ceil_div(r0max, MK_WAVES * 4)));
-    }
+    bx = std::max<u32>(bx, std::max<u32>(1, 2u * (u32)std::max(1, c.dev.cus) / S));
     auto mark = [&]() {
         hipLaunchKernelGGL(k_mark_rows, dim3(bx, S), dim3(MK_THREADS), mark_lds, s, dsegs, rows_t.ptr,
                            rows_k.ptr, row_lmrank.ptr, ctr, present, done, leadmap, local_bitmap);
