@@ -846,10 +846,14 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
     std::vector<u32> hs(8 * S);
     const bool small_words = W <= WORDS_SMALL;
     const bool fused_summary = small_words && S <= SUMMARY_SMALL_S && RC <= SUMMARY_SMALL_ROWS;
+    u32 spec = 2;  // speculative rounds per host check
     for (;;) {
         if (closure) {
-            // two speculative rounds per host check: dense systems converge in two
-            for (int k = 0; k < 2; ++k) {
+            // two speculative rounds at the first host check (dense systems
+            // converge in two), then twice as many after each check that
+            // finds a frontier left (a round past convergence only relaunches
+            // three kernels on an empty frontier)
+            for (u32 k = 0; k < spec; ++k) {
                 if (small_words) {
                     hipLaunchKernelGGL(k_words_small, dim3(1), dim3(1024), 0, s, dsegs, S, present, done, (u32)W, 0,
                                        fcnt.ptr, list_q.ptr, list_s.ptr, ctr, leadmap, lcnt.ptr);
@@ -921,6 +925,7 @@ void build_batch(Ctx& c, const std::vector<BuildArgs>& args, Matrix& out) {
         }
         if (!closure || !more) break;
         if (rounds > 4 * (max_nmax + 8)) throw F4Error{5, "closure did not converge"};
+        spec = std::min<u32>(2 * spec, 8);
     }
 
     // ---- sizes and output layout
