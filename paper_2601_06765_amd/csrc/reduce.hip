@@ -696,9 +696,19 @@ __global__ __launch_bounds__(1024) void k_ech_block(const SegR* segs, u32* lead,
             u32 v = s_B[tid];
             if (q && k < b) {
                 u64 acc = 0;
-                for (u32 u = 0; u < b; ++u) {
-                    const u32 z = s_RZ[k * ECH_RS + ECH_CH + u];
-                    if (z) acc += SMALL ? (u64)mul24(z, s_B[u * ECH_CH + j]) : (u64)fp_mul(f, z, s_B[u * ECH_CH + j]);
+                if (SMALL) {
+                    for (u32 u = 0; u < b; ++u) acc += (u64)mul24(s_RZ[k * ECH_RS + ECH_CH + u], s_B[u * ECH_CH + j]);
+                } else {
+                    // four raw products (below 4 p^2 < 2^64) per reduction
+                    for (u32 u0 = 0; u0 < b; u0 += 4) {
+                        u64 part = 0;
+#pragma unroll
+                        for (u32 du = 0; du < 4; ++du) {
+                            const u32 u = u0 + du;
+                            if (u < b) part += (u64)s_RZ[k * ECH_RS + ECH_CH + u] * s_B[u * ECH_CH + j];
+                        }
+                        acc += fp_reduce_any(f, part);
+                    }
                 }
                 v = fp_reduce_any(f, acc);
                 if (j == 0) nops += (u64)b * ECH_CH;  // the row's products, counted once
