@@ -205,7 +205,7 @@ def headline_leg(f4, torch, steps, warmup, autotune, dict_path):
     `steps` runs), then the same runs with HIP events around every launch of the
     elimination kernels (roofline), and the autotuner's table."""
     import synth
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     ctx = f4.Context(0, timing=True, stop_deg=STEP_DEG, autotune=autotune, dict_path=dict_path)
     prep = ctx.prepare(p, n, polys)
     for _ in range(warmup):
@@ -272,7 +272,7 @@ def full_f4_leg(f4, torch, runs, warmup, autotune, dict_path):
     """Full F4 runs of the n=10, m=12 dense quadratics over F_65521 (seed 2):
     nnz/s over all steps of a run, and the per-step stage times."""
     import synth
-    n, p, polys = synth.config_system(2)
+    n, p, polys = synth.system("dense_n10")
     ctx = f4.Context(0, dict_path=dict_path, autotune=autotune)
     prep = ctx.prepare(p, n, polys)
     for _ in range(warmup):
@@ -315,14 +315,14 @@ def full_f4_leg(f4, torch, runs, warmup, autotune, dict_path):
 
 def spmm_leg(f4, shift_deg, b, reps):
     """Block operator application of the Krylov solvers (Y = A X, Y = A^T X)
-    on the Macaulay matrix of workload 3's input: rows t*f_i for every monomial
+    on the Macaulay matrix of the sparse n=14 system's input: rows t*f_i for every monomial
     t of degree <= shift_deg and each of the 15 sparse quadratics over
     F_(2^31-1), built by the symbolic preprocessing; b random vectors.  Each
     product is timed with HIP events on the stream it runs on (the library's
     timed call: mean of `reps` after a warm-up that also builds the transpose)."""
     import numpy as np
     import synth
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     polys = f4.normalize(p, n, polys)
     t = f4.pack_many(n, synth.monomials_upto(n, shift_deg))
     ctx = f4.Context(0)
@@ -403,14 +403,14 @@ def spmm_leg(f4, shift_deg, b, reps):
 
 def wiedemann_leg(f4, shift_deg, b):
     """Block Wiedemann (left-kernel vectors = syzygies) on the Macaulay matrix of
-    workload 3's input at degree shift_deg + 2: rows t*f_i for every monomial t
+    the sparse n=14 system's input at degree shift_deg + 2: rows t*f_i for every monomial t
     of degree <= shift_deg and each of the 15 sparse quadratics over
     F_(2^31-1), built by the symbolic preprocessing; the diagonal D and the
     blocks X, Y from splitmix64 (seed 6).  Reports the three phases' times
     and the vectors found (each checked on the device against A^T v = 0)."""
     import numpy as np
     import synth
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     polys = f4.normalize(p, n, polys)
     t = f4.pack_many(n, synth.monomials_upto(n, shift_deg))
     tw, ks = np.repeat(t, len(polys)), np.tile(np.arange(len(polys), dtype=np.uint32), len(t))
@@ -438,7 +438,7 @@ def wiedemann_leg(f4, shift_deg, b):
 
 
 def signature_leg(f4, shift_deg, build_shift_deg, reps):
-    """Signature admissibility in bulk on workload 3's input (the 15 sparse
+    """Signature admissibility in bulk on the sparse n=14 system's input (the 15 sparse
     quadratics in n=14 over F_(2^31-1)): f_i carries the signature 1 e_i and
     index i lists the principal syzygies LM(f_j), j < i, so the filter is the
     F5 syzygy criterion.  (1) f4_sig_filter over the Macaulay rows t*f_i for
@@ -450,7 +450,7 @@ def signature_leg(f4, shift_deg, build_shift_deg, reps):
     rows, nonzeros and device time of both."""
     import numpy as np
     import synth
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     G = f4.normalize(p, n, polys, monic=True)
     m = len(G)
     lms = [tuple(g[0][0]) for g in G]
@@ -571,7 +571,7 @@ def same_bases(a, b):
 
 
 def batch_leg(f4, torch, count, autotune):
-    """Workload 4: `count` independent systems (n ~ U{6..9}, m = n+1 dense,
+    """The batch workload: `count` independent systems (n ~ U{6..9}, m = n+1 dense,
     F_65521): one f4_groebner_batch call vs the same systems one by one; every
     batched basis must equal its one-by-one basis (the bench fails otherwise)."""
     import synth
@@ -606,7 +606,7 @@ def batch_leg(f4, torch, count, autotune):
 
 
 def crt_leg(f4, torch, autotune):
-    """Workload 4's CRT part: one n=9 dense system read modulo the 8 largest
+    """The CRT part of the batch workload: one n=9 dense system read modulo the 8 largest
     primes below 2^31, as one batch of 8 against 8 plain runs; bases compared."""
     import synth
     n, polys = synth.crt_system()
@@ -638,7 +638,7 @@ def crt_leg(f4, torch, autotune):
 
 
 def serve_leg(f4, ctx, seconds):
-    """Workload 5: Poisson arrivals (500/s) of systems n ~ U{5..12}, p from
+    """The serving workload: Poisson arrivals (500/s) of systems n ~ U{5..12}, p from
     {65521, 2^31-1}.  The continuous-batching server (admission by estimated
     device footprint) against a plain FIFO that runs f4_groebner per request,
     both on this GPU, on the same stream; latency = completion - arrival."""
@@ -765,7 +765,7 @@ def main():
             sctx.close()
     if not args.no_cpu_baseline:
         import synth
-        n, p, polys = synth.config_system(3)
+        n, p, polys = synth.system("sparse_n14")
         out["cpu_baseline"] = cpu_baseline_step(n, p, polys, s["nnz"])
     print(json.dumps(out))
 

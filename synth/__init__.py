@@ -153,22 +153,25 @@ def reduce_coeffs(polys, p):
 
 
 # ---------------------------------------------------------------------------
-# The five workloads (dense random quadratic systems; one sparse variant).
+# The workloads: dense random quadratic systems and one sparse variant.
 # ---------------------------------------------------------------------------
 
-def config_system(cfg):
-    """Return (n, p, polys) for the single-system workloads 1..3."""
-    if cfg == 1:   # n=6, m=7 dense, F_65521, seed 1
+def system(name):
+    """(n, p, polys) of a named single system: "dense_n6" (n=6, m=7, all 28
+    monomials of degree <= 2, F_65521, seed 1), "dense_n10" (n=10, m=12,
+    F_65521, seed 2), "sparse_n14" (n=14, m=15, 20 monomials each, F_(2^31-1),
+    seed 3)."""
+    if name == "dense_n6":
         return 6, P16, dense_quadratics(6, 7, 1, P16 - 1)
-    if cfg == 2:   # n=10, m=12 dense, F_65521, seed 2
+    if name == "dense_n10":
         return 10, P16, dense_quadratics(10, 12, 2, P16 - 1)
-    if cfg == 3:   # n=14, m=15, 20 monomials each, F_(2^31-1), seed 3
+    if name == "sparse_n14":
         return 14, P31, sparse_quadratics(14, 15, 3, P31 - 1, 20)
-    raise ValueError("single-system workloads are 1, 2 and 3")
+    raise ValueError("single systems: dense_n6, dense_n10, sparse_n14")
 
 
 def batch_systems(count=256):
-    """Workload 4: `count` systems, n ~ U{6..9}, m = n+1 dense, F_65521.
+    """The batch workload: `count` systems, n ~ U{6..9}, m = n+1 dense, F_65521.
 
     System j uses the stream seeded 4*2^32 + j: the first draw picks n, the
     following draws the coefficients.
@@ -185,13 +188,13 @@ def batch_systems(count=256):
 
 
 def crt_system():
-    """Workload 4, CRT leg: one n=9, m=10 dense system (seed 4*2^32+256) with
+    """The CRT leg of the batch workload: one n=9, m=10 dense system (seed 4*2^32+256) with
     integer coefficients in [1, 65520]; read it mod each of CRT_PRIMES."""
     return 9, dense_quadratics(9, 10, (4 << 32) + 256, P16 - 1)
 
 
 def serve_stream(rate=500.0, duration=60.0, limit=None):
-    """Workload 5: Poisson arrivals (exponential gaps from seed 5*2^32 + 2^31).
+    """The serving workload: Poisson arrivals (exponential gaps from seed 5*2^32 + 2^31).
 
     Request j: seed 5*2^32 + j; first draw n ~ U{5..12}, second draw
     p ~ U{65521, 2^31-1}, then dense coefficients U[1, p-1].

@@ -1,4 +1,4 @@
-"""Writes the stored step shapes of workloads 1 and 2 from the CPU oracle O1
+"""Writes the stored step shapes of the dense n=6 and n=10 systems from the CPU oracle O1
 (and nothing else): one line per F4 step,
     d r N M npiv rank rho
 the step degree, rows, dictionary size |T|, nonzeros, pivot columns, rank of
@@ -19,16 +19,16 @@ import synth  # noqa: E402
 
 
 def shapes(cfg):
-    n, p, polys = synth.config_system(cfg)
+    n, p, polys = synth.system(cfg)
     run = oracle.OracleRun(n, p, polys)
     return [(s["d"], s["r"], s["N"], s["M"], s["npiv"], s["rank"], s["rho"]) for s in run.steps()]
 
 
 def main():
-    for cfg in (1, 2):
-        path = os.path.join(HERE, "steps_config%d.txt" % cfg)
+    for cfg in ("dense_n6", "dense_n10"):
+        path = os.path.join(HERE, "steps_%s.txt" % cfg)
         with open(path, "w") as f:
-            f.write("# F4 step shapes of workload %d from the CPU oracle O1 (tests/golden/make_golden.py)\n" % cfg)
+            f.write("# F4 step shapes of the %s system from the CPU oracle O1 (tests/golden/make_golden.py)\n" % cfg)
             f.write("# d r N M npiv rank rho\n")
             for row in shapes(cfg):
                 f.write(" ".join(str(x) for x in row) + "\n")

@@ -1,4 +1,4 @@
-"""The stored step shapes (tests/golden/steps_config*.txt, written by
+"""The stored step shapes (tests/golden/steps_dense_n*.txt, written by
 tests/golden/make_golden.py from O1 alone): the oracle still produces them,
 and they satisfy what the mathematics fixes for any F4 step: |T| <= N(n, d) =
 C(n+d, d) (equation "monomial-count"), rank(A) = |pivot columns| + rank of
@@ -18,16 +18,16 @@ HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 def load(cfg):
     rows = []
-    for line in open(os.path.join(HERE, "steps_config%d.txt" % cfg)):
+    for line in open(os.path.join(HERE, "steps_%s.txt" % cfg)):
         if line.startswith("#") or not line.strip():
             continue
         rows.append(tuple(int(x) for x in line.split()))
     return rows
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("cfg", ["dense_n6", "dense_n10"])
 def test_golden_shapes_invariants_and_oracle(cfg):
-    n, p, polys = synth.config_system(cfg)
+    n, p, polys = synth.system(cfg)
     stored = load(cfg)
     assert stored
     for d, r, N, M, npiv, rank, rho in stored:

@@ -44,16 +44,16 @@ def oracle_shapes(run):
 
 
 @pytest.fixture(scope="module")
-def cfg2():
-    n, p, polys = synth.config_system(2)
+def dense_n10():
+    n, p, polys = synth.system("dense_n10")
     run = oracle.OracleRun(n, p, polys)
     return n, p, polys, canon(run.basis()), oracle_shapes(run)
 
 
 @pytest.mark.parametrize("rows", [1, 2, 3, 4])
-def test_forced_trsm_rows(f4, cfg2, rows):
-    n, p, polys, want_b, want_s = cfg2
-    say("cfg2 trsm_rows", rows)
+def test_forced_trsm_rows(f4, dense_n10, rows):
+    n, p, polys, want_b, want_s = dense_n10
+    say("dense_n10 trsm_rows", rows)
     c = f4.Context(0, trsm_rows=rows)
     B, steps = c.groebner(p, n, polys)
     c.close()
@@ -61,20 +61,20 @@ def test_forced_trsm_rows(f4, cfg2, rows):
 
 
 @pytest.mark.parametrize("bits", [1, 5, 6, 7])
-def test_forced_radix_digits(f4, cfg2, bits):
+def test_forced_radix_digits(f4, dense_n10, bits):
     # the radix dictionary sorts every generated key (hundreds of thousands,
     # multi-workgroup passes); row and emit sorts are single-workgroup
-    n, p, polys, want_b, want_s = cfg2
-    say("cfg2 radix dictionary, radix_bits", bits)
+    n, p, polys, want_b, want_s = dense_n10
+    say("dense_n10 radix dictionary, radix_bits", bits)
     c = f4.Context(0, dict_path="radix", radix_bits=bits)
     B, steps = c.groebner(p, n, polys)
     c.close()
     assert canon(B) == want_b and shapes(steps) == want_s
 
 
-def test_autotuned_runs_and_table_round_trip(f4, cfg2):
-    n, p, polys, want_b, want_s = cfg2
-    say("cfg2 autotune, radix dictionary")
+def test_autotuned_runs_and_table_round_trip(f4, dense_n10):
+    n, p, polys, want_b, want_s = dense_n10
+    say("dense_n10 autotune, radix dictionary")
     c = f4.Context(0, autotune=True, dict_path="radix")
     B, steps = c.groebner(p, n, polys)
     assert canon(B) == want_b and shapes(steps) == want_s
@@ -86,7 +86,7 @@ def test_autotuned_runs_and_table_round_trip(f4, cfg2):
     assert canon(B2) == want_b and shapes(steps2) == want_s
     assert c.tune_table() == text
     c.close()
-    say("cfg2 imported table")
+    say("dense_n10 imported table")
     d = f4.Context(0, autotune=True, dict_path="radix")
     d.load_tune_table(text)
     assert d.tune_table() == text

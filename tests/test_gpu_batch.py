@@ -79,7 +79,7 @@ def test_batch_equals_alone_and_oracle(f4, ctx):
 
 
 def test_batch_of_one_and_repeat(f4, ctx):
-    n, p, polys = synth.config_system(1)
+    n, p, polys = synth.system("dense_n6")
     say("batch of 1 x2")
     a = ctx.groebner_batch([(p, n, polys)])
     b = ctx.groebner_batch([(p, n, polys)])

@@ -51,7 +51,7 @@ def device_basis(f4, ctx, n, mon, coeff, off):
 
 
 def test_build_rejects_malformed_basis(f4, ctx):
-    n, p, polys = synth.config_system(1)
+    n, p, polys = synth.system("dense_n6")
     rec = step_record(n, p, polys, 2)
     mon, coeff, off = f4.polys_to_arrays(n, rec["G"])
     say("build_matrix with the recorded basis (host and device arrays)")
@@ -194,7 +194,7 @@ class HipBudget:
 
 def test_nomem_through_allocator_callbacks(f4):
     # the n = 10 system: its largest step alone holds about 5 MB of CSR
-    n, p, polys = synth.config_system(2)
+    n, p, polys = synth.system("dense_n10")
     want = oracle.OracleRun(n, p, polys).basis()
     hb = HipBudget(1 << 20)  # 1 MiB: far too little for the run
     c = f4.Context(0, alloc=hb.alloc, free=hb.free)

@@ -11,10 +11,10 @@ from test_golden import load
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("cfg", ["dense_n6", "dense_n10"])
 def test_gpu_step_shapes_equal_golden(cfg):
     import paper_2601_06765_amd.f4 as f4
-    n, p, polys = synth.config_system(cfg)
+    n, p, polys = synth.system(cfg)
     print("[case] golden shapes, workload", cfg, flush=True)
     sys.stdout.flush()
     c = f4.Context(0)

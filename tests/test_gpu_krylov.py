@@ -149,7 +149,7 @@ def test_spmm_full_size_macaulay_sampled(env):
     # the operator the benchmark times: degree-10 Macaulay matrix of the
     # sparse n=14 system over F_(2^31-1), b = 8
     f4, c = env
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     polys = f4.normalize(p, n, polys)
     tw, ks = macaulay_rows(f4, n, 8, len(polys))
     say("spmm full-size Macaulay n=14 shift degree 8, rows", len(tw))

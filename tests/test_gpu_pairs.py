@@ -65,10 +65,10 @@ def same_run(dev, host, p, n, polys, label):
     return bd, sd
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_configs(dev, host, cfg):
-    n, p, polys = synth.config_system(cfg)
-    same_run(dev, host, p, n, polys, "config %d" % cfg)
+@pytest.mark.parametrize("cfg", ["dense_n6", "dense_n10"])
+def test_named_systems(dev, host, cfg):
+    n, p, polys = synth.system(cfg)
+    same_run(dev, host, p, n, polys, "system %s" % cfg)
 
 
 RANDOM = [  # n, m, p, seed, density, max_deg
@@ -134,7 +134,7 @@ def test_wide_exponent_lanes(dev, host):
 def test_n14_steps_equal_oracle(f4, host):
     """The n=14 workload up to its first degree-5 step: the device pair sets
     give the oracle's selections and step shapes, and the host pair sets'."""
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     say("n=14 sparse quadratics to degree 5: device pairs vs oracle and host pairs")
     c = f4.Context(0, stop_deg=5)
     try:
@@ -203,7 +203,7 @@ def test_server_equals_host(f4, host):
 
 
 def test_pair_time_is_recorded(f4):
-    n, p, polys = synth.config_system(2)
+    n, p, polys = synth.system("dense_n10")
     say("timing of the device pair update")
     c = f4.Context(0, timing=True)
     try:

@@ -88,27 +88,27 @@ def run_steps(f4, ctx, n, p, polys, label, stop_deg=-1, only=None):
 
 
 # ----------------------------------------------------------- step parity
-def test_steps_config1(f4, ctx):
-    n, p, polys = synth.config_system(1)
-    run_steps(f4, ctx, n, p, polys, "cfg1")
+def test_steps_dense_n6(f4, ctx):
+    n, p, polys = synth.system("dense_n6")
+    run_steps(f4, ctx, n, p, polys, "dense_n6")
 
 
-def test_steps_config1_radix_dictionary(f4, ctx_radix):
-    n, p, polys = synth.config_system(1)
-    run_steps(f4, ctx_radix, n, p, polys, "cfg1/radix")
+def test_steps_dense_n6_radix_dictionary(f4, ctx_radix):
+    n, p, polys = synth.system("dense_n6")
+    run_steps(f4, ctx_radix, n, p, polys, "dense_n6/radix")
 
 
-def test_steps_config2(f4, ctx):
-    n, p, polys = synth.config_system(2)
-    run_steps(f4, ctx, n, p, polys, "cfg2")
+def test_steps_dense_n10(f4, ctx):
+    n, p, polys = synth.system("dense_n10")
+    run_steps(f4, ctx, n, p, polys, "dense_n10")
 
 
-def test_steps_config2_radix_dictionary_large_steps(f4, ctx_radix):
-    n, p, polys = synth.config_system(2)
+def test_steps_dense_n10_radix_dictionary_large_steps(f4, ctx_radix):
+    n, p, polys = synth.system("dense_n10")
     run = oracle.OracleRun(n, p, polys, record=4)
     rec = run.step_record(4)
-    A = check_build(f4, ctx_radix, n, p, rec, "cfg2 step 4 radix")
-    check_reduce(ctx_radix, p, A, rec, "cfg2 step 4 radix")
+    A = check_build(f4, ctx_radix, n, p, rec, "dense_n10 step 4 radix")
+    check_reduce(ctx_radix, p, A, rec, "dense_n10 step 4 radix")
 
 
 @pytest.mark.parametrize("n,p,seed", [(3, 7, 1), (4, 31, 2), (5, 65521, 3), (4, 2147483647, 4),
@@ -123,15 +123,15 @@ def test_steps_sparse_p31(f4, ctx):
     run_steps(f4, ctx, 8, synth.P31, polys, "sparse n=8 p31")
 
 
-def test_step_config3_degree5_full_size(f4, ctx):
+def test_step_sparse_n14_degree5_full_size(f4, ctx):
     # the single degree-5 step of the sparse n=14 system over F_(2^31-1)
-    n, p, polys = synth.config_system(3)
-    say("oracle cfg3 up to d=5 (about 20 s)")
+    n, p, polys = synth.system("sparse_n14")
+    say("oracle sparse_n14 up to d=5 (about 20 s)")
     run = oracle.OracleRun(n, p, polys, record=3, stop_deg=5)
     rec = run.step_record(3)
     assert rec["d"] == 5
-    A = check_build(f4, ctx, n, p, rec, "cfg3 d=5")
-    check_reduce(ctx, p, A, rec, "cfg3 d=5")
+    A = check_build(f4, ctx, n, p, rec, "sparse_n14 d=5")
+    check_reduce(ctx, p, A, rec, "sparse_n14 d=5")
 
 
 # --------------------------------------------------- reduce on given matrices
@@ -227,9 +227,9 @@ def oracle_shapes(run):
     return [(s["d"], s["r"], s["N"], s["M"], s["npiv"], s["rank"], s["rho"]) for s in run.steps()]
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("cfg", ["dense_n6", "dense_n10"])
 def test_groebner_configs(f4, ctx, cfg):
-    n, p, polys = synth.config_system(cfg)
+    n, p, polys = synth.system(cfg)
     say("groebner cfg", cfg)
     B, steps = ctx.groebner(p, n, polys)
     run = oracle.OracleRun(n, p, polys)
@@ -293,10 +293,10 @@ def test_crt_primes_same_system(f4, ctx):
 
 
 def test_determinism_repeated_runs(f4, ctx):
-    n, p, polys = synth.config_system(2)
+    n, p, polys = synth.system("dense_n10")
     run = oracle.OracleRun(n, p, polys, record=3)
     rec = run.step_record(3)
-    say("determinism cfg2 step 3 x3")
+    say("determinism dense_n10 step 3 x3")
     outs = []
     for _ in range(3):
         A = ctx.build_matrix(p, n, rec["G"], rec["active"], rec["sel"])
@@ -310,7 +310,7 @@ def test_determinism_repeated_runs(f4, ctx):
 def test_stop_degree_keeps_leading_steps(f4):
     """A context with a stop degree runs the same steps as a full run up to
     and including the first step of that degree, then stops (empty basis)."""
-    n, p, polys = synth.config_system(1)
+    n, p, polys = synth.system("dense_n6")
     full = f4.Context(0)
     B, steps = full.groebner(p, n, polys)
     full.close()

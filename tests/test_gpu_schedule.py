@@ -93,7 +93,7 @@ def test_random(f4, ctx, r, N, W, C, sigma, seed):
 
 
 def test_every_step_of_n6(f4, ctx):
-    n, p, polys = synth.config_system(1)
+    n, p, polys = synth.system("dense_n6")
     run = oracle.OracleRun(n, p, polys, record=-2)
     for k in range(len(run.steps())):
         rec = run.step_record(k)
@@ -107,7 +107,7 @@ def test_every_step_of_n6(f4, ctx):
 
 
 def test_macaulay_n14(f4, ctx):
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     G = f4.normalize(p, n, polys)
     t = f4.pack_many(n, synth.monomials_upto(n, 3))
     A = ctx.build_matrix_rows_packed(p, n, G, np.repeat(t, len(G)), np.tile(np.arange(len(G), dtype=np.uint32), len(t)))

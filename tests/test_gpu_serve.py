@@ -78,7 +78,7 @@ def test_server_mix_invariance_and_admission(f4):
 def test_server_busy_and_unknown_ticket(f4):
     ctx = f4.Context(0)
     try:
-        n, p, polys = synth.config_system(1)
+        n, p, polys = synth.system("dense_n6")
         srv = f4.Server(ctx, hbm_budget=f4.server_footprint(n, len(polys)), max_slots=8)
         t = srv.submit(p, n, polys)
         assert t is not None

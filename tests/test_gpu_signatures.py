@@ -76,7 +76,7 @@ def test_filter_principal_syzygies(ctx, n, seed):
 
 
 def recorded_steps(cfg, stop_deg=-1):
-    n, p, polys = synth.config_system(cfg)
+    n, p, polys = synth.system(cfg)
     run = oracle.OracleRun(n, p, polys, record=-2, stop_deg=stop_deg)
     return n, p, [run.step_record(k) for k in range(len(run.steps()))]
 
@@ -111,17 +111,17 @@ def check_build(f4, ctx, n, p, rec, m_index, seed, label):
     return st, flags
 
 
-@pytest.mark.parametrize("cfg,m_index,seed", [(1, 7, 1), (1, 3, 2), (2, 12, 3), (2, 5, 4)])
+@pytest.mark.parametrize("cfg,m_index,seed", [("dense_n6", 7, 1), ("dense_n6", 3, 2), ("dense_n10", 12, 3), ("dense_n10", 5, 4)])
 def test_build_sig_every_step(f4, ctx, cfg, m_index, seed):
     n, p, recs = recorded_steps(cfg)
     for k, rec in enumerate(recs):
-        check_build(f4, ctx, n, p, rec, m_index, seed + k, "config %d step %d" % (cfg, k))
+        check_build(f4, ctx, n, p, rec, m_index, seed + k, "system %s step %d" % (cfg, k))
 
 
 def test_build_sig_unconstrained_equals_build(f4, ctx):
     """Distinct indices and no syzygies: every row is admissible and the
     matrix is f4_build_matrix's."""
-    n, p, recs = recorded_steps(2)
+    n, p, recs = recorded_steps("dense_n10")
     rec = recs[-2]
     G = lib_form([list(g) for g in rec["G"]])
     m = len(G)
@@ -138,7 +138,7 @@ def test_build_sig_unconstrained_equals_build(f4, ctx):
 
 
 def test_build_sig_n14_degree4(f4, ctx):
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     run = oracle.OracleRun(n, p, polys, stop_deg=4)
     k = len(run.steps()) - 1
     rec = oracle.OracleRun(n, p, polys, record=k, stop_deg=4).step_record(k)

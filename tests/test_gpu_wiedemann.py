@@ -186,7 +186,7 @@ def test_large_macaulay_step(env):
     the device's symbolic preprocessing from the oracle's recorded selection:
     b = 8 vectors, checked by v^T A = 0 (O5) and by their rank (min(b, r - rank))."""
     f4, c = env
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     run = oracle.OracleRun(n, p, polys, stop_deg=4)
     k = len(run.steps()) - 1
     st = run.steps()[k]

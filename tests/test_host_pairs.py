@@ -47,7 +47,7 @@ def insertion_sequence(n, p, polys):
 
 
 CASES = {
-    "config1": lambda: synth.config_system(1),
+    "dense_n6": lambda: synth.system("dense_n6"),
     "dense_n7": lambda: (7, synth.P16, synth.dense_quadratics(7, 8, 11, synth.P16 - 1)),
     "dense_n8_p31": lambda: (8, synth.P31, synth.dense_quadratics(8, 9, 12, synth.P31 - 1)),
     "sparse_n9": lambda: (9, synth.P16, synth.sparse_quadratics(9, 10, 13, synth.P16 - 1, 12)),

@@ -87,7 +87,7 @@ def test_o1_equals_sympy_homogeneous_and_cubic():
 
 
 def test_unit_ideal_closed_form():
-    n, p, polys = synth.config_system(1)
+    n, p, polys = synth.system("dense_n6")
     B = oracle.groebner(n, p, polys)
     assert B == [[(tuple([0] * n), 1)]]
 
@@ -222,9 +222,9 @@ def check_step(n, p, rec):
     return A, ids
 
 
-@pytest.mark.parametrize("cfg", [1])
-def test_step_objects_config1(cfg):
-    n, p, polys = synth.config_system(cfg)
+@pytest.mark.parametrize("cfg", ["dense_n6"])
+def test_step_objects_dense_n6(cfg):
+    n, p, polys = synth.system(cfg)
     run = oracle.OracleRun(n, p, polys, record=-2)
     steps = run.steps()
     assert len(steps) >= 4

@@ -107,7 +107,7 @@ def test_random_properties(r, N, W, C, sigma, seed):
 
 
 def test_macaulay_product_through_sell():
-    n, p, polys = synth.config_system(1)
+    n, p, polys = synth.system("dense_n6")
     import oracle
     rec = oracle.OracleRun(n, p, polys, record=-2).step_record(2)
     rp, ci, vv = [list(map(int, rec[k])) for k in ("row_ptr", "col_ind", "val")]

@@ -120,7 +120,7 @@ def test_syzygy_rejections_are_principal_syzygies(n, seed):
 
 
 def step_records(cfg):
-    n, p, polys = synth.config_system(cfg)
+    n, p, polys = synth.system(cfg)
     run = oracle.OracleRun(n, p, polys, record=-2)
     return n, [run.step_record(k) for k in range(len(run.steps()))]
 
@@ -135,7 +135,7 @@ def halves(rec, n):
     return rows
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("cfg", ["dense_n6", "dense_n10"])
 def test_unconstrained_closure_is_o1(cfg):
     n, recs = step_records(cfg)
     for rec in recs:
@@ -156,7 +156,7 @@ def synthetic_signatures(G, n, m_index, seed):
     return synth.signatures([o7.lead(g) for g in G], m_index, seed)
 
 
-@pytest.mark.parametrize("cfg,m_index,seed", [(1, 7, 5), (1, 3, 6)])
+@pytest.mark.parametrize("cfg,m_index,seed", [("dense_n6", 7, 5), ("dense_n6", 3, 6)])
 def test_signature_aware_closure_fixed_point(cfg, m_index, seed):
     n, recs = step_records(cfg)
     tested = 0
@@ -205,7 +205,7 @@ def test_signature_aware_closure_fixed_point(cfg, m_index, seed):
 
 def test_schedule_is_stable_bucket_sort():
     rng = random.Random(9)
-    n, recs = step_records(1)
+    n, recs = step_records("dense_n6")
     rec = recs[-1]
     G = [list(g) for g in rec["G"]]
     sidx, smon = synthetic_signatures(G, n, 4, 10)

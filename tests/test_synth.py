@@ -46,13 +46,13 @@ def test_below_is_uniform_and_in_range():
 
 
 def test_workload_shapes():
-    n, p, polys = synth.config_system(1)
+    n, p, polys = synth.system("dense_n6")
     assert (n, p, len(polys)) == (6, 65521, 7)
     assert all(len(f) == 28 for f in polys)
     assert all(1 <= c <= 65520 for f in polys for _, c in f)
-    n, p, polys = synth.config_system(2)
+    n, p, polys = synth.system("dense_n10")
     assert (n, p, len(polys)) == (10, 65521, 12) and all(len(f) == 66 for f in polys)
-    n, p, polys = synth.config_system(3)
+    n, p, polys = synth.system("sparse_n14")
     assert (n, p, len(polys)) == (14, 2147483647, 15)
     for f in polys:
         mons = [e for e, _ in f]
@@ -60,7 +60,7 @@ def test_workload_shapes():
         assert all(sum(e) <= 2 for e in mons)
         assert all(1 <= c <= p - 1 for _, c in f)
     # determinism
-    assert synth.config_system(2) == synth.config_system(2)
+    assert synth.system("dense_n10") == synth.system("dense_n10")
 
 
 def test_batch_and_stream_shapes():
