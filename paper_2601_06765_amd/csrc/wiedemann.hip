@@ -7,10 +7,12 @@
 //   1. the projected block Krylov sequence S_t = X^T B^t (B Y): two block
 //      operator applications (k_spmm on A^T with D folded into its values,
 //      then on A) and a projection per term;
-//   2. the generator: an M-Basis sigma-basis of [S(x)^T ; -I_b] (residual of
-//      every row at the current order, one wave's fraction-free elimination in
-//      the order of (shift, index), the row operations and the multiplication
-//      of pivot rows by x applied to all coefficients), one order per pass;
+//   2. the generator: an M-Basis sigma-basis of [S(x)^T ; -I_b] (one wave's
+//      fraction-free elimination of the residuals at the current order in the
+//      order of (shift, index), then the row operations and the
+//      multiplication of pivot rows by x applied to every coefficient of the
+//      basis P and of the residual series R = P [S^T ; -I], whose next
+//      coefficient is the next order's residual), one order per pass;
 //   3. kernel vectors: u = sum_m B^m Y f_m by Horner for every generator
 //      column at once, then B applied until each column vanishes (its last
 //      nonzero iterate is in ker B), and A^T v = 0 checked.
@@ -100,99 +102,99 @@ void bw_sequence(Ctx& c, u32 p, const BwCsr& A, u32 b, const u32* X, const u32* 
 // P[(i m + j) W + l], W = L + 2 (a row's degree is at most its shift, at most
 // L + 1).  Shifts start at (0^b, 1^b).
 
-// residual coefficient of x^k of row i, column c of P F, F = [S(x)^T ; -I]:
-// sum_{j<b} sum_{l<=min(k, s_i)} P[i][j][l] S[k-l][c][j] - P[i][b+c][k]
-__global__ __launch_bounds__(256) void k_mb_residual(Fp f, u32 b, u32 W, u32 k, const u32* __restrict__ P,
-                                                     const u32* __restrict__ S, const u32* __restrict__ shifts,
-                                                     u32* __restrict__ Delta) {
-    __shared__ u32 s_part[256 / F4_WAVE];
-    const u32 c = blockIdx.x, i = blockIdx.y, m = 2 * b, tid = threadIdx.x;
-    const u32 lmax = min(k, shifts[i]), len = lmax + 1;
-    u64 lo = 0;
-    u32 hi = 0;
-    for (u32 x = tid; x < b * len; x += 256) {
-        const u32 j = x / len, l = x % len;
-        const u64 t = (u64)P[((u64)i * m + j) * W + l] * S[((u64)(k - l) * b + c) * b + j];
-        const u64 n = lo + t;
-        hi += n < lo ? 1u : 0u;
-        lo = n;
-    }
-    const u32 c64 = fp_reduce(f, (u64)f.r32 * f.r32);
-    u64 v = (u64)fp_reduce_any(f, lo) + fp_reduce(f, (u64)fp_reduce32(f, hi) * c64);
-    for (u32 dd = F4_WAVE / 2; dd > 0; dd >>= 1) v += __shfl_xor((unsigned long long)v, dd, F4_WAVE);
-    if (lane_id() == 0) s_part[tid / F4_WAVE] = fp_reduce_any(f, v);
-    __syncthreads();
-    if (tid == 0) {
-        u64 sum = 0;
-        for (u32 w = 0; w < 256 / F4_WAVE; ++w) sum += s_part[w];
-        const u32 own = P[((u64)i * m + b + c) * W + k];
-        Delta[i * b + c] = fp_reduce(f, fp_reduce_any(f, sum) + (u64)(f.p - own));
+// R = P F for P = I, F = [S(x)^T ; -I]: R[i][c] = sum_t S_t[c][i] x^t for
+// i < b, R[b + c][c] = -1; coefficient l of R[i][c] at R[(i b + c) W + l],
+// l < W (coefficients of x^L and above are never read)
+__global__ void k_mb_init_r(Fp f, u32 b, u32 W, u32 L, const u32* __restrict__ S, u32* __restrict__ R) {
+    const u32 m = 2 * b;
+    const u64 total = (u64)m * b * W;
+    for (u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (u64)gridDim.x * blockDim.x) {
+        const u32 l = (u32)(e % W), ic = (u32)(e / W), i = ic / b, c = ic % b;
+        u32 v = 0;
+        if (i < b)
+            v = l < L ? S[((u64)l * b + c) * b + i] : 0u;
+        else
+            v = (l == 0 && i - b == c) ? f.p - 1 : 0u;
+        R[e] = v;
     }
 }
 
-// One wave: the elimination of the residual rows in the order of (shift,
-// index), fraction-free (row_j <- piv row_j - D_j[c] row_i for the rows j
-// after the pivot row i with D_j[c] != 0, c the pivot row's first nonzero
-// column).  Writes the row transform T (m x m, applied to P as P' = T P),
-// the pivot flags and the new shifts (+1 for pivot rows).
-__global__ __launch_bounds__(64) void k_mb_elim(Fp f, u32 b, const u32* __restrict__ Delta,
-                                                const u32* __restrict__ shifts_in, u32* __restrict__ shifts_out,
-                                                u32* __restrict__ T, u32* __restrict__ piv) {
+// The elimination of the residual rows (coefficient k of R) in the order of
+// (shift, index), fraction-free (row_j <- piv row_j - D_j[c] row_i for the
+// rows j after the pivot row i with D_j[c] != 0, c the pivot row's first
+// nonzero column).  One workgroup: per pivot step every (row, entry) of the
+// rows after the pivot row is a thread of its own (entries of D, then of the
+// row transform).  Writes the row transform T (m x m, applied to P as
+// P' = T P), the pivot flags and the new shifts (+1 for pivot rows).
+#define MB_ELIM_THREADS 512
+__global__ __launch_bounds__(MB_ELIM_THREADS) void k_mb_elim(Fp f, u32 b, const u32* __restrict__ R, u32 W, u32 k,
+                                                             const u32* __restrict__ shifts_in,
+                                                             u32* __restrict__ shifts_out, u32* __restrict__ T,
+                                                             u32* __restrict__ piv) {
     __shared__ u32 s_D[32][16];
     __shared__ u32 s_T[32][32];
     __shared__ u32 s_order[32];
-    const u32 m = 2 * b, lane = threadIdx.x;
-    for (u32 x = lane; x < m * b; x += 64) s_D[x / b][x % b] = Delta[x];
-    for (u32 x = lane; x < m * m; x += 64) s_T[x / m][x % m] = (x / m == x % m) ? 1u : 0u;
+    __shared__ u32 s_f[32];  // the pivot column's entry of every row, read before the step's updates
+    __shared__ u32 s_c, s_pv, s_i;
+    const u32 m = 2 * b, tid = threadIdx.x, e = b + m;  // e: entries of a row (D, then T)
+    for (u32 x = tid; x < m * b; x += MB_ELIM_THREADS) s_D[x / b][x % b] = R[(u64)x * W + k];  // residuals at order k
+    for (u32 x = tid; x < m * m; x += MB_ELIM_THREADS) s_T[x / m][x % m] = (x / m == x % m) ? 1u : 0u;
     u32 si = 0;
-    if (lane < m) {
-        si = shifts_in[lane];
+    if (tid < m) {
+        si = shifts_in[tid];
         u32 rank = 0;  // position in the order of (shift, index)
         for (u32 j = 0; j < m; ++j) {
             const u32 sj = shifts_in[j];
-            rank += (sj < si || (sj == si && j < lane)) ? 1u : 0u;
+            rank += (sj < si || (sj == si && j < tid)) ? 1u : 0u;
         }
-        s_order[rank] = lane;
+        s_order[rank] = tid;
     }
     __syncthreads();
-    u32 pivmask = 0;
+    u32 pivmask = 0;  // kept by thread 0
     for (u32 a = 0; a < m; ++a) {
-        const u32 i = s_order[a];
-        const u64 nzc = __ballot(lane < b && s_D[i][lane] != 0);
-        if (!nzc) continue;
-        const u32 c = __ffsll((long long)nzc) - 1;
-        pivmask |= 1u << i;
-        const u32 pv = s_D[i][c];
-        // rows after i in the order: lane handles row order[a + 1 + lane]
-        const u32 jpos = a + 1 + lane;
-        u32 j = 0, fj = 0;
-        if (jpos < m) {
-            j = s_order[jpos];
-            fj = s_D[j][c];
+        if (tid < F4_WAVE) {  // wave 0: the pivot column of row order[a]
+            const u32 i = s_order[a];
+            const u64 nzc = __ballot(tid < b && s_D[i][tid] != 0);
+            if (tid == 0) {
+                s_i = i;
+                s_c = nzc ? (u32)(__ffsll((long long)nzc) - 1) : 0xffffffffu;
+                s_pv = nzc ? s_D[i][s_c] : 0u;
+                if (nzc) pivmask |= 1u << i;
+            }
         }
         __syncthreads();
-        if (jpos < m && fj) {
-            for (u32 x = 0; x < b; ++x)
-                s_D[j][x] = fp_reduce(f, (u64)fp_mul(f, pv, s_D[j][x]) + (f.p - fp_mul(f, fj, s_D[i][x])));
-            for (u32 x = 0; x < m; ++x)
-                s_T[j][x] = fp_reduce(f, (u64)fp_mul(f, pv, s_T[j][x]) + (f.p - fp_mul(f, fj, s_T[i][x])));
+        const u32 c = s_c, i = s_i, pv = s_pv;
+        if (c != 0xffffffffu && tid < m) s_f[tid] = s_D[tid][c];
+        __syncthreads();  // every thread has read this step's s_c before wave 0 writes the next
+        if (c == 0xffffffffu) continue;  // the same in every thread: no pivot in this row
+        for (u32 x = tid; x < (m - 1 - a) * e; x += MB_ELIM_THREADS) {
+            const u32 j = s_order[a + 1 + x / e], y = x % e, fj = s_f[j];
+            if (!fj) continue;
+            u32* el = y < b ? &s_D[j][y] : &s_T[j][y - b];
+            const u32 src = y < b ? s_D[i][y] : s_T[i][y - b];
+            *el = fp_reduce(f, (u64)fp_mul(f, pv, *el) + (f.p - fp_mul(f, fj, src)));
         }
         __syncthreads();
     }
-    for (u32 x = lane; x < m * m; x += 64) T[x] = s_T[x / m][x % m];
-    if (lane < m) {
-        const u32 pv = (pivmask >> lane) & 1u;
-        piv[lane] = pv;
-        shifts_out[lane] = si + pv;
+    for (u32 x = tid; x < m * m; x += MB_ELIM_THREADS) T[x] = s_T[x / m][x % m];
+    __shared__ u32 s_pm;
+    if (tid == 0) s_pm = pivmask;
+    __syncthreads();
+    if (tid < m) {
+        const u32 pvf = (s_pm >> tid) & 1u;
+        piv[tid] = pvf;
+        shifts_out[tid] = si + pvf;
     }
 }
 
 // P'[i][j][l] = sum_q T[i][q] P[q][j][l'] with l' = l - 1 for pivot rows i
 // (multiplication by x) and l' = l otherwise, for l < lcount (higher
-// coefficients are zero in both buffers)
-__global__ __launch_bounds__(256) void k_mb_apply(Fp f, u32 b, u32 W, u32 lcount, const u32* __restrict__ Pin,
-                                                  u32* __restrict__ Pout, const u32* __restrict__ T,
-                                                  const u32* __restrict__ piv) {
+// coefficients are zero in both buffers); the same for the residual series,
+// R'[i][c][l] for k < l < L (the coefficients still to be read)
+__global__ __launch_bounds__(256) void k_mb_apply(Fp f, u32 b, u32 W, u32 lcount, u32 k, u32 L,
+                                                  const u32* __restrict__ Pin, u32* __restrict__ Pout,
+                                                  const u32* __restrict__ Rin, u32* __restrict__ Rout,
+                                                  const u32* __restrict__ T, const u32* __restrict__ piv) {
     __shared__ u32 s_T[32 * 32];
     __shared__ u32 s_piv[32];
     const u32 m = 2 * b, tid = threadIdx.x;
@@ -200,20 +202,27 @@ __global__ __launch_bounds__(256) void k_mb_apply(Fp f, u32 b, u32 W, u32 lcount
     if (tid < m) s_piv[tid] = piv[tid];
     __syncthreads();
     const u64 e = (u64)blockIdx.x * 256 + tid;
-    const u64 total = (u64)m * m * lcount;
-    if (e >= total) return;
-    const u32 l = (u32)(e % lcount), ij = (u32)(e / lcount), i = ij / m, j = ij % m;
+    const u64 totalP = (u64)m * m * lcount;
+    const u32 rcount = L > k + 1 ? L - k - 1 : 0u;
+    const u64 totalR = (u64)m * b * rcount;
+    if (e >= totalP + totalR) return;
+    const bool isP = e < totalP;
+    const u64 x = isP ? e : e - totalP;
+    const u32 span = isP ? lcount : rcount, ncol = isP ? m : b;
+    const u32 l = isP ? (u32)(x % span) : k + 1 + (u32)(x % span);
+    const u32 ij = (u32)(x / span), i = ij / ncol, j = ij % ncol;
+    const u32* in = isP ? Pin : Rin;
     u32 v = 0;
     if (!(s_piv[i] && l == 0)) {
         const u32 ls = s_piv[i] ? l - 1 : l;
         u64 acc = 0;
         for (u32 q = 0; q < m; ++q) {
             const u32 t = s_T[i * m + q];
-            if (t) acc += fp_mul(f, t, Pin[((u64)q * m + j) * W + ls]);
+            if (t) acc += fp_mul(f, t, in[((u64)q * ncol + j) * W + ls]);
         }
         v = fp_reduce_any(f, acc);
     }
-    Pout[((u64)i * m + j) * W + l] = v;
+    (isP ? Pout : Rout)[((u64)i * ncol + j) * W + l] = v;
 }
 
 __global__ void k_bw_identity(u32 m, u32 W, u32* P) {
@@ -224,33 +233,38 @@ void bw_mbasis(Ctx& c, u32 p, u32 b, u32 L, const u32* S, u32* P, u32* shifts) {
     hipStream_t s = c.stream;
     const Fp f = make_fp(p);
     const u32 m = 2 * b, W = L + 2;
-    const u64 psize = (u64)m * m * W;
-    DBuf<u32> P2(&c.pool, psize), Delta(&c.pool, (u64)m * b), T(&c.pool, (u64)m * m), piv(&c.pool, m),
+    const u64 psize = (u64)m * m * W, rsize = (u64)m * b * W;
+    DBuf<u32> P2(&c.pool, psize), R1(&c.pool, rsize), R2(&c.pool, rsize), T(&c.pool, (u64)m * m), piv(&c.pool, m),
         sh2(&c.pool, m);
     fill_u32(P, psize, 0, s);
     fill_u32(P2.ptr, psize, 0, s);
-    // P = I, shifts (0^b, 1^b)
+    // P = I, shifts (0^b, 1^b), R = F
     std::vector<u32> hs(m);
     for (u32 i = 0; i < m; ++i) hs[i] = i < b ? 0u : 1u;
     upload(c, shifts, hs.data(), m * 4);
     hipLaunchKernelGGL(k_bw_identity, dim3(1), dim3(64), 0, s, m, W, P);
     F4_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mb_init_r, dim3(std::max<u32>(1, std::min<u32>(1024, ceil_div(rsize, 256)))), dim3(256), 0, s,
+                       f, b, W, L, S, R1.ptr);
+    F4_LAUNCH_CHECK();
     u32* cur = P;
     u32* nxt = P2.ptr;
+    u32* rcur = R1.ptr;
+    u32* rnxt = R2.ptr;
     u32* scur = shifts;
     u32* snxt = sh2.ptr;
     for (u32 k = 0; k < L; ++k) {
-        hipLaunchKernelGGL(k_mb_residual, dim3(b, m), dim3(256), 0, s, f, b, W, k, cur, S, scur, Delta.ptr);
-        F4_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_mb_elim, dim3(1), dim3(64), 0, s, f, b, Delta.ptr, scur, snxt, T.ptr, piv.ptr);
+        hipLaunchKernelGGL(k_mb_elim, dim3(1), dim3(MB_ELIM_THREADS), 0, s, f, b, rcur, W, k, scur, snxt, T.ptr,
+                           piv.ptr);
         F4_LAUNCH_CHECK();
         // degrees after this order are at most k + 2
         const u32 lcount = std::min(W, k + 3);
-        const u64 total = (u64)m * m * lcount;
-        hipLaunchKernelGGL(k_mb_apply, dim3(ceil_div(total, 256)), dim3(256), 0, s, f, b, W, lcount, cur, nxt,
-                           T.ptr, piv.ptr);
+        const u64 total = (u64)m * m * lcount + (u64)m * b * (L > k + 1 ? L - k - 1 : 0u);
+        hipLaunchKernelGGL(k_mb_apply, dim3(ceil_div(total, 256)), dim3(256), 0, s, f, b, W, lcount, k, L, cur, nxt,
+                           rcur, rnxt, T.ptr, piv.ptr);
         F4_LAUNCH_CHECK();
         std::swap(cur, nxt);
+        std::swap(rcur, rnxt);
         std::swap(scur, snxt);
     }
     if (cur != P) F4_HIP_TRY(hipMemcpyAsync(P, cur, psize * 4, hipMemcpyDeviceToDevice, s));
