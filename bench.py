@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--batch-systems", type=int, default=256, help="systems in the batched leg (0: skip)")
     ap.add_argument("--crt", type=int, default=1, help="run the 8-prime CRT leg (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg (0: skip)")
+    ap.add_argument("--serve-light-rate", type=float, default=60.0,
+                    help="arrival rate of a second serving run below the service's throughput (0: skip)")
     ap.add_argument("--modloop-chains", type=int, default=1 << 21,
                     help="chains of the modular inner-loop microbenchmark (0: skip)")
     ap.add_argument("--modloop-iters", type=int, default=4096)
@@ -637,13 +639,16 @@ def crt_leg(f4, torch, autotune):
             "nnz_total": sum(s["nnz"] for _, st in res for s in st)}
 
 
-def serve_leg(f4, ctx, seconds):
+def serve_leg(f4, ctx, seconds, rate=500.0):
     """The serving workload: Poisson arrivals (500/s) of systems n ~ U{5..12}, p from
     {65521, 2^31-1}.  The continuous-batching server (admission by estimated
     device footprint) against a plain FIFO that runs f4_groebner per request,
-    both on this GPU, on the same stream; latency = completion - arrival."""
+    both on this GPU, on the same stream; latency = completion - arrival.
+    At 500/s both saturate (the latencies grow with the window); a lower
+    `rate`, below both throughputs, gives the latencies of the service
+    itself."""
     import synth
-    stream = synth.serve_stream(rate=500.0, duration=seconds)
+    stream = synth.serve_stream(rate=rate, duration=seconds)
     preps = [f4.Server.prepare(p, n, polys) for _, n, p, polys in stream]
     arrivals = [t for t, _, _, _ in stream]
 
@@ -686,8 +691,8 @@ def serve_leg(f4, ctx, seconds):
         ctx.groebner_prepared(pprep[i])
         plat.append(time.perf_counter() - t0 - arrivals[i])
     plain_s = time.perf_counter() - t0
-    return {"workload": "Poisson 500/s for %.1f s: %d requests, n ~ U{5..12}, p in {65521, 2^31-1}" %
-                        (seconds, len(stream)),
+    return {"workload": "Poisson %g/s for %.1f s: %d requests, n ~ U{5..12}, p in {65521, 2^31-1}" %
+                        (rate, seconds, len(stream)),
             "requests": len(stream),
             "served_systems_per_s": len(stream) / served_s,
             "served_p50_s": pct(lat, 0.50), "served_p99_s": pct(lat, 0.99),
@@ -762,6 +767,8 @@ def main():
         if args.serve_seconds > 0:
             sctx = f4.Context(0, autotune=tune)
             out["serve"] = serve_leg(f4, sctx, args.serve_seconds)
+            if args.serve_light_rate > 0:
+                out["serve_below_capacity"] = serve_leg(f4, sctx, args.serve_seconds, args.serve_light_rate)
             sctx.close()
     if not args.no_cpu_baseline:
         import synth
