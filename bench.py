@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10, help="timed runs of the headline step (median reported)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-batch-systems", type=int, default=64,
+                    help="batch systems the oracle solves for the batch baseline (0: skip)")
+    ap.add_argument("--cpu-workers", type=int, default=16, help="host processes of the batch baseline")
     ap.add_argument("--dict", choices=["rank", "radix"], default=None)
     ap.add_argument("--full-runs", type=int, default=20, help="timed full F4 runs of the n=10 system (0: skip)")
     ap.add_argument("--batch-systems", type=int, default=256, help="systems in the batched leg (0: skip)")
@@ -268,6 +271,31 @@ def cpu_baseline_step(n, p, polys, nnz):
     return {"value": nnz / step_s, "unit": "nnz/s", "cores": 1, "kind": "oracle",
             "sample": "one oracle run to the first degree-5 step of the n=14 sparse system (%.1f s in all); "
                       "that step's build %.2f s + elimination %.2f s, single thread" % (dt, tb * 1e-9, tr * 1e-9)}
+
+
+def _oracle_basis(job):
+    """One oracle Groebner basis (a worker of the batch baseline)."""
+    import oracle
+    n, p, polys = job
+    oracle.OracleRun(n, p, polys).basis()
+    return n
+
+
+def cpu_baseline_batch(count, workers):
+    """The oracle on the batch workload's first `count` systems (the same
+    n ~ U{6..9} dense systems as the batched leg), one process per host core
+    up to `workers`: systems per second of wall time."""
+    import multiprocessing as mp
+    import synth
+    jobs = [(n, p, polys) for n, p, polys in synth.batch_systems(count)]
+    cores = max(1, min(workers, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        sizes = pool.map(_oracle_basis, jobs, chunksize=1)
+    dt = time.perf_counter() - t0
+    return {"value": len(jobs) / dt, "unit": "systems/s", "cores": cores, "kind": "oracle",
+            "sample": "the first %d systems of the batch workload (n = 6..9: %s), %.1f s of wall time" %
+                      (len(jobs), "/".join(str(sizes.count(k)) for k in (6, 7, 8, 9)), dt)}
 
 
 def full_f4_leg(f4, torch, runs, warmup, autotune, dict_path):
@@ -774,6 +802,10 @@ def main():
         import synth
         n, p, polys = synth.system("sparse_n14")
         out["cpu_baseline"] = cpu_baseline_step(n, p, polys, s["nnz"])
+        if args.batch_systems and args.cpu_batch_systems:
+            # the batch metric's host reference, in the same leg (a process pool)
+            out["cpu_baseline"]["batch"] = cpu_baseline_batch(min(args.batch_systems, args.cpu_batch_systems),
+                                                              args.cpu_workers)
     print(json.dumps(out))
 
 
