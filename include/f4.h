@@ -436,11 +436,12 @@ typedef struct f4_schedule_view {
 /* Build (or rebuild) the schedule of a handle of one system.  W >= 1,
  * 1 <= C <= 64, sigma >= 1; out may be NULL.  F4_E_ARG: bad parameters or a
  * batch handle; F4_E_STATE: unknown handle; F4_E_RANGE: key widths exceeded
- * (more than 2^30 panels); F4_E_NOMEM. */
+ * (2^30 panels or more, or a sort key of the rows past 64 bits); F4_E_NOMEM. */
 int f4_matrix_schedule(f4_ctx* ctx, f4_matrix* A, uint32_t W, uint32_t C, uint32_t sigma, f4_schedule_view* out,
                        void* stream);
-/* Y = A X over F_p through the schedule's slices (one wave per slice, a lane
- * per row; b <= 8 device vectors, row-major as for f4_spmm; the same result
+/* Y = A X over F_p through the schedule's slices (one wave per slice, each
+ * row of the slice on a few lanes that split the b vectors; b <= 8 device
+ * vectors, row-major as for f4_spmm, any 4-byte alignment; the same result
  * as f4_spmm).  F4_E_STATE: no schedule built; F4_E_ARG: bad p, b, blocks. */
 int f4_spmm_sell(f4_ctx* ctx, uint32_t p, const f4_matrix* A, uint32_t b, const uint32_t* X, uint32_t* Y,
                  void* stream);
