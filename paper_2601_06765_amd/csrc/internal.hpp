@@ -229,8 +229,23 @@ void tune_parse(Ctx& c, const char* text);
 // Block operator application (krylov.hip): Y = A X over F_p for a CSR matrix
 // (nrows rows) and a row-major block X of b <= 64 columns; words of the
 // matrix values and of X are read modulo p.  Enqueued on c.stream.
+// optional epilogues of the block product (Krylov branch): a projection
+// PX^T Y added into S64; AY AF added to the output; or the output's
+// nonzero-column flags into NZ with the columns of KP flagged in KNZ copied
+// into K
+struct SpmmEpi {
+    const u32* PX = nullptr;
+    unsigned long long* S64 = nullptr;
+    const u32* AY = nullptr;
+    const u32* AF = nullptr;
+    u32 ayb = 0;
+    u32* NZ = nullptr;
+    const u32* KP = nullptr;
+    const u32* KNZ = nullptr;
+    u32* K = nullptr;
+};
 void spmm_run(hipStream_t s, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X,
-              u32* Y);
+              u32* Y, const SpmmEpi& ep = SpmmEpi());
 // CSR of the transpose (the CSC of A): column pointers, row indices, values.
 void csr_transpose(Ctx& c, u32 nrows, u32 ncols, u64 nnz, const u32* ptr, const u32* idx, const u32* val,
                    DBuf<u32>& tptr, DBuf<u32>& tidx, DBuf<u32>& tval);

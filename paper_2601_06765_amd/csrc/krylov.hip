@@ -24,11 +24,39 @@
 #include "../../include/f4.h"
 
 #define SPMM_WG 256
+#define SPMM_PROJ_MAX 16  // widest block of the fused projection
 
-template <int BP, int G, int VW>
+// Epilogues (EPI) for the Krylov branch, each saving a launch per term:
+// SPMM_EPI_PROJ also adds the projection PX^T Y (b x b, PX an nrows x b
+// block) into the 64-bit accumulators S64: every output word times the b
+// words of its row of PX, each product reduced, summed in LDS per workgroup
+// and added with one atomic per entry and workgroup (X^T B^t (B Y) of the
+// sequence); SPMM_EPI_ADD adds AY AF to the output (AY nrows x ayb, AF
+// ayb x b), the Horner step Y F_m of the kernel vectors; SPMM_EPI_NZKEEP
+// flags the output's nonzero columns in NZ (an OR per column and
+// workgroup) and copies the columns of the previous iterate KP flagged in
+// KNZ into K (the kernel vectors' iterates B^e u).
+#define SPMM_EPI_NONE 0
+#define SPMM_EPI_PROJ 1
+#define SPMM_EPI_ADD 2
+#define SPMM_EPI_NZKEEP 3
+template <int BP, int G, int VW, int EPI = SPMM_EPI_NONE>
 __global__ __launch_bounds__(SPMM_WG) void k_spmm(Fp f, u32 nrows, u32 b, const u32* __restrict__ ptr,
                                                    const u32* __restrict__ idx, const u32* __restrict__ val,
-                                                   const u32* __restrict__ X, u32* __restrict__ Y) {
+                                                   const u32* __restrict__ X, u32* __restrict__ Y, SpmmEpi ep) {
+    constexpr bool PROJ = EPI == SPMM_EPI_PROJ;
+    const u32* __restrict__ PX = ep.PX;
+    unsigned long long* __restrict__ S64 = ep.S64;
+    __shared__ unsigned long long s_pj[PROJ ? SPMM_PROJ_MAX * SPMM_PROJ_MAX : 1];
+    __shared__ u32 s_nz[EPI == SPMM_EPI_NZKEEP ? 64 : 1];
+    if (PROJ) {
+        for (u32 x = threadIdx.x; x < b * b; x += SPMM_WG) s_pj[x] = 0;
+        __syncthreads();
+    }
+    if (EPI == SPMM_EPI_NZKEEP) {
+        for (u32 x = threadIdx.x; x < b; x += SPMM_WG) s_nz[x] = 0;
+        __syncthreads();
+    }
     constexpr u32 SLOTS = G / BP;
     static_assert(G <= F4_WAVE && G % BP == 0 && (VW == 1 || VW == 2), "group layout");
     // workgroups go to the eight XCDs in turn; give each XCD a contiguous range
@@ -92,57 +120,111 @@ __global__ __launch_bounds__(SPMM_WG) void k_spmm(Fp f, u32 nrows, u32 b, const 
         for (u32 d = BP; d < G; d <<= 1) acc += (u64)__shfl_xor((unsigned long long)acc, (int)d, G);
         out[v] = fp_reduce_any(f, acc);
     }
+    if (EPI == SPMM_EPI_ADD && live && slot == 0 && k < b) {
+#pragma unroll
+        for (u32 v = 0; v < VW; ++v) {
+            if (k + v >= b) continue;
+            u64 acc = out[v];
+            for (u32 kk = 0; kk < ep.ayb; ++kk) {
+                const u32 fk = ep.AF[kk * b + k + v];
+                if (fk) acc += fp_mul(f, fp_reduce32(f, ep.AY[g * ep.ayb + kk]), fk);
+            }
+            out[v] = fp_reduce_any(f, acc);
+        }
+    }
     if (live && slot == 0 && k < b) {
         if (VW == 2)
             *reinterpret_cast<uint2*>(Y + g * b + k) = make_uint2(out[0], out[VW - 1]);
         else
             Y[g * b + k] = out[0];
+        if (PROJ) {
+            // entry (kk, l) of the projection: PX[g][kk] Y[g][l]; products
+            // below p, at most SPMM_WG of them per entry and workgroup
+            for (u32 kk = 0; kk < b; ++kk) {
+                const u32 xk = fp_reduce32(f, PX[g * b + kk]);
+#pragma unroll
+                for (u32 v = 0; v < VW; ++v)
+                    if (k + v < b && xk && out[v])
+                        atomicAdd(&s_pj[kk * b + k + v], (unsigned long long)fp_mul(f, xk, out[v]));
+            }
+        }
+    }
+    if (EPI == SPMM_EPI_NZKEEP && live && slot == 0 && k < b) {
+#pragma unroll
+        for (u32 v = 0; v < VW; ++v) {
+            const u32 col = k + v;
+            if (col >= b) continue;
+            if (out[v]) s_nz[col] = 1u;  // every writer stores 1
+            if (ep.KNZ[col]) ep.K[g * b + col] = ep.KP[g * b + col];
+        }
+    }
+    if (PROJ) {
+        __syncthreads();
+        for (u32 x = threadIdx.x; x < b * b; x += SPMM_WG)
+            if (s_pj[x]) atomicAdd(&S64[x], s_pj[x]);
+    }
+    if (EPI == SPMM_EPI_NZKEEP) {
+        __syncthreads();
+        for (u32 x = threadIdx.x; x < b; x += SPMM_WG)
+            if (s_nz[x]) atomicOr(&ep.NZ[x], 1u);
     }
 }
 
 template <int BP, int G, int VW>
 static void spmm_launch(hipStream_t s, const Fp& f, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val,
-                        const u32* X, u32* Y) {
+                        const u32* X, u32* Y, const SpmmEpi& ep) {
     const u32 grid = ceil_div((u64)nrows * G, SPMM_WG);
-    hipLaunchKernelGGL((k_spmm<BP, G, VW>), dim3(grid), dim3(SPMM_WG), 0, s, f, nrows, b, ptr, idx, val, X, Y);
+    if (ep.PX)
+        hipLaunchKernelGGL((k_spmm<BP, G, VW, SPMM_EPI_PROJ>), dim3(grid), dim3(SPMM_WG), 0, s, f, nrows, b, ptr, idx,
+                           val, X, Y, ep);
+    else if (ep.AY)
+        hipLaunchKernelGGL((k_spmm<BP, G, VW, SPMM_EPI_ADD>), dim3(grid), dim3(SPMM_WG), 0, s, f, nrows, b, ptr, idx,
+                           val, X, Y, ep);
+    else if (ep.NZ)
+        hipLaunchKernelGGL((k_spmm<BP, G, VW, SPMM_EPI_NZKEEP>), dim3(grid), dim3(SPMM_WG), 0, s, f, nrows, b, ptr,
+                           idx, val, X, Y, ep);
+    else
+        hipLaunchKernelGGL((k_spmm<BP, G, VW>), dim3(grid), dim3(SPMM_WG), 0, s, f, nrows, b, ptr, idx, val, X, Y, ep);
     F4_LAUNCH_CHECK();
 }
 
 void spmm_run(hipStream_t s, u32 p, u32 nrows, u32 b, const u32* ptr, const u32* idx, const u32* val, const u32* X,
-              u32* Y) {
+              u32* Y, const SpmmEpi& ep) {
     if (nrows == 0) return;
+    if (ep.PX && b > SPMM_PROJ_MAX) throw F4Error{1, "projection wider than the fused form"};
+    if (ep.NZ && b > 64) throw F4Error{1, "flagged block wider than the fused form"};
     const Fp f = make_fp(p);
     // two words per lane: an even b, and X and Y 8-byte aligned (caller
     // blocks need not be; then one word per lane)
     if (b % 2 == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 7) == 0) {
         if (b <= 2)
-            spmm_launch<1, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<1, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
         else if (b <= 4)
-            spmm_launch<2, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<2, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
         else if (b <= 8)
-            spmm_launch<4, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<4, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
         else if (b <= 16)
-            spmm_launch<8, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<8, 8, 2>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
         else if (b <= 32)
-            spmm_launch<16, 16, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<16, 16, 2>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
         else
-            spmm_launch<32, 32, 2>(s, f, nrows, b, ptr, idx, val, X, Y);
+            spmm_launch<32, 32, 2>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
         return;
     }
     if (b <= 1)
-        spmm_launch<1, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<1, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
     else if (b <= 2)
-        spmm_launch<2, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<2, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
     else if (b <= 4)
-        spmm_launch<4, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<4, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
     else if (b <= 8)
-        spmm_launch<8, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<8, 8, 1>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
     else if (b <= 16)
-        spmm_launch<16, 16, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<16, 16, 1>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
     else if (b <= 32)
-        spmm_launch<32, 32, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<32, 32, 1>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
     else
-        spmm_launch<64, 64, 1>(s, f, nrows, b, ptr, idx, val, X, Y);
+        spmm_launch<64, 64, 1>(s, f, nrows, b, ptr, idx, val, X, Y, ep);
 }
 
 // ------------------------------------------------------------ transpose

@@ -5,8 +5,8 @@
 // dictionary closure").  The square operator is B = A D A^T (D a diagonal of
 // nonzero elements); every step below runs on the device:
 //   1. the projected block Krylov sequence S_t = X^T B^t (B Y): two block
-//      operator applications (k_spmm on A^T with D folded into its values,
-//      then on A) and a projection per term;
+//      operator applications per term (k_spmm on A^T with D folded into its
+//      values, then on A with the projection X^T Z added by the same launch);
 //   2. the generator: an M-Basis sigma-basis of [S(x)^T ; -I_b] (one wave's
 //      fraction-free elimination of the residuals at the current order in the
 //      order of (shift, index), then the row operations and the
@@ -29,36 +29,17 @@ __global__ void k_bw_scale_rows(Fp f, u32 nrows, const u32* __restrict__ ptr, co
     for (u32 e = ptr[j]; e < ptr[j + 1]; ++e) out[e] = fp_mul(f, fp_reduce32(f, val[e]), dj);
 }
 
-// S64[k b + l] += sum over this workgroup's rows g of X[g][k] Z[g][l]: one
-// thread per (k, l), the products summed exactly in 96 bits, reduced once
-__global__ __launch_bounds__(256) void k_bw_proj(Fp f, u32 r, u32 b, u32 rows_per, const u32* __restrict__ X,
-                                                 const u32* __restrict__ Z, unsigned long long* __restrict__ S64) {
-    const u32 tid = threadIdx.x;
-    if (tid >= b * b) return;
-    const u32 k = tid / b, l = tid % b;
-    const u32 g0 = blockIdx.x * rows_per, g1 = min(r, g0 + rows_per);
-    u64 lo = 0;
-    u32 hi = 0;
-    for (u32 g = g0; g < g1; ++g) {
-        const u64 t = (u64)fp_reduce32(f, X[(u64)g * b + k]) * Z[(u64)g * b + l];
-        const u64 n = lo + t;
-        hi += n < lo ? 1u : 0u;
-        lo = n;
-    }
-    const u32 c64 = fp_reduce(f, (u64)f.r32 * f.r32);  // 2^64 mod p
-    const u32 v = fp_reduce_any(f, (u64)fp_reduce_any(f, lo) + fp_reduce(f, (u64)fp_reduce32(f, hi) * c64));
-    if (v) atomicAdd(&S64[tid], (unsigned long long)v);
-}
-
 __global__ void k_bw_reduce64(Fp f, u64 n, const unsigned long long* __restrict__ in, u32* __restrict__ out) {
     const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = fp_reduce_any(f, in[i]);
 }
 
-static void bw_apply(Ctx& c, u32 p, const BwCsr& A, u32 w, const u32* V, u32* U, u32* Out) {
-    // Out = A (D (A^T V)): U is N x w scratch
+static void bw_apply(Ctx& c, u32 p, const BwCsr& A, u32 w, const u32* V, u32* U, u32* Out,
+                     const SpmmEpi& ep = SpmmEpi()) {
+    // Out = A (D (A^T V)): U is N x w scratch; the epilogue (a projection of
+    // Out, or an added block) runs in the second product
     spmm_run(c.stream, p, A.N, w, A.tptr, A.tidx, A.tval_d, V, U);
-    spmm_run(c.stream, p, A.r, w, A.ptr, A.idx, A.val, U, Out);
+    spmm_run(c.stream, p, A.r, w, A.ptr, A.idx, A.val, U, Out, ep);
 }
 
 void bw_scale_transpose(Ctx& c, u32 p, const BwCsr& A, const u32* d, u32* tval_d) {
@@ -75,19 +56,18 @@ void bw_sequence(Ctx& c, u32 p, const BwCsr& A, u32 b, const u32* X, const u32* 
         Z2(&c.pool, std::max<u64>((u64)A.r * b, 1));
     DBuf<u64> S64(&c.pool, std::max<u64>((u64)L * b * b, 1));
     fill_u64(S64.ptr, (u64)L * b * b, 0, s);
-    bw_apply(c, p, A, b, Y, U.ptr, Z.ptr);
-    const u32 groups = std::max<u32>(1, std::min<u32>(1024, ceil_div(A.r, 64)));
-    const u32 rows_per = ceil_div(A.r, groups);
-    for (u32 t = 0; t < L; ++t) {
-        if (A.r) {
-            hipLaunchKernelGGL(k_bw_proj, dim3(groups), dim3(256), 0, s, f, A.r, b, rows_per, X, Z.ptr,
-                               (unsigned long long*)S64.ptr + (u64)t * b * b);
-            F4_LAUNCH_CHECK();
-        }
-        if (t + 1 < L) {
-            bw_apply(c, p, A, b, Z.ptr, U.ptr, Z2.ptr);
-            std::swap(Z.ptr, Z2.ptr);
-        }
+    // term t: Z = B^(t+1) Y, its projection X^T Z formed by the second block
+    // product of the term (two launches per term)
+    SpmmEpi ep;
+    ep.PX = X;
+    if (L) {
+        ep.S64 = (unsigned long long*)S64.ptr;
+        bw_apply(c, p, A, b, Y, U.ptr, Z.ptr, ep);
+    }
+    for (u32 t = 1; t < L; ++t) {
+        ep.S64 = (unsigned long long*)S64.ptr + (u64)t * b * b;
+        bw_apply(c, p, A, b, Z.ptr, U.ptr, Z2.ptr, ep);
+        std::swap(Z.ptr, Z2.ptr);
     }
     const u64 n = (u64)L * b * b;
     if (n) {
@@ -312,28 +292,39 @@ void bw_kernel_vectors(Ctx& c, u32 p, const BwCsr& A, u32 b, const u32* Y, u32 w
     fill_u32(K, rw, 0, s);
     fill_u32(nzhist, (u64)E * w, 0, s);
     fill_u32(nzcheck, w, 0, s);
-    for (u32 mm = Dmax + 1; mm-- > 0;) {
-        if (mm != Dmax) {
-            bw_apply(c, p, A, w, U.ptr, T.ptr, V.ptr);
-            std::swap(U.ptr, V.ptr);
-        }
-        if (rw) {
-            hipLaunchKernelGGL(k_bw_axpy, dim3(g), dim3(256), 0, s, f, A.r, b, w, Y, F + (u64)mm * b * w, U.ptr);
-            F4_LAUNCH_CHECK();
-        }
+    if (rw) {
+        hipLaunchKernelGGL(k_bw_axpy, dim3(g), dim3(256), 0, s, f, A.r, b, w, Y, F + (u64)Dmax * b * w, U.ptr);
+        F4_LAUNCH_CHECK();
     }
-    // iterates U, B U, B^2 U, ...: nonzero flags per iterate, nonzero columns kept
-    for (u32 e = 0; e < E; ++e) {
-        if (rw) {
-            hipLaunchKernelGGL(k_bw_nzcols, dim3(g), dim3(256), 0, s, A.r, w, U.ptr, nzhist + (u64)e * w);
-            F4_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_bw_keep, dim3(g), dim3(256), 0, s, A.r, w, U.ptr, nzhist + (u64)e * w, K);
-            F4_LAUNCH_CHECK();
-        }
-        if (e + 1 < E) {
-            bw_apply(c, p, A, w, U.ptr, T.ptr, V.ptr);
-            std::swap(U.ptr, V.ptr);
-        }
+    for (u32 mm = Dmax; mm-- > 0;) {
+        // U <- B U + Y F_m: the addition is the second product's epilogue
+        SpmmEpi ep;
+        ep.AY = Y;
+        ep.AF = F + (u64)mm * b * w;
+        ep.ayb = b;
+        bw_apply(c, p, A, w, U.ptr, T.ptr, V.ptr, ep);
+        std::swap(U.ptr, V.ptr);
+    }
+    // iterates U, B U, B^2 U, ...: nonzero flags per iterate, nonzero columns
+    // kept.  The product that forms iterate e + 1 also flags its nonzero
+    // columns and keeps the nonzero columns of iterate e (its input, whose
+    // flags are complete), so an iterate costs the two products alone.
+    if (rw && E) {
+        hipLaunchKernelGGL(k_bw_nzcols, dim3(g), dim3(256), 0, s, A.r, w, U.ptr, nzhist);
+        F4_LAUNCH_CHECK();
+    }
+    for (u32 e = 0; e + 1 < E; ++e) {
+        SpmmEpi ep;
+        ep.NZ = nzhist + (u64)(e + 1) * w;
+        ep.KP = U.ptr;
+        ep.KNZ = nzhist + (u64)e * w;
+        ep.K = K;
+        bw_apply(c, p, A, w, U.ptr, T.ptr, V.ptr, ep);
+        std::swap(U.ptr, V.ptr);
+    }
+    if (rw && E) {
+        hipLaunchKernelGGL(k_bw_keep, dim3(g), dim3(256), 0, s, A.r, w, U.ptr, nzhist + (u64)(E - 1) * w, K);
+        F4_LAUNCH_CHECK();
     }
     // A^T K: zero columns are syzygies
     spmm_run(s, p, A.N, w, A.tptr, A.tidx, A.tval, K, T.ptr);
