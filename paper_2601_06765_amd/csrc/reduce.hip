@@ -312,6 +312,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
     __shared__ u64 s_xs[2][TR_MAXR][PANEL];  // partial sums of x = l T^-1 (double buffered)
     __shared__ u64 s_hit[TR_MAXR];
     __shared__ u32 s_lead[TR_MAXR];
+    __shared__ u32 s_first_pc;
     const SegR S = segs[sys_base + blockIdx.y];
     if (trsm_class(S) != MODE || S.c == 0) return;
     const u32 cnt = tail ? S.r : S.L;  // rows of this system in the list
@@ -325,15 +326,26 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
     for (u32 j = tid; j < nr * N; j += TR_THREADS) acc[j] = 0;
     if (tid < TR_MAXR) s_lead[tid] = 0xffffffffu;
     if (tid < PANEL) s_x[tid] = make_uint4(0u, 0u, 0u, 0u);
+    if (tid == 0) s_first_pc = 0xffffffffu;
     __syncthreads();
     const u32* pm = perm + S.cb;
+    // the tile's first pivot column with a nonzero entry: the panels before
+    // it hold zeros in every row of the tile and receive nothing (updates
+    // only flow to later columns), so the solve starts at its panel
+    u32 mnpc = 0xffffffffu;
     for (u32 r = 0; r < nr; ++r) {
         const u32 i = list[S.lb + t0 + r];
-        for (u32 e = row_ptr[i] + (skip_lead ? 1 : 0) + tid; e < row_ptr[i + 1]; e += TR_THREADS)
-            acc[r * N + pm[col_ind[e]]] = val[e];
+        for (u32 e = row_ptr[i] + (skip_lead ? 1 : 0) + tid; e < row_ptr[i + 1]; e += TR_THREADS) {
+            const u32 pc = pm[col_ind[e]];
+            acc[r * N + pc] = val[e];
+            mnpc = min(mnpc, pc);
+        }
     }
+    for (u32 d = F4_WAVE / 2; d > 0; d >>= 1) mnpc = min(mnpc, (u32)__shfl_xor((int)mnpc, (int)d, F4_WAVE));
+    if (lane == 0) atomicMin(&s_first_pc, mnpc);
     __syncthreads();
     const u32 npanels = (npiv + PANEL - 1) / PANEL;
+    const u32 kp0 = s_first_pc < npiv ? s_first_pc / PANEL : npanels;  // npanels: no pivot column set
     // Per panel: (A) every wave w forms, for each row of the tile, the partial
     // products of rows 4w..4w+3 of T^-1 with the row's panel values and adds
     // them into s_xs; (B) the tile's waves finish x = l T^-1; (C) every
@@ -360,9 +372,9 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm(const SegR* segs, u32 sys_b
         }
     };
     if (tid < 2 * TR_MAXR * PANEL) (&s_xs[0][0][0])[tid] = 0;
-    if (npanels) load_panel(0, tin, t, ea, eb);
+    if (kp0 < npanels) load_panel(kp0, tin, t, ea, eb);
     __syncthreads();
-    for (u32 kp = 0; kp < npanels; ++kp) {
+    for (u32 kp = kp0; kp < npanels; ++kp) {
         const u32 qa = kp * PANEL, wk = min((u32)PANEL, npiv - qa), buf = kp & 1;
         // (A) partial products: lane j reduces the row's panel value l_j once
         // (contiguous LDS reads), and the wave takes its BW values from those
