@@ -874,6 +874,7 @@ __device__ __forceinline__ double dmod(double x, double pd, double pinv) {
 // there), except in new pivot rows, which are written whole.
 #define ECH_RT 32
 #define ECH_CT 256
+typedef double ech_d4 __attribute__((ext_vector_type(4)));
 #define ECH_SPAN_MAX 1024  // most columns of one tile (passes of ECH_CT columns)
 #define ECH_SHORT 1024     // rows of at most this many trailing columns use the per-row update forms
 template <bool SMALL>
@@ -969,43 +970,80 @@ __global__ __launch_bounds__(ECH_CT) void k_ech_gemm(const SegR* segs, u32 S, co
         }
         s_w[r][u] = SMALL ? make_double2((double)w, 0.0) : make_double2((double)(w >> 16), (double)(w & 0xffffu));
     }
-    __syncthreads();
+    // no row of the tile has work (tiles left of the round's first pivot
+    // column without new pivot rows, rows without coefficients)
+    const bool mine = tid < ECH_RT && (s_kind[tid] >= 2 || (s_kind[tid] == 1 && s_any[tid]));
+    if (!__syncthreads_or(mine)) return;
     // a row that fits in one tile has its coefficients read by this workgroup
     // only, so it clears the pivot columns and finds the new leading columns
     // itself (k_ech_lead then finds nothing left to do)
     const bool whole = j0 == 0 && c <= span;
-    for (u32 j = j0 + tid; j < min(c, j0 + span); j += ECH_CT) {
-        const u32* D = Dp + G.dpb;
-        double xb[ECH_B];  // this column of the block rows that became pivot rows
+    // The product on the double-precision matrix cores: per wave, blocks of 16
+    // columns; a 16 x 16 x 4 product takes A = weights (row i = lane % 16,
+    // block-row index k = lane / 16) and B = block rows (k = lane / 16,
+    // column lane % 16), and leaves rows lane / 16 + 4 v, v < 4, of column
+    // lane % 16.  Every partial sum is an integer below 2^53, so the products
+    // are exact in any summation order.
+    const u32 lane = tid % F4_WAVE, wv = tid / F4_WAVE;
+    const u32 li = lane % 16, lk = lane / 16;
+    double ah[ECH_RT / 16][ECH_B / 4], al[ECH_RT / 16][ECH_B / 4];
 #pragma unroll
-        for (u32 u = 0; u < ECH_B; ++u) xb[u] = ((pm >> u) & 1u) ? (double)D[(u64)s_rows[u] * c + j] : 0.0;
-        const bool pcol = (s_pc[(j - j0) / 32] >> ((j - j0) % 32)) & 1u;
-        for (u32 r = 0; r < ECH_RT; ++r) {
-            const u32 kind = s_kind[r];
-            if (kind == 0 || (kind == 1 && !s_any[r])) continue;
-            if (kind == 1 && j < cmin) continue;
-            u32* row = row_of(l0 + r);
-            if (kind == 1 && pcol) {
-                if (whole) row[j] = 0;
-                continue;
-            }
-            double sh = 0.0, sl = 0.0;
+    for (u32 m = 0; m < ECH_RT / 16; ++m)
 #pragma unroll
-            for (u32 u = 0; u < ECH_B; ++u) {
-                const double2 w = s_w[r][u];
-                sh = fma(w.x, xb[u], sh);
-                if (!SMALL) sl = fma(w.y, xb[u], sl);
-            }
-            const u32 v = (u32)(SMALL ? dmod(sh, pd, pinv) : dmod(fma(dmod(sh, pd, pinv), 65536.0, sl), pd, pinv));
-            if (kind >= 2) {
-                row[j] = v;
-            } else {
-                u32 nv = row[j] + v;  // both below p < 2^31
-                nv = nv >= f.p ? nv - f.p : nv;
-                row[j] = nv;
-                if (whole && nv && l0 + r < G.L) atomicMin(&s_lead[r], j);
-            }
+        for (u32 kk = 0; kk < ECH_B / 4; ++kk) {
+            const double2 w = s_w[16 * m + li][4 * kk + lk];
+            ah[m][kk] = w.x;
+            al[m][kk] = w.y;
         }
+    const u32* D = Dp + G.dpb;
+    const u32 jend = min(c, j0 + span);
+    for (u32 jb = j0 + 16 * wv; jb < jend; jb += 16 * (ECH_CT / F4_WAVE)) {
+        const u32 j = jb + li;
+        double xb[ECH_B / 4];
+#pragma unroll
+        for (u32 kk = 0; kk < ECH_B / 4; ++kk) {
+            const u32 u = 4 * kk + lk;
+            xb[kk] = (((pm >> u) & 1u) && j < jend) ? (double)D[(u64)s_rows[u] * c + j] : 0.0;
+        }
+        ech_d4 sh[ECH_RT / 16], sl[ECH_RT / 16];
+#pragma unroll
+        for (u32 m = 0; m < ECH_RT / 16; ++m) {
+            sh[m] = ech_d4{0.0, 0.0, 0.0, 0.0};
+            sl[m] = ech_d4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (u32 kk = 0; kk < ECH_B / 4; ++kk)
+#pragma unroll
+            for (u32 m = 0; m < ECH_RT / 16; ++m) {
+                sh[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ah[m][kk], xb[kk], sh[m], 0, 0, 0);
+                if (!SMALL) sl[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(al[m][kk], xb[kk], sl[m], 0, 0, 0);
+            }
+        if (j >= jend) continue;
+        const bool pcol = (s_pc[(j - j0) / 32] >> ((j - j0) % 32)) & 1u;
+#pragma unroll
+        for (u32 m = 0; m < ECH_RT / 16; ++m)
+#pragma unroll
+            for (u32 v = 0; v < 4; ++v) {
+                const u32 r = 16 * m + lk + 4 * v;
+                const u32 kind = s_kind[r];
+                if (kind == 0 || (kind == 1 && !s_any[r])) continue;
+                if (kind == 1 && j < cmin) continue;
+                u32* row = row_of(l0 + r);
+                if (kind == 1 && pcol) {
+                    if (whole) row[j] = 0;
+                    continue;
+                }
+                const u32 val = (u32)(SMALL ? dmod(sh[m][v], pd, pinv)
+                                            : dmod(fma(dmod(sh[m][v], pd, pinv), 65536.0, sl[m][v]), pd, pinv));
+                if (kind >= 2) {
+                    row[j] = val;
+                } else {
+                    u32 nv = row[j] + val;  // both below p < 2^31
+                    nv = nv >= f.p ? nv - f.p : nv;
+                    row[j] = nv;
+                    if (whole && nv && l0 + r < G.L) atomicMin(&s_lead[r], j);
+                }
+            }
     }
     if (whole) {
         __syncthreads();
