@@ -857,8 +857,8 @@ __device__ __forceinline__ double dmod(double x, double pd, double pinv) {
     return r >= pd ? r - pd : r;
 }
 
-// One round's update of a tile of ECH_RT row slots x ECH_CT columns (one
-// column per thread), per prime class.  Row slots of a system: its L
+// One round's update of a tile of ECH_RT row slots x ECH_CT columns, per
+// prime class.  Row slots of a system: its L
 // remaining rows of D', then its pivot-row store.  Store slots npr0 ..
 // npr0+q-1 become this round's new pivot rows NP_t = sum_u Z[t][u] (block row
 // u); every other live row r (remaining rows, earlier pivot rows) loses its
