@@ -112,6 +112,7 @@ struct SegSP {
 // t * m of the row as seen.  One wave per row, lanes over terms; seen-bits are
 // gathered in an LDS bitmap per workgroup, flushed with one atomic OR per
 // nonzero word.
+#define MK_UNROLL 4
 __global__ __launch_bounds__(MK_THREADS) void k_mark_rows(const SegSP* segs, const u64* rows_t, const u32* rows_k,
                                                            u32* row_lmrank, u32* ctr, u32* present, u32* done,
                                                            u32* lead, int local_bitmap) {
@@ -146,16 +147,28 @@ __global__ __launch_bounds__(MK_THREADS) void k_mark_rows(const SegSP* segs, con
         }
         const u64 off = S.off[k];
         const u32 len = S.len[k];
-        for (u32 j = lane; j < len; j += F4_WAVE) {
-            const u32 q = mono_rank(t + S.mon[off + j], n, w, D, tab);
-            if (q == F4_BAD_RANK) {
-                C[3] = 1u;
-                continue;
+        // MK_UNROLL chunks of the row's terms are loaded before any is ranked:
+        // one wait for memory per MK_UNROLL * 64 terms
+        for (u32 j0 = 0; j0 < len; j0 += MK_UNROLL * F4_WAVE) {
+            u64 mm[MK_UNROLL];
+#pragma unroll
+            for (u32 i = 0; i < MK_UNROLL; ++i) {
+                const u32 j = j0 + i * F4_WAVE + lane;
+                mm[i] = j < len ? S.mon[off + j] : 0;
             }
-            if (local_bitmap)
-                atomicOr(&lbits[q >> 5], 1u << (q & 31));
-            else
-                atomicOr(&P[q >> 5], 1u << (q & 31));
+#pragma unroll
+            for (u32 i = 0; i < MK_UNROLL; ++i) {
+                if (j0 + i * F4_WAVE + lane >= len) continue;
+                const u32 q = mono_rank(t + mm[i], n, w, D, tab);
+                if (q == F4_BAD_RANK) {
+                    C[3] = 1u;
+                    continue;
+                }
+                if (local_bitmap)
+                    atomicOr(&lbits[q >> 5], 1u << (q & 31));
+                else
+                    atomicOr(&P[q >> 5], 1u << (q & 31));
+            }
         }
     }
     if (local_bitmap) {
