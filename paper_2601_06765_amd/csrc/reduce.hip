@@ -1057,7 +1057,6 @@ __global__ __launch_bounds__(ECH_CT) void k_ech_gemm(const SegR* segs, u32 S, co
 // and 0 at the other pivot columns), and an updated remaining row gets its
 // new leading column (none: the row is zero and leaves the elimination).
 #define ECH_LW 4
-#define ECH_LU 4  // chunks of 64 columns per load batch of the leading-column scan
 __global__ __launch_bounds__(64 * ECH_LW) void k_ech_lead(const SegR* segs, u32 S, const u32* ubase, u32* Dp,
                                                           const u32* status, u32* lead, const EchRound* rounds,
                                                           u32* PR) {
@@ -1094,25 +1093,16 @@ __global__ __launch_bounds__(64 * ECH_LW) void k_ech_lead(const SegR* segs, u32 
     if (coef) row[col] = 0;
     if (!rem) return;
     // first nonzero at or after cmin that is not one of the round's pivot
-    // columns (the zeros just written are not read back); ECH_LU chunks of 64
-    // columns are loaded before any is tested, one wait for memory per
-    // ECH_LU * 64 columns
+    // columns (the zeros just written are not read back)
     u32 first = 0xffffffffu;
-    for (u32 j0 = R->cmin; j0 < c && first == 0xffffffffu; j0 += ECH_LU * F4_WAVE) {
-        u32 vv[ECH_LU];
-#pragma unroll
-        for (u32 i = 0; i < ECH_LU; ++i) {
-            const u32 j = j0 + i * F4_WAVE + lane;
-            vv[i] = j < c ? row[j] : 0u;
-        }
-#pragma unroll
-        for (u32 i = 0; i < ECH_LU; ++i) {
-            if (first != 0xffffffffu) break;  // uniform: from a ballot
-            const u32 j = j0 + i * F4_WAVE + lane;
-            bool nz = vv[i] != 0;
-            for (u32 t = 0; t < q; ++t) nz = nz && j != (u32)__builtin_amdgcn_readlane((int)col, (int)t);
-            const u64 m = wave_ballot(nz);
-            if (m) first = j0 + i * F4_WAVE + (u32)__ffsll((long long)m) - 1;
+    for (u32 j0 = R->cmin; j0 < c; j0 += F4_WAVE) {
+        const u32 j = j0 + lane;
+        bool nz = j < c && row[j] != 0;
+        for (u32 t = 0; t < q; ++t) nz = nz && j != (u32)__builtin_amdgcn_readlane((int)col, (int)t);
+        const u64 m = wave_ballot(nz);
+        if (m) {
+            first = j0 + (u32)__ffsll((long long)m) - 1;
+            break;
         }
     }
     if (lane == 0) lead[G.lb + local] = first;
