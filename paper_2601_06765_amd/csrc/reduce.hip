@@ -997,14 +997,34 @@ __global__ __launch_bounds__(ECH_CT) void k_ech_gemm(const SegR* segs, u32 S, co
         }
     const u32* D = Dp + G.dpb;
     const u32 jend = min(c, j0 + span);
+    // software pipeline over a wave's column blocks: the block rows of the
+    // next block and the current entries of this block's updated rows are
+    // requested before this block's products, so their latency overlaps them
+    u32 xn[ECH_B / 4];
+    auto load_x = [&](u32 jb) {
+        const u32 j = jb + li;
+#pragma unroll
+        for (u32 kk = 0; kk < ECH_B / 4; ++kk) {
+            const u32 u = 4 * kk + lk;
+            xn[kk] = (((pm >> u) & 1u) && j < jend) ? D[(u64)s_rows[u] * c + j] : 0u;
+        }
+    };
+    if (j0 + 16 * wv < jend) load_x(j0 + 16 * wv);
     for (u32 jb = j0 + 16 * wv; jb < jend; jb += 16 * (ECH_CT / F4_WAVE)) {
         const u32 j = jb + li;
         double xb[ECH_B / 4];
 #pragma unroll
-        for (u32 kk = 0; kk < ECH_B / 4; ++kk) {
-            const u32 u = 4 * kk + lk;
-            xb[kk] = (((pm >> u) & 1u) && j < jend) ? (double)D[(u64)s_rows[u] * c + j] : 0.0;
-        }
+        for (u32 kk = 0; kk < ECH_B / 4; ++kk) xb[kk] = (double)xn[kk];
+        const bool pcol = j < jend && ((s_pc[(j - j0) / 32] >> ((j - j0) % 32)) & 1u);
+        u32 ov[ECH_RT / 16][4];
+#pragma unroll
+        for (u32 m = 0; m < ECH_RT / 16; ++m)
+#pragma unroll
+            for (u32 v = 0; v < 4; ++v) {
+                const u32 r = 16 * m + lk + 4 * v;
+                ov[m][v] = (s_kind[r] == 1 && s_any[r] && j >= cmin && j < jend && !pcol) ? row_of(l0 + r)[j] : 0u;
+            }
+        if (jb + 16 * (ECH_CT / F4_WAVE) < jend) load_x(jb + 16 * (ECH_CT / F4_WAVE));
         ech_d4 sh[ECH_RT / 16], sl[ECH_RT / 16];
 #pragma unroll
         for (u32 m = 0; m < ECH_RT / 16; ++m) {
@@ -1019,7 +1039,6 @@ __global__ __launch_bounds__(ECH_CT) void k_ech_gemm(const SegR* segs, u32 S, co
                 if (!SMALL) sl[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(al[m][kk], xb[kk], sl[m], 0, 0, 0);
             }
         if (j >= jend) continue;
-        const bool pcol = (s_pc[(j - j0) / 32] >> ((j - j0) % 32)) & 1u;
 #pragma unroll
         for (u32 m = 0; m < ECH_RT / 16; ++m)
 #pragma unroll
@@ -1038,7 +1057,7 @@ __global__ __launch_bounds__(ECH_CT) void k_ech_gemm(const SegR* segs, u32 S, co
                 if (kind >= 2) {
                     row[j] = val;
                 } else {
-                    u32 nv = row[j] + val;  // both below p < 2^31
+                    u32 nv = ov[m][v] + val;  // both below p < 2^31
                     nv = nv >= f.p ? nv - f.p : nv;
                     row[j] = nv;
                     if (whole && nv && l0 + r < G.L) atomicMin(&s_lead[r], j);
