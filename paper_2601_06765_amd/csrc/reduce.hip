@@ -935,6 +935,20 @@ __global__ __launch_bounds__(ECH_CT) void k_ech_gemm(const SegR* segs, u32 S, co
     if (tid < ECH_SPAN_MAX / 32) s_pc[tid] = 0;
     for (u32 x = tid; x < q * ECH_B; x += ECH_CT) s_Z[x / ECH_B][x % ECH_B] = R->Z[x];
     __syncthreads();
+    const u32 lane = tid % F4_WAVE, wv = tid / F4_WAVE;
+    const u32 li = lane % 16, lk = lane / 16;
+    const u32* D = Dp + G.dpb;
+    const u32 jend = min(c, j0 + span);
+    u32 xn[ECH_B / 4];  // block-row entries of a wave's next column block (lane: column li, rows 4 kk + lk)
+    auto load_x = [&](u32 jb) {
+        const u32 j = jb + li;
+#pragma unroll
+        for (u32 kk = 0; kk < ECH_B / 4; ++kk) {
+            const u32 u = 4 * kk + lk;
+            xn[kk] = (((pm >> u) & 1u) && j < jend) ? D[(u64)s_rows[u] * c + j] : 0u;
+        }
+    };
+    if (j0 + 16 * wv < jend) load_x(j0 + 16 * wv);
     if (tid < q && s_cols[tid] >= j0 && s_cols[tid] < j0 + span)
         atomicOr(&s_pc[(s_cols[tid] - j0) / 32], 1u << ((s_cols[tid] - j0) % 32));
     // coefficients of the update rows on the round's pivot columns
@@ -984,8 +998,6 @@ __global__ __launch_bounds__(ECH_CT) void k_ech_gemm(const SegR* segs, u32 S, co
     // column lane % 16), and leaves rows lane / 16 + 4 v, v < 4, of column
     // lane % 16.  Every partial sum is an integer below 2^53, so the products
     // are exact in any summation order.
-    const u32 lane = tid % F4_WAVE, wv = tid / F4_WAVE;
-    const u32 li = lane % 16, lk = lane / 16;
     double ah[ECH_RT / 16][ECH_B / 4], al[ECH_RT / 16][ECH_B / 4];
 #pragma unroll
     for (u32 m = 0; m < ECH_RT / 16; ++m)
@@ -995,21 +1007,10 @@ __global__ __launch_bounds__(ECH_CT) void k_ech_gemm(const SegR* segs, u32 S, co
             ah[m][kk] = w.x;
             al[m][kk] = w.y;
         }
-    const u32* D = Dp + G.dpb;
-    const u32 jend = min(c, j0 + span);
     // software pipeline over a wave's column blocks: the block rows of the
     // next block and the current entries of this block's updated rows are
     // requested before this block's products, so their latency overlaps them
-    u32 xn[ECH_B / 4];
-    auto load_x = [&](u32 jb) {
-        const u32 j = jb + li;
-#pragma unroll
-        for (u32 kk = 0; kk < ECH_B / 4; ++kk) {
-            const u32 u = 4 * kk + lk;
-            xn[kk] = (((pm >> u) & 1u) && j < jend) ? D[(u64)s_rows[u] * c + j] : 0u;
-        }
-    };
-    if (j0 + 16 * wv < jend) load_x(j0 + 16 * wv);
+    // (the first block's block rows were requested before the weights)
     for (u32 jb = j0 + 16 * wv; jb < jend; jb += 16 * (ECH_CT / F4_WAVE)) {
         const u32 j = jb + li;
         double xb[ECH_B / 4];
