@@ -153,7 +153,11 @@ def random_csr(r, N, p, density, seed):
 @pytest.mark.parametrize("r,N,p,density,seed", [
     (40, 30, 65521, 0.2, 1), (70, 150, 65521, 0.08, 2), (90, 200, 2147483647, 0.06, 3),
     (130, 70, 7, 0.3, 4), (200, 300, 65521, 0.02, 5), (3, 5, 31, 0.9, 6), (1, 1, 31, 1.0, 7),
-    (64, 64, 65521, 0.5, 8), (150, 520, 2147483629, 0.03, 9)])
+    (64, 64, 65521, 0.5, 8), (150, 520, 2147483629, 0.03, 9),
+    # more than 1 024 trailing columns: the echelon's tiled update on the fp64
+    # matrix cores (one tile per 32 rows x 256 columns, a ragged last tile),
+    # for the small-prime and the large-prime instance
+    (60, 1300, 65521, 0.05, 10), (60, 1250, 2147483647, 0.05, 11)])
 def test_reduce_random_matrices_vs_dense_rref(f4, ctx, r, N, p, density, seed):
     rp, ci, vv = random_csr(r, N, p, density, seed)
     say("reduce random", r, N, p, density, "nnz", len(ci))
